@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Throughput of the ptychographic reconstruction hot path on one MI355X.
+
+Workload: 256 x 256 probe window, 3 incoherent modes, 2,500-point Fermat
+spiral with +-0.5 px jitter (~70% overlap), 1700 x 1700 object, Poisson noise
+at 1e8 photons per pattern; synthetic, seeded.  One step = one DM iteration
+plus one LSQML iteration (5 groups of 500) over all 2,500 patterns, probe
+updates on.  Value = pattern-iterations per second (2 x 2,500 per step).
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pattern-iterations/s (256², 3 modes)"
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (packed)
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(torch):
+    """Config-2 inputs on the GPU: counts via the library's forward model + a seeded Poisson draw."""
+    import ptysynth
+    from paper_2202_03144_amd import Plan
+
+    wl = ptysynth.workload(2)
+    obj_true = wl.obj().astype(np.complex64)
+    probe = wl.probe().astype(np.complex64)
+    pos = wl.positions()
+    expected = torch.empty((wl.j, wl.n, wl.n), dtype=torch.float32, device="cuda")
+    with Plan(wl.n, wl.k, wl.j, (wl.h, wl.w)) as sim:
+        sim.load_positions(pos)
+        sim.set_object(obj_true)
+        sim.set_probe(probe)
+        sim.simulate(wl.photons, out=expected)
+        probe = sim.probe()
+    counts = ptysynth.poisson_counts(expected.cpu().numpy(), wl.noise_rng())
+    del expected
+    return wl, obj_true, probe, pos, torch.from_numpy(counts).cuda()
+
+
+# Algorithmic HBM bytes per pattern-iteration of each kernel family at N, K (float32
+# complex = 8 B): the traffic the method's data dependencies force, not the
+# implementation's intermediates (the chunk scratch is sized to stay on chip).
+def algorithmic_bytes(n, k):
+    nn = n * n
+    return {
+        # DM: psi read (K modes)
+        "rows_fwd_dm": 8 * k * nn,
+        # both: measured moduli A read
+        "cols": 4 * nn,
+        # DM: psi write; LSQML: chi write (K modes); both: contribution plane write
+        "rows_inv": 8 * k * nn + 8 * nn,
+    }
+
+
+def fft_flops(n):
+    """Nominal 5 N log2 N flops of one length-N complex line transform."""
+    return 5.0 * n * math.log2(n)
+
+
+def cpu_baseline(n_sample: int):
+    """The FP64 oracle on a bounded sample of the same workload: one DM and one
+    LSQML iteration over the first n_sample spiral positions."""
+    import oracle
+    import ptysynth
+
+    wl = ptysynth.workload(2)
+    obj_true = wl.obj()
+    pos = wl.positions()[:n_sample]
+    expected, probe = oracle.simulate(obj_true, wl.probe(), pos, wl.photons)
+    counts = ptysynth.poisson_counts(expected, wl.noise_rng())
+    amp = oracle.amplitude(counts.astype(np.float64))
+    o0 = np.ones(obj_true.shape, np.complex128)
+    t0 = time.perf_counter()
+    psi = oracle.dm_init(o0, probe, pos)
+    oracle.dm(o0, probe, psi, amp, pos, 1, start=0)
+    t1 = time.perf_counter()
+    oracle.lsqml(o0, probe, amp, pos, 1, start=0, batch=100)
+    t2 = time.perf_counter()
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": 2 * n_sample / (t2 - t0),
+        "unit": "pattern-iterations/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"first {n_sample} of the 2,500 spiral positions (same object, probe and photon "
+                   f"budget), one DM + one LSQML iteration in float64 NumPy/SciPy "
+                   f"(scipy.fft workers={os.cpu_count()}); DM {t1 - t0:.1f} s, LSQML {t2 - t1:.1f} s"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=200, help="positions in the oracle sample (0 = skip)")
+    ap.add_argument("--no-timing-pass", action="store_true", help="skip the event-timed kernel pass")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing was run.",
+              file=sys.stderr)
+        return 2
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    from paper_2202_03144_amd import Plan
+
+    log("building config-2 inputs")
+    wl, obj_true, probe, pos, counts = make_inputs(torch)
+    stream = torch.cuda.current_stream()
+    plans = {}
+    for algo in ("dm", "lsqml"):
+        pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
+        pl.load_patterns(counts)
+        pl.load_positions(pos)
+        pl.set_object(np.ones((wl.h, wl.w), np.complex64))
+        pl.set_probe(probe)
+        plans[algo] = pl
+    params = {"dm": dict(probe_update_start=0), "lsqml": dict(probe_update_start=0, lsqml_batch=500)}
+
+    def step():
+        for algo, pl in plans.items():
+            pl.iterate(algo, 1, **params[algo])
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    for pl in plans.values():
+        pl.sync()
+    torch.cuda.synchronize()
+
+    log(f"timed {args.steps} steps")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(args.steps):
+        plans["dm"].iterate("dm", 1, **params["dm"])
+        ev[2 * s + 1].record(stream)
+        plans["lsqml"].iterate("lsqml", 1, **params["lsqml"])
+        ev[2 * s + 2].record(stream)
+    for pl in plans.values():
+        pl.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dm_ms = sum(ev[2 * s].elapsed_time(ev[2 * s + 1]) for s in range(args.steps)) / args.steps
+    lsq_ms = sum(ev[2 * s + 1].elapsed_time(ev[2 * s + 2]) for s in range(args.steps)) / args.steps
+    ms_per_step = 1e3 * wall / args.steps
+    value = 2 * wl.j / (ms_per_step / 1e3)
+    errs = {a: pl.errors() for a, pl in plans.items()}
+    for a, e in errs.items():
+        if not np.all(np.isfinite(e)):
+            print(f"non-finite error history in {a}", file=sys.stderr)
+            return 1
+    log(f"{ms_per_step:.2f} ms/step (DM {dm_ms:.2f} ms, LSQML {lsq_ms:.2f} ms)")
+
+    roofline = None
+    families = None
+    if not args.no_timing_pass:
+        log("event-timed kernel pass")
+        for pl in plans.values():
+            pl.set_timing(True)
+        for _ in range(args.steps):
+            step()
+        families = {}
+        for algo, pl in plans.items():
+            for fam, (ms, cnt) in pl.timing().items():
+                if cnt:
+                    families[f"{algo}.{fam}"] = {"ms_per_iter": ms / args.steps, "launches_per_iter": cnt / args.steps}
+            pl.set_timing(False)
+        dom = max(families, key=lambda f: families[f]["ms_per_iter"])
+        n, k, j = wl.n, wl.k, wl.j
+        ab = algorithmic_bytes(n, k)
+        # FFT flops per pattern of each pass: K modes x N lines x one line transform
+        lines = k * n * fft_flops(n)
+        fam_flops = {"rows_fwd": lines, "cols": 2 * lines, "rows_inv": lines}
+        base = dom.split(".", 1)[1]
+        fdat = families[dom]
+        per_launch_ms = fdat["ms_per_iter"] / fdat["launches_per_iter"]
+        patterns_per_launch = j / fdat["launches_per_iter"]
+        if base in fam_flops:
+            achieved = fam_flops[base] * patterns_per_launch / (per_launch_ms / 1e3) / 1e12
+            roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2),
+                        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                        "per_launch_ms": round(per_launch_ms, 4),
+                        "patterns_per_launch": round(patterns_per_launch, 2)}
+        log(f"dominant kernel family {dom}: {fdat}")
+
+    cpu = None
+    if args.cpu_sample > 0:
+        log(f"cpu baseline on {args.cpu_sample} positions")
+        cpu = cpu_baseline(args.cpu_sample)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "pattern-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256x256 probe, 3 modes, 2500-point jittered Fermat spiral, 1700x1700 object, "
+                               "Poisson 1e8 photons; one DM + one LSQML (5x500) iteration per step",
+                   "n": wl.n, "modes": wl.k, "positions": wl.j, "object": [wl.h, wl.w]},
+        "dm_pattern_it_per_s": round(wl.j / (dm_ms / 1e3), 1),
+        "lsqml_pattern_it_per_s": round(wl.j / (lsq_ms / 1e3), 1),
+        "dm_ms_per_iter": round(dm_ms, 3),
+        "lsqml_ms_per_iter": round(lsq_ms, 3),
+        "roofline": roofline,
+        "kernel_families": families,
+        "cpu_baseline": cpu,
+    }
+    for pl in plans.values():
+        pl.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

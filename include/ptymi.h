@@ -1,0 +1,193 @@
+/*
+ * ptymi: multi-mode ptychographic reconstruction on one MI355X (gfx950).
+ *
+ * The library reconstructs a complex object and a set of K incoherent probe
+ * modes from far-field diffraction patterns recorded at overlapping scan
+ * positions, with the three algorithms the ptychopy paper provides (Sec. 2.3:
+ * ePIE, sequential over positions; DM, all positions batched with a stored
+ * copy of the exit waves; LSQML, batched with per-position step lengths).
+ * The call pattern follows the paper's step API (Sec. 3.2, Fig. 3, Listing 1):
+ * initialise and load, iterate any number of times, fetch object and probe at
+ * any time, then release.
+ *
+ * Notation (all sizes in pixels):
+ *   N   probe window (square), K probe modes, J scan positions, H x W object.
+ *   R_j = (y_j, x_j): top-left corner of patch j in object pixels, 0-based,
+ *         real-valued; patches are read by bilinear interpolation (exact slices
+ *         at integer positions) and written back by its exact adjoint.
+ *   F   unitary 2-D DFT in natural order.
+ *   complex64 = two little-endian float32 (re, im), interleaved.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a pty_status; no C++ exception crosses this boundary.
+ *     The message of the last failure is available from pty_last_error().
+ *   - Arguments are validated before any device work: a null pointer or a
+ *     size that does not match the plan gives PTY_E_INVALID; calls made out of
+ *     order (e.g. iterating before patterns and positions are loaded) give
+ *     PTY_E_STATE; a HIP failure gives PTY_E_DEVICE; a failed device
+ *     allocation gives PTY_E_NOMEM and leaves the context as it was.
+ *   - The caller owns every buffer it passes.  pty_load_* and pty_set_* copy
+ *     the data before returning.  pty_get_* copy into the caller's buffer and
+ *     synchronise.  pty_iterate only enqueues work on the context's stream;
+ *     its errors surface at the next pty_get_* / pty_sync.
+ *   - "on_device" = 1 means the pointer is device memory on the plan's device
+ *     (e.g. a torch tensor's data_ptr()); 0 means host memory.
+ *   - A context is not thread-safe; distinct contexts may run concurrently.
+ */
+#ifndef PTYMI_H
+#define PTYMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pty_ctx pty_ctx; /* opaque; owns every device buffer it allocates */
+
+typedef enum {
+  PTY_OK = 0,
+  PTY_E_INVALID = 1,     /* bad argument: null pointer, size or range */
+  PTY_E_STATE = 2,       /* call out of order */
+  PTY_E_NOMEM = 3,       /* device allocation failed (nothing leaked) */
+  PTY_E_DEVICE = 4,      /* no usable device, or a HIP call failed */
+  PTY_E_NUMERIC = 5,     /* NaN or Inf in the iteration error; state kept */
+  PTY_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} pty_status;
+
+typedef enum { PTY_EPIE = 0, PTY_DM = 1, PTY_LSQML = 2 } pty_algo;
+
+/* Plan: sizes and device.  n in {32, 64, 128, 256}; 1 <= modes <= 4;
+ * n_pos >= 1; obj_h, obj_w >= n + 1.  stream: a hipStream_t to enqueue on
+ * (NULL = the library creates its own stream). */
+typedef struct {
+  int32_t n, modes, n_pos, obj_h, obj_w;
+  int32_t device;
+  void* stream;
+  uint32_t flags; /* reserved, must be 0 */
+} pty_plan_desc;
+
+/* Iteration parameters; pty_default_params() fills the documented defaults.
+ *   alpha, beta          ePIE object / probe step (default 1, 1).
+ *   probe_update_start   first global iteration index (0-based) at which the
+ *                        probe is updated; < 0 = never (Sec. 2.2, the
+ *                        "after which iteration to update the probe" setting).
+ *   lsqml_batch          LSQML positions per group; groups are interleaved,
+ *                        group g = {j : j mod G = g}, G = ceil(J / batch)
+ *                        (default 512).
+ *   gamma_obj, gamma_probe  regularisers delta = gamma * max(denominator)
+ *                        (DM default 1e-6; LSQML default 1e-3; a value < 0
+ *                        selects the algorithm's default).
+ *   beta_obj, beta_probe LSQML relaxation of the update (default 1, 1).
+ *   order_seed           ePIE visiting order: 0 = identity, otherwise a
+ *                        Fisher-Yates shuffle driven by SplitMix64 seeded with
+ *                        order_seed + t in iteration t.
+ *   chunk                patterns per Fourier-pass chunk (0 = automatic). */
+typedef struct {
+  float alpha, beta;
+  int32_t probe_update_start;
+  int32_t lsqml_batch;
+  float gamma_obj, gamma_probe;
+  float beta_obj, beta_probe;
+  uint64_t order_seed;
+  int32_t chunk;
+  uint32_t flags; /* reserved, must be 0 */
+} pty_iter_params;
+
+/* Fills *p with the defaults listed above. */
+pty_status pty_default_params(pty_iter_params* p);
+
+/* Creates a context for the plan: checks the device, allocates the object,
+ * probe and pattern buffers.  *out is set only on success.
+ * PTY_E_DEVICE when no device with that index is present. */
+pty_status pty_create(const pty_plan_desc* plan, pty_ctx** out);
+
+/* Loads J diffraction patterns of photon counts, J x N x N float32, row-major,
+ * with the zero frequency at (N/2, N/2) (detector convention).  Each pattern
+ * is normalised on load to its measured modulus sqrt(counts) in natural
+ * (unshifted) order (Sec. 3.2: normalisation at initialisation).  Negative
+ * counts are treated as 0. */
+pty_status pty_load_patterns(pty_ctx* ctx, const float* counts, int on_device);
+
+/* Loads J scan positions, J x 2 float64 (y, x), top-left corner of each patch
+ * in object pixels.  Every patch must lie inside the object:
+ * 0 <= y, floor(y) + N + (y non-integer) <= H, likewise for x with W. */
+pty_status pty_load_positions(pty_ctx* ctx, const double* yx);
+
+/* Sets the object, H x W complex64 (Sec. 2.2: the object guess). */
+pty_status pty_set_object(pty_ctx* ctx, const void* c64, int on_device);
+
+/* Sets the probe modes, K x N x N complex64 (Sec. 2.2: the probe guess). */
+pty_status pty_set_probe(pty_ctx* ctx, const void* c64, int on_device);
+
+/* Enqueues n_iter iterations of algorithm `algo` (Sec. 2.3) with parameters
+ * `prm` (NULL = defaults).  Requires patterns, positions, object and probe.
+ * The global iteration counter advances by n_iter and drives
+ * probe_update_start.  DM keeps its exit waves between calls and initialises
+ * them from the current object and probe when it starts after another
+ * algorithm or after pty_set_object / pty_set_probe.  n_iter = 0 is a no-op. */
+pty_status pty_iterate(pty_ctx* ctx, pty_algo algo, int32_t n_iter, const pty_iter_params* prm);
+
+/* Copies the object (H x W complex64) / probe (K x N x N complex64) out; sync. */
+pty_status pty_get_object(pty_ctx* ctx, void* out, int on_device);
+pty_status pty_get_probe(pty_ctx* ctx, void* out, int on_device);
+
+/* Copies the per-iteration amplitude error
+ *   E = sum_j sum_q (sqrt(I_jq) - A_jq)^2 / sum_j sum_q A_jq^2
+ * of every iteration run so far (float64, oldest first) into out[0..cap);
+ * *n_written receives the number copied.  Synchronises.  Returns
+ * PTY_E_NUMERIC if any of them is NaN or Inf (the values are still copied). */
+pty_status pty_get_errors(pty_ctx* ctx, double* out, int32_t cap, int32_t* n_written);
+
+/* Last LSQML step lengths (alpha_O, alpha_P) per position, J x 2 float32. */
+pty_status pty_get_lsqml_steps(pty_ctx* ctx, float* out);
+
+/* Copies the DM exit waves, J x K x N x N complex64 (host or device); sync.
+ * PTY_E_STATE if DM has not run since the last change of object or probe. */
+pty_status pty_get_exit_waves(pty_ctx* ctx, void* out, int on_device);
+
+/* Device memory currently held by the context, in bytes. */
+pty_status pty_mem_bytes(const pty_ctx* ctx, size_t* out);
+
+/* Kernel timing.  While enabled, every kernel launch of the context is
+ * bracketed by HIP events on the context's stream and its duration is added
+ * to its family's total.  Families, in this order (PTY_TIMING_FAMILIES):
+ *   0 rows_fwd (gather, exit waves, forward FFT along x)
+ *   1 cols     (FFT along y, modulus projection / NLL factor, inverse FFT along y)
+ *   2 rows_inv (inverse FFT along x and the algorithm's epilogue)
+ *   3 obj_gather (object tiles: sum_j S_j^T of per-pattern contributions)
+ *   4 probe_acc  (probe sums over positions)
+ *   5 probe_finish_apply
+ *   6 lsq_steps  (LSQML per-position step lengths)
+ *   7 epie_update
+ *   8 other      (initialisation, reductions, fills)
+ * pty_set_timing(ctx, 1) clears the totals and enables timing; 0 disables it.
+ * pty_get_timing synchronises and copies, for the first `cap` families, the
+ * summed duration in milliseconds and the number of launches. */
+#define PTY_TIMING_FAMILIES 9
+pty_status pty_set_timing(pty_ctx* ctx, int enable);
+pty_status pty_get_timing(pty_ctx* ctx, double* ms, int64_t* launches, int32_t cap);
+
+/* Waits for all enqueued work; reports deferred device errors. */
+pty_status pty_sync(pty_ctx* ctx);
+
+/* Releases every resource of the context (Listing 1's post call).  NULL-safe. */
+void pty_destroy(pty_ctx* ctx);
+
+/* Message of the last failure on this context (ctx == NULL: of the calling
+ * thread's last failure without a context).  Never NULL. */
+const char* pty_last_error(const pty_ctx* ctx);
+
+/* Simulation mode (Listing 1's -simulate=1): expected photon counts
+ * I_j = sum_k |F(P_k S_j O)|^2 of every position for the context's current
+ * object, probe and positions, written centred (zero frequency at (N/2, N/2))
+ * as J x N x N float32 to `out` (host or device).  If photons > 0 the context's
+ * probe is first rescaled so that the mean pattern total equals `photons`.
+ * Synchronises. */
+pty_status pty_simulate(pty_ctx* ctx, double photons, float* out, int on_device);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTYMI_H */

@@ -1,0 +1,106 @@
+"""ctypes declarations of the C ABI in include/ptymi.h.
+
+Loading fails loudly when the HIP library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptymi.so")
+
+OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(7)
+STATUS_NAMES = {
+    OK: "PTY_OK",
+    E_INVALID: "PTY_E_INVALID",
+    E_STATE: "PTY_E_STATE",
+    E_NOMEM: "PTY_E_NOMEM",
+    E_DEVICE: "PTY_E_DEVICE",
+    E_NUMERIC: "PTY_E_NUMERIC",
+    E_UNSUPPORTED: "PTY_E_UNSUPPORTED",
+}
+EPIE, DM, LSQML = 0, 1, 2
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("modes", C.c_int32),
+        ("n_pos", C.c_int32),
+        ("obj_h", C.c_int32),
+        ("obj_w", C.c_int32),
+        ("device", C.c_int32),
+        ("stream", C.c_void_p),
+        ("flags", C.c_uint32),
+    ]
+
+
+class IterParams(C.Structure):
+    _fields_ = [
+        ("alpha", C.c_float),
+        ("beta", C.c_float),
+        ("probe_update_start", C.c_int32),
+        ("lsqml_batch", C.c_int32),
+        ("gamma_obj", C.c_float),
+        ("gamma_probe", C.c_float),
+        ("beta_obj", C.c_float),
+        ("beta_probe", C.c_float),
+        ("order_seed", C.c_uint64),
+        ("chunk", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+# name -> (restype, argtypes); every symbol declared in include/ptymi.h
+SIGNATURES = {
+    "pty_default_params": (C.c_int, [C.POINTER(IterParams)]),
+    "pty_create": (C.c_int, [C.POINTER(PlanDesc), C.POINTER(C.c_void_p)]),
+    "pty_load_patterns": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_load_positions": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pty_set_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_set_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_iterate": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(IterParams)]),
+    "pty_get_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_get_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_get_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "pty_get_lsqml_steps": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pty_get_exit_waves": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_mem_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "pty_sync": (C.c_int, [C.c_void_p]),
+    "pty_destroy": (None, [C.c_void_p]),
+    "pty_last_error": (C.c_char_p, [C.c_void_p]),
+    "pty_simulate": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int]),
+    "pty_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "pty_get_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+}
+
+TIMING_FAMILIES = ["rows_fwd", "cols", "rows_inv", "obj_gather", "probe_acc", "probe_finish_apply",
+                   "lsq_steps", "epie_update", "other"]
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2202_03144_amd.build` "
+                "(there is no CPU fallback)")
+        handle = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+class PtyError(RuntimeError):
+    """A non-OK status from the library."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status

@@ -1,0 +1,1023 @@
+// C ABI of the ptymi library: context ownership, validation, and the
+// per-iteration phase schedule of ePIE, DM and LSQML (Sec. 2.3 of the ptychopy
+// paper; step API of Sec. 3.2 / Fig. 3 / Listing 1).
+#include "ptymi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pty_common.hpp"
+#include "pty_kernels.hpp"
+
+using namespace pty;
+
+namespace {
+
+thread_local std::string g_tls_error;
+
+struct InvalidArg : std::runtime_error {
+  explicit InvalidArg(const std::string& m) : std::runtime_error(m) {}
+};
+struct StateError : std::runtime_error {
+  explicit StateError(const std::string& m) : std::runtime_error(m) {}
+};
+struct Unsupported : std::runtime_error {
+  explicit Unsupported(const std::string& m) : std::runtime_error(m) {}
+};
+
+// Object tiles with the list of patches (slots) that overlap each of them.
+struct TileSet {
+  TileEntry* tiles = nullptr;
+  PatchRef* refs = nullptr;
+  int ntiles = 0;
+  int nrefs = 0;
+};
+
+// A set of positions iterated together (DM: all; LSQML: one group).
+struct Group {
+  std::vector<int> jl;   // slot -> pattern index
+  int* d_jl = nullptr;   // device copy
+  TileSet tiles;
+};
+
+}  // namespace
+
+struct pty_ctx {
+  int N = 0, K = 0, J = 0, H = 0, W = 0, device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  std::vector<std::pair<void*, size_t>> allocs;
+  size_t mem = 0, mem_limit = 0;
+
+  // state
+  float2* obj = nullptr;
+  float2* probe = nullptr;
+  float2* probe_alt = nullptr;
+  float* amp = nullptr;
+  PosInfo* pos = nullptr;
+  float2* tw = nullptr;
+  int* jl_identity = nullptr;
+  std::vector<PosInfo> hpos;
+  bool have_patterns = false, have_positions = false, have_object = false, have_probe = false;
+  int iter = 0;
+
+  // error history (device, one double per iteration)
+  double* err_dev = nullptr;
+  int err_cap = 0;
+
+  // work buffers (allocated on first use, grown as needed)
+  float2* zs = nullptr;            size_t zs_patterns = 0;
+  float2* psi = nullptr;
+  float2* contrib = nullptr;       size_t contrib_slots = 0;
+  float2* chi = nullptr;           size_t chi_slots = 0;
+  double* errp = nullptr;
+  double* posgrad = nullptr;       size_t posgrad_slots = 0;
+  float* den = nullptr;
+  float2* dobj = nullptr;
+  unsigned* scal = nullptr;        // [0] max den_O, [1] max den_P (float bits)
+  float* pint = nullptr;
+  float2* part_num = nullptr;      size_t part_slices = 0;
+  float* part_den = nullptr;
+  float2* num_p = nullptr;
+  float2* num_p2 = nullptr;
+  float* den_p = nullptr;
+  float2* dprobe = nullptr;
+  double* lsq_part = nullptr;      size_t lsq_part_n = 0;
+  float2* alpha = nullptr;         size_t alpha_slots = 0;
+  float2* alpha_by_j = nullptr;
+
+  bool dm_valid = false;           // psi / contrib consistent with object and probe
+  bool den_valid = false;          // den holds sum_j S_j^T sum_k |P_k|^2 for all positions
+  Group all;                       // DM: every position
+  std::vector<Group> groups;       // LSQML groups
+  int groups_batch = -1;
+
+  // kernel timing (families as in the header)
+  static constexpr int kFamilies = PTY_TIMING_FAMILIES;
+  struct Pending {
+    int fam;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> pending;
+  double fam_ms[kFamilies] = {};
+  int64_t fam_n[kFamilies] = {};
+
+  hipEvent_t get_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    PTY_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void drain_timing() {
+    if (pending.empty()) return;
+    PTY_HIP(hipStreamSynchronize(stream));
+    for (auto& p : pending) {
+      float ms = 0.f;
+      PTY_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+      fam_ms[p.fam] += ms;
+      fam_n[p.fam] += 1;
+      ev_pool.push_back(p.a);
+      ev_pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+
+  void set_device() const { PTY_HIP(hipSetDevice(device)); }
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (mem_limit && mem + bytes > mem_limit)
+      throw NoMemError("device memory limit (PTY_MEM_LIMIT) reached");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw NoMemError(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    }
+    allocs.emplace_back(p, bytes);
+    mem += bytes;
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < allocs.size(); ++i) {
+      if (allocs[i].first == p) {
+        mem -= allocs[i].second;
+        allocs.erase(allocs.begin() + i);
+        (void)hipFree(p);
+        return;
+      }
+    }
+  }
+  template <typename T>
+  T* alloc(size_t n) { return static_cast<T*>(dalloc(n * sizeof(T))); }
+
+  // Replaces *slot by a new buffer of n elements if it holds fewer than n.
+  template <typename T>
+  void ensure(T*& buf, size_t& have, size_t n) {
+    if (buf && have >= n) return;
+    T* nb = alloc<T>(n);
+    dfree(buf);
+    buf = nb;
+    have = n;
+  }
+  template <typename T>
+  void ensure_once(T*& buf, size_t n) {
+    if (!buf) buf = alloc<T>(n);
+  }
+
+  ~pty_ctx() {
+    for (auto& p : pending) {
+      ev_pool.push_back(p.a);
+      ev_pool.push_back(p.b);
+    }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    for (auto& a : allocs) (void)hipFree(a.first);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+pty_status fail(pty_ctx* ctx, pty_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  g_tls_error = msg;
+  if (std::getenv("PTY_LOG")) std::fprintf(stderr, "[ptymi] %s\n", msg.c_str());
+  return st;
+}
+
+template <typename F>
+pty_status guarded(pty_ctx* ctx, F&& f) {
+  try {
+    f();
+    return PTY_OK;
+  } catch (const InvalidArg& e) {
+    return fail(ctx, PTY_E_INVALID, e.what());
+  } catch (const StateError& e) {
+    return fail(ctx, PTY_E_STATE, e.what());
+  } catch (const Unsupported& e) {
+    return fail(ctx, PTY_E_UNSUPPORTED, e.what());
+  } catch (const NoMemError& e) {
+    return fail(ctx, PTY_E_NOMEM, e.what());
+  } catch (const DeviceError& e) {
+    return fail(ctx, PTY_E_DEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, PTY_E_NOMEM, "host allocation failed");
+  } catch (const std::invalid_argument& e) {
+    return fail(ctx, PTY_E_INVALID, e.what());
+  } catch (const std::exception& e) {
+    return fail(ctx, PTY_E_DEVICE, e.what());
+  } catch (...) {
+    return fail(ctx, PTY_E_DEVICE, "unknown error");
+  }
+}
+
+void require(bool ok, const char* msg) {
+  if (!ok) throw InvalidArg(msg);
+}
+
+enum Fam { kRowsFwd = 0, kCols, kRowsInv, kObjGather, kProbeAcc, kProbeFin, kLsqSteps, kEpie, kOther };
+
+// Runs a launch; when timing is on, brackets it with events on the stream.
+template <typename F>
+void timed(pty_ctx* c, int fam, F&& f) {
+  if (!c->timing) {
+    f();
+    return;
+  }
+  hipEvent_t a = c->get_event(), b = c->get_event();
+  PTY_HIP(hipEventRecord(a, c->stream));
+  f();
+  PTY_HIP(hipEventRecord(b, c->stream));
+  c->pending.push_back({fam, a, b});
+  if (c->pending.size() > 50000) c->drain_timing();
+}
+
+bool supported_n(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+
+void copy_in(pty_ctx* c, void* dst, const void* src, size_t bytes, int on_device) {
+  PTY_HIP(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  PTY_HIP(hipStreamSynchronize(c->stream));
+}
+
+void copy_out(pty_ctx* c, void* dst, const void* src, size_t bytes, int on_device) {
+  PTY_HIP(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  PTY_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Host-side tile lists: for every object tile the patches whose (N+1)^2
+// footprint overlaps it, in slot order.
+void build_tiles(pty_ctx* c, Group& g) {
+  const int nty = (c->H + kTileH - 1) / kTileH, ntx = (c->W + kTileW - 1) / kTileW;
+  std::vector<std::vector<PatchRef>> per(size_t(nty) * ntx);
+  for (int s = 0; s < (int)g.jl.size(); ++s) {
+    const int j = g.jl[s];
+    const PosInfo& p = c->hpos[j];
+    const int y0 = p.iy / kTileH, y1 = std::min(nty - 1, (p.iy + c->N) / kTileH);
+    const int x0 = p.ix / kTileW, x1 = std::min(ntx - 1, (p.ix + c->N) / kTileW);
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) per[size_t(ty) * ntx + tx].push_back({s, j});
+  }
+  std::vector<TileEntry> tiles;
+  std::vector<PatchRef> refs;
+  for (int ty = 0; ty < nty; ++ty)
+    for (int tx = 0; tx < ntx; ++tx) {
+      auto& v = per[size_t(ty) * ntx + tx];
+      if (v.empty()) continue;
+      tiles.push_back({ty * kTileH, tx * kTileW, (int)refs.size(), (int)(refs.size() + v.size())});
+      refs.insert(refs.end(), v.begin(), v.end());
+    }
+  g.tiles.ntiles = (int)tiles.size();
+  g.tiles.nrefs = (int)refs.size();
+  g.tiles.tiles = c->alloc<TileEntry>(std::max<size_t>(1, tiles.size()));
+  g.tiles.refs = c->alloc<PatchRef>(std::max<size_t>(1, refs.size()));
+  PTY_HIP(hipMemcpy(g.tiles.tiles, tiles.data(), tiles.size() * sizeof(TileEntry), hipMemcpyHostToDevice));
+  PTY_HIP(hipMemcpy(g.tiles.refs, refs.data(), refs.size() * sizeof(PatchRef), hipMemcpyHostToDevice));
+}
+
+void free_group(pty_ctx* c, Group& g) {
+  c->dfree(g.d_jl);
+  c->dfree(g.tiles.tiles);
+  c->dfree(g.tiles.refs);
+  g = Group{};
+}
+
+void make_group(pty_ctx* c, Group& g, std::vector<int> jl) {
+  g.jl = std::move(jl);
+  g.d_jl = c->alloc<int>(g.jl.size());
+  PTY_HIP(hipMemcpy(g.d_jl, g.jl.data(), g.jl.size() * sizeof(int), hipMemcpyHostToDevice));
+  build_tiles(c, g);
+}
+
+void ensure_all_group(pty_ctx* c) {
+  if (c->all.d_jl) return;
+  std::vector<int> jl(c->J);
+  for (int j = 0; j < c->J; ++j) jl[j] = j;
+  make_group(c, c->all, std::move(jl));
+}
+
+void ensure_lsq_groups(pty_ctx* c, int batch) {
+  const int G = std::max(1, (c->J + batch - 1) / batch);
+  if (c->groups_batch == batch && (int)c->groups.size() == G) return;
+  for (auto& g : c->groups) free_group(c, g);
+  c->groups.clear();
+  c->groups.resize(G);
+  for (int g = 0; g < G; ++g) {
+    std::vector<int> jl;
+    for (int j = g; j < c->J; j += G) jl.push_back(j);
+    make_group(c, c->groups[g], std::move(jl));
+  }
+  c->groups_batch = batch;
+}
+
+int chunk_patterns(const pty_ctx* c, const pty_iter_params& p) {
+  if (p.chunk > 0) return p.chunk;
+  const size_t per = size_t(c->K) * c->N * c->N * sizeof(float2);
+  const size_t budget = size_t(64) << 20;  // stays inside the 256 MB Infinity Cache
+  return (int)std::max<size_t>(1, budget / per);
+}
+
+constexpr int kProbeSlice = 32;
+
+// Common work buffers of the Fourier passes.
+void ensure_common(pty_ctx* c, int chunk, size_t slots) {
+  const size_t nn = size_t(c->N) * c->N;
+  c->ensure(c->zs, c->zs_patterns, size_t(chunk) * c->K * nn);
+  c->ensure(c->contrib, c->contrib_slots, slots * nn);
+  c->ensure_once(c->errp, size_t(c->J) * col_blocks(c->N) * 2);
+  c->ensure_once(c->den, size_t(c->H) * c->W);
+  c->ensure_once(c->scal, 16);
+  c->ensure_once(c->pint, nn);
+  c->ensure_once(c->num_p, size_t(c->K) * nn);
+  c->ensure_once(c->num_p2, size_t(c->K) * nn);
+  c->ensure_once(c->den_p, nn);
+  c->ensure_once(c->dprobe, size_t(c->K) * nn);
+}
+
+void ensure_err_slot(pty_ctx* c, int n_iter) {
+  if (c->iter + n_iter <= c->err_cap) return;
+  int cap = std::max(256, c->err_cap);
+  while (cap < c->iter + n_iter) cap *= 2;
+  double* nb = c->alloc<double>(cap);
+  if (c->err_dev && c->iter > 0)
+    PTY_HIP(hipMemcpyAsync(nb, c->err_dev, sizeof(double) * c->iter, hipMemcpyDeviceToDevice, c->stream));
+  PTY_HIP(hipStreamSynchronize(c->stream));
+  c->dfree(c->err_dev);
+  c->err_dev = nb;
+  c->err_cap = cap;
+}
+
+FourierArgs fourier_args(pty_ctx* c, const Group& g) {
+  FourierArgs a{};
+  a.n = c->N;
+  a.k = c->K;
+  a.obj = c->obj;
+  a.h = c->H;
+  a.w = c->W;
+  a.probe = c->probe;
+  a.jlist = g.d_jl;
+  a.pos = c->pos;
+  a.amp = c->amp;
+  a.psi = c->psi;
+  a.chi = c->chi;
+  a.contrib = c->contrib;
+  a.zs = c->zs;
+  a.errp = c->errp;
+  a.posgrad = c->posgrad;
+  a.tw = reinterpret_cast<const float*>(c->tw);
+  a.nll_eps = 1e-6f;
+  a.stream = c->stream;
+  return a;
+}
+
+// Forward rows, columns with the modulus projection, inverse rows, over the
+// slots [s0, s0 + count) of group g in chunks.
+void fourier_pass(pty_ctx* c, const Group& g, int s0, int count, int chunk, RowIn in, ColOp op,
+                  RowOut out) {
+  FourierArgs a = fourier_args(c, g);
+  for (int off = 0; off < count; off += chunk) {
+    a.jl_off = s0 + off;
+    a.slot_off = s0 + off;
+    a.nc = std::min(chunk, count - off);
+    timed(c, kRowsFwd, [&] { launch_rows_fwd(a, in); });
+    timed(c, kCols, [&] { launch_cols(a, op); });
+    if (op != ColOp::Intensity) timed(c, kRowsInv, [&] { launch_rows_inv(a, out); });
+  }
+}
+
+ObjGatherArgs obj_args(pty_ctx* c, const Group& g) {
+  ObjGatherArgs o{};
+  o.n = c->N;
+  o.h = c->H;
+  o.w = c->W;
+  o.tiles = g.tiles.tiles;
+  o.ntiles = g.tiles.ntiles;
+  o.refs = g.tiles.refs;
+  o.pos = c->pos;
+  o.src = c->contrib;
+  o.pint = c->pint;
+  o.alpha = c->alpha;
+  o.obj = c->obj;
+  o.den = c->den;
+  o.den_max = c->scal;
+  o.stream = c->stream;
+  return o;
+}
+
+// den_O = sum over the group of S_j^T sum_k |P_k|^2 and its maximum
+void density(pty_ctx* c, const Group& g) {
+  timed(c, kOther, [&] { launch_probe_intensity(c->probe, c->pint, c->N, c->K, c->stream); });
+  timed(c, kOther, [&] { launch_fill_u32(c->scal, 1, 0u, c->stream); });
+  ObjGatherArgs o = obj_args(c, g);
+  timed(c, kObjGather, [&] { launch_obj_gather(o, ObjOp::Density); });
+}
+
+// Probe sums over slots [0, count) of group g: part -> num_p / den_p
+void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern, PrbOp op,
+                  float2* num, bool with_den) {
+  const int count = (int)g.jl.size();
+  const int slices = probe_slices(count, kProbeSlice);
+  ProbeAccArgs pa{};
+  pa.n = c->N;
+  pa.k = c->K;
+  pa.obj = c->obj;
+  pa.h = c->H;
+  pa.w = c->W;
+  pa.jlist = g.d_jl;
+  pa.pos = c->pos;
+  pa.src = src;
+  pa.src_by_pattern = by_pattern;
+  pa.alpha = c->alpha;
+  pa.s0 = 0;
+  pa.count = count;
+  pa.per_slice = kProbeSlice;
+  pa.part_num = c->part_num;
+  pa.part_den = c->part_den;
+  pa.stream = c->stream;
+  timed(c, kProbeAcc, [&] { launch_probe_acc(pa, op); });
+  ProbeFinishArgs pf{};
+  pf.n = c->N;
+  pf.k = c->K;
+  pf.slices = slices;
+  pf.part_num = c->part_num;
+  pf.part_den = with_den ? c->part_den : nullptr;
+  pf.num = num;
+  pf.den = with_den ? c->den_p : nullptr;
+  pf.den_max = with_den ? c->scal + 1 : nullptr;
+  pf.stream = c->stream;
+  if (with_den) timed(c, kOther, [&] { launch_fill_u32(c->scal + 1, 1, 0u, c->stream); });
+  timed(c, kProbeFin, [&] { launch_probe_finish(pf); });
+}
+
+void ensure_probe_parts(pty_ctx* c, int count) {
+  const int slices = probe_slices(count, kProbeSlice);
+  const size_t nn = size_t(c->N) * c->N;
+  size_t have = c->part_slices;
+  if (c->part_num && have >= size_t(slices) * c->K * nn && c->part_den) return;
+  c->dfree(c->part_num);
+  c->dfree(c->part_den);
+  c->part_num = c->alloc<float2>(size_t(slices) * c->K * nn);
+  c->part_den = c->alloc<float>(size_t(slices) * nn);
+  c->part_slices = size_t(slices) * c->K * nn;
+}
+
+void probe_apply(pty_ctx* c, PrbApply op, const float2* num, float gamma, float beta) {
+  ProbeApplyArgs ap{};
+  ap.n = c->N;
+  ap.k = c->K;
+  ap.num = num;
+  ap.den = c->den_p;
+  ap.den_max = c->scal + 1;
+  ap.gamma = gamma;
+  ap.beta = beta;
+  ap.probe = c->probe;
+  ap.dir = c->dprobe;
+  ap.stream = c->stream;
+  timed(c, kProbeFin, [&] { launch_probe_apply(ap, op); });
+}
+
+void require_loaded(pty_ctx* c) {
+  if (!c->have_patterns) throw StateError("patterns not loaded");
+  if (!c->have_positions) throw StateError("positions not loaded");
+  if (!c->have_object) throw StateError("object not set");
+  if (!c->have_probe) throw StateError("probe not set");
+}
+
+bool probe_on(const pty_iter_params& p, int t) { return p.probe_update_start >= 0 && t >= p.probe_update_start; }
+
+// ---------------------------------------------------------------------------
+// DM
+// ---------------------------------------------------------------------------
+void run_dm(pty_ctx* c, int n_iter, const pty_iter_params& p) {
+  const float g_obj = p.gamma_obj < 0 ? 1e-6f : p.gamma_obj;
+  const float g_prb = p.gamma_probe < 0 ? 1e-6f : p.gamma_probe;
+  const int chunk = chunk_patterns(c, p);
+  const size_t nn = size_t(c->N) * c->N;
+  ensure_all_group(c);
+  ensure_common(c, std::min(chunk, c->J), c->J);
+  c->ensure_once(c->psi, size_t(c->J) * c->K * nn);
+  ensure_probe_parts(c, c->J);
+  ensure_err_slot(c, n_iter);
+  const Group& g = c->all;
+  if (!c->dm_valid) {
+    DmInitArgs di{};
+    di.n = c->N;
+    di.k = c->K;
+    di.obj = c->obj;
+    di.h = c->H;
+    di.w = c->W;
+    di.probe = c->probe;
+    di.pos = c->pos;
+    di.j = c->J;
+    di.psi = c->psi;
+    di.contrib = c->contrib;
+    di.stream = c->stream;
+    timed(c, kOther, [&] { launch_dm_init(di); });
+    c->dm_valid = true;
+    c->den_valid = false;
+  }
+  for (int it = 0; it < n_iter; ++it) {
+    const int t = c->iter;
+    if (!c->den_valid) {
+      density(c, g);
+      c->den_valid = true;
+    }
+    ObjGatherArgs o = obj_args(c, g);
+    o.gamma = g_obj;
+    timed(c, kObjGather, [&] { launch_obj_gather(o, ObjOp::DmObject); });
+    if (probe_on(p, t)) {
+      probe_reduce(c, g, c->psi, 1, PrbOp::Plain, c->num_p, true);
+      probe_apply(c, PrbApply::Dm, c->num_p, g_prb, 1.f);
+      c->den_valid = false;
+    }
+    fourier_pass(c, g, 0, c->J, chunk, RowIn::DmReflect, ColOp::Project, RowOut::DmUpdate);
+    timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
+    c->iter++;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LSQML
+// ---------------------------------------------------------------------------
+void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
+  const float g_obj = p.gamma_obj < 0 ? 1e-3f : p.gamma_obj;
+  const float g_prb = p.gamma_probe < 0 ? 1e-3f : p.gamma_probe;
+  const int batch = p.lsqml_batch > 0 ? p.lsqml_batch : 512;
+  const int chunk = chunk_patterns(c, p);
+  const size_t nn = size_t(c->N) * c->N;
+  ensure_lsq_groups(c, batch);
+  int bmax = 0;
+  for (auto& g : c->groups) bmax = std::max(bmax, (int)g.jl.size());
+  ensure_common(c, std::min(chunk, bmax), bmax);
+  c->ensure(c->chi, c->chi_slots, size_t(bmax) * c->K * nn);
+  c->ensure_once(c->dobj, size_t(c->H) * c->W);
+  c->ensure(c->alpha, c->alpha_slots, size_t(bmax));
+  c->ensure_once(c->alpha_by_j, size_t(c->J));
+  int nrb = std::max(1, c->N * c->N / 2048);
+  c->ensure(c->lsq_part, c->lsq_part_n, size_t(bmax) * nrb * 5);
+  ensure_probe_parts(c, bmax);
+  ensure_err_slot(c, n_iter);
+  c->dm_valid = false;
+  for (int it = 0; it < n_iter; ++it) {
+    const int t = c->iter;
+    const bool pon = probe_on(p, t);
+    for (auto& g : c->groups) {
+      const int count = (int)g.jl.size();
+      density(c, g);
+      fourier_pass(c, g, 0, count, chunk, RowIn::Plain, ColOp::Project, RowOut::StoreChi);
+      ObjGatherArgs o = obj_args(c, g);
+      o.gamma = g_obj;
+      o.out = c->dobj;
+      timed(c, kObjGather, [&] { launch_obj_gather(o, ObjOp::LsqDirection); });
+      if (pon) {
+        probe_reduce(c, g, c->chi, 0, PrbOp::Plain, c->num_p, true);
+        probe_apply(c, PrbApply::LsqDirection, c->num_p, g_prb, 1.f);
+      }
+      LsqStepArgs ls{};
+      ls.n = c->N;
+      ls.k = c->K;
+      ls.obj = c->obj;
+      ls.dobj = c->dobj;
+      ls.h = c->H;
+      ls.w = c->W;
+      ls.probe = c->probe;
+      ls.dprobe = c->dprobe;
+      ls.chi = c->chi;
+      ls.contrib = c->contrib;
+      ls.jlist = g.d_jl;
+      ls.pos = c->pos;
+      ls.count = count;
+      ls.probe_on = pon ? 1 : 0;
+      ls.part = c->lsq_part;
+      ls.alpha = c->alpha;
+      ls.alpha_by_j = c->alpha_by_j;
+      ls.stream = c->stream;
+      timed(c, kLsqSteps, [&] { launch_lsq_steps(ls); });
+      if (pon) probe_reduce(c, g, c->chi, 0, PrbOp::AlphaWeighted, c->num_p2, false);
+      ObjGatherArgs u = obj_args(c, g);
+      u.gamma = g_obj;
+      u.beta = p.beta_obj;
+      timed(c, kObjGather, [&] { launch_obj_gather(u, ObjOp::LsqUpdate); });
+      if (pon) probe_apply(c, PrbApply::LsqUpdate, c->num_p2, g_prb, p.beta_probe);
+    }
+    timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
+    c->iter++;
+  }
+  c->den_valid = false;  // den holds the last group's density only
+}
+
+// ---------------------------------------------------------------------------
+// ePIE
+// ---------------------------------------------------------------------------
+uint64_t splitmix64_next(uint64_t& s) {
+  s += 0x9E3779B97F4A7C15ull;
+  uint64_t z = s;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
+  const size_t nn = size_t(c->N) * c->N;
+  ensure_all_group(c);
+  ensure_common(c, 1, 1);
+  c->ensure(c->chi, c->chi_slots, size_t(c->K) * nn);
+  ensure_err_slot(c, n_iter);
+  c->dm_valid = false;
+  FourierArgs a = fourier_args(c, c->all);
+  a.nc = 1;
+  a.slot_off = 0;
+  std::vector<int> order(c->J);
+  for (int it = 0; it < n_iter; ++it) {
+    const int t = c->iter;
+    for (int j = 0; j < c->J; ++j) order[j] = j;
+    if (p.order_seed != 0) {
+      uint64_t st = p.order_seed + (uint64_t)t;
+      for (int i = c->J - 1; i >= 1; --i) {
+        const uint64_t k = splitmix64_next(st) % (uint64_t)(i + 1);
+        std::swap(order[i], order[k]);
+      }
+    }
+    const bool pon = probe_on(p, t);
+    for (int j : order) {
+      a.jl_off = j;
+      a.obj = c->obj;
+      a.probe = c->probe;
+      timed(c, kRowsFwd, [&] { launch_rows_fwd(a, RowIn::Plain); });
+      timed(c, kCols, [&] { launch_cols(a, ColOp::Project); });
+      timed(c, kRowsInv, [&] { launch_rows_inv(a, RowOut::StoreChi); });
+      EpieArgs e{};
+      e.n = c->N;
+      e.k = c->K;
+      e.obj = c->obj;
+      e.h = c->H;
+      e.w = c->W;
+      e.probe = c->probe;
+      e.probe_out = c->probe_alt;
+      e.chi = c->chi;
+      e.pos = c->hpos[j];
+      e.alpha = p.alpha;
+      e.beta = p.beta;
+      e.probe_on = pon ? 1 : 0;
+      e.stream = c->stream;
+      timed(c, kEpie, [&] { launch_epie_update(e); });
+      std::swap(c->probe, c->probe_alt);
+    }
+    timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
+    c->iter++;
+  }
+  c->den_valid = false;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Entry points
+// ===========================================================================
+extern "C" {
+
+pty_status pty_default_params(pty_iter_params* p) {
+  return guarded(nullptr, [&] {
+    require(p != nullptr, "pty_default_params: null params");
+    std::memset(p, 0, sizeof(*p));
+    p->alpha = 1.f;
+    p->beta = 1.f;
+    p->probe_update_start = 0;
+    p->lsqml_batch = 512;
+    p->gamma_obj = -1.f;
+    p->gamma_probe = -1.f;
+    p->beta_obj = 1.f;
+    p->beta_probe = 1.f;
+    p->order_seed = 0;
+    p->chunk = 0;
+    p->flags = 0;
+  });
+}
+
+pty_status pty_create(const pty_plan_desc* plan, pty_ctx** out) {
+  return guarded(nullptr, [&] {
+    require(plan != nullptr && out != nullptr, "pty_create: null argument");
+    require(supported_n(plan->n), "pty_create: n must be 32, 64, 128 or 256");
+    require(plan->modes >= 1 && plan->modes <= 4, "pty_create: modes must be in 1..4");
+    require(plan->n_pos >= 1, "pty_create: n_pos must be >= 1");
+    require(plan->obj_h >= plan->n + 1 && plan->obj_w >= plan->n + 1, "pty_create: object must be at least (n+1) x (n+1)");
+    require(plan->flags == 0, "pty_create: flags must be 0");
+    require(plan->device >= 0, "pty_create: negative device");
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= plan->device) {
+      (void)hipGetLastError();
+      throw DeviceError("pty_create: no HIP device " + std::to_string(plan->device) +
+                        (e != hipSuccess ? std::string(" (") + hipGetErrorString(e) + ")" : std::string()));
+    }
+    std::unique_ptr<pty_ctx> c(new pty_ctx());
+    c->N = plan->n;
+    c->K = plan->modes;
+    c->J = plan->n_pos;
+    c->H = plan->obj_h;
+    c->W = plan->obj_w;
+    c->device = plan->device;
+    if (const char* lim = std::getenv("PTY_MEM_LIMIT")) c->mem_limit = std::strtoull(lim, nullptr, 10);
+    c->set_device();
+    if (plan->stream) {
+      c->stream = static_cast<hipStream_t>(plan->stream);
+    } else {
+      PTY_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    const size_t nn = size_t(c->N) * c->N;
+    c->obj = c->alloc<float2>(size_t(c->H) * c->W);
+    c->probe = c->alloc<float2>(size_t(c->K) * nn);
+    c->probe_alt = c->alloc<float2>(size_t(c->K) * nn);
+    c->amp = c->alloc<float>(size_t(c->J) * nn);
+    c->pos = c->alloc<PosInfo>(size_t(c->J));
+    c->tw = c->alloc<float2>(size_t(c->N));
+    std::vector<float2> tw(c->N);
+    for (int i = 0; i < c->N; ++i) {
+      const double ang = -2.0 * M_PI * (double)i / (double)c->N;
+      tw[i] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    PTY_HIP(hipMemcpy(c->tw, tw.data(), sizeof(float2) * c->N, hipMemcpyHostToDevice));
+    *out = c.release();
+  });
+}
+
+pty_status pty_load_patterns(pty_ctx* c, const float* counts, int on_device) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_load_patterns: null context");
+    require(counts != nullptr, "pty_load_patterns: null counts");
+    c->set_device();
+    const size_t n = size_t(c->J) * c->N * c->N;
+    const float* src = counts;
+    float* tmp = nullptr;
+    if (!on_device) {
+      tmp = c->alloc<float>(n);
+      PTY_HIP(hipMemcpyAsync(tmp, counts, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+      src = tmp;
+    }
+    try {
+      launch_amplitude(src, c->amp, nullptr, c->N, c->J, c->stream);
+      PTY_HIP(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      c->dfree(tmp);
+      throw;
+    }
+    c->dfree(tmp);
+    c->have_patterns = true;
+  });
+}
+
+pty_status pty_load_positions(pty_ctx* c, const double* yx) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_load_positions: null context");
+    require(yx != nullptr, "pty_load_positions: null positions");
+    std::vector<PosInfo> hp(c->J);
+    for (int j = 0; j < c->J; ++j) {
+      const double y = yx[2 * j], x = yx[2 * j + 1];
+      if (!(std::isfinite(y) && std::isfinite(x)) || y < 0 || x < 0)
+        throw InvalidArg("pty_load_positions: position " + std::to_string(j) + " is negative or not finite");
+      const double fy = std::floor(y), fx = std::floor(x);
+      const int ey = (int)fy + c->N + (y != fy ? 1 : 0), ex = (int)fx + c->N + (x != fx ? 1 : 0);
+      if (ey > c->H || ex > c->W)
+        throw InvalidArg("pty_load_positions: patch " + std::to_string(j) + " extends past the object");
+      hp[j] = PosInfo{(int)fy, (int)fx, (float)(y - fy), (float)(x - fx)};
+    }
+    c->set_device();
+    PTY_HIP(hipMemcpy(c->pos, hp.data(), sizeof(PosInfo) * c->J, hipMemcpyHostToDevice));
+    c->hpos = std::move(hp);
+    free_group(c, c->all);
+    for (auto& g : c->groups) free_group(c, g);
+    c->groups.clear();
+    c->groups_batch = -1;
+    c->have_positions = true;
+    c->dm_valid = false;
+    c->den_valid = false;
+  });
+}
+
+pty_status pty_set_object(pty_ctx* c, const void* src, int on_device) {
+  return guarded(c, [&] {
+    require(c != nullptr && src != nullptr, "pty_set_object: null argument");
+    c->set_device();
+    copy_in(c, c->obj, src, size_t(c->H) * c->W * sizeof(float2), on_device);
+    c->have_object = true;
+    c->dm_valid = false;
+  });
+}
+
+pty_status pty_set_probe(pty_ctx* c, const void* src, int on_device) {
+  return guarded(c, [&] {
+    require(c != nullptr && src != nullptr, "pty_set_probe: null argument");
+    c->set_device();
+    copy_in(c, c->probe, src, size_t(c->K) * c->N * c->N * sizeof(float2), on_device);
+    c->have_probe = true;
+    c->dm_valid = false;
+    c->den_valid = false;
+  });
+}
+
+pty_status pty_iterate(pty_ctx* c, pty_algo algo, int32_t n_iter, const pty_iter_params* prm) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_iterate: null context");
+    require(algo == PTY_EPIE || algo == PTY_DM || algo == PTY_LSQML, "pty_iterate: unknown algorithm");
+    require(n_iter >= 0, "pty_iterate: negative iteration count");
+    pty_iter_params p;
+    pty_default_params(&p);
+    if (prm) p = *prm;
+    require(p.flags == 0, "pty_iterate: flags must be 0");
+    require(p.chunk >= 0, "pty_iterate: negative chunk");
+    require(p.lsqml_batch >= 0, "pty_iterate: negative lsqml_batch");
+    require_loaded(c);
+    if (n_iter == 0) return;
+    c->set_device();
+    if (algo == PTY_DM)
+      run_dm(c, n_iter, p);
+    else if (algo == PTY_LSQML)
+      run_lsqml(c, n_iter, p);
+    else
+      run_epie(c, n_iter, p);
+  });
+}
+
+pty_status pty_get_object(pty_ctx* c, void* out, int on_device) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_get_object: null argument");
+    c->set_device();
+    copy_out(c, out, c->obj, size_t(c->H) * c->W * sizeof(float2), on_device);
+  });
+}
+
+pty_status pty_get_probe(pty_ctx* c, void* out, int on_device) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_get_probe: null argument");
+    c->set_device();
+    copy_out(c, out, c->probe, size_t(c->K) * c->N * c->N * sizeof(float2), on_device);
+  });
+}
+
+pty_status pty_get_errors(pty_ctx* c, double* out, int32_t cap, int32_t* n_written) {
+  bool finite = true;
+  pty_status st = guarded(c, [&] {
+    require(c != nullptr && n_written != nullptr, "pty_get_errors: null argument");
+    require(cap >= 0 && (cap == 0 || out != nullptr), "pty_get_errors: bad buffer");
+    c->set_device();
+    const int n = std::min<int>(cap, c->iter);
+    if (n > 0)
+      copy_out(c, out, c->err_dev, sizeof(double) * n, 0);
+    else
+      PTY_HIP(hipStreamSynchronize(c->stream));
+    *n_written = n;
+    for (int i = 0; i < n; ++i) finite = finite && std::isfinite(out[i]);
+  });
+  if (st == PTY_OK && !finite) return fail(c, PTY_E_NUMERIC, "pty_get_errors: NaN or Inf in the iteration error");
+  return st;
+}
+
+pty_status pty_get_lsqml_steps(pty_ctx* c, float* out) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_get_lsqml_steps: null argument");
+    if (!c->alpha_by_j) throw StateError("pty_get_lsqml_steps: LSQML has not run");
+    c->set_device();
+    copy_out(c, out, c->alpha_by_j, sizeof(float2) * c->J, 0);
+  });
+}
+
+pty_status pty_get_exit_waves(pty_ctx* c, void* out, int on_device) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_get_exit_waves: null argument");
+    if (!c->dm_valid || !c->psi) throw StateError("pty_get_exit_waves: no DM exit waves");
+    c->set_device();
+    copy_out(c, out, c->psi, size_t(c->J) * c->K * c->N * c->N * sizeof(float2), on_device);
+  });
+}
+
+pty_status pty_mem_bytes(const pty_ctx* c, size_t* out) {
+  return guarded(const_cast<pty_ctx*>(c), [&] {
+    require(c != nullptr && out != nullptr, "pty_mem_bytes: null argument");
+    *out = c->mem;
+  });
+}
+
+pty_status pty_set_timing(pty_ctx* c, int enable) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_set_timing: null context");
+    c->set_device();
+    c->drain_timing();
+    for (int i = 0; i < pty_ctx::kFamilies; ++i) {
+      c->fam_ms[i] = 0.0;
+      c->fam_n[i] = 0;
+    }
+    c->timing = enable != 0;
+  });
+}
+
+pty_status pty_get_timing(pty_ctx* c, double* ms, int64_t* launches, int32_t cap) {
+  return guarded(c, [&] {
+    require(c != nullptr && ms != nullptr && launches != nullptr, "pty_get_timing: null argument");
+    require(cap >= 0, "pty_get_timing: negative cap");
+    c->set_device();
+    c->drain_timing();
+    for (int i = 0; i < std::min<int>(cap, pty_ctx::kFamilies); ++i) {
+      ms[i] = c->fam_ms[i];
+      launches[i] = c->fam_n[i];
+    }
+  });
+}
+
+pty_status pty_sync(pty_ctx* c) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_sync: null context");
+    c->set_device();
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+void pty_destroy(pty_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+const char* pty_last_error(const pty_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_tls_error.c_str();
+}
+
+pty_status pty_simulate(pty_ctx* c, double photons, float* out, int on_device) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_simulate: null argument");
+    require(std::isfinite(photons) && photons >= 0, "pty_simulate: photons must be finite and >= 0");
+    if (!c->have_positions) throw StateError("positions not loaded");
+    if (!c->have_object) throw StateError("object not set");
+    if (!c->have_probe) throw StateError("probe not set");
+    c->set_device();
+    pty_iter_params p;
+    pty_default_params(&p);
+    const int chunk = chunk_patterns(c, p);
+    ensure_all_group(c);
+    ensure_common(c, std::min(chunk, c->J), 1);
+    const size_t n = size_t(c->J) * c->N * c->N;
+    float* dst = on_device ? out : c->alloc<float>(n);
+    try {
+      FourierArgs a = fourier_args(c, c->all);
+      a.intensity_out = dst;
+      for (int off = 0; off < c->J; off += chunk) {
+        a.jl_off = off;
+        a.slot_off = off;
+        a.nc = std::min(chunk, c->J - off);
+        launch_rows_fwd(a, RowIn::Plain);
+        launch_cols(a, ColOp::Intensity);
+      }
+      if (photons > 0) {
+        double* tot = c->alloc<double>(c->J);
+        std::vector<double> ht(c->J);
+        try {
+          launch_pattern_totals(dst, tot, c->N, c->J, c->stream);
+          PTY_HIP(hipMemcpyAsync(ht.data(), tot, sizeof(double) * c->J, hipMemcpyDeviceToHost, c->stream));
+          PTY_HIP(hipStreamSynchronize(c->stream));
+        } catch (...) {
+          c->dfree(tot);
+          throw;
+        }
+        c->dfree(tot);
+        double mean = 0;
+        for (double v : ht) mean += v;
+        mean /= c->J;
+        if (!(mean > 0)) throw InvalidArg("pty_simulate: zero total intensity");
+        const double s = photons / mean;
+        launch_scale_f32(dst, n, (float)s, c->stream);
+        launch_scale_c64(c->probe, size_t(c->K) * c->N * c->N, (float)std::sqrt(s), c->stream);
+        c->dm_valid = false;
+        c->den_valid = false;
+      }
+      if (!on_device) {
+        PTY_HIP(hipMemcpyAsync(out, dst, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+      }
+      PTY_HIP(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      if (!on_device) c->dfree(dst);
+      throw;
+    }
+    if (!on_device) c->dfree(dst);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// Fused Fourier passes of one reconstruction iteration.
+//
+// For a chunk of patterns the 2-D transforms are split into three passes that
+// communicate through a chunk-sized scratch buffer (sized to stay in the
+// MI355X Infinity Cache):
+//   rows_fwd : gather S_j O (bilinear), exit wave P_k S_j O (DM: reflected
+//              2 P S_j O - psi), forward FFT along x, all K modes per block;
+//   cols     : forward FFT along y of all K modes, then per far-field pixel
+//              the multi-mode modulus projection (Delta = (A / max(sqrt I, eps)
+//              - 1) Psi) with the amplitude-error partials, or the Poisson-NLL
+//              factor (1 - d / (I + eps)), then the inverse FFT along y;
+//   rows_inv : inverse FFT along x and the algorithm's epilogue (DM: new exit
+//              waves psi = phi + chi; LSQML / ePIE: store chi; adjoint: store
+//              g_psi and the position-gradient partials), plus the per-pattern
+//              contribution sum_k conj(P_k) (.) used by the object update.
+// Methods: Sec. 2.3 (far-field ptychography with ePIE, DM and LSQML; multi-mode
+// probes, Sec. 2.2).
+#include "pty_geom.hpp"
+#include "pty_kernels.hpp"
+
+namespace pty {
+namespace {
+
+template <int N, int K, RowIn MODE>
+__global__ __launch_bounds__(Geo<N>::BS) void k_rows_fwd(FourierArgs a) {
+  using G = Geo<N>;
+  constexpr int R = G::R, T = G::T;
+  __shared__ float2 tw_s[N];
+  __shared__ float2 xb[G::LINES * G::W];
+  load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
+  const int line = threadIdx.x / T, t = threadIdx.x % T;
+  const int c = blockIdx.y;
+  const int y = blockIdx.x * G::LINES + line;
+  const int slot = a.slot_off + c;
+  const int j = a.jlist[a.jl_off + c];
+  const PosInfo p = a.pos[j];
+  float2 o[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    float2 z[R];
+    const float2* pr = a.probe + ((size_t)k * N + y) * N;
+#pragma unroll
+    for (int m = 0; m < R; ++m) z[m] = cmul(pr[t + T * m], o[m]);
+    if constexpr (MODE == RowIn::DmReflect) {
+      const float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) z[m] = 2.f * z[m] - ps[t + T * m];
+    }
+    line_fft<N, false>(z, xb + line * G::W, tw_s, t);
+    float2* out = a.zs + (((size_t)c * K + k) * N + y) * N;
+#pragma unroll
+    for (int m = 0; m < R; ++m) out[t + T * m] = z[m];
+  }
+}
+
+template <int N, int K, ColOp OP>
+__global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
+  using G = Geo<N>;
+  constexpr int R = G::R, T = G::T, CW = G::LINES;
+  __shared__ float2 tw_s[N];
+  __shared__ float2 xb[CW * G::W];
+  __shared__ double red[G::BS / 64];
+  load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
+  const int col = threadIdx.x % CW, t = threadIdx.x / CW;
+  const int c = blockIdx.y, x = blockIdx.x * CW + col;
+  const int slot = a.slot_off + c;
+  const int j = a.jlist[a.jl_off + c];
+  float2 z[K][R];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float2* src = a.zs + ((size_t)c * K + k) * N * N + x;
+#pragma unroll
+    for (int m = 0; m < R; ++m) z[k][m] = src[(size_t)(t + T * m) * N];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) line_fft<N, false>(z[k], xb + col * G::W, tw_s, t);
+  const float sc = 1.0f / N;  // the unitary 2-D forward scale
+  float e_num = 0.f, e_den = 0.f;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int pr = t + T * m;
+    float inten = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      z[k][m] = sc * z[k][m];
+      inten += cabs2(z[k][m]);
+    }
+    if constexpr (OP == ColOp::Intensity) {
+      a.intensity_out[((size_t)j * N + ((pr + N / 2) & (N - 1))) * N + ((x + N / 2) & (N - 1))] = inten;
+    } else {
+      const float am = a.amp[((size_t)j * N + pr) * N + x];
+      float f;
+      if constexpr (OP == ColOp::Project) {
+        const float mod = sqrtf(inten);
+        f = am / fmaxf(mod, 1e-6f) - 1.f;
+        e_num += (mod - am) * (mod - am);
+        e_den += am * am;
+      } else {
+        const float d = am * am;
+        f = 1.f - d / (inten + a.nll_eps);
+        e_num += inten - d * logf(inten + a.nll_eps);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) z[k][m] = f * z[k][m];
+    }
+  }
+  if constexpr (OP != ColOp::Intensity) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) line_fft<N, true>(z[k], xb + col * G::W, tw_s, t);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      float2* dst = a.zs + ((size_t)c * K + k) * N * N + x;
+#pragma unroll
+      for (int m = 0; m < R; ++m) dst[(size_t)(t + T * m) * N] = z[k][m];
+    }
+    const double s0 = block_sum<G::BS>((double)e_num, red);
+    const double s1 = block_sum<G::BS>((double)e_den, red);
+    if (threadIdx.x == 0) {
+      double* e = a.errp + ((size_t)j * (N / CW) + blockIdx.x) * 2;
+      e[0] = s0;
+      e[1] = s1;
+    }
+  }
+}
+
+template <int N, int K, RowOut MODE>
+__global__ __launch_bounds__(Geo<N>::BS) void k_rows_inv(FourierArgs a) {
+  using G = Geo<N>;
+  constexpr int R = G::R, T = G::T;
+  __shared__ float2 tw_s[N];
+  __shared__ float2 xb[G::LINES * G::W];
+  __shared__ double red[G::BS / 64];
+  load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
+  const int line = threadIdx.x / T, t = threadIdx.x % T;
+  const int c = blockIdx.y;
+  const int y = blockIdx.x * G::LINES + line;
+  const int slot = a.slot_off + c;
+  const int j = a.jlist[a.jl_off + c];
+  const PosInfo p = a.pos[j];
+  const float sc = 1.0f / N;  // the unitary 2-D inverse scale
+  float2 z[K][R];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float2* src = a.zs + (((size_t)c * K + k) * N + y) * N;
+#pragma unroll
+    for (int m = 0; m < R; ++m) z[k][m] = src[t + T * m];
+    line_fft<N, true>(z[k], xb + line * G::W, tw_s, t);
+#pragma unroll
+    for (int m = 0; m < R; ++m) z[k][m] = sc * z[k][m];
+  }
+  float2 cacc[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) cacc[m] = make_float2(0.f, 0.f);
+  if constexpr (MODE == RowOut::DmUpdate) {
+    float2 o[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float2* pr = a.probe + ((size_t)k * N + y) * N;
+      float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const float2 pk = pr[t + T * m];
+        const float2 nw = cmul(pk, o[m]) + z[k][m];
+        ps[t + T * m] = nw;
+        cacc[m] = cacc[m] + cconjmul(pk, nw);
+      }
+    }
+  } else {
+    const float gscale = (MODE == RowOut::NllGrad) ? 2.f : 1.f;
+    float gy = 0.f, gx = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float2* pr = a.probe + ((size_t)k * N + y) * N;
+      float2* ch = a.chi + (((size_t)slot * K + k) * N + y) * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const float2 pk = pr[t + T * m];
+        ch[t + T * m] = z[k][m];
+        cacc[m] = cacc[m] + gscale * cconjmul(pk, z[k][m]);
+      }
+    }
+    if constexpr (MODE == RowOut::NllGrad) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        float2 dy, dx;
+        obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, dy, dx);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float2 pk = a.probe[((size_t)k * N + y) * N + t + T * m];
+          const float2 gpy = cmul(pk, dy), gpx = cmul(pk, dx);
+          // Re(conj(g_psi) * P_k * d(S_j O))
+          gy += z[k][m].x * gpy.x + z[k][m].y * gpy.y;
+          gx += z[k][m].x * gpx.x + z[k][m].y * gpx.y;
+        }
+      }
+      const double sy = block_sum<G::BS>(2.0 * gy, red);
+      const double sx = block_sum<G::BS>(2.0 * gx, red);
+      if (threadIdx.x == 0) {
+        double* g = a.posgrad + ((size_t)slot * (N / G::LINES) + blockIdx.x) * 2;
+        g[0] = sy;
+        g[1] = sx;
+      }
+    }
+  }
+  float2* cb = a.contrib + ((size_t)slot * N + y) * N;
+#pragma unroll
+  for (int m = 0; m < R; ++m) cb[t + T * m] = cacc[m];
+}
+
+}  // namespace
+
+int col_blocks(int n) {
+  int r = 0;
+  dispatch_n(n, [&](auto nc) { constexpr int N = decltype(nc)::value; r = N / Geo<N>::LINES; });
+  return r;
+}
+int row_blocks(int n) { return col_blocks(n); }
+
+void launch_rows_fwd(const FourierArgs& a, RowIn mode) {
+  if (a.nc <= 0) return;
+  dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    const dim3 grid(N / Geo<N>::LINES, a.nc);
+    if (mode == RowIn::Plain)
+      k_rows_fwd<N, K, RowIn::Plain><<<grid, Geo<N>::BS, 0, a.stream>>>(a);
+    else
+      k_rows_fwd<N, K, RowIn::DmReflect><<<grid, Geo<N>::BS, 0, a.stream>>>(a);
+  });
+  PTY_LAUNCH_CHECK("rows_fwd");
+}
+
+void launch_cols(const FourierArgs& a, ColOp op) {
+  if (a.nc <= 0) return;
+  dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    const dim3 grid(N / Geo<N>::LINES, a.nc);
+    switch (op) {
+      case ColOp::Project: k_cols<N, K, ColOp::Project><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+      case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+      case ColOp::Intensity: k_cols<N, K, ColOp::Intensity><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+    }
+  });
+  PTY_LAUNCH_CHECK("cols");
+}
+
+void launch_rows_inv(const FourierArgs& a, RowOut mode) {
+  if (a.nc <= 0) return;
+  dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    const dim3 grid(N / Geo<N>::LINES, a.nc);
+    switch (mode) {
+      case RowOut::DmUpdate: k_rows_inv<N, K, RowOut::DmUpdate><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+      case RowOut::StoreChi: k_rows_inv<N, K, RowOut::StoreChi><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+      case RowOut::NllGrad: k_rows_inv<N, K, RowOut::NllGrad><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+    }
+  });
+  PTY_LAUNCH_CHECK("rows_inv");
+}
+
+}  // namespace pty

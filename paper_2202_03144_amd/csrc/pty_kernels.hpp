@@ -1,0 +1,169 @@
+// Host-side launchers of the ptymi kernels (one entry per kernel family).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pty_common.hpp"
+
+namespace pty {
+
+// Prologue of the forward row pass: z = P S_j O, or z = 2 P S_j O - psi_j (DM).
+enum class RowIn { Plain = 0, DmReflect = 1 };
+// Per-pixel step of the column pass.
+enum class ColOp { Project = 0, NllGrad = 1, Intensity = 2 };
+// Epilogue of the inverse row pass.
+enum class RowOut { DmUpdate = 0, StoreChi = 1, NllGrad = 2 };
+// Object-tile gather: what is accumulated and how it is applied.
+enum class ObjOp { Density = 0, DmObject = 1, LsqDirection = 2, LsqUpdate = 3, Gradient = 4 };
+// Probe reduction over positions.
+enum class PrbOp { Plain = 0, AlphaWeighted = 1, Gradient = 2 };
+// Probe apply step.
+enum class PrbApply { Dm = 0, LsqDirection = 1, LsqUpdate = 2 };
+
+struct FourierArgs {
+  int n, k;
+  const float2* obj;
+  int h, w;
+  const float2* probe;
+  const int* jlist;       // pattern index of slot s = jlist[s]
+  const PosInfo* pos;     // by pattern index
+  const float* amp;       // J x N x N measured moduli (natural order), by pattern index
+  float2* psi;            // DM exit waves J x K x N x N (by pattern index); may be null
+  float2* chi;            // per-slot K x N x N (StoreChi / NllGrad); may be null
+  float2* contrib;        // per-slot N x N sum_k conj(P_k) (.) ; may be null
+  float2* zs;             // chunk scratch C x K x N x N
+  double* errp;           // per (pattern index, column block) partials (2 doubles)
+  double* posgrad;        // per (slot, row block) position-gradient partials (2 doubles)
+  float* intensity_out;   // Intensity: J x N x N centred, by pattern index
+  const float* tw;        // W_N table (N float2)
+  int jl_off;             // chunk entry c reads pattern jlist[jl_off + c]
+  int slot_off;           // ... and writes chi / contrib / posgrad slot slot_off + c
+  int nc;                 // patterns in the chunk
+  float nll_eps;
+  hipStream_t stream;
+};
+
+void launch_rows_fwd(const FourierArgs& a, RowIn mode);
+void launch_cols(const FourierArgs& a, ColOp op);
+void launch_rows_inv(const FourierArgs& a, RowOut mode);
+int col_blocks(int n);   // column blocks per pattern in the column pass
+int row_blocks(int n);   // row blocks per pattern in the row passes
+
+struct ObjGatherArgs {
+  int n;
+  int h, w;
+  const TileEntry* tiles;
+  int ntiles;
+  const PatchRef* refs;
+  const PosInfo* pos;
+  const float2* src;      // per-slot N x N complex contributions
+  const float* pint;      // N x N probe intensity (Density)
+  const float2* alpha;    // per-slot step lengths (LsqUpdate uses .x)
+  float2* obj;            // object (DmObject, LsqUpdate: in/out)
+  float2* out;            // LsqDirection: direction plane; Gradient: gradient plane
+  float* den;             // Density: output; others: input
+  unsigned* den_max;      // Density: atomic max (float bits); others: input
+  float gamma;            // delta = gamma * max(den)
+  float beta;             // LsqUpdate relaxation
+  hipStream_t stream;
+};
+void launch_obj_gather(const ObjGatherArgs& a, ObjOp op);
+
+struct ProbeAccArgs {
+  int n, k;
+  const float2* obj;
+  int h, w;
+  const int* jlist;
+  const PosInfo* pos;
+  const float2* src;      // per-slot (or per-pattern for DM) K x N x N
+  int src_by_pattern;     // 1: src indexed by pattern index j (DM psi); 0: by slot
+  const float2* alpha;    // AlphaWeighted: weight alpha[slot].y
+  int s0, count;          // slots [s0, s0 + count)
+  int per_slice;
+  float2* part_num;       // slices x K x N x N
+  float* part_den;        // slices x N x N
+  hipStream_t stream;
+};
+int probe_slices(int count, int per_slice);
+void launch_probe_acc(const ProbeAccArgs& a, PrbOp op);
+
+struct ProbeFinishArgs {
+  int n, k, slices;
+  const float2* part_num;
+  const float* part_den;   // may be null (Gradient)
+  float2* num;             // K x N x N
+  float* den;              // N x N (may be null)
+  unsigned* den_max;       // atomic max of den (float bits), may be null
+  hipStream_t stream;
+};
+void launch_probe_finish(const ProbeFinishArgs& a);
+
+struct ProbeApplyArgs {
+  int n, k;
+  const float2* num;
+  const float* den;
+  const unsigned* den_max;
+  float gamma, beta;
+  float2* probe;           // Dm: in/out; LsqUpdate: in/out
+  float2* dir;             // LsqDirection: output
+  hipStream_t stream;
+};
+void launch_probe_apply(const ProbeApplyArgs& a, PrbApply op);
+
+struct LsqStepArgs {
+  int n, k;
+  const float2* obj;
+  const float2* dobj;
+  int h, w;
+  const float2* probe;
+  const float2* dprobe;
+  const float2* chi;
+  const float2* contrib;
+  const int* jlist;
+  const PosInfo* pos;
+  int count;
+  int probe_on;
+  double* part;            // count x row_blocks x 5
+  float2* alpha;           // per slot
+  float2* alpha_by_j;      // per pattern index (reporting)
+  hipStream_t stream;
+};
+void launch_lsq_steps(const LsqStepArgs& a);
+
+struct EpieArgs {
+  int n, k;
+  float2* obj;
+  int h, w;
+  const float2* probe;
+  float2* probe_out;
+  const float2* chi;
+  PosInfo pos;
+  float alpha, beta;
+  int probe_on;
+  hipStream_t stream;
+};
+void launch_epie_update(const EpieArgs& a);
+
+struct DmInitArgs {
+  int n, k;
+  const float2* obj;
+  int h, w;
+  const float2* probe;
+  const PosInfo* pos;
+  int j;
+  float2* psi;
+  float2* contrib;
+  hipStream_t stream;
+};
+void launch_dm_init(const DmInitArgs& a);
+
+// Small utilities
+void launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s);
+void launch_amplitude(const float* counts, float* amp, double* totals, int n, int j, hipStream_t s);
+void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s);
+void launch_err_reduce(const double* errp, int count, double* out, hipStream_t s);
+void launch_posgrad_reduce(const double* part, int count, int nrb, float* out, const int* jlist, hipStream_t s);
+void launch_scale_f32(float* p, size_t n, float s, hipStream_t st);
+void launch_scale_c64(float2* p, size_t n, float s, hipStream_t st);
+void launch_pattern_totals(const float* x, double* totals, int n, int j, hipStream_t s);
+
+}  // namespace pty

@@ -1,0 +1,545 @@
+// Object and probe updates, LSQML step lengths, ePIE update, reductions.
+//
+// Object planes are accumulated in gather form: every object tile walks the
+// list of patches that overlap it and sums their per-pattern contributions
+// through the bilinear adjoint S_j^T, in a fixed order.  No float atomics are
+// used (their throughput on MI355X is far below the HBM stream rate), and the
+// result is bit-for-bit reproducible run to run.
+// Methods: DM overlap projection (Thibault et al. 2009), LSQML directions and
+// per-position steps (Odstrcil et al. 2018), ePIE (Maiden & Rodenburg 2009);
+// all three named in Sec. 2.3.
+#include "pty_geom.hpp"
+#include "pty_kernels.hpp"
+
+namespace pty {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Object tiles: sum_j S_j^T (.) in gather form, then the algorithm's update
+// ---------------------------------------------------------------------------
+template <int N, ObjOp OP>
+__global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
+  constexpr int ROWS = 256 / kTileW;   // rows covered per sweep
+  constexpr int PR = kTileH / ROWS;    // pixels per thread
+  __shared__ float redf[4];
+  const TileEntry te = a.tiles[blockIdx.x];
+  const int cx = threadIdx.x % kTileW, ry = threadIdx.x / kTileW;
+  const int X = te.tx + cx;
+  float2 acc[PR];
+#pragma unroll
+  for (int i = 0; i < PR; ++i) acc[i] = make_float2(0.f, 0.f);
+  for (int e = te.beg; e < te.end; ++e) {
+    const PatchRef r = a.refs[e];
+    const PosInfo p = a.pos[r.j];
+    float wgt = 1.f;
+    if constexpr (OP == ObjOp::LsqUpdate) wgt = a.alpha[r.slot].x;
+    const int v = X - p.ix;
+    const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
+    const bool v0ok = (unsigned)v < (unsigned)N, v1ok = (unsigned)(v - 1) < (unsigned)N;
+#pragma unroll
+    for (int i = 0; i < PR; ++i) {
+      const int u = te.ty + ry + ROWS * i - p.iy;
+      const bool u0ok = (unsigned)u < (unsigned)N, u1ok = (unsigned)(u - 1) < (unsigned)N;
+      float2 s = make_float2(0.f, 0.f);
+      if constexpr (OP == ObjOp::Density) {
+        const float* src = a.pint;
+        float d = 0.f;
+        if (u0ok && v0ok) d += wy0 * wx0 * src[u * N + v];
+        if (u0ok && v1ok) d += wy0 * wx1 * src[u * N + v - 1];
+        if (u1ok && v0ok) d += wy1 * wx0 * src[(u - 1) * N + v];
+        if (u1ok && v1ok) d += wy1 * wx1 * src[(u - 1) * N + v - 1];
+        s.x = d;
+      } else {
+        const float2* src = a.src + (size_t)r.slot * N * N;
+        if (u0ok && v0ok) s = s + (wy0 * wx0) * src[u * N + v];
+        if (u0ok && v1ok) s = s + (wy0 * wx1) * src[u * N + v - 1];
+        if (u1ok && v0ok) s = s + (wy1 * wx0) * src[(u - 1) * N + v];
+        if (u1ok && v1ok) s = s + (wy1 * wx1) * src[(u - 1) * N + v - 1];
+      }
+      acc[i] = acc[i] + wgt * s;
+    }
+  }
+  float mx = 0.f;
+  const float dmax = (OP == ObjOp::Density || OP == ObjOp::Gradient) ? 0.f : __uint_as_float(*a.den_max);
+  const float delta = a.gamma * dmax;
+#pragma unroll
+  for (int i = 0; i < PR; ++i) {
+    const int Y = te.ty + ry + ROWS * i;
+    if (Y >= a.h || X >= a.w) continue;
+    const size_t o = (size_t)Y * a.w + X;
+    if constexpr (OP == ObjOp::Density) {
+      a.den[o] = acc[i].x;
+      mx = fmaxf(mx, acc[i].x);
+    } else if constexpr (OP == ObjOp::Gradient) {
+      a.out[o] = acc[i];
+    } else {
+      const float d = a.den[o] + delta;
+      if constexpr (OP == ObjOp::DmObject) {
+        if (d > 0.f) {
+          const float2 ov = a.obj[o];
+          a.obj[o] = (1.f / d) * (acc[i] + delta * ov);
+        }
+      } else if constexpr (OP == ObjOp::LsqDirection) {
+        a.out[o] = d > 0.f ? (1.f / d) * acc[i] : make_float2(0.f, 0.f);
+      } else {
+        if (d > 0.f) a.obj[o] = a.obj[o] + (a.beta / d) * acc[i];
+      }
+    }
+  }
+  if constexpr (OP == ObjOp::Density) {
+    mx = block_max_all<256>(mx, redf);
+    if (threadIdx.x == 0) atomicMax(a.den_max, __float_as_uint(mx));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Probe reductions over positions: sum_j w_j conj(S_j O) src_jk and sum_j |S_j O|^2
+// ---------------------------------------------------------------------------
+template <int N>
+struct ProbePix {
+  static constexpr int PPT = (N * N >= 1024) ? 4 : 1;
+  static constexpr int PIX = 256 * PPT;  // pixels per block
+};
+
+template <int N, int K, PrbOp OP>
+__global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
+  constexpr int PPT = ProbePix<N>::PPT;
+  const int s_beg = a.s0 + blockIdx.y * a.per_slice;
+  const int s_end = min(s_beg + a.per_slice, a.s0 + a.count);
+  float2 num[K][PPT];
+  float den[PPT];
+  int qu[PPT], qv[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int q = blockIdx.x * ProbePix<N>::PIX + i * 256 + threadIdx.x;
+    qu[i] = q / N;
+    qv[i] = q % N;
+    den[i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) num[k][i] = make_float2(0.f, 0.f);
+  }
+  for (int s = s_beg; s < s_end; ++s) {
+    const int j = a.jlist[s];
+    const PosInfo p = a.pos[j];
+    float w = 1.f;
+    if constexpr (OP == PrbOp::AlphaWeighted) w = a.alpha[s].y;
+    if constexpr (OP == PrbOp::Gradient) w = 2.f;
+    const float2* src = a.src + (size_t)(a.src_by_pattern ? j : s) * K * N * N;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const float2 o = obj_bilinear(a.obj, a.h, a.w, p, qu[i], qv[i]);
+      if constexpr (OP == PrbOp::Plain) den[i] += cabs2(o);
+      const float2 ow = w * o;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        num[k][i] = num[k][i] + cconjmul(ow, src[(size_t)k * N * N + qu[i] * N + qv[i]]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int q = qu[i] * N + qv[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a.part_num[((size_t)blockIdx.y * K + k) * N * N + q] = num[k][i];
+    if constexpr (OP == PrbOp::Plain) a.part_den[(size_t)blockIdx.y * N * N + q] = den[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_probe_finish(ProbeFinishArgs a) {
+  __shared__ float redf[4];
+  const int nn = a.n * a.n;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  float dv = 0.f;
+  if (q < nn) {
+    for (int k = 0; k < a.k; ++k) {
+      float2 s = make_float2(0.f, 0.f);
+      for (int sl = 0; sl < a.slices; ++sl) s = s + a.part_num[((size_t)sl * a.k + k) * nn + q];
+      a.num[(size_t)k * nn + q] = s;
+    }
+    if (a.part_den) {
+      for (int sl = 0; sl < a.slices; ++sl) dv += a.part_den[(size_t)sl * nn + q];
+      a.den[q] = dv;
+    }
+  }
+  if (a.den_max) {
+    const float mx = block_max_all<256>(dv, redf);
+    if (threadIdx.x == 0) atomicMax(a.den_max, __float_as_uint(mx));
+  }
+}
+
+template <PrbApply OP>
+__global__ __launch_bounds__(256) void k_probe_apply(ProbeApplyArgs a) {
+  const int nn = a.n * a.n;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nn) return;
+  const float delta = a.gamma * __uint_as_float(*a.den_max);
+  const float d = a.den[q] + delta;
+  for (int k = 0; k < a.k; ++k) {
+    const size_t o = (size_t)k * nn + q;
+    if constexpr (OP == PrbApply::Dm) {
+      if (d > 0.f) a.probe[o] = (1.f / d) * (a.num[o] + delta * a.probe[o]);
+    } else if constexpr (OP == PrbApply::LsqDirection) {
+      a.dir[o] = d > 0.f ? (1.f / d) * a.num[o] : make_float2(0.f, 0.f);
+    } else {
+      if (d > 0.f) a.probe[o] = a.probe[o] + (a.beta / d) * a.num[o];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LSQML per-position step lengths (pass B)
+// ---------------------------------------------------------------------------
+template <int N>
+struct LsqPix {
+  static constexpr int PIX = (N * N >= 2048) ? 2048 : N * N;  // pixels per block
+  static constexpr int PPT = PIX / 256;
+  static constexpr int NRB = N * N / PIX;
+};
+
+template <int N, int K, bool PROBE_ON>
+__global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
+  constexpr int PPT = LsqPix<N>::PPT;
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  const int j = a.jlist[b];
+  const PosInfo p = a.pos[j];
+  float m00 = 0.f, m11 = 0.f, m01 = 0.f, v0 = 0.f, v1 = 0.f;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int q = blockIdx.x * LsqPix<N>::PIX + i * 256 + threadIdx.x;
+    const int u = q / N, v = q % N;
+    const float2 dob = obj_bilinear(a.dobj, a.h, a.w, p, u, v);
+    const float2 cb = a.contrib[(size_t)b * N * N + q];
+    v0 += dob.x * cb.x + dob.y * cb.y;  // Re(conj(S dO) sum_k conj(P_k) chi_k)
+    float2 ob = make_float2(0.f, 0.f);
+    if constexpr (PROBE_ON) ob = obj_bilinear(a.obj, a.h, a.w, p, u, v);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float2 av = cmul(a.probe[(size_t)k * N * N + q], dob);
+      m00 += cabs2(av);
+      if constexpr (PROBE_ON) {
+        const float2 bv = cmul(a.dprobe[(size_t)k * N * N + q], ob);
+        const float2 ch = a.chi[((size_t)b * K + k) * N * N + q];
+        m11 += cabs2(bv);
+        m01 += av.x * bv.x + av.y * bv.y;
+        v1 += bv.x * ch.x + bv.y * ch.y;
+      }
+    }
+  }
+  const double s[5] = {block_sum<256>(m00, red), block_sum<256>(m11, red), block_sum<256>(m01, red),
+                       block_sum<256>(v0, red), block_sum<256>(v1, red)};
+  if (threadIdx.x == 0) {
+    double* o = a.part + ((size_t)b * LsqPix<N>::NRB + blockIdx.x) * 5;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) o[i] = s[i];
+  }
+}
+
+__global__ void k_lsq_solve(LsqStepArgs a, int nrb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.count) return;
+  double s[5] = {0, 0, 0, 0, 0};
+  for (int r = 0; r < nrb; ++r)
+    for (int i = 0; i < 5; ++i) s[i] += a.part[((size_t)b * nrb + r) * 5 + i];
+  const double m00 = s[0], m11 = s[1], m01 = s[2], v0 = s[3], v1 = s[4];
+  const double mx = fmax(m00, m11);
+  double ao = 0.0, ap = 0.0;
+  if (mx > 0.0) {
+    const double eta = 1e-6 * mx;
+    if (!a.probe_on) {
+      ao = v0 / (m00 + eta);
+    } else {
+      const double a00 = m00 + eta, a11 = m11 + eta;
+      const double det = a00 * a11 - m01 * m01;
+      ao = (a11 * v0 - m01 * v1) / det;
+      ap = (a00 * v1 - m01 * v0) / det;
+    }
+  }
+  const float2 al = make_float2((float)ao, (float)ap);
+  a.alpha[b] = al;
+  a.alpha_by_j[a.jlist[b]] = al;
+}
+
+// ---------------------------------------------------------------------------
+// ePIE update of one position (one block; positions are sequential)
+// ---------------------------------------------------------------------------
+template <int N, int K>
+__global__ __launch_bounds__(1024) void k_epie_update(EpieArgs a) {
+  __shared__ float redf[16];
+  const PosInfo p = a.pos;
+  constexpr int NN = N * N;
+  float pm = 0.f, om = 0.f;
+  for (int q = threadIdx.x; q < NN; q += 1024) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += cabs2(a.probe[(size_t)k * NN + q]);
+    pm = fmaxf(pm, s);
+    om = fmaxf(om, cabs2(obj_bilinear(a.obj, a.h, a.w, p, q / N, q % N)));
+  }
+  const float pmax = block_max_all<1024>(pm, redf);
+  const float omax = block_max_all<1024>(om, redf);
+  // probe update with the pre-update object patch
+  const bool pu = a.probe_on && omax > 0.f;
+  const float bs = pu ? a.beta / omax : 0.f;
+  for (int q = threadIdx.x; q < NN; q += 1024) {
+    const float2 o = obj_bilinear(a.obj, a.h, a.w, p, q / N, q % N);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const size_t i = (size_t)k * NN + q;
+      a.probe_out[i] = a.probe[i] + bs * cconjmul(o, a.chi[i]);
+    }
+  }
+  __syncthreads();
+  if (!(pmax > 0.f)) return;
+  // object update over the (N+1)^2 footprint with the pre-update probe
+  const float as = a.alpha / pmax;
+  const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
+  for (int e = threadIdx.x; e < (N + 1) * (N + 1); e += 1024) {
+    const int u = e / (N + 1), v = e % (N + 1);
+    const int Y = p.iy + u, X = p.ix + v;
+    if (Y >= a.h || X >= a.w) continue;
+    float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int tap = 0; tap < 4; ++tap) {
+      const int uu = u - (tap >> 1), vv = v - (tap & 1);
+      if ((unsigned)uu >= (unsigned)N || (unsigned)vv >= (unsigned)N) continue;
+      const float wt = ((tap >> 1) ? wy1 : wy0) * ((tap & 1) ? wx1 : wx0);
+      float2 tv = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const size_t i = (size_t)k * NN + uu * N + vv;
+        tv = tv + cconjmul(a.probe[i], a.chi[i]);
+      }
+      s = s + wt * tv;
+    }
+    const size_t o = (size_t)Y * a.w + X;
+    a.obj[o] = a.obj[o] + as * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// DM exit-wave initialisation: psi_jk = P_k S_j O, contribution sum_k |P_k|^2 S_j O
+// ---------------------------------------------------------------------------
+template <int N, int K>
+__global__ __launch_bounds__(256) void k_dm_init(DmInitArgs a) {
+  const int j = blockIdx.y;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= N * N) return;
+  const PosInfo p = a.pos[j];
+  const float2 o = obj_bilinear(a.obj, a.h, a.w, p, q / N, q % N);
+  float2 c = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float2 pk = a.probe[(size_t)k * N * N + q];
+    const float2 ps = cmul(pk, o);
+    a.psi[((size_t)j * K + k) * N * N + q] = ps;
+    c = c + cconjmul(pk, ps);
+  }
+  a.contrib[(size_t)j * N * N + q] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Utilities
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(unsigned* p, size_t n, unsigned v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_amplitude(const float* __restrict__ cnt, float* __restrict__ amp, int n, size_t total) {
+  const size_t i = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (i >= total) return;
+  const size_t nn = (size_t)n * n;
+  const size_t j = i / nn;
+  const int pr = (int)((i % nn) / n), pc = (int)(i % n);
+  const int h = n / 2;
+  const float d = cnt[j * nn + (size_t)((pr + h) & (n - 1)) * n + ((pc + h) & (n - 1))];
+  amp[i] = sqrtf(fmaxf(d, 0.f));
+}
+
+__global__ __launch_bounds__(256) void k_pattern_totals(const float* __restrict__ x, double* totals, int n) {
+  __shared__ double red[4];
+  const size_t nn = (size_t)n * n;
+  const float* xp = x + blockIdx.x * nn;
+  double s = 0.0;
+  for (size_t i = threadIdx.x; i < nn; i += 256) s += fmaxf(xp[i], 0.f);
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) totals[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_probe_intensity(const float2* probe, float* pint, int n, int k) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const int nn = n * n;
+  if (q >= nn) return;
+  float s = 0.f;
+  for (int i = 0; i < k; ++i) s += cabs2(probe[(size_t)i * nn + q]);
+  pint[q] = s;
+}
+
+// Deterministic sum of `count` (num, den) partial pairs; out = num / den.
+__global__ __launch_bounds__(1024) void k_err_reduce(const double* errp, int count, double* out) {
+  __shared__ double red[16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < count; i += 1024) {
+    a += errp[2 * (size_t)i];
+    b += errp[2 * (size_t)i + 1];
+  }
+  a = block_sum<1024>(a, red);
+  b = block_sum<1024>(b, red);
+  if (threadIdx.x == 0) out[0] = b != 0.0 ? a / b : a;
+}
+
+__global__ void k_posgrad_reduce(const double* part, int count, int nrb, float* out, const int* jlist) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= count) return;
+  double gy = 0.0, gx = 0.0;
+  for (int r = 0; r < nrb; ++r) {
+    gy += part[((size_t)s * nrb + r) * 2];
+    gx += part[((size_t)s * nrb + r) * 2 + 1];
+  }
+  const int j = jlist[s];
+  out[2 * j] = (float)gy;
+  out[2 * j + 1] = (float)gx;
+}
+
+__global__ void k_scale_f32(float* p, size_t n, float s) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] *= s;
+}
+__global__ void k_scale_c64(float2* p, size_t n, float s) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = s * p[i];
+}
+
+inline unsigned grid_for(size_t n, unsigned bs, unsigned cap = 65535u * 4) {
+  size_t g = (n + bs - 1) / bs;
+  if (g < 1) g = 1;
+  return (unsigned)(g > cap ? cap : g);
+}
+
+}  // namespace
+
+void launch_obj_gather(const ObjGatherArgs& a, ObjOp op) {
+  if (a.ntiles <= 0) return;
+  dispatch_n(a.n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    switch (op) {
+      case ObjOp::Density: k_obj_gather<N, ObjOp::Density><<<a.ntiles, 256, 0, a.stream>>>(a); break;
+      case ObjOp::DmObject: k_obj_gather<N, ObjOp::DmObject><<<a.ntiles, 256, 0, a.stream>>>(a); break;
+      case ObjOp::LsqDirection: k_obj_gather<N, ObjOp::LsqDirection><<<a.ntiles, 256, 0, a.stream>>>(a); break;
+      case ObjOp::LsqUpdate: k_obj_gather<N, ObjOp::LsqUpdate><<<a.ntiles, 256, 0, a.stream>>>(a); break;
+      case ObjOp::Gradient: k_obj_gather<N, ObjOp::Gradient><<<a.ntiles, 256, 0, a.stream>>>(a); break;
+    }
+  });
+  PTY_LAUNCH_CHECK("obj_gather");
+}
+
+int probe_slices(int count, int per_slice) { return (count + per_slice - 1) / per_slice; }
+
+void launch_probe_acc(const ProbeAccArgs& a, PrbOp op) {
+  if (a.count <= 0) return;
+  dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    const dim3 grid(N * N / ProbePix<N>::PIX, probe_slices(a.count, a.per_slice));
+    switch (op) {
+      case PrbOp::Plain: k_probe_acc<N, K, PrbOp::Plain><<<grid, 256, 0, a.stream>>>(a); break;
+      case PrbOp::AlphaWeighted: k_probe_acc<N, K, PrbOp::AlphaWeighted><<<grid, 256, 0, a.stream>>>(a); break;
+      case PrbOp::Gradient: k_probe_acc<N, K, PrbOp::Gradient><<<grid, 256, 0, a.stream>>>(a); break;
+    }
+  });
+  PTY_LAUNCH_CHECK("probe_acc");
+}
+
+void launch_probe_finish(const ProbeFinishArgs& a) {
+  k_probe_finish<<<(a.n * a.n + 255) / 256, 256, 0, a.stream>>>(a);
+  PTY_LAUNCH_CHECK("probe_finish");
+}
+
+void launch_probe_apply(const ProbeApplyArgs& a, PrbApply op) {
+  const unsigned g = (a.n * a.n + 255) / 256;
+  switch (op) {
+    case PrbApply::Dm: k_probe_apply<PrbApply::Dm><<<g, 256, 0, a.stream>>>(a); break;
+    case PrbApply::LsqDirection: k_probe_apply<PrbApply::LsqDirection><<<g, 256, 0, a.stream>>>(a); break;
+    case PrbApply::LsqUpdate: k_probe_apply<PrbApply::LsqUpdate><<<g, 256, 0, a.stream>>>(a); break;
+  }
+  PTY_LAUNCH_CHECK("probe_apply");
+}
+
+void launch_lsq_steps(const LsqStepArgs& a) {
+  if (a.count <= 0) return;
+  int nrb = 0;
+  dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    nrb = LsqPix<N>::NRB;
+    const dim3 grid(LsqPix<N>::NRB, a.count);
+    if (a.probe_on)
+      k_lsq_sums<N, K, true><<<grid, 256, 0, a.stream>>>(a);
+    else
+      k_lsq_sums<N, K, false><<<grid, 256, 0, a.stream>>>(a);
+  });
+  PTY_LAUNCH_CHECK("lsq_sums");
+  k_lsq_solve<<<(a.count + 127) / 128, 128, 0, a.stream>>>(a, nrb);
+  PTY_LAUNCH_CHECK("lsq_solve");
+}
+
+void launch_epie_update(const EpieArgs& a) {
+  dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    k_epie_update<N, K><<<1, 1024, 0, a.stream>>>(a);
+  });
+  PTY_LAUNCH_CHECK("epie_update");
+}
+
+void launch_dm_init(const DmInitArgs& a) {
+  dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    const dim3 grid((N * N + 255) / 256, a.j);
+    k_dm_init<N, K><<<grid, 256, 0, a.stream>>>(a);
+  });
+  PTY_LAUNCH_CHECK("dm_init");
+}
+
+void launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s) {
+  if (n == 0) return;
+  k_fill_u32<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
+  PTY_LAUNCH_CHECK("fill");
+}
+
+void launch_amplitude(const float* counts, float* amp, double* totals, int n, int j, hipStream_t s) {
+  const size_t total = (size_t)j * n * n;
+  k_amplitude<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(counts, amp, n, total);
+  PTY_LAUNCH_CHECK("amplitude");
+  if (totals) launch_pattern_totals(counts, totals, n, j, s);
+}
+
+void launch_pattern_totals(const float* x, double* totals, int n, int j, hipStream_t s) {
+  k_pattern_totals<<<j, 256, 0, s>>>(x, totals, n);
+  PTY_LAUNCH_CHECK("pattern_totals");
+}
+
+void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s) {
+  k_probe_intensity<<<(n * n + 255) / 256, 256, 0, s>>>(probe, pint, n, k);
+  PTY_LAUNCH_CHECK("probe_intensity");
+}
+
+void launch_err_reduce(const double* errp, int count, double* out, hipStream_t s) {
+  k_err_reduce<<<1, 1024, 0, s>>>(errp, count, out);
+  PTY_LAUNCH_CHECK("err_reduce");
+}
+
+void launch_posgrad_reduce(const double* part, int count, int nrb, float* out, const int* jlist, hipStream_t s) {
+  if (count <= 0) return;
+  k_posgrad_reduce<<<(count + 127) / 128, 128, 0, s>>>(part, count, nrb, out, jlist);
+  PTY_LAUNCH_CHECK("posgrad_reduce");
+}
+
+void launch_scale_f32(float* p, size_t n, float s, hipStream_t st) {
+  if (n == 0) return;
+  k_scale_f32<<<grid_for(n, 256, 4096), 256, 0, st>>>(p, n, s);
+  PTY_LAUNCH_CHECK("scale_f32");
+}
+
+void launch_scale_c64(float2* p, size_t n, float s, hipStream_t st) {
+  if (n == 0) return;
+  k_scale_c64<<<grid_for(n, 256, 4096), 256, 0, st>>>(p, n, s);
+  PTY_LAUNCH_CHECK("scale_c64");
+}
+
+}  // namespace pty

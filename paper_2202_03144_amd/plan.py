@@ -1,0 +1,212 @@
+"""Python front end of the ptymi C ABI (argument marshalling only).
+
+Every step of a reconstruction runs in the HIP kernels behind
+``include/ptymi.h``; this module converts NumPy arrays or torch tensors into
+pointers and status codes into exceptions.  torch is used only for device
+memory and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import PtyError
+
+ALGOS = {"epie": L.EPIE, "dm": L.DM, "lsqml": L.LSQML}
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype, shape):
+    """(pointer, on_device, keepalive) for a NumPy array or torch tensor of the given layout."""
+    if _is_torch(x):
+        import torch
+
+        want = {np.float32: torch.float32, np.float64: torch.float64, np.complex64: torch.complex64}[dtype]
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {tuple(x.shape)}")
+        if x.dtype != want:
+            raise ValueError(f"expected dtype {want}, got {x.dtype}")
+        if x.is_cuda:
+            x = x.contiguous()
+            return C.c_void_p(x.data_ptr()), 1, x
+        x = x.detach().contiguous().numpy()
+    a = np.ascontiguousarray(x, dtype=dtype)
+    if a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a.ctypes.data_as(C.c_void_p), 0, a
+
+
+class Plan:
+    """One reconstruction context on one GPU.
+
+    Parameters mirror ``pty_plan_desc``: window ``n``, ``modes``, positions
+    ``n_pos``, object shape ``(H, W)``.  ``stream``: a HIP stream handle (an
+    int, or a ``torch.cuda.Stream``); None lets the library own its stream.
+    """
+
+    def __init__(self, n: int, modes: int, n_pos: int, obj_shape, device: int = 0, stream=None):
+        self._lib = L.lib()
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        desc = L.PlanDesc(int(n), int(modes), int(n_pos), int(obj_shape[0]), int(obj_shape[1]),
+                          int(device), C.c_void_p(stream) if stream else None, 0)
+        out = C.c_void_p()
+        st = self._lib.pty_create(C.byref(desc), C.byref(out))
+        if st != L.OK:
+            raise PtyError(st, self._lib.pty_last_error(None).decode())
+        self._ctx = out
+        self.n, self.modes, self.n_pos = int(n), int(modes), int(n_pos)
+        self.obj_shape = (int(obj_shape[0]), int(obj_shape[1]))
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st: int) -> None:
+        if st != L.OK:
+            raise PtyError(st, self._lib.pty_last_error(self._ctx).decode())
+
+    def _live(self):
+        if self._ctx is None:
+            raise PtyError(L.E_STATE, "plan is closed")
+        return self._ctx
+
+    @staticmethod
+    def default_params(**overrides) -> L.IterParams:
+        p = L.IterParams()
+        L.lib().pty_default_params(C.byref(p))
+        for k, v in overrides.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown iteration parameter {k!r}")
+            setattr(p, k, v)
+        return p
+
+    # -- inputs ------------------------------------------------------------
+    def load_patterns(self, counts) -> None:
+        """Photon counts (J, N, N) float32, zero frequency at (N/2, N/2)."""
+        ptr, dev, keep = _ptr(counts, np.float32, (self.n_pos, self.n, self.n))
+        self._check(self._lib.pty_load_patterns(self._live(), ptr, dev))
+        del keep
+
+    def load_positions(self, yx) -> None:
+        """Top-left corners (J, 2) float64 in object pixels."""
+        ptr, _, keep = _ptr(yx, np.float64, (self.n_pos, 2))
+        self._check(self._lib.pty_load_positions(self._live(), ptr))
+        del keep
+
+    def set_object(self, obj) -> None:
+        ptr, dev, keep = _ptr(obj, np.complex64, self.obj_shape)
+        self._check(self._lib.pty_set_object(self._live(), ptr, dev))
+        del keep
+
+    def set_probe(self, probe) -> None:
+        ptr, dev, keep = _ptr(probe, np.complex64, (self.modes, self.n, self.n))
+        self._check(self._lib.pty_set_probe(self._live(), ptr, dev))
+        del keep
+
+    # -- iteration ---------------------------------------------------------
+    def iterate(self, algo, n_iter: int = 1, **params) -> None:
+        """Enqueue ``n_iter`` iterations of 'epie', 'dm' or 'lsqml' (asynchronous)."""
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        p = self.default_params(**params)
+        self._check(self._lib.pty_iterate(self._live(), a, int(n_iter), C.byref(p)))
+
+    def sync(self) -> None:
+        self._check(self._lib.pty_sync(self._live()))
+
+    # -- outputs -----------------------------------------------------------
+    def _get(self, fn, shape, dtype, out):
+        if out is not None:
+            ptr, dev, keep = _ptr(out, dtype, shape)
+            self._check(fn(self._live(), ptr, dev))
+            if dev == 0 and _is_torch(out):
+                out.copy_(__import__("torch").from_numpy(keep))
+            return out
+        a = np.empty(shape, dtype=dtype)
+        self._check(fn(self._live(), a.ctypes.data_as(C.c_void_p), 0))
+        return a
+
+    def object(self, out=None):
+        return self._get(self._lib.pty_get_object, self.obj_shape, np.complex64, out)
+
+    def probe(self, out=None):
+        return self._get(self._lib.pty_get_probe, (self.modes, self.n, self.n), np.complex64, out)
+
+    def exit_waves(self, out=None):
+        return self._get(self._lib.pty_get_exit_waves, (self.n_pos, self.modes, self.n, self.n),
+                         np.complex64, out)
+
+    def errors(self) -> np.ndarray:
+        """Amplitude error E of every iteration so far (float64)."""
+        cap = 1 << 16
+        buf = np.empty(cap, dtype=np.float64)
+        n = C.c_int32()
+        self._check(self._lib.pty_get_errors(self._live(), buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
+        return buf[: n.value].copy()
+
+    def lsqml_steps(self) -> np.ndarray:
+        out = np.empty((self.n_pos, 2), dtype=np.float32)
+        self._check(self._lib.pty_get_lsqml_steps(self._live(), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def simulate(self, photons: float = 0.0, out=None):
+        """Expected counts (J, N, N), centred; rescales the probe if photons > 0."""
+        shape = (self.n_pos, self.n, self.n)
+        if out is not None:
+            ptr, dev, keep = _ptr(out, np.float32, shape)
+            self._check(self._lib.pty_simulate(self._live(), float(photons), ptr, dev))
+            return out
+        a = np.empty(shape, dtype=np.float32)
+        self._check(self._lib.pty_simulate(self._live(), float(photons), a.ctypes.data_as(C.c_void_p), 0))
+        return a
+
+    def set_timing(self, enable: bool = True) -> None:
+        """Clear the per-family kernel times and enable (or disable) event timing."""
+        self._check(self._lib.pty_set_timing(self._live(), 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """{family: (milliseconds, launches)} accumulated since set_timing(True)."""
+        nf = len(L.TIMING_FAMILIES)
+        ms = np.zeros(nf, dtype=np.float64)
+        cnt = np.zeros(nf, dtype=np.int64)
+        self._check(self._lib.pty_get_timing(self._live(), ms.ctypes.data_as(C.c_void_p),
+                                             cnt.ctypes.data_as(C.c_void_p), nf))
+        return {f: (float(ms[i]), int(cnt[i])) for i, f in enumerate(L.TIMING_FAMILIES)}
+
+    def mem_bytes(self) -> int:
+        v = C.c_size_t()
+        self._check(self._lib.pty_mem_bytes(self._live(), C.byref(v)))
+        return int(v.value)
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None) is not None:
+            self._lib.pty_destroy(self._ctx)
+            self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reconstruct(algo: str, counts, positions, obj, probe, n_iter: int, device: int = 0, **params):
+    """Whole-mode reconstruction (Sec. 3.2: run without returning between
+    iterations); returns (object, probe, errors) as NumPy arrays."""
+    counts_shape = tuple(counts.shape)
+    with Plan(counts_shape[-1], probe.shape[0], counts_shape[0], obj.shape, device=device) as pl:
+        pl.load_patterns(counts)
+        pl.load_positions(positions)
+        pl.set_object(obj)
+        pl.set_probe(probe)
+        pl.iterate(algo, n_iter, **params)
+        return pl.object(), pl.probe(), pl.errors()

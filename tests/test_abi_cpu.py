@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before touching a device, and reports a
+missing device as PTY_E_DEVICE."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_03144_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptymi.h")
+
+
+def _have_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pty_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    syms = header_symbols()
+    assert len(syms) >= 17
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def test_default_params():
+    p = L.IterParams()
+    assert L.lib().pty_default_params(C.byref(p)) == L.OK
+    assert (p.alpha, p.beta, p.lsqml_batch, p.beta_obj, p.beta_probe) == (1.0, 1.0, 512, 1.0, 1.0)
+    assert p.gamma_obj < 0 and p.gamma_probe < 0 and p.order_seed == 0 and p.chunk == 0
+    assert L.lib().pty_default_params(None) == L.E_INVALID
+
+
+@pytest.mark.parametrize("field,value", [("n", 48), ("n", 512), ("modes", 0), ("modes", 5), ("n_pos", 0),
+                                         ("obj_h", 64), ("flags", 1), ("device", -1)])
+def test_create_rejects_bad_plan_before_device(field, value):
+    d = L.PlanDesc(64, 1, 10, 160, 160, 0, None, 0)
+    setattr(d, field, value)
+    out = C.c_void_p()
+    assert L.lib().pty_create(C.byref(d), C.byref(out)) == L.E_INVALID
+    assert out.value is None
+    assert L.lib().pty_last_error(None)
+
+
+def test_null_arguments_are_invalid():
+    lib = L.lib()
+    assert lib.pty_create(None, None) == L.E_INVALID
+    for fn, args in [("pty_load_patterns", (None, None, 0)), ("pty_load_positions", (None, None)),
+                     ("pty_set_object", (None, None, 0)), ("pty_set_probe", (None, None, 0)),
+                     ("pty_iterate", (None, 1, 1, None)), ("pty_get_object", (None, None, 0)),
+                     ("pty_get_probe", (None, None, 0)), ("pty_sync", (None,)),
+                     ("pty_get_lsqml_steps", (None, None)), ("pty_get_exit_waves", (None, None, 0)),
+                     ("pty_simulate", (None, 0.0, None, 0))]:
+        assert getattr(lib, fn)(*args) == L.E_INVALID, fn
+    n = C.c_int32()
+    assert lib.pty_get_errors(None, None, 0, C.byref(n)) == L.E_INVALID
+    assert lib.pty_mem_bytes(None, None) == L.E_INVALID
+    lib.pty_destroy(None)  # NULL-safe
+
+
+@pytest.mark.skipif(_have_gpu(), reason="checks the no-device path")
+def test_create_without_device_reports_device_error():
+    d = L.PlanDesc(64, 1, 10, 160, 160, 0, None, 0)
+    out = C.c_void_p()
+    assert L.lib().pty_create(C.byref(d), C.byref(out)) == L.E_DEVICE
+    assert b"device" in L.lib().pty_last_error(None)
+    from paper_2202_03144_amd import Plan, PtyError
+    with pytest.raises(PtyError) as e:
+        Plan(64, 1, 10, (160, 160))
+    assert e.value.status == L.E_DEVICE
+
+
+def test_product_path_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_2202_03144_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "ptysynth" not in text, f
