@@ -93,6 +93,8 @@ struct pty_ctx {
   float2* num_p2 = nullptr;
   float* den_p = nullptr;
   float2* dprobe = nullptr;
+  float2* lsq_pq = nullptr;
+  float* lsq_dint = nullptr;
   double* lsq_part = nullptr;      size_t lsq_part_n = 0;
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
@@ -570,7 +572,9 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   c->ensure_once(c->dobj, size_t(c->H) * c->W);
   c->ensure(c->alpha, c->alpha_slots, size_t(bmax));
   c->ensure_once(c->alpha_by_j, size_t(c->J));
-  int nrb = std::max(1, c->N * c->N / 2048);
+  const int nrb = c->N * c->N >= 2048 ? c->N * c->N / 2048 : 1;  // row blocks of the step sums
+  c->ensure_once(c->lsq_pq, nn);
+  c->ensure_once(c->lsq_dint, nn);
   c->ensure(c->lsq_part, c->lsq_part_n, size_t(bmax) * nrb * 5);
   ensure_probe_parts(c, bmax);
   ensure_err_slot(c, n_iter);
@@ -601,6 +605,9 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       ls.dprobe = c->dprobe;
       ls.chi = c->chi;
       ls.contrib = c->contrib;
+      ls.pint = c->pint;
+      ls.pq = c->lsq_pq;
+      ls.dint = c->lsq_dint;
       ls.jlist = g.d_jl;
       ls.pos = c->pos;
       ls.count = count;

@@ -26,8 +26,8 @@ struct PatchRef {
   int slot, j;
 };
 
-constexpr int kTileH = 8;    // object tile height (rows)
-constexpr int kTileW = 64;   // object tile width (columns)
+constexpr int kTileH = 16;   // object tile height (rows): one thread walks a column of the tile
+constexpr int kTileW = 64;   // object tile width (columns): one wavefront per tile
 
 struct DeviceError : std::runtime_error {
   explicit DeviceError(const std::string& m) : std::runtime_error(m) {}

@@ -135,11 +135,21 @@ struct LineLds {
   static constexpr int words = R * (T + 1);
 };
 
-// One length-N line transform held by T threads (t = index within the line).
+// Orders LDS traffic between the lanes of one wavefront.  A wavefront's LDS
+// instructions execute in issue order, so a fence that keeps the compiler from
+// moving them across this point is all the exchange inside one wave needs.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One length-N line transform held by T threads (t = index within the line),
+// unscaled (forward: sum x e^{-2 pi i ...}; inverse: sum x e^{+2 pi i ...}).
+// The T threads of a line must be consecutive lanes of one wavefront: the
+// exchange is synchronised at wave level only.
 // `buf`: this line's LDS exchange area (LineLds<N>::words float2).
 // `tw`: W_N^i = exp(-2 pi i i / N), i = 0..N-1 (LDS or global).
-// Every thread of the block must call this the same number of times: it
-// contains block barriers.
 template <int N, bool INV>
 __device__ __forceinline__ void line_fft(float2* v, float2* buf, const float2* tw, int t) {
   constexpr int R = FftShape<N>::R, T = FftShape<N>::T;
@@ -150,9 +160,10 @@ __device__ __forceinline__ void line_fft(float2* v, float2* buf, const float2* t
     if (INV) w.y = -w.y;
     v[q] = cmul(v[q], w);
   }
+  static_assert(64 % T == 0, "a line must not straddle wavefronts");
 #pragma unroll
   for (int q = 0; q < R; ++q) buf[q * (T + 1) + t] = v[q];
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int i = 0; i < R / T; ++i) {
     float2 u[T];
@@ -163,7 +174,7 @@ __device__ __forceinline__ void line_fft(float2* v, float2* buf, const float2* t
 #pragma unroll
     for (int s = 0; s < T; ++s) v[i + (R / T) * s] = u[s];
   }
-  __syncthreads();
+  wave_sync();
 }
 
 }  // namespace pty

@@ -21,6 +21,15 @@
 namespace pty {
 namespace {
 
+// Scratch layout of one pattern-mode: 4-column blocks, [x / 4][y][x % 4].
+// Row passes (16 lanes per row, 4 rows per wavefront) touch 128-byte runs;
+// the column pass (16 lanes per column, 4 adjacent columns per wavefront)
+// reads and writes 512 contiguous bytes per instruction.
+template <int N>
+__device__ __forceinline__ size_t zoff(int y, int x) {
+  return ((size_t)(x >> 2) * N + y) * 4 + (x & 3);
+}
+
 template <int N, int K, RowIn MODE>
 __global__ __launch_bounds__(Geo<N>::BS) void k_rows_fwd(FourierArgs a) {
   using G = Geo<N>;
@@ -37,7 +46,8 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_rows_fwd(FourierArgs a) {
   float2 o[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
-#pragma unroll
+  // one mode at a time keeps the register footprint at one line per thread
+#pragma unroll 1
   for (int k = 0; k < K; ++k) {
     float2 z[R];
     const float2* pr = a.probe + ((size_t)k * N + y) * N;
@@ -49,9 +59,9 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_rows_fwd(FourierArgs a) {
       for (int m = 0; m < R; ++m) z[m] = 2.f * z[m] - ps[t + T * m];
     }
     line_fft<N, false>(z, xb + line * G::W, tw_s, t);
-    float2* out = a.zs + (((size_t)c * K + k) * N + y) * N;
+    float2* out = a.zs + ((size_t)c * K + k) * N * N;
 #pragma unroll
-    for (int m = 0; m < R; ++m) out[t + T * m] = z[m];
+    for (int m = 0; m < R; ++m) out[zoff<N>(y, t + T * m)] = z[m];
   }
 }
 
@@ -63,37 +73,38 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
   __shared__ float2 xb[CW * G::W];
   __shared__ double red[G::BS / 64];
   load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
-  const int col = threadIdx.x % CW, t = threadIdx.x / CW;
+  // each column's T threads are consecutive lanes of one wavefront
+  const int col = threadIdx.x / T, t = threadIdx.x % T;
   const int c = blockIdx.y, x = blockIdx.x * CW + col;
-  const int slot = a.slot_off + c;
   const int j = a.jlist[a.jl_off + c];
+  float2* base = a.zs + (size_t)c * K * N * N;
   float2 z[K][R];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float2* src = a.zs + ((size_t)c * K + k) * N * N + x;
 #pragma unroll
-    for (int m = 0; m < R; ++m) z[k][m] = src[(size_t)(t + T * m) * N];
+    for (int m = 0; m < R; ++m) z[k][m] = base[(size_t)k * N * N + zoff<N>(t + T * m, x)];
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) line_fft<N, false>(z[k], xb + col * G::W, tw_s, t);
-  const float sc = 1.0f / N;  // the unitary 2-D forward scale
+  // The transforms are unscaled: the unitary far field is z / N and the
+  // unitary inverse of the whole pipeline contributes another 1 / N^2, both
+  // folded into the per-pixel factor applied before the inverse transforms.
+  constexpr float sc = 1.0f / N, sc2 = 1.0f / (float(N) * float(N));
   float e_num = 0.f, e_den = 0.f;
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int pr = t + T * m;
-    float inten = 0.f;
+    float iraw = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      z[k][m] = sc * z[k][m];
-      inten += cabs2(z[k][m]);
-    }
+    for (int k = 0; k < K; ++k) iraw += cabs2(z[k][m]);
+    const float inten = iraw * sc2;
     if constexpr (OP == ColOp::Intensity) {
       a.intensity_out[((size_t)j * N + ((pr + N / 2) & (N - 1))) * N + ((x + N / 2) & (N - 1))] = inten;
     } else {
       const float am = a.amp[((size_t)j * N + pr) * N + x];
       float f;
       if constexpr (OP == ColOp::Project) {
-        const float mod = sqrtf(inten);
+        const float mod = sqrtf(iraw) * sc;
         f = am / fmaxf(mod, 1e-6f) - 1.f;
         e_num += (mod - am) * (mod - am);
         e_den += am * am;
@@ -102,6 +113,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
         f = 1.f - d / (inten + a.nll_eps);
         e_num += inten - d * logf(inten + a.nll_eps);
       }
+      f *= sc2;
 #pragma unroll
       for (int k = 0; k < K; ++k) z[k][m] = f * z[k][m];
     }
@@ -111,9 +123,8 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
     for (int k = 0; k < K; ++k) line_fft<N, true>(z[k], xb + col * G::W, tw_s, t);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      float2* dst = a.zs + ((size_t)c * K + k) * N * N + x;
 #pragma unroll
-      for (int m = 0; m < R; ++m) dst[(size_t)(t + T * m) * N] = z[k][m];
+      for (int m = 0; m < R; ++m) base[(size_t)k * N * N + zoff<N>(t + T * m, x)] = z[k][m];
     }
     const double s0 = block_sum<G::BS>((double)e_num, red);
     const double s1 = block_sum<G::BS>((double)e_den, red);
@@ -139,71 +150,63 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_rows_inv(FourierArgs a) {
   const int slot = a.slot_off + c;
   const int j = a.jlist[a.jl_off + c];
   const PosInfo p = a.pos[j];
-  const float sc = 1.0f / N;  // the unitary 2-D inverse scale
-  float2 z[K][R];
+  // the column pass already applied the unitary scales of both transforms
+  float2 o[MODE == RowOut::DmUpdate ? R : 1];
+  float2 gdy[MODE == RowOut::NllGrad ? R : 1], gdx[MODE == RowOut::NllGrad ? R : 1];
+  if constexpr (MODE == RowOut::DmUpdate) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const float2* src = a.zs + (((size_t)c * K + k) * N + y) * N;
+    for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
+  }
+  if constexpr (MODE == RowOut::NllGrad) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) z[k][m] = src[t + T * m];
-    line_fft<N, true>(z[k], xb + line * G::W, tw_s, t);
-#pragma unroll
-    for (int m = 0; m < R; ++m) z[k][m] = sc * z[k][m];
+    for (int m = 0; m < R; ++m) obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, gdy[m], gdx[m]);
   }
   float2 cacc[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) cacc[m] = make_float2(0.f, 0.f);
-  if constexpr (MODE == RowOut::DmUpdate) {
-    float2 o[R];
+  float gy = 0.f, gx = 0.f;
+  // one mode at a time keeps the register footprint at one line per thread
+#pragma unroll 1
+  for (int k = 0; k < K; ++k) {
+    float2 z[R];
+    const float2* src = a.zs + ((size_t)c * K + k) * N * N;
 #pragma unroll
-    for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float2* pr = a.probe + ((size_t)k * N + y) * N;
+    for (int m = 0; m < R; ++m) z[m] = src[zoff<N>(y, t + T * m)];
+    line_fft<N, true>(z, xb + line * G::W, tw_s, t);
+    const float2* pr = a.probe + ((size_t)k * N + y) * N;
+    if constexpr (MODE == RowOut::DmUpdate) {
       float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         const float2 pk = pr[t + T * m];
-        const float2 nw = cmul(pk, o[m]) + z[k][m];
+        const float2 nw = cmul(pk, o[m]) + z[m];
         ps[t + T * m] = nw;
         cacc[m] = cacc[m] + cconjmul(pk, nw);
       }
-    }
-  } else {
-    const float gscale = (MODE == RowOut::NllGrad) ? 2.f : 1.f;
-    float gy = 0.f, gx = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float2* pr = a.probe + ((size_t)k * N + y) * N;
+    } else {
+      const float gscale = (MODE == RowOut::NllGrad) ? 2.f : 1.f;
       float2* ch = a.chi + (((size_t)slot * K + k) * N + y) * N;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         const float2 pk = pr[t + T * m];
-        ch[t + T * m] = z[k][m];
-        cacc[m] = cacc[m] + gscale * cconjmul(pk, z[k][m]);
-      }
-    }
-    if constexpr (MODE == RowOut::NllGrad) {
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        float2 dy, dx;
-        obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, dy, dx);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float2 pk = a.probe[((size_t)k * N + y) * N + t + T * m];
-          const float2 gpy = cmul(pk, dy), gpx = cmul(pk, dx);
+        ch[t + T * m] = z[m];
+        cacc[m] = cacc[m] + gscale * cconjmul(pk, z[m]);
+        if constexpr (MODE == RowOut::NllGrad) {
+          const float2 gpy = cmul(pk, gdy[m]), gpx = cmul(pk, gdx[m]);
           // Re(conj(g_psi) * P_k * d(S_j O))
-          gy += z[k][m].x * gpy.x + z[k][m].y * gpy.y;
-          gx += z[k][m].x * gpx.x + z[k][m].y * gpx.y;
+          gy += z[m].x * gpy.x + z[m].y * gpy.y;
+          gx += z[m].x * gpx.x + z[m].y * gpx.y;
         }
       }
-      const double sy = block_sum<G::BS>(2.0 * gy, red);
-      const double sx = block_sum<G::BS>(2.0 * gx, red);
-      if (threadIdx.x == 0) {
-        double* g = a.posgrad + ((size_t)slot * (N / G::LINES) + blockIdx.x) * 2;
-        g[0] = sy;
-        g[1] = sx;
-      }
+    }
+  }
+  if constexpr (MODE == RowOut::NllGrad) {
+    const double sy = block_sum<G::BS>(2.0 * gy, red);
+    const double sx = block_sum<G::BS>(2.0 * gx, red);
+    if (threadIdx.x == 0) {
+      double* g = a.posgrad + ((size_t)slot * (N / G::LINES) + blockIdx.x) * 2;
+      g[0] = sy;
+      g[1] = sx;
     }
   }
   float2* cb = a.contrib + ((size_t)slot * N + y) * N;

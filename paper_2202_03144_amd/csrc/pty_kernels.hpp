@@ -118,6 +118,9 @@ struct LsqStepArgs {
   const float2* dprobe;
   const float2* chi;
   const float2* contrib;
+  const float* pint;       // N x N scratch: sum_k |P_k|^2
+  const float2* pq;        // N x N scratch: sum_k conj(P_k) dP_k
+  const float* dint;       // N x N scratch: sum_k |dP_k|^2
   const int* jlist;
   const PosInfo* pos;
   int count;

@@ -17,72 +17,110 @@ namespace {
 // ---------------------------------------------------------------------------
 // Object tiles: sum_j S_j^T (.) in gather form, then the algorithm's update
 // ---------------------------------------------------------------------------
+// One block of four wavefronts per 16 x 64 tile; lane = column, and the
+// wavefronts split the tile's patch list.  For each patch the thread walks its
+// column downwards: the horizontal combination of patch row u (taps v and
+// v - 1) is computed once and used for object rows u and u + 1, so each patch
+// row is read once per tile column.
+template <typename V>
+struct Zero;
+template <>
+struct Zero<float> { __device__ static float v() { return 0.f; } };
+template <>
+struct Zero<float2> { __device__ static float2 v() { return make_float2(0.f, 0.f); } };
+
+__device__ __forceinline__ float2 axpy(float a, float2 x, float2 y) { return make_float2(fmaf(a, x.x, y.x), fmaf(a, x.y, y.y)); }
+__device__ __forceinline__ float axpy(float a, float x, float y) { return fmaf(a, x, y); }
+
+template <int N, typename V>
+__device__ __forceinline__ V hrow(const V* __restrict__ src, int u, int v, bool v0ok, bool v1ok, float wx0, float wx1) {
+  V s = Zero<V>::v();
+  if ((unsigned)u < (unsigned)N) {
+    const V* r = src + u * N;
+    if (v0ok) s = axpy(wx0, r[v], s);
+    if (v1ok) s = axpy(wx1, r[v - 1], s);
+  }
+  return s;
+}
+
 template <int N, ObjOp OP>
 __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
-  constexpr int ROWS = 256 / kTileW;   // rows covered per sweep
-  constexpr int PR = kTileH / ROWS;    // pixels per thread
+  using V = typename std::conditional<OP == ObjOp::Density, float, float2>::type;
+  constexpr int TH = kTileH;
+  constexpr int NW = 4;  // wavefronts per tile; wave w takes every NW-th patch
+  __shared__ V part[NW - 1][TH][kTileW];
   __shared__ float redf[4];
   const TileEntry te = a.tiles[blockIdx.x];
-  const int cx = threadIdx.x % kTileW, ry = threadIdx.x / kTileW;
-  const int X = te.tx + cx;
-  float2 acc[PR];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int X = te.tx + lane;
+  V acc[TH];
 #pragma unroll
-  for (int i = 0; i < PR; ++i) acc[i] = make_float2(0.f, 0.f);
-  for (int e = te.beg; e < te.end; ++e) {
+  for (int i = 0; i < TH; ++i) acc[i] = Zero<V>::v();
+  for (int e = te.beg + wv; e < te.end; e += NW) {
     const PatchRef r = a.refs[e];
     const PosInfo p = a.pos[r.j];
     float wgt = 1.f;
     if constexpr (OP == ObjOp::LsqUpdate) wgt = a.alpha[r.slot].x;
+    const V* src;
+    if constexpr (OP == ObjOp::Density)
+      src = a.pint;
+    else
+      src = a.src + (size_t)r.slot * N * N;
     const int v = X - p.ix;
-    const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
     const bool v0ok = (unsigned)v < (unsigned)N, v1ok = (unsigned)(v - 1) < (unsigned)N;
+    const float wx0 = 1.f - p.fx, wx1 = p.fx;
+    const float wy0 = wgt * (1.f - p.fy), wy1 = wgt * p.fy;
+    const int u0 = te.ty - p.iy;
+    V prev = hrow<N, V>(src, u0 - 1, v, v0ok, v1ok, wx0, wx1);
 #pragma unroll
-    for (int i = 0; i < PR; ++i) {
-      const int u = te.ty + ry + ROWS * i - p.iy;
-      const bool u0ok = (unsigned)u < (unsigned)N, u1ok = (unsigned)(u - 1) < (unsigned)N;
-      float2 s = make_float2(0.f, 0.f);
-      if constexpr (OP == ObjOp::Density) {
-        const float* src = a.pint;
-        float d = 0.f;
-        if (u0ok && v0ok) d += wy0 * wx0 * src[u * N + v];
-        if (u0ok && v1ok) d += wy0 * wx1 * src[u * N + v - 1];
-        if (u1ok && v0ok) d += wy1 * wx0 * src[(u - 1) * N + v];
-        if (u1ok && v1ok) d += wy1 * wx1 * src[(u - 1) * N + v - 1];
-        s.x = d;
-      } else {
-        const float2* src = a.src + (size_t)r.slot * N * N;
-        if (u0ok && v0ok) s = s + (wy0 * wx0) * src[u * N + v];
-        if (u0ok && v1ok) s = s + (wy0 * wx1) * src[u * N + v - 1];
-        if (u1ok && v0ok) s = s + (wy1 * wx0) * src[(u - 1) * N + v];
-        if (u1ok && v1ok) s = s + (wy1 * wx1) * src[(u - 1) * N + v - 1];
-      }
-      acc[i] = acc[i] + wgt * s;
+    for (int i = 0; i < TH; ++i) {
+      const V cur = hrow<N, V>(src, u0 + i, v, v0ok, v1ok, wx0, wx1);
+      acc[i] = axpy(wy0, cur, axpy(wy1, prev, acc[i]));
+      prev = cur;
     }
   }
-  float mx = 0.f;
-  const float dmax = (OP == ObjOp::Density || OP == ObjOp::Gradient) ? 0.f : __uint_as_float(*a.den_max);
-  const float delta = a.gamma * dmax;
+  // combine the wavefronts' partial sums in a fixed order (wave 0 + 1 + 2 + 3)
+  if (wv > 0) {
 #pragma unroll
-  for (int i = 0; i < PR; ++i) {
-    const int Y = te.ty + ry + ROWS * i;
+    for (int i = 0; i < TH; ++i) part[wv - 1][i][lane] = acc[i];
+  }
+  __syncthreads();
+  // each wave applies TH / NW rows of the tile
+  float mx = 0.f;
+  float delta = 0.f;
+  if constexpr (OP != ObjOp::Density && OP != ObjOp::Gradient) delta = a.gamma * __uint_as_float(*a.den_max);
+  if (wv == 0) {
+#pragma unroll
+    for (int i = 0; i < TH; ++i) {
+#pragma unroll
+      for (int w = 0; w < NW - 1; ++w) acc[i] = acc[i] + part[w][i][lane];
+      part[0][i][lane] = acc[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ii = 0; ii < TH / NW; ++ii) {
+    const int i = wv * (TH / NW) + ii;
+    const V val = part[0][i][lane];
+    const int Y = te.ty + i;
     if (Y >= a.h || X >= a.w) continue;
     const size_t o = (size_t)Y * a.w + X;
     if constexpr (OP == ObjOp::Density) {
-      a.den[o] = acc[i].x;
-      mx = fmaxf(mx, acc[i].x);
+      a.den[o] = val;
+      mx = fmaxf(mx, val);
     } else if constexpr (OP == ObjOp::Gradient) {
-      a.out[o] = acc[i];
+      a.out[o] = val;
     } else {
       const float d = a.den[o] + delta;
       if constexpr (OP == ObjOp::DmObject) {
         if (d > 0.f) {
           const float2 ov = a.obj[o];
-          a.obj[o] = (1.f / d) * (acc[i] + delta * ov);
+          a.obj[o] = (1.f / d) * (val + delta * ov);
         }
       } else if constexpr (OP == ObjOp::LsqDirection) {
-        a.out[o] = d > 0.f ? (1.f / d) * acc[i] : make_float2(0.f, 0.f);
+        a.out[o] = d > 0.f ? (1.f / d) * val : make_float2(0.f, 0.f);
       } else {
-        if (d > 0.f) a.obj[o] = a.obj[o] + (a.beta / d) * acc[i];
+        if (d > 0.f) a.obj[o] = a.obj[o] + (a.beta / d) * val;
       }
     }
   }
@@ -95,25 +133,46 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
 // ---------------------------------------------------------------------------
 // Probe reductions over positions: sum_j w_j conj(S_j O) src_jk and sum_j |S_j O|^2
 // ---------------------------------------------------------------------------
+// Pixel mapping shared by the probe sums and the LSQML step sums: a block of
+// 256 threads covers G = 256 / N column groups; thread (column v, group)
+// walks RB consecutive rows u0 .. u0 + RB - 1, so the object rows under a
+// patch are read once and used for two bilinear rows.
+template <int N, int RB>
+struct ColWalk {
+  static constexpr int G = 256 / N;               // row groups per block
+  static constexpr int ROWS = G * RB;             // rows per block
+  static constexpr int BLOCKS = N / ROWS;         // blocks per window
+  static_assert(N % ROWS == 0 && BLOCKS >= 1, "window must tile");
+};
+
+// Horizontal bilinear combination of object row r at columns c0, c0 + 1
+// (the second clamped; it then has zero weight, as in obj_bilinear).
+__device__ __forceinline__ float2 obj_hrow(const float2* __restrict__ o, int h, int w, int r, int c0, float wx0,
+                                           float wx1) {
+  r = min(r, h - 1);
+  const int c1 = min(c0 + 1, w - 1);
+  const float2 a = o[(size_t)r * w + c0], b = o[(size_t)r * w + c1];
+  return make_float2(wx0 * a.x + wx1 * b.x, wx0 * a.y + wx1 * b.y);
+}
+
 template <int N>
 struct ProbePix {
-  static constexpr int PPT = (N * N >= 1024) ? 4 : 1;
-  static constexpr int PIX = 256 * PPT;  // pixels per block
+  static constexpr int RB = (N >= 64) ? 8 : 4;
+  using W = ColWalk<N, RB>;
 };
 
 template <int N, int K, PrbOp OP>
 __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
-  constexpr int PPT = ProbePix<N>::PPT;
+  using W = typename ProbePix<N>::W;
+  constexpr int RB = ProbePix<N>::RB;
   const int s_beg = a.s0 + blockIdx.y * a.per_slice;
   const int s_end = min(s_beg + a.per_slice, a.s0 + a.count);
-  float2 num[K][PPT];
-  float den[PPT];
-  int qu[PPT], qv[PPT];
+  const int v = threadIdx.x % N;
+  const int u0 = (blockIdx.x * W::G + threadIdx.x / N) * RB;
+  float2 num[K][RB];
+  float den[RB];
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int q = blockIdx.x * ProbePix<N>::PIX + i * 256 + threadIdx.x;
-    qu[i] = q / N;
-    qv[i] = q % N;
+  for (int i = 0; i < RB; ++i) {
     den[i] = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) num[k][i] = make_float2(0.f, 0.f);
@@ -124,20 +183,23 @@ __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
     float w = 1.f;
     if constexpr (OP == PrbOp::AlphaWeighted) w = a.alpha[s].y;
     if constexpr (OP == PrbOp::Gradient) w = 2.f;
-    const float2* src = a.src + (size_t)(a.src_by_pattern ? j : s) * K * N * N;
+    const float2* src = a.src + (size_t)(a.src_by_pattern ? j : s) * K * N * N + u0 * N + v;
+    const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
+    float2 top = obj_hrow(a.obj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const float2 o = obj_bilinear(a.obj, a.h, a.w, p, qu[i], qv[i]);
+    for (int i = 0; i < RB; ++i) {
+      const float2 bot = obj_hrow(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
+      const float2 o = make_float2(wy0 * top.x + wy1 * bot.x, wy0 * top.y + wy1 * bot.y);
+      top = bot;
       if constexpr (OP == PrbOp::Plain) den[i] += cabs2(o);
       const float2 ow = w * o;
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        num[k][i] = num[k][i] + cconjmul(ow, src[(size_t)k * N * N + qu[i] * N + qv[i]]);
+      for (int k = 0; k < K; ++k) num[k][i] = num[k][i] + cconjmul(ow, src[(size_t)k * N * N + i * N]);
     }
   }
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int q = qu[i] * N + qv[i];
+  for (int i = 0; i < RB; ++i) {
+    const int q = (u0 + i) * N + v;
 #pragma unroll
     for (int k = 0; k < K; ++k) a.part_num[((size_t)blockIdx.y * K + k) * N * N + q] = num[k][i];
     if constexpr (OP == PrbOp::Plain) a.part_den[(size_t)blockIdx.y * N * N + q] = den[i];
@@ -190,43 +252,96 @@ __global__ __launch_bounds__(256) void k_probe_apply(ProbeApplyArgs a) {
 // ---------------------------------------------------------------------------
 template <int N>
 struct LsqPix {
-  static constexpr int PIX = (N * N >= 2048) ? 2048 : N * N;  // pixels per block
-  static constexpr int PPT = PIX / 256;
-  static constexpr int NRB = N * N / PIX;
+  static constexpr int RB = (N * N >= 2048) ? 8 : 4;
+  using W = ColWalk<N, RB>;
+  static constexpr int NRB = W::BLOCKS;
 };
 
+// Deterministic block sum of five doubles; valid in thread 0.
+__device__ __forceinline__ void block_sum5(double (&v)[5], double* sh /* 5 * 4 */) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sh[i * 4 + wid] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) v[i] = sh[i * 4] + sh[i * 4 + 1] + sh[i * 4 + 2] + sh[i * 4 + 3];
+}
+
+// Per-pixel probe quantities of one LSQML group: sum_k |P_k|^2,
+// sum_k conj(P_k) dP_k and sum_k |dP_k|^2.
+__global__ __launch_bounds__(256) void k_lsq_planes(const float2* probe, const float2* dprobe, int n, int k,
+                                                    int probe_on, float* pint, float2* pq, float* dint) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const int nn = n * n;
+  if (q >= nn) return;
+  float a = 0.f, d = 0.f;
+  float2 c = make_float2(0.f, 0.f);
+  for (int i = 0; i < k; ++i) {
+    const float2 pk = probe[(size_t)i * nn + q];
+    a += cabs2(pk);
+    if (probe_on) {
+      const float2 dk = dprobe[(size_t)i * nn + q];
+      d += cabs2(dk);
+      c = c + cconjmul(pk, dk);
+    }
+  }
+  pint[q] = a;
+  pq[q] = c;
+  dint[q] = d;
+}
+
+// Five sums of one (position, row block): with a_k = P_k S dO, b_k = dP_k S O,
+// |a|^2 = |S dO|^2 sum|P_k|^2, |b|^2 = |S O|^2 sum|dP_k|^2,
+// Re conj(a) b = Re conj(S dO) S O sum conj(P_k) dP_k,
+// Re conj(a) chi = Re conj(S dO) sum_k conj(P_k) chi_k (the stored contribution),
+// Re conj(b) chi = Re conj(S O) sum_k conj(dP_k) chi_k.
 template <int N, int K, bool PROBE_ON>
 __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
-  constexpr int PPT = LsqPix<N>::PPT;
-  __shared__ double red[4];
+  using W = typename LsqPix<N>::W;
+  constexpr int RB = LsqPix<N>::RB;
+  __shared__ double red[20];
   const int b = blockIdx.y;
   const int j = a.jlist[b];
   const PosInfo p = a.pos[j];
+  const int v = threadIdx.x % N;
+  const int u0 = (blockIdx.x * W::G + threadIdx.x / N) * RB;
+  const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
   float m00 = 0.f, m11 = 0.f, m01 = 0.f, v0 = 0.f, v1 = 0.f;
+  float2 dtop = obj_hrow(a.dobj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
+  float2 otop = make_float2(0.f, 0.f);
+  if constexpr (PROBE_ON) otop = obj_hrow(a.obj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int q = blockIdx.x * LsqPix<N>::PIX + i * 256 + threadIdx.x;
-    const int u = q / N, v = q % N;
-    const float2 dob = obj_bilinear(a.dobj, a.h, a.w, p, u, v);
+  for (int i = 0; i < RB; ++i) {
+    const int q = (u0 + i) * N + v;
+    const float2 dbot = obj_hrow(a.dobj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
+    const float2 dob = make_float2(wy0 * dtop.x + wy1 * dbot.x, wy0 * dtop.y + wy1 * dbot.y);
+    dtop = dbot;
     const float2 cb = a.contrib[(size_t)b * N * N + q];
-    v0 += dob.x * cb.x + dob.y * cb.y;  // Re(conj(S dO) sum_k conj(P_k) chi_k)
-    float2 ob = make_float2(0.f, 0.f);
-    if constexpr (PROBE_ON) ob = obj_bilinear(a.obj, a.h, a.w, p, u, v);
+    m00 += cabs2(dob) * a.pint[q];
+    v0 += dob.x * cb.x + dob.y * cb.y;
+    if constexpr (PROBE_ON) {
+      const float2 obot = obj_hrow(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
+      const float2 ob = make_float2(wy0 * otop.x + wy1 * obot.x, wy0 * otop.y + wy1 * obot.y);
+      otop = obot;
+      m11 += cabs2(ob) * a.dint[q];
+      const float2 pq = a.pq[q];
+      const float2 dc = cconjmul(dob, ob);  // conj(S dO) S O
+      m01 += dc.x * pq.x - dc.y * pq.y;     // Re(dc * pq)
+      float2 t = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float2 av = cmul(a.probe[(size_t)k * N * N + q], dob);
-      m00 += cabs2(av);
-      if constexpr (PROBE_ON) {
-        const float2 bv = cmul(a.dprobe[(size_t)k * N * N + q], ob);
-        const float2 ch = a.chi[((size_t)b * K + k) * N * N + q];
-        m11 += cabs2(bv);
-        m01 += av.x * bv.x + av.y * bv.y;
-        v1 += bv.x * ch.x + bv.y * ch.y;
-      }
+      for (int k = 0; k < K; ++k)
+        t = t + cconjmul(a.dprobe[(size_t)k * N * N + q], a.chi[((size_t)b * K + k) * N * N + q]);
+      v1 += ob.x * t.x + ob.y * t.y;        // Re(conj(S O) t)
     }
   }
-  const double s[5] = {block_sum<256>(m00, red), block_sum<256>(m11, red), block_sum<256>(m01, red),
-                       block_sum<256>(v0, red), block_sum<256>(v1, red)};
+  double s[5] = {m00, m11, m01, v0, v1};
+  block_sum5(s, red);
   if (threadIdx.x == 0) {
     double* o = a.part + ((size_t)b * LsqPix<N>::NRB + blockIdx.x) * 5;
 #pragma unroll
@@ -437,7 +552,7 @@ void launch_probe_acc(const ProbeAccArgs& a, PrbOp op) {
   if (a.count <= 0) return;
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
-    const dim3 grid(N * N / ProbePix<N>::PIX, probe_slices(a.count, a.per_slice));
+    const dim3 grid(ProbePix<N>::W::BLOCKS, probe_slices(a.count, a.per_slice));
     switch (op) {
       case PrbOp::Plain: k_probe_acc<N, K, PrbOp::Plain><<<grid, 256, 0, a.stream>>>(a); break;
       case PrbOp::AlphaWeighted: k_probe_acc<N, K, PrbOp::AlphaWeighted><<<grid, 256, 0, a.stream>>>(a); break;
@@ -464,6 +579,11 @@ void launch_probe_apply(const ProbeApplyArgs& a, PrbApply op) {
 
 void launch_lsq_steps(const LsqStepArgs& a) {
   if (a.count <= 0) return;
+  k_lsq_planes<<<(a.n * a.n + 255) / 256, 256, 0, a.stream>>>(a.probe, a.dprobe, a.n, a.k, a.probe_on,
+                                                              const_cast<float*>(a.pint),
+                                                              const_cast<float2*>(a.pq),
+                                                              const_cast<float*>(a.dint));
+  PTY_LAUNCH_CHECK("lsq_planes");
   int nrb = 0;
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
