@@ -187,6 +187,23 @@ const char* pty_last_error(const pty_ctx* ctx);
  * Synchronises. */
 pty_status pty_simulate(pty_ctx* ctx, double photons, float* out, int on_device);
 
+/* Adjoint of the Poisson likelihood (not in the paper; a differentiable forward
+ * model for gradient-based refinement).  For the loaded counts d (natural
+ * order) and the loaded positions,
+ *   L = sum_j sum_q [I_jq - d_jq log(I_jq + 1e-6)],  I_j = sum_k |F(P_k S_j O)|^2
+ * (the constant log(d!) dropped).  obj (H x W) and probe (K x N x N) are
+ * complex64 device pointers.  pty_nll_forward writes L to *loss (host) and
+ * synchronises; it stores no exit waves.  pty_nll_backward recomputes them
+ * and writes grad_out times the gradients in PyTorch's convention for complex
+ * tensors (dL/dRe z + i dL/dIm z): g_obj (H x W complex64), g_probe
+ * (K x N x N complex64) and g_pos (J x 2 float32, derivatives with respect to
+ * the top-left corners y_j, x_j; bilinear weights differentiated at fixed
+ * floor), all device pointers; any of them may be NULL.  *loss (may be NULL)
+ * receives L.  Synchronises. */
+pty_status pty_nll_forward(pty_ctx* ctx, const void* obj, const void* probe, double* loss);
+pty_status pty_nll_backward(pty_ctx* ctx, const void* obj, const void* probe, float grad_out,
+                            void* g_obj, void* g_probe, float* g_pos, double* loss);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,9 @@ SIGNATURES = {
     "pty_simulate": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int]),
     "pty_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "pty_get_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "pty_nll_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "pty_nll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.POINTER(C.c_double)]),
 }
 
 TIMING_FAMILIES = ["rows_fwd", "cols", "rows_inv", "obj_gather", "probe_acc", "probe_finish_apply",
@@ -82,9 +85,20 @@ _lib = None
 
 
 def lib() -> C.CDLL:
-    """The loaded library (raises if it has not been built)."""
+    """The loaded library (raises if it has not been built).
+
+    PyTorch for ROCm ships its own HIP runtime with the same SONAME
+    (libamdhip64.so.7).  Importing torch first lets the dynamic linker satisfy
+    the library's dependency with that already-loaded runtime, so the process
+    holds one HIP runtime and torch's device pointers and streams are valid
+    here; without torch the system runtime is used.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_2202_03144_amd.build` "

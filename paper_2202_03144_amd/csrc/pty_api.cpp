@@ -93,6 +93,7 @@ struct pty_ctx {
   float2* num_p2 = nullptr;
   float* den_p = nullptr;
   float2* dprobe = nullptr;
+  double* loss_dev = nullptr;
   float2* lsq_pq = nullptr;
   float* lsq_dint = nullptr;
   double* lsq_part = nullptr;      size_t lsq_part_n = 0;
@@ -433,13 +434,13 @@ void density(pty_ctx* c, const Group& g) {
 
 // Probe sums over slots [0, count) of group g: part -> num_p / den_p
 void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern, PrbOp op,
-                  float2* num, bool with_den) {
+                  float2* num, bool with_den, const float2* obj = nullptr) {
   const int count = (int)g.jl.size();
   const int slices = probe_slices(count, kProbeSlice);
   ProbeAccArgs pa{};
   pa.n = c->N;
   pa.k = c->K;
-  pa.obj = c->obj;
+  pa.obj = obj ? obj : c->obj;
   pa.h = c->H;
   pa.w = c->W;
   pa.jlist = g.d_jl;
@@ -691,6 +692,56 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
     c->iter++;
   }
   c->den_valid = false;
+}
+
+// ---------------------------------------------------------------------------
+// Poisson-likelihood adjoint
+// ---------------------------------------------------------------------------
+double run_nll(pty_ctx* c, const float2* obj, const float2* probe, bool grad, float grad_out, float2* g_obj,
+               float2* g_probe, float* g_pos) {
+  if (!c->have_patterns) throw StateError("patterns not loaded");
+  if (!c->have_positions) throw StateError("positions not loaded");
+  pty_iter_params p;
+  pty_default_params(&p);
+  const int chunk = chunk_patterns(c, p);
+  const size_t nn = size_t(c->N) * c->N;
+  ensure_all_group(c);
+  ensure_common(c, std::min(chunk, c->J), grad ? c->J : 1);
+  c->ensure_once(c->loss_dev, 2);
+  if (grad) {
+    c->ensure(c->chi, c->chi_slots, size_t(c->J) * c->K * nn);
+    c->ensure(c->posgrad, c->posgrad_slots, size_t(c->J) * row_blocks(c->N) * 2);
+    ensure_probe_parts(c, c->J);
+  }
+  const Group& g = c->all;
+  FourierArgs a = fourier_args(c, g);
+  a.obj = obj;
+  a.probe = probe;
+  a.chi = c->chi;
+  a.posgrad = c->posgrad;
+  a.grad_scale = grad_out;
+  for (int off = 0; off < c->J; off += chunk) {
+    a.jl_off = off;
+    a.slot_off = off;
+    a.nc = std::min(chunk, c->J - off);
+    timed(c, kRowsFwd, [&] { launch_rows_fwd(a, RowIn::Plain); });
+    timed(c, kCols, [&] { launch_cols(a, grad ? ColOp::NllGrad : ColOp::NllLoss); });
+    if (grad) timed(c, kRowsInv, [&] { launch_rows_inv(a, RowOut::NllGrad); });
+  }
+  timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->loss_dev, c->stream); });
+  if (grad && g_obj) {
+    timed(c, kOther, [&] { launch_fill_u32(reinterpret_cast<unsigned*>(g_obj), size_t(c->H) * c->W * 2, 0u, c->stream); });
+    ObjGatherArgs o = obj_args(c, g);
+    o.out = g_obj;
+    timed(c, kObjGather, [&] { launch_obj_gather(o, ObjOp::Gradient); });
+  }
+  if (grad && g_probe) probe_reduce(c, g, c->chi, 0, PrbOp::Gradient, g_probe, false, obj);
+  if (grad && g_pos)
+    timed(c, kOther, [&] { launch_posgrad_reduce(c->posgrad, c->J, row_blocks(c->N), g_pos, g.d_jl, c->stream); });
+  double loss = 0.0;
+  PTY_HIP(hipMemcpyAsync(&loss, c->loss_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  PTY_HIP(hipStreamSynchronize(c->stream));
+  return loss;
 }
 
 }  // namespace
@@ -966,6 +1017,27 @@ void pty_destroy(pty_ctx* c) {
 const char* pty_last_error(const pty_ctx* c) {
   if (c) return c->err.c_str();
   return g_tls_error.c_str();
+}
+
+pty_status pty_nll_forward(pty_ctx* c, const void* obj, const void* probe, double* loss) {
+  return guarded(c, [&] {
+    require(c != nullptr && obj != nullptr && probe != nullptr && loss != nullptr, "pty_nll_forward: null argument");
+    c->set_device();
+    *loss = run_nll(c, static_cast<const float2*>(obj), static_cast<const float2*>(probe), false, 1.f, nullptr,
+                    nullptr, nullptr);
+  });
+}
+
+pty_status pty_nll_backward(pty_ctx* c, const void* obj, const void* probe, float grad_out, void* g_obj,
+                            void* g_probe, float* g_pos, double* loss) {
+  return guarded(c, [&] {
+    require(c != nullptr && obj != nullptr && probe != nullptr, "pty_nll_backward: null argument");
+    require(std::isfinite(grad_out), "pty_nll_backward: grad_out must be finite");
+    c->set_device();
+    const double l = run_nll(c, static_cast<const float2*>(obj), static_cast<const float2*>(probe), true, grad_out,
+                             static_cast<float2*>(g_obj), static_cast<float2*>(g_probe), g_pos);
+    if (loss) *loss = l;
+  });
 }
 
 pty_status pty_simulate(pty_ctx* c, double photons, float* out, int on_device) {

@@ -31,7 +31,8 @@ __device__ __forceinline__ size_t zoff(int y, int x) {
 }
 
 template <int N, int K, RowIn MODE>
-__global__ __launch_bounds__(Geo<N>::BS) void k_rows_fwd(FourierArgs a) {
+__global__ __launch_bounds__(Geo<N>::BS)
+void k_rows_fwd(FourierArgs a) {
   using G = Geo<N>;
   constexpr int R = G::R, T = G::T;
   __shared__ float2 tw_s[N];
@@ -66,16 +67,17 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_rows_fwd(FourierArgs a) {
 }
 
 template <int N, int K, ColOp OP>
-__global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
+__global__ __launch_bounds__(Geo<N>::BS)
+void k_cols(FourierArgs a) {
   using G = Geo<N>;
-  constexpr int R = G::R, T = G::T, CW = G::LINES;
+  constexpr int R = G::R, T = G::T, CW = G::LINES, BPP = N / CW;
   __shared__ float2 tw_s[N];
   __shared__ float2 xb[CW * G::W];
   __shared__ double red[G::BS / 64];
   load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
   // each column's T threads are consecutive lanes of one wavefront
   const int col = threadIdx.x / T, t = threadIdx.x % T;
-  const int c = blockIdx.y, x = blockIdx.x * CW + col;
+  const int c = blockIdx.y, cb = blockIdx.x, x = cb * CW + col;
   const int j = a.jlist[a.jl_off + c];
   float2* base = a.zs + (size_t)c * K * N * N;
   float2 z[K][R];
@@ -100,6 +102,10 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
     const float inten = iraw * sc2;
     if constexpr (OP == ColOp::Intensity) {
       a.intensity_out[((size_t)j * N + ((pr + N / 2) & (N - 1))) * N + ((x + N / 2) & (N - 1))] = inten;
+    } else if constexpr (OP == ColOp::NllLoss) {
+      const float am = a.amp[((size_t)j * N + pr) * N + x];
+      const float d = am * am;
+      e_num += inten - d * logf(inten + a.nll_eps);
     } else {
       const float am = a.amp[((size_t)j * N + pr) * N + x];
       float f;
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
         e_den += am * am;
       } else {
         const float d = am * am;
-        f = 1.f - d / (inten + a.nll_eps);
+        f = a.grad_scale * (1.f - d / (inten + a.nll_eps));
         e_num += inten - d * logf(inten + a.nll_eps);
       }
       f *= sc2;
@@ -118,7 +124,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
       for (int k = 0; k < K; ++k) z[k][m] = f * z[k][m];
     }
   }
-  if constexpr (OP != ColOp::Intensity) {
+  if constexpr (OP == ColOp::Project || OP == ColOp::NllGrad) {
 #pragma unroll
     for (int k = 0; k < K; ++k) line_fft<N, true>(z[k], xb + col * G::W, tw_s, t);
 #pragma unroll
@@ -126,10 +132,12 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
 #pragma unroll
       for (int m = 0; m < R; ++m) base[(size_t)k * N * N + zoff<N>(t + T * m, x)] = z[k][m];
     }
+  }
+  if constexpr (OP != ColOp::Intensity) {
     const double s0 = block_sum<G::BS>((double)e_num, red);
     const double s1 = block_sum<G::BS>((double)e_den, red);
     if (threadIdx.x == 0) {
-      double* e = a.errp + ((size_t)j * (N / CW) + blockIdx.x) * 2;
+      double* e = a.errp + ((size_t)j * BPP + cb) * 2;
       e[0] = s0;
       e[1] = s1;
     }
@@ -137,16 +145,17 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_cols(FourierArgs a) {
 }
 
 template <int N, int K, RowOut MODE>
-__global__ __launch_bounds__(Geo<N>::BS) void k_rows_inv(FourierArgs a) {
+__global__ __launch_bounds__(Geo<N>::BS)
+void k_rows_inv(FourierArgs a) {
   using G = Geo<N>;
-  constexpr int R = G::R, T = G::T;
+  constexpr int R = G::R, T = G::T, BPP = N / G::LINES;
   __shared__ float2 tw_s[N];
   __shared__ float2 xb[G::LINES * G::W];
   __shared__ double red[G::BS / 64];
   load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
   const int line = threadIdx.x / T, t = threadIdx.x % T;
-  const int c = blockIdx.y;
-  const int y = blockIdx.x * G::LINES + line;
+  const int c = blockIdx.y, rb = blockIdx.x;
+  const int y = rb * G::LINES + line;
   const int slot = a.slot_off + c;
   const int j = a.jlist[a.jl_off + c];
   const PosInfo p = a.pos[j];
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_rows_inv(FourierArgs a) {
     const double sy = block_sum<G::BS>(2.0 * gy, red);
     const double sx = block_sum<G::BS>(2.0 * gx, red);
     if (threadIdx.x == 0) {
-      double* g = a.posgrad + ((size_t)slot * (N / G::LINES) + blockIdx.x) * 2;
+      double* g = a.posgrad + ((size_t)slot * BPP + rb) * 2;
       g[0] = sy;
       g[1] = sx;
     }
@@ -245,6 +254,7 @@ void launch_cols(const FourierArgs& a, ColOp op) {
       case ColOp::Project: k_cols<N, K, ColOp::Project><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
       case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
       case ColOp::Intensity: k_cols<N, K, ColOp::Intensity><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+      case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
     }
   });
   PTY_LAUNCH_CHECK("cols");

@@ -9,7 +9,7 @@ namespace pty {
 // Prologue of the forward row pass: z = P S_j O, or z = 2 P S_j O - psi_j (DM).
 enum class RowIn { Plain = 0, DmReflect = 1 };
 // Per-pixel step of the column pass.
-enum class ColOp { Project = 0, NllGrad = 1, Intensity = 2 };
+enum class ColOp { Project = 0, NllGrad = 1, Intensity = 2, NllLoss = 3 };
 // Epilogue of the inverse row pass.
 enum class RowOut { DmUpdate = 0, StoreChi = 1, NllGrad = 2 };
 // Object-tile gather: what is accumulated and how it is applied.
@@ -39,6 +39,7 @@ struct FourierArgs {
   int slot_off;           // ... and writes chi / contrib / posgrad slot slot_off + c
   int nc;                 // patterns in the chunk
   float nll_eps;
+  float grad_scale;       // NllGrad: multiplies every gradient
   hipStream_t stream;
 };
 

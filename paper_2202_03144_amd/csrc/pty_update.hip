@@ -165,10 +165,11 @@ template <int N, int K, PrbOp OP>
 __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
   using W = typename ProbePix<N>::W;
   constexpr int RB = ProbePix<N>::RB;
-  const int s_beg = a.s0 + blockIdx.y * a.per_slice;
+  const int slice = blockIdx.y, rblk = blockIdx.x;
+  const int s_beg = a.s0 + slice * a.per_slice;
   const int s_end = min(s_beg + a.per_slice, a.s0 + a.count);
   const int v = threadIdx.x % N;
-  const int u0 = (blockIdx.x * W::G + threadIdx.x / N) * RB;
+  const int u0 = (rblk * W::G + threadIdx.x / N) * RB;
   float2 num[K][RB];
   float den[RB];
 #pragma unroll
@@ -201,8 +202,8 @@ __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
   for (int i = 0; i < RB; ++i) {
     const int q = (u0 + i) * N + v;
 #pragma unroll
-    for (int k = 0; k < K; ++k) a.part_num[((size_t)blockIdx.y * K + k) * N * N + q] = num[k][i];
-    if constexpr (OP == PrbOp::Plain) a.part_den[(size_t)blockIdx.y * N * N + q] = den[i];
+    for (int k = 0; k < K; ++k) a.part_num[((size_t)slice * K + k) * N * N + q] = num[k][i];
+    if constexpr (OP == PrbOp::Plain) a.part_den[(size_t)slice * N * N + q] = den[i];
   }
 }
 
@@ -305,12 +306,12 @@ template <int N, int K, bool PROBE_ON>
 __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
   using W = typename LsqPix<N>::W;
   constexpr int RB = LsqPix<N>::RB;
+  const int b = blockIdx.y, rblk = blockIdx.x;
   __shared__ double red[20];
-  const int b = blockIdx.y;
   const int j = a.jlist[b];
   const PosInfo p = a.pos[j];
   const int v = threadIdx.x % N;
-  const int u0 = (blockIdx.x * W::G + threadIdx.x / N) * RB;
+  const int u0 = (rblk * W::G + threadIdx.x / N) * RB;
   const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
   float m00 = 0.f, m11 = 0.f, m01 = 0.f, v0 = 0.f, v1 = 0.f;
   float2 dtop = obj_hrow(a.dobj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
   double s[5] = {m00, m11, m01, v0, v1};
   block_sum5(s, red);
   if (threadIdx.x == 0) {
-    double* o = a.part + ((size_t)b * LsqPix<N>::NRB + blockIdx.x) * 5;
+    double* o = a.part + ((size_t)b * LsqPix<N>::NRB + rblk) * 5;
 #pragma unroll
     for (int i = 0; i < 5; ++i) o[i] = s[i];
   }

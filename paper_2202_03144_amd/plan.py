@@ -163,6 +163,36 @@ class Plan:
         self._check(self._lib.pty_simulate(self._live(), float(photons), a.ctypes.data_as(C.c_void_p), 0))
         return a
 
+    def _dev(self, x, dtype, shape, name):
+        """Device pointer of a CUDA tensor with the given layout (adjoint inputs/outputs)."""
+        if x is None:
+            return None
+        if not (_is_torch(x) and x.is_cuda):
+            raise TypeError(f"{name} must be a CUDA tensor")
+        ptr, _, _ = _ptr(x, dtype, shape)
+        if not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return ptr
+
+    def nll_forward(self, obj, probe) -> float:
+        """Poisson NLL of the loaded counts for (obj, probe) given as CUDA complex64 tensors."""
+        loss = C.c_double()
+        self._check(self._lib.pty_nll_forward(
+            self._live(), self._dev(obj, np.complex64, self.obj_shape, "obj"),
+            self._dev(probe, np.complex64, (self.modes, self.n, self.n), "probe"), C.byref(loss)))
+        return loss.value
+
+    def nll_backward(self, obj, probe, grad_out: float = 1.0, g_obj=None, g_probe=None, g_pos=None) -> float:
+        """Writes grad_out times the NLL gradients into the given CUDA tensors (any may be None)."""
+        loss = C.c_double()
+        self._check(self._lib.pty_nll_backward(
+            self._live(), self._dev(obj, np.complex64, self.obj_shape, "obj"),
+            self._dev(probe, np.complex64, (self.modes, self.n, self.n), "probe"), float(grad_out),
+            self._dev(g_obj, np.complex64, self.obj_shape, "g_obj"),
+            self._dev(g_probe, np.complex64, (self.modes, self.n, self.n), "g_probe"),
+            self._dev(g_pos, np.float32, (self.n_pos, 2), "g_pos"), C.byref(loss)))
+        return loss.value
+
     def set_timing(self, enable: bool = True) -> None:
         """Clear the per-family kernel times and enable (or disable) event timing."""
         self._check(self._lib.pty_set_timing(self._live(), 1 if enable else 0))

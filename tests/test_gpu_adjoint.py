@@ -1,0 +1,160 @@
+"""Poisson-NLL adjoint on the GPU vs the FP64 oracle gradients (which are
+themselves pinned by central finite differences in test_oracle_pins.py)."""
+import numpy as np
+import pytest
+
+import oracle
+import ptysynth
+from _cases import c64, spiral_case
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _rel(x, y):
+    x = np.asarray(x, np.complex128).ravel()
+    y = np.asarray(y, np.complex128).ravel()
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+def _fd_case():
+    """32^2 window, 4 modes, 4x4 raster with fractional offsets in [0.1, 0.9]."""
+    wl = ptysynth.scaled(ptysynth.workload(3), cfg=31, n=32, k=4, h=48, w=48, d=11.0,
+                         sigma_e=1.0, sigma_p=3.0, photons=1e4)
+    rng = np.random.default_rng(15)
+    pos = ptysynth.raster_positions(4, 4, 4.0, 1.0) + rng.uniform(0.1, 0.9, (16, 2))
+    o = wl.obj()
+    p = wl.probe()
+    cnt, p = oracle.simulate(o, p, pos, wl.photons)
+    cnt = ptysynth.poisson_counts(cnt, wl.noise_rng())
+    o = o * (1 + 0.05 * (rng.standard_normal(o.shape) + 1j * rng.standard_normal(o.shape)))
+    p = p * (1 + 0.05 * (rng.standard_normal(p.shape) + 1j * rng.standard_normal(p.shape)))
+    return c64(o), c64(p), pos, cnt
+
+
+def _plan(n, k, pos, shape, counts):
+    from paper_2202_03144_amd import Plan
+    pl = Plan(n, k, len(pos), shape)
+    pl.load_patterns(counts)
+    pl.load_positions(pos)
+    return pl
+
+
+def _gpu_grads(pl, o, p, grad_out=1.0):
+    import torch
+    ot = torch.from_numpy(o).cuda()
+    pt = torch.from_numpy(p).cuda()
+    go = torch.empty_like(ot)
+    gp = torch.empty_like(pt)
+    gr = torch.empty((pl.n_pos, 2), dtype=torch.float32, device="cuda")
+    loss = pl.nll_backward(ot, pt, grad_out, go, gp, gr)
+    lf = pl.nll_forward(ot, pt)
+    return loss, lf, go.cpu().numpy(), gp.cpu().numpy(), gr.cpu().numpy()
+
+
+@pytest.mark.parametrize("grad_out", [1.0, -0.37])
+def test_adjoint_matches_oracle_fd_case(grad_out):
+    o, p, pos, cnt = _fd_case()
+    pl = _plan(32, 4, pos, o.shape, cnt)
+    loss, lf, go, gp, gr = _gpu_grads(pl, o, p, grad_out)
+    pl.close()
+    ref_l, ref_go, ref_gp, ref_gr = oracle.nll_grad(o.astype(np.complex128), p.astype(np.complex128), pos,
+                                                    cnt.astype(np.float64))
+    assert abs(loss - ref_l) <= 1e-5 * abs(ref_l) and abs(lf - ref_l) <= 1e-5 * abs(ref_l)
+    assert _rel(go, grad_out * ref_go) <= TOL
+    assert _rel(gp, grad_out * ref_gp) <= TOL
+    assert np.linalg.norm(gr - grad_out * ref_gr) <= TOL * np.linalg.norm(grad_out * ref_gr)
+
+
+def test_adjoint_main_shape():
+    """128^2 window, 4 modes, 1,000 jittered spiral positions (the adjoint workload)."""
+    wl = ptysynth.workload(3)
+    o_true = wl.obj()
+    pos = wl.positions()
+    cnt, p = oracle.simulate(o_true, wl.probe(), pos, wl.photons)
+    cnt = ptysynth.poisson_counts(cnt, wl.noise_rng())
+    rng = np.random.default_rng(3)
+    o = c64(o_true * (1 + 0.02 * rng.standard_normal(o_true.shape)))
+    p = c64(p)
+    pl = _plan(wl.n, wl.k, pos, o.shape, cnt)
+    loss, lf, go, gp, gr = _gpu_grads(pl, o, p)
+    pl.close()
+    ref_l, ref_go, ref_gp, ref_gr = oracle.nll_grad(o.astype(np.complex128), p.astype(np.complex128), pos,
+                                                    cnt.astype(np.float64))
+    assert abs(loss - ref_l) <= 1e-5 * abs(ref_l)
+    assert _rel(go, ref_go) <= TOL
+    assert _rel(gp, ref_gp) <= TOL
+    assert np.linalg.norm(gr - ref_gr) <= TOL * np.linalg.norm(ref_gr)
+
+
+def test_autograd_function():
+    import torch
+    from paper_2202_03144_amd.adjoint import NLL
+    o, p, pos, cnt = _fd_case()
+    pl = _plan(32, 4, pos, o.shape, cnt)
+    ot = torch.from_numpy(o).cuda().requires_grad_(True)
+    pt = torch.from_numpy(p).cuda().requires_grad_(True)
+    rt = torch.from_numpy(pos).requires_grad_(True)
+    loss = NLL.apply(ot, pt, rt, pl)
+    (2.0 * loss).backward()
+    ref_l, ref_go, ref_gp, ref_gr = oracle.nll_grad(o.astype(np.complex128), p.astype(np.complex128), pos,
+                                                    cnt.astype(np.float64))
+    assert abs(loss.item() - ref_l) <= 1e-5 * abs(ref_l)
+    assert _rel(ot.grad.cpu().numpy(), 2 * ref_go) <= TOL
+    assert _rel(pt.grad.cpu().numpy(), 2 * ref_gp) <= TOL
+    assert rt.grad.dtype == torch.float64
+    assert np.linalg.norm(rt.grad.numpy() - 2 * ref_gr) <= TOL * np.linalg.norm(2 * ref_gr)
+    # moving the positions reloads them (bilinear weights change)
+    rt2 = (rt.detach() + 0.25).requires_grad_(True)
+    l2 = NLL.apply(ot.detach(), pt.detach(), rt2, pl)
+    assert abs(l2.item() - oracle.nll(o.astype(np.complex128), p.astype(np.complex128), pos + 0.25,
+                                      cnt.astype(np.float64))) <= 1e-5 * abs(l2.item())
+    pl.close()
+
+
+def test_gradient_descent_on_object_reduces_nll():
+    """A few plain gradient steps on the object (true probe) lower the likelihood."""
+    import torch
+    from paper_2202_03144_amd.adjoint import NLL
+    case = spiral_case(64, 2, 20, cfg=95)
+    pl = _plan(64, 2, case.pos, case.shape, case.counts)
+    ot = torch.ones(case.shape, dtype=torch.complex64, device="cuda", requires_grad=True)
+    pt = torch.from_numpy(c64(case.probe)).cuda()
+    rt = torch.from_numpy(case.pos)
+    losses = []
+    opt = torch.optim.SGD([ot], lr=1e-6)
+    for _ in range(5):
+        opt.zero_grad()
+        loss = NLL.apply(ot, pt, rt, pl)
+        loss.backward()
+        losses.append(loss.item())
+        opt.step()
+    pl.close()
+    assert losses[-1] < losses[0]
+
+
+def test_single_hip_runtime_and_torch_stream():
+    """The library and torch share one HIP runtime, so a torch stream can carry the work."""
+    import torch
+    from paper_2202_03144_amd import Plan
+    from paper_2202_03144_amd import _lib
+    _lib.lib()
+    maps = open("/proc/self/maps").read()
+    hips = sorted({l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l})
+    assert len(hips) == 1, hips
+    case = spiral_case(64, 1, 12, cfg=96)
+    s = torch.cuda.Stream()
+    o0 = c64(np.ones(case.shape))
+    with Plan(64, 1, 12, case.shape, stream=s) as pl:
+        pl.load_patterns(torch.from_numpy(case.counts).cuda())
+        pl.load_positions(case.pos)
+        pl.set_object(torch.from_numpy(o0).cuda())
+        pl.set_probe(c64(case.probe))
+        pl.iterate("dm", 2, probe_update_start=0)
+        s.synchronize()
+        got = pl.object()
+    o_ref, _, _, _ = oracle.dm(o0.astype(np.complex128), c64(case.probe).astype(np.complex128),
+                               oracle.dm_init(o0.astype(np.complex128), c64(case.probe).astype(np.complex128),
+                                              case.pos), case.amp, case.pos, 2, start=0)
+    assert oracle.phase_aligned_rel(got, o_ref) <= TOL
