@@ -14,7 +14,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -26,7 +25,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pattern-iterations/s (256², 3 modes)"
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
-PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (packed)
 
 
 def log(msg: str) -> None:
@@ -54,24 +52,66 @@ def make_inputs(torch):
     return wl, obj_true, probe, pos, torch.from_numpy(counts).cuda()
 
 
-# Algorithmic HBM bytes per pattern-iteration of each kernel family at N, K (float32
-# complex = 8 B): the traffic the method's data dependencies force, not the
-# implementation's intermediates (the chunk scratch is sized to stay on chip).
-def algorithmic_bytes(n, k):
+# Algorithmic HBM bytes per pattern of the Fourier-pass kernels at N, K (complex
+# float32 = 8 B): the traffic the method's data dependencies force.  The chunk
+# scratch between the passes and the per-pattern contribution planes are
+# intermediates of this implementation and are not counted.
+def algorithmic_bytes_per_pattern(plan, fam, n, k):
     nn = n * n
-    return {
-        # DM: psi read (K modes)
-        "rows_fwd_dm": 8 * k * nn,
-        # both: measured moduli A read
-        "cols": 4 * nn,
-        # DM: psi write; LSQML: chi write (K modes); both: contribution plane write
-        "rows_inv": 8 * k * nn + 8 * nn,
+    table = {
+        ("dm", "rows_fwd"): 8 * k * nn,      # exit waves psi read
+        ("dm", "cols"): 4 * nn,              # measured moduli A read
+        ("dm", "rows_inv"): 8 * k * nn,      # exit waves psi written
+        ("lsqml", "rows_fwd"): 0,            # gathers only (object and probe stay in cache)
+        ("lsqml", "cols"): 4 * nn,           # A read
+        ("lsqml", "rows_inv"): 8 * k * nn,   # chi written
     }
+    return table.get((plan, fam))
 
 
-def fft_flops(n):
-    """Nominal 5 N log2 N flops of one length-N complex line transform."""
-    return 5.0 * n * math.log2(n)
+# Whole-iteration algorithmic bytes: DM reads psi twice (probe update, Fourier
+# pass), writes it once and reads A; LSQML writes chi, reads it in the step-length
+# sums, reads A; both add the object planes (DM ~40 B/px once, LSQML ~64 B/px per group).
+def iteration_bytes(plan, n, k, j, h, w, groups):
+    nn = n * n
+    if plan == "dm":
+        return j * nn * (4 + 24 * k) + 40 * h * w
+    return j * nn * (4 + 16 * k) + 64 * h * w * groups
+
+
+# HBM bytes measured by rocprofv3 FETCH_SIZE / WRITE_SIZE for full 42-pattern
+# launches (profiles/dm_fourier_256x3_hbm_counters.md): read = 2.0 x FETCH_SIZE,
+# written = 1.0 x WRITE_SIZE (factors from a plain copy of known size).  Valid
+# only while the kernel sources hash to COUNTER_SRC_HASH.
+COUNTER_SRC_HASH = "ba0671651a9b304b"
+COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp", "pty_kernels.hpp"]
+MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns per launch)
+    ("dm", "rows_fwd"): (43668.2, 64512.0, 42),
+    ("dm", "cols"): (43199.3, 64533.0, 42),
+    ("dm", "rows_inv"): (44646.9, 86016.0, 42),
+    ("lsqml", "rows_fwd"): (11221.3, 64512.0, 42),
+    ("lsqml", "cols"): (43199.3, 64533.0, 42),
+    ("lsqml", "rows_inv"): (33116.3, 86016.0, 42),
+}
+
+
+def kernel_src_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in COUNTER_SRCS:
+        with open(os.path.join(ROOT, "paper_2202_03144_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_NAMES = {
+    ("dm", "rows_fwd"): "k_rows_fwd<256,3,DmReflect>",
+    ("dm", "cols"): "k_cols<256,3,Project>",
+    ("dm", "rows_inv"): "k_rows_inv<256,3,DmUpdate>",
+    ("lsqml", "rows_fwd"): "k_rows_fwd<256,3,Plain>",
+    ("lsqml", "cols"): "k_cols<256,3,Project>",
+    ("lsqml", "rows_inv"): "k_rows_inv<256,3,StoreChi>",
+}
 
 
 def cpu_baseline(n_sample: int):
@@ -193,24 +233,31 @@ def main() -> int:
                 if cnt:
                     families[f"{algo}.{fam}"] = {"ms_per_iter": ms / args.steps, "launches_per_iter": cnt / args.steps}
             pl.set_timing(False)
-        dom = max(families, key=lambda f: families[f]["ms_per_iter"])
-        n, k, j = wl.n, wl.k, wl.j
-        ab = algorithmic_bytes(n, k)
-        # FFT flops per pattern of each pass: K modes x N lines x one line transform
-        lines = k * n * fft_flops(n)
-        fam_flops = {"rows_fwd": lines, "cols": 2 * lines, "rows_inv": lines}
-        base = dom.split(".", 1)[1]
+        fourier = [f for f in families if f.split(".", 1)[1] in ("rows_fwd", "cols", "rows_inv")]
+        dom = max(fourier, key=lambda f: families[f]["ms_per_iter"])
+        plan_name, fam = dom.split(".", 1)
         fdat = families[dom]
         per_launch_ms = fdat["ms_per_iter"] / fdat["launches_per_iter"]
-        patterns_per_launch = j / fdat["launches_per_iter"]
-        if base in fam_flops:
-            achieved = fam_flops[base] * patterns_per_launch / (per_launch_ms / 1e3) / 1e12
-            roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2),
-                        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                        "per_launch_ms": round(per_launch_ms, 4),
-                        "patterns_per_launch": round(patterns_per_launch, 2)}
-        log(f"dominant kernel family {dom}: {fdat}")
+        patterns_per_launch = wl.j / fdat["launches_per_iter"]
+        alg = algorithmic_bytes_per_pattern(plan_name, fam, wl.n, wl.k) * patterns_per_launch
+        achieved = alg / (per_launch_ms / 1e3) / 1e9
+        traffic = None
+        if kernel_src_hash() == COUNTER_SRC_HASH and (plan_name, fam) in MEASURED_KIB:
+            fk, wk, npl = MEASURED_KIB[(plan_name, fam)]
+            traffic = round((2.0 * fk + 1.0 * wk) * 1024 / npl * patterns_per_launch)
+        roofline = {"bound": "hbm", "kernel": f"{KERNEL_NAMES[(plan_name, fam)]} ({dom})",
+                    "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                    "algorithmic_bytes_per_launch": round(alg), "avg_launch_ms": round(per_launch_ms, 4),
+                    "patterns_per_launch": round(patterns_per_launch, 2)}
+        log(f"dominant kernel {dom}: {fdat}")
+    groups = -(-wl.j // params["lsqml"]["lsqml_batch"])
+    iteration = {}
+    for plan_name, ms in (("dm", dm_ms), ("lsqml", lsq_ms)):
+        b = iteration_bytes(plan_name, wl.n, wl.k, wl.j, wl.h, wl.w, groups)
+        iteration[plan_name] = {"algorithmic_GB": round(b / 1e9, 3), "ms": round(ms, 3),
+                                "achieved_GBs": round(b / (ms / 1e3) / 1e9, 1),
+                                "frac": round(b / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
 
     cpu = None
     if args.cpu_sample > 0:
@@ -238,6 +285,7 @@ def main() -> int:
         "dm_ms_per_iter": round(dm_ms, 3),
         "lsqml_ms_per_iter": round(lsq_ms, 3),
         "roofline": roofline,
+        "iteration_roofline": iteration,
         "kernel_families": families,
         "cpu_baseline": cpu,
     }
