@@ -1,0 +1,80 @@
+"""Pins of the FP64 reference of the learned seed's data path: stitching
+recovers an object exactly from consistent patches with arbitrary per-patch
+phase offsets, the chain's special cases, targets and inputs in closed form."""
+import numpy as np
+
+import ptysynth
+from oracle import seed
+
+
+def _object(h, w, s=5):
+    rng = np.random.default_rng(s)
+    amp = 0.8 + 0.2 * rng.uniform(size=(h, w))
+    ph = rng.uniform(-2.5, 2.5, size=(h, w))
+    return amp * np.exp(1j * ph)
+
+
+def _cut(obj, pos, rng):
+    """Patches of the object at the oracle's placements, each with a random phase offset."""
+    t = seed.placements(pos)
+    out = np.empty((len(t), 64, 64, 2))
+    for j, (ty, tx) in enumerate(t):
+        o = obj[ty:ty + 64, tx:tx + 64] * np.exp(1j * rng.uniform(-np.pi, np.pi))
+        out[j, ..., 0] = np.abs(o)
+        out[j, ..., 1] = np.angle(o)
+    return out, t
+
+
+def test_stitch_recovers_consistent_patches_up_to_global_phase():
+    h, w = 300, 280
+    obj = _object(h, w)
+    pos = ptysynth.spiral_positions(60, 6.0, 140.0, 128)
+    pos += np.random.default_rng(1).uniform(0.0, 1.0, pos.shape)   # fractional parts round both ways
+    rng = np.random.default_rng(2)
+    patches, t = _cut(obj, pos, rng)
+    out, e = seed.stitch(patches, pos, h, w)
+    cov = np.zeros((h, w), bool)
+    for ty, tx in t:
+        cov[ty:ty + 64, tx:tx + 64] = True
+    g = out[cov] / obj[cov]
+    assert np.allclose(np.abs(g), 1.0, atol=1e-12)
+    assert np.allclose(g, g[0], atol=1e-10)          # one global phase everywhere
+    assert np.all(out[~cov] == 1.0)
+    assert abs(e[0] - 1.0) == 0.0                     # the first patch has nothing to align to
+
+
+def test_stitch_single_patch_and_disjoint_patches():
+    h, w = 256, 256
+    rng = np.random.default_rng(3)
+    p = np.stack([rng.uniform(0.5, 1.0, (2, 64, 64)), rng.uniform(-3, 3, (2, 64, 64))], axis=-1)
+    pos = np.array([[0.2, 0.4], [120.0, 110.6]])     # placements (32, 32) and (152, 143): disjoint
+    out, e = seed.stitch(p, pos, h, w)
+    np.testing.assert_allclose(out[32:96, 32:96], p[0, ..., 0] * np.exp(1j * p[0, ..., 1]), atol=1e-13)
+    np.testing.assert_allclose(out[152:216, 143:207], p[1, ..., 0] * np.exp(1j * p[1, ..., 1]), atol=1e-13)
+    assert np.all(e == 1.0)
+    assert np.all(out[:32] == 1.0)
+
+
+def test_placement_rounding():
+    t = seed.placements(np.array([[10.49, 10.5], [0.0, 7.999]]))
+    assert t.tolist() == [[42, 43], [32, 40]]
+
+
+def test_targets_closed_form():
+    rng = np.random.default_rng(4)
+    obj = _object(200, 220, 6)
+    pos = rng.integers(0, 70, size=(5, 2))
+    tg = seed.targets(obj, pos)
+    for j, (y, x) in enumerate(pos):
+        o = obj[y + 32:y + 96, x + 32:x + 96]
+        v = tg[j, ..., 0] * np.exp(1j * tg[j, ..., 1])
+        # v is o times one unit phasor, and that phasor makes sum(v) real and positive
+        r = v / o
+        assert np.allclose(np.abs(r), 1.0, atol=1e-12) and np.allclose(r, r[0, 0], atol=1e-12)
+        s = v.sum()
+        assert s.real > 0 and abs(s.imag) <= 1e-9 * abs(s)
+
+
+def test_network_input_closed_form():
+    d = np.array([np.e - 1.0, 0.0, -3.0, np.e ** 2 - 1.0])
+    np.testing.assert_allclose(seed.network_input(d, np.e - 1.0), [1.0, 0.0, 0.0, 2.0], atol=1e-15)
