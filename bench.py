@@ -83,8 +83,8 @@ def iteration_bytes(plan, n, k, j, h, w, groups):
 # launches (profiles/dm_fourier_256x3_hbm_counters.md): read = 2.0 x FETCH_SIZE,
 # written = 1.0 x WRITE_SIZE (factors from a plain copy of known size).  Valid
 # only while the kernel sources hash to COUNTER_SRC_HASH.
-COUNTER_SRC_HASH = "ba0671651a9b304b"
-COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp", "pty_kernels.hpp"]
+COUNTER_SRC_HASH = "1b8b81f78178bd59"
+COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp"]
 MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns per launch)
     ("dm", "rows_fwd"): (43668.2, 64512.0, 42),
     ("dm", "cols"): (43199.3, 64533.0, 42),
@@ -96,11 +96,17 @@ MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns pe
 
 
 def kernel_src_hash():
+    """Hash of what the Fourier kernels are compiled from: their sources and
+    the part of the launcher header that defines their arguments."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in COUNTER_SRCS:
         with open(os.path.join(ROOT, "paper_2202_03144_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2202_03144_amd", "csrc", "pty_kernels.hpp")) as fh:
+        hdr = fh.read()
+    h.update(hdr[:hdr.index("void launch_rows_fwd")].encode())
     return h.hexdigest()[:16]
 
 

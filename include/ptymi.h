@@ -126,7 +126,9 @@ pty_status pty_set_probe(pty_ctx* ctx, const void* c64, int on_device);
  * The global iteration counter advances by n_iter and drives
  * probe_update_start.  DM keeps its exit waves between calls and initialises
  * them from the current object and probe when it starts after another
- * algorithm or after pty_set_object / pty_set_probe.  n_iter = 0 is a no-op. */
+ * algorithm or after pty_set_object / pty_set_probe.  n_iter = 0 runs no
+ * iteration; for DM and LSQML it allocates the work buffers those iterations
+ * need (and synchronises), so that later calls only enqueue kernels. */
 pty_status pty_iterate(pty_ctx* ctx, pty_algo algo, int32_t n_iter, const pty_iter_params* prm);
 
 /* Copies the object (H x W complex64) / probe (K x N x N complex64) out; sync. */
@@ -203,6 +205,99 @@ pty_status pty_simulate(pty_ctx* ctx, double photons, float* out, int on_device)
 pty_status pty_nll_forward(pty_ctx* ctx, const void* obj, const void* probe, double* loss);
 pty_status pty_nll_backward(pty_ctx* ctx, const void* obj, const void* probe, float grad_out,
                             void* g_obj, void* g_probe, float* g_pos, double* loss);
+
+/* ------------------------------------------------------------------------
+ * Evaluation against a known object (not in the paper; reconstruction
+ * quality for synthetic data).
+ * ---------------------------------------------------------------------- */
+
+/* Amplitude error E (Sec. 2.3's error metric) of the context's current object
+ * and probe over all positions, without changing the state.  Synchronises. */
+pty_status pty_model_error(pty_ctx* ctx, double* out);
+
+/* Sets the true object (H x W complex64, host or device; copied) and the
+ * region of interest: pixels whose illumination sum_j S_j^T sum_k |P_k|^2
+ * under the current probe and positions is at least roi_frac of its maximum.
+ * From then on every iteration records the invariant NRMSE
+ *   min_c ||c O - O_true|| / ||O_true||   over the region (Fienup 1997)
+ * on the device, read back with pty_get_nrmse (entries of iterations run
+ * without a truth are undefined).  truth == NULL switches recording off.
+ * Synchronises. */
+pty_status pty_set_truth(pty_ctx* ctx, const void* truth, int on_device, float roi_frac);
+/* NRMSE of the current object (needs a truth).  Synchronises. */
+pty_status pty_nrmse(pty_ctx* ctx, double* out);
+/* Copies up to cap per-iteration NRMSE values (iterations 0 .. n-1).  Synchronises. */
+pty_status pty_get_nrmse(pty_ctx* ctx, double* out, int32_t cap, int32_t* n_written);
+
+/* ------------------------------------------------------------------------
+ * Learned initialiser (not in the paper): a U-Net that maps one 128 x 128
+ * pattern to the amplitude and phase of the central 64 x 64 object patch,
+ * trained on the device, whose patches are stitched into an object seed for
+ * LSQML.
+ *
+ * Network: 3 x 3 convolutions (zero padding) with ReLU, 2 x 2 average
+ * pooling, 2x nearest upsampling, skips concatenated after the upsampled
+ * channels; channel widths 32-32-64-128-256-256-128-64-32-2 at resolutions
+ * 128-64-32-16-8-8-16-32-64-64.  Parameters (float32 masters, bf16 copies used
+ * by the kernels): per layer W[cout][3][3][cin] then b[cout].  Input
+ * log1p(max(d, 0)) / log1p(photons) of the centred counts d; output channel 0
+ * amplitude, channel 1 phase relative to the patch's mean phasor.  Loss: mean
+ * squared error; optimiser: Adam (beta 0.9, 0.999, eps 1e-8).
+ * ---------------------------------------------------------------------- */
+typedef struct pty_cnn pty_cnn;
+
+/* Creates a network on `device` with buffers for batches of up to max_batch
+ * patterns (about 5 MB of device memory per pattern); He-normal weights drawn
+ * from `seed`, zero biases.  stream NULL: the network creates its own. */
+pty_status pty_cnn_create(int32_t device, void* stream, int32_t max_batch, uint64_t seed, pty_cnn** out);
+void pty_cnn_destroy(pty_cnn* net);                    /* NULL-safe */
+const char* pty_cnn_last_error(const pty_cnn* net);   /* never NULL */
+pty_status pty_cnn_num_params(const pty_cnn* net, int64_t* n);
+/* Host copies of the float32 parameters (pty_cnn_num_params floats). */
+pty_status pty_cnn_get_params(pty_cnn* net, float* out);
+pty_status pty_cnn_set_params(pty_cnn* net, const float* in);
+/* Forward pass: x (batch x 128 x 128 float32, device) -> y (batch x 64 x 64 x 2
+ * float32, device).  Synchronises. */
+pty_status pty_cnn_forward(pty_cnn* net, const float* x, int32_t batch, float* y);
+/* Loss and gradient with respect to the parameters for targets t (batch x 64
+ * x 64 x 2, device); grad is a host array of pty_cnn_num_params floats.  The
+ * parameters are not changed.  Synchronises. */
+pty_status pty_cnn_grad(pty_cnn* net, const float* x, const float* target, int32_t batch, float* grad,
+                        double* loss);
+/* One Adam step with learning rate lr on the batch; *loss (may be NULL) gets
+ * the loss before the step.  Synchronises. */
+pty_status pty_cnn_train_step(pty_cnn* net, const float* x, const float* target, int32_t batch, float lr,
+                              double* loss);
+/* Network input from n centred counts (device): x = log1p(max(d, 0)) / log1p(photons). */
+pty_status pty_cnn_input(pty_cnn* net, const float* counts, size_t n, double photons, float* x);
+
+/* Training data on the context's device and stream.
+ * pty_poisson: out[i] ~ Poisson(lam[i]) (device arrays; lam < 64 by
+ * inversion, larger by the rounded normal approximation), a counter-based
+ * stream per element keyed by seed.  pty_training_targets: for integer
+ * positions and N = 128, the network targets of every window (J x 64 x 64 x 2,
+ * device) from the context's object.  Both synchronise. */
+pty_status pty_poisson(pty_ctx* ctx, const float* lam, float* out, size_t n, uint64_t seed);
+pty_status pty_training_targets(pty_ctx* ctx, float* out);
+
+/* Stitches J predicted patches (J x 64 x 64 x (amplitude, phase), device) into
+ * an object: patch j sits at the nearest integer position of window j plus
+ * (32, 32); a sequential chain in position order gives each patch a phase
+ * factor e_j = z / |z|, z = sum over already stitched samples (the pixels
+ * whose coordinates are multiples of 8) of S conj(c_j); the result is the
+ * mean of c_j e_j over the patches covering a pixel, 1 where none does.
+ * out: H x W complex64 device buffer, or NULL to replace the context's
+ * object.  N must be 128.  Synchronises. */
+pty_status pty_stitch(pty_ctx* ctx, const float* patches, void* out);
+
+/* Learned seed of the context's object: the network's forward pass over all
+ * loaded patterns in batches of `batch` (on the context's stream), then
+ * pty_stitch.  With fallback != 0 the seed is kept only if its model error is
+ * not above that of the flat object O = 1 (else the flat object is used and
+ * *used_fallback = 1); *e_seed and *e_flat (each may be NULL) receive the two
+ * errors.  The network must live on the context's device.  Synchronises. */
+pty_status pty_seed_object(pty_ctx* ctx, pty_cnn* net, double photons, int32_t batch, int32_t fallback,
+                           int32_t* used_fallback, double* e_seed, double* e_flat);
 
 #ifdef __cplusplus
 }

@@ -76,6 +76,27 @@ SIGNATURES = {
     "pty_nll_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pty_nll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_double)]),
+    "pty_model_error": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pty_set_truth": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_float]),
+    "pty_nrmse": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pty_get_nrmse": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "pty_cnn_create": (C.c_int, [C.c_int32, C.c_void_p, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]),
+    "pty_cnn_destroy": (None, [C.c_void_p]),
+    "pty_cnn_last_error": (C.c_char_p, [C.c_void_p]),
+    "pty_cnn_num_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "pty_cnn_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pty_cnn_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pty_cnn_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "pty_cnn_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                               C.POINTER(C.c_double)]),
+    "pty_cnn_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                     C.POINTER(C.c_double)]),
+    "pty_cnn_input": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_double, C.c_void_p]),
+    "pty_poisson": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_uint64]),
+    "pty_training_targets": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pty_stitch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pty_seed_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
 
 TIMING_FAMILIES = ["rows_fwd", "cols", "rows_inv", "obj_gather", "probe_acc", "probe_finish_apply",

@@ -100,6 +100,17 @@ struct pty_ctx {
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
 
+  // evaluation against a known object: invariant NRMSE on a region of interest
+  float2* truth = nullptr;
+  unsigned char* roi = nullptr;
+  double* nrmse_dev = nullptr;     // one per iteration (capacity err_cap)
+  double* nrmse_part = nullptr;
+  double* eval_dev = nullptr;      // scratch scalars
+  bool have_truth = false;
+  // learned seed
+  float* seed_patches = nullptr;   size_t seed_patches_n = 0;
+  float2* seed_obj = nullptr;
+
   bool dm_valid = false;           // psi / contrib consistent with object and probe
   bool den_valid = false;          // den holds sum_j S_j^T sum_k |P_k|^2 for all positions
   Group all;                       // DM: every position
@@ -355,16 +366,30 @@ void ensure_common(pty_ctx* c, int chunk, size_t slots) {
 }
 
 void ensure_err_slot(pty_ctx* c, int n_iter) {
-  if (c->iter + n_iter <= c->err_cap) return;
+  if (c->err_dev && c->iter + n_iter <= c->err_cap) return;
   int cap = std::max(256, c->err_cap);
   while (cap < c->iter + n_iter) cap *= 2;
   double* nb = c->alloc<double>(cap);
-  if (c->err_dev && c->iter > 0)
+  double* nr = c->alloc<double>(cap);
+  if (c->err_dev && c->iter > 0) {
     PTY_HIP(hipMemcpyAsync(nb, c->err_dev, sizeof(double) * c->iter, hipMemcpyDeviceToDevice, c->stream));
+    PTY_HIP(hipMemcpyAsync(nr, c->nrmse_dev, sizeof(double) * c->iter, hipMemcpyDeviceToDevice, c->stream));
+  }
   PTY_HIP(hipStreamSynchronize(c->stream));
   c->dfree(c->err_dev);
+  c->dfree(c->nrmse_dev);
   c->err_dev = nb;
+  c->nrmse_dev = nr;
   c->err_cap = cap;
+}
+
+// Closes iteration t: records the NRMSE against the truth, if one is set.
+void end_iteration(pty_ctx* c, int t) {
+  if (c->have_truth)
+    timed(c, kOther, [&] {
+      launch_nrmse(c->obj, c->truth, c->roi, size_t(c->H) * c->W, c->nrmse_part, c->nrmse_dev + t, c->stream);
+    });
+  c->iter++;
 }
 
 FourierArgs fourier_args(pty_ctx* c, const Group& g) {
@@ -393,7 +418,7 @@ FourierArgs fourier_args(pty_ctx* c, const Group& g) {
 // Forward rows, columns with the modulus projection, inverse rows, over the
 // slots [s0, s0 + count) of group g in chunks.
 void fourier_pass(pty_ctx* c, const Group& g, int s0, int count, int chunk, RowIn in, ColOp op,
-                  RowOut out) {
+                  RowOut out, bool inverse = true) {
   FourierArgs a = fourier_args(c, g);
   for (int off = 0; off < count; off += chunk) {
     a.jl_off = s0 + off;
@@ -401,7 +426,7 @@ void fourier_pass(pty_ctx* c, const Group& g, int s0, int count, int chunk, RowI
     a.nc = std::min(chunk, count - off);
     timed(c, kRowsFwd, [&] { launch_rows_fwd(a, in); });
     timed(c, kCols, [&] { launch_cols(a, op); });
-    if (op != ColOp::Intensity) timed(c, kRowsInv, [&] { launch_rows_inv(a, out); });
+    if (inverse && op != ColOp::Intensity) timed(c, kRowsInv, [&] { launch_rows_inv(a, out); });
   }
 }
 
@@ -552,7 +577,7 @@ void run_dm(pty_ctx* c, int n_iter, const pty_iter_params& p) {
     }
     fourier_pass(c, g, 0, c->J, chunk, RowIn::DmReflect, ColOp::Project, RowOut::DmUpdate);
     timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
-    c->iter++;
+    end_iteration(c, t);
   }
 }
 
@@ -626,7 +651,7 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       if (pon) probe_apply(c, PrbApply::LsqUpdate, c->num_p2, g_prb, p.beta_probe);
     }
     timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
-    c->iter++;
+    end_iteration(c, t);
   }
   c->den_valid = false;  // den holds the last group's density only
 }
@@ -689,7 +714,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       std::swap(c->probe, c->probe_alt);
     }
     timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
-    c->iter++;
+    end_iteration(c, t);
   }
   c->den_valid = false;
 }
@@ -742,6 +767,80 @@ double run_nll(pty_ctx* c, const float2* obj, const float2* probe, bool grad, fl
   PTY_HIP(hipMemcpyAsync(&loss, c->loss_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   PTY_HIP(hipStreamSynchronize(c->stream));
   return loss;
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation and the learned seed
+// ---------------------------------------------------------------------------
+// Amplitude error E of the current object and probe over all positions
+// (forward rows, columns with the projection's error partials, no inverse).
+double model_error(pty_ctx* c) {
+  pty_iter_params p;
+  pty_default_params(&p);
+  const int chunk = chunk_patterns(c, p);
+  ensure_all_group(c);
+  ensure_common(c, std::min(chunk, c->J), 1);
+  c->ensure_once(c->eval_dev, 8);
+  fourier_pass(c, c->all, 0, c->J, chunk, RowIn::Plain, ColOp::Project, RowOut::StoreChi, false);
+  launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->eval_dev, c->stream);
+  double e = 0.0;
+  PTY_HIP(hipMemcpyAsync(&e, c->eval_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  PTY_HIP(hipStreamSynchronize(c->stream));
+  return e;
+}
+
+// Placement of each predicted patch: the central N/2 x N/2 of the window at
+// the nearest integer position.
+std::vector<int2> seed_placements(const pty_ctx* c) {
+  std::vector<int2> t(c->J);
+  for (int j = 0; j < c->J; ++j) {
+    const PosInfo& p = c->hpos[j];
+    t[j] = make_int2(p.iy + (p.fy >= 0.5f ? 1 : 0) + c->N / 4, p.ix + (p.fx >= 0.5f ? 1 : 0) + c->N / 4);
+  }
+  return t;
+}
+
+// Stitches J patches (J x 64 x 64 x (amplitude, phase), device) into dst.
+void stitch(pty_ctx* c, const float* patches, float2* dst) {
+  if (c->N != 128) throw Unsupported("stitching needs 128 x 128 windows (64 x 64 patches)");
+  const std::vector<int2> t = seed_placements(c);
+  const int bh = (c->H + 63) / 64, bw = (c->W + 63) / 64;
+  std::vector<int> beg(size_t(bh) * bw + 1, 0), idx(c->J);
+  for (int j = 0; j < c->J; ++j) beg[size_t(t[j].x / 64) * bw + t[j].y / 64 + 1]++;
+  for (size_t b = 0; b < size_t(bh) * bw; ++b) beg[b + 1] += beg[b];
+  std::vector<int> fill(beg.begin(), beg.end() - 1);
+  for (int j = 0; j < c->J; ++j) idx[fill[size_t(t[j].x / 64) * bw + t[j].y / 64]++] = j;
+  const int hc = (c->H + 7) / 8, wc = (c->W + 7) / 8;
+  int2* d_t = c->alloc<int2>(c->J);
+  int* d_beg = nullptr;
+  int* d_idx = nullptr;
+  float2* d_S = nullptr;
+  float2* d_ph = nullptr;
+  try {
+    d_beg = c->alloc<int>(beg.size());
+    d_idx = c->alloc<int>(idx.size());
+    d_S = c->alloc<float2>(size_t(hc) * wc);
+    d_ph = c->alloc<float2>(c->J);
+    PTY_HIP(hipMemcpyAsync(d_t, t.data(), sizeof(int2) * c->J, hipMemcpyHostToDevice, c->stream));
+    PTY_HIP(hipMemcpyAsync(d_beg, beg.data(), sizeof(int) * beg.size(), hipMemcpyHostToDevice, c->stream));
+    PTY_HIP(hipMemcpyAsync(d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
+    launch_fill_u32(reinterpret_cast<unsigned*>(d_S), size_t(hc) * wc * 2, 0u, c->stream);
+    launch_seed_chain(patches, d_t, c->J, d_S, wc, d_ph, c->stream);
+    launch_seed_stitch(patches, d_t, d_ph, d_beg, d_idx, bw, bh, dst, c->H, c->W, c->stream);
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  } catch (...) {
+    c->dfree(d_t);
+    c->dfree(d_beg);
+    c->dfree(d_idx);
+    c->dfree(d_S);
+    c->dfree(d_ph);
+    throw;
+  }
+  c->dfree(d_t);
+  c->dfree(d_beg);
+  c->dfree(d_idx);
+  c->dfree(d_S);
+  c->dfree(d_ph);
 }
 
 }  // namespace
@@ -903,7 +1002,7 @@ pty_status pty_iterate(pty_ctx* c, pty_algo algo, int32_t n_iter, const pty_iter
     require(p.chunk >= 0, "pty_iterate: negative chunk");
     require(p.lsqml_batch >= 0, "pty_iterate: negative lsqml_batch");
     require_loaded(c);
-    if (n_iter == 0) return;
+    if (n_iter == 0 && algo == PTY_EPIE) return;
     c->set_device();
     if (algo == PTY_DM)
       run_dm(c, n_iter, p);
@@ -911,6 +1010,7 @@ pty_status pty_iterate(pty_ctx* c, pty_algo algo, int32_t n_iter, const pty_iter
       run_lsqml(c, n_iter, p);
     else
       run_epie(c, n_iter, p);
+    if (n_iter == 0) PTY_HIP(hipStreamSynchronize(c->stream));
   });
 }
 
@@ -1096,6 +1196,156 @@ pty_status pty_simulate(pty_ctx* c, double photons, float* out, int on_device) {
       throw;
     }
     if (!on_device) c->dfree(dst);
+  });
+}
+
+pty_status pty_model_error(pty_ctx* c, double* out) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_model_error: null argument");
+    if (!c->have_patterns) throw StateError("patterns not loaded");
+    if (!c->have_positions) throw StateError("positions not loaded");
+    if (!c->have_object) throw StateError("object not set");
+    if (!c->have_probe) throw StateError("probe not set");
+    c->set_device();
+    *out = model_error(c);
+  });
+}
+
+pty_status pty_set_truth(pty_ctx* c, const void* truth, int on_device, float roi_frac) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_set_truth: null context");
+    c->set_device();
+    if (!truth) {
+      c->have_truth = false;
+      return;
+    }
+    require(roi_frac >= 0.f && roi_frac <= 1.f, "pty_set_truth: roi_frac must be in [0, 1]");
+    if (!c->have_positions) throw StateError("positions not loaded");
+    if (!c->have_probe) throw StateError("probe not set");
+    const size_t hw = size_t(c->H) * c->W;
+    ensure_all_group(c);
+    ensure_common(c, 1, 1);
+    c->ensure_once(c->truth, hw);
+    c->ensure_once(c->roi, hw);
+    c->ensure_once(c->nrmse_part, nrmse_part_doubles());
+    copy_in(c, c->truth, truth, hw * sizeof(float2), on_device);
+    // the density pass writes only tiles that some patch overlaps
+    launch_fill_u32(reinterpret_cast<unsigned*>(c->den), hw, 0u, c->stream);
+    density(c, c->all);
+    c->den_valid = true;
+    launch_roi_mask(c->den, c->scal, roi_frac, hw, c->roi, c->stream);
+    PTY_HIP(hipStreamSynchronize(c->stream));
+    c->have_truth = true;
+  });
+}
+
+pty_status pty_nrmse(pty_ctx* c, double* out) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_nrmse: null argument");
+    if (!c->have_truth) throw StateError("no truth set");
+    if (!c->have_object) throw StateError("object not set");
+    c->set_device();
+    c->ensure_once(c->eval_dev, 8);
+    launch_nrmse(c->obj, c->truth, c->roi, size_t(c->H) * c->W, c->nrmse_part, c->eval_dev, c->stream);
+    PTY_HIP(hipMemcpyAsync(out, c->eval_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+pty_status pty_get_nrmse(pty_ctx* c, double* out, int32_t cap, int32_t* n_written) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr && n_written != nullptr && cap >= 0, "pty_get_nrmse: bad argument");
+    c->set_device();
+    const int n = std::min(cap, c->iter);
+    if (n > 0) copy_out(c, out, c->nrmse_dev, sizeof(double) * n, 0);
+    else PTY_HIP(hipStreamSynchronize(c->stream));
+    *n_written = n;
+  });
+}
+
+pty_status pty_stitch(pty_ctx* c, const float* patches, void* out) {
+  return guarded(c, [&] {
+    require(c != nullptr && patches != nullptr, "pty_stitch: null argument");
+    if (!c->have_positions) throw StateError("positions not loaded");
+    c->set_device();
+    if (out) {
+      stitch(c, patches, static_cast<float2*>(out));
+    } else {
+      stitch(c, patches, c->obj);
+      c->have_object = true;
+      c->dm_valid = false;
+    }
+  });
+}
+
+pty_status pty_seed_object(pty_ctx* c, pty_cnn* net, double photons, int32_t batch, int32_t fallback,
+                           int32_t* used_fallback, double* e_seed, double* e_flat) {
+  return guarded(c, [&] {
+    require(c != nullptr && net != nullptr, "pty_seed_object: null argument");
+    require(std::isfinite(photons) && photons > 1.0, "pty_seed_object: photons must be > 1");
+    require(batch >= 1 && batch <= cnn_max_batch(net), "pty_seed_object: batch must be in 1..max_batch");
+    if (c->N != 128) throw Unsupported("the learned seed needs 128 x 128 windows");
+    if (cnn_device(net) != c->device) throw InvalidArg("pty_seed_object: network on another device");
+    if (!c->have_patterns) throw StateError("patterns not loaded");
+    if (!c->have_positions) throw StateError("positions not loaded");
+    if (fallback && !c->have_probe) throw StateError("probe not set");
+    c->set_device();
+    const size_t per = size_t(64) * 64 * 2;
+    c->ensure(c->seed_patches, c->seed_patches_n, size_t(c->J) * per);
+    const float inv = (float)(1.0 / std::log1p(photons));
+    float* x = cnn_input_buffer(net);
+    for (int j0 = 0; j0 < c->J; j0 += batch) {
+      const int nb = std::min(batch, c->J - j0);
+      launch_input_from_amp(c->amp, c->N, j0, nb, x, inv, c->stream);
+      const float* y = cnn_forward_batch(net, x, nb, c->stream);
+      PTY_HIP(hipMemcpyAsync(c->seed_patches + size_t(j0) * per, y, sizeof(float) * per * nb,
+                             hipMemcpyDeviceToDevice, c->stream));
+    }
+    const size_t hw = size_t(c->H) * c->W;
+    if (!fallback) {
+      stitch(c, c->seed_patches, c->obj);
+      c->have_object = true;
+      c->dm_valid = false;
+      if (used_fallback) *used_fallback = 0;
+      return;
+    }
+    c->ensure_once(c->seed_obj, hw);
+    stitch(c, c->seed_patches, c->seed_obj);
+    PTY_HIP(hipMemcpyAsync(c->obj, c->seed_obj, hw * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+    const double es = model_error(c);
+    launch_fill_c64(c->obj, hw, make_float2(1.f, 0.f), c->stream);
+    const double ef = model_error(c);
+    const bool use_seed = std::isfinite(es) && es <= ef;
+    if (use_seed)
+      PTY_HIP(hipMemcpyAsync(c->obj, c->seed_obj, hw * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+    PTY_HIP(hipStreamSynchronize(c->stream));
+    c->have_object = true;
+    c->dm_valid = false;
+    if (used_fallback) *used_fallback = use_seed ? 0 : 1;
+    if (e_seed) *e_seed = es;
+    if (e_flat) *e_flat = ef;
+  });
+}
+
+pty_status pty_training_targets(pty_ctx* c, float* out) {
+  return guarded(c, [&] {
+    require(c != nullptr && out != nullptr, "pty_training_targets: null argument");
+    if (!c->have_positions) throw StateError("positions not loaded");
+    if (!c->have_object) throw StateError("object not set");
+    for (const PosInfo& p : c->hpos)
+      require(p.fy == 0.f && p.fx == 0.f, "pty_training_targets: positions must be integers");
+    c->set_device();
+    launch_targets(c->obj, c->W, c->pos, c->J, c->N, out, c->stream);
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+pty_status pty_poisson(pty_ctx* c, const float* lam, float* out, size_t n, uint64_t seed) {
+  return guarded(c, [&] {
+    require(c != nullptr && lam != nullptr && out != nullptr, "pty_poisson: null argument");
+    c->set_device();
+    launch_poisson(lam, out, n, seed, c->stream);
+    PTY_HIP(hipStreamSynchronize(c->stream));
   });
 }
 

@@ -1,0 +1,906 @@
+// Learned initialiser: a small U-Net on bf16 MFMA (gfx950), trained on the GPU.
+//
+// Architecture (NHWC activations, 3 x 3 convolutions with zero padding 1,
+// 2 x 2 average pooling, 2x nearest upsampling, skips concatenated after the
+// upsampled channels):
+//   L0 conv 1->32 @128 relu, pool; L1 32->32 @64 relu (e1), pool;
+//   L2 32->64 @32 relu (e2), pool; L3 64->128 @16 relu (e3), pool;
+//   L4 128->256 @8 relu; L5 256->256 @8 relu, up, concat e3;
+//   L6 384->128 @16 relu, up, concat e2; L7 192->64 @32 relu, up, concat e1;
+//   L8 96->32 @64 relu; L9 32->2 @64 linear (amplitude, phase).
+// Input: one 128 x 128 pattern as log1p(counts) / log1p(photons); output: the
+// central 64 x 64 object patch.  Weights W[cout][ky][kx][cin] (bf16 copies of
+// float32 masters), biases float32; loss = mean squared error; Adam.
+//
+// Convolutions with cin, cout multiples of 32 are implicit GEMMs on
+// v_mfma_f32_16x16x32_bf16 (pixels x output channels, reduction over
+// taps x input channels, float32 accumulation); the input gradient is the same
+// GEMM with transposed, spatially flipped weights; the weight gradient is an
+// MFMA GEMM over pixels with split-K partials summed in a fixed order.  The
+// 1-channel input layer and the 2-channel output layer use direct kernels.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "ptymi.h"
+#include "pty_common.hpp"
+#include "pty_kernels.hpp"
+
+namespace pty {
+namespace {
+
+using bf16 = __hip_bfloat16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+__device__ __forceinline__ float tof(bf16 v) { return __bfloat162float(v); }
+__device__ __forceinline__ bf16 tob(float v) { return __float2bfloat16(v); }
+
+// A strided NHWC view: element (b, y, x, c) at ((b*H + y)*W + x)*cs + co + c.
+struct View {
+  bf16* p;
+  int cs, co;
+};
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM convolution on MFMA.  out[m][n] = act(bias[n] +
+// sum_{tap, c} in[m + tap][c] * w[n][tap][c]), m = (b, y, x) pixels of an
+// S x S image, n output channels.  Block: 4 wavefronts x 16 pixels, BN output
+// channels (BN / 16 MFMA tiles per wavefront).
+// ---------------------------------------------------------------------------
+template <int BN, bool RELU, bool BIAS>
+__global__ __launch_bounds__(256) void k_conv_mfma(View in, const bf16* __restrict__ w,
+                                                   const float* __restrict__ bias, View out, int nb, int S,
+                                                   int cin, int cout) {
+  constexpr int NT = BN / 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * 64 + wv * 16;
+  const int n0 = blockIdx.y * BN;
+  const int mtot = nb * S * S;
+  const int row = lane & 15, grp = lane >> 4;
+  // the pixel whose row of A this lane supplies
+  const int am = m0 + row;
+  const bool am_ok = am < mtot;
+  const int ab = am / (S * S), ay = (am / S) % S, ax = am % S;
+  f32x4_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int ktap = 9 * cin;
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = ay + tap / 3 - 1, xx = ax + tap % 3 - 1;
+    const bool ok = am_ok && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
+    const bf16* ap = in.p + ((size_t)(ab * S + yy) * S + xx) * in.cs + in.co + grp * 8;
+    for (int c0 = 0; c0 < cin; c0 += 32) {
+      bf16x8_t a;
+      if (ok) {
+        a = *reinterpret_cast<const bf16x8_t*>(ap + c0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = (__bf16)0.0f;
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int n = n0 + t * 16 + row;
+        const bf16x8_t b =
+            *reinterpret_cast<const bf16x8_t*>(w + ((size_t)n * 9 + tap) * cin + c0 + grp * 8);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  (void)ktap;
+  // D[i][j]: j = lane % 16 (output channel), i = 4 * (lane / 16) + r (pixel)
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int n = n0 + t * 16 + row;
+    const float bv = BIAS ? bias[n] : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + grp * 4 + r;
+      if (m >= mtot) continue;
+      float v = acc[t][r] + bv;
+      if (RELU) v = fmaxf(v, 0.f);
+      out.p[(size_t)m * out.cs + out.co + n] = tob(v);
+    }
+  }
+}
+
+// Weight gradient on MFMA: part[split][n][tap][c] = sum over the split's pixels
+// m of dz[m][n] * in[m + tap][c].  Block = 4 wavefronts on a 32 x 32 (n, c)
+// tile of one tap; each wavefront owns a 16 x 16 quarter.  Pixel chunks of 32
+// are staged through LDS transposed so every fragment is 16 contiguous bytes.
+__global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __restrict__ part, int nb, int S,
+                                                    int cin, int cout, int px_per_split) {
+  __shared__ __align__(16) bf16 sd[32][40];  // [n][pixel], padded rows
+  __shared__ __align__(16) bf16 sx[32][40];  // [c][pixel]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n0 = blockIdx.x * 32, c0 = (blockIdx.y % (cin / 32)) * 32, tap = blockIdx.y / (cin / 32);
+  const int split = blockIdx.z;
+  const int mtot = nb * S * S;
+  const int mb = split * px_per_split, me = min(mtot, mb + px_per_split);
+  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const int wi = (wv >> 1) * 16, wj = (wv & 1) * 16;  // this wavefront's (n, c) quarter
+  const int row = lane & 15, grp = lane >> 4;
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  // loader: thread t -> pixel t / 8, channel group t % 8 (4 channels each)
+  const int lp = threadIdx.x >> 3, lc = (threadIdx.x & 7) * 4;
+  for (int m = mb; m < me; m += 32) {
+    const int pm = m + lp;
+    bf16 vd[4], vx[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      vd[i] = tob(0.f);
+      vx[i] = tob(0.f);
+    }
+    if (pm < me) {
+      const int b = pm / (S * S), y = (pm / S) % S, x = pm % S;
+      const bf16* dp = dz.p + (size_t)pm * dz.cs + dz.co + n0 + lc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) vd[i] = dp[i];
+      const int yy = y + dy, xx = x + dx;
+      if ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
+        const bf16* xp = in.p + ((size_t)(b * S + yy) * S + xx) * in.cs + in.co + c0 + lc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vx[i] = xp[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      sd[lc + i][lp] = vd[i];
+      sx[lc + i][lp] = vx[i];
+    }
+    __syncthreads();
+    // rows are 80 bytes, so every 8-element fragment is 16-byte aligned
+    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sd[wi + row][grp * 8]);
+    const bf16x8_t bb = *reinterpret_cast<const bf16x8_t*>(&sx[wj + row][grp * 8]);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+  }
+  // D[i][j]: i = n (4 * grp + r), j = c (row)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int n = n0 + wi + grp * 4 + r, c = c0 + wj + row;
+    part[(((size_t)split * cout + n) * 9 + tap) * cin + c] = acc[r];
+  }
+}
+
+// sum over splits in order: dst[i] = sum_s part[s][i]
+__global__ void k_sum_splits(const float* __restrict__ part, int splits, size_t n, float* __restrict__ dst) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
+  dst[i] = s;
+}
+
+// split a [n][k + 1] gradient block (k weights, then the bias) into w[n][k] and b[n]
+__global__ void k_unpack_wb(const float* __restrict__ src, int k, int cout, float* __restrict__ w,
+                            float* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cout * (k + 1)) return;
+  const int n = i / (k + 1), r = i % (k + 1);
+  if (r < k) w[n * k + r] = src[i];
+  else b[n] = src[i];
+}
+
+// bias gradient: db[n] = sum_m dz[m][n]; one block per channel, ordered partial sums
+__global__ __launch_bounds__(256) void k_bias_grad(View dz, int mtot, int cout, float* __restrict__ db) {
+  __shared__ float sh[256];
+  const int n = blockIdx.x;
+  float s = 0.f;
+  for (int m = threadIdx.x; m < mtot; m += 256) s += tof(dz.p[(size_t)m * dz.cs + dz.co + n]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[n] = sh[0];
+}
+
+// transposed, spatially flipped weights for the input gradient:
+// wt[c][tap][n] = w[n][8 - tap][c]
+__global__ void k_wflip(const bf16* __restrict__ w, bf16* __restrict__ wt, int cin, int cout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cin * 9 * cout) return;
+  const int n = i % cout, tap = (i / cout) % 9, c = i / (cout * 9);
+  wt[i] = w[((size_t)n * 9 + (8 - tap)) * cin + c];
+}
+
+// ---------------------------------------------------------------------------
+// Direct kernels of the 1-channel input and 2-channel output layers
+// ---------------------------------------------------------------------------
+// L0: out[b][y][x][n] = relu(bias[n] + sum_tap in[b][y+dy][x+dx] w[n][tap]); in float32
+__global__ void k_conv_in(const float* __restrict__ in, const bf16* __restrict__ w, const float* __restrict__ bias,
+                          View out, int nb, int S, int cout) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nb * S * S) return;
+  const int b = m / (S * S), y = (m / S) % S, x = m % S;
+  float v[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    v[tap] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) ? in[((size_t)b * S + yy) * S + xx] : 0.f;
+  }
+  for (int n = 0; n < cout; ++n) {
+    float s = bias[n];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) s += v[tap] * tof(w[n * 9 + tap]);
+    out.p[(size_t)m * out.cs + out.co + n] = tob(fmaxf(s, 0.f));
+  }
+}
+
+// L9: y[m][n] = bias[n] + sum_{tap,c} in[m + tap][c] w[n][tap][c], float32 out (n < 2)
+__global__ void k_conv_out(View in, const bf16* __restrict__ w, const float* __restrict__ bias, float* __restrict__ y,
+                           int nb, int S, int cin) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nb * S * S) return;
+  const int b = m / (S * S), yy0 = (m / S) % S, xx0 = m % S;
+  float s0 = bias[0], s1 = bias[1];
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = yy0 + tap / 3 - 1, xx = xx0 + tap % 3 - 1;
+    if ((unsigned)yy >= (unsigned)S || (unsigned)xx >= (unsigned)S) continue;
+    const bf16* ip = in.p + ((size_t)(b * S + yy) * S + xx) * in.cs + in.co;
+    for (int c = 0; c < cin; ++c) {
+      const float a = tof(ip[c]);
+      s0 += a * tof(w[(0 * 9 + tap) * cin + c]);
+      s1 += a * tof(w[(1 * 9 + tap) * cin + c]);
+    }
+  }
+  y[(size_t)m * 2] = s0;
+  y[(size_t)m * 2 + 1] = s1;
+}
+
+// L9 input gradient fused with L8's relu: dz8[m][c] = (a8[m][c] > 0) *
+// sum_{n, tap} dy[m - tap][n] w[n][tap][c]
+__global__ void k_conv_out_dgrad(const float* __restrict__ dy, const bf16* __restrict__ w, View a8, View dz8,
+                                 int nb, int S, int cin) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nb * S * S) return;
+  const int b = m / (S * S), y0 = (m / S) % S, x0 = m % S;
+  float g[2][9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    // output pixel o with o + tap - 1 = m, i.e. o = m - (tap - 1)
+    const int yy = y0 - (tap / 3 - 1), xx = x0 - (tap % 3 - 1);
+    const bool ok = (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
+    const size_t o = ((size_t)(b * S + yy) * S + xx) * 2;
+    g[0][tap] = ok ? dy[o] : 0.f;
+    g[1][tap] = ok ? dy[o + 1] : 0.f;
+  }
+  for (int c = 0; c < cin; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+      s += g[0][tap] * tof(w[(0 * 9 + tap) * cin + c]) + g[1][tap] * tof(w[(1 * 9 + tap) * cin + c]);
+    const float act = tof(a8.p[(size_t)m * a8.cs + a8.co + c]);
+    dz8.p[(size_t)m * dz8.cs + dz8.co + c] = tob(act > 0.f ? s : 0.f);
+  }
+}
+
+// Weight and bias gradient of a small layer by direct sums: thread = one
+// parameter, block = one pixel slice; part[split][param].
+// L0 (in float32, 1 channel) and L9 (dz float32, 2 channels) variants.
+__global__ void k_wgrad_in(const float* __restrict__ in, View dz, float* __restrict__ part, int nb, int S, int cout,
+                           int px_per_split) {
+  const int np = cout * 10;  // 9 taps + bias per output channel
+  const int pidx = threadIdx.x;
+  if (pidx >= np) return;
+  const int n = pidx / 10, k = pidx % 10;
+  const int mtot = nb * S * S, mb = blockIdx.x * px_per_split, me = min(mtot, mb + px_per_split);
+  float s = 0.f;
+  for (int m = mb; m < me; ++m) {
+    const float d = tof(dz.p[(size_t)m * dz.cs + dz.co + n]);
+    if (k == 9) {
+      s += d;
+    } else {
+      const int b = m / (S * S), y = (m / S) % S + k / 3 - 1, x = m % S + k % 3 - 1;
+      if ((unsigned)y < (unsigned)S && (unsigned)x < (unsigned)S) s += d * in[((size_t)b * S + y) * S + x];
+    }
+  }
+  part[(size_t)blockIdx.x * np + pidx] = s;
+}
+
+__global__ void k_wgrad_out(View in, const float* __restrict__ dy, float* __restrict__ part, int nb, int S, int cin,
+                            int px_per_split) {
+  const int np = 2 * (9 * cin + 1);
+  const int mtot = nb * S * S, mb = blockIdx.x * px_per_split, me = min(mtot, mb + px_per_split);
+  for (int pidx = threadIdx.x; pidx < np; pidx += blockDim.x) {
+    const int n = pidx / (9 * cin + 1), k = pidx % (9 * cin + 1);
+    float s = 0.f;
+    if (k == 9 * cin) {
+      for (int m = mb; m < me; ++m) s += dy[(size_t)m * 2 + n];
+    } else {
+      const int tap = k / cin, c = k % cin;
+      for (int m = mb; m < me; ++m) {
+        const int b = m / (S * S), y = (m / S) % S + tap / 3 - 1, x = m % S + tap % 3 - 1;
+        if ((unsigned)y < (unsigned)S && (unsigned)x < (unsigned)S)
+          s += dy[(size_t)m * 2 + n] * tof(in.p[((size_t)(b * S + y) * S + x) * in.cs + in.co + c]);
+      }
+    }
+    part[(size_t)blockIdx.x * np + pidx] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pooling, upsampling, relu masks, loss, Adam
+// ---------------------------------------------------------------------------
+// out (S/2) = mean of 2x2 of in (S)
+__global__ void k_pool(View in, View out, int nb, int S, int c) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int so = S / 2;
+  if (i >= (size_t)nb * so * so * c) return;
+  const int ch = i % c;
+  const size_t m = i / c;
+  const int b = m / (so * so), y = (m / so) % so, x = m % so;
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    s += tof(in.p[((size_t)(b * S + 2 * y + k / 2) * S + 2 * x + k % 2) * in.cs + in.co + ch]);
+  out.p[m * out.cs + out.co + ch] = tob(0.25f * s);
+}
+
+// dx (S) += or = dy (S/2) / 4 broadcast
+template <bool ACC>
+__global__ void k_pool_back(View dy, View dx, int nb, int S, int c) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= (size_t)nb * S * S * c) return;
+  const int ch = i % c;
+  const size_t m = i / c;
+  const int b = m / (S * S), y = (m / S) % S, x = m % S, so = S / 2;
+  const float g = 0.25f * tof(dy.p[((size_t)(b * so + y / 2) * so + x / 2) * dy.cs + dy.co + ch]);
+  bf16* d = dx.p + m * dx.cs + dx.co + ch;
+  *d = tob(ACC ? tof(*d) + g : g);
+}
+
+// out (2S) = nearest upsampling of in (S)
+__global__ void k_up(View in, View out, int nb, int S, int c) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int so = 2 * S;
+  if (i >= (size_t)nb * so * so * c) return;
+  const int ch = i % c;
+  const size_t m = i / c;
+  const int b = m / (so * so), y = (m / so) % so, x = m % so;
+  out.p[m * out.cs + out.co + ch] = in.p[((size_t)(b * S + y / 2) * S + x / 2) * in.cs + in.co + ch];
+}
+
+// dx (S) = sum of the 2x2 block of dy (2S); relu mask of the layer that produced x applied
+__global__ void k_up_back_relu(View dy, View act, View dz, int nb, int S, int c) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= (size_t)nb * S * S * c) return;
+  const int ch = i % c;
+  const size_t m = i / c;
+  const int b = m / (S * S), y = (m / S) % S, x = m % S, si = 2 * S;
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    s += tof(dy.p[((size_t)(b * si + 2 * y + k / 2) * si + 2 * x + k % 2) * dy.cs + dy.co + ch]);
+  const float a = tof(act.p[m * act.cs + act.co + ch]);
+  dz.p[m * dz.cs + dz.co + ch] = tob(a > 0.f ? s : 0.f);
+}
+
+// in place: d = d * (act > 0)
+__global__ void k_relu_mask(View d, View act, size_t npx, int c) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= npx * c) return;
+  const int ch = i % c;
+  const size_t m = i / c;
+  if (!(tof(act.p[m * act.cs + act.co + ch]) > 0.f)) d.p[m * d.cs + d.co + ch] = tob(0.f);
+}
+
+// mean squared error: dy = 2 (y - t) / n, per-block partial loss sums
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t, size_t n,
+                                             float* __restrict__ dy, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const size_t i = blockIdx.x * (size_t)256 + threadIdx.x;
+  double s = 0.0;
+  if (i < n) {
+    const float d = y[i] - t[i];
+    dy[i] = 2.f * d / (float)n;
+    s = (double)d * d;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_d(const double* part, int n, double scale, double* out) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  *out = s * scale;
+}
+
+// Adam on float32 masters; refreshes the bf16 weight copy (bias entries keep float32)
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
+                       float* __restrict__ m2, size_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  p[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ src, bf16* __restrict__ dst, size_t n) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = tob(src[i]);
+}
+
+// network input from centred counts: log1p(max(d, 0)) / log1p(photons)
+__global__ void k_cnn_input(const float* __restrict__ d, float* __restrict__ x, size_t n, float inv) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = log1pf(fmaxf(d[i], 0.f)) * inv;
+}
+
+inline unsigned blocks(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------------------
+// Host side: buffers and the layer schedule
+// ---------------------------------------------------------------------------
+struct Conv {
+  int cin, cout, S;
+  bool relu;
+  size_t woff, boff;  // offsets in the flat parameter vector
+};
+
+constexpr int kLayers = 10;
+const int kSpec[kLayers][4] = {{1, 32, 128, 1},   {32, 32, 64, 1},   {32, 64, 32, 1},  {64, 128, 16, 1},
+                               {128, 256, 8, 1},  {256, 256, 8, 1},  {384, 128, 16, 1}, {192, 64, 32, 1},
+                               {96, 32, 64, 1},   {32, 2, 64, 0}};
+
+}  // namespace
+}  // namespace pty
+
+using namespace pty;
+
+struct pty_cnn {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int max_batch = 0;
+  std::string err;
+  std::vector<std::pair<void*, size_t>> allocs;
+  Conv L[kLayers];
+  size_t nparams = 0;
+  float* p = nullptr;    // float32 masters
+  float* g = nullptr;    // gradient
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  bf16* wb = nullptr;    // bf16 copy of the whole vector (weights used from it)
+  bf16* wt = nullptr;    // transposed-flipped weights scratch
+  float* part = nullptr; size_t part_n = 0;
+  double* lpart = nullptr; double* lsum = nullptr;
+  int64_t step = 0;
+  // activations (bf16 NHWC)
+  bf16 *a0, *p0, *cat8, *p1, *cat7, *p2, *cat6, *p3, *a4, *a5, *a6, *a7, *a8;
+  // gradients
+  bf16 *g0, *gp0, *gcat8, *gp1, *gcat7, *gp2, *gcat6, *gp3, *g4, *g5, *g6, *g7, *g8;
+  float *y, *gy, *xin;
+
+  void* dalloc(size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw NoMemError(std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    allocs.emplace_back(q, bytes);
+    return q;
+  }
+  template <typename T>
+  T* alloc(size_t n) { return static_cast<T*>(dalloc(n * sizeof(T))); }
+  ~pty_cnn() {
+    for (auto& a : allocs) (void)hipFree(a.first);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+thread_local std::string g_cnn_err;
+
+template <typename F>
+pty_status cnn_guard(pty_cnn* c, F&& f) {
+  try {
+    f();
+    return PTY_OK;
+  } catch (const std::invalid_argument& e) {
+    if (c) c->err = e.what();
+    g_cnn_err = e.what();
+    return PTY_E_INVALID;
+  } catch (const NoMemError& e) {
+    if (c) c->err = e.what();
+    g_cnn_err = e.what();
+    return PTY_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    g_cnn_err = e.what();
+    return PTY_E_DEVICE;
+  }
+}
+
+View V(bf16* p, int cs, int co = 0) { return View{p, cs, co}; }
+
+void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out, int nb, int S, int cin, int cout,
+                 bool relu) {
+  const int mtot = nb * S * S;
+  if (cin % 32 != 0 || cout % 32 != 0) throw std::invalid_argument("conv channels must be multiples of 32");
+  const int bn = cout % 64 == 0 ? 64 : 32;
+  dim3 grid(blocks(mtot, 64), cout / bn);
+  if (bn == 64) {
+    if (relu) k_conv_mfma<64, true, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+    else if (bias) k_conv_mfma<64, false, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+    else k_conv_mfma<64, false, false><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+  } else {
+    if (relu) k_conv_mfma<32, true, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+    else if (bias) k_conv_mfma<32, false, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+    else k_conv_mfma<32, false, false><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+  }
+  PTY_LAUNCH_CHECK("conv_mfma");
+}
+
+// input gradient of an MFMA layer: dx = conv(dz, flipped transposed w)
+void launch_dgrad(pty_cnn* c, int li, View dz, View dx, int nb) {
+  const Conv& l = c->L[li];
+  const int n = l.cin * 9 * l.cout;
+  k_wflip<<<blocks(n), 256, 0, c->stream>>>(c->wb + l.woff, c->wt, l.cin, l.cout);
+  PTY_LAUNCH_CHECK("wflip");
+  launch_conv(c, dz, c->wt, nullptr, dx, nb, l.S, l.cout, l.cin, false);
+}
+
+// weight + bias gradient of an MFMA layer into c->g
+void launch_wgrad(pty_cnn* c, int li, View dz, View in, int nb) {
+  const Conv& l = c->L[li];
+  const int mtot = nb * l.S * l.S;
+  const int px = 4096;
+  const int splits = (mtot + px - 1) / px;
+  const size_t nw = (size_t)l.cout * 9 * l.cin;
+  if ((size_t)splits * nw > c->part_n) throw std::invalid_argument("wgrad scratch too small");
+  dim3 grid(l.cout / 32, 9 * (l.cin / 32), splits);
+  k_wgrad_mfma<<<grid, 256, 0, c->stream>>>(dz, in, c->part, nb, l.S, l.cin, l.cout, px);
+  PTY_LAUNCH_CHECK("wgrad_mfma");
+  k_sum_splits<<<blocks(nw), 256, 0, c->stream>>>(c->part, splits, nw, c->g + l.woff);
+  PTY_LAUNCH_CHECK("sum_splits");
+  k_bias_grad<<<l.cout, 256, 0, c->stream>>>(dz, mtot, l.cout, c->g + l.boff);
+  PTY_LAUNCH_CHECK("bias_grad");
+}
+
+void forward(pty_cnn* c, const float* x, int nb) {
+  auto& L = c->L;
+  const bf16* w = c->wb;
+  hipStream_t s = c->stream;
+  k_conv_in<<<blocks((size_t)nb * 128 * 128), 256, 0, s>>>(x, w + L[0].woff, c->p + L[0].boff, V(c->a0, 32), nb, 128,
+                                                          32);
+  PTY_LAUNCH_CHECK("conv_in");
+  k_pool<<<blocks((size_t)nb * 64 * 64 * 32), 256, 0, s>>>(V(c->a0, 32), V(c->p0, 32), nb, 128, 32);
+  launch_conv(c, V(c->p0, 32), w + L[1].woff, c->p + L[1].boff, V(c->cat8, 96, 64), nb, 64, 32, 32, true);  // e1
+  k_pool<<<blocks((size_t)nb * 32 * 32 * 32), 256, 0, s>>>(V(c->cat8, 96, 64), V(c->p1, 32), nb, 64, 32);
+  launch_conv(c, V(c->p1, 32), w + L[2].woff, c->p + L[2].boff, V(c->cat7, 192, 128), nb, 32, 32, 64, true);  // e2
+  k_pool<<<blocks((size_t)nb * 16 * 16 * 64), 256, 0, s>>>(V(c->cat7, 192, 128), V(c->p2, 64), nb, 32, 64);
+  launch_conv(c, V(c->p2, 64), w + L[3].woff, c->p + L[3].boff, V(c->cat6, 384, 256), nb, 16, 64, 128, true);  // e3
+  k_pool<<<blocks((size_t)nb * 8 * 8 * 128), 256, 0, s>>>(V(c->cat6, 384, 256), V(c->p3, 128), nb, 16, 128);
+  launch_conv(c, V(c->p3, 128), w + L[4].woff, c->p + L[4].boff, V(c->a4, 256), nb, 8, 128, 256, true);
+  launch_conv(c, V(c->a4, 256), w + L[5].woff, c->p + L[5].boff, V(c->a5, 256), nb, 8, 256, 256, true);
+  k_up<<<blocks((size_t)nb * 16 * 16 * 256), 256, 0, s>>>(V(c->a5, 256), V(c->cat6, 384, 0), nb, 8, 256);
+  launch_conv(c, V(c->cat6, 384), w + L[6].woff, c->p + L[6].boff, V(c->a6, 128), nb, 16, 384, 128, true);
+  k_up<<<blocks((size_t)nb * 32 * 32 * 128), 256, 0, s>>>(V(c->a6, 128), V(c->cat7, 192, 0), nb, 16, 128);
+  launch_conv(c, V(c->cat7, 192), w + L[7].woff, c->p + L[7].boff, V(c->a7, 64), nb, 32, 192, 64, true);
+  k_up<<<blocks((size_t)nb * 64 * 64 * 64), 256, 0, s>>>(V(c->a7, 64), V(c->cat8, 96, 0), nb, 32, 64);
+  launch_conv(c, V(c->cat8, 96), w + L[8].woff, c->p + L[8].boff, V(c->a8, 32), nb, 64, 96, 32, true);
+  k_conv_out<<<blocks((size_t)nb * 64 * 64), 256, 0, s>>>(V(c->a8, 32), w + L[9].woff, c->p + L[9].boff, c->y, nb, 64,
+                                                         32);
+  PTY_LAUNCH_CHECK("cnn_forward");
+}
+
+// gradient of the loss into c->g, given dL/dy in c->gy
+void backward(pty_cnn* c, const float* x, int nb) {
+  auto& L = c->L;
+  hipStream_t s = c->stream;
+  const int px = 4096;
+  // L9: weight gradient and input gradient (with L8's relu)
+  {
+    const int mtot = nb * 64 * 64, splits = (mtot + px - 1) / px, np = 2 * (9 * 32 + 1);
+    k_wgrad_out<<<splits, 256, 0, s>>>(V(c->a8, 32), c->gy, c->part, nb, 64, 32, px);
+    k_sum_splits<<<blocks(np), 256, 0, s>>>(c->part, splits, np, c->part + (size_t)splits * np);
+    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)splits * np, 9 * 32, 2, c->g + L[9].woff,
+                                           c->g + L[9].boff);
+    PTY_LAUNCH_CHECK("wgrad_out");
+    k_conv_out_dgrad<<<blocks((size_t)mtot), 256, 0, s>>>(c->gy, c->wb + L[9].woff, V(c->a8, 32), V(c->g8, 32), nb, 64,
+                                                         32);
+    PTY_LAUNCH_CHECK("conv_out_dgrad");
+  }
+  // L8 (input cat8 = [up(a7) | e1]); g8 holds dz8
+  launch_wgrad(c, 8, V(c->g8, 32), V(c->cat8, 96), nb);
+  launch_dgrad(c, 8, V(c->g8, 32), V(c->gcat8, 96), nb);
+  // up(a7) part -> dz7 (relu of L7), stored in g7
+  k_up_back_relu<<<blocks((size_t)nb * 32 * 32 * 64), 256, 0, s>>>(V(c->gcat8, 96, 0), V(c->a7, 64), V(c->g7, 64), nb, 32,
+                                                                  64);
+  launch_wgrad(c, 7, V(c->g7, 64), V(c->cat7, 192), nb);
+  launch_dgrad(c, 7, V(c->g7, 64), V(c->gcat7, 192), nb);
+  k_up_back_relu<<<blocks((size_t)nb * 16 * 16 * 128), 256, 0, s>>>(V(c->gcat7, 192, 0), V(c->a6, 128), V(c->g6, 128),
+                                                                   nb, 16, 128);
+  launch_wgrad(c, 6, V(c->g6, 128), V(c->cat6, 384), nb);
+  launch_dgrad(c, 6, V(c->g6, 128), V(c->gcat6, 384), nb);
+  k_up_back_relu<<<blocks((size_t)nb * 8 * 8 * 256), 256, 0, s>>>(V(c->gcat6, 384, 0), V(c->a5, 256), V(c->g5, 256), nb,
+                                                                 8, 256);
+  launch_wgrad(c, 5, V(c->g5, 256), V(c->a4, 256), nb);
+  launch_dgrad(c, 5, V(c->g5, 256), V(c->g4, 256), nb);
+  k_relu_mask<<<blocks((size_t)nb * 64 * 256), 256, 0, s>>>(V(c->g4, 256), V(c->a4, 256), (size_t)nb * 64, 256);
+  launch_wgrad(c, 4, V(c->g4, 256), V(c->p3, 128), nb);
+  launch_dgrad(c, 4, V(c->g4, 256), V(c->gp3, 128), nb);
+  // e3 gradient = skip slice of gcat6 + pooled path; then relu of L3
+  k_pool_back<true><<<blocks((size_t)nb * 16 * 16 * 128), 256, 0, s>>>(V(c->gp3, 128), V(c->gcat6, 384, 256), nb, 16,
+                                                                      128);
+  k_relu_mask<<<blocks((size_t)nb * 256 * 128), 256, 0, s>>>(V(c->gcat6, 384, 256), V(c->cat6, 384, 256),
+                                                             (size_t)nb * 256, 128);
+  launch_wgrad(c, 3, V(c->gcat6, 384, 256), V(c->p2, 64), nb);
+  launch_dgrad(c, 3, V(c->gcat6, 384, 256), V(c->gp2, 64), nb);
+  k_pool_back<true><<<blocks((size_t)nb * 32 * 32 * 64), 256, 0, s>>>(V(c->gp2, 64), V(c->gcat7, 192, 128), nb, 32, 64);
+  k_relu_mask<<<blocks((size_t)nb * 1024 * 64), 256, 0, s>>>(V(c->gcat7, 192, 128), V(c->cat7, 192, 128),
+                                                             (size_t)nb * 1024, 64);
+  launch_wgrad(c, 2, V(c->gcat7, 192, 128), V(c->p1, 32), nb);
+  launch_dgrad(c, 2, V(c->gcat7, 192, 128), V(c->gp1, 32), nb);
+  k_pool_back<true><<<blocks((size_t)nb * 64 * 64 * 32), 256, 0, s>>>(V(c->gp1, 32), V(c->gcat8, 96, 64), nb, 64, 32);
+  k_relu_mask<<<blocks((size_t)nb * 4096 * 32), 256, 0, s>>>(V(c->gcat8, 96, 64), V(c->cat8, 96, 64),
+                                                             (size_t)nb * 4096, 32);
+  launch_wgrad(c, 1, V(c->gcat8, 96, 64), V(c->p0, 32), nb);
+  launch_dgrad(c, 1, V(c->gcat8, 96, 64), V(c->gp0, 32), nb);
+  // L0: pooled gradient back to 128 x 128, relu, then the direct weight gradient
+  k_pool_back<false><<<blocks((size_t)nb * 128 * 128 * 32), 256, 0, s>>>(V(c->gp0, 32), V(c->g0, 32), nb, 128, 32);
+  k_relu_mask<<<blocks((size_t)nb * 16384 * 32), 256, 0, s>>>(V(c->g0, 32), V(c->a0, 32), (size_t)nb * 16384, 32);
+  {
+    const int mtot = nb * 128 * 128, splits = (mtot + px - 1) / px, np = 32 * 10;
+    k_wgrad_in<<<splits, 320, 0, s>>>(x, V(c->g0, 32), c->part, nb, 128, 32, px);
+    k_sum_splits<<<blocks(np), 256, 0, s>>>(c->part, splits, np, c->part + (size_t)splits * np);
+    PTY_LAUNCH_CHECK("wgrad_in");
+    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)splits * np, 9, 32, c->g + L[0].woff, c->g + L[0].boff);
+  }
+  PTY_LAUNCH_CHECK("cnn_backward");
+}
+
+void refresh_bf16(pty_cnn* c) {
+  k_to_bf16<<<blocks(c->nparams), 256, 0, c->stream>>>(c->p, c->wb, c->nparams);
+  PTY_LAUNCH_CHECK("to_bf16");
+}
+
+double loss_grad(pty_cnn* c, const float* x, const float* t, int nb) {
+  const size_t n = (size_t)nb * 64 * 64 * 2;
+  forward(c, x, nb);
+  const unsigned nbk = blocks(n);
+  k_mse<<<nbk, 256, 0, c->stream>>>(c->y, t, n, c->gy, c->lpart);
+  k_sum_d<<<1, 1, 0, c->stream>>>(c->lpart, nbk, 1.0 / (double)n, c->lsum);
+  PTY_LAUNCH_CHECK("mse");
+  backward(c, x, nb);
+  double loss = 0.0;
+  PTY_HIP(hipMemcpyAsync(&loss, c->lsum, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  PTY_HIP(hipStreamSynchronize(c->stream));
+  return loss;
+}
+
+void check_batch(pty_cnn* c, int nb) {
+  if (nb < 1 || nb > c->max_batch) throw std::invalid_argument("batch must be in 1..max_batch");
+}
+
+}  // namespace
+
+namespace pty {
+
+float* cnn_input_buffer(pty_cnn* c) { return c->xin; }
+int cnn_max_batch(const pty_cnn* c) { return c->max_batch; }
+int cnn_device(const pty_cnn* c) { return c->device; }
+
+// Forward pass of nb inputs on stream s; returns the network's output buffer
+// (nb x 64 x 64 x 2 float32), valid until the next call on this network.
+const float* cnn_forward_batch(pty_cnn* c, const float* x, int nb, hipStream_t s) {
+  check_batch(c, nb);
+  hipStream_t keep = c->stream;
+  c->stream = s;
+  try {
+    forward(c, x, nb);
+  } catch (...) {
+    c->stream = keep;
+    throw;
+  }
+  c->stream = keep;
+  return c->y;
+}
+
+}  // namespace pty
+
+extern "C" {
+
+pty_status pty_cnn_create(int32_t device, void* stream, int32_t max_batch, uint64_t seed, pty_cnn** out) {
+  return cnn_guard(nullptr, [&] {
+    if (!out || max_batch < 1) throw std::invalid_argument("pty_cnn_create: bad argument");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= device || device < 0) {
+      (void)hipGetLastError();
+      throw DeviceError("pty_cnn_create: no HIP device " + std::to_string(device));
+    }
+    PTY_HIP(hipSetDevice(device));
+    std::unique_ptr<pty_cnn> c(new pty_cnn());
+    c->device = device;
+    c->max_batch = max_batch;
+    if (stream) {
+      c->stream = static_cast<hipStream_t>(stream);
+    } else {
+      PTY_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    size_t off = 0;
+    for (int i = 0; i < kLayers; ++i) {
+      Conv& l = c->L[i];
+      l.cin = kSpec[i][0];
+      l.cout = kSpec[i][1];
+      l.S = kSpec[i][2];
+      l.relu = kSpec[i][3] != 0;
+      l.woff = off;
+      off += (size_t)l.cout * 9 * l.cin;
+      l.boff = off;
+      off += l.cout;
+    }
+    c->nparams = off;
+    c->p = c->alloc<float>(off);
+    c->g = c->alloc<float>(off);
+    c->m1 = c->alloc<float>(off);
+    c->m2 = c->alloc<float>(off);
+    c->wb = c->alloc<bf16>(off);
+    c->wt = c->alloc<bf16>((size_t)384 * 9 * 256);
+    // He-normal initialisation (std sqrt(2 / (9 cin))), zero biases
+    std::vector<float> hp(off, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int i = 0; i < kLayers; ++i) {
+      const double sd = std::sqrt(2.0 / (9.0 * c->L[i].cin));
+      for (size_t k = 0; k < (size_t)c->L[i].cout * 9 * c->L[i].cin; ++k) hp[c->L[i].woff + k] = (float)(nd(rng) * sd);
+    }
+    PTY_HIP(hipMemcpy(c->p, hp.data(), off * sizeof(float), hipMemcpyHostToDevice));
+    PTY_HIP(hipMemset(c->m1, 0, off * sizeof(float)));
+    PTY_HIP(hipMemset(c->m2, 0, off * sizeof(float)));
+    const size_t B = max_batch;
+    auto act = [&](size_t px, int ch) { return c->alloc<bf16>(B * px * ch); };
+    c->a0 = act(16384, 32);
+    c->p0 = act(4096, 32);
+    c->cat8 = act(4096, 96);
+    c->p1 = act(1024, 32);
+    c->cat7 = act(1024, 192);
+    c->p2 = act(256, 64);
+    c->cat6 = act(256, 384);
+    c->p3 = act(64, 128);
+    c->a4 = act(64, 256);
+    c->a5 = act(64, 256);
+    c->a6 = act(256, 128);
+    c->a7 = act(1024, 64);
+    c->a8 = act(4096, 32);
+    c->g0 = act(16384, 32);
+    c->gp0 = act(4096, 32);
+    c->gcat8 = act(4096, 96);
+    c->gp1 = act(1024, 32);
+    c->gcat7 = act(1024, 192);
+    c->gp2 = act(256, 64);
+    c->gcat6 = act(256, 384);
+    c->gp3 = act(64, 128);
+    c->g4 = act(64, 256);
+    c->g5 = act(64, 256);
+    c->g6 = act(256, 128);
+    c->g7 = act(1024, 64);
+    c->g8 = act(4096, 32);
+    c->y = c->alloc<float>(B * 4096 * 2);
+    c->gy = c->alloc<float>(B * 4096 * 2);
+    c->xin = c->alloc<float>(B * 16384);
+    // split-K scratch: the largest (splits x weights) of any layer, plus unpack room
+    size_t need = 0;
+    for (int i = 0; i < kLayers; ++i) {
+      const size_t mtot = B * c->L[i].S * c->L[i].S;
+      const size_t splits = (mtot + 4095) / 4096;
+      need = std::max(need, splits * ((size_t)c->L[i].cout * 9 * c->L[i].cin + c->L[i].cout) * 2 + 4096);
+    }
+    c->part = c->alloc<float>(need);
+    c->part_n = need;
+    c->lpart = c->alloc<double>(blocks(B * 4096 * 2) + 16);
+    c->lsum = c->alloc<double>(2);
+    refresh_bf16(c.get());
+    PTY_HIP(hipStreamSynchronize(c->stream));
+    *out = c.release();
+  });
+}
+
+void pty_cnn_destroy(pty_cnn* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+pty_status pty_cnn_num_params(const pty_cnn* c, int64_t* n) {
+  return cnn_guard(const_cast<pty_cnn*>(c), [&] {
+    if (!c || !n) throw std::invalid_argument("pty_cnn_num_params: null argument");
+    *n = (int64_t)c->nparams;
+  });
+}
+
+pty_status pty_cnn_get_params(pty_cnn* c, float* out) {
+  return cnn_guard(c, [&] {
+    if (!c || !out) throw std::invalid_argument("pty_cnn_get_params: null argument");
+    PTY_HIP(hipSetDevice(c->device));
+    PTY_HIP(hipMemcpyAsync(out, c->p, c->nparams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+pty_status pty_cnn_set_params(pty_cnn* c, const float* in) {
+  return cnn_guard(c, [&] {
+    if (!c || !in) throw std::invalid_argument("pty_cnn_set_params: null argument");
+    PTY_HIP(hipSetDevice(c->device));
+    PTY_HIP(hipMemcpyAsync(c->p, in, c->nparams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    refresh_bf16(c);
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+pty_status pty_cnn_forward(pty_cnn* c, const float* x, int32_t batch, float* y) {
+  return cnn_guard(c, [&] {
+    if (!c || !x || !y) throw std::invalid_argument("pty_cnn_forward: null argument");
+    check_batch(c, batch);
+    PTY_HIP(hipSetDevice(c->device));
+    forward(c, x, batch);
+    PTY_HIP(hipMemcpyAsync(y, c->y, sizeof(float) * batch * 4096 * 2, hipMemcpyDeviceToDevice, c->stream));
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+pty_status pty_cnn_grad(pty_cnn* c, const float* x, const float* target, int32_t batch, float* grad, double* loss) {
+  return cnn_guard(c, [&] {
+    if (!c || !x || !target || !grad) throw std::invalid_argument("pty_cnn_grad: null argument");
+    check_batch(c, batch);
+    PTY_HIP(hipSetDevice(c->device));
+    const double l = loss_grad(c, x, target, batch);
+    PTY_HIP(hipMemcpy(grad, c->g, c->nparams * sizeof(float), hipMemcpyDeviceToHost));
+    if (loss) *loss = l;
+  });
+}
+
+pty_status pty_cnn_train_step(pty_cnn* c, const float* x, const float* target, int32_t batch, float lr, double* loss) {
+  return cnn_guard(c, [&] {
+    if (!c || !x || !target) throw std::invalid_argument("pty_cnn_train_step: null argument");
+    if (!(lr > 0.f) || !std::isfinite(lr)) throw std::invalid_argument("pty_cnn_train_step: lr must be > 0");
+    check_batch(c, batch);
+    PTY_HIP(hipSetDevice(c->device));
+    const double l = loss_grad(c, x, target, batch);
+    c->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)c->step), c2 = 1.f - std::pow(b2, (float)c->step);
+    k_adam<<<blocks(c->nparams), 256, 0, c->stream>>>(c->p, c->g, c->m1, c->m2, c->nparams, lr, b1, b2, 1e-8f, c1, c2);
+    PTY_LAUNCH_CHECK("adam");
+    refresh_bf16(c);
+    PTY_HIP(hipStreamSynchronize(c->stream));
+    if (loss) *loss = l;
+  });
+}
+
+pty_status pty_cnn_input(pty_cnn* c, const float* counts, size_t n, double photons, float* x) {
+  return cnn_guard(c, [&] {
+    if (!c || !counts || !x) throw std::invalid_argument("pty_cnn_input: null argument");
+    if (!(photons > 1.0)) throw std::invalid_argument("pty_cnn_input: photons must be > 1");
+    PTY_HIP(hipSetDevice(c->device));
+    k_cnn_input<<<blocks(n), 256, 0, c->stream>>>(counts, x, n, (float)(1.0 / std::log1p(photons)));
+    PTY_LAUNCH_CHECK("cnn_input");
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+const char* pty_cnn_last_error(const pty_cnn* c) { return c ? c->err.c_str() : g_cnn_err.c_str(); }
+
+}  // extern "C"

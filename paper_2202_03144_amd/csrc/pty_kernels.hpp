@@ -170,4 +170,30 @@ void launch_scale_f32(float* p, size_t n, float s, hipStream_t st);
 void launch_scale_c64(float2* p, size_t n, float s, hipStream_t st);
 void launch_pattern_totals(const float* x, double* totals, int n, int j, hipStream_t s);
 
+// Learned initialiser data path and evaluation helpers.
+void launch_fill_c64(float2* p, size_t n, float2 v, hipStream_t s);
+void launch_poisson(const float* lam, float* out, size_t n, uint64_t seed, hipStream_t s);
+void launch_input_from_amp(const float* amp, int n, int j0, int nb, float* x, float inv, hipStream_t s);
+void launch_targets(const float2* obj, int w, const PosInfo* pos, int j, int n, float* out, hipStream_t s);
+void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int wc, float2* phasor,
+                       hipStream_t s);
+void launch_seed_stitch(const float* patches, const int2* place, const float2* phasor, const int* bin_beg,
+                        const int* bin_idx, int bins_w, int bins_h, float2* obj, int h, int w, hipStream_t s);
+size_t nrmse_part_doubles();
+void launch_nrmse(const float2* o, const float2* t, const unsigned char* mask, size_t n, double* part, double* out,
+                  hipStream_t s);
+void launch_roi_mask(const float* den, const unsigned* den_max, float frac, size_t n, unsigned char* mask,
+                     hipStream_t s);
+
+}  // namespace pty
+
+// The network (defined with its kernels); the seeding entry point runs its
+// forward pass on the context's stream.
+struct pty_cnn;
+namespace pty {
+float* cnn_input_buffer(pty_cnn* c);
+int cnn_max_batch(const pty_cnn* c);
+int cnn_device(const pty_cnn* c);
+const float* cnn_forward_batch(pty_cnn* c, const float* x, int nb, hipStream_t s);
+
 }  // namespace pty

@@ -1,0 +1,295 @@
+// Kernels of the learned initialiser's data path and of the evaluation
+// helpers: Poisson sampling of training patterns, network inputs and targets,
+// the stitching of predicted patches into an object seed, and the invariant
+// NRMSE (Fienup 1997) on a region of interest.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "pty_common.hpp"
+#include "pty_kernels.hpp"
+
+namespace pty {
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// uniform in (0, 1) from 53 random bits of a counter
+__device__ __forceinline__ double unit_open(uint64_t key) {
+  return ((double)(splitmix64(key) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// Poisson(lambda) draws, one counter stream per element.  lambda < 64:
+// inversion of the cumulative distribution; otherwise the normal
+// approximation lambda + sqrt(lambda) z, rounded and clipped at zero (used for
+// training patterns, where the exact tail shape does not matter).
+__global__ void k_poisson(const float* __restrict__ lam, float* __restrict__ out, size_t n, uint64_t seed) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double l = (double)lam[i];
+  const uint64_t base = splitmix64(seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(i + 1)));
+  float r = 0.f;
+  if (l > 0.0 && l < 64.0) {
+    const double u = unit_open(base);
+    double p = exp(-l), f = p;
+    int k = 0;
+    while (u > f && k < 400) {
+      ++k;
+      p *= l / k;
+      f += p;
+    }
+    r = (float)k;
+  } else if (l >= 64.0) {
+    const double u1 = unit_open(base), u2 = unit_open(base + 1);
+    const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    r = (float)fmax(0.0, floor(l + sqrt(l) * z + 0.5));
+  }
+  out[i] = r;
+}
+
+// Network input of pattern j0 + b from the measured moduli (natural order):
+// x[b][y][x] = log1p(A^2 at the centred pixel (y, x)) * inv.
+__global__ void k_input_from_amp(const float* __restrict__ amp, int n, int j0, int nb, float* __restrict__ x,
+                                 float inv) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t nn = (size_t)n * n;
+  if (i >= (size_t)nb * nn) return;
+  const int b = (int)(i / nn), q = (int)(i % nn), y = q / n, xx = q % n;
+  const int h = n / 2;
+  const float a = amp[(size_t)(j0 + b) * nn + (size_t)((y + h) % n) * n + (xx + h) % n];
+  x[i] = log1pf(a * a) * inv;
+}
+
+// Training targets: amplitude and phase (relative to the mean phasor) of the
+// central n/2 x n/2 object patch of each window at an integer position.
+// One block (256 threads) per pattern.
+__global__ __launch_bounds__(256) void k_targets(const float2* __restrict__ obj, int w, const PosInfo* __restrict__ pos,
+                                                 int n, float* __restrict__ out) {
+  __shared__ double sh[2][4];
+  const int j = blockIdx.x, m = n / 2, q = n / 4;
+  const PosInfo p = pos[j];
+  double sr = 0.0, si = 0.0;
+  for (int e = threadIdx.x; e < m * m; e += 256) {
+    const float2 o = obj[(size_t)(p.iy + q + e / m) * w + p.ix + q + e % m];
+    sr += o.x;
+    si += o.y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_down(sr, off, 64);
+    si += __shfl_down(si, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = sr;
+    sh[1][threadIdx.x >> 6] = si;
+  }
+  __syncthreads();
+  const double mr = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+  const double mi = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  const double mn = sqrt(mr * mr + mi * mi);
+  const float cr = mn > 0 ? (float)(mr / mn) : 1.f, ci = mn > 0 ? (float)(mi / mn) : 0.f;
+  for (int e = threadIdx.x; e < m * m; e += 256) {
+    const float2 o = obj[(size_t)(p.iy + q + e / m) * w + p.ix + q + e % m];
+    // o * conj(mean phasor)
+    const float re = o.x * cr + o.y * ci, im = o.y * cr - o.x * ci;
+    out[((size_t)j * m * m + e) * 2] = sqrtf(o.x * o.x + o.y * o.y);
+    out[((size_t)j * m * m + e) * 2 + 1] = atan2f(im, re);
+  }
+}
+
+__device__ __forceinline__ float2 patch_value(const float* __restrict__ pt, size_t idx) {
+  const float a = pt[idx * 2], ph = pt[idx * 2 + 1];
+  float s, c;
+  sincosf(ph, &s, &c);
+  return make_float2(a * c, a * s);
+}
+
+// Sequential phase-offset chain over the patches in index order, on the
+// coarse grid of object pixels whose coordinates are multiples of 8 (8 x 8
+// samples per 64 x 64 patch, one per lane of a single wavefront).  For patch
+// j: z = sum over its samples of S * conj(c_j), e_j = z / |z| (1 if z = 0),
+// S += c_j e_j.  Writes e_j to phasor[j].
+__global__ __launch_bounds__(64) void k_seed_chain(const float* __restrict__ patches, const int2* __restrict__ place,
+                                                   int j_count, float2* S, int wc, float2* __restrict__ phasor) {
+  const int lane = threadIdx.x;
+  const int sy = lane >> 3, sx = lane & 7;
+  for (int j = 0; j < j_count; ++j) {
+    const int2 t = place[j];
+    const int gy = (t.x + 7) & ~7, gx = (t.y + 7) & ~7;
+    const int u = gy - t.x + 8 * sy, v = gx - t.y + 8 * sx;
+    const float2 c = patch_value(patches, (size_t)j * 4096 + u * 64 + v);
+    float2* sp = S + (size_t)(gy / 8 + sy) * wc + gx / 8 + sx;
+    const float2 s = *sp;
+    float zr = s.x * c.x + s.y * c.y, zi = s.y * c.x - s.x * c.y;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      zr += __shfl_xor(zr, off, 64);
+      zi += __shfl_xor(zi, off, 64);
+    }
+    const float zn = sqrtf(zr * zr + zi * zi);
+    const float er = zn > 0.f ? zr / zn : 1.f, ei = zn > 0.f ? zi / zn : 0.f;
+    *sp = make_float2(s.x + c.x * er - c.y * ei, s.y + c.x * ei + c.y * er);
+    if (lane == 0) phasor[j] = make_float2(er, ei);
+    // the next patch may read what this one wrote: let the store complete first
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+}
+
+// Stitch: O(p) = mean over the patches covering p of c_j(p - t_j) e_j;
+// 1 where no patch covers p.  Candidate patches come from 64 x 64 bins of the
+// placements (CSR `bin_beg`, `bin_idx`): a patch covering p has its corner in
+// p's bin or the bins above / to the left.
+__global__ void k_seed_stitch(const float* __restrict__ patches, const int2* __restrict__ place,
+                              const float2* __restrict__ phasor, const int* __restrict__ bin_beg,
+                              const int* __restrict__ bin_idx, int bins_w, int bins_h, float2* __restrict__ obj, int h,
+                              int w) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= (size_t)h * w) return;
+  const int y = (int)(i / w), x = (int)(i % w);
+  const int by = y >> 6, bx = x >> 6;
+  float ar = 0.f, ai = 0.f;
+  int cnt = 0;
+  for (int dy = -1; dy <= 0; ++dy) {
+    const int yy = by + dy;
+    if (yy < 0 || yy >= bins_h) continue;
+    for (int dx = -1; dx <= 0; ++dx) {
+      const int xx = bx + dx;
+      if (xx < 0 || xx >= bins_w) continue;
+      const int b = yy * bins_w + xx;
+      for (int e = bin_beg[b]; e < bin_beg[b + 1]; ++e) {
+        const int j = bin_idx[e];
+        const int2 t = place[j];
+        const int u = y - t.x, v = x - t.y;
+        if ((unsigned)u >= 64u || (unsigned)v >= 64u) continue;
+        const float2 c = patch_value(patches, (size_t)j * 4096 + u * 64 + v);
+        const float2 ph = phasor[j];
+        ar += c.x * ph.x - c.y * ph.y;
+        ai += c.x * ph.y + c.y * ph.x;
+        ++cnt;
+      }
+    }
+  }
+  obj[i] = cnt ? make_float2(ar / cnt, ai / cnt) : make_float2(1.f, 0.f);
+}
+
+// NRMSE partial sums over the mask: (sum |o|^2, Re sum conj(o) t, Im ..., sum |t|^2)
+constexpr int kNrmseBlocks = 512;
+__global__ __launch_bounds__(256) void k_nrmse_part(const float2* __restrict__ o, const float2* __restrict__ t,
+                                                    const unsigned char* __restrict__ mask, size_t n,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[4][4];
+  double a = 0, b = 0, c = 0, d = 0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)kNrmseBlocks * 256) {
+    if (!mask[i]) continue;
+    const float2 x = o[i], y = t[i];
+    a += (double)x.x * x.x + (double)x.y * x.y;
+    b += (double)x.x * y.x + (double)x.y * y.y;
+    c += (double)x.x * y.y - (double)x.y * y.x;
+    d += (double)y.x * y.x + (double)y.y * y.y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+    c += __shfl_down(c, off, 64);
+    d += __shfl_down(d, off, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wv] = a;
+    sh[1][wv] = b;
+    sh[2][wv] = c;
+    sh[3][wv] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int r = threadIdx.x;
+    part[blockIdx.x * 4 + r] = sh[r][0] + sh[r][1] + sh[r][2] + sh[r][3];
+  }
+}
+
+// ||c o - t||^2 at the optimal c is sum|t|^2 - |<o, t>|^2 / sum|o|^2
+__global__ void k_nrmse_final(const double* __restrict__ part, double* __restrict__ out) {
+  double s[4] = {0, 0, 0, 0};
+  for (int b = 0; b < kNrmseBlocks; ++b)
+    for (int r = 0; r < 4; ++r) s[r] += part[b * 4 + r];
+  const double num = s[0] > 0 ? s[3] - (s[1] * s[1] + s[2] * s[2]) / s[0] : s[3];
+  *out = s[3] > 0 ? sqrt(fmax(num, 0.0) / s[3]) : 0.0;
+}
+
+// mask[i] = den[i] >= frac * max(den)
+__global__ void k_roi_mask(const float* __restrict__ den, const unsigned* __restrict__ den_max, float frac, size_t n,
+                           unsigned char* __restrict__ mask) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  mask[i] = den[i] >= frac * __uint_as_float(*den_max) ? 1 : 0;
+}
+
+__global__ void k_fill_c64(float2* __restrict__ p, size_t n, float2 v) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned nblk(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+void launch_fill_c64(float2* p, size_t n, float2 v, hipStream_t s) {
+  if (n == 0) return;
+  k_fill_c64<<<nblk(n), 256, 0, s>>>(p, n, v);
+  PTY_LAUNCH_CHECK("fill_c64");
+}
+
+void launch_poisson(const float* lam, float* out, size_t n, uint64_t seed, hipStream_t s) {
+  if (n == 0) return;
+  k_poisson<<<nblk(n), 256, 0, s>>>(lam, out, n, seed);
+  PTY_LAUNCH_CHECK("poisson");
+}
+
+void launch_input_from_amp(const float* amp, int n, int j0, int nb, float* x, float inv, hipStream_t s) {
+  k_input_from_amp<<<nblk((size_t)nb * n * n), 256, 0, s>>>(amp, n, j0, nb, x, inv);
+  PTY_LAUNCH_CHECK("input_from_amp");
+}
+
+void launch_targets(const float2* obj, int w, const PosInfo* pos, int j, int n, float* out, hipStream_t s) {
+  if (j == 0) return;
+  k_targets<<<j, 256, 0, s>>>(obj, w, pos, n, out);
+  PTY_LAUNCH_CHECK("targets");
+}
+
+void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int wc, float2* phasor,
+                       hipStream_t s) {
+  k_seed_chain<<<1, 64, 0, s>>>(patches, place, j, S, wc, phasor);
+  PTY_LAUNCH_CHECK("seed_chain");
+}
+
+void launch_seed_stitch(const float* patches, const int2* place, const float2* phasor, const int* bin_beg,
+                        const int* bin_idx, int bins_w, int bins_h, float2* obj, int h, int w, hipStream_t s) {
+  k_seed_stitch<<<nblk((size_t)h * w), 256, 0, s>>>(patches, place, phasor, bin_beg, bin_idx, bins_w, bins_h, obj, h,
+                                                   w);
+  PTY_LAUNCH_CHECK("seed_stitch");
+}
+
+size_t nrmse_part_doubles() { return kNrmseBlocks * 4; }
+
+void launch_nrmse(const float2* o, const float2* t, const unsigned char* mask, size_t n, double* part, double* out,
+                  hipStream_t s) {
+  k_nrmse_part<<<kNrmseBlocks, 256, 0, s>>>(o, t, mask, n, part);
+  k_nrmse_final<<<1, 1, 0, s>>>(part, out);
+  PTY_LAUNCH_CHECK("nrmse");
+}
+
+void launch_roi_mask(const float* den, const unsigned* den_max, float frac, size_t n, unsigned char* mask,
+                     hipStream_t s) {
+  k_roi_mask<<<nblk(n), 256, 0, s>>>(den, den_max, frac, n, mask);
+  PTY_LAUNCH_CHECK("roi_mask");
+}
+
+}  // namespace pty

@@ -193,6 +193,65 @@ class Plan:
             self._dev(g_pos, np.float32, (self.n_pos, 2), "g_pos"), C.byref(loss)))
         return loss.value
 
+    # -- evaluation and the learned seed --------------------------------------
+    def model_error(self) -> float:
+        """Amplitude error E of the current object and probe (state unchanged)."""
+        v = C.c_double()
+        self._check(self._lib.pty_model_error(self._live(), C.byref(v)))
+        return v.value
+
+    def set_truth(self, truth, roi_frac: float = 0.3) -> None:
+        """Record the NRMSE against `truth` after every iteration (None: stop)."""
+        if truth is None:
+            self._check(self._lib.pty_set_truth(self._live(), None, 0, 0.0))
+            return
+        ptr, dev, keep = _ptr(truth, np.complex64, self.obj_shape)
+        self._check(self._lib.pty_set_truth(self._live(), ptr, dev, float(roi_frac)))
+
+    def nrmse(self) -> float:
+        v = C.c_double()
+        self._check(self._lib.pty_nrmse(self._live(), C.byref(v)))
+        return v.value
+
+    def nrmse_history(self) -> np.ndarray:
+        cap = 1 << 16
+        buf = np.empty(cap, dtype=np.float64)
+        n = C.c_int32()
+        self._check(self._lib.pty_get_nrmse(self._live(), buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
+        return buf[: n.value].copy()
+
+    def stitch(self, patches, out=None):
+        """Stitch (J, 64, 64, 2) amplitude/phase patches (CUDA float32) into an
+        object; into `out` (CUDA complex64) if given, else into the plan's object."""
+        pp = self._dev(patches, np.float32, (self.n_pos, 64, 64, 2), "patches")
+        po = self._dev(out, np.complex64, self.obj_shape, "out")
+        self._check(self._lib.pty_stitch(self._live(), pp, po))
+        return out
+
+    def seed_object(self, net, photons: float, batch: int = 4096, fallback: bool = True) -> dict:
+        """Learned seed of the object from the loaded patterns (see pty_seed_object)."""
+        used = C.c_int32()
+        es = C.c_double(float("nan"))
+        ef = C.c_double(float("nan"))
+        self._check(self._lib.pty_seed_object(self._live(), net._live(), float(photons), int(batch),
+                                              1 if fallback else 0, C.byref(used), C.byref(es), C.byref(ef)))
+        return {"used_fallback": bool(used.value), "e_seed": es.value, "e_flat": ef.value}
+
+    def training_targets(self, out):
+        """Network targets (J, 64, 64, 2) of every (integer) window, into a CUDA tensor."""
+        self._check(self._lib.pty_training_targets(
+            self._live(), self._dev(out, np.float32, (self.n_pos, self.n // 2, self.n // 2, 2), "out")))
+        return out
+
+    def poisson(self, lam, out, seed: int) -> None:
+        """out ~ Poisson(lam) elementwise (CUDA float32 tensors of equal shape)."""
+        if tuple(lam.shape) != tuple(out.shape):
+            raise ValueError("lam and out shapes differ")
+        n = int(np.prod(lam.shape))
+        self._check(self._lib.pty_poisson(self._live(), self._dev(lam, np.float32, lam.shape, "lam"),
+                                          self._dev(out, np.float32, out.shape, "out"), n,
+                                          int(seed) & ((1 << 64) - 1)))
+
     def set_timing(self, enable: bool = True) -> None:
         """Clear the per-family kernel times and enable (or disable) event timing."""
         self._check(self._lib.pty_set_timing(self._live(), 1 if enable else 0))

@@ -1,0 +1,290 @@
+"""Learned initialiser on the GPU vs the FP64 references (oracle.unet,
+oracle.seed, oracle.ptycho), which are pinned on the CPU.
+
+The network computes with bf16 weights and activations and float32
+accumulation; the reference is evaluated in FP64 with the same bf16-rounded
+weights, so the tolerance covers only the rounding of activations and
+gradients to bf16 (8 significant bits): relative L2 error 3e-2 for outputs
+and 6e-2 per layer for gradients."""
+import numpy as np
+import pytest
+
+import oracle
+import ptysynth
+from oracle import seed as oseed
+from oracle import unet
+from _cases import c64
+
+pytestmark = pytest.mark.gpu
+
+TOL_Y = 3e-2
+TOL_G = 6e-2
+
+
+def _bf16(a):
+    """float32 -> nearest bf16 (ties to even), returned as float32."""
+    a = np.ascontiguousarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def _as_kernel_sees(flat32):
+    """FP64 parameters as the kernels use them: bf16 weights, float32 biases."""
+    ps = unet.unflatten(flat32.astype(np.float64))
+    for i in range(0, len(ps), 2):
+        ps[i] = _bf16(ps[i].astype(np.float32)).astype(np.float64)
+    return unet.flatten(ps)
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _params(seed=11):
+    flat = unet.init_params(seed).astype(np.float32)
+    # non-zero biases so that they are exercised
+    rng = np.random.default_rng(seed)
+    ps = unet.unflatten(flat.astype(np.float64))
+    for i in range(1, len(ps), 2):
+        ps[i] = 0.05 * rng.standard_normal(ps[i].shape)
+    return unet.flatten(ps).astype(np.float32)
+
+
+def _inputs(b, seed=12):
+    """Network inputs of simulated patterns (config-4 proportions) at integer positions."""
+    wl = ptysynth.workload(4)
+    obj = ptysynth.make_object(40 + seed, 128 + 16 * b, 144, wl.sigma_o)
+    probe = wl.probe()
+    pos = np.array([[16.0 * i, 8.0] for i in range(b)])
+    cnt, _ = oracle.simulate(obj, probe, pos, wl.photons)
+    return oseed.network_input(cnt, wl.photons), obj, pos
+
+
+def _net(b, flat):
+    from paper_2202_03144_amd.cnn import Net
+    net = Net(b, seed=0)
+    net.set_params(flat)
+    return net
+
+
+def test_forward_matches_oracle():
+    import torch
+    b = 3
+    flat = _params()
+    x, _, _ = _inputs(b)
+    net = _net(b, flat)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    y = torch.empty((b, 64, 64, 2), dtype=torch.float32, device="cuda")
+    net.forward(xt, y)
+    ref, _ = unet.forward(_as_kernel_sees(flat), x.astype(np.float32).astype(np.float64)[..., None])
+    err = _rel(y.cpu().numpy(), ref)
+    print("forward rel err", err)
+    assert err <= TOL_Y
+    # params round trip exactly (float32 masters)
+    assert np.array_equal(net.params(), flat)
+    net.close()
+
+
+def test_gradient_matches_oracle():
+    import torch
+    b = 2
+    flat = _params(13)
+    x, _, _ = _inputs(b, 14)
+    rng = np.random.default_rng(15)
+    t = (0.3 * rng.standard_normal((b, 64, 64, 2))).astype(np.float32)
+    net = _net(b, flat)
+    loss, g = net.grad(torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(t).cuda())
+    rl, rg = unet.loss_and_grad(_as_kernel_sees(flat), x.astype(np.float32).astype(np.float64)[..., None],
+                                t.astype(np.float64))
+    print("loss", loss, rl)
+    assert abs(loss - rl) <= TOL_Y * rl
+    off = 0
+    for li, (cin, cout, _, _) in enumerate(unet.LAYERS):
+        nw = 9 * cin * cout
+        for name, sl in (("w", slice(off, off + nw)), ("b", slice(off + nw, off + nw + cout))):
+            e = _rel(g[sl], rg[sl])
+            print(f"layer {li} {name} rel err {e:.3e}")
+            assert e <= TOL_G, (li, name, e)
+        off += nw + cout
+    assert np.array_equal(net.params(), flat)   # grad leaves the parameters alone
+    net.close()
+
+
+def test_train_steps_reduce_loss():
+    import torch
+    b = 8
+    x, obj, pos = _inputs(b, 16)
+    from paper_2202_03144_amd import Plan
+    with Plan(128, 1, b, obj.shape) as pl:
+        pl.load_positions(pos)
+        pl.set_object(c64(obj))
+        tg = torch.empty((b, 64, 64, 2), dtype=torch.float32, device="cuda")
+        pl.training_targets(tg)
+    np.testing.assert_allclose(tg.cpu().numpy(), oseed.targets(obj.astype(np.complex64).astype(np.complex128), pos),
+                               rtol=0, atol=2e-5)
+    from paper_2202_03144_amd.cnn import Net
+    net = Net(b, seed=3)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    losses = [net.train_step(xt, tg, 1e-3) for _ in range(30)]
+    print("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    net.close()
+
+
+def test_bad_arguments():
+    import torch
+    from paper_2202_03144_amd import PtyError
+    from paper_2202_03144_amd.cnn import Net
+    net = Net(2, seed=0)
+    x = torch.zeros((3, 128, 128), dtype=torch.float32, device="cuda")
+    y = torch.zeros((3, 64, 64, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(PtyError, match="INVALID"):
+        net.forward(x, y)            # batch above max_batch
+    with pytest.raises(PtyError, match="INVALID"):
+        net.train_step(x[:2], y[:2], -1.0)
+    with pytest.raises(ValueError):
+        net.set_params(np.zeros(5, np.float32))
+    net.close()
+
+
+def test_poisson_statistics():
+    import torch
+    from paper_2202_03144_amd import Plan
+    lam_values = [0.3, 4.0, 40.0, 200.0, 5e4]
+    n = 200_000
+    lam = torch.tensor(np.repeat(lam_values, n).astype(np.float32), device="cuda")
+    out = torch.empty_like(lam)
+    with Plan(32, 1, 1, (33, 33)) as pl:
+        pl.poisson(lam, out, seed=99)
+        a = out.cpu().numpy().reshape(len(lam_values), n)
+        out2 = torch.empty_like(lam)
+        pl.poisson(lam, out2, seed=99)
+        assert torch.equal(out, out2)              # counter-based: same seed, same draws
+    assert np.all(a == np.round(a)) and np.all(a >= 0)
+    for i, l in enumerate(lam_values):
+        m, v = a[i].mean(), a[i].var()
+        se = np.sqrt(l / n)
+        assert abs(m - l) <= 5 * se + 0.5 / n, (l, m)
+        assert abs(v / l - 1) <= 0.03, (l, v)
+
+
+def _spiral_patches(j=60, h=300, w=280):
+    obj = ptysynth.make_object(77, h, w, 3.0)
+    pos = ptysynth.spiral_positions(j, 6.0, 140.0, 128, ptysynth.stream(77, 3))
+    rng = np.random.default_rng(8)
+    t = oseed.placements(pos)
+    p = np.empty((j, 64, 64, 2), np.float32)
+    for i, (ty, tx) in enumerate(t):
+        o = obj[ty:ty + 64, tx:tx + 64] * np.exp(1j * rng.uniform(-np.pi, np.pi))
+        o = o * (1 + 0.05 * rng.standard_normal(o.shape))        # inconsistent patches
+        p[i, ..., 0] = np.abs(o)
+        p[i, ..., 1] = np.angle(o)
+    return p, pos, obj
+
+
+def test_stitch_matches_oracle():
+    import torch
+    from paper_2202_03144_amd import Plan
+    p, pos, obj = _spiral_patches()
+    h, w = obj.shape
+    with Plan(128, 1, len(pos), (h, w)) as pl:
+        pl.load_positions(pos)
+        out = torch.empty((h, w), dtype=torch.complex64, device="cuda")
+        pl.stitch(torch.from_numpy(p).cuda(), out)
+        got = out.cpu().numpy()
+    ref, _ = oseed.stitch(p.astype(np.float64), pos, h, w)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print("stitch rel err", err)
+    assert err <= 1e-5
+    # uncovered pixels are exactly 1
+    assert np.all(got[ref == 1.0] == 1.0)
+
+
+def _seed_case(j=10):
+    wl = ptysynth.workload(4)
+    h = w = 300
+    obj = ptysynth.make_object(81, h, w, wl.sigma_o)
+    pos = ptysynth.spiral_positions(j, wl.pitch, 150.0, 128, ptysynth.stream(81, 3))
+    cnt, probe = oracle.simulate(obj, wl.probe(), pos, wl.photons)
+    cnt = ptysynth.poisson_counts(cnt, ptysynth.stream(81, 4))
+    return obj, probe, pos, cnt, wl.photons
+
+
+def test_seed_object_matches_oracle():
+    from paper_2202_03144_amd import Plan
+    from paper_2202_03144_amd.cnn import Net
+    obj, probe, pos, cnt, photons = _seed_case()
+    flat = _params(21)
+    j = len(pos)
+    with Plan(128, 1, j, obj.shape) as pl, Net(4, seed=0) as net:
+        net.set_params(flat)
+        pl.load_patterns(cnt)
+        pl.load_positions(pos)
+        r = pl.seed_object(net, photons, batch=4, fallback=False)   # ragged last batch (10 = 4 + 4 + 2)
+        assert r["used_fallback"] is False
+        got = pl.object()
+    # the kernels read the counts through A = sqrt(max(d, 0)) in float32
+    a32 = np.sqrt(np.maximum(cnt, 0).astype(np.float32))
+    x = np.log1p(a32.astype(np.float64) ** 2) / np.log1p(photons)
+    y, _ = unet.forward(_as_kernel_sees(flat), x[..., None])
+    ref, _ = oseed.stitch(y, pos, *obj.shape)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print("seed rel err", err)
+    assert err <= TOL_Y
+
+
+def test_seed_fallback_and_model_error():
+    from paper_2202_03144_amd import Plan
+    from paper_2202_03144_amd.cnn import Net
+    obj, probe, pos, cnt, photons = _seed_case(8)
+    j = len(pos)
+    with Plan(128, 1, j, obj.shape) as pl, Net(8, seed=5) as net:
+        pl.load_patterns(cnt)
+        pl.load_positions(pos)
+        pl.set_probe(c64(probe))
+        pl.seed_object(net, photons, batch=8, fallback=False)
+        seed_obj = pl.object()
+        e_seed_direct = pl.model_error()
+        r = pl.seed_object(net, photons, batch=8, fallback=True)
+        got = pl.object()
+    amp = oracle.amplitude(cnt.astype(np.float64))
+    pr = c64(probe).astype(np.complex128)
+    e_flat_ref = oracle.model_error(np.ones(obj.shape), pr, amp, pos)
+    e_seed_ref = oracle.model_error(seed_obj.astype(np.complex128), pr, amp, pos)
+    assert abs(r["e_flat"] - e_flat_ref) <= 1e-5 * e_flat_ref
+    assert abs(r["e_seed"] - e_seed_ref) <= 1e-5 * e_seed_ref
+    assert abs(e_seed_direct - e_seed_ref) <= 1e-5 * e_seed_ref
+    if r["used_fallback"]:
+        assert r["e_seed"] > r["e_flat"] and np.all(got == 1.0)
+    else:
+        assert r["e_seed"] <= r["e_flat"] and np.array_equal(got, seed_obj)
+
+
+def test_nrmse_and_history():
+    from paper_2202_03144_amd import Plan
+    obj, probe, pos, cnt, photons = _seed_case(12)
+    j = len(pos)
+    pr = c64(probe)
+    with Plan(128, 1, j, obj.shape) as pl:
+        pl.load_patterns(cnt)
+        pl.load_positions(pos)
+        pl.set_probe(pr)
+        o0 = c64(np.ones(obj.shape) * (1 + 0.1j))
+        pl.set_object(o0)
+        pl.set_truth(c64(obj), 0.3)
+        v0 = pl.nrmse()
+        pl.iterate("lsqml", 3, probe_update_start=1 << 30, lsqml_batch=6)
+        hist = pl.nrmse_history()
+        v3 = pl.nrmse()
+        last = pl.object()
+        pl.set_truth(c64(obj), 0.0)          # every pixel
+        v_all = pl.nrmse()
+    mask = oracle.roi_mask(pr.astype(np.complex128), pos, *obj.shape)
+    truth = c64(obj).astype(np.complex128)
+    assert abs(v0 - oracle.nrmse(o0.astype(np.complex128), truth, mask)) <= 1e-5 * v0
+    assert len(hist) == 3 and hist[-1] == v3
+    assert abs(v3 - oracle.nrmse(last.astype(np.complex128), truth, mask)) <= 1e-5 * v3
+    assert abs(v_all - oracle.nrmse(last.astype(np.complex128), truth, np.ones(obj.shape, bool))) <= 1e-5 * v_all
