@@ -151,6 +151,98 @@ def cpu_baseline(n_sample: int):
     }
 
 
+def learned_leg(args, torch) -> dict:
+    """Time to NRMSE <= 1e-2 with the learned seed vs the flat start (LSQML,
+    fixed true probe) on the 128 x 128, 4,096-position spiral workload."""
+    import ptysynth
+    from paper_2202_03144_amd import Plan
+    from paper_2202_03144_amd.cnn import Net
+    from paper_2202_03144_amd.learned import time_to_nrmse, train
+
+    wl = ptysynth.workload(4)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    # held-out evaluation data: counts from the library's forward model and Poisson sampler
+    obj_true = wl.obj().astype(np.complex64)
+    pos = wl.positions()
+    lam = torch.empty((wl.j, wl.n, wl.n), dtype=torch.float32, device="cuda")
+    counts = torch.empty_like(lam)
+    with Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream) as sim:
+        sim.load_positions(pos)
+        sim.set_object(obj_true)
+        sim.set_probe(wl.probe().astype(np.complex64))
+        sim.simulate(wl.photons, out=lam)
+        sim.poisson(lam, counts, seed=4)
+        probe = sim.probe()
+    del lam
+    # training objects: same generator and statistics, other seeds
+    side = 1024
+    objs = [torch.from_numpy(ptysynth.make_object(1000 + i, side, side, wl.sigma_o).astype(np.complex64)).cuda()
+            for i in range(args.train_objects)]
+    net = Net(args.infer_batch, seed=7, stream=stream)
+    log(f"training: {args.train_steps} steps x {args.train_batch} patterns on {len(objs)} objects")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = train(net, objs, wl.probe().astype(np.complex64), wl.photons, args.train_steps, args.train_batch,
+                   lr=1e-3, lr_final=1e-4, seed=11, log_every=max(1, args.train_steps // 10), log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del objs
+
+    def arm(learned: bool, max_iter: int):
+        pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
+        pl.load_patterns(counts)
+        pl.load_positions(pos)
+        pl.set_probe(probe)
+        pl.set_object(np.ones((wl.h, wl.w), np.complex64))
+        pl.set_truth(obj_true, 0.3)
+        seed_ms, info, nrmse0 = 0.0, {}, pl.nrmse()
+        if learned:
+            pl.seed_object(net, wl.photons, batch=args.infer_batch)   # warm: allocations
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = pl.seed_object(net, wl.photons, batch=args.infer_batch)
+            torch.cuda.synchronize()
+            seed_ms = (time.perf_counter() - t) * 1e3
+            nrmse0 = pl.nrmse()
+        hist, ms, hit = time_to_nrmse(pl, args.nrmse_target, max_iter, stream,
+                                      probe_update_start=1 << 30)
+        pl.close()
+        res = {"nrmse_start": round(nrmse0, 5), "seed_ms": round(seed_ms, 2),
+               "iterations_to_target": None if hit is None else hit + 1,
+               "ms_to_target": None if hit is None else round(seed_ms + float(ms[hit]), 2),
+               "lsqml_ms_per_iter": round(float(ms[-1]) / len(ms), 3),
+               "nrmse_last": round(float(hist[-1]), 5), "iterations_run": len(ms)}
+        if learned:
+            res.update({"used_fallback": info["used_fallback"], "e_seed": round(info["e_seed"], 5),
+                        "e_flat": round(info["e_flat"], 5)})
+        return res
+
+    log("learned arm")
+    learned = arm(True, args.learned_iters)
+    log(f"learned: {learned}")
+    log("plain arm")
+    plain = arm(False, args.plain_iters)
+    log(f"plain: {plain}")
+    net.close()
+    speed = None
+    if learned["ms_to_target"] and plain["ms_to_target"]:
+        speed = round(plain["ms_to_target"] / learned["ms_to_target"], 3)
+    return {
+        "metric": f"time to NRMSE {args.nrmse_target:g} (ms)",
+        "value": learned["ms_to_target"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+        "vs_baseline": None, "dtype": "bf16 network, f32 reconstruction", "data": "synthetic",
+        "config": {"workload": "128x128 probe (D 48), 1 mode fixed, 4,096-point Fermat spiral (c 8), "
+                               "1200x1200 object, Poisson 1e8 photons; LSQML groups of 512",
+                   "n": wl.n, "positions": wl.j, "object": [wl.h, wl.w]},
+        "learned": learned, "plain": plain, "plain_over_learned": speed,
+        "training": {"patterns": args.train_steps * args.train_batch, "steps": args.train_steps,
+                     "batch": args.train_batch, "seconds": round(train_s, 2),
+                     "loss_first": round(float(np.mean(losses[:10])), 5),
+                     "loss_last": round(float(np.mean(losses[-10:])), 5)},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +250,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=1200, help="positions in the oracle sample (0 = skip)")
     ap.add_argument("--no-timing-pass", action="store_true", help="skip the event-timed kernel pass")
+    ap.add_argument("--learned", action="store_true",
+                    help="instead: train the learned initialiser and time NRMSE 1e-2, learned vs flat start")
+    ap.add_argument("--train-steps", type=int, default=800)
+    ap.add_argument("--train-batch", type=int, default=256)
+    ap.add_argument("--train-objects", type=int, default=8)
+    ap.add_argument("--infer-batch", type=int, default=4096)
+    ap.add_argument("--learned-iters", type=int, default=20)
+    ap.add_argument("--plain-iters", type=int, default=200)
+    ap.add_argument("--nrmse-target", type=float, default=1e-2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing was run.",
@@ -170,6 +271,9 @@ def main() -> int:
         return 1
     from paper_2202_03144_amd import Plan
 
+    if args.learned:
+        print(json.dumps(learned_leg(args, torch)), flush=True)
+        return 0
     log("building config-2 inputs")
     wl, obj_true, probe, pos, counts = make_inputs(torch)
     # a plain device copy of known size (J x N x N float32 read + written); its

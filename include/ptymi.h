@@ -83,7 +83,14 @@ typedef struct {
  *   order_seed           ePIE visiting order: 0 = identity, otherwise a
  *                        Fisher-Yates shuffle driven by SplitMix64 seeded with
  *                        order_seed + t in iteration t.
- *   chunk                patterns per Fourier-pass chunk (0 = automatic). */
+ *   chunk                patterns per Fourier-pass chunk (0 = automatic:
+ *                        the value pty_autotune chose, else a 64 MB budget).
+ *   flags                PTY_ITER_GRAPH: DM and LSQML iterations are captured
+ *                        once per distinct setting into a HIP graph and
+ *                        replayed (fewer launches; same kernels, same results
+ *                        as eager iterations); ignored for ePIE.  Kernel
+ *                        timing is suspended while graphs run. */
+#define PTY_ITER_GRAPH 1u
 typedef struct {
   float alpha, beta;
   int32_t probe_update_start;
@@ -92,7 +99,7 @@ typedef struct {
   float beta_obj, beta_probe;
   uint64_t order_seed;
   int32_t chunk;
-  uint32_t flags; /* reserved, must be 0 */
+  uint32_t flags; /* 0 or PTY_ITER_GRAPH */
 } pty_iter_params;
 
 /* Fills *p with the defaults listed above. */
@@ -298,6 +305,37 @@ pty_status pty_stitch(pty_ctx* ctx, const float* patches, void* out);
  * errors.  The network must live on the context's device.  Synchronises. */
 pty_status pty_seed_object(pty_ctx* ctx, pty_cnn* net, double photons, int32_t batch, int32_t fallback,
                            int32_t* used_fallback, double* e_seed, double* e_flat);
+
+/* ------------------------------------------------------------------------
+ * Batches of datasets and tuning (not in the paper; many reconstructions of
+ * uneven size on one GPU).
+ * ---------------------------------------------------------------------- */
+typedef struct pty_batch pty_batch;
+
+/* A batch over n existing contexts (not owned; they must outlive the batch
+ * and should each have their own stream, so that their work overlaps on the
+ * device).  *out is set only on success. */
+pty_status pty_batch_create(pty_ctx* const* ctxs, int32_t n, pty_batch** out);
+/* Enqueues n_iter iterations of `algo` on every context, iteration-major
+ * (iteration t of every context before iteration t + 1 of any), each on its
+ * context's stream; prm applies to all (PTY_ITER_GRAPH included).  On failure
+ * returns the first context's status; the message names the context index. */
+pty_status pty_batch_iterate(pty_batch* b, pty_algo algo, int32_t n_iter, const pty_iter_params* prm);
+/* Waits for every context of the batch. */
+pty_status pty_batch_sync(pty_batch* b);
+void pty_batch_destroy(pty_batch* b);                  /* NULL-safe */
+const char* pty_batch_last_error(const pty_batch* b); /* never NULL */
+
+/* Chooses the Fourier-pass chunk (patterns per launch) for this context,
+ * algorithm and parameters by timing one iteration per candidate (8 to 256
+ * patterns) after a warm-up iteration, then restores the object, probe and
+ * iteration counter (DM restarts its exit waves from them).  With a non-NULL
+ * cache_path the choice is looked up in, and added to, that JSON file, keyed
+ * by device architecture, N, K, J and algorithm.  *chunk (may be NULL)
+ * receives the choice; later iterations with chunk = 0 use it.
+ * Synchronises. */
+pty_status pty_autotune(pty_ctx* ctx, pty_algo algo, const pty_iter_params* prm, const char* cache_path,
+                        int32_t* chunk);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ at any time, release); :func:`reconstruct` is the whole mode; the
 ``epieinit / epiestep / ...`` functions mirror the paper's Python API.
 """
 from ._lib import DM, EPIE, LSQML, PtyError  # noqa: F401
-from .plan import Plan, reconstruct  # noqa: F401
+from .plan import Batch, Plan, reconstruct  # noqa: F401
 from .compat import (  # noqa: F401
     dminit, dmpost, dmresobj, dmresprobe, dmstep,
     epieinit, epiepost, epieresobj, epieresprobe, epiestep,
@@ -16,4 +16,4 @@ from .compat import (  # noqa: F401
     epie, dm, lsqml,
 )
 
-__all__ = ["Plan", "reconstruct", "PtyError", "EPIE", "DM", "LSQML"]
+__all__ = ["Plan", "Batch", "reconstruct", "PtyError", "EPIE", "DM", "LSQML"]

@@ -97,7 +97,15 @@ SIGNATURES = {
     "pty_stitch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pty_seed_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pty_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "pty_batch_iterate": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(IterParams)]),
+    "pty_batch_sync": (C.c_int, [C.c_void_p]),
+    "pty_batch_destroy": (None, [C.c_void_p]),
+    "pty_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "pty_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(IterParams), C.c_char_p, C.POINTER(C.c_int32)]),
 }
+
+ITER_GRAPH = 1
 
 TIMING_FAMILIES = ["rows_fwd", "cols", "rows_inv", "obj_gather", "probe_acc", "probe_finish_apply",
                    "lsq_steps", "epie_update", "other"]

@@ -10,7 +10,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -100,6 +103,26 @@ struct pty_ctx {
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
 
+  // device-side iteration counter (error / NRMSE history slot of the running
+  // iteration), so that one captured iteration can be replayed
+  int* iter_dev = nullptr;
+  uint64_t gen = 0;                // bumped by every device (de)allocation
+  // captured iterations: replayed while the key (algorithm, parameters, probe
+  // update on/off, buffers, state flags) matches
+  struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int algo = -1;
+    bool pon = false, dm_valid = false, den_valid = false;
+    bool dm_valid_after = false, den_valid_after = false;
+    pty_iter_params p{};
+    uint64_t gen = 0;
+    const float2* probe = nullptr;
+    bool have_truth = false;
+  };
+  std::vector<GraphEntry> graphs;
+  int tuned_chunk = 0;             // from pty_autotune; 0 = the default rule
+
   // evaluation against a known object: invariant NRMSE on a region of interest
   float2* truth = nullptr;
   unsigned char* roi = nullptr;
@@ -167,6 +190,7 @@ struct pty_ctx {
     }
     allocs.emplace_back(p, bytes);
     mem += bytes;
+    ++gen;
     return p;
   }
   void dfree(void* p) {
@@ -176,6 +200,7 @@ struct pty_ctx {
         mem -= allocs[i].second;
         allocs.erase(allocs.begin() + i);
         (void)hipFree(p);
+        ++gen;
         return;
       }
     }
@@ -197,7 +222,16 @@ struct pty_ctx {
     if (!buf) buf = alloc<T>(n);
   }
 
+  void drop_graphs() {
+    for (auto& g : graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
+  }
+
   ~pty_ctx() {
+    drop_graphs();
     for (auto& p : pending) {
       ev_pool.push_back(p.a);
       ev_pool.push_back(p.b);
@@ -343,6 +377,7 @@ void ensure_lsq_groups(pty_ctx* c, int batch) {
 
 int chunk_patterns(const pty_ctx* c, const pty_iter_params& p) {
   if (p.chunk > 0) return p.chunk;
+  if (c->tuned_chunk > 0) return c->tuned_chunk;
   const size_t per = size_t(c->K) * c->N * c->N * sizeof(float2);
   const size_t budget = size_t(64) << 20;  // stays inside the 256 MB Infinity Cache
   return (int)std::max<size_t>(1, budget / per);
@@ -366,6 +401,10 @@ void ensure_common(pty_ctx* c, int chunk, size_t slots) {
 }
 
 void ensure_err_slot(pty_ctx* c, int n_iter) {
+  if (!c->iter_dev) {
+    c->iter_dev = c->alloc<int>(1);
+    launch_set_i32(c->iter_dev, c->iter, c->stream);
+  }
   if (c->err_dev && c->iter + n_iter <= c->err_cap) return;
   int cap = std::max(256, c->err_cap);
   while (cap < c->iter + n_iter) cap *= 2;
@@ -384,10 +423,18 @@ void ensure_err_slot(pty_ctx* c, int n_iter) {
 }
 
 // Closes iteration t: records the NRMSE against the truth, if one is set.
+// Records E of iteration t (and the NRMSE against the truth, if one is set) in
+// the device histories at the device counter's slot, advances that counter,
+// and closes the iteration.
 void end_iteration(pty_ctx* c, int t) {
+  (void)t;
+  timed(c, kOther, [&] {
+    launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev, c->stream, c->iter_dev, !c->have_truth);
+  });
   if (c->have_truth)
     timed(c, kOther, [&] {
-      launch_nrmse(c->obj, c->truth, c->roi, size_t(c->H) * c->W, c->nrmse_part, c->nrmse_dev + t, c->stream);
+      launch_nrmse(c->obj, c->truth, c->roi, size_t(c->H) * c->W, c->nrmse_part, c->nrmse_dev, c->stream,
+                   c->iter_dev, true);
     });
   c->iter++;
 }
@@ -576,7 +623,6 @@ void run_dm(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       c->den_valid = false;
     }
     fourier_pass(c, g, 0, c->J, chunk, RowIn::DmReflect, ColOp::Project, RowOut::DmUpdate);
-    timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
     end_iteration(c, t);
   }
 }
@@ -650,7 +696,6 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       timed(c, kObjGather, [&] { launch_obj_gather(u, ObjOp::LsqUpdate); });
       if (pon) probe_apply(c, PrbApply::LsqUpdate, c->num_p2, g_prb, p.beta_probe);
     }
-    timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
     end_iteration(c, t);
   }
   c->den_valid = false;  // den holds the last group's density only
@@ -713,7 +758,6 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       timed(c, kEpie, [&] { launch_epie_update(e); });
       std::swap(c->probe, c->probe_alt);
     }
-    timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev + t, c->stream); });
     end_iteration(c, t);
   }
   c->den_valid = false;
@@ -841,6 +885,198 @@ void stitch(pty_ctx* c, const float* patches, float2* dst) {
   c->dfree(d_idx);
   c->dfree(d_S);
   c->dfree(d_ph);
+}
+
+void run_algo(pty_ctx* c, int algo, int n_iter, const pty_iter_params& p) {
+  if (algo == PTY_DM)
+    run_dm(c, n_iter, p);
+  else if (algo == PTY_LSQML)
+    run_lsqml(c, n_iter, p);
+  else
+    run_epie(c, n_iter, p);
+}
+
+bool same_params(const pty_iter_params& a, const pty_iter_params& b) {
+  return a.alpha == b.alpha && a.beta == b.beta && a.probe_update_start == b.probe_update_start &&
+         a.lsqml_batch == b.lsqml_batch && a.gamma_obj == b.gamma_obj && a.gamma_probe == b.gamma_probe &&
+         a.beta_obj == b.beta_obj && a.beta_probe == b.beta_probe && a.order_seed == b.order_seed &&
+         a.chunk == b.chunk && a.flags == b.flags;
+}
+
+// Iterations as replays of captured single iterations (DM and LSQML).  Each
+// distinct key (algorithm, parameters, probe update on/off, buffer
+// generation, probe buffer, truth on/off, state flags before the iteration)
+// is captured once: the capture records the same launches an eager
+// iteration makes, then the graph is launched.  The host-side state flags an
+// eager iteration would leave are restored after each replay.  All buffers
+// are prepared before capturing, so no allocation or synchronisation happens
+// inside a capture.
+void run_graphed(pty_ctx* c, int algo, int n_iter, const pty_iter_params& p) {
+  run_algo(c, algo, 0, p);                 // work buffers
+  ensure_err_slot(c, n_iter);              // history capacity for every replay
+  const bool timing = c->timing;
+  c->timing = false;
+  try {
+    for (int it = 0; it < n_iter; ++it) {
+      const bool pon = probe_on(p, c->iter);
+      pty_ctx::GraphEntry* hit = nullptr;
+      for (auto& g : c->graphs)
+        if (g.algo == algo && g.pon == pon && g.gen == c->gen && g.probe == c->probe &&
+            g.dm_valid == c->dm_valid && g.den_valid == c->den_valid && g.have_truth == c->have_truth &&
+            same_params(g.p, p)) {
+          hit = &g;
+          break;
+        }
+      if (!hit) {
+        if (!c->graphs.empty() && c->graphs.front().gen != c->gen) c->drop_graphs();
+        if (c->graphs.size() >= 8) c->drop_graphs();
+        pty_ctx::GraphEntry g;
+        g.algo = algo;
+        g.pon = pon;
+        g.gen = c->gen;
+        g.probe = c->probe;
+        g.dm_valid = c->dm_valid;
+        g.den_valid = c->den_valid;
+        g.have_truth = c->have_truth;
+        g.p = p;
+        const int iter0 = c->iter;
+        PTY_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        try {
+          run_algo(c, algo, 1, p);
+        } catch (...) {
+          hipGraph_t dead = nullptr;
+          (void)hipStreamEndCapture(c->stream, &dead);
+          if (dead) (void)hipGraphDestroy(dead);
+          (void)hipGetLastError();
+          c->iter = iter0;
+          throw;
+        }
+        PTY_HIP(hipStreamEndCapture(c->stream, &g.graph));
+        c->iter = iter0;                   // the capture ran nothing
+        if (g.gen != c->gen) throw DeviceError("pty_iterate: buffers changed while capturing");
+        PTY_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+        g.dm_valid_after = c->dm_valid;
+        g.den_valid_after = c->den_valid;
+        c->graphs.push_back(g);
+        hit = &c->graphs.back();
+      }
+      PTY_HIP(hipGraphLaunch(hit->exec, c->stream));
+      c->dm_valid = hit->dm_valid_after;
+      c->den_valid = hit->den_valid_after;
+      c->iter++;
+    }
+  } catch (...) {
+    c->timing = timing;
+    throw;
+  }
+  c->timing = timing;
+}
+
+// ---- chunk autotuning: a small JSON cache {"key": chunk, ...} ----
+std::map<std::string, int> read_tune_cache(const char* path) {
+  std::map<std::string, int> m;
+  std::ifstream f(path);
+  if (!f) return m;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t i = 0;
+  while ((i = t.find('"', i)) != std::string::npos) {
+    const size_t e = t.find('"', i + 1);
+    if (e == std::string::npos) break;
+    const std::string key = t.substr(i + 1, e - i - 1);
+    size_t k = t.find(':', e);
+    if (k == std::string::npos) break;
+    const int v = std::atoi(t.c_str() + k + 1);
+    if (v > 0) m[key] = v;
+    i = t.find_first_of(",}", k);
+    if (i == std::string::npos) break;
+  }
+  return m;
+}
+
+void write_tune_cache(const char* path, const std::map<std::string, int>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) throw InvalidArg(std::string("pty_autotune: cannot write ") + tmp);
+    f << "{\n";
+    size_t n = 0;
+    for (auto& kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++n < m.size() ? ",\n" : "\n");
+    f << "}\n";
+  }
+  if (std::rename(tmp.c_str(), path) != 0) throw InvalidArg(std::string("pty_autotune: cannot replace ") + path);
+}
+
+std::string tune_key(pty_ctx* c, int algo, const pty_iter_params& p) {
+  hipDeviceProp_t prop;
+  PTY_HIP(hipGetDeviceProperties(&prop, c->device));
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  const int batch = p.lsqml_batch > 0 ? p.lsqml_batch : 512;
+  return arch + " n=" + std::to_string(c->N) + " k=" + std::to_string(c->K) + " j=" + std::to_string(c->J) +
+         (algo == PTY_DM ? " dm" : " lsqml b=" + std::to_string(batch));
+}
+
+int tune_chunk(pty_ctx* c, int algo, pty_iter_params p) {
+  const size_t hw = size_t(c->H) * c->W, kn = size_t(c->K) * c->N * c->N;
+  const int batch = p.lsqml_batch > 0 ? p.lsqml_batch : 512;
+  const int G = std::max(1, (c->J + batch - 1) / batch);
+  const int slots = algo == PTY_DM ? c->J : (c->J + G - 1) / G;
+  std::vector<int> cands;
+  for (int v : {8, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+    if (v <= std::max(8, slots) && size_t(v) * kn * sizeof(float2) <= (size_t(1) << 30)) cands.push_back(v);
+  float2* o_save = c->alloc<float2>(hw);
+  float2* p_save = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int iter0 = c->iter;
+  const bool timing = c->timing;
+  int best = 0;
+  try {
+    p_save = c->alloc<float2>(kn);
+    PTY_HIP(hipMemcpyAsync(o_save, c->obj, hw * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+    PTY_HIP(hipMemcpyAsync(p_save, c->probe, kn * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+    PTY_HIP(hipEventCreate(&e0));
+    PTY_HIP(hipEventCreate(&e1));
+    c->timing = false;
+    p.flags = 0;
+    float best_ms = 0.f;
+    for (int v : cands) {
+      p.chunk = v;
+      run_algo(c, algo, 1, p);             // warm: buffers for this chunk size
+      PTY_HIP(hipEventRecord(e0, c->stream));
+      run_algo(c, algo, 1, p);
+      PTY_HIP(hipEventRecord(e1, c->stream));
+      PTY_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      PTY_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (!best || ms < best_ms) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+  } catch (...) {
+    c->timing = timing;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->dfree(o_save);
+    c->dfree(p_save);
+    throw;
+  }
+  c->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // restore the state the tuning iterations changed
+  PTY_HIP(hipMemcpyAsync(c->obj, o_save, hw * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+  PTY_HIP(hipMemcpyAsync(c->probe, p_save, kn * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
+  c->iter = iter0;
+  launch_set_i32(c->iter_dev, iter0, c->stream);
+  PTY_HIP(hipStreamSynchronize(c->stream));
+  c->dfree(o_save);
+  c->dfree(p_save);
+  c->dm_valid = false;
+  c->den_valid = false;
+  return best;
 }
 
 }  // namespace
@@ -998,18 +1234,17 @@ pty_status pty_iterate(pty_ctx* c, pty_algo algo, int32_t n_iter, const pty_iter
     pty_iter_params p;
     pty_default_params(&p);
     if (prm) p = *prm;
-    require(p.flags == 0, "pty_iterate: flags must be 0");
+    require((p.flags & ~PTY_ITER_GRAPH) == 0, "pty_iterate: unknown flags");
     require(p.chunk >= 0, "pty_iterate: negative chunk");
     require(p.lsqml_batch >= 0, "pty_iterate: negative lsqml_batch");
     require_loaded(c);
     if (n_iter == 0 && algo == PTY_EPIE) return;
     c->set_device();
-    if (algo == PTY_DM)
-      run_dm(c, n_iter, p);
-    else if (algo == PTY_LSQML)
-      run_lsqml(c, n_iter, p);
-    else
-      run_epie(c, n_iter, p);
+    if ((p.flags & PTY_ITER_GRAPH) && algo != PTY_EPIE && n_iter > 0) {
+      run_graphed(c, algo, n_iter, p);
+      return;
+    }
+    run_algo(c, algo, n_iter, p);
     if (n_iter == 0) PTY_HIP(hipStreamSynchronize(c->stream));
   });
 }
@@ -1348,5 +1583,94 @@ pty_status pty_poisson(pty_ctx* c, const float* lam, float* out, size_t n, uint6
     PTY_HIP(hipStreamSynchronize(c->stream));
   });
 }
+
+pty_status pty_autotune(pty_ctx* c, pty_algo algo, const pty_iter_params* prm, const char* cache_path,
+                        int32_t* chunk) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_autotune: null context");
+    if (algo != PTY_DM && algo != PTY_LSQML) throw Unsupported("pty_autotune: DM and LSQML only");
+    pty_iter_params p;
+    pty_default_params(&p);
+    if (prm) p = *prm;
+    require((p.flags & ~PTY_ITER_GRAPH) == 0, "pty_autotune: unknown flags");
+    require_loaded(c);
+    c->set_device();
+    const std::string key = tune_key(c, algo, p);
+    std::map<std::string, int> cache;
+    if (cache_path) cache = read_tune_cache(cache_path);
+    auto it = cache.find(key);
+    int best;
+    if (it != cache.end()) {
+      best = it->second;
+    } else {
+      best = tune_chunk(c, algo, p);
+      if (cache_path) {
+        cache[key] = best;
+        write_tune_cache(cache_path, cache);
+      }
+    }
+    c->tuned_chunk = best;
+    if (chunk) *chunk = best;
+  });
+}
+
+}  // extern "C"
+
+struct pty_batch {
+  std::vector<pty_ctx*> ctxs;
+  std::string err;
+};
+
+extern "C" {
+
+pty_status pty_batch_create(pty_ctx* const* ctxs, int32_t n, pty_batch** out) {
+  return guarded(nullptr, [&] {
+    require(ctxs != nullptr && out != nullptr && n >= 1, "pty_batch_create: bad argument");
+    std::unique_ptr<pty_batch> b(new pty_batch());
+    for (int i = 0; i < n; ++i) {
+      require(ctxs[i] != nullptr, "pty_batch_create: null context");
+      b->ctxs.push_back(ctxs[i]);
+    }
+    *out = b.release();
+  });
+}
+
+pty_status pty_batch_iterate(pty_batch* b, pty_algo algo, int32_t n_iter, const pty_iter_params* prm) {
+  if (!b) return fail(nullptr, PTY_E_INVALID, "pty_batch_iterate: null batch");
+  if (n_iter < 0) return fail(nullptr, PTY_E_INVALID, (b->err = "pty_batch_iterate: negative iteration count"));
+  // buffers first (allocation synchronises), then the iterations back to back
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    const pty_status st = pty_iterate(b->ctxs[i], algo, 0, prm);
+    if (st != PTY_OK) {
+      b->err = "context " + std::to_string(i) + ": " + pty_last_error(b->ctxs[i]);
+      return st;
+    }
+  }
+  for (int t = 0; t < n_iter; ++t)
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+      const pty_status st = pty_iterate(b->ctxs[i], algo, 1, prm);
+      if (st != PTY_OK) {
+        b->err = "context " + std::to_string(i) + ": " + pty_last_error(b->ctxs[i]);
+        return st;
+      }
+    }
+  return PTY_OK;
+}
+
+pty_status pty_batch_sync(pty_batch* b) {
+  if (!b) return fail(nullptr, PTY_E_INVALID, "pty_batch_sync: null batch");
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    const pty_status st = pty_sync(b->ctxs[i]);
+    if (st != PTY_OK) {
+      b->err = "context " + std::to_string(i) + ": " + pty_last_error(b->ctxs[i]);
+      return st;
+    }
+  }
+  return PTY_OK;
+}
+
+void pty_batch_destroy(pty_batch* b) { delete b; }
+
+const char* pty_batch_last_error(const pty_batch* b) { return b ? b->err.c_str() : g_tls_error.c_str(); }
 
 }  // extern "C"

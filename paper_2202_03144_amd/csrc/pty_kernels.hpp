@@ -164,7 +164,10 @@ void launch_dm_init(const DmInitArgs& a);
 void launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s);
 void launch_amplitude(const float* counts, float* amp, double* totals, int n, int j, hipStream_t s);
 void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s);
-void launch_err_reduce(const double* errp, int count, double* out, hipStream_t s);
+// out[*slot] = E of the partials (slot NULL: out[0]); advance: then ++*slot (the
+// device-side iteration counter, so that a captured iteration can be replayed).
+void launch_err_reduce(const double* errp, int count, double* out, hipStream_t s, int* slot = nullptr,
+                       bool advance = false);
 void launch_posgrad_reduce(const double* part, int count, int nrb, float* out, const int* jlist, hipStream_t s);
 void launch_scale_f32(float* p, size_t n, float s, hipStream_t st);
 void launch_scale_c64(float2* p, size_t n, float s, hipStream_t st);
@@ -181,7 +184,8 @@ void launch_seed_stitch(const float* patches, const int2* place, const float2* p
                         const int* bin_idx, int bins_w, int bins_h, float2* obj, int h, int w, hipStream_t s);
 size_t nrmse_part_doubles();
 void launch_nrmse(const float2* o, const float2* t, const unsigned char* mask, size_t n, double* part, double* out,
-                  hipStream_t s);
+                  hipStream_t s, int* slot = nullptr, bool advance = false);
+void launch_set_i32(int* p, int v, hipStream_t s);
 void launch_roi_mask(const float* den, const unsigned* den_max, float frac, size_t n, unsigned char* mask,
                      hipStream_t s);
 

@@ -216,13 +216,17 @@ __global__ __launch_bounds__(256) void k_nrmse_part(const float2* __restrict__ o
 }
 
 // ||c o - t||^2 at the optimal c is sum|t|^2 - |<o, t>|^2 / sum|o|^2
-__global__ void k_nrmse_final(const double* __restrict__ part, double* __restrict__ out) {
+__global__ void k_nrmse_final(const double* __restrict__ part, double* __restrict__ out, int* slot, int advance) {
   double s[4] = {0, 0, 0, 0};
   for (int b = 0; b < kNrmseBlocks; ++b)
     for (int r = 0; r < 4; ++r) s[r] += part[b * 4 + r];
   const double num = s[0] > 0 ? s[3] - (s[1] * s[1] + s[2] * s[2]) / s[0] : s[3];
-  *out = s[3] > 0 ? sqrt(fmax(num, 0.0) / s[3]) : 0.0;
+  const int t = slot ? *slot : 0;
+  out[t] = s[3] > 0 ? sqrt(fmax(num, 0.0) / s[3]) : 0.0;
+  if (advance) *slot = t + 1;
 }
+
+__global__ void k_set_i32(int* p, int v) { *p = v; }
 
 // mask[i] = den[i] >= frac * max(den)
 __global__ void k_roi_mask(const float* __restrict__ den, const unsigned* __restrict__ den_max, float frac, size_t n,
@@ -280,10 +284,15 @@ void launch_seed_stitch(const float* patches, const int2* place, const float2* p
 size_t nrmse_part_doubles() { return kNrmseBlocks * 4; }
 
 void launch_nrmse(const float2* o, const float2* t, const unsigned char* mask, size_t n, double* part, double* out,
-                  hipStream_t s) {
+                  hipStream_t s, int* slot, bool advance) {
   k_nrmse_part<<<kNrmseBlocks, 256, 0, s>>>(o, t, mask, n, part);
-  k_nrmse_final<<<1, 1, 0, s>>>(part, out);
+  k_nrmse_final<<<1, 1, 0, s>>>(part, out, slot, advance ? 1 : 0);
   PTY_LAUNCH_CHECK("nrmse");
+}
+
+void launch_set_i32(int* p, int v, hipStream_t s) {
+  k_set_i32<<<1, 1, 0, s>>>(p, v);
+  PTY_LAUNCH_CHECK("set_i32");
 }
 
 void launch_roi_mask(const float* den, const unsigned* den_max, float frac, size_t n, unsigned char* mask,

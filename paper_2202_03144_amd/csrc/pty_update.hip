@@ -491,7 +491,9 @@ __global__ __launch_bounds__(256) void k_probe_intensity(const float2* probe, fl
 }
 
 // Deterministic sum of `count` (num, den) partial pairs; out = num / den.
-__global__ __launch_bounds__(1024) void k_err_reduce(const double* errp, int count, double* out) {
+// out[*slot] = E (slot NULL: out[0]); with advance != 0 thread 0 then increments *slot
+__global__ __launch_bounds__(1024) void k_err_reduce(const double* errp, int count, double* out, int* slot,
+                                                     int advance) {
   __shared__ double red[16];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < count; i += 1024) {
@@ -500,7 +502,11 @@ __global__ __launch_bounds__(1024) void k_err_reduce(const double* errp, int cou
   }
   a = block_sum<1024>(a, red);
   b = block_sum<1024>(b, red);
-  if (threadIdx.x == 0) out[0] = b != 0.0 ? a / b : a;
+  if (threadIdx.x == 0) {
+    const int t = slot ? *slot : 0;
+    out[t] = b != 0.0 ? a / b : a;
+    if (advance) *slot = t + 1;
+  }
 }
 
 __global__ void k_posgrad_reduce(const double* part, int count, int nrb, float* out, const int* jlist) {
@@ -640,8 +646,8 @@ void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipS
   PTY_LAUNCH_CHECK("probe_intensity");
 }
 
-void launch_err_reduce(const double* errp, int count, double* out, hipStream_t s) {
-  k_err_reduce<<<1, 1024, 0, s>>>(errp, count, out);
+void launch_err_reduce(const double* errp, int count, double* out, hipStream_t s, int* slot, bool advance) {
+  k_err_reduce<<<1, 1024, 0, s>>>(errp, count, out, slot, advance ? 1 : 0);
   PTY_LAUNCH_CHECK("err_reduce");
 }
 

@@ -108,11 +108,24 @@ class Plan:
         del keep
 
     # -- iteration ---------------------------------------------------------
-    def iterate(self, algo, n_iter: int = 1, **params) -> None:
-        """Enqueue ``n_iter`` iterations of 'epie', 'dm' or 'lsqml' (asynchronous)."""
+    def iterate(self, algo, n_iter: int = 1, graph: bool = False, **params) -> None:
+        """Enqueue ``n_iter`` iterations of 'epie', 'dm' or 'lsqml' (asynchronous).
+
+        graph=True replays captured iterations (PTY_ITER_GRAPH; DM and LSQML)."""
         a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        if graph:
+            params["flags"] = params.get("flags", 0) | L.ITER_GRAPH
         p = self.default_params(**params)
         self._check(self._lib.pty_iterate(self._live(), a, int(n_iter), C.byref(p)))
+
+    def autotune(self, algo, cache_path: Optional[str] = None, **params) -> int:
+        """Choose the Fourier-pass chunk by timing (see pty_autotune); returns it."""
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        p = self.default_params(**params)
+        out = C.c_int32()
+        self._check(self._lib.pty_autotune(self._live(), a, C.byref(p),
+                                           cache_path.encode() if cache_path else None, C.byref(out)))
+        return int(out.value)
 
     def sync(self) -> None:
         self._check(self._lib.pty_sync(self._live()))
@@ -274,6 +287,51 @@ class Plan:
         if getattr(self, "_ctx", None) is not None:
             self._lib.pty_destroy(self._ctx)
             self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several plans iterated together, each on its own stream (pty_batch_*)."""
+
+    def __init__(self, plans):
+        self._lib = L.lib()
+        self.plans = list(plans)
+        arr = (C.c_void_p * len(self.plans))(*[pl._live().value for pl in self.plans])
+        out = C.c_void_p()
+        st = self._lib.pty_batch_create(arr, len(self.plans), C.byref(out))
+        if st != L.OK:
+            raise PtyError(st, self._lib.pty_batch_last_error(None).decode())
+        self._b = out
+
+    def _check(self, st: int) -> None:
+        if st != L.OK:
+            raise PtyError(st, self._lib.pty_batch_last_error(self._b).decode())
+
+    def iterate(self, algo, n_iter: int = 1, graph: bool = False, **params) -> None:
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        if graph:
+            params["flags"] = params.get("flags", 0) | L.ITER_GRAPH
+        p = Plan.default_params(**params)
+        self._check(self._lib.pty_batch_iterate(self._b, a, int(n_iter), C.byref(p)))
+
+    def sync(self) -> None:
+        self._check(self._lib.pty_batch_sync(self._b))
+
+    def close(self) -> None:
+        if getattr(self, "_b", None) is not None:
+            self._lib.pty_batch_destroy(self._b)
+            self._b = None
 
     def __enter__(self):
         return self

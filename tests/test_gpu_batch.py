@@ -1,0 +1,121 @@
+"""Graph-replayed iterations, batches of uneven datasets and the chunk
+autotuner against eager single-dataset iterations.
+
+All three only change how the same kernels are launched (captured once and
+replayed; several contexts on their own streams; patterns per Fourier-pass
+launch), never what they compute, so the results must be bit-identical to
+eager iterations of each dataset alone."""
+import json
+
+import numpy as np
+import pytest
+
+from _cases import c64, raster_case, spiral_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(case, stream=None, truth=False):
+    import torch
+    from paper_2202_03144_amd import Plan
+    pl = Plan(case.n, case.k, case.j, case.shape, stream=stream)
+    pl.load_patterns(case.counts)
+    pl.load_positions(case.pos)
+    pl.set_object(c64(np.ones(case.shape)))
+    pl.set_probe(c64(case.probe))
+    if truth:
+        pl.set_truth(c64(case.obj_true), 0.3)
+    return pl
+
+
+def _state(pl):
+    return pl.object(), pl.probe(), pl.errors()
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("algo,params", [
+    ("dm", dict(probe_update_start=2)),
+    ("lsqml", dict(probe_update_start=1, lsqml_batch=12)),
+])
+def test_graph_replays_match_eager(algo, params):
+    import torch
+    case = spiral_case(64, 2, 30, cfg=97)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    eager = _plan(case, s1, truth=True)
+    graph = _plan(case, s2, truth=True)
+    for it in range(5):
+        eager.iterate(algo, 1, **params)
+        graph.iterate(algo, 1, graph=True, **params)
+        # eager work and synchronisation between the replays
+        a, b = _state(eager), _state(graph)
+        assert _same(a, b), f"iteration {it}"
+        assert np.array_equal(eager.nrmse_history(), graph.nrmse_history())
+    # several replays in one call
+    eager.iterate(algo, 3, **params)
+    graph.iterate(algo, 3, graph=True, **params)
+    assert _same(_state(eager), _state(graph))
+    # switching back to eager iterations continues the same trajectory
+    eager.iterate(algo, 1, **params)
+    graph.iterate(algo, 1, **params)
+    assert _same(_state(eager), _state(graph))
+    eager.close()
+    graph.close()
+
+
+def _uneven_cases():
+    return [spiral_case(64, 1, 20, cfg=98), spiral_case(128, 1, 12, cfg=99),
+            raster_case(64, 2, 5, 6, 7.0, 4.0, 110, cfg=100), spiral_case(32, 3, 40, cfg=101)]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_individual(graph):
+    import torch
+    from paper_2202_03144_amd import Batch
+    cases = _uneven_cases()
+    params = dict(probe_update_start=1, lsqml_batch=8)
+    singles = [_plan(c) for c in cases]
+    for pl in singles:
+        pl.iterate("lsqml", 3, **params)
+    batched = [_plan(c, torch.cuda.Stream()) for c in cases]
+    with Batch(batched) as b:
+        b.iterate("lsqml", 3, graph=graph, **params)
+        b.sync()
+    for i, (x, y) in enumerate(zip(singles, batched)):
+        assert _same(_state(x), _state(y)), f"dataset {i}"
+    for pl in singles + batched:
+        pl.close()
+
+
+def test_batch_reports_failing_context():
+    from paper_2202_03144_amd import Batch, Plan, PtyError
+    case = spiral_case(64, 1, 20, cfg=98)
+    good = _plan(case)
+    empty = Plan(64, 1, 20, case.shape)      # nothing loaded
+    with Batch([good, empty]) as b:
+        with pytest.raises(PtyError, match="STATE.*context 1"):
+            b.iterate("dm", 1)
+    good.close()
+    empty.close()
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    case = spiral_case(64, 2, 30, cfg=97)
+    params = dict(probe_update_start=0, lsqml_batch=15)
+    ref = _plan(case)
+    ref.iterate("lsqml", 2, chunk=7, **params)
+    tuned = _plan(case)
+    cache = str(tmp_path / "tune.json")
+    ch = tuned.autotune("lsqml", cache, **params)
+    assert ch in (8, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+    tuned.iterate("lsqml", 2, **params)         # uses the tuned chunk
+    assert _same(_state(ref), _state(tuned))
+    data = json.load(open(cache))
+    assert list(data.values()) == [ch] and "n=64 k=2 j=30 lsqml b=15" in list(data)[0]
+    # a second plan of the same shape reads the cache
+    again = _plan(case)
+    assert again.autotune("lsqml", cache, **params) == ch
+    for pl in (ref, tuned, again):
+        pl.close()
