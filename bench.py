@@ -208,11 +208,18 @@ def learned_leg(args, torch) -> dict:
         hist, ms, hit = time_to_nrmse(pl, args.nrmse_target, max_iter, stream,
                                       probe_update_start=1 << 30)
         pl.close()
-        res = {"nrmse_start": round(nrmse0, 5), "seed_ms": round(seed_ms, 2),
+        reach = {}
+        for thr in (3e-2, 2e-2, 1.2e-2, args.nrmse_target):
+            k = np.nonzero(hist <= thr)[0]
+            reach[f"{thr:g}"] = None if not k.size else {"iterations": int(k[0]) + 1,
+                                                          "ms": round(seed_ms + float(ms[k[0]]), 2)}
+        res = {"nrmse_start": round(nrmse0, 5), "seed_ms": round(seed_ms, 2), "time_to": reach,
                "iterations_to_target": None if hit is None else hit + 1,
                "ms_to_target": None if hit is None else round(seed_ms + float(ms[hit]), 2),
                "lsqml_ms_per_iter": round(float(ms[-1]) / len(ms), 3),
-               "nrmse_last": round(float(hist[-1]), 5), "iterations_run": len(ms)}
+               "nrmse_last": round(float(hist[-1]), 5), "iterations_run": len(ms),
+               "nrmse_at": {str(i): round(float(hist[i - 1]), 5) for i in (1, 2, 5, 10, 20, 50, 100, 200, 400)
+                            if i <= len(hist)}}
         if learned:
             res.update({"used_fallback": info["used_fallback"], "e_seed": round(info["e_seed"], 5),
                         "e_flat": round(info["e_flat"], 5)})

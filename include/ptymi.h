@@ -291,7 +291,7 @@ pty_status pty_training_targets(pty_ctx* ctx, float* out);
  * an object: patch j sits at the nearest integer position of window j plus
  * (32, 32); a sequential chain in position order gives each patch a phase
  * factor e_j = z / |z|, z = sum over already stitched samples (the pixels
- * whose coordinates are multiples of 8) of S conj(c_j); the result is the
+ * whose coordinates are multiples of 16) of S conj(c_j); the result is the
  * mean of c_j e_j over the patches covering a pixel, 1 where none does.
  * out: H x W complex64 device buffer, or NULL to replace the context's
  * object.  N must be 128.  Synchronises. */

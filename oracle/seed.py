@@ -6,7 +6,7 @@ Network input and training targets, and the stitching of predicted
 * placement: the central 64 x 64 of window j, at the window's nearest
   integer position (floor(p + 1/2)) plus (32, 32);
 * phase offsets: a sequential chain over the patches in position order on
-  the coarse grid of object pixels whose coordinates are multiples of 8:
+  the coarse grid of object pixels whose coordinates are multiples of 16:
   z_j = sum over patch j's coarse samples of S conj(c_j), e_j = z_j / |z_j|
   (1 if z_j = 0), then S += c_j e_j on those samples;
 * the seed: the mean of c_j e_j over the patches covering a pixel, 1 where no
@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 PATCH = 64
-GRID = 8
+GRID = 16
 
 
 def network_input(counts, photons):
@@ -55,8 +55,8 @@ def stitch(patches, pos, h, w, n=128):
     S = np.zeros(((h + GRID - 1) // GRID, (w + GRID - 1) // GRID), np.complex128)
     e = np.ones(len(t), np.complex128)
     for j, (ty, tx) in enumerate(t):
-        gy, gx = -(-ty // GRID) * GRID, -(-tx // GRID) * GRID   # first multiples of 8 inside
-        samples = c[j, gy - ty::GRID, gx - tx::GRID]               # 8 x 8
+        gy, gx = -(-ty // GRID) * GRID, -(-tx // GRID) * GRID   # first grid points inside
+        samples = c[j, gy - ty::GRID, gx - tx::GRID]               # 4 x 4
         win = S[gy // GRID:gy // GRID + samples.shape[0], gx // GRID:gx // GRID + samples.shape[1]]
         z = np.sum(win * np.conj(samples))
         e[j] = z / abs(z) if abs(z) > 0 else 1.0

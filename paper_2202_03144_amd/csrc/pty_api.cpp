@@ -854,7 +854,8 @@ void stitch(pty_ctx* c, const float* patches, float2* dst) {
   for (size_t b = 0; b < size_t(bh) * bw; ++b) beg[b + 1] += beg[b];
   std::vector<int> fill(beg.begin(), beg.end() - 1);
   for (int j = 0; j < c->J; ++j) idx[fill[size_t(t[j].x / 64) * bw + t[j].y / 64]++] = j;
-  const int hc = (c->H + 7) / 8, wc = (c->W + 7) / 8;
+  const int gs = seed_chain_grid();
+  const int hc = (c->H + gs - 1) / gs, wc = (c->W + gs - 1) / gs;
   int2* d_t = c->alloc<int2>(c->J);
   int* d_beg = nullptr;
   int* d_idx = nullptr;
@@ -869,7 +870,7 @@ void stitch(pty_ctx* c, const float* patches, float2* dst) {
     PTY_HIP(hipMemcpyAsync(d_beg, beg.data(), sizeof(int) * beg.size(), hipMemcpyHostToDevice, c->stream));
     PTY_HIP(hipMemcpyAsync(d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
     launch_fill_u32(reinterpret_cast<unsigned*>(d_S), size_t(hc) * wc * 2, 0u, c->stream);
-    launch_seed_chain(patches, d_t, c->J, d_S, wc, d_ph, c->stream);
+    launch_seed_chain(patches, d_t, c->J, d_S, hc, wc, d_ph, c->stream);
     launch_seed_stitch(patches, d_t, d_ph, d_beg, d_idx, bw, bh, dst, c->H, c->W, c->stream);
     PTY_HIP(hipStreamSynchronize(c->stream));
   } catch (...) {

@@ -36,99 +36,137 @@
 namespace pty {
 namespace {
 
-using bf16 = __hip_bfloat16;
+using bf16 = __bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
-__device__ __forceinline__ float tof(bf16 v) { return __bfloat162float(v); }
-__device__ __forceinline__ bf16 tob(float v) { return __float2bfloat16(v); }
+__device__ __forceinline__ float tof(bf16 v) { return static_cast<float>(v); }
+__device__ __forceinline__ bf16 tob(float v) { return static_cast<bf16>(v); }  // round to nearest even
+
+// 8 consecutive channels (16 bytes; every channel stride and offset here is a
+// multiple of 8)
+__device__ __forceinline__ void ld8(const bf16* p, float (&v)[8]) {
+  const bf16x8_t x = *reinterpret_cast<const bf16x8_t*>(p);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = static_cast<float>(x[i]);
+}
+__device__ __forceinline__ void st8(bf16* p, const float (&v)[8]) {
+  bf16x8_t x;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) x[i] = static_cast<bf16>(v[i]);
+  *reinterpret_cast<bf16x8_t*>(p) = x;
+}
 
 // A strided NHWC view: element (b, y, x, c) at ((b*H + y)*W + x)*cs + co + c.
 struct View {
   bf16* p;
   int cs, co;
+  __device__ __forceinline__ bf16* at(size_t m) const { return p + m * cs + co; }
 };
 
 // ---------------------------------------------------------------------------
 // Implicit-GEMM convolution on MFMA.  out[m][n] = act(bias[n] +
 // sum_{tap, c} in[m + tap][c] * w[n][tap][c]), m = (b, y, x) pixels of an
-// S x S image, n output channels.  Block: 4 wavefronts x 16 pixels, BN output
-// channels (BN / 16 MFMA tiles per wavefront).
+// S x S image, n output channels.  Block: 4 wavefronts; each wavefront owns
+// MT x 16 pixels and BN output channels (BN / 16 tiles), so every 16-byte A
+// fragment feeds BN / 16 MFMAs and every B fragment MT of them.
 // ---------------------------------------------------------------------------
-template <int BN, bool RELU, bool BIAS>
+template <int BN, int MT, bool RELU, bool BIAS>
 __global__ __launch_bounds__(256) void k_conv_mfma(View in, const bf16* __restrict__ w,
                                                    const float* __restrict__ bias, View out, int nb, int S,
                                                    int cin, int cout) {
   constexpr int NT = BN / 16;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int m0 = blockIdx.x * 64 + wv * 16;
+  const int m0 = (blockIdx.x * 4 + wv) * (MT * 16);
   const int n0 = blockIdx.y * BN;
   const int mtot = nb * S * S;
   const int row = lane & 15, grp = lane >> 4;
-  // the pixel whose row of A this lane supplies
-  const int am = m0 + row;
-  const bool am_ok = am < mtot;
-  const int ab = am / (S * S), ay = (am / S) % S, ax = am % S;
-  f32x4_t acc[NT];
+  int ab[MT], ay[MT], ax[MT];
+  bool aok[MT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const int ktap = 9 * cin;
+  for (int i = 0; i < MT; ++i) {
+    const int am = m0 + i * 16 + row;
+    aok[i] = am < mtot;
+    ab[i] = am / (S * S);
+    ay[i] = (am / S) % S;
+    ax[i] = am % S;
+  }
+  f32x4_t acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[i][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   for (int tap = 0; tap < 9; ++tap) {
-    const int yy = ay + tap / 3 - 1, xx = ax + tap % 3 - 1;
-    const bool ok = am_ok && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
-    const bf16* ap = in.p + ((size_t)(ab * S + yy) * S + xx) * in.cs + in.co + grp * 8;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const bf16* ap[MT];
+    bool ok[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const int yy = ay[i] + dy, xx = ax[i] + dx;
+      ok[i] = aok[i] && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
+      ap[i] = in.p + ((size_t)(ab[i] * S + yy) * S + xx) * in.cs + in.co + grp * 8;
+    }
+    const bf16* bp = w + ((size_t)(n0 + row) * 9 + tap) * cin + grp * 8;
     for (int c0 = 0; c0 < cin; c0 += 32) {
-      bf16x8_t a;
-      if (ok) {
-        a = *reinterpret_cast<const bf16x8_t*>(ap + c0);
-      } else {
+      bf16x8_t a[MT], b[NT];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = (__bf16)0.0f;
+      for (int i = 0; i < MT; ++i) {
+        if (ok[i]) {
+          a[i] = *reinterpret_cast<const bf16x8_t*>(ap[i] + c0);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a[i][e] = static_cast<bf16>(0.0f);
+        }
       }
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int n = n0 + t * 16 + row;
-        const bf16x8_t b =
-            *reinterpret_cast<const bf16x8_t*>(w + ((size_t)n * 9 + tap) * cin + c0 + grp * 8);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const bf16x8_t*>(bp + (size_t)t * 16 * 9 * cin + c0);
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[t], acc[i][t], 0, 0, 0);
     }
   }
-  (void)ktap;
   // D[i][j]: j = lane % 16 (output channel), i = 4 * (lane / 16) + r (pixel)
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int n = n0 + t * 16 + row;
     const float bv = BIAS ? bias[n] : 0.f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + grp * 4 + r;
-      if (m >= mtot) continue;
-      float v = acc[t][r] + bv;
-      if (RELU) v = fmaxf(v, 0.f);
-      out.p[(size_t)m * out.cs + out.co + n] = tob(v);
-    }
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + i * 16 + grp * 4 + r;
+        if (m >= mtot) continue;
+        float v = acc[i][t][r] + bv;
+        if (RELU) v = fmaxf(v, 0.f);
+        out.p[(size_t)m * out.cs + out.co + n] = tob(v);
+      }
   }
 }
 
 // Weight gradient on MFMA: part[split][n][tap][c] = sum over the split's pixels
-// m of dz[m][n] * in[m + tap][c].  Block = 4 wavefronts on a 32 x 32 (n, c)
-// tile of one tap; each wavefront owns a 16 x 16 quarter.  Pixel chunks of 32
-// are staged through LDS transposed so every fragment is 16 contiguous bytes.
-__global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __restrict__ part, int nb, int S,
-                                                    int cin, int cout, int px_per_split) {
-  __shared__ __align__(16) bf16 sd[32][40];  // [n][pixel], padded rows
+// m of dz[m][n] * in[m + tap][c]; the centre-tap blocks of the first channel
+// block also sum dz over the split into bpart[split][n] (the bias gradient).
+// Block = 4 wavefronts on a 32 x 32 (n, c) tile of one tap; each wavefront
+// owns a 16 x 16 quarter.  Pixel chunks of 32 are staged through LDS
+// transposed so that every fragment is 16 contiguous bytes.
+__global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __restrict__ part,
+                                                    float* __restrict__ bpart, int nb, int S, int cin, int cout,
+                                                    int px_per_split) {
+  __shared__ __align__(16) bf16 sd[32][40];  // [n][pixel], 80-byte rows
   __shared__ __align__(16) bf16 sx[32][40];  // [c][pixel]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int n0 = blockIdx.x * 32, c0 = (blockIdx.y % (cin / 32)) * 32, tap = blockIdx.y / (cin / 32);
+  const int cblk = blockIdx.y % (cin / 32), tap = blockIdx.y / (cin / 32);
+  const int n0 = blockIdx.x * 32, c0 = cblk * 32;
   const int split = blockIdx.z;
   const int mtot = nb * S * S;
   const int mb = split * px_per_split, me = min(mtot, mb + px_per_split);
   const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  const int wi = (wv >> 1) * 16, wj = (wv & 1) * 16;  // this wavefront's (n, c) quarter
+  const int wi = (wv >> 1) * 16, wj = (wv & 1) * 16;
   const int row = lane & 15, grp = lane >> 4;
+  const bool do_bias = tap == 4 && cblk == 0;
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  // loader: thread t -> pixel t / 8, channel group t % 8 (4 channels each)
+  float bacc = 0.f;
   const int lp = threadIdx.x >> 3, lc = (threadIdx.x & 7) * 4;
   for (int m = mb; m < me; m += 32) {
     const int pm = m + lp;
@@ -140,12 +178,12 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __r
     }
     if (pm < me) {
       const int b = pm / (S * S), y = (pm / S) % S, x = pm % S;
-      const bf16* dp = dz.p + (size_t)pm * dz.cs + dz.co + n0 + lc;
+      const bf16* dp = dz.at(pm) + n0 + lc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) vd[i] = dp[i];
       const int yy = y + dy, xx = x + dx;
       if ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
-        const bf16* xp = in.p + ((size_t)(b * S + yy) * S + xx) * in.cs + in.co + c0 + lc;
+        const bf16* xp = in.at((size_t)(b * S + yy) * S + xx) + c0 + lc;
 #pragma unroll
         for (int i = 0; i < 4; ++i) vx[i] = xp[i];
       }
@@ -157,20 +195,23 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __r
       sx[lc + i][lp] = vx[i];
     }
     __syncthreads();
-    // rows are 80 bytes, so every 8-element fragment is 16-byte aligned
     const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sd[wi + row][grp * 8]);
     const bf16x8_t bb = *reinterpret_cast<const bf16x8_t*>(&sx[wj + row][grp * 8]);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+    if (do_bias && threadIdx.x < 32) {
+#pragma unroll 8
+      for (int q = 0; q < 32; ++q) bacc += tof(sd[threadIdx.x][q]);
+    }
   }
-  // D[i][j]: i = n (4 * grp + r), j = c (row)
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int n = n0 + wi + grp * 4 + r, c = c0 + wj + row;
     part[(((size_t)split * cout + n) * 9 + tap) * cin + c] = acc[r];
   }
+  if (do_bias && threadIdx.x < 32) bpart[(size_t)split * cout + n0 + threadIdx.x] = bacc;
 }
 
-// sum over splits in order: dst[i] = sum_s part[s][i]
+// dst[i] = sum over s of part[s * n + i], in order
 __global__ void k_sum_splits(const float* __restrict__ part, int splits, size_t n, float* __restrict__ dst) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -189,21 +230,6 @@ __global__ void k_unpack_wb(const float* __restrict__ src, int k, int cout, floa
   else b[n] = src[i];
 }
 
-// bias gradient: db[n] = sum_m dz[m][n]; one block per channel, ordered partial sums
-__global__ __launch_bounds__(256) void k_bias_grad(View dz, int mtot, int cout, float* __restrict__ db) {
-  __shared__ float sh[256];
-  const int n = blockIdx.x;
-  float s = 0.f;
-  for (int m = threadIdx.x; m < mtot; m += 256) s += tof(dz.p[(size_t)m * dz.cs + dz.co + n]);
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) db[n] = sh[0];
-}
-
 // transposed, spatially flipped weights for the input gradient:
 // wt[c][tap][n] = w[n][8 - tap][c]
 __global__ void k_wflip(const bf16* __restrict__ w, bf16* __restrict__ wt, int cin, int cout) {
@@ -214,184 +240,326 @@ __global__ void k_wflip(const bf16* __restrict__ w, bf16* __restrict__ wt, int c
 }
 
 // ---------------------------------------------------------------------------
-// Direct kernels of the 1-channel input and 2-channel output layers
+// The 1-channel input layer and the 2-channel output layer
 // ---------------------------------------------------------------------------
-// L0: out[b][y][x][n] = relu(bias[n] + sum_tap in[b][y+dy][x+dx] w[n][tap]); in float32
-__global__ void k_conv_in(const float* __restrict__ in, const bf16* __restrict__ w, const float* __restrict__ bias,
-                          View out, int nb, int S, int cout) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nb * S * S) return;
-  const int b = m / (S * S), y = (m / S) % S, x = m % S;
-  float v[9];
+// L0 + ReLU + 2 x 2 pooling: one thread per pooled pixel computes the four
+// 32-channel pre-activations below it; writes the pooled p0 and, for
+// training, the activations a0.
+template <bool STORE_A0>
+__global__ __launch_bounds__(256) void k_conv_in_pool(const float* __restrict__ x, const bf16* __restrict__ w,
+                                                      const float* __restrict__ bias, View a0, View p0, int nb) {
+  constexpr int S = 128, P = 64, C = 32;
+  __shared__ float ws[C * 9], bs[C];
+  for (int i = threadIdx.x; i < C * 9; i += 256) ws[i] = tof(w[i]);
+  if (threadIdx.x < C) bs[threadIdx.x] = bias[threadIdx.x];
+  __syncthreads();
+  const size_t q = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (q >= (size_t)nb * P * P) return;
+  const int b = (int)(q / (P * P)), py = (int)(q / P) % P, px = (int)(q % P);
+  float v[4][4];  // input rows 2py-1 .. 2py+2, cols 2px-1 .. 2px+2
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-    v[tap] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) ? in[((size_t)b * S + yy) * S + xx] : 0.f;
-  }
-  for (int n = 0; n < cout; ++n) {
-    float s = bias[n];
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) s += v[tap] * tof(w[n * 9 + tap]);
-    out.p[(size_t)m * out.cs + out.co + n] = tob(fmaxf(s, 0.f));
+    for (int c = 0; c < 4; ++c) {
+      const int yy = 2 * py - 1 + r, xx = 2 * px - 1 + c;
+      v[r][c] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) ? x[((size_t)b * S + yy) * S + xx] : 0.f;
+    }
+#pragma unroll 1
+  for (int g = 0; g < C; g += 8) {
+    float pool[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) pool[k] = 0.f;
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        float o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          float s = bs[g + k];
+#pragma unroll
+          for (int tap = 0; tap < 9; ++tap) s += v[sy + tap / 3][sx + tap % 3] * ws[(g + k) * 9 + tap];
+          o[k] = fmaxf(s, 0.f);
+          pool[k] += o[k];
+        }
+        if (STORE_A0) st8(a0.at(((size_t)b * S + 2 * py + sy) * S + 2 * px + sx) + g, o);
+      }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) pool[k] *= 0.25f;
+    st8(p0.at(q) + g, pool);
   }
 }
 
-// L9: y[m][n] = bias[n] + sum_{tap,c} in[m + tap][c] w[n][tap][c], float32 out (n < 2)
-__global__ void k_conv_out(View in, const bf16* __restrict__ w, const float* __restrict__ bias, float* __restrict__ y,
-                           int nb, int S, int cin) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nb * S * S) return;
-  const int b = m / (S * S), yy0 = (m / S) % S, xx0 = m % S;
+// L9: y[m][n] = bias[n] + sum_{tap, c} in[m + tap][c] w[n][tap][c], float32, n < 2
+__global__ __launch_bounds__(256) void k_conv_out(View in, const bf16* __restrict__ w, const float* __restrict__ bias,
+                                                  float* __restrict__ y, int nb) {
+  constexpr int S = 64, C = 32;
+  __shared__ float ws[2 * 9 * C];
+  for (int i = threadIdx.x; i < 2 * 9 * C; i += 256) ws[i] = tof(w[i]);
+  __syncthreads();
+  const size_t m = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (m >= (size_t)nb * S * S) return;
+  const int b = (int)(m / (S * S)), y0 = (int)(m / S) % S, x0 = (int)(m % S);
   float s0 = bias[0], s1 = bias[1];
   for (int tap = 0; tap < 9; ++tap) {
-    const int yy = yy0 + tap / 3 - 1, xx = xx0 + tap % 3 - 1;
+    const int yy = y0 + tap / 3 - 1, xx = x0 + tap % 3 - 1;
     if ((unsigned)yy >= (unsigned)S || (unsigned)xx >= (unsigned)S) continue;
-    const bf16* ip = in.p + ((size_t)(b * S + yy) * S + xx) * in.cs + in.co;
-    for (int c = 0; c < cin; ++c) {
-      const float a = tof(ip[c]);
-      s0 += a * tof(w[(0 * 9 + tap) * cin + c]);
-      s1 += a * tof(w[(1 * 9 + tap) * cin + c]);
+    const bf16* ip = in.at(((size_t)b * S + yy) * S + xx);
+#pragma unroll
+    for (int g = 0; g < C; g += 8) {
+      float a[8];
+      ld8(ip + g, a);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        s0 += a[k] * ws[tap * C + g + k];
+        s1 += a[k] * ws[(9 + tap) * C + g + k];
+      }
     }
   }
-  y[(size_t)m * 2] = s0;
-  y[(size_t)m * 2 + 1] = s1;
+  y[m * 2] = s0;
+  y[m * 2 + 1] = s1;
 }
 
-// L9 input gradient fused with L8's relu: dz8[m][c] = (a8[m][c] > 0) *
+// L9 input gradient with L8's ReLU: dz8[m][c] = (a8[m][c] > 0) *
 // sum_{n, tap} dy[m - tap][n] w[n][tap][c]
-__global__ void k_conv_out_dgrad(const float* __restrict__ dy, const bf16* __restrict__ w, View a8, View dz8,
-                                 int nb, int S, int cin) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nb * S * S) return;
-  const int b = m / (S * S), y0 = (m / S) % S, x0 = m % S;
+__global__ __launch_bounds__(256) void k_conv_out_dgrad(const float* __restrict__ dy, const bf16* __restrict__ w,
+                                                        View a8, View dz8, int nb) {
+  constexpr int S = 64, C = 32;
+  __shared__ float ws[2 * 9 * C];
+  for (int i = threadIdx.x; i < 2 * 9 * C; i += 256) ws[i] = tof(w[i]);
+  __syncthreads();
+  const size_t m = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (m >= (size_t)nb * S * S) return;
+  const int b = (int)(m / (S * S)), y0 = (int)(m / S) % S, x0 = (int)(m % S);
   float g[2][9];
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
-    // output pixel o with o + tap - 1 = m, i.e. o = m - (tap - 1)
     const int yy = y0 - (tap / 3 - 1), xx = x0 - (tap % 3 - 1);
     const bool ok = (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
-    const size_t o = ((size_t)(b * S + yy) * S + xx) * 2;
+    const size_t o = (((size_t)b * S + yy) * S + xx) * 2;
     g[0][tap] = ok ? dy[o] : 0.f;
     g[1][tap] = ok ? dy[o + 1] : 0.f;
   }
-  for (int c = 0; c < cin; ++c) {
+#pragma unroll
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    float act[8], out[8];
+    ld8(a8.at(m) + c0, act);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float s = 0.f;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap)
+        s += g[0][tap] * ws[tap * C + c0 + k] + g[1][tap] * ws[(9 + tap) * C + c0 + k];
+      out[k] = act[k] > 0.f ? s : 0.f;
+    }
+    st8(dz8.at(m) + c0, out);
+  }
+}
+
+// L0 weight and bias gradient, tiled: each block sums over bands of 4 image
+// rows (grid-stride, fixed assignment), dz formed on the fly from the pooled
+// gradient and the ReLU of a0: dz[p][n] = (a0[p][n] > 0) gp0[parent(p)][n] / 4.
+// part[block][n * 10 + k]: k < 9 tap, k = 9 bias.
+constexpr int kInRows = 4;
+__global__ __launch_bounds__(256) void k_wgrad_in(const float* __restrict__ x, View a0, View gp0,
+                                                  float* __restrict__ part, int nb) {
+  constexpr int S = 128, C = 32, R = kInRows;
+  __shared__ float xs[R + 2][S + 2];
+  __shared__ float ds[R * S][C + 1];
+  __shared__ float red[8][C * 10];
+  const int n = threadIdx.x & 31, q = threadIdx.x >> 5;
+  float acc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) acc[k] = 0.f;
+  const int bands = nb * (S / R);
+  for (int band = blockIdx.x; band < bands; band += gridDim.x) {
+    const int b = band / (S / R), y0 = (band % (S / R)) * R;
+    __syncthreads();
+    for (int i = threadIdx.x; i < (R + 2) * (S + 2); i += 256) {
+      const int r = i / (S + 2), cc = i % (S + 2);
+      const int yy = y0 - 1 + r, xx = cc - 1;
+      xs[r][cc] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) ? x[((size_t)b * S + yy) * S + xx] : 0.f;
+    }
+    for (int i = threadIdx.x; i < R * S * (C / 8); i += 256) {
+      const int pix = i / (C / 8), g = (i % (C / 8)) * 8;
+      const int yy = y0 + pix / S, xx = pix % S;
+      float a[8], d[8];
+      ld8(a0.at(((size_t)b * S + yy) * S + xx) + g, a);
+      ld8(gp0.at(((size_t)b * (S / 2) + yy / 2) * (S / 2) + xx / 2) + g, d);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ds[pix][g + k] = a[k] > 0.f ? 0.25f * d[k] : 0.f;
+    }
+    __syncthreads();
+    for (int pix = q; pix < R * S; pix += 8) {
+      const int r = pix / S, cc = pix % S;
+      const float d = ds[pix][n];
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) acc[tap] += d * xs[r + tap / 3][cc + tap % 3];
+      acc[9] += d;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 10; ++k) red[q][n * 10 + k] = acc[k];
+  __syncthreads();
+  for (int i = threadIdx.x; i < C * 10; i += 256) {
     float s = 0.f;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap)
-      s += g[0][tap] * tof(w[(0 * 9 + tap) * cin + c]) + g[1][tap] * tof(w[(1 * 9 + tap) * cin + c]);
-    const float act = tof(a8.p[(size_t)m * a8.cs + a8.co + c]);
-    dz8.p[(size_t)m * dz8.cs + dz8.co + c] = tob(act > 0.f ? s : 0.f);
+    for (int qq = 0; qq < 8; ++qq) s += red[qq][i];
+    part[(size_t)blockIdx.x * C * 10 + i] = s;
   }
 }
 
-// Weight and bias gradient of a small layer by direct sums: thread = one
-// parameter, block = one pixel slice; part[split][param].
-// L0 (in float32, 1 channel) and L9 (dz float32, 2 channels) variants.
-__global__ void k_wgrad_in(const float* __restrict__ in, View dz, float* __restrict__ part, int nb, int S, int cout,
-                           int px_per_split) {
-  const int np = cout * 10;  // 9 taps + bias per output channel
-  const int pidx = threadIdx.x;
-  if (pidx >= np) return;
-  const int n = pidx / 10, k = pidx % 10;
-  const int mtot = nb * S * S, mb = blockIdx.x * px_per_split, me = min(mtot, mb + px_per_split);
-  float s = 0.f;
-  for (int m = mb; m < me; ++m) {
-    const float d = tof(dz.p[(size_t)m * dz.cs + dz.co + n]);
-    if (k == 9) {
-      s += d;
-    } else {
-      const int b = m / (S * S), y = (m / S) % S + k / 3 - 1, x = m % S + k % 3 - 1;
-      if ((unsigned)y < (unsigned)S && (unsigned)x < (unsigned)S) s += d * in[((size_t)b * S + y) * S + x];
-    }
-  }
-  part[(size_t)blockIdx.x * np + pidx] = s;
-}
-
-__global__ void k_wgrad_out(View in, const float* __restrict__ dy, float* __restrict__ part, int nb, int S, int cin,
-                            int px_per_split) {
-  const int np = 2 * (9 * cin + 1);
-  const int mtot = nb * S * S, mb = blockIdx.x * px_per_split, me = min(mtot, mb + px_per_split);
-  for (int pidx = threadIdx.x; pidx < np; pidx += blockDim.x) {
-    const int n = pidx / (9 * cin + 1), k = pidx % (9 * cin + 1);
-    float s = 0.f;
-    if (k == 9 * cin) {
-      for (int m = mb; m < me; ++m) s += dy[(size_t)m * 2 + n];
-    } else {
-      const int tap = k / cin, c = k % cin;
-      for (int m = mb; m < me; ++m) {
-        const int b = m / (S * S), y = (m / S) % S + tap / 3 - 1, x = m % S + tap % 3 - 1;
-        if ((unsigned)y < (unsigned)S && (unsigned)x < (unsigned)S)
-          s += dy[(size_t)m * 2 + n] * tof(in.p[((size_t)(b * S + y) * S + x) * in.cs + in.co + c]);
+// L9 weight and bias gradient, tiled over bands of 4 rows:
+// part[block][n][k], k = tap * 32 + c (weights) and k = 288 (bias).
+constexpr int kOutRows = 4;
+__global__ __launch_bounds__(256) void k_wgrad_out(View in, const float* __restrict__ dy, float* __restrict__ part,
+                                                   int nb) {
+  constexpr int S = 64, C = 32, R = kOutRows, K1 = 9 * C + 1;
+  __shared__ float as[R + 2][S + 2][C + 1];
+  __shared__ float dys[R * S][2];
+  __shared__ float red[8][2 * K1];
+  const int c = threadIdx.x & 31, q = threadIdx.x >> 5;
+  float acc[2][9], bacc[2] = {0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[0][t] = acc[1][t] = 0.f;
+  const int bands = nb * (S / R);
+  for (int band = blockIdx.x; band < bands; band += gridDim.x) {
+    const int b = band / (S / R), y0 = (band % (S / R)) * R;
+    __syncthreads();
+    for (int i = threadIdx.x; i < (R + 2) * (S + 2) * (C / 8); i += 256) {
+      const int cell = i / (C / 8), g = (i % (C / 8)) * 8;
+      const int r = cell / (S + 2), cc = cell % (S + 2);
+      const int yy = y0 - 1 + r, xx = cc - 1;
+      float a[8];
+      if ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
+        ld8(in.at(((size_t)b * S + yy) * S + xx) + g, a);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] = 0.f;
       }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) as[r][cc][g + k] = a[k];
     }
-    part[(size_t)blockIdx.x * np + pidx] = s;
+    for (int i = threadIdx.x; i < R * S * 2; i += 256)
+      dys[i / 2][i % 2] = dy[(((size_t)b * S + y0) * S) * 2 + i];
+    __syncthreads();
+    for (int pix = q; pix < R * S; pix += 8) {
+      const int r = pix / S, cc = pix % S;
+      const float d0 = dys[pix][0], d1 = dys[pix][1];
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const float a = as[r + tap / 3][cc + tap % 3][c];
+        acc[0][tap] += d0 * a;
+        acc[1][tap] += d1 * a;
+      }
+      bacc[0] += d0;
+      bacc[1] += d1;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < 2; ++n) {
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) red[q][n * K1 + tap * C + c] = acc[n][tap];
+    if (c == 0) red[q][n * K1 + 9 * C] = bacc[n];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * K1; i += 256) {
+    float s = 0.f;
+#pragma unroll
+    for (int qq = 0; qq < 8; ++qq) s += red[qq][i];
+    part[(size_t)blockIdx.x * 2 * K1 + i] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Pooling, upsampling, relu masks, loss, Adam
+// Pooling, upsampling, ReLU masks (8 channels per thread), loss, Adam
 // ---------------------------------------------------------------------------
 // out (S/2) = mean of 2x2 of in (S)
 __global__ void k_pool(View in, View out, int nb, int S, int c) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int so = S / 2;
-  if (i >= (size_t)nb * so * so * c) return;
-  const int ch = i % c;
-  const size_t m = i / c;
-  const int b = m / (so * so), y = (m / so) % so, x = m % so;
-  float s = 0.f;
+  const int so = S / 2, c8 = c / 8;
+  if (i >= (size_t)nb * so * so * c8) return;
+  const int g = (int)(i % c8) * 8;
+  const size_t m = i / c8;
+  const int b = (int)(m / (so * so)), y = (int)(m / so) % so, x = (int)(m % so);
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0}, v[8];
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    s += tof(in.p[((size_t)(b * S + 2 * y + k / 2) * S + 2 * x + k % 2) * in.cs + in.co + ch]);
-  out.p[m * out.cs + out.co + ch] = tob(0.25f * s);
+  for (int k = 0; k < 4; ++k) {
+    ld8(in.at(((size_t)b * S + 2 * y + k / 2) * S + 2 * x + k % 2) + g, v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += v[e];
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) s[e] *= 0.25f;
+  st8(out.at(m) + g, s);
 }
 
-// dx (S) += or = dy (S/2) / 4 broadcast
-template <bool ACC>
-__global__ void k_pool_back(View dy, View dx, int nb, int S, int c) {
+// dx (S) += dy (S/2) / 4 broadcast, then dx *= (act > 0): the skip gradient
+// of an encoder layer plus its pooled path, through its ReLU
+__global__ void k_pool_back_relu(View dy, View dx, View act, int nb, int S, int c) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= (size_t)nb * S * S * c) return;
-  const int ch = i % c;
-  const size_t m = i / c;
-  const int b = m / (S * S), y = (m / S) % S, x = m % S, so = S / 2;
-  const float g = 0.25f * tof(dy.p[((size_t)(b * so + y / 2) * so + x / 2) * dy.cs + dy.co + ch]);
-  bf16* d = dx.p + m * dx.cs + dx.co + ch;
-  *d = tob(ACC ? tof(*d) + g : g);
+  const int c8 = c / 8;
+  if (i >= (size_t)nb * S * S * c8) return;
+  const int g = (int)(i % c8) * 8;
+  const size_t m = i / c8;
+  const int b = (int)(m / (S * S)), y = (int)(m / S) % S, x = (int)(m % S), so = S / 2;
+  float d[8], v[8], a[8];
+  ld8(dy.at(((size_t)b * so + y / 2) * so + x / 2) + g, d);
+  ld8(dx.at(m) + g, v);
+  ld8(act.at(m) + g, a);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = a[e] > 0.f ? v[e] + 0.25f * d[e] : 0.f;
+  st8(dx.at(m) + g, v);
 }
 
 // out (2S) = nearest upsampling of in (S)
 __global__ void k_up(View in, View out, int nb, int S, int c) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int so = 2 * S;
-  if (i >= (size_t)nb * so * so * c) return;
-  const int ch = i % c;
-  const size_t m = i / c;
-  const int b = m / (so * so), y = (m / so) % so, x = m % so;
-  out.p[m * out.cs + out.co + ch] = in.p[((size_t)(b * S + y / 2) * S + x / 2) * in.cs + in.co + ch];
+  const int so = 2 * S, c8 = c / 8;
+  if (i >= (size_t)nb * so * so * c8) return;
+  const int g = (int)(i % c8) * 8;
+  const size_t m = i / c8;
+  const int b = (int)(m / (so * so)), y = (int)(m / so) % so, x = (int)(m % so);
+  *reinterpret_cast<bf16x8_t*>(out.at(m) + g) =
+      *reinterpret_cast<const bf16x8_t*>(in.at(((size_t)b * S + y / 2) * S + x / 2) + g);
 }
 
-// dx (S) = sum of the 2x2 block of dy (2S); relu mask of the layer that produced x applied
+// dz (S) = sum of the 2x2 block of dy (2S), through the ReLU of act (S)
 __global__ void k_up_back_relu(View dy, View act, View dz, int nb, int S, int c) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= (size_t)nb * S * S * c) return;
-  const int ch = i % c;
-  const size_t m = i / c;
-  const int b = m / (S * S), y = (m / S) % S, x = m % S, si = 2 * S;
-  float s = 0.f;
+  const int c8 = c / 8;
+  if (i >= (size_t)nb * S * S * c8) return;
+  const int g = (int)(i % c8) * 8;
+  const size_t m = i / c8;
+  const int b = (int)(m / (S * S)), y = (int)(m / S) % S, x = (int)(m % S), si = 2 * S;
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0}, v[8], a[8];
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    s += tof(dy.p[((size_t)(b * si + 2 * y + k / 2) * si + 2 * x + k % 2) * dy.cs + dy.co + ch]);
-  const float a = tof(act.p[m * act.cs + act.co + ch]);
-  dz.p[m * dz.cs + dz.co + ch] = tob(a > 0.f ? s : 0.f);
+  for (int k = 0; k < 4; ++k) {
+    ld8(dy.at(((size_t)b * si + 2 * y + k / 2) * si + 2 * x + k % 2) + g, v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += v[e];
+  }
+  ld8(act.at(m) + g, a);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) s[e] = a[e] > 0.f ? s[e] : 0.f;
+  st8(dz.at(m) + g, s);
 }
 
 // in place: d = d * (act > 0)
 __global__ void k_relu_mask(View d, View act, size_t npx, int c) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= npx * c) return;
-  const int ch = i % c;
-  const size_t m = i / c;
-  if (!(tof(act.p[m * act.cs + act.co + ch]) > 0.f)) d.p[m * d.cs + d.co + ch] = tob(0.f);
+  const int c8 = c / 8;
+  if (i >= npx * c8) return;
+  const int g = (int)(i % c8) * 8;
+  const size_t m = i / c8;
+  float v[8], a[8];
+  ld8(d.at(m) + g, v);
+  ld8(act.at(m) + g, a);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = a[e] > 0.f ? v[e] : 0.f;
+  st8(d.at(m) + g, v);
 }
 
 // mean squared error: dy = 2 (y - t) / n, per-block partial loss sums
@@ -414,13 +582,21 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_sum_d(const double* part, int n, double scale, double* out) {
+// out = scale * sum of n partials (one block, fixed order)
+__global__ __launch_bounds__(256) void k_sum_d(const double* part, int n, double scale, double* out) {
+  __shared__ double sh[256];
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += part[i];
-  *out = s * scale;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0] * scale;
 }
 
-// Adam on float32 masters; refreshes the bf16 weight copy (bias entries keep float32)
+// Adam on float32 masters
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
                        float* __restrict__ m2, size_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -486,7 +662,7 @@ struct pty_cnn {
   // activations (bf16 NHWC)
   bf16 *a0, *p0, *cat8, *p1, *cat7, *p2, *cat6, *p3, *a4, *a5, *a6, *a7, *a8;
   // gradients
-  bf16 *g0, *gp0, *gcat8, *gp1, *gcat7, *gp2, *gcat6, *gp3, *g4, *g5, *g6, *g7, *g8;
+  bf16 *gp0, *gcat8, *gp1, *gcat7, *gp2, *gcat6, *gp3, *g4, *g5, *g6, *g7, *g8;
   float *y, *gy, *xin;
 
   void* dalloc(size_t bytes) {
@@ -535,18 +711,20 @@ View V(bf16* p, int cs, int co = 0) { return View{p, cs, co}; }
 
 void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out, int nb, int S, int cin, int cout,
                  bool relu) {
+  constexpr int MT = 4;  // 16-pixel tiles per wavefront: 256 pixels per block
   const int mtot = nb * S * S;
   if (cin % 32 != 0 || cout % 32 != 0) throw std::invalid_argument("conv channels must be multiples of 32");
   const int bn = cout % 64 == 0 ? 64 : 32;
-  dim3 grid(blocks(mtot, 64), cout / bn);
+  dim3 grid(blocks(mtot, 64 * MT), cout / bn);
+  hipStream_t s = c->stream;
   if (bn == 64) {
-    if (relu) k_conv_mfma<64, true, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
-    else if (bias) k_conv_mfma<64, false, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
-    else k_conv_mfma<64, false, false><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+    if (relu) k_conv_mfma<64, MT, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else if (bias) k_conv_mfma<64, MT, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else k_conv_mfma<64, MT, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
   } else {
-    if (relu) k_conv_mfma<32, true, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
-    else if (bias) k_conv_mfma<32, false, true><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
-    else k_conv_mfma<32, false, false><<<grid, 256, 0, c->stream>>>(in, w, bias, out, nb, S, cin, cout);
+    if (relu) k_conv_mfma<32, MT, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else if (bias) k_conv_mfma<32, MT, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else k_conv_mfma<32, MT, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
   }
   PTY_LAUNCH_CHECK("conv_mfma");
 }
@@ -560,47 +738,51 @@ void launch_dgrad(pty_cnn* c, int li, View dz, View dx, int nb) {
   launch_conv(c, dz, c->wt, nullptr, dx, nb, l.S, l.cout, l.cin, false);
 }
 
+constexpr int kWgradPx = 4096;   // pixels per split of the MFMA weight gradient
+constexpr int kSmallGrid = 1024; // blocks of the tiled small-layer weight gradients
+
 // weight + bias gradient of an MFMA layer into c->g
 void launch_wgrad(pty_cnn* c, int li, View dz, View in, int nb) {
   const Conv& l = c->L[li];
   const int mtot = nb * l.S * l.S;
-  const int px = 4096;
-  const int splits = (mtot + px - 1) / px;
+  const int splits = (mtot + kWgradPx - 1) / kWgradPx;
   const size_t nw = (size_t)l.cout * 9 * l.cin;
-  if ((size_t)splits * nw > c->part_n) throw std::invalid_argument("wgrad scratch too small");
+  if ((size_t)splits * (nw + l.cout) > c->part_n) throw std::invalid_argument("wgrad scratch too small");
+  float* bpart = c->part + (size_t)splits * nw;
   dim3 grid(l.cout / 32, 9 * (l.cin / 32), splits);
-  k_wgrad_mfma<<<grid, 256, 0, c->stream>>>(dz, in, c->part, nb, l.S, l.cin, l.cout, px);
+  k_wgrad_mfma<<<grid, 256, 0, c->stream>>>(dz, in, c->part, bpart, nb, l.S, l.cin, l.cout, kWgradPx);
   PTY_LAUNCH_CHECK("wgrad_mfma");
   k_sum_splits<<<blocks(nw), 256, 0, c->stream>>>(c->part, splits, nw, c->g + l.woff);
+  k_sum_splits<<<blocks(l.cout), 256, 0, c->stream>>>(bpart, splits, l.cout, c->g + l.boff);
   PTY_LAUNCH_CHECK("sum_splits");
-  k_bias_grad<<<l.cout, 256, 0, c->stream>>>(dz, mtot, l.cout, c->g + l.boff);
-  PTY_LAUNCH_CHECK("bias_grad");
 }
 
-void forward(pty_cnn* c, const float* x, int nb) {
+// Forward pass; with train the L0 activations are kept for the backward pass.
+void forward(pty_cnn* c, const float* x, int nb, bool train) {
   auto& L = c->L;
   const bf16* w = c->wb;
   hipStream_t s = c->stream;
-  k_conv_in<<<blocks((size_t)nb * 128 * 128), 256, 0, s>>>(x, w + L[0].woff, c->p + L[0].boff, V(c->a0, 32), nb, 128,
-                                                          32);
-  PTY_LAUNCH_CHECK("conv_in");
-  k_pool<<<blocks((size_t)nb * 64 * 64 * 32), 256, 0, s>>>(V(c->a0, 32), V(c->p0, 32), nb, 128, 32);
+  const unsigned gb = blocks((size_t)nb * 64 * 64);
+  if (train)
+    k_conv_in_pool<true><<<gb, 256, 0, s>>>(x, w + L[0].woff, c->p + L[0].boff, V(c->a0, 32), V(c->p0, 32), nb);
+  else
+    k_conv_in_pool<false><<<gb, 256, 0, s>>>(x, w + L[0].woff, c->p + L[0].boff, V(c->a0, 32), V(c->p0, 32), nb);
+  PTY_LAUNCH_CHECK("conv_in_pool");
   launch_conv(c, V(c->p0, 32), w + L[1].woff, c->p + L[1].boff, V(c->cat8, 96, 64), nb, 64, 32, 32, true);  // e1
-  k_pool<<<blocks((size_t)nb * 32 * 32 * 32), 256, 0, s>>>(V(c->cat8, 96, 64), V(c->p1, 32), nb, 64, 32);
+  k_pool<<<blocks((size_t)nb * 32 * 32 * 4), 256, 0, s>>>(V(c->cat8, 96, 64), V(c->p1, 32), nb, 64, 32);
   launch_conv(c, V(c->p1, 32), w + L[2].woff, c->p + L[2].boff, V(c->cat7, 192, 128), nb, 32, 32, 64, true);  // e2
-  k_pool<<<blocks((size_t)nb * 16 * 16 * 64), 256, 0, s>>>(V(c->cat7, 192, 128), V(c->p2, 64), nb, 32, 64);
+  k_pool<<<blocks((size_t)nb * 16 * 16 * 8), 256, 0, s>>>(V(c->cat7, 192, 128), V(c->p2, 64), nb, 32, 64);
   launch_conv(c, V(c->p2, 64), w + L[3].woff, c->p + L[3].boff, V(c->cat6, 384, 256), nb, 16, 64, 128, true);  // e3
-  k_pool<<<blocks((size_t)nb * 8 * 8 * 128), 256, 0, s>>>(V(c->cat6, 384, 256), V(c->p3, 128), nb, 16, 128);
+  k_pool<<<blocks((size_t)nb * 8 * 8 * 16), 256, 0, s>>>(V(c->cat6, 384, 256), V(c->p3, 128), nb, 16, 128);
   launch_conv(c, V(c->p3, 128), w + L[4].woff, c->p + L[4].boff, V(c->a4, 256), nb, 8, 128, 256, true);
   launch_conv(c, V(c->a4, 256), w + L[5].woff, c->p + L[5].boff, V(c->a5, 256), nb, 8, 256, 256, true);
-  k_up<<<blocks((size_t)nb * 16 * 16 * 256), 256, 0, s>>>(V(c->a5, 256), V(c->cat6, 384, 0), nb, 8, 256);
+  k_up<<<blocks((size_t)nb * 16 * 16 * 32), 256, 0, s>>>(V(c->a5, 256), V(c->cat6, 384, 0), nb, 8, 256);
   launch_conv(c, V(c->cat6, 384), w + L[6].woff, c->p + L[6].boff, V(c->a6, 128), nb, 16, 384, 128, true);
-  k_up<<<blocks((size_t)nb * 32 * 32 * 128), 256, 0, s>>>(V(c->a6, 128), V(c->cat7, 192, 0), nb, 16, 128);
+  k_up<<<blocks((size_t)nb * 32 * 32 * 16), 256, 0, s>>>(V(c->a6, 128), V(c->cat7, 192, 0), nb, 16, 128);
   launch_conv(c, V(c->cat7, 192), w + L[7].woff, c->p + L[7].boff, V(c->a7, 64), nb, 32, 192, 64, true);
-  k_up<<<blocks((size_t)nb * 64 * 64 * 64), 256, 0, s>>>(V(c->a7, 64), V(c->cat8, 96, 0), nb, 32, 64);
+  k_up<<<blocks((size_t)nb * 64 * 64 * 8), 256, 0, s>>>(V(c->a7, 64), V(c->cat8, 96, 0), nb, 32, 64);
   launch_conv(c, V(c->cat8, 96), w + L[8].woff, c->p + L[8].boff, V(c->a8, 32), nb, 64, 96, 32, true);
-  k_conv_out<<<blocks((size_t)nb * 64 * 64), 256, 0, s>>>(V(c->a8, 32), w + L[9].woff, c->p + L[9].boff, c->y, nb, 64,
-                                                         32);
+  k_conv_out<<<blocks((size_t)nb * 64 * 64), 256, 0, s>>>(V(c->a8, 32), w + L[9].woff, c->p + L[9].boff, c->y, nb);
   PTY_LAUNCH_CHECK("cnn_forward");
 }
 
@@ -608,64 +790,57 @@ void forward(pty_cnn* c, const float* x, int nb) {
 void backward(pty_cnn* c, const float* x, int nb) {
   auto& L = c->L;
   hipStream_t s = c->stream;
-  const int px = 4096;
-  // L9: weight gradient and input gradient (with L8's relu)
+  // L9: weight gradient (tiled, in-block partial sums) and input gradient with L8's ReLU
   {
-    const int mtot = nb * 64 * 64, splits = (mtot + px - 1) / px, np = 2 * (9 * 32 + 1);
-    k_wgrad_out<<<splits, 256, 0, s>>>(V(c->a8, 32), c->gy, c->part, nb, 64, 32, px);
-    k_sum_splits<<<blocks(np), 256, 0, s>>>(c->part, splits, np, c->part + (size_t)splits * np);
-    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)splits * np, 9 * 32, 2, c->g + L[9].woff,
+    const int grid = std::min(nb * (64 / kOutRows), kSmallGrid), np = 2 * (9 * 32 + 1);
+    k_wgrad_out<<<grid, 256, 0, s>>>(V(c->a8, 32), c->gy, c->part, nb);
+    k_sum_splits<<<blocks(np), 256, 0, s>>>(c->part, grid, np, c->part + (size_t)grid * np);
+    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)grid * np, 9 * 32, 2, c->g + L[9].woff,
                                            c->g + L[9].boff);
     PTY_LAUNCH_CHECK("wgrad_out");
-    k_conv_out_dgrad<<<blocks((size_t)mtot), 256, 0, s>>>(c->gy, c->wb + L[9].woff, V(c->a8, 32), V(c->g8, 32), nb, 64,
-                                                         32);
+    k_conv_out_dgrad<<<blocks((size_t)nb * 64 * 64), 256, 0, s>>>(c->gy, c->wb + L[9].woff, V(c->a8, 32),
+                                                                 V(c->g8, 32), nb);
     PTY_LAUNCH_CHECK("conv_out_dgrad");
   }
   // L8 (input cat8 = [up(a7) | e1]); g8 holds dz8
   launch_wgrad(c, 8, V(c->g8, 32), V(c->cat8, 96), nb);
   launch_dgrad(c, 8, V(c->g8, 32), V(c->gcat8, 96), nb);
-  // up(a7) part -> dz7 (relu of L7), stored in g7
-  k_up_back_relu<<<blocks((size_t)nb * 32 * 32 * 64), 256, 0, s>>>(V(c->gcat8, 96, 0), V(c->a7, 64), V(c->g7, 64), nb, 32,
-                                                                  64);
+  // upsampled part -> dz7 through L7's ReLU
+  k_up_back_relu<<<blocks((size_t)nb * 32 * 32 * 8), 256, 0, s>>>(V(c->gcat8, 96, 0), V(c->a7, 64), V(c->g7, 64), nb,
+                                                                 32, 64);
   launch_wgrad(c, 7, V(c->g7, 64), V(c->cat7, 192), nb);
   launch_dgrad(c, 7, V(c->g7, 64), V(c->gcat7, 192), nb);
-  k_up_back_relu<<<blocks((size_t)nb * 16 * 16 * 128), 256, 0, s>>>(V(c->gcat7, 192, 0), V(c->a6, 128), V(c->g6, 128),
-                                                                   nb, 16, 128);
+  k_up_back_relu<<<blocks((size_t)nb * 16 * 16 * 16), 256, 0, s>>>(V(c->gcat7, 192, 0), V(c->a6, 128), V(c->g6, 128),
+                                                                  nb, 16, 128);
   launch_wgrad(c, 6, V(c->g6, 128), V(c->cat6, 384), nb);
   launch_dgrad(c, 6, V(c->g6, 128), V(c->gcat6, 384), nb);
-  k_up_back_relu<<<blocks((size_t)nb * 8 * 8 * 256), 256, 0, s>>>(V(c->gcat6, 384, 0), V(c->a5, 256), V(c->g5, 256), nb,
-                                                                 8, 256);
+  k_up_back_relu<<<blocks((size_t)nb * 8 * 8 * 32), 256, 0, s>>>(V(c->gcat6, 384, 0), V(c->a5, 256), V(c->g5, 256), nb,
+                                                                8, 256);
   launch_wgrad(c, 5, V(c->g5, 256), V(c->a4, 256), nb);
   launch_dgrad(c, 5, V(c->g5, 256), V(c->g4, 256), nb);
-  k_relu_mask<<<blocks((size_t)nb * 64 * 256), 256, 0, s>>>(V(c->g4, 256), V(c->a4, 256), (size_t)nb * 64, 256);
+  k_relu_mask<<<blocks((size_t)nb * 64 * 32), 256, 0, s>>>(V(c->g4, 256), V(c->a4, 256), (size_t)nb * 64, 256);
   launch_wgrad(c, 4, V(c->g4, 256), V(c->p3, 128), nb);
   launch_dgrad(c, 4, V(c->g4, 256), V(c->gp3, 128), nb);
-  // e3 gradient = skip slice of gcat6 + pooled path; then relu of L3
-  k_pool_back<true><<<blocks((size_t)nb * 16 * 16 * 128), 256, 0, s>>>(V(c->gp3, 128), V(c->gcat6, 384, 256), nb, 16,
-                                                                      128);
-  k_relu_mask<<<blocks((size_t)nb * 256 * 128), 256, 0, s>>>(V(c->gcat6, 384, 256), V(c->cat6, 384, 256),
-                                                             (size_t)nb * 256, 128);
+  // e3 gradient = skip slice of gcat6 + pooled path, through L3's ReLU
+  k_pool_back_relu<<<blocks((size_t)nb * 16 * 16 * 16), 256, 0, s>>>(V(c->gp3, 128), V(c->gcat6, 384, 256),
+                                                                    V(c->cat6, 384, 256), nb, 16, 128);
   launch_wgrad(c, 3, V(c->gcat6, 384, 256), V(c->p2, 64), nb);
   launch_dgrad(c, 3, V(c->gcat6, 384, 256), V(c->gp2, 64), nb);
-  k_pool_back<true><<<blocks((size_t)nb * 32 * 32 * 64), 256, 0, s>>>(V(c->gp2, 64), V(c->gcat7, 192, 128), nb, 32, 64);
-  k_relu_mask<<<blocks((size_t)nb * 1024 * 64), 256, 0, s>>>(V(c->gcat7, 192, 128), V(c->cat7, 192, 128),
-                                                             (size_t)nb * 1024, 64);
+  k_pool_back_relu<<<blocks((size_t)nb * 32 * 32 * 8), 256, 0, s>>>(V(c->gp2, 64), V(c->gcat7, 192, 128),
+                                                                   V(c->cat7, 192, 128), nb, 32, 64);
   launch_wgrad(c, 2, V(c->gcat7, 192, 128), V(c->p1, 32), nb);
   launch_dgrad(c, 2, V(c->gcat7, 192, 128), V(c->gp1, 32), nb);
-  k_pool_back<true><<<blocks((size_t)nb * 64 * 64 * 32), 256, 0, s>>>(V(c->gp1, 32), V(c->gcat8, 96, 64), nb, 64, 32);
-  k_relu_mask<<<blocks((size_t)nb * 4096 * 32), 256, 0, s>>>(V(c->gcat8, 96, 64), V(c->cat8, 96, 64),
-                                                             (size_t)nb * 4096, 32);
+  k_pool_back_relu<<<blocks((size_t)nb * 64 * 64 * 4), 256, 0, s>>>(V(c->gp1, 32), V(c->gcat8, 96, 64),
+                                                                   V(c->cat8, 96, 64), nb, 64, 32);
   launch_wgrad(c, 1, V(c->gcat8, 96, 64), V(c->p0, 32), nb);
   launch_dgrad(c, 1, V(c->gcat8, 96, 64), V(c->gp0, 32), nb);
-  // L0: pooled gradient back to 128 x 128, relu, then the direct weight gradient
-  k_pool_back<false><<<blocks((size_t)nb * 128 * 128 * 32), 256, 0, s>>>(V(c->gp0, 32), V(c->g0, 32), nb, 128, 32);
-  k_relu_mask<<<blocks((size_t)nb * 16384 * 32), 256, 0, s>>>(V(c->g0, 32), V(c->a0, 32), (size_t)nb * 16384, 32);
+  // L0: dz formed inside the tiled weight-gradient kernel from gp0 and a0
   {
-    const int mtot = nb * 128 * 128, splits = (mtot + px - 1) / px, np = 32 * 10;
-    k_wgrad_in<<<splits, 320, 0, s>>>(x, V(c->g0, 32), c->part, nb, 128, 32, px);
-    k_sum_splits<<<blocks(np), 256, 0, s>>>(c->part, splits, np, c->part + (size_t)splits * np);
+    const int grid = std::min(nb * (128 / kInRows), kSmallGrid), np = 32 * 10;
+    k_wgrad_in<<<grid, 256, 0, s>>>(x, V(c->a0, 32), V(c->gp0, 32), c->part, nb);
+    k_sum_splits<<<blocks(np), 256, 0, s>>>(c->part, grid, np, c->part + (size_t)grid * np);
     PTY_LAUNCH_CHECK("wgrad_in");
-    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)splits * np, 9, 32, c->g + L[0].woff, c->g + L[0].boff);
+    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)grid * np, 9, 32, c->g + L[0].woff, c->g + L[0].boff);
   }
   PTY_LAUNCH_CHECK("cnn_backward");
 }
@@ -677,10 +852,10 @@ void refresh_bf16(pty_cnn* c) {
 
 double loss_grad(pty_cnn* c, const float* x, const float* t, int nb) {
   const size_t n = (size_t)nb * 64 * 64 * 2;
-  forward(c, x, nb);
+  forward(c, x, nb, true);
   const unsigned nbk = blocks(n);
   k_mse<<<nbk, 256, 0, c->stream>>>(c->y, t, n, c->gy, c->lpart);
-  k_sum_d<<<1, 1, 0, c->stream>>>(c->lpart, nbk, 1.0 / (double)n, c->lsum);
+  k_sum_d<<<1, 256, 0, c->stream>>>(c->lpart, nbk, 1.0 / (double)n, c->lsum);
   PTY_LAUNCH_CHECK("mse");
   backward(c, x, nb);
   double loss = 0.0;
@@ -708,7 +883,7 @@ const float* cnn_forward_batch(pty_cnn* c, const float* x, int nb, hipStream_t s
   hipStream_t keep = c->stream;
   c->stream = s;
   try {
-    forward(c, x, nb);
+    forward(c, x, nb, false);
   } catch (...) {
     c->stream = keep;
     throw;
@@ -784,7 +959,6 @@ pty_status pty_cnn_create(int32_t device, void* stream, int32_t max_batch, uint6
     c->a6 = act(256, 128);
     c->a7 = act(1024, 64);
     c->a8 = act(4096, 32);
-    c->g0 = act(16384, 32);
     c->gp0 = act(4096, 32);
     c->gcat8 = act(4096, 96);
     c->gp1 = act(1024, 32);
@@ -807,6 +981,8 @@ pty_status pty_cnn_create(int32_t device, void* stream, int32_t max_batch, uint6
       const size_t splits = (mtot + 4095) / 4096;
       need = std::max(need, splits * ((size_t)c->L[i].cout * 9 * c->L[i].cin + c->L[i].cout) * 2 + 4096);
     }
+    // the tiled L0 / L9 weight gradients: up to kSmallGrid block partials plus their sums
+    need = std::max(need, (size_t)(kSmallGrid + 1) * 2 * (9 * 32 + 1));
     c->part = c->alloc<float>(need);
     c->part_n = need;
     c->lpart = c->alloc<double>(blocks(B * 4096 * 2) + 16);
@@ -855,7 +1031,7 @@ pty_status pty_cnn_forward(pty_cnn* c, const float* x, int32_t batch, float* y) 
     if (!c || !x || !y) throw std::invalid_argument("pty_cnn_forward: null argument");
     check_batch(c, batch);
     PTY_HIP(hipSetDevice(c->device));
-    forward(c, x, batch);
+    forward(c, x, batch, false);
     PTY_HIP(hipMemcpyAsync(y, c->y, sizeof(float) * batch * 4096 * 2, hipMemcpyDeviceToDevice, c->stream));
     PTY_HIP(hipStreamSynchronize(c->stream));
   });

@@ -178,7 +178,8 @@ void launch_fill_c64(float2* p, size_t n, float2 v, hipStream_t s);
 void launch_poisson(const float* lam, float* out, size_t n, uint64_t seed, hipStream_t s);
 void launch_input_from_amp(const float* amp, int n, int j0, int nb, float* x, float inv, hipStream_t s);
 void launch_targets(const float2* obj, int w, const PosInfo* pos, int j, int n, float* out, hipStream_t s);
-void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int wc, float2* phasor,
+int seed_chain_grid();   // spacing of the chain's coarse sample grid (object pixels)
+void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int hc, int wc, float2* phasor,
                        hipStream_t s);
 void launch_seed_stitch(const float* patches, const int2* place, const float2* phasor, const int* bin_beg,
                         const int* bin_idx, int bins_w, int bins_h, float2* obj, int h, int w, hipStream_t s);

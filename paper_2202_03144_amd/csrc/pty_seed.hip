@@ -111,34 +111,56 @@ __device__ __forceinline__ float2 patch_value(const float* __restrict__ pt, size
 }
 
 // Sequential phase-offset chain over the patches in index order, on the
-// coarse grid of object pixels whose coordinates are multiples of 8 (8 x 8
-// samples per 64 x 64 patch, one per lane of a single wavefront).  For patch
-// j: z = sum over its samples of S * conj(c_j), e_j = z / |z| (1 if z = 0),
-// S += c_j e_j.  Writes e_j to phasor[j].
+// coarse grid G of object pixels whose coordinates are multiples of 16 (4 x 4
+// samples per 64 x 64 patch; lane l of the single wavefront takes sample
+// l mod 16).  For patch j: z = sum over its samples of S * conj(c_j),
+// e_j = z / |z| (1 if z = 0), then S += c_j e_j on those samples.  Writes
+// e_j to phasor[j].  S lives in LDS when it fits (IN_LDS), else in the
+// zero-filled global array S_g.  The next patch's samples are loaded while
+// the current one is processed (they do not depend on S).
+constexpr int kChainGrid = 16;
+template <bool IN_LDS>
 __global__ __launch_bounds__(64) void k_seed_chain(const float* __restrict__ patches, const int2* __restrict__ place,
-                                                   int j_count, float2* S, int wc, float2* __restrict__ phasor) {
+                                                   int j_count, float2* S_g, int hc, int wc,
+                                                   float2* __restrict__ phasor) {
+  extern __shared__ float2 S_l[];
   const int lane = threadIdx.x;
-  const int sy = lane >> 3, sx = lane & 7;
-  for (int j = 0; j < j_count; ++j) {
+  const int sy = (lane >> 2) & 3, sx = lane & 3;
+  float2* S = IN_LDS ? S_l : S_g;
+  if (IN_LDS) {
+    for (int i = lane; i < hc * wc; i += 64) S_l[i] = make_float2(0.f, 0.f);
+    __syncthreads();
+  }
+  auto sample = [&](int j, int& cell) -> float2 {
     const int2 t = place[j];
-    const int gy = (t.x + 7) & ~7, gx = (t.y + 7) & ~7;
-    const int u = gy - t.x + 8 * sy, v = gx - t.y + 8 * sx;
-    const float2 c = patch_value(patches, (size_t)j * 4096 + u * 64 + v);
-    float2* sp = S + (size_t)(gy / 8 + sy) * wc + gx / 8 + sx;
-    const float2 s = *sp;
+    const int gy = (t.x + kChainGrid - 1) & ~(kChainGrid - 1), gx = (t.y + kChainGrid - 1) & ~(kChainGrid - 1);
+    const int u = gy - t.x + kChainGrid * sy, v = gx - t.y + kChainGrid * sx;
+    cell = (gy / kChainGrid + sy) * wc + gx / kChainGrid + sx;
+    return patch_value(patches, (size_t)j * 4096 + u * 64 + v);
+  };
+  int cell_next = 0;
+  float2 c_next = j_count > 0 ? sample(0, cell_next) : make_float2(0.f, 0.f);
+  for (int j = 0; j < j_count; ++j) {
+    const float2 c = c_next;
+    const int cell = cell_next;
+    if (j + 1 < j_count) c_next = sample(j + 1, cell_next);
+    const float2 s = S[cell];
     float zr = s.x * c.x + s.y * c.y, zi = s.y * c.x - s.x * c.y;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      zr += __shfl_xor(zr, off, 64);
-      zi += __shfl_xor(zi, off, 64);
+    for (int off = 8; off > 0; off >>= 1) {
+      zr += __shfl_xor(zr, off, 16);
+      zi += __shfl_xor(zi, off, 16);
     }
     const float zn = sqrtf(zr * zr + zi * zi);
     const float er = zn > 0.f ? zr / zn : 1.f, ei = zn > 0.f ? zi / zn : 0.f;
-    *sp = make_float2(s.x + c.x * er - c.y * ei, s.y + c.x * ei + c.y * er);
+    if (lane < 16) S[cell] = make_float2(s.x + c.x * er - c.y * ei, s.y + c.x * ei + c.y * er);
     if (lane == 0) phasor[j] = make_float2(er, ei);
-    // the next patch may read what this one wrote: let the store complete first
+    // the next patch may read what this one wrote
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (IN_LDS)
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
 }
 
@@ -268,9 +290,15 @@ void launch_targets(const float2* obj, int w, const PosInfo* pos, int j, int n, 
   PTY_LAUNCH_CHECK("targets");
 }
 
-void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int wc, float2* phasor,
+int seed_chain_grid() { return kChainGrid; }
+
+void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int hc, int wc, float2* phasor,
                        hipStream_t s) {
-  k_seed_chain<<<1, 64, 0, s>>>(patches, place, j, S, wc, phasor);
+  const size_t lds = (size_t)hc * wc * sizeof(float2);
+  if (lds <= 128 * 1024)
+    k_seed_chain<true><<<1, 64, lds, s>>>(patches, place, j, S, hc, wc, phasor);
+  else
+    k_seed_chain<false><<<1, 64, 0, s>>>(patches, place, j, S, hc, wc, phasor);
   PTY_LAUNCH_CHECK("seed_chain");
 }
 
