@@ -250,6 +250,112 @@ def learned_leg(args, torch) -> dict:
     }
 
 
+def batch_leg(args, torch) -> dict:
+    """64 LSQML reconstructions of uneven size on one GPU: one after another
+    (eager, one stream) vs together (per-dataset streams, graph-replayed
+    iterations), per window-size class, before and after chunk autotuning."""
+    import ptysynth
+    from paper_2202_03144_amd import Batch, Plan
+
+    rng = np.random.default_rng(2202)
+    specs = []
+    for i in range(args.datasets):
+        n = (64, 128, 256)[i % 3]
+        k = 1 + (i // 3) % 3
+        jmax = 10000 if n < 256 else 3000
+        j = int(round(200 * (jmax / 200) ** rng.uniform()))
+        specs.append((n, k, j))
+    log(f"building {len(specs)} datasets")
+    datasets = []
+    for i, (n, k, j) in enumerate(specs):
+        c = 14.0 * n / 256.0
+        side = ptysynth.spiral_object_side(j, c, n, 3.0)
+        obj = ptysynth.make_object(500 + i, side, side, max(2.0, 4.0 * n / 256.0)).astype(np.complex64)
+        probe = ptysynth.make_probe(500 + i, n, k, 84.0 * n / 256.0, max(1.0, 3.0 * n / 256),
+                                    max(2.0, 12.0 * n / 256), 5.0).astype(np.complex64)
+        pos = ptysynth.spiral_positions(j, c, side / 2.0, n, ptysynth.stream(500 + i, 3))
+        lam = torch.empty((j, n, n), dtype=torch.float32, device="cuda")
+        cnt = torch.empty_like(lam)
+        with Plan(n, k, j, (side, side)) as sim:
+            sim.load_positions(pos)
+            sim.set_object(obj)
+            sim.set_probe(probe)
+            sim.simulate(1e6 if n < 256 else 1e8, out=lam)
+            sim.poisson(lam, cnt, seed=500 + i)
+            probe = sim.probe()
+        del lam
+        datasets.append(dict(n=n, k=k, j=j, shape=(side, side), counts=cnt, pos=pos, probe=probe))
+    params = dict(probe_update_start=0, lsqml_batch=512)
+    iters = args.batch_iters
+
+    def make_plans(streams: bool):
+        plans = []
+        for d in datasets:
+            pl = Plan(d["n"], d["k"], d["j"], d["shape"], stream=torch.cuda.Stream() if streams else None)
+            pl.load_patterns(d["counts"])
+            pl.load_positions(d["pos"])
+            pl.set_object(np.ones(d["shape"], np.complex64))
+            pl.set_probe(d["probe"])
+            plans.append(pl)
+        return plans
+
+    def run_sequential(plans, idx):
+        for i in idx:
+            plans[i].iterate("lsqml", 1, **params)      # warm-up (buffers)
+            plans[i].sync()
+        t = time.perf_counter()
+        for i in idx:
+            plans[i].iterate("lsqml", iters, **params)
+            plans[i].sync()
+        return time.perf_counter() - t
+
+    def run_batched(plans, idx):
+        with Batch([plans[i] for i in idx]) as b:
+            b.iterate("lsqml", 1, graph=True, **params)   # warm-up (buffers, graph capture)
+            b.sync()
+            t = time.perf_counter()
+            b.iterate("lsqml", iters, graph=True, **params)
+            b.sync()
+            return time.perf_counter() - t
+
+    import tempfile
+    cache = os.path.join(tempfile.mkdtemp(prefix="ptymi_tune_"), "tune.json")
+    classes = {f"n{n}": [i for i, d in enumerate(datasets) if d["n"] == n] for n in (64, 128, 256)}
+    classes["all"] = list(range(len(datasets)))
+    out = {}
+    for name, idx in classes.items():
+        pit = sum(datasets[i]["j"] for i in idx) * iters
+        seq_plans = make_plans(False)
+        t_seq = run_sequential(seq_plans, idx)
+        for pl in seq_plans:
+            pl.close()
+        b_plans = make_plans(True)
+        t_b = run_batched(b_plans, idx)
+        t0 = time.perf_counter()
+        chunks = [b_plans[i].autotune("lsqml", cache, **params) for i in idx]
+        tune_s = time.perf_counter() - t0
+        t_bt = run_batched(b_plans, idx)
+        for pl in b_plans:
+            pl.close()
+        out[name] = {"datasets": len(idx), "pattern_iterations": pit,
+                     "sequential_pit_per_s": round(pit / t_seq, 1),
+                     "batched_graph_pit_per_s": round(pit / t_b, 1),
+                     "batched_graph_tuned_pit_per_s": round(pit / t_bt, 1),
+                     "batched_over_sequential": round(t_seq / t_b, 3),
+                     "autotune_s": round(tune_s, 2), "tuned_chunks": sorted(set(chunks))}
+        log(f"{name}: {out[name]}")
+    return {
+        "metric": "pattern-iterations/s (64 uneven LSQML datasets)",
+        "value": out["all"]["batched_graph_tuned_pit_per_s"], "unit": "pattern-iterations/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(datasets)} Fermat-spiral datasets, N in (64, 128, 256), K 1-3, "
+                               "J log-uniform 200-10,000 (200-3,000 at N = 256); LSQML groups of 512, "
+                               f"probe updates on; {iters} timed iterations each",
+                   "sizes": [[d["n"], d["k"], d["j"]] for d in datasets]},
+        "per_class": out,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +372,10 @@ def main() -> int:
     ap.add_argument("--learned-iters", type=int, default=20)
     ap.add_argument("--plain-iters", type=int, default=200)
     ap.add_argument("--nrmse-target", type=float, default=1e-2)
+    ap.add_argument("--batch", action="store_true",
+                    help="instead: 64 uneven LSQML datasets, sequential vs batched with graphs and autotuning")
+    ap.add_argument("--datasets", type=int, default=64)
+    ap.add_argument("--batch-iters", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing was run.",
@@ -280,6 +390,9 @@ def main() -> int:
 
     if args.learned:
         print(json.dumps(learned_leg(args, torch)), flush=True)
+        return 0
+    if args.batch:
+        print(json.dumps(batch_leg(args, torch)), flush=True)
         return 0
     log("building config-2 inputs")
     wl, obj_true, probe, pos, counts = make_inputs(torch)
