@@ -321,7 +321,7 @@ void build_tiles(pty_ctx* c, Group& g) {
     const int y0 = p.iy / kTileH, y1 = std::min(nty - 1, (p.iy + c->N) / kTileH);
     const int x0 = p.ix / kTileW, x1 = std::min(ntx - 1, (p.ix + c->N) / kTileW);
     for (int ty = y0; ty <= y1; ++ty)
-      for (int tx = x0; tx <= x1; ++tx) per[size_t(ty) * ntx + tx].push_back({s, j});
+      for (int tx = x0; tx <= x1; ++tx) per[size_t(ty) * ntx + tx].push_back({s, j, p.iy, p.ix, p.fy, p.fx, 0, 0});
   }
   std::vector<TileEntry> tiles;
   std::vector<PatchRef> refs;

@@ -21,9 +21,13 @@ struct TileEntry {
 };
 
 // An entry of a tile's patch list: the patch's slot in the contribution
-// buffer and its global position index.
-struct PatchRef {
+// buffer, its global position index and a copy of its position (so that a
+// tile walk needs one load per patch).
+struct alignas(16) PatchRef {
   int slot, j;
+  int iy, ix;
+  float fy, fx;
+  int pad0, pad1;
 };
 
 constexpr int kTileH = 16;   // object tile height (rows): one thread walks a column of the tile

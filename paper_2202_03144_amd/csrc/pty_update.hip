@@ -32,16 +32,17 @@ struct Zero<float2> { __device__ static float2 v() { return make_float2(0.f, 0.f
 __device__ __forceinline__ float2 axpy(float a, float2 x, float2 y) { return make_float2(fmaf(a, x.x, y.x), fmaf(a, x.y, y.y)); }
 __device__ __forceinline__ float axpy(float a, float x, float y) { return fmaf(a, x, y); }
 
+// Horizontal combination of patch row u at columns v (weight w0) and v - 1
+// (weight w1).  Branch-free: indices are clamped into the plane and the
+// weights are zero where a tap falls outside it, so the loads of all rows can
+// be issued together.
 template <int N, typename V>
-__device__ __forceinline__ V hrow(const V* __restrict__ src, int u, int v, bool v0ok, bool v1ok, float wx0, float wx1) {
-  V s = Zero<V>::v();
-  if ((unsigned)u < (unsigned)N) {
-    const V* r = src + u * N;
-    if (v0ok) s = axpy(wx0, r[v], s);
-    if (v1ok) s = axpy(wx1, r[v - 1], s);
-  }
-  return s;
+__device__ __forceinline__ V hrow(const V* __restrict__ src, int u, int v0c, int v1c, float w0, float w1) {
+  const float uok = (unsigned)u < (unsigned)N ? 1.f : 0.f;
+  const V* r = src + min(max(u, 0), N - 1) * N;
+  return axpy(w1 * uok, r[v1c], axpy(w0 * uok, r[v0c], Zero<V>::v()));
 }
+
 
 template <int N, ObjOp OP>
 __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
@@ -56,9 +57,11 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
   V acc[TH];
 #pragma unroll
   for (int i = 0; i < TH; ++i) acc[i] = Zero<V>::v();
-  for (int e = te.beg + wv; e < te.end; e += NW) {
-    const PatchRef r = a.refs[e];
-    const PosInfo p = a.pos[r.j];
+  int e = te.beg + wv;
+  PatchRef rn = e < te.end ? a.refs[e] : PatchRef{};
+  for (; e < te.end; e += NW) {
+    const PatchRef r = rn;
+    if (e + NW < te.end) rn = a.refs[e + NW];   // the next patch's entry, while this one is summed
     float wgt = 1.f;
     if constexpr (OP == ObjOp::LsqUpdate) wgt = a.alpha[r.slot].x;
     const V* src;
@@ -66,15 +69,16 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
       src = a.pint;
     else
       src = a.src + (size_t)r.slot * N * N;
-    const int v = X - p.ix;
-    const bool v0ok = (unsigned)v < (unsigned)N, v1ok = (unsigned)(v - 1) < (unsigned)N;
-    const float wx0 = 1.f - p.fx, wx1 = p.fx;
-    const float wy0 = wgt * (1.f - p.fy), wy1 = wgt * p.fy;
-    const int u0 = te.ty - p.iy;
-    V prev = hrow<N, V>(src, u0 - 1, v, v0ok, v1ok, wx0, wx1);
+    const int v = X - r.ix;
+    const float w0 = (unsigned)v < (unsigned)N ? 1.f - r.fx : 0.f;
+    const float w1 = (unsigned)(v - 1) < (unsigned)N ? r.fx : 0.f;
+    const int v0c = min(max(v, 0), N - 1), v1c = min(max(v - 1, 0), N - 1);
+    const float wy0 = wgt * (1.f - r.fy), wy1 = wgt * r.fy;
+    const int u0 = te.ty - r.iy;
+    V prev = hrow<N, V>(src, u0 - 1, v0c, v1c, w0, w1);
 #pragma unroll
     for (int i = 0; i < TH; ++i) {
-      const V cur = hrow<N, V>(src, u0 + i, v, v0ok, v1ok, wx0, wx1);
+      const V cur = hrow<N, V>(src, u0 + i, v0c, v1c, w0, w1);
       acc[i] = axpy(wy0, cur, axpy(wy1, prev, acc[i]));
       prev = cur;
     }
