@@ -79,19 +79,19 @@ def iteration_bytes(plan, n, k, j, h, w, groups):
     return j * nn * (4 + 16 * k) + 64 * h * w * groups
 
 
-# HBM bytes measured by rocprofv3 FETCH_SIZE / WRITE_SIZE for full 42-pattern
+# HBM bytes measured by rocprofv3 FETCH_SIZE / WRITE_SIZE for full 64-pattern
 # launches (profiles/dm_fourier_256x3_hbm_counters.md): read = 2.0 x FETCH_SIZE,
 # written = 1.0 x WRITE_SIZE (factors from a plain copy of known size).  Valid
 # only while the kernel sources hash to COUNTER_SRC_HASH.
-COUNTER_SRC_HASH = "1b8b81f78178bd59"
+COUNTER_SRC_HASH = "65545b66993d25eb"
 COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp"]
 MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns per launch)
-    ("dm", "rows_fwd"): (43668.2, 64512.0, 42),
-    ("dm", "cols"): (43199.3, 64533.0, 42),
-    ("dm", "rows_inv"): (44646.9, 86016.0, 42),
-    ("lsqml", "rows_fwd"): (11221.3, 64512.0, 42),
-    ("lsqml", "cols"): (43199.3, 64533.0, 42),
-    ("lsqml", "rows_inv"): (33116.3, 86016.0, 42),
+    ("dm", "rows_fwd"): (66919.3, 98304.0, 64),
+    ("dm", "cols"): (65738.3, 98336.0, 64),
+    ("dm", "rows_inv"): (66713.2, 131072.0, 64),
+    ("lsqml", "rows_fwd"): (16655.7, 98304.0, 64),
+    ("lsqml", "cols"): (65738.3, 98336.0, 64),
+    ("lsqml", "rows_inv"): (50210.6, 131072.0, 64),
 }
 
 

@@ -375,12 +375,18 @@ void ensure_lsq_groups(pty_ctx* c, int batch) {
   c->groups_batch = batch;
 }
 
+// Patterns per Fourier-pass launch: as many as a 96 MB scratch budget holds
+// (inside the 256 MB Infinity Cache), rounded down to a whole number of block
+// waves over the 256 compute units (a ragged last wave of blocks left the
+// passes ~15% slower at 256^2).  pty_autotune can replace it.
 int chunk_patterns(const pty_ctx* c, const pty_iter_params& p) {
   if (p.chunk > 0) return p.chunk;
   if (c->tuned_chunk > 0) return c->tuned_chunk;
   const size_t per = size_t(c->K) * c->N * c->N * sizeof(float2);
-  const size_t budget = size_t(64) << 20;  // stays inside the 256 MB Infinity Cache
-  return (int)std::max<size_t>(1, budget / per);
+  const size_t budget = size_t(96) << 20;
+  const int fit = (int)std::max<size_t>(1, budget / per);
+  const int wave = std::max(1, 256 / row_blocks(c->N));   // patterns per 256 blocks
+  return fit >= wave ? fit / wave * wave : fit;
 }
 
 constexpr int kProbeSlice = 32;
