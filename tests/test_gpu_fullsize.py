@@ -1,0 +1,100 @@
+"""Parity at the production shape, in the launch configuration the benchmark
+times (default Fourier chunk, LSQML groups of 500, probe updates on):
+256 x 256 probe with 3 modes, 2,500 jittered Fermat-spiral positions,
+1700 x 1700 object, Poisson counts at 1e8 photons.
+
+* one DM and one LSQML iteration from an identical state against the FP64
+  oracle's iteration over all 2,500 positions (object, probe, E, LSQML step
+  lengths, sampled DM exit waves), phase-aligned relative L2 <= 1e-4;
+* the final NRMSE after 100 iterations (probe updates from iteration 10)
+  within 2% of the oracle's, read from tests/golden/config2_nrmse.json, which
+  tests/golden/make_config2_nrmse.py writes by calling only the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import ptysynth
+from _cases import c64, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_nrmse.json")
+
+
+@pytest.fixture(scope="module")
+def prod():
+    wl = ptysynth.workload(2)
+    obj = wl.obj()
+    pos = wl.positions()
+    expected, probe = oracle.simulate(obj, wl.probe(), pos, wl.photons)
+    counts = ptysynth.poisson_counts(expected, wl.noise_rng())
+    del expected
+    amp = oracle.amplitude(counts.astype(np.float64))
+    o0 = np.ones(obj.shape, np.complex64)
+    return wl, obj, c64(probe), pos, counts, amp, o0
+
+
+def _plan(prod):
+    from paper_2202_03144_amd import Plan
+    wl, obj, probe, pos, counts, amp, o0 = prod
+    pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w))
+    pl.load_patterns(counts)
+    pl.load_positions(pos)
+    pl.set_object(o0)
+    pl.set_probe(probe)
+    return pl
+
+
+def test_dm_one_iteration_full_size(prod):
+    wl, obj, probe, pos, counts, amp, o0 = prod
+    pl = _plan(prod)
+    pl.iterate("dm", 1, probe_update_start=0)
+    go, gp, ge = pl.object(), pl.probe(), pl.errors()
+    psi = pl.exit_waves()
+    pl.close()
+    o_in, p_in = o0.astype(np.complex128), probe.astype(np.complex128)
+    ro, rp, rpsi, re = oracle.dm(o_in, p_in, oracle.dm_init(o_in, p_in, pos), amp, pos, 1, start=0)
+    assert rel(go, ro) <= TOL
+    assert rel(gp, rp) <= TOL
+    assert abs(ge[0] - re[0]) <= TOL * re[0]
+    for j in (0, 777, 1500, 2499):
+        assert rel(psi[j], rpsi[j]) <= TOL, j
+
+
+def test_lsqml_one_iteration_full_size(prod):
+    wl, obj, probe, pos, counts, amp, o0 = prod
+    pl = _plan(prod)
+    pl.iterate("lsqml", 1, probe_update_start=0, lsqml_batch=500)
+    go, gp, ge, ga = pl.object(), pl.probe(), pl.errors(), pl.lsqml_steps()
+    pl.close()
+    ro, rp, re, ra = oracle.lsqml(o0.astype(np.complex128), probe.astype(np.complex128), amp, pos, 1,
+                                  start=0, batch=500, return_alpha=True)
+    assert rel(go, ro) <= TOL
+    assert rel(gp, rp) <= TOL
+    assert abs(ge[0] - re[0]) <= TOL * re[0]
+    ra = np.asarray(ra, np.float64).reshape(ga.shape)
+    assert np.linalg.norm(ga - ra) <= TOL * np.linalg.norm(ra)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle reference run not present")
+@pytest.mark.parametrize("algo", ["dm", "lsqml"])
+def test_final_nrmse_within_2pct_full_size(prod, algo):
+    wl, obj, probe, pos, counts, amp, o0 = prod
+    golden = json.load(open(GOLDEN))
+    ref = golden[algo]["nrmse"]
+    pl = _plan(prod)
+    pl.set_truth(c64(obj), 0.3)
+    start = pl.nrmse()
+    assert abs(start - golden["nrmse_start"]) <= 1e-5 * golden["nrmse_start"]
+    params = dict(probe_update_start=10)
+    if algo == "lsqml":
+        params["lsqml_batch"] = 500
+    pl.iterate(algo, len(ref), **params)
+    hist = pl.nrmse_history()
+    pl.close()
+    print(algo, "gpu", hist[[0, 9, 49, -1]], "oracle", [ref[i] for i in (0, 9, 49, -1)])
+    assert abs(hist[-1] - ref[-1]) <= 0.02 * ref[-1]
