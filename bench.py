@@ -356,6 +356,77 @@ def batch_leg(args, torch) -> dict:
     }
 
 
+def tiny_leg(args, torch) -> dict:
+    """64 x 64 probe, 1 mode, 10 x 10 raster (100 positions), 160 x 160 object,
+    Poisson 1e6: ePIE, DM and LSQML, 50 iterations each (probe updates from
+    10), eager and (DM, LSQML) graph-replayed; the oracle timed beside."""
+    import ptysynth
+    import oracle
+    from paper_2202_03144_amd import Plan
+
+    wl = ptysynth.workload(1)
+    obj = wl.obj()
+    pos = wl.positions()
+    expected, probe = oracle.simulate(obj, wl.probe(), pos, wl.photons)
+    counts = ptysynth.poisson_counts(expected, wl.noise_rng())
+    probe = probe.astype(np.complex64)
+    iters = 50
+    res = {}
+
+    def run(algo, graph):
+        pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w))
+        pl.load_patterns(counts)
+        pl.load_positions(pos)
+        pl.set_object(np.ones((wl.h, wl.w), np.complex64))
+        pl.set_probe(probe)
+        pl.iterate(algo, 1, graph=graph, probe_update_start=10)    # warm-up (buffers, capture)
+        pl.sync()
+        pl.set_object(np.ones((wl.h, wl.w), np.complex64))
+        pl.set_probe(probe)
+        t = time.perf_counter()
+        pl.iterate(algo, iters, graph=graph, probe_update_start=10)
+        pl.sync()
+        dt = time.perf_counter() - t
+        pl.close()
+        return dt
+
+    for algo in ("epie", "dm", "lsqml"):
+        dt = run(algo, False)
+        res[algo] = {"eager_pit_per_s": round(wl.j * iters / dt, 1), "eager_us_per_iter": round(dt / iters * 1e6, 1)}
+        if algo != "epie":
+            dg = run(algo, True)
+            res[algo].update({"graph_pit_per_s": round(wl.j * iters / dg, 1),
+                              "graph_us_per_iter": round(dg / iters * 1e6, 1)})
+        log(f"{algo}: {res[algo]}")
+    # the oracle, same inputs, 50 iterations each
+    amp = oracle.amplitude(counts.astype(np.float64))
+    o0 = np.ones((wl.h, wl.w), np.complex128)
+    p0 = probe.astype(np.complex128)
+    cpu = {}
+    t = time.perf_counter()
+    oracle.epie(o0, p0, amp, pos, iters, start=10)
+    cpu["epie_s"] = round(time.perf_counter() - t, 2)
+    t = time.perf_counter()
+    oracle.dm(o0, p0, oracle.dm_init(o0, p0, pos), amp, pos, iters, start=10)
+    cpu["dm_s"] = round(time.perf_counter() - t, 2)
+    t = time.perf_counter()
+    oracle.lsqml(o0, p0, amp, pos, iters, start=10)
+    cpu["lsqml_s"] = round(time.perf_counter() - t, 2)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {
+        "metric": "pattern-iterations/s (64², 1 mode, 100 positions)",
+        "value": res["dm"]["graph_pit_per_s"], "unit": "pattern-iterations/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64x64 probe, 1 mode, 10x10 raster (8 px step), 160x160 object, Poisson 1e6; "
+                               "50 iterations, probe updates from 10", "n": 64, "positions": 100},
+        "algorithms": res,
+        "cpu_baseline": {"kind": "oracle", "cores": cores, "seconds_for_50_iterations": cpu,
+                         "epie_pit_per_s": round(wl.j * iters / cpu["epie_s"], 1),
+                         "dm_pit_per_s": round(wl.j * iters / cpu["dm_s"], 1),
+                         "lsqml_pit_per_s": round(wl.j * iters / cpu["lsqml_s"], 1)},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +446,8 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true",
                     help="instead: 64 uneven LSQML datasets, sequential vs batched with graphs and autotuning")
     ap.add_argument("--datasets", type=int, default=64)
+    ap.add_argument("--tiny", action="store_true",
+                    help="instead: the 64x64 one-mode raster workload, ePIE / DM / LSQML eager and graphed")
     ap.add_argument("--batch-iters", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -393,6 +466,9 @@ def main() -> int:
         return 0
     if args.batch:
         print(json.dumps(batch_leg(args, torch)), flush=True)
+        return 0
+    if args.tiny:
+        print(json.dumps(tiny_leg(args, torch)), flush=True)
         return 0
     log("building config-2 inputs")
     wl, obj_true, probe, pos, counts = make_inputs(torch)

@@ -102,6 +102,7 @@ struct pty_ctx {
   double* lsq_part = nullptr;      size_t lsq_part_n = 0;
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
+  int* epie_order = nullptr;       // device copy of a shuffled ePIE order
 
   // device-side iteration counter (error / NRMSE history slot of the running
   // iteration), so that one captured iteration can be replayed
@@ -740,6 +741,39 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       }
     }
     const bool pon = probe_on(p, t);
+    if (epie_fused_supported(c->N, c->K)) {
+      // one workgroup runs the whole iteration; positions in `order`
+      const int* d_order = c->all.d_jl;   // identity
+      if (p.order_seed != 0) {
+        c->ensure_once(c->epie_order, size_t(c->J));
+        PTY_HIP(hipMemcpyAsync(c->epie_order, order.data(), sizeof(int) * c->J, hipMemcpyHostToDevice,
+                               c->stream));
+        d_order = c->epie_order;
+      }
+      EpieRunArgs r{};
+      r.n = c->N;
+      r.k = c->K;
+      r.obj = c->obj;
+      r.h = c->H;
+      r.w = c->W;
+      r.probe0 = c->probe;
+      r.probe1 = c->probe_alt;
+      r.amp = c->amp;
+      r.pos = c->pos;
+      r.order = d_order;
+      r.count = c->J;
+      r.errp = c->errp;
+      r.bpp = col_blocks(c->N);
+      r.tw = reinterpret_cast<const float*>(c->tw);
+      r.alpha = p.alpha;
+      r.beta = p.beta;
+      r.probe_on = pon ? 1 : 0;
+      r.stream = c->stream;
+      timed(c, kEpie, [&] { launch_epie_fused(r); });
+      if (c->J % 2 == 1) std::swap(c->probe, c->probe_alt);
+      end_iteration(c, t);
+      continue;
+    }
     for (int j : order) {
       a.jl_off = j;
       a.obj = c->obj;

@@ -147,6 +147,31 @@ struct EpieArgs {
 };
 void launch_epie_update(const EpieArgs& a);
 
+// A whole ePIE iteration in one workgroup (small windows): for each position
+// in `order`, the exit waves, both 2-D transforms, the projection with its
+// error partials and both updates stay in LDS; positions run in sequence
+// inside the kernel.  The probe alternates between probe0 and probe1 (after an
+// odd number of positions the updated probe is in probe1).
+struct EpieRunArgs {
+  int n, k;
+  float2* obj;
+  int h, w;
+  float2* probe0;
+  float2* probe1;
+  const float* amp;
+  const PosInfo* pos;
+  const int* order;
+  int count;
+  double* errp;
+  int bpp;                // column blocks per pattern of the error partials
+  const float* tw;
+  float alpha, beta;
+  int probe_on;
+  hipStream_t stream;
+};
+bool epie_fused_supported(int n, int k);
+void launch_epie_fused(const EpieRunArgs& a);
+
 struct DmInitArgs {
   int n, k;
   const float2* obj;

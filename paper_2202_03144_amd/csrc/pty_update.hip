@@ -540,6 +540,216 @@ inline unsigned grid_for(size_t n, unsigned bs, unsigned cap = 65535u * 4) {
   return (unsigned)(g > cap ? cap : g);
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused ePIE iteration for small windows (one workgroup, positions in order)
+// ---------------------------------------------------------------------------
+constexpr int kEpieThreads = 512;
+
+template <int N>
+struct EpieFusedGeo {
+  static constexpr int R = FftShape<N>::R, T = FftShape<N>::T;
+  static constexpr int P = N + 1;                      // padded row (LDS banks)
+  static constexpr int LINES = kEpieThreads / T;       // lines transformed at once
+  static constexpr int W = LineLds<N>::words;
+  static constexpr int F = N + 1;                      // object footprint side
+  template <int K>
+  static constexpr size_t base_bytes() {
+    return sizeof(float2) * ((size_t)K * N * P + LINES * W + N + F * F);
+  }
+  // the probe stays in LDS too when it fits
+  template <int K>
+  static constexpr bool probe_lds() { return base_bytes<K>() + sizeof(float2) * K * N * N <= 150 * 1024; }
+  template <int K>
+  static constexpr size_t lds_bytes() { return base_bytes<K>() + (probe_lds<K>() ? sizeof(float2) * K * N * N : 0); }
+};
+
+// All K x N rows (ROWS) or columns of the LDS field Z transformed in place.
+template <int N, int K, bool INV, bool ROWS>
+__device__ __forceinline__ void epie_fft_pass(float2* Z, float2* xb, const float2* tw) {
+  using G = EpieFusedGeo<N>;
+  constexpr int R = G::R, T = G::T, P = G::P;
+  const int li = threadIdx.x / T, t = threadIdx.x % T;
+  float2* buf = xb + li * G::W;
+  for (int l0 = 0; l0 < K * N; l0 += G::LINES) {
+    const int l = l0 + li;
+    if (l < K * N) {
+      const int k = l / N, r = l % N;
+      float2 v[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = ROWS ? Z[(k * N + r) * P + t + T * m] : Z[(k * N + t + T * m) * P + r];
+      line_fft<N, INV>(v, buf, tw, t);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        if (ROWS) Z[(k * N + r) * P + t + T * m] = v[m];
+        else Z[(k * N + t + T * m) * P + r] = v[m];
+      }
+    }
+  }
+}
+
+template <int N, int K>
+__global__ __launch_bounds__(kEpieThreads) void k_epie_fused(EpieRunArgs a) {
+  using G = EpieFusedGeo<N>;
+  constexpr int NN = N * N, P = G::P, F = G::F;
+  constexpr bool PL = G::template probe_lds<K>();
+  constexpr int QP = (NN + kEpieThreads - 1) / kEpieThreads;   // pixels per thread
+  extern __shared__ float2 lds[];
+  float2* Z = lds;                                   // K x N x P: exit waves / far field / chi
+  float2* xb = Z + (size_t)K * N * P;                // line-transform exchange
+  float2* tw_s = xb + G::LINES * G::W;               // W_N table
+  float2* foot = tw_s + N;                           // F x F pre-update object footprint
+  float2* pl = foot + F * F;                         // K x N x N probe (when PL)
+  __shared__ double redd[kEpieThreads / 64];
+  __shared__ float redf[kEpieThreads / 64];
+  for (int i = threadIdx.x; i < N; i += kEpieThreads) tw_s[i] = reinterpret_cast<const float2*>(a.tw)[i];
+  float2* probe = a.probe0;
+  float2* probe_nxt = a.probe1;
+  if constexpr (PL) {
+    for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) pl[i] = a.probe0[i];
+  }
+  // the next position's moduli, fetched while the current one is processed
+  float amp_n[QP];
+  if (a.count > 0) {
+    const int j0 = a.order[0];
+#pragma unroll
+    for (int r = 0; r < QP; ++r) {
+      const int q = threadIdx.x + r * kEpieThreads;
+      amp_n[r] = q < NN ? a.amp[(size_t)j0 * NN + q] : 0.f;
+    }
+  }
+  __syncthreads();
+  // the transforms are unscaled: the unitary far field is Z / N, and the
+  // unitary inverse contributes another 1 / N^2, folded into the projection
+  constexpr float sc = 1.0f / N, sc2 = 1.0f / (float(N) * float(N));
+  for (int n = 0; n < a.count; ++n) {
+    const int j = a.order[n];
+    const PosInfo p = a.pos[j];
+    float amp_c[QP];
+#pragma unroll
+    for (int r = 0; r < QP; ++r) amp_c[r] = amp_n[r];
+    if (n + 1 < a.count) {
+      const int jn = a.order[n + 1];
+#pragma unroll
+      for (int r = 0; r < QP; ++r) {
+        const int q = threadIdx.x + r * kEpieThreads;
+        amp_n[r] = q < NN ? a.amp[(size_t)jn * NN + q] : 0.f;
+      }
+    }
+    // pre-update footprint (reads clamped to the object, as the bilinear gather does)
+    for (int e = threadIdx.x; e < F * F; e += kEpieThreads) {
+      const int u = e / F, v = e % F;
+      foot[e] = a.obj[(size_t)min(p.iy + u, a.h - 1) * a.w + min(p.ix + v, a.w - 1)];
+    }
+    __syncthreads();
+    const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
+    auto patch = [&](int u, int v) -> float2 {
+      const float2 a0 = foot[u * F + v], b0 = foot[u * F + v + 1];
+      const float2 c0 = foot[(u + 1) * F + v], d0 = foot[(u + 1) * F + v + 1];
+      return make_float2(wy0 * (wx0 * a0.x + wx1 * b0.x) + wy1 * (wx0 * c0.x + wx1 * d0.x),
+                         wy0 * (wx0 * a0.y + wx1 * b0.y) + wy1 * (wx0 * c0.y + wx1 * d0.y));
+    };
+    const float2* pr = PL ? pl : probe;
+    // exit waves P_k S_j O
+    for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) {
+      const int k = i / NN, q = i % NN, u = q / N, v = q % N;
+      Z[(k * N + u) * P + v] = cmul(pr[i], patch(u, v));
+    }
+    __syncthreads();
+    epie_fft_pass<N, K, false, true>(Z, xb, tw_s);
+    __syncthreads();
+    epie_fft_pass<N, K, false, false>(Z, xb, tw_s);
+    __syncthreads();
+    // modulus projection and the amplitude-error partials of this position
+    float en = 0.f, ed = 0.f;
+#pragma unroll
+    for (int r = 0; r < QP; ++r) {
+      const int q = threadIdx.x + r * kEpieThreads;
+      if (q >= NN) continue;
+      const int u = q / N, v = q % N;
+      float iraw = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) iraw += cabs2(Z[(k * N + u) * P + v]);
+      const float mod = sqrtf(iraw) * sc;
+      const float am = amp_c[r];
+      const float f = (am / fmaxf(mod, 1e-6f) - 1.f) * sc2;
+      en += (mod - am) * (mod - am);
+      ed += am * am;
+#pragma unroll
+      for (int k = 0; k < K; ++k) Z[(k * N + u) * P + v] = f * Z[(k * N + u) * P + v];
+    }
+    const double s0 = block_sum<kEpieThreads>((double)en, redd);
+    const double s1 = block_sum<kEpieThreads>((double)ed, redd);
+    if (threadIdx.x == 0) {
+      double* e = a.errp + (size_t)j * a.bpp * 2;
+      e[0] = s0;
+      e[1] = s1;
+      for (int cb = 1; cb < a.bpp; ++cb) e[2 * cb] = e[2 * cb + 1] = 0.0;
+    }
+    __syncthreads();
+    epie_fft_pass<N, K, true, true>(Z, xb, tw_s);
+    __syncthreads();
+    epie_fft_pass<N, K, true, false>(Z, xb, tw_s);
+    __syncthreads();
+    // Z now holds chi_k.  Step normalisers from the pre-update probe and patch.
+    float pm = 0.f, om = 0.f;
+    for (int q = threadIdx.x; q < NN; q += kEpieThreads) {
+      float sp = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) sp += cabs2(pr[(size_t)k * NN + q]);
+      pm = fmaxf(pm, sp);
+      om = fmaxf(om, cabs2(patch(q / N, q % N)));
+    }
+    const float pmax = block_max_all<kEpieThreads>(pm, redf);
+    const float omax = block_max_all<kEpieThreads>(om, redf);
+    // object update over the (N+1)^2 footprint with the pre-update probe
+    if (pmax > 0.f) {
+      const float as = a.alpha / pmax;
+      for (int e = threadIdx.x; e < F * F; e += kEpieThreads) {
+        const int u = e / F, v = e % F;
+        const int Y = p.iy + u, X = p.ix + v;
+        if (Y >= a.h || X >= a.w) continue;
+        float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int tap = 0; tap < 4; ++tap) {
+          const int uu = u - (tap >> 1), vv = v - (tap & 1);
+          if ((unsigned)uu >= (unsigned)N || (unsigned)vv >= (unsigned)N) continue;
+          const float wt = ((tap >> 1) ? wy1 : wy0) * ((tap & 1) ? wx1 : wx0);
+          float2 tv = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int k = 0; k < K; ++k) tv = tv + cconjmul(pr[(size_t)k * NN + uu * N + vv], Z[(k * N + uu) * P + vv]);
+          s = s + wt * tv;
+        }
+        a.obj[(size_t)Y * a.w + X] = foot[e] + as * s;
+      }
+    }
+    // probe update with the pre-update patch (after every read of the old probe)
+    const float bs = (a.probe_on && omax > 0.f) ? a.beta / omax : 0.f;
+    if constexpr (PL) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) {
+        const int k = i / NN, q = i % NN, u = q / N, v = q % N;
+        pl[i] = pl[i] + bs * cconjmul(patch(u, v), Z[(k * N + u) * P + v]);
+      }
+    } else {
+      for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) {
+        const int k = i / NN, q = i % NN, u = q / N, v = q % N;
+        probe_nxt[i] = probe[i] + bs * cconjmul(patch(u, v), Z[(k * N + u) * P + v]);
+      }
+      float2* tmp = probe;
+      probe = probe_nxt;
+      probe_nxt = tmp;
+    }
+    // the next position reads the updated object and probe
+    __syncthreads();
+  }
+  if constexpr (PL) {
+    // leave the probe where the alternating scheme would: probe1 after an odd count
+    float2* dst = (a.count % 2 == 1) ? a.probe1 : a.probe0;
+    for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) dst[i] = pl[i];
+  }
+}
+
 }  // namespace
 
 void launch_obj_gather(const ObjGatherArgs& a, ObjOp op) {
@@ -608,6 +818,30 @@ void launch_lsq_steps(const LsqStepArgs& a) {
   PTY_LAUNCH_CHECK("lsq_sums");
   k_lsq_solve<<<(a.count + 127) / 128, 128, 0, a.stream>>>(a, nrb);
   PTY_LAUNCH_CHECK("lsq_solve");
+}
+
+bool epie_fused_supported(int n, int k) {
+  if (n == 32) return k >= 1 && k <= 4;
+  if (n == 64) return k >= 1 && k <= 2;
+  return false;
+}
+
+void launch_epie_fused(const EpieRunArgs& a) {
+  if (a.count <= 0) return;
+  if (!epie_fused_supported(a.n, a.k)) throw std::invalid_argument("fused ePIE: unsupported window");
+  auto go = [&](auto nc, auto kc) {
+    constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
+    if constexpr ((N == 32 && K <= 4) || (N == 64 && K <= 2)) {
+      constexpr size_t lds = EpieFusedGeo<N>::template lds_bytes<K>();
+      static_assert(lds <= 150 * 1024, "fused ePIE field must fit in LDS");
+      PTY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_epie_fused<N, K>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      k_epie_fused<N, K><<<1, kEpieThreads, lds, a.stream>>>(a);
+    }
+  };
+  if (a.n == 32) dispatch_k<32>(a.k, go);
+  else dispatch_k<64>(a.k, go);
+  PTY_LAUNCH_CHECK("epie_fused");
 }
 
 void launch_epie_update(const EpieArgs& a) {
