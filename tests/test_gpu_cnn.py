@@ -288,3 +288,49 @@ def test_nrmse_and_history():
     assert len(hist) == 3 and hist[-1] == v3
     assert abs(v3 - oracle.nrmse(last.astype(np.complex128), truth, mask)) <= 1e-5 * v3
     assert abs(v_all - oracle.nrmse(last.astype(np.complex128), truth, np.ones(obj.shape, bool))) <= 1e-5 * v_all
+
+
+def test_full_size_inference_and_stitch():
+    """The evaluation shape of the learned seed: 4,096 patterns in one batch
+    (outputs sampled against the FP64 network) and 4,096 seeded patches
+    stitched into a 1200 x 1200 object on the 4,096-point spiral (compared
+    whole against the oracle's stitch)."""
+    import torch
+    from paper_2202_03144_amd import Plan
+    from paper_2202_03144_amd.cnn import Net
+    wl = ptysynth.workload(4)
+    b = wl.j
+    flat = _params(31)
+    rng = np.random.default_rng(32)
+    x = rng.uniform(0.0, 0.6, (b, 128, 128)).astype(np.float32)
+    with Net(b, seed=0) as net:
+        net.set_params(flat)
+        xt = torch.from_numpy(x).cuda()
+        y = torch.empty((b, 64, 64, 2), dtype=torch.float32, device="cuda")
+        net.forward(xt, y)
+        yh = y.cpu().numpy()
+    samples = [0, 1777, b - 1]
+    ref, _ = unet.forward(_as_kernel_sees(flat), x[samples].astype(np.float64)[..., None])
+    err = _rel(yh[samples], ref)
+    print("full-batch forward rel err", err)
+    assert err <= TOL_Y
+    # full-size stitch of seeded patches cut from an object, with random phase
+    # offsets and 5% noise
+    pos = wl.positions()
+    obj = ptysynth.make_object(78, wl.h, wl.w, wl.sigma_o)
+    t = oseed.placements(pos)
+    pt = np.empty((b, 64, 64, 2), np.float32)
+    for i, (ty, tx) in enumerate(t):
+        o = obj[ty:ty + 64, tx:tx + 64] * np.exp(1j * rng.uniform(-np.pi, np.pi))
+        o = o * (1 + 0.05 * rng.standard_normal(o.shape))
+        pt[i, ..., 0] = np.abs(o)
+        pt[i, ..., 1] = np.angle(o)
+    with Plan(128, 1, b, (wl.h, wl.w)) as pl:
+        pl.load_positions(pos)
+        out = torch.empty((wl.h, wl.w), dtype=torch.complex64, device="cuda")
+        pl.stitch(torch.from_numpy(pt).cuda(), out)
+        got = out.cpu().numpy()
+    ref_o, _ = oseed.stitch(pt.astype(np.float64), pos, wl.h, wl.w)
+    err_o = float(np.linalg.norm(got - ref_o) / np.linalg.norm(ref_o))
+    print("full-size stitch rel err", err_o)
+    assert err_o <= 1e-4
