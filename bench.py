@@ -188,6 +188,19 @@ def learned_leg(args, torch) -> dict:
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del objs
+    # one full-batch inference, timed alone: the network's MFMA roofline
+    xin = torch.rand((args.infer_batch, 128, 128), device="cuda") * 0.6
+    yout = torch.empty((args.infer_batch, 64, 64, 2), dtype=torch.float32, device="cuda")
+    net.forward(xin, yout)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(3):
+        net.forward(xin, yout)
+    ev1.record(stream)
+    stream.synchronize()
+    infer_ms = ev0.elapsed_time(ev1) / 3
+    infer_flop = 0.9576e9 * args.infer_batch       # 2 x MACs of the ten convolutions per pattern
+    del xin, yout
 
     def arm(learned: bool, max_iter: int):
         pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
@@ -243,6 +256,10 @@ def learned_leg(args, torch) -> dict:
                                "1200x1200 object, Poisson 1e8 photons; LSQML groups of 512",
                    "n": wl.n, "positions": wl.j, "object": [wl.h, wl.w]},
         "learned": learned, "plain": plain, "plain_over_learned": speed,
+        "roofline": {"bound": "mfma", "kernel": f"network forward, batch {args.infer_batch}",
+                     "achieved": round(infer_flop / (infer_ms * 1e-3) / 1e12, 1), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(infer_flop / (infer_ms * 1e-3) / 1e12 / 2500.0, 4),
+                     "traffic": None, "ms": round(infer_ms, 3)},
         "training": {"patterns": args.train_steps * args.train_batch, "steps": args.train_steps,
                      "batch": args.train_batch, "seconds": round(train_s, 2),
                      "loss_first": round(float(np.mean(losses[:10])), 5),
@@ -427,6 +444,81 @@ def tiny_leg(args, torch) -> dict:
     }
 
 
+def adjoint_leg(args, torch) -> dict:
+    """Poisson-NLL forward and backward (object, probe and position
+    gradients) on the 128 x 128, 4-mode, 1,000-position workload."""
+    import ptysynth
+    import oracle
+    from paper_2202_03144_amd import Plan
+
+    wl = ptysynth.workload(3)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    obj_true = wl.obj().astype(np.complex64)
+    pos = wl.positions()
+    lam = torch.empty((wl.j, wl.n, wl.n), dtype=torch.float32, device="cuda")
+    counts = torch.empty_like(lam)
+    with Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream) as sim:
+        sim.load_positions(pos)
+        sim.set_object(obj_true)
+        sim.set_probe(wl.probe().astype(np.complex64))
+        sim.simulate(wl.photons, out=lam)
+        sim.poisson(lam, counts, seed=3)
+        probe = sim.probe()
+    del lam
+    rng = np.random.default_rng(3)
+    o = torch.from_numpy((obj_true * (1 + 0.02 * rng.standard_normal(obj_true.shape))).astype(np.complex64)).cuda()
+    p = torch.from_numpy(probe).cuda()
+    g_o, g_p = torch.empty_like(o), torch.empty_like(p)
+    g_r = torch.empty((wl.j, 2), dtype=torch.float32, device="cuda")
+    pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
+    pl.load_patterns(counts)
+    pl.load_positions(pos)
+    for _ in range(2):
+        pl.nll_forward(o, p)
+        pl.nll_backward(o, p, 1.0, g_o, g_p, g_r)
+    reps = 10
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        pl.nll_forward(o, p)
+    e1.record(stream)
+    for _ in range(reps):
+        pl.nll_backward(o, p, 1.0, g_o, g_p, g_r)
+    e2.record(stream)
+    stream.synchronize()
+    ms_f = e0.elapsed_time(e1) / reps
+    ms_b = e1.elapsed_time(e2) / reps
+    pl.close()
+    n2 = wl.n * wl.n
+    fft_flop = 5.0 * n2 * np.log2(n2)               # one 2-D transform
+    flop_f = wl.j * wl.k * fft_flop                   # K forward transforms per pattern
+    flop_b = wl.j * 2 * wl.k * fft_flop               # recomputed forward + inverse
+    achieved = flop_b / (ms_b * 1e-3) / 1e12
+    # the oracle on a bounded sample of the same workload
+    ns = args.adjoint_cpu_sample
+    cnt_h = counts[:ns].cpu().numpy().astype(np.float64)
+    t = time.perf_counter()
+    oracle.nll_grad(o.cpu().numpy().astype(np.complex128), probe.astype(np.complex128), pos[:ns], cnt_h)
+    cpu_s = time.perf_counter() - t
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {
+        "metric": "Poisson-NLL forward+backward (µs per pattern)",
+        "value": round((ms_f + ms_b) * 1e3 / wl.j, 3), "unit": "us/pattern", "n_gpus": 1,
+        "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "128x128 probe, 4 modes, 1,000 jittered spiral positions (c 7), 600x600 object, "
+                               "Poisson 1e6; exit waves recomputed in the backward pass",
+                   "n": wl.n, "modes": wl.k, "positions": wl.j},
+        "forward_ms": round(ms_f, 4), "backward_ms": round(ms_b, 4),
+        "roofline": {"bound": "alu", "kernel": "backward (all launches)", "achieved": round(achieved, 2),
+                     "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4), "traffic": None,
+                     "algorithmic_flop_per_pattern": 2 * wl.k * fft_flop},
+        "cpu_baseline": {"value": round((cpu_s / ns) * 1e6, 1), "unit": "us/pattern", "cores": cores,
+                         "kind": "oracle", "sample": f"first {ns} of the 1,000 positions, forward + gradients in FP64"},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,6 +538,9 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true",
                     help="instead: 64 uneven LSQML datasets, sequential vs batched with graphs and autotuning")
     ap.add_argument("--datasets", type=int, default=64)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead: Poisson-NLL forward and backward on the 128x128x4, 1,000-position workload")
+    ap.add_argument("--adjoint-cpu-sample", type=int, default=100)
     ap.add_argument("--tiny", action="store_true",
                     help="instead: the 64x64 one-mode raster workload, ePIE / DM / LSQML eager and graphed")
     ap.add_argument("--batch-iters", type=int, default=5)
@@ -466,6 +561,9 @@ def main() -> int:
         return 0
     if args.batch:
         print(json.dumps(batch_leg(args, torch)), flush=True)
+        return 0
+    if args.adjoint:
+        print(json.dumps(adjoint_leg(args, torch)), flush=True)
         return 0
     if args.tiny:
         print(json.dumps(tiny_leg(args, torch)), flush=True)
