@@ -65,82 +65,122 @@ struct View {
 };
 
 // ---------------------------------------------------------------------------
-// Implicit-GEMM convolution on MFMA.  out[m][n] = act(bias[n] +
-// sum_{tap, c} in[m + tap][c] * w[n][tap][c]), m = (b, y, x) pixels of an
-// S x S image, n output channels.  Block: 4 wavefronts; each wavefront owns
-// MT x 16 pixels and BN output channels (BN / 16 tiles), so every 16-byte A
-// fragment feeds BN / 16 MFMAs and every B fragment MT of them.
+// Convolutions whose channel counts are multiples of 32 are implicit GEMMs on
+// MFMA: out[m][n] = act(bias[n] + sum_{tap, c} in[m + tap][c] * w[n][tap][c]),
+// m = (b, y, x) pixels of an S x S image, n output channels, reduction over
+// taps x input channels, float32 accumulation.
 // ---------------------------------------------------------------------------
-template <int BN, int MT, bool RELU, bool BIAS>
-__global__ __launch_bounds__(256) void k_conv_mfma(View in, const bf16* __restrict__ w,
+// LDS-tiled implicit GEMM.  Block = 4 wavefronts on a BM-pixel x BN-channel
+// tile, each wavefront on 64 pixels x 32 channels (4 x 2 MFMA tiles); the
+// reduction runs over (tap, 32-channel block) steps; each step's A (BM x 32)
+// and B (BN x 32) bf16 tiles are fetched from global memory into registers
+// while the MFMAs of the previous step run from LDS (two LDS buffers).  The
+// epilogue goes through LDS so that every pixel's channels are written as
+// 16-byte vectors.
+template <int BM, int BN, bool RELU, bool BIAS>
+__global__ __launch_bounds__(256) void k_conv_gemm(View in, const bf16* __restrict__ w,
                                                    const float* __restrict__ bias, View out, int nb, int S,
                                                    int cin, int cout) {
-  constexpr int NT = BN / 16;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int m0 = (blockIdx.x * 4 + wv) * (MT * 16);
-  const int n0 = blockIdx.y * BN;
-  const int mtot = nb * S * S;
+  constexpr int WN = BN / 32, WM = 4 / WN;
+  static_assert(WM * 64 == BM, "wavefront tiles must cover the block tile");
+  constexpr int MT = 4, NT = 2;
+  constexpr int LD = 40;                                // padded rows (80 bytes)
+  constexpr int AP = BM / 64;                           // 16-byte A pieces per thread per step
+  __shared__ __align__(16) bf16 sa[2][BM * LD];
+  __shared__ __align__(16) bf16 sb[2][BN * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv / WN, wn = wv % WN;
   const int row = lane & 15, grp = lane >> 4;
-  int ab[MT], ay[MT], ax[MT];
-  bool aok[MT];
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int mtot = nb * S * S;
+  // loader roles: A piece r of this thread = pixel (tid + 256 r) / 4, channels
+  // ((tid + 256 r) % 4) * 8 .. +8; B: output channel tid / 4, channels (tid % 4) * 8
+  // .. +8 (threads below BN * 4)
+  int ab[AP], ay[AP], ax[AP];
+  bool aok[AP];
+  const int ac = (tid & 3) * 8;
 #pragma unroll
-  for (int i = 0; i < MT; ++i) {
-    const int am = m0 + i * 16 + row;
-    aok[i] = am < mtot;
-    ab[i] = am / (S * S);
-    ay[i] = (am / S) % S;
-    ax[i] = am % S;
+  for (int r = 0; r < AP; ++r) {
+    const int am = m0 + (tid + 256 * r) / 4;
+    aok[r] = am < mtot;
+    ab[r] = am / (S * S);
+    ay[r] = (am / S) % S;
+    ax[r] = am % S;
   }
+  const int bnr = tid >> 2;
+  const bool b_on = tid < BN * 4;
+  const int cb = cin / 32, steps = 9 * cb;
+  bf16x8_t ra[AP], rb;
+  auto fetch = [&](int st) {
+    const int tap = st / cb, c0 = (st % cb) * 32;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+    for (int r = 0; r < AP; ++r) {
+      const int yy = ay[r] + dy, xx = ax[r] + dx;
+      if (aok[r] && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
+        ra[r] = *reinterpret_cast<const bf16x8_t*>(in.p + ((size_t)(ab[r] * S + yy) * S + xx) * in.cs + in.co + c0 + ac);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ra[r][e] = static_cast<bf16>(0.0f);
+      }
+    }
+    if (b_on) rb = *reinterpret_cast<const bf16x8_t*>(w + ((size_t)(n0 + bnr) * 9 + tap) * cin + c0 + ac);
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < AP; ++r)
+      *reinterpret_cast<bf16x8_t*>(&sa[buf][((tid + 256 * r) >> 2) * LD + ac]) = ra[r];
+    if (b_on) *reinterpret_cast<bf16x8_t*>(&sb[buf][bnr * LD + ac]) = rb;
+  };
   f32x4_t acc[MT][NT];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[i][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int tap = 0; tap < 9; ++tap) {
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const bf16* ap[MT];
-    bool ok[MT];
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < steps; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < steps) fetch(st + 1);
+    bf16x8_t a[MT], b[NT];
 #pragma unroll
-    for (int i = 0; i < MT; ++i) {
-      const int yy = ay[i] + dy, xx = ax[i] + dx;
-      ok[i] = aok[i] && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
-      ap[i] = in.p + ((size_t)(ab[i] * S + yy) * S + xx) * in.cs + in.co + grp * 8;
-    }
-    const bf16* bp = w + ((size_t)(n0 + row) * 9 + tap) * cin + grp * 8;
-    for (int c0 = 0; c0 < cin; c0 += 32) {
-      bf16x8_t a[MT], b[NT];
+    for (int i = 0; i < MT; ++i)
+      a[i] = *reinterpret_cast<const bf16x8_t*>(&sa[buf][(wm * 64 + i * 16 + row) * LD + grp * 8]);
 #pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        if (ok[i]) {
-          a[i] = *reinterpret_cast<const bf16x8_t*>(ap[i] + c0);
-        } else {
+    for (int t = 0; t < NT; ++t)
+      b[t] = *reinterpret_cast<const bf16x8_t*>(&sb[buf][(wn * 32 + t * 16 + row) * LD + grp * 8]);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) a[i][e] = static_cast<bf16>(0.0f);
-        }
-      }
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const bf16x8_t*>(bp + (size_t)t * 16 * 9 * cin + c0);
-#pragma unroll
-      for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[t], acc[i][t], 0, 0, 0);
-    }
+      for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[t], acc[i][t], 0, 0, 0);
+    if (st + 1 < steps) stash(buf ^ 1);
+    __syncthreads();
   }
-  // D[i][j]: j = lane % 16 (output channel), i = 4 * (lane / 16) + r (pixel)
+  // epilogue: D[i][j], i = 4 * (lane / 16) + r (pixel), j = lane % 16 (channel),
+  // staged as bf16 [pixel][channel] in the A buffers
+  bf16* so = &sa[0][0];
+  constexpr int LDO = BN + 8;
+  static_assert(BM * LDO <= 2 * BM * LD, "epilogue tile must fit");
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int n = n0 + t * 16 + row;
-    const float bv = BIAS ? bias[n] : 0.f;
+    const int nl = wn * 32 + t * 16 + row;
+    const float bv = BIAS ? bias[n0 + nl] : 0.f;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + i * 16 + grp * 4 + r;
-        if (m >= mtot) continue;
         float v = acc[i][t][r] + bv;
         if (RELU) v = fmaxf(v, 0.f);
-        out.p[(size_t)m * out.cs + out.co + n] = tob(v);
+        so[(wm * 64 + i * 16 + grp * 4 + r) * LDO + nl] = tob(v);
       }
+  }
+  __syncthreads();
+  for (int e = tid; e < BM * (BN / 8); e += 256) {
+    const int pl = e / (BN / 8), g = (e % (BN / 8)) * 8;
+    const int m = m0 + pl;
+    if (m >= mtot) continue;
+    *reinterpret_cast<bf16x8_t*>(out.at(m) + n0 + g) = *reinterpret_cast<const bf16x8_t*>(&so[pl * LDO + g]);
   }
 }
 
@@ -711,22 +751,21 @@ View V(bf16* p, int cs, int co = 0) { return View{p, cs, co}; }
 
 void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out, int nb, int S, int cin, int cout,
                  bool relu) {
-  constexpr int MT = 4;  // 16-pixel tiles per wavefront: 256 pixels per block
   const int mtot = nb * S * S;
   if (cin % 32 != 0 || cout % 32 != 0) throw std::invalid_argument("conv channels must be multiples of 32");
-  const int bn = cout % 64 == 0 ? 64 : 32;
-  dim3 grid(blocks(mtot, 64 * MT), cout / bn);
   hipStream_t s = c->stream;
-  if (bn == 64) {
-    if (relu) k_conv_mfma<64, MT, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else if (bias) k_conv_mfma<64, MT, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else k_conv_mfma<64, MT, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+  if (cout % 64 == 0) {
+    dim3 grid(blocks(mtot, 128), cout / 64);
+    if (relu) k_conv_gemm<128, 64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else if (bias) k_conv_gemm<128, 64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else k_conv_gemm<128, 64, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
   } else {
-    if (relu) k_conv_mfma<32, MT, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else if (bias) k_conv_mfma<32, MT, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else k_conv_mfma<32, MT, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    dim3 grid(blocks(mtot, 256), cout / 32);
+    if (relu) k_conv_gemm<256, 32, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else if (bias) k_conv_gemm<256, 32, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    else k_conv_gemm<256, 32, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
   }
-  PTY_LAUNCH_CHECK("conv_mfma");
+  PTY_LAUNCH_CHECK("conv_gemm");
 }
 
 // input gradient of an MFMA layer: dx = conv(dz, flipped transposed w)
