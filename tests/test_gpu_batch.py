@@ -119,3 +119,36 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert again.autotune("lsqml", cache, **params) == ch
     for pl in (ref, tuned, again):
         pl.close()
+
+
+def test_error_paths_of_the_newer_entry_points():
+    """State and shape errors are reported as statuses, before any device work."""
+    import torch
+    from paper_2202_03144_amd import Plan, PtyError
+    from paper_2202_03144_amd.cnn import Net
+    case = spiral_case(64, 1, 20, cfg=98)
+    with Plan(64, 1, 20, case.shape) as pl:
+        with pytest.raises(PtyError, match="STATE"):
+            pl.set_truth(c64(case.obj_true))          # no positions yet
+        with pytest.raises(PtyError, match="STATE"):
+            pl.nrmse()                                # no truth
+        with pytest.raises(PtyError, match="STATE"):
+            pl.model_error()                          # nothing loaded
+        pl.load_patterns(case.counts)
+        pl.load_positions(case.pos)
+        pl.set_object(c64(np.ones(case.shape)))
+        pl.set_probe(c64(case.probe))
+        with pytest.raises(PtyError, match="UNSUPPORTED"):
+            pl.autotune("epie")
+        with pytest.raises(PtyError, match="UNSUPPORTED"):
+            pl.stitch(torch.zeros((20, 64, 64, 2), dtype=torch.float32, device="cuda"))
+        with Net(4, seed=0) as net:
+            with pytest.raises(PtyError, match="UNSUPPORTED"):
+                pl.seed_object(net, 1e6, batch=4)     # the network takes 128 x 128 windows
+        with pytest.raises(PtyError, match="INVALID"):
+            pl.set_truth(c64(case.obj_true), 1.5)     # roi_frac outside [0, 1]
+        with pytest.raises(PtyError, match="INVALID"):
+            pl.training_targets(torch.zeros((20, 32, 32, 2), dtype=torch.float32, device="cuda"))
+        # state survives the failed calls
+        pl.iterate("dm", 1)
+        assert np.isfinite(pl.errors()).all()
