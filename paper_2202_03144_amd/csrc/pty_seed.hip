@@ -295,8 +295,11 @@ int seed_chain_grid() { return kChainGrid; }
 void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int hc, int wc, float2* phasor,
                        hipStream_t s) {
   const size_t lds = (size_t)hc * wc * sizeof(float2);
-  if (lds <= 128 * 1024)
+  if (lds <= 128 * 1024) {
+    PTY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seed_chain<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     k_seed_chain<true><<<1, 64, lds, s>>>(patches, place, j, S, hc, wc, phasor);
+  }
   else
     k_seed_chain<false><<<1, 64, 0, s>>>(patches, place, j, S, hc, wc, phasor);
   PTY_LAUNCH_CHECK("seed_chain");

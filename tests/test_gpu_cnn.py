@@ -334,3 +334,30 @@ def test_full_size_inference_and_stitch():
     err_o = float(np.linalg.norm(got - ref_o) / np.linalg.norm(ref_o))
     print("full-size stitch rel err", err_o)
     assert err_o <= 1e-4
+
+
+def test_stitch_large_object_global_chain():
+    """An object whose coarse chain grid does not fit in LDS (2,200 x 2,100:
+    138 x 132 cells of 8 bytes) takes the global-memory chain."""
+    import torch
+    from paper_2202_03144_amd import Plan
+    h, w = 2200, 2100
+    rng = np.random.default_rng(41)
+    pos = np.concatenate([ptysynth.spiral_positions(40, 6.0, 600.0, 128, ptysynth.stream(41, 3)),
+                          ptysynth.spiral_positions(40, 6.0, 1500.0, 128, ptysynth.stream(42, 3))])
+    obj = ptysynth.make_object(41, h, w, 3.0)
+    t = oseed.placements(pos)
+    p = np.empty((len(pos), 64, 64, 2), np.float32)
+    for i, (ty, tx) in enumerate(t):
+        o = obj[ty:ty + 64, tx:tx + 64] * np.exp(1j * rng.uniform(-np.pi, np.pi))
+        p[i, ..., 0] = np.abs(o)
+        p[i, ..., 1] = np.angle(o)
+    with Plan(128, 1, len(pos), (h, w)) as pl:
+        pl.load_positions(pos)
+        out = torch.empty((h, w), dtype=torch.complex64, device="cuda")
+        pl.stitch(torch.from_numpy(p).cuda(), out)
+        got = out.cpu().numpy()
+    ref, _ = oseed.stitch(p.astype(np.float64), pos, h, w)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print("global-chain stitch rel err", err)
+    assert err <= 1e-5
