@@ -181,13 +181,22 @@ void k_rows_inv(FourierArgs a) {
     const float2* src = a.zs + ((size_t)c * K + k) * N * N;
 #pragma unroll
     for (int m = 0; m < R; ++m) z[m] = src[zoff<N>(y, t + T * m)];
-    line_fft<N, true>(z, xb + line * G::W, tw_s, t);
+    // the probe row is read before the transform: the epilogue's stores could
+    // alias it, so loads issued among them would each wait for the memory
+    // (the position-gradient epilogue keeps the late loads: its registers are full)
     const float2* pr = a.probe + ((size_t)k * N + y) * N;
+    constexpr bool PRE = MODE != RowOut::NllGrad;
+    float2 pkr[PRE ? R : 1];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) pkr[m] = pr[t + T * m];
+    }
+    line_fft<N, true>(z, xb + line * G::W, tw_s, t);
     if constexpr (MODE == RowOut::DmUpdate) {
       float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const float2 pk = pr[t + T * m];
+        const float2 pk = pkr[m];
         const float2 nw = cmul(pk, o[m]) + z[m];
         ps[t + T * m] = nw;
         cacc[m] = cacc[m] + cconjmul(pk, nw);
@@ -197,7 +206,9 @@ void k_rows_inv(FourierArgs a) {
       float2* ch = a.chi + (((size_t)slot * K + k) * N + y) * N;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const float2 pk = pr[t + T * m];
+        float2 pk;
+        if constexpr (PRE) pk = pkr[m];
+        else pk = pr[t + T * m];
         ch[t + T * m] = z[m];
         cacc[m] = cacc[m] + gscale * cconjmul(pk, z[m]);
         if constexpr (MODE == RowOut::NllGrad) {
