@@ -47,18 +47,31 @@ void k_rows_fwd(FourierArgs a) {
   float2 o[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
-  // one mode at a time keeps the register footprint at one line per thread
+  // One mode at a time keeps the register footprint at one line per thread;
+  // the next mode's probe (and DM exit-wave) row is loaded before this mode's
+  // transform and stores, so the loads overlap them.
+  constexpr bool DMR = MODE == RowIn::DmReflect;
+  float2 pa[R], pb[DMR ? R : 1];
+  auto load_mode = [&](int k) {
+    const float2* pr = a.probe + ((size_t)k * N + y) * N;
+#pragma unroll
+    for (int m = 0; m < R; ++m) pa[m] = pr[t + T * m];
+    if constexpr (DMR) {
+      const float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) pb[m] = ps[t + T * m];
+    }
+  };
+  load_mode(0);
 #pragma unroll 1
   for (int k = 0; k < K; ++k) {
     float2 z[R];
-    const float2* pr = a.probe + ((size_t)k * N + y) * N;
 #pragma unroll
-    for (int m = 0; m < R; ++m) z[m] = cmul(pr[t + T * m], o[m]);
-    if constexpr (MODE == RowIn::DmReflect) {
-      const float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
-#pragma unroll
-      for (int m = 0; m < R; ++m) z[m] = 2.f * z[m] - ps[t + T * m];
+    for (int m = 0; m < R; ++m) {
+      z[m] = cmul(pa[m], o[m]);
+      if constexpr (DMR) z[m] = 2.f * z[m] - pb[m];
     }
+    if (k + 1 < K) load_mode(k + 1);
     line_fft<N, false>(z, xb + line * G::W, tw_s, t);
     float2* out = a.zs + ((size_t)c * K + k) * N * N;
 #pragma unroll
