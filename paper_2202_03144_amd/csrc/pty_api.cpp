@@ -390,14 +390,13 @@ int chunk_patterns(const pty_ctx* c, const pty_iter_params& p) {
   return fit >= wave ? fit / wave * wave : fit;
 }
 
-constexpr int kProbeSlice = 32;
 
 // Common work buffers of the Fourier passes.
 void ensure_common(pty_ctx* c, int chunk, size_t slots) {
   const size_t nn = size_t(c->N) * c->N;
   c->ensure(c->zs, c->zs_patterns, size_t(chunk) * c->K * nn);
   c->ensure(c->contrib, c->contrib_slots, slots * nn);
-  c->ensure_once(c->errp, size_t(c->J) * col_blocks(c->N) * 2);
+  c->ensure_once(c->errp, size_t(c->J) * col_blocks(c->N, c->K) * 2);
   c->ensure_once(c->den, size_t(c->H) * c->W);
   c->ensure_once(c->scal, 16);
   c->ensure_once(c->pint, nn);
@@ -436,7 +435,7 @@ void ensure_err_slot(pty_ctx* c, int n_iter) {
 void end_iteration(pty_ctx* c, int t) {
   (void)t;
   timed(c, kOther, [&] {
-    launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->err_dev, c->stream, c->iter_dev, !c->have_truth);
+    launch_err_reduce(c->errp, c->J * col_blocks(c->N, c->K), c->err_dev, c->stream, c->iter_dev, !c->have_truth);
   });
   if (c->have_truth)
     timed(c, kOther, [&] {
@@ -515,7 +514,8 @@ void density(pty_ctx* c, const Group& g) {
 void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern, PrbOp op,
                   float2* num, bool with_den, const float2* obj = nullptr) {
   const int count = (int)g.jl.size();
-  const int slices = probe_slices(count, kProbeSlice);
+  const int per_slice = probe_per_slice(c->N, count);
+  const int slices = probe_slices(count, per_slice);
   ProbeAccArgs pa{};
   pa.n = c->N;
   pa.k = c->K;
@@ -529,7 +529,7 @@ void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern,
   pa.alpha = c->alpha;
   pa.s0 = 0;
   pa.count = count;
-  pa.per_slice = kProbeSlice;
+  pa.per_slice = per_slice;
   pa.part_num = c->part_num;
   pa.part_den = c->part_den;
   pa.stream = c->stream;
@@ -549,7 +549,7 @@ void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern,
 }
 
 void ensure_probe_parts(pty_ctx* c, int count) {
-  const int slices = probe_slices(count, kProbeSlice);
+  const int slices = probe_slices_max(c->N, count);
   const size_t nn = size_t(c->N) * c->N;
   size_t have = c->part_slices;
   if (c->part_num && have >= size_t(slices) * c->K * nn && c->part_den) return;
@@ -763,7 +763,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       r.order = d_order;
       r.count = c->J;
       r.errp = c->errp;
-      r.bpp = col_blocks(c->N);
+      r.bpp = col_blocks(c->N, c->K);
       r.tw = reinterpret_cast<const float*>(c->tw);
       r.alpha = p.alpha;
       r.beta = p.beta;
@@ -837,7 +837,7 @@ double run_nll(pty_ctx* c, const float2* obj, const float2* probe, bool grad, fl
     timed(c, kCols, [&] { launch_cols(a, grad ? ColOp::NllGrad : ColOp::NllLoss); });
     if (grad) timed(c, kRowsInv, [&] { launch_rows_inv(a, RowOut::NllGrad); });
   }
-  timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->loss_dev, c->stream); });
+  timed(c, kOther, [&] { launch_err_reduce(c->errp, c->J * col_blocks(c->N, c->K), c->loss_dev, c->stream); });
   if (grad && g_obj) {
     timed(c, kOther, [&] { launch_fill_u32(reinterpret_cast<unsigned*>(g_obj), size_t(c->H) * c->W * 2, 0u, c->stream); });
     ObjGatherArgs o = obj_args(c, g);
@@ -866,7 +866,7 @@ double model_error(pty_ctx* c) {
   ensure_common(c, std::min(chunk, c->J), 1);
   c->ensure_once(c->eval_dev, 8);
   fourier_pass(c, c->all, 0, c->J, chunk, RowIn::Plain, ColOp::Project, RowOut::StoreChi, false);
-  launch_err_reduce(c->errp, c->J * col_blocks(c->N), c->eval_dev, c->stream);
+  launch_err_reduce(c->errp, c->J * col_blocks(c->N, c->K), c->eval_dev, c->stream);
   double e = 0.0;
   PTY_HIP(hipMemcpyAsync(&e, c->eval_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   PTY_HIP(hipStreamSynchronize(c->stream));

@@ -79,28 +79,47 @@ void k_rows_fwd(FourierArgs a) {
   }
 }
 
+// Modes per thread group in the column pass.  The projection needs every
+// mode of a far-field pixel at once; holding all K modes of an R-value line
+// costs 2 K R registers, which at K = 4, R = 16 leaves one wavefront per SIMD.
+// There the modes are split over MS = 2 groups of T lanes per column (one
+// after the other in a wavefront), which add their partial intensities with
+// one lane shuffle; a block then covers 1 / MS as many columns and a pattern
+// MS times as many blocks.
+template <int N, int K>
+struct ColSplit {
+  static constexpr int MS = (K % 2 == 0 && (K * FftShape<N>::R) > 48) ? 2 : 1;
+  static constexpr int CW = Geo<N>::LINES / MS;   // columns per block
+  static constexpr int BPP = N / CW;              // blocks per pattern
+};
+
 template <int N, int K, ColOp OP>
 __global__ __launch_bounds__(Geo<N>::BS)
 void k_cols(FourierArgs a) {
   using G = Geo<N>;
-  constexpr int R = G::R, T = G::T, CW = G::LINES, BPP = N / CW;
+  using S = ColSplit<N, K>;
+  constexpr int R = G::R, T = G::T, CW = S::CW, BPP = S::BPP, MS = S::MS, KM = K / MS;
   __shared__ float2 tw_s[N];
-  __shared__ float2 xb[CW * G::W];
+  __shared__ float2 xb[G::LINES * G::W];
   __shared__ double red[G::BS / 64];
   load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
-  // each column's T threads are consecutive lanes of one wavefront
-  const int col = threadIdx.x / T, t = threadIdx.x % T;
+  // each line's T threads are consecutive lanes of one wavefront; the MS
+  // groups of a column are adjacent, so their lanes differ by T
+  const int grp = threadIdx.x / T, t = threadIdx.x % T;
+  const int col = grp / MS, kg = grp % MS;
+  const bool lead = kg == 0;
   const int c = blockIdx.y, cb = blockIdx.x, x = cb * CW + col;
   const int j = a.jlist[a.jl_off + c];
-  float2* base = a.zs + (size_t)c * K * N * N;
-  float2 z[K][R];
+  float2* base = a.zs + ((size_t)c * K + kg * KM) * N * N;
+  float2* buf = xb + grp * G::W;
+  float2 z[KM][R];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < KM; ++k) {
 #pragma unroll
     for (int m = 0; m < R; ++m) z[k][m] = base[(size_t)k * N * N + zoff<N>(t + T * m, x)];
   }
 #pragma unroll
-  for (int k = 0; k < K; ++k) line_fft<N, false>(z[k], xb + col * G::W, tw_s, t);
+  for (int k = 0; k < KM; ++k) line_fft<N, false>(z[k], buf, tw_s, t);
   // The transforms are unscaled: the unitary far field is z / N and the
   // unitary inverse of the whole pipeline contributes another 1 / N^2, both
   // folded into the per-pixel factor applied before the inverse transforms.
@@ -111,37 +130,43 @@ void k_cols(FourierArgs a) {
     const int pr = t + T * m;
     float iraw = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) iraw += cabs2(z[k][m]);
+    for (int k = 0; k < KM; ++k) iraw += cabs2(z[k][m]);
+    if constexpr (MS == 2) iraw += __shfl_xor(iraw, T, 64);
     const float inten = iraw * sc2;
     if constexpr (OP == ColOp::Intensity) {
-      a.intensity_out[((size_t)j * N + ((pr + N / 2) & (N - 1))) * N + ((x + N / 2) & (N - 1))] = inten;
+      if (lead)
+        a.intensity_out[((size_t)j * N + ((pr + N / 2) & (N - 1))) * N + ((x + N / 2) & (N - 1))] = inten;
     } else if constexpr (OP == ColOp::NllLoss) {
-      const float am = a.amp[((size_t)j * N + pr) * N + x];
-      const float d = am * am;
-      e_num += inten - d * logf(inten + a.nll_eps);
+      if (lead) {
+        const float am = a.amp[((size_t)j * N + pr) * N + x];
+        const float d = am * am;
+        e_num += inten - d * logf(inten + a.nll_eps);
+      }
     } else {
       const float am = a.amp[((size_t)j * N + pr) * N + x];
       float f;
       if constexpr (OP == ColOp::Project) {
         const float mod = sqrtf(iraw) * sc;
         f = am / fmaxf(mod, 1e-6f) - 1.f;
-        e_num += (mod - am) * (mod - am);
-        e_den += am * am;
+        if (lead) {
+          e_num += (mod - am) * (mod - am);
+          e_den += am * am;
+        }
       } else {
         const float d = am * am;
         f = a.grad_scale * (1.f - d / (inten + a.nll_eps));
-        e_num += inten - d * logf(inten + a.nll_eps);
+        if (lead) e_num += inten - d * logf(inten + a.nll_eps);
       }
       f *= sc2;
 #pragma unroll
-      for (int k = 0; k < K; ++k) z[k][m] = f * z[k][m];
+      for (int k = 0; k < KM; ++k) z[k][m] = f * z[k][m];
     }
   }
   if constexpr (OP == ColOp::Project || OP == ColOp::NllGrad) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) line_fft<N, true>(z[k], xb + col * G::W, tw_s, t);
+    for (int k = 0; k < KM; ++k) line_fft<N, true>(z[k], buf, tw_s, t);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < KM; ++k) {
 #pragma unroll
       for (int m = 0; m < R; ++m) base[(size_t)k * N * N + zoff<N>(t + T * m, x)] = z[k][m];
     }
@@ -249,12 +274,16 @@ void k_rows_inv(FourierArgs a) {
 
 }  // namespace
 
-int col_blocks(int n) {
+int col_blocks(int n, int k) {
+  int r = 0;
+  dispatch_nk(n, k, [&](auto nc, auto kc) { r = ColSplit<decltype(nc)::value, decltype(kc)::value>::BPP; });
+  return r;
+}
+int row_blocks(int n) {
   int r = 0;
   dispatch_n(n, [&](auto nc) { constexpr int N = decltype(nc)::value; r = N / Geo<N>::LINES; });
   return r;
 }
-int row_blocks(int n) { return col_blocks(n); }
 
 void launch_rows_fwd(const FourierArgs& a, RowIn mode) {
   if (a.nc <= 0) return;
@@ -273,12 +302,13 @@ void launch_cols(const FourierArgs& a, ColOp op) {
   if (a.nc <= 0) return;
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
-    const dim3 grid(N / Geo<N>::LINES, a.nc);
+    const dim3 grid(ColSplit<N, K>::BPP, a.nc);
+    constexpr int BS = Geo<N>::BS;
     switch (op) {
-      case ColOp::Project: k_cols<N, K, ColOp::Project><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
-      case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
-      case ColOp::Intensity: k_cols<N, K, ColOp::Intensity><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
-      case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+      case ColOp::Project: k_cols<N, K, ColOp::Project><<<grid, BS, 0, a.stream>>>(a); break;
+      case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad><<<grid, BS, 0, a.stream>>>(a); break;
+      case ColOp::Intensity: k_cols<N, K, ColOp::Intensity><<<grid, BS, 0, a.stream>>>(a); break;
+      case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss><<<grid, BS, 0, a.stream>>>(a); break;
     }
   });
   PTY_LAUNCH_CHECK("cols");

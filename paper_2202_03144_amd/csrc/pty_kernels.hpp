@@ -46,7 +46,7 @@ struct FourierArgs {
 void launch_rows_fwd(const FourierArgs& a, RowIn mode);
 void launch_cols(const FourierArgs& a, ColOp op);
 void launch_rows_inv(const FourierArgs& a, RowOut mode);
-int col_blocks(int n);   // column blocks per pattern in the column pass
+int col_blocks(int n, int k);   // column blocks per pattern in the column pass
 int row_blocks(int n);   // row blocks per pattern in the row passes
 
 struct ObjGatherArgs {
@@ -85,6 +85,8 @@ struct ProbeAccArgs {
   hipStream_t stream;
 };
 int probe_slices(int count, int per_slice);
+int probe_per_slice(int n, int count);
+int probe_slices_max(int n, int count);
 void launch_probe_acc(const ProbeAccArgs& a, PrbOp op);
 
 struct ProbeFinishArgs {

@@ -211,23 +211,27 @@ __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
   }
 }
 
+// One thread per (pixel, mode): the mode is blockIdx.y, so a launch has
+// K times as many blocks as the window has pixel blocks; the density and its
+// maximum come from the mode-0 blocks.
 __global__ __launch_bounds__(256) void k_probe_finish(ProbeFinishArgs a) {
   __shared__ float redf[4];
   const int nn = a.n * a.n;
   const int q = blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.y;
   float dv = 0.f;
   if (q < nn) {
-    for (int k = 0; k < a.k; ++k) {
-      float2 s = make_float2(0.f, 0.f);
-      for (int sl = 0; sl < a.slices; ++sl) s = s + a.part_num[((size_t)sl * a.k + k) * nn + q];
-      a.num[(size_t)k * nn + q] = s;
-    }
-    if (a.part_den) {
+    float2 s = make_float2(0.f, 0.f);
+#pragma unroll 8
+    for (int sl = 0; sl < a.slices; ++sl) s = s + a.part_num[((size_t)sl * a.k + k) * nn + q];
+    a.num[(size_t)k * nn + q] = s;
+    if (k == 0 && a.part_den) {
+#pragma unroll 8
       for (int sl = 0; sl < a.slices; ++sl) dv += a.part_den[(size_t)sl * nn + q];
       a.den[q] = dv;
     }
   }
-  if (a.den_max) {
+  if (k == 0 && a.den_max) {
     const float mx = block_max_all<256>(dv, redf);
     if (threadIdx.x == 0) atomicMax(a.den_max, __float_as_uint(mx));
   }
@@ -769,6 +773,32 @@ void launch_obj_gather(const ObjGatherArgs& a, ObjOp op) {
 
 int probe_slices(int count, int per_slice) { return (count + per_slice - 1) / per_slice; }
 
+int probe_acc_blocks(int n) {
+  int b = 0;
+  dispatch_n(n, [&](auto nc) { b = ProbePix<decltype(nc)::value>::W::BLOCKS; });
+  return b;
+}
+
+// Patterns per slice: 32, halved (down to 8) while a launch would have
+// fewer than 512 blocks, two per compute unit, so that small windows and
+// small groups still keep every CU busy; the partial sums then cost at most a
+// quarter of the source traffic. (Above 512 blocks the longer per-block
+// loops win: at 256 x 256 x 3 in groups of 500, 16 patterns per slice take
+// 10% longer than 32.)
+int probe_per_slice(int n, int count) {
+  const int b = probe_acc_blocks(n);
+  int per = 32;
+  while (per > 8 && b * probe_slices(count, per) < 512) per /= 2;
+  return per;
+}
+
+// Upper bound of probe_slices(c, probe_per_slice(n, c)) over 1 <= c <= count:
+// a halving happens only below 512 blocks, so it leaves under 1,024.
+int probe_slices_max(int n, int count) {
+  const int b = probe_acc_blocks(n);
+  return std::min(probe_slices(count, 8), std::max(probe_slices(count, 32), (1024 + b - 1) / b));
+}
+
 void launch_probe_acc(const ProbeAccArgs& a, PrbOp op) {
   if (a.count <= 0) return;
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
@@ -784,7 +814,7 @@ void launch_probe_acc(const ProbeAccArgs& a, PrbOp op) {
 }
 
 void launch_probe_finish(const ProbeFinishArgs& a) {
-  k_probe_finish<<<(a.n * a.n + 255) / 256, 256, 0, a.stream>>>(a);
+  k_probe_finish<<<dim3((a.n * a.n + 255) / 256, a.k), 256, 0, a.stream>>>(a);
   PTY_LAUNCH_CHECK("probe_finish");
 }
 

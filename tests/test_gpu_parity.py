@@ -21,6 +21,7 @@ SHAPES = [
     (64, 1, 24, 7, 10),
     (128, 4, 9, 4, 4),
     (256, 3, 10, 3, 4),
+    (256, 4, 6, 4, 4),     # modes split over two lane groups in the column pass
 ]
 
 
