@@ -159,6 +159,35 @@ pty_status pty_get_exit_waves(pty_ctx* ctx, void* out, int on_device);
 /* Device memory currently held by the context, in bytes. */
 pty_status pty_mem_bytes(const pty_ctx* ctx, size_t* out);
 
+/* Checkpoint and exact resume.  The step API lets a caller stop after any
+ * iteration, fetch object and probe, and start again from supplied guesses
+ * (Sec. 3.2, Listing 1; Sec. 2.2 for the guesses).  What object and probe do
+ * not carry is copied here: the iteration counter (it decides
+ * probe_update_start and the ePIE visiting order), the error history, the
+ * NRMSE history while a truth is set, and the DM exit waves while they are
+ * current.  With them a new context of the same shape continues a run
+ * exactly: n iterations, save, restore, n iterations reproduce 2n.
+ *
+ * Host buffer, native byte order:
+ *   64-byte header: the 8 characters "PTYSTAT1"; int32 n, modes, n_pos,
+ *     obj_h, obj_w, iterations, has_exit_waves, has_nrmse; zero padding;
+ *   float64 errors[iterations];
+ *   float64 nrmse[iterations]                    if has_nrmse;
+ *   complex64 exit waves[n_pos][modes][n][n]     if has_exit_waves,
+ *     followed by the planes sum_k conj(P_k) psi_k [n_pos][n][n] that the
+ *     last DM iteration left for the next object update.
+ * pty_get_state: *n receives the size in bytes; out == NULL only asks for the
+ * size; cap below it gives PTY_E_INVALID.  Synchronises.
+ * pty_set_state: call after pty_set_object / pty_set_probe, which discard the
+ * exit waves.  A wrong magic, a shape other than the context's or a size that
+ * does not match the header gives PTY_E_INVALID with the context unchanged.
+ * The NRMSE history is restored only when the context has a truth.
+ * Synchronises. */
+#define PTY_STATE_HEADER_BYTES 64
+pty_status pty_get_state(pty_ctx* ctx, void* out, size_t cap, size_t* n);
+pty_status pty_set_state(pty_ctx* ctx, const void* in, size_t n);
+
+
 /* Kernel timing.  While enabled, every kernel launch of the context is
  * bracketed by HIP events on the context's stream and its duration is added
  * to its family's total.  Families, in this order (PTY_TIMING_FAMILIES):

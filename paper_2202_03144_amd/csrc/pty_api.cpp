@@ -1342,6 +1342,104 @@ pty_status pty_get_exit_waves(pty_ctx* c, void* out, int on_device) {
   });
 }
 
+namespace {
+struct StateHeader {
+  char magic[8];
+  int32_t n, modes, n_pos, obj_h, obj_w, iterations, has_psi, has_nrmse;
+  int32_t pad[6];
+};
+static_assert(sizeof(StateHeader) == PTY_STATE_HEADER_BYTES, "state header layout");
+constexpr char kStateMagic[8] = {'P', 'T', 'Y', 'S', 'T', 'A', 'T', '1'};
+
+// DM state: the exit waves and the per-pattern planes sum_k conj(P_k) psi_k
+// that the last Fourier pass left for the next object update.
+size_t psi_elems(const pty_ctx* c) { return size_t(c->J) * c->K * c->N * c->N; }
+size_t contrib_elems(const pty_ctx* c) { return size_t(c->J) * c->N * c->N; }
+
+size_t state_bytes(const pty_ctx* c, const StateHeader& h) {
+  size_t b = sizeof(StateHeader) + sizeof(double) * size_t(h.iterations) * (h.has_nrmse ? 2 : 1);
+  if (h.has_psi) b += (psi_elems(c) + contrib_elems(c)) * sizeof(float2);
+  return b;
+}
+}  // namespace
+
+pty_status pty_get_state(pty_ctx* c, void* out, size_t cap, size_t* n) {
+  return guarded(c, [&] {
+    require(c != nullptr && n != nullptr, "pty_get_state: null argument");
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, sizeof(h.magic));
+    h.n = c->N;
+    h.modes = c->K;
+    h.n_pos = c->J;
+    h.obj_h = c->H;
+    h.obj_w = c->W;
+    h.iterations = c->iter;
+    h.has_psi = (c->dm_valid && c->psi && c->contrib && c->contrib_slots >= contrib_elems(c)) ? 1 : 0;
+    h.has_nrmse = (c->have_truth && c->iter > 0) ? 1 : 0;
+    const size_t bytes = state_bytes(c, h);
+    *n = bytes;
+    if (out == nullptr) return;
+    require(cap >= bytes, "pty_get_state: buffer smaller than the state");
+    c->set_device();
+    char* p = static_cast<char*>(out);
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    if (h.iterations > 0) {
+      copy_out(c, p, c->err_dev, sizeof(double) * h.iterations, 0);
+      p += sizeof(double) * h.iterations;
+    }
+    if (h.has_nrmse) {
+      copy_out(c, p, c->nrmse_dev, sizeof(double) * h.iterations, 0);
+      p += sizeof(double) * h.iterations;
+    }
+    if (h.has_psi) {
+      copy_out(c, p, c->psi, psi_elems(c) * sizeof(float2), 0);
+      p += psi_elems(c) * sizeof(float2);
+      copy_out(c, p, c->contrib, contrib_elems(c) * sizeof(float2), 0);
+    }
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+pty_status pty_set_state(pty_ctx* c, const void* in, size_t n) {
+  return guarded(c, [&] {
+    require(c != nullptr && in != nullptr, "pty_set_state: null argument");
+    require(n >= sizeof(StateHeader), "pty_set_state: buffer shorter than the header");
+    StateHeader h;
+    std::memcpy(&h, in, sizeof(h));
+    require(std::memcmp(h.magic, kStateMagic, sizeof(h.magic)) == 0, "pty_set_state: not a state buffer");
+    require(h.n == c->N && h.modes == c->K && h.n_pos == c->J && h.obj_h == c->H && h.obj_w == c->W,
+            "pty_set_state: shape differs from the context's");
+    require(h.iterations >= 0 && (h.has_psi == 0 || h.has_psi == 1) && (h.has_nrmse == 0 || h.has_nrmse == 1),
+            "pty_set_state: bad header");
+    require(n == state_bytes(c, h), "pty_set_state: size does not match the header");
+    c->set_device();
+    const char* p = static_cast<const char*>(in) + sizeof(h);
+    // allocations first, so that a failure leaves the context as it was
+    ensure_err_slot(c, std::max(1, h.iterations - c->iter));
+    if (h.has_psi) {
+      c->ensure_once(c->psi, psi_elems(c));
+      c->ensure(c->contrib, c->contrib_slots, contrib_elems(c));
+    }
+    if (h.iterations > 0) copy_in(c, c->err_dev, p, sizeof(double) * h.iterations, 0);
+    p += sizeof(double) * h.iterations;
+    if (h.has_nrmse) {
+      if (c->have_truth) copy_in(c, c->nrmse_dev, p, sizeof(double) * h.iterations, 0);
+      p += sizeof(double) * h.iterations;
+    }
+    if (h.has_psi) {
+      copy_in(c, c->psi, p, psi_elems(c) * sizeof(float2), 0);
+      p += psi_elems(c) * sizeof(float2);
+      copy_in(c, c->contrib, p, contrib_elems(c) * sizeof(float2), 0);
+    }
+    c->iter = h.iterations;
+    launch_set_i32(c->iter_dev, c->iter, c->stream);
+    c->dm_valid = h.has_psi == 1;
+    c->den_valid = false;
+    PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
 pty_status pty_mem_bytes(const pty_ctx* c, size_t* out) {
   return guarded(const_cast<pty_ctx*>(c), [&] {
     require(c != nullptr && out != nullptr, "pty_mem_bytes: null argument");

@@ -160,6 +160,21 @@ class Plan:
         self._check(self._lib.pty_get_errors(self._live(), buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
         return buf[: n.value].copy()
 
+    def state(self) -> bytes:
+        """Checkpoint of what object and probe do not carry (iteration
+        counter, error and NRMSE histories, current DM exit waves), for
+        `set_state` on a plan of the same shape."""
+        n = C.c_size_t()
+        self._check(self._lib.pty_get_state(self._live(), None, 0, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self._lib.pty_get_state(self._live(), buf.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+        return buf.tobytes()
+
+    def set_state(self, blob: bytes) -> None:
+        """Restores a checkpoint from `state`; call after set_object / set_probe."""
+        buf = np.frombuffer(blob, dtype=np.uint8)
+        self._check(self._lib.pty_set_state(self._live(), buf.ctypes.data_as(C.c_void_p), buf.size))
+
     def lsqml_steps(self) -> np.ndarray:
         out = np.empty((self.n_pos, 2), dtype=np.float32)
         self._check(self._lib.pty_get_lsqml_steps(self._live(), out.ctypes.data_as(C.c_void_p)))

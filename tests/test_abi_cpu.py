@@ -69,6 +69,9 @@ def test_null_arguments_are_invalid():
     n = C.c_int32()
     assert lib.pty_get_errors(None, None, 0, C.byref(n)) == L.E_INVALID
     assert lib.pty_mem_bytes(None, None) == L.E_INVALID
+    sz = C.c_size_t()
+    assert lib.pty_get_state(None, None, 0, C.byref(sz)) == L.E_INVALID
+    assert lib.pty_set_state(None, None, 0) == L.E_INVALID
     lib.pty_destroy(None)  # NULL-safe
 
 
