@@ -146,23 +146,37 @@ def scatter_add(acc: np.ndarray, y: np.ndarray, r) -> None:
 # ---------------------------------------------------------------------------
 # Data, projection, forward model
 # ---------------------------------------------------------------------------
-def amplitude(d: np.ndarray) -> np.ndarray:
-    """Measured moduli in natural order: A = sqrt(ifftshift(d)) (Sec. 3.2 normalisation)."""
+def amplitude(d: np.ndarray, mask: np.ndarray | None = None) -> np.ndarray:
+    """Measured moduli in natural order: A = sqrt(ifftshift(d)) (Sec. 3.2 normalisation).
+
+    ``mask``: optional detector mask in the same centred layout as one pattern,
+    nonzero where the pixel measured something (saturated or dead pixels and
+    a beam stop are the excluded ones, Sec. 2.2's preprocessing parameters).
+    Unmeasured pixels get NaN: no measurement.
+    """
     d = np.asarray(d, dtype=np.float64)
-    return np.sqrt(np.fft.ifftshift(d, axes=(-2, -1)))
+    a = np.sqrt(np.fft.ifftshift(d, axes=(-2, -1)))
+    if mask is not None:
+        valid = np.fft.ifftshift(np.asarray(mask) != 0)
+        a = np.where(valid, a, np.nan)
+    return a
 
 
 def project_delta(psi_f: np.ndarray, a: np.ndarray):
     """Difference Delta = Pi(Psi) - Psi of the multi-mode modulus projection.
 
-    ``psi_f``: (K, N, N) far field; ``a``: (N, N) measured moduli.
-    Returns (Delta, sum (sqrt(I) - A)^2, sum A^2).
+    ``psi_f``: (K, N, N) far field; ``a``: (N, N) measured moduli, NaN where
+    nothing was measured: there the projection keeps the model (Delta = 0)
+    and the pixel adds nothing to either error sum.
+    Returns (Delta, sum (sqrt(I) - A)^2, sum A^2) over the measured pixels.
     """
     inten = np.sum(np.abs(psi_f) ** 2, axis=0)
     mod = np.sqrt(inten)
-    ratio = a / np.maximum(mod, EPS_M)
+    valid = np.isfinite(a)
+    am = np.where(valid, a, 0.0)
+    ratio = np.where(valid, am / np.maximum(mod, EPS_M), 1.0)
     delta = (ratio - 1.0)[None] * psi_f
-    return delta, float(np.sum((mod - a) ** 2)), float(np.sum(a * a))
+    return delta, float(np.sum(np.where(valid, (mod - am) ** 2, 0.0))), float(np.sum(am * am))
 
 
 def forward_intensity(obj: np.ndarray, probe: np.ndarray, r) -> np.ndarray:
@@ -469,29 +483,41 @@ def phase_aligned_rel(x, y) -> float:
 # ---------------------------------------------------------------------------
 # Poisson negative log-likelihood and its gradients
 # ---------------------------------------------------------------------------
-def nll(obj, probe, pos, d, eps=EPS_L) -> float:
-    """L = sum_j sum_q [I_jq - d_jq log(I_jq + eps)], d given centred (log(d!) dropped)."""
+def _measured(mask, n):
+    """Natural-order boolean plane of measured pixels (all of them without a mask)."""
+    if mask is None:
+        return np.ones((n, n), dtype=bool)
+    return np.fft.ifftshift(np.asarray(mask) != 0)
+
+
+def nll(obj, probe, pos, d, eps=EPS_L, mask=None) -> float:
+    """L = sum_j sum_q [I_jq - d_jq log(I_jq + eps)] over the measured pixels,
+    d given centred (log(d!) dropped); ``mask`` as in ``amplitude``."""
     n = probe.shape[-1]
     dn = np.fft.ifftshift(np.asarray(d, dtype=np.float64), axes=(-2, -1))
+    valid = _measured(mask, n)
     total = 0.0
     for j, r in enumerate(pos):
         inten = np.sum(np.abs(fft2u(probe * gather(obj, r, n)[None])) ** 2, axis=0)
-        total += float(np.sum(inten - dn[j] * np.log(inten + eps)))
+        total += float(np.sum(np.where(valid, inten - dn[j] * np.log(inten + eps), 0.0)))
     return total
 
 
-def nll_grad(obj, probe, pos, d, eps=EPS_L):
+def nll_grad(obj, probe, pos, d, eps=EPS_L, mask=None):
     """(L, g_O, g_P, g_R) in PyTorch's convention for complex leaves.
 
     For a real loss of complex z the gradient is dL/dRe z + i dL/dIm z.  With
     g_psi = F^-1[(1 - d/(I + eps)) Psi] (the derivative with respect to conj(psi)):
     g_O = 2 sum_j S_j^T sum_k conj(P_k) g_psi,jk;  g_P,k = 2 sum_j conj(S_j O) g_psi,jk;
     dL/dy_j = 2 Re sum_k sum_r conj(g_psi,jk) P_k d_y(S_j O), likewise for x.
+    Unmeasured pixels (``mask`` as in ``amplitude``) add nothing to L, so their
+    factor (1 - d/(I + eps)) is 0.
     """
     obj = np.asarray(obj, dtype=np.complex128)
     probe = np.asarray(probe, dtype=np.complex128)
     n = probe.shape[-1]
     dn = np.fft.ifftshift(np.asarray(d, dtype=np.float64), axes=(-2, -1))
+    valid = _measured(mask, n)
     g_o = np.zeros_like(obj)
     g_p = np.zeros_like(probe)
     g_r = np.zeros((len(pos), 2))
@@ -500,8 +526,8 @@ def nll_grad(obj, probe, pos, d, eps=EPS_L):
         oj = gather(obj, r, n)
         psi_f = fft2u(probe * oj[None])
         inten = np.sum(np.abs(psi_f) ** 2, axis=0)
-        total += float(np.sum(inten - dn[j] * np.log(inten + eps)))
-        g_psi = ifft2u((1.0 - dn[j] / (inten + eps))[None] * psi_f)
+        total += float(np.sum(np.where(valid, inten - dn[j] * np.log(inten + eps), 0.0)))
+        g_psi = ifft2u(np.where(valid, 1.0 - dn[j] / (inten + eps), 0.0)[None] * psi_f)
         scatter_add(g_o, 2.0 * np.sum(np.conj(probe) * g_psi, axis=0), r)
         g_p += 2.0 * np.conj(oj)[None] * g_psi
         dy, dx = gather_grad(obj, r, n)
