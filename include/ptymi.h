@@ -117,6 +117,18 @@ pty_status pty_create(const pty_plan_desc* plan, pty_ctx** out);
  * counts are treated as 0. */
 pty_status pty_load_patterns(pty_ctx* ctx, const float* counts, int on_device);
 
+/* Detector mask shared by all patterns: N x N bytes in host memory, in the
+ * counts' centred layout, nonzero where the pixel measured something and 0
+ * where it did not (saturated or dead pixels, a beam stop: what Sec. 2.2's
+ * saturated-pixel and noise-threshold preprocessing parameters exclude).  At
+ * an unmeasured pixel the modulus projection keeps the model, and the pixel
+ * adds nothing to the amplitude error E or to the Poisson likelihood and its
+ * gradients.  May be called before or after pty_load_patterns and changed
+ * between iterations; mask == NULL measures every pixel again.  Copies the
+ * mask; synchronises.  A mask that leaves no pixel measured makes E 0/0
+ * (PTY_E_NUMERIC at pty_get_errors). */
+pty_status pty_set_mask(pty_ctx* ctx, const uint8_t* mask);
+
 /* Loads J scan positions, J x 2 float64 (y, x), top-left corner of each patch
  * in object pixels.  Every patch must lie inside the object:
  * 0 <= y, floor(y) + N + (y non-integer) <= H, likewise for x with W. */

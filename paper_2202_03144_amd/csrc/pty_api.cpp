@@ -68,6 +68,8 @@ struct pty_ctx {
   float2* probe = nullptr;
   float2* probe_alt = nullptr;
   float* amp = nullptr;
+  unsigned char* mask = nullptr;   // detector mask, natural order, 1 = measured
+  bool have_mask = false;
   PosInfo* pos = nullptr;
   float2* tw = nullptr;
   int* jl_identity = nullptr;
@@ -1208,6 +1210,7 @@ pty_status pty_load_patterns(pty_ctx* c, const float* counts, int on_device) {
     }
     try {
       launch_amplitude(src, c->amp, nullptr, c->N, c->J, c->stream);
+      if (c->have_mask) launch_apply_mask(c->amp, c->mask, c->N, c->J, c->stream);
       PTY_HIP(hipStreamSynchronize(c->stream));
     } catch (...) {
       c->dfree(tmp);
@@ -1215,6 +1218,25 @@ pty_status pty_load_patterns(pty_ctx* c, const float* counts, int on_device) {
     }
     c->dfree(tmp);
     c->have_patterns = true;
+  });
+}
+
+pty_status pty_set_mask(pty_ctx* c, const uint8_t* mask) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_set_mask: null context");
+    c->set_device();
+    const int n = c->N, h = n / 2;
+    if (mask) {
+      std::vector<unsigned char> nat(size_t(n) * n);
+      for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x)
+          nat[size_t(y) * n + x] = mask[size_t((y + h) % n) * n + (x + h) % n] ? 1 : 0;
+      c->ensure_once(c->mask, nat.size());
+      copy_in(c, c->mask, nat.data(), nat.size(), 0);
+    }
+    c->have_mask = mask != nullptr;
+    if (c->have_patterns) launch_apply_mask(c->amp, c->have_mask ? c->mask : nullptr, c->N, c->J, c->stream);
+    PTY_HIP(hipStreamSynchronize(c->stream));
   });
 }
 

@@ -138,24 +138,28 @@ void k_cols(FourierArgs a) {
         a.intensity_out[((size_t)j * N + ((pr + N / 2) & (N - 1))) * N + ((x + N / 2) & (N - 1))] = inten;
     } else if constexpr (OP == ColOp::NllLoss) {
       if (lead) {
-        const float am = a.amp[((size_t)j * N + pr) * N + x];
-        const float d = am * am;
-        e_num += inten - d * logf(inten + a.nll_eps);
+        const float ar = a.amp[((size_t)j * N + pr) * N + x];
+        const float d = ar * ar;
+        if (!signbit(ar)) e_num += inten - d * logf(inten + a.nll_eps);
       }
     } else {
-      const float am = a.amp[((size_t)j * N + pr) * N + x];
+      // a set sign bit marks a pixel without a measurement: the projection
+      // keeps the model there and the pixel adds to no sum
+      const float ar = a.amp[((size_t)j * N + pr) * N + x];
+      const bool meas = !signbit(ar);
+      const float am = fabsf(ar);
       float f;
       if constexpr (OP == ColOp::Project) {
         const float mod = sqrtf(iraw) * sc;
-        f = am / fmaxf(mod, 1e-6f) - 1.f;
-        if (lead) {
+        f = meas ? am / fmaxf(mod, 1e-6f) - 1.f : 0.f;
+        if (lead && meas) {
           e_num += (mod - am) * (mod - am);
           e_den += am * am;
         }
       } else {
         const float d = am * am;
-        f = a.grad_scale * (1.f - d / (inten + a.nll_eps));
-        if (lead) e_num += inten - d * logf(inten + a.nll_eps);
+        f = meas ? a.grad_scale * (1.f - d / (inten + a.nll_eps)) : 0.f;
+        if (lead && meas) e_num += inten - d * logf(inten + a.nll_eps);
       }
       f *= sc2;
 #pragma unroll

@@ -476,7 +476,18 @@ __global__ __launch_bounds__(256) void k_amplitude(const float* __restrict__ cnt
   const int pr = (int)((i % nn) / n), pc = (int)(i % n);
   const int h = n / 2;
   const float d = cnt[j * nn + (size_t)((pr + h) & (n - 1)) * n + ((pc + h) & (n - 1))];
-  amp[i] = sqrtf(fmaxf(d, 0.f));
+  amp[i] = d > 0.f ? sqrtf(d) : 0.f;   // +0 for d <= 0 and NaN: a clear sign bit means measured
+}
+
+// Detector mask: the sign bit of a stored modulus marks a pixel without a
+// measurement (-0 included), so masking is reversible and costs the Fourier
+// passes no extra load.  mask == nullptr: every pixel measured.
+__global__ __launch_bounds__(256) void k_apply_mask(float* __restrict__ amp, const unsigned char* __restrict__ mask,
+                                                    size_t nn, size_t total) {
+  const size_t i = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (i >= total) return;
+  const float v = fabsf(amp[i]);
+  amp[i] = (mask == nullptr || mask[i % nn]) ? v : -v;
 }
 
 __global__ __launch_bounds__(256) void k_pattern_totals(const float* __restrict__ x, double* totals, int n) {
@@ -675,10 +686,13 @@ __global__ __launch_bounds__(kEpieThreads) void k_epie_fused(EpieRunArgs a) {
 #pragma unroll
       for (int k = 0; k < K; ++k) iraw += cabs2(Z[(k * N + u) * P + v]);
       const float mod = sqrtf(iraw) * sc;
-      const float am = amp_c[r];
-      const float f = (am / fmaxf(mod, 1e-6f) - 1.f) * sc2;
-      en += (mod - am) * (mod - am);
-      ed += am * am;
+      const bool meas = !signbit(amp_c[r]);      // sign bit: no measurement
+      const float am = fabsf(amp_c[r]);
+      const float f = meas ? (am / fmaxf(mod, 1e-6f) - 1.f) * sc2 : 0.f;
+      if (meas) {
+        en += (mod - am) * (mod - am);
+        ed += am * am;
+      }
 #pragma unroll
       for (int k = 0; k < K; ++k) Z[(k * N + u) * P + v] = f * Z[(k * N + u) * P + v];
     }
@@ -902,6 +916,12 @@ void launch_amplitude(const float* counts, float* amp, double* totals, int n, in
   k_amplitude<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(counts, amp, n, total);
   PTY_LAUNCH_CHECK("amplitude");
   if (totals) launch_pattern_totals(counts, totals, n, j, s);
+}
+
+void launch_apply_mask(float* amp, const unsigned char* mask, int n, int j, hipStream_t s) {
+  const size_t total = (size_t)j * n * n;
+  k_apply_mask<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(amp, mask, (size_t)n * n, total);
+  PTY_LAUNCH_CHECK("apply_mask");
 }
 
 void launch_pattern_totals(const float* x, double* totals, int n, int j, hipStream_t s) {

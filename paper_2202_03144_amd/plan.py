@@ -160,6 +160,17 @@ class Plan:
         self._check(self._lib.pty_get_errors(self._live(), buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
         return buf[: n.value].copy()
 
+    def set_mask(self, mask) -> None:
+        """Detector mask (N x N, centred like the counts, nonzero = measured);
+        None measures every pixel again."""
+        if mask is None:
+            self._check(self._lib.pty_set_mask(self._live(), None))
+            return
+        m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+        if m.shape != (self.n, self.n):
+            raise ValueError(f"mask must be {self.n} x {self.n}")
+        self._check(self._lib.pty_set_mask(self._live(), m.ctypes.data_as(C.c_void_p)))
+
     def state(self) -> bytes:
         """Checkpoint of what object and probe do not carry (iteration
         counter, error and NRMSE histories, current DM exit waves), for
