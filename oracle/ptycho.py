@@ -59,6 +59,7 @@ __all__ = [
     "dm_init",
     "dm",
     "lsqml_solve2",
+    "position_shift",
     "lsqml",
     "illumination",
     "roi_mask",
@@ -365,8 +366,26 @@ def lsqml_solve2(m00, m11, m01, v0, v1, probe_on=True):
     return (a11 * v0 - m01 * v1) / det, (a00 * v1 - m01 * v0) / det
 
 
+def position_shift(obj, probe, chi, r, max_shift):
+    """Least-squares shift of one position from its exit-wave update (LSQML's
+    position correction, Odstrcil et al. 2018): with d_y psi_k = P_k d_y(S_j O)
+    (and likewise x), the shift along each axis that best explains chi,
+    sum Re(conj(d psi) chi) / sum |d psi|^2 (0 where the denominator is 0),
+    clipped to [-max_shift, max_shift]."""
+    n = probe.shape[-1]
+    dy, dx = gather_grad(obj, r, n)
+    out = np.zeros(2)
+    for ax, d in enumerate((dy, dx)):
+        dpsi = probe * d[None]
+        den = float(np.sum(np.abs(dpsi) ** 2))
+        if den > 0.0:
+            out[ax] = float(np.real(np.vdot(dpsi, chi))) / den
+    return np.clip(out, -max_shift, max_shift)
+
+
 def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
-          gamma_probe=1e-3, beta_obj=1.0, beta_probe=1.0, return_alpha=False):
+          gamma_probe=1e-3, beta_obj=1.0, beta_probe=1.0, return_alpha=False,
+          pos_start=-1, max_shift=0.5, return_positions=False):
     """``n_iter`` LSQML iterations; returns (object, probe, [E], alpha of last iteration).
 
     Positions are split into G = ceil(J / batch) interleaved groups
@@ -381,10 +400,17 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
       :func:`lsqml_solve2` from sums over pixels and modes of |a|^2, |b|^2,
       Re conj(a) b, Re conj(a) chi, Re conj(b) chi;
     * update: O += beta_O sum S_j^T(alpha_O,j sum_k conj(P_k) chi_jk) / (den_O + delta_O),
-      P_k += beta_P sum alpha_P,j conj(S_j O) chi_jk / (den_P + delta_P)  (t >= start).
+      P_k += beta_P sum alpha_P,j conj(S_j O) chi_jk / (den_P + delta_P)  (t >= start);
+    * position refinement (t >= pos_start >= 0): after the group's update each
+      of its positions moves by :func:`position_shift` of its pass-A chi
+      (object and probe at the start of the group), kept inside the object
+      (0 <= R <= size - N).  ``return_positions`` adds the refined positions
+      to the returned tuple.
     """
     obj = np.array(obj, dtype=np.complex128)
     probe = np.array(probe, dtype=np.complex128)
+    pos = np.array(pos, dtype=np.float64)
+    lim = np.array([obj.shape[0] - probe.shape[-1], obj.shape[1] - probe.shape[-1]], dtype=np.float64)
     n = probe.shape[-1]
     jn = len(pos)
     g_count = max(1, -(-jn // batch))
@@ -392,6 +418,7 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
     alpha = np.zeros((jn, 2))
     for t in range(t0, t0 + n_iter):
         probe_on = t >= start
+        refine = 0 <= pos_start <= t
         e_num = e_den = 0.0
         for g in range(g_count):
             idx = range(g, jn, g_count)
@@ -416,6 +443,7 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
             d_p = gamma_probe * float(den_p.max())
             dir_p = num_p / (den_p + d_p) if probe_on else np.zeros_like(probe)
 
+            shifts = {j: position_shift(obj, probe, chis[j], pos[j], max_shift) for j in idx} if refine else {}
             for j in idx:
                 av = probe * gather(dir_o, pos[j], n)[None]
                 bv = dir_p * ojs[j][None]
@@ -435,10 +463,11 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
             obj = obj + beta_obj * upd_o / (den_o + d_o)
             if probe_on:
                 probe = probe + beta_probe * upd_p / (den_p + d_p)
+            for j, sh in shifts.items():
+                pos[j] = np.clip(pos[j] + sh, 0.0, lim)
         errs.append(e_num / e_den)
-    if return_alpha:
-        return obj, probe, errs, alpha
-    return obj, probe, errs
+    out = (obj, probe, errs) + ((alpha,) if return_alpha else ()) + ((pos,) if return_positions else ())
+    return out
 
 
 # ---------------------------------------------------------------------------
