@@ -519,6 +519,73 @@ def adjoint_leg(args, torch) -> dict:
     }
 
 
+def positions_leg(args, torch) -> dict:
+    """LSQML given the nominal (unjittered) spiral positions of the 256 x 256,
+    3-mode, 2,500-position workload whose data were recorded at the jittered
+    ones: with and without position refinement, NRMSE and position error
+    against the truth, and the per-iteration cost of refining."""
+    import dataclasses
+    import ptysynth
+    from paper_2202_03144_amd import Plan
+
+    wl, obj_true, probe, pos_true, counts = make_inputs(torch)
+    nominal = dataclasses.replace(wl, jitter=False).positions()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    iters = args.position_iters
+    base = dict(probe_update_start=wl.probe_start, lsqml_batch=500)
+
+    def err(p):
+        d = p - pos_true
+        return float(np.sqrt(np.mean((d - d.mean(0)) ** 2)))
+
+    def run(refine: bool):
+        pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
+        pl.load_patterns(counts)
+        pl.load_positions(nominal)
+        pl.set_object(np.ones((wl.h, wl.w), np.complex64))
+        pl.set_probe(probe)
+        pl.set_truth(obj_true, 0.3)
+        prm = dict(base, position_start=args.position_start) if refine else base
+        pl.iterate("lsqml", 0, **prm)
+        pl.sync()
+        t = time.perf_counter()
+        pl.iterate("lsqml", iters, **prm)
+        pl.sync()
+        ms = (time.perf_counter() - t) * 1e3 / iters
+        h, e, p = pl.nrmse_history(), pl.errors(), pl.positions()
+        # one more iteration with per-family kernel timing (event-bracketed)
+        pl.set_timing(True)
+        pl.iterate("lsqml", 1, **prm)
+        fam = {k: round(v[0], 3) for k, v in pl.timing().items() if v[1]}
+        pl.set_timing(False)
+        pl.close()
+        at = {str(i): round(float(h[i - 1]), 5) for i in (1, 5, 10, 20, 30, 50, 100) if i <= len(h)}
+        return {"ms_per_iter": round(ms, 3), "nrmse_at": at, "e_last": float(e[-1]),
+                "position_rms_error_px": round(err(p), 4), "kernel_ms_one_iteration": fam,
+                "kernel_ms_total": round(sum(fam.values()), 3)}
+
+    log("plain")
+    plain = run(False)
+    log(f"plain: {plain}")
+    log("refined")
+    refined = run(True)
+    log(f"refined: {refined}")
+    return {
+        "metric": "LSQML with position refinement: NRMSE and position error from nominal positions",
+        "value": refined["nrmse_at"][str(iters)], "unit": "NRMSE", "n_gpus": 1, "higher_is_better": False,
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256x256 probe, 3 modes, 2,500-point Fermat spiral, 1700x1700 object, Poisson 1e8; "
+                               "data at the jittered positions (+-0.5 px), solver given the unjittered ones; "
+                               f"LSQML groups of 500, probe updates from {wl.probe_start}, refinement from "
+                               f"{args.position_start}, {iters} iterations (host-timed, incl. the patch-list rebuild)",
+                   "n": wl.n, "modes": wl.k, "positions": wl.j},
+        "nominal_position_rms_error_px": round(err(nominal), 4),
+        "plain": plain, "refined": refined,
+        "refinement_cost": round(refined["ms_per_iter"] / plain["ms_per_iter"], 3),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -547,6 +614,10 @@ def main() -> int:
     ap.add_argument("--tiny", action="store_true",
                     help="instead: the 64x64 one-mode raster workload, ePIE / DM / LSQML eager and graphed")
     ap.add_argument("--batch-iters", type=int, default=5)
+    ap.add_argument("--positions", action="store_true",
+                    help="instead: LSQML from nominal positions with and without position refinement")
+    ap.add_argument("--position-iters", type=int, default=30)
+    ap.add_argument("--position-start", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing was run.",
@@ -570,6 +641,9 @@ def main() -> int:
         return 0
     if args.tiny:
         print(json.dumps(tiny_leg(args, torch)), flush=True)
+        return 0
+    if args.positions:
+        print(json.dumps(positions_leg(args, torch)), flush=True)
         return 0
     log("building config-2 inputs")
     wl, obj_true, probe, pos, counts = make_inputs(torch)

@@ -89,7 +89,21 @@ typedef struct {
  *                        once per distinct setting into a HIP graph and
  *                        replayed (fewer launches; same kernels, same results
  *                        as eager iterations); ignored for ePIE.  Kernel
- *                        timing is suspended while graphs run. */
+ *                        timing is suspended while graphs run.
+ *   position_start       LSQML position refinement from this global iteration
+ *                        on; < 0 = never (default).  Each position moves by
+ *                        the least-squares shift that explains its exit-wave
+ *                        update along each axis (LSQML's position correction,
+ *                        Odstrcil et al. 2018: sum Re(conj(d psi) chi) /
+ *                        sum |d psi|^2 with d psi = P_k d(S_j O)/dy, /dx),
+ *                        computed with the group's object and probe and
+ *                        applied after the group's update, kept inside the
+ *                        object.  The patch lists are rebuilt on the host
+ *                        after each such iteration, so these iterations
+ *                        synchronise; PTY_E_UNSUPPORTED with ePIE, DM or
+ *                        PTY_ITER_GRAPH.  pty_get_positions returns them.
+ *   position_max_shift   clip of each shift component per iteration, pixels
+ *                        (default 0.5). */
 #define PTY_ITER_GRAPH 1u
 typedef struct {
   float alpha, beta;
@@ -100,6 +114,8 @@ typedef struct {
   uint64_t order_seed;
   int32_t chunk;
   uint32_t flags; /* 0 or PTY_ITER_GRAPH */
+  int32_t position_start;
+  float position_max_shift;
 } pty_iter_params;
 
 /* Fills *p with the defaults listed above. */
@@ -167,6 +183,11 @@ pty_status pty_get_lsqml_steps(pty_ctx* ctx, float* out);
 /* Copies the DM exit waves, J x K x N x N complex64 (host or device); sync.
  * PTY_E_STATE if DM has not run since the last change of object or probe. */
 pty_status pty_get_exit_waves(pty_ctx* ctx, void* out, int on_device);
+
+/* Current scan positions, J x 2 float64 (y, x), into host memory: the loaded
+ * ones, or the refined ones after LSQML iterations with position refinement.
+ * Synchronises.  PTY_E_STATE before pty_load_positions. */
+pty_status pty_get_positions(pty_ctx* ctx, double* yx);
 
 /* Device memory currently held by the context, in bytes. */
 pty_status pty_mem_bytes(const pty_ctx* ctx, size_t* out);

@@ -49,6 +49,8 @@ class IterParams(C.Structure):
         ("order_seed", C.c_uint64),
         ("chunk", C.c_int32),
         ("flags", C.c_uint32),
+        ("position_start", C.c_int32),
+        ("position_max_shift", C.c_float),
     ]
 
 
@@ -68,6 +70,7 @@ SIGNATURES = {
     "pty_get_exit_waves": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pty_mem_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "pty_set_mask": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pty_get_positions": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pty_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "pty_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "pty_sync": (C.c_int, [C.c_void_p]),

@@ -43,6 +43,7 @@ struct TileSet {
   PatchRef* refs = nullptr;
   int ntiles = 0;
   int nrefs = 0;
+  size_t tiles_cap = 0, refs_cap = 0;   // allocated entries (lists are rebuilt in place)
 };
 
 // A set of positions iterated together (DM: all; LSQML: one group).
@@ -104,6 +105,7 @@ struct pty_ctx {
   double* lsq_part = nullptr;      size_t lsq_part_n = 0;
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
+  float2* shift = nullptr;         size_t shift_slots = 0;   // LSQML position shifts per slot
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
 
   // device-side iteration counter (error / NRMSE history slot of the running
@@ -317,28 +319,60 @@ void copy_out(pty_ctx* c, void* dst, const void* src, size_t bytes, int on_devic
 // footprint overlaps it, in slot order.
 void build_tiles(pty_ctx* c, Group& g) {
   const int nty = (c->H + kTileH - 1) / kTileH, ntx = (c->W + kTileW - 1) / kTileW;
-  std::vector<std::vector<PatchRef>> per(size_t(nty) * ntx);
+  const size_t nt = size_t(nty) * ntx;
+  auto span = [&](const PosInfo& p, int& y0, int& y1, int& x0, int& x1) {
+    y0 = p.iy / kTileH;
+    y1 = std::min(nty - 1, (p.iy + c->N) / kTileH);
+    x0 = p.ix / kTileW;
+    x1 = std::min(ntx - 1, (p.ix + c->N) / kTileW);
+  };
+  // counting sort by tile: entries per tile, tile offsets, then the entries
+  // in slot order within each tile
+  std::vector<int> cnt(nt, 0);
+  for (int s = 0; s < (int)g.jl.size(); ++s) {
+    int y0, y1, x0, x1;
+    span(c->hpos[g.jl[s]], y0, y1, x0, x1);
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) ++cnt[size_t(ty) * ntx + tx];
+  }
+  std::vector<TileEntry> tiles;
+  std::vector<int> next(nt, 0);
+  int total = 0;
+  for (int ty = 0; ty < nty; ++ty)
+    for (int tx = 0; tx < ntx; ++tx) {
+      const size_t t = size_t(ty) * ntx + tx;
+      if (!cnt[t]) continue;
+      tiles.push_back({ty * kTileH, tx * kTileW, total, total + cnt[t]});
+      next[t] = total;
+      total += cnt[t];
+    }
+  std::vector<PatchRef> refs(total);
   for (int s = 0; s < (int)g.jl.size(); ++s) {
     const int j = g.jl[s];
     const PosInfo& p = c->hpos[j];
-    const int y0 = p.iy / kTileH, y1 = std::min(nty - 1, (p.iy + c->N) / kTileH);
-    const int x0 = p.ix / kTileW, x1 = std::min(ntx - 1, (p.ix + c->N) / kTileW);
+    int y0, y1, x0, x1;
+    span(p, y0, y1, x0, x1);
     for (int ty = y0; ty <= y1; ++ty)
-      for (int tx = x0; tx <= x1; ++tx) per[size_t(ty) * ntx + tx].push_back({s, j, p.iy, p.ix, p.fy, p.fx, 0, 0});
+      for (int tx = x0; tx <= x1; ++tx) refs[next[size_t(ty) * ntx + tx]++] = {s, j, p.iy, p.ix, p.fy, p.fx, 0, 0};
   }
-  std::vector<TileEntry> tiles;
-  std::vector<PatchRef> refs;
-  for (int ty = 0; ty < nty; ++ty)
-    for (int tx = 0; tx < ntx; ++tx) {
-      auto& v = per[size_t(ty) * ntx + tx];
-      if (v.empty()) continue;
-      tiles.push_back({ty * kTileH, tx * kTileW, (int)refs.size(), (int)(refs.size() + v.size())});
-      refs.insert(refs.end(), v.begin(), v.end());
-    }
   g.tiles.ntiles = (int)tiles.size();
   g.tiles.nrefs = (int)refs.size();
-  g.tiles.tiles = c->alloc<TileEntry>(std::max<size_t>(1, tiles.size()));
-  g.tiles.refs = c->alloc<PatchRef>(std::max<size_t>(1, refs.size()));
+  // reuse the lists' buffers when they are large enough (position refinement
+  // rebuilds them every iteration), with a quarter of headroom when growing
+  if (!g.tiles.tiles || g.tiles.tiles_cap < tiles.size()) {
+    const size_t cap = std::max<size_t>(1, tiles.size() + tiles.size() / 4);
+    TileEntry* nb = c->alloc<TileEntry>(cap);
+    c->dfree(g.tiles.tiles);
+    g.tiles.tiles = nb;
+    g.tiles.tiles_cap = cap;
+  }
+  if (!g.tiles.refs || g.tiles.refs_cap < refs.size()) {
+    const size_t cap = std::max<size_t>(1, refs.size() + refs.size() / 4);
+    PatchRef* nb = c->alloc<PatchRef>(cap);
+    c->dfree(g.tiles.refs);
+    g.tiles.refs = nb;
+    g.tiles.refs_cap = cap;
+  }
   PTY_HIP(hipMemcpy(g.tiles.tiles, tiles.data(), tiles.size() * sizeof(TileEntry), hipMemcpyHostToDevice));
   PTY_HIP(hipMemcpy(g.tiles.refs, refs.data(), refs.size() * sizeof(PatchRef), hipMemcpyHostToDevice));
 }
@@ -639,6 +673,16 @@ void run_dm(pty_ctx* c, int n_iter, const pty_iter_params& p) {
 // ---------------------------------------------------------------------------
 // LSQML
 // ---------------------------------------------------------------------------
+// After positions moved on the device: the host copy, and every patch list
+// built from it (LSQML groups now; the all-positions group on its next use).
+void refresh_positions(pty_ctx* c) {
+  PTY_HIP(hipMemcpyAsync(c->hpos.data(), c->pos, sizeof(PosInfo) * c->J, hipMemcpyDeviceToHost, c->stream));
+  PTY_HIP(hipStreamSynchronize(c->stream));
+  for (auto& g : c->groups) build_tiles(c, g);
+  free_group(c, c->all);
+  c->den_valid = false;
+}
+
 void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   const float g_obj = p.gamma_obj < 0 ? 1e-3f : p.gamma_obj;
   const float g_prb = p.gamma_probe < 0 ? 1e-3f : p.gamma_probe;
@@ -656,13 +700,16 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   const int nrb = c->N * c->N >= 2048 ? c->N * c->N / 2048 : 1;  // row blocks of the step sums
   c->ensure_once(c->lsq_pq, nn);
   c->ensure_once(c->lsq_dint, nn);
-  c->ensure(c->lsq_part, c->lsq_part_n, size_t(bmax) * nrb * 5);
+  const bool refining = p.position_start >= 0 && p.position_start < c->iter + n_iter;
+  c->ensure(c->lsq_part, c->lsq_part_n, size_t(bmax) * nrb * (refining ? 9 : 5));
+  if (refining) c->ensure(c->shift, c->shift_slots, size_t(bmax));
   ensure_probe_parts(c, bmax);
   ensure_err_slot(c, n_iter);
   c->dm_valid = false;
   for (int it = 0; it < n_iter; ++it) {
     const int t = c->iter;
     const bool pon = probe_on(p, t);
+    const bool refine = p.position_start >= 0 && t >= p.position_start;
     for (auto& g : c->groups) {
       const int count = (int)g.jl.size();
       density(c, g);
@@ -696,6 +743,8 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       ls.part = c->lsq_part;
       ls.alpha = c->alpha;
       ls.alpha_by_j = c->alpha_by_j;
+      ls.shift = refine ? c->shift : nullptr;
+      ls.max_shift = p.position_max_shift;
       ls.stream = c->stream;
       timed(c, kLsqSteps, [&] { launch_lsq_steps(ls); });
       if (pon) probe_reduce(c, g, c->chi, 0, PrbOp::AlphaWeighted, c->num_p2, false);
@@ -704,8 +753,13 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       u.beta = p.beta_obj;
       timed(c, kObjGather, [&] { launch_obj_gather(u, ObjOp::LsqUpdate); });
       if (pon) probe_apply(c, PrbApply::LsqUpdate, c->num_p2, g_prb, p.beta_probe);
+      if (refine)
+        timed(c, kOther, [&] {
+          launch_pos_update(c->pos, g.d_jl, c->shift, count, c->H - c->N, c->W - c->N, c->stream);
+        });
     }
     end_iteration(c, t);
+    if (refine) refresh_positions(c);
   }
   c->den_valid = false;  // den holds the last group's density only
 }
@@ -943,7 +997,8 @@ bool same_params(const pty_iter_params& a, const pty_iter_params& b) {
   return a.alpha == b.alpha && a.beta == b.beta && a.probe_update_start == b.probe_update_start &&
          a.lsqml_batch == b.lsqml_batch && a.gamma_obj == b.gamma_obj && a.gamma_probe == b.gamma_probe &&
          a.beta_obj == b.beta_obj && a.beta_probe == b.beta_probe && a.order_seed == b.order_seed &&
-         a.chunk == b.chunk && a.flags == b.flags;
+         a.chunk == b.chunk && a.flags == b.flags && a.position_start == b.position_start &&
+         a.position_max_shift == b.position_max_shift;
 }
 
 // Iterations as replays of captured single iterations (DM and LSQML).  Each
@@ -1083,6 +1138,7 @@ int tune_chunk(pty_ctx* c, int algo, pty_iter_params p) {
     PTY_HIP(hipEventCreate(&e1));
     c->timing = false;
     p.flags = 0;
+    p.position_start = -1;   // tuning iterations never move positions
     float best_ms = 0.f;
     for (int v : cands) {
       p.chunk = v;
@@ -1144,6 +1200,8 @@ pty_status pty_default_params(pty_iter_params* p) {
     p->order_seed = 0;
     p->chunk = 0;
     p->flags = 0;
+    p->position_start = -1;
+    p->position_max_shift = 0.5f;
   });
 }
 
@@ -1300,6 +1358,13 @@ pty_status pty_iterate(pty_ctx* c, pty_algo algo, int32_t n_iter, const pty_iter
     require((p.flags & ~PTY_ITER_GRAPH) == 0, "pty_iterate: unknown flags");
     require(p.chunk >= 0, "pty_iterate: negative chunk");
     require(p.lsqml_batch >= 0, "pty_iterate: negative lsqml_batch");
+    if (p.position_start >= 0) {
+      require(std::isfinite(p.position_max_shift) && p.position_max_shift > 0.f,
+              "pty_iterate: position_max_shift must be positive");
+      if (algo != PTY_LSQML) throw Unsupported("pty_iterate: position refinement runs in LSQML only");
+      if (p.flags & PTY_ITER_GRAPH)
+        throw Unsupported("pty_iterate: position refinement rebuilds the patch lists on the host; no graph replay");
+    }
     require_loaded(c);
     if (n_iter == 0 && algo == PTY_EPIE) return;
     c->set_device();
@@ -1459,6 +1524,20 @@ pty_status pty_set_state(pty_ctx* c, const void* in, size_t n) {
     c->dm_valid = h.has_psi == 1;
     c->den_valid = false;
     PTY_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+pty_status pty_get_positions(pty_ctx* c, double* yx) {
+  return guarded(c, [&] {
+    require(c != nullptr && yx != nullptr, "pty_get_positions: null argument");
+    if (!c->have_positions) throw StateError("pty_get_positions: positions not loaded");
+    c->set_device();
+    std::vector<PosInfo> hp(c->J);
+    copy_out(c, hp.data(), c->pos, sizeof(PosInfo) * c->J, 0);
+    for (int j = 0; j < c->J; ++j) {
+      yx[2 * j] = double(hp[j].iy) + double(hp[j].fy);
+      yx[2 * j + 1] = double(hp[j].ix) + double(hp[j].fx);
+    }
   });
 }
 

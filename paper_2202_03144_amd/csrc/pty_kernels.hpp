@@ -128,12 +128,17 @@ struct LsqStepArgs {
   const PosInfo* pos;
   int count;
   int probe_on;
-  double* part;            // count x row_blocks x 5
+  double* part;            // count x row_blocks x (5, or 9 with shift)
   float2* alpha;           // per slot
   float2* alpha_by_j;      // per pattern index (reporting)
+  float2* shift;           // per slot (dy, dx) of the position refinement, or nullptr
+  float max_shift;         // clip of each shift component, px
   hipStream_t stream;
 };
 void launch_lsq_steps(const LsqStepArgs& a);
+// pos[jlist[b]] += shift[b] for b < count, kept in [0, lim]
+void launch_pos_update(PosInfo* pos, const int* jlist, const float2* shift, int count, int lim_y, int lim_x,
+                       hipStream_t s);
 
 struct EpieArgs {
   int n, k;

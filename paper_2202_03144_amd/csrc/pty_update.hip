@@ -266,20 +266,34 @@ struct LsqPix {
   static constexpr int NRB = W::BLOCKS;
 };
 
-// Deterministic block sum of five doubles; valid in thread 0.
-__device__ __forceinline__ void block_sum5(double (&v)[5], double* sh /* 5 * 4 */) {
+// Deterministic block sum of NV doubles over 256 threads; valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum_n(double (&v)[NV], double* sh /* NV * 4 */) {
 #pragma unroll
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < NV; ++i)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int i = 0; i < 5; ++i) sh[i * 4 + wid] = v[i];
+    for (int i = 0; i < NV; ++i) sh[i * 4 + wid] = v[i];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < 5; ++i) v[i] = sh[i * 4] + sh[i * 4 + 1] + sh[i * 4 + 2] + sh[i * 4 + 3];
+    for (int i = 0; i < NV; ++i) v[i] = sh[i * 4] + sh[i * 4 + 1] + sh[i * 4 + 2] + sh[i * 4 + 3];
+}
+
+// Object taps O[r][c0], O[r][c0 + 1] for the position derivatives, zero past
+// the object's last row or column (only a patch at an integer position on the
+// far edge reaches them).
+__device__ __forceinline__ void obj_taps(const float2* __restrict__ o, int h, int w, int r, int c0, float2& a,
+                                         float2& b) {
+  const bool rin = r < h, bin = rin && c0 + 1 < w;
+  const size_t row = (size_t)min(r, h - 1) * w;
+  a = o[row + c0];
+  b = o[row + min(c0 + 1, w - 1)];
+  if (!rin) a = make_float2(0.f, 0.f);
+  if (!bin) b = make_float2(0.f, 0.f);
 }
 
 // Per-pixel probe quantities of one LSQML group: sum_k |P_k|^2,
@@ -310,21 +324,28 @@ __global__ __launch_bounds__(256) void k_lsq_planes(const float2* probe, const f
 // Re conj(a) b = Re conj(S dO) S O sum conj(P_k) dP_k,
 // Re conj(a) chi = Re conj(S dO) sum_k conj(P_k) chi_k (the stored contribution),
 // Re conj(b) chi = Re conj(S O) sum_k conj(dP_k) chi_k.
-template <int N, int K, bool PROBE_ON>
+// With POS, four more for the position refinement: with g = d(S O)/dy (and
+// likewise x) and d psi_k = P_k g, Re sum_k conj(d psi_k) chi_k =
+// Re conj(g) sum_k conj(P_k) chi_k and sum_k |d psi_k|^2 = |g|^2 sum_k |P_k|^2.
+template <int N, int K, bool PROBE_ON, bool POS>
 __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
   using W = typename LsqPix<N>::W;
   constexpr int RB = LsqPix<N>::RB;
+  constexpr int NV = POS ? 9 : 5;
   const int b = blockIdx.y, rblk = blockIdx.x;
-  __shared__ double red[20];
+  __shared__ double red[NV * 4];
   const int j = a.jlist[b];
   const PosInfo p = a.pos[j];
   const int v = threadIdx.x % N;
   const int u0 = (rblk * W::G + threadIdx.x / N) * RB;
   const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
   float m00 = 0.f, m11 = 0.f, m01 = 0.f, v0 = 0.f, v1 = 0.f;
+  float ny = 0.f, nx = 0.f, gyy = 0.f, gxx = 0.f;
   float2 dtop = obj_hrow(a.dobj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
   float2 otop = make_float2(0.f, 0.f);
   if constexpr (PROBE_ON) otop = obj_hrow(a.obj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
+  float2 ta = make_float2(0.f, 0.f), tb = make_float2(0.f, 0.f);
+  if constexpr (POS) obj_taps(a.obj, a.h, a.w, p.iy + u0, p.ix + v, ta, tb);
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
     const int q = (u0 + i) * N + v;
@@ -334,6 +355,21 @@ __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
     const float2 cb = a.contrib[(size_t)b * N * N + q];
     m00 += cabs2(dob) * a.pint[q];
     v0 += dob.x * cb.x + dob.y * cb.y;
+    if constexpr (POS) {
+      float2 ba, bb;
+      obj_taps(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, ba, bb);
+      // d/dy: bottom minus top row, each interpolated along x;
+      // d/dx: right minus left tap, interpolated along y
+      const float2 gy = make_float2(wx0 * (ba.x - ta.x) + wx1 * (bb.x - tb.x), wx0 * (ba.y - ta.y) + wx1 * (bb.y - tb.y));
+      const float2 gx = make_float2(wy0 * (tb.x - ta.x) + wy1 * (bb.x - ba.x), wy0 * (tb.y - ta.y) + wy1 * (bb.y - ba.y));
+      ta = ba;
+      tb = bb;
+      const float pi = a.pint[q];
+      ny += gy.x * cb.x + gy.y * cb.y;
+      nx += gx.x * cb.x + gx.y * cb.y;
+      gyy += cabs2(gy) * pi;
+      gxx += cabs2(gx) * pi;
+    }
     if constexpr (PROBE_ON) {
       const float2 obot = obj_hrow(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
       const float2 ob = make_float2(wy0 * otop.x + wy1 * obot.x, wy0 * otop.y + wy1 * obot.y);
@@ -349,21 +385,39 @@ __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
       v1 += ob.x * t.x + ob.y * t.y;        // Re(conj(S O) t)
     }
   }
-  double s[5] = {m00, m11, m01, v0, v1};
-  block_sum5(s, red);
+  double s[NV];
+  s[0] = m00;
+  s[1] = m11;
+  s[2] = m01;
+  s[3] = v0;
+  s[4] = v1;
+  if constexpr (POS) {
+    s[5] = ny;
+    s[6] = nx;
+    s[7] = gyy;
+    s[8] = gxx;
+  }
+  block_sum_n<NV>(s, red);
   if (threadIdx.x == 0) {
-    double* o = a.part + ((size_t)b * LsqPix<N>::NRB + rblk) * 5;
+    double* o = a.part + ((size_t)b * LsqPix<N>::NRB + rblk) * NV;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) o[i] = s[i];
+    for (int i = 0; i < NV; ++i) o[i] = s[i];
   }
 }
 
 __global__ void k_lsq_solve(LsqStepArgs a, int nrb) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.count) return;
-  double s[5] = {0, 0, 0, 0, 0};
+  const int nv = a.shift ? 9 : 5;
+  double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < nrb; ++r)
-    for (int i = 0; i < 5; ++i) s[i] += a.part[((size_t)b * nrb + r) * 5 + i];
+    for (int i = 0; i < nv; ++i) s[i] += a.part[((size_t)b * nrb + r) * nv + i];
+  if (a.shift) {
+    // least-squares shift along each axis, clipped
+    const double m = a.max_shift;
+    const double sy = s[7] > 0.0 ? s[5] / s[7] : 0.0, sx = s[8] > 0.0 ? s[6] / s[8] : 0.0;
+    a.shift[b] = make_float2((float)fmin(fmax(sy, -m), m), (float)fmin(fmax(sx, -m), m));
+  }
   const double m00 = s[0], m11 = s[1], m01 = s[2], v0 = s[3], v1 = s[4];
   const double mx = fmax(m00, m11);
   double ao = 0.0, ap = 0.0;
@@ -854,14 +908,52 @@ void launch_lsq_steps(const LsqStepArgs& a) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
     nrb = LsqPix<N>::NRB;
     const dim3 grid(LsqPix<N>::NRB, a.count);
-    if (a.probe_on)
-      k_lsq_sums<N, K, true><<<grid, 256, 0, a.stream>>>(a);
-    else
-      k_lsq_sums<N, K, false><<<grid, 256, 0, a.stream>>>(a);
+    if (a.shift) {
+      if (a.probe_on)
+        k_lsq_sums<N, K, true, true><<<grid, 256, 0, a.stream>>>(a);
+      else
+        k_lsq_sums<N, K, false, true><<<grid, 256, 0, a.stream>>>(a);
+    } else {
+      if (a.probe_on)
+        k_lsq_sums<N, K, true, false><<<grid, 256, 0, a.stream>>>(a);
+      else
+        k_lsq_sums<N, K, false, false><<<grid, 256, 0, a.stream>>>(a);
+    }
   });
   PTY_LAUNCH_CHECK("lsq_sums");
   k_lsq_solve<<<(a.count + 127) / 128, 128, 0, a.stream>>>(a, nrb);
   PTY_LAUNCH_CHECK("lsq_solve");
+}
+
+// Moves the group's positions by their shifts, kept inside the object
+// (0 <= y <= lim_y, 0 <= x <= lim_x), and splits them again into floor and
+// fraction.
+__global__ void k_pos_update(PosInfo* pos, const int* jlist, const float2* shift, int count, int lim_y,
+                             int lim_x) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  const int j = jlist[b];
+  PosInfo p = pos[j];
+  const float2 sh = shift[b];
+  auto move = [](int& i, float& f, double d, int lim) {
+    const double r = fmin(fmax((double)i + (double)f + d, 0.0), (double)lim);
+    i = (int)floor(r);
+    f = (float)(r - i);
+    if (f >= 1.f) {   // rounding to float reached the next integer
+      i += 1;
+      f = 0.f;
+    }
+  };
+  move(p.iy, p.fy, sh.x, lim_y);
+  move(p.ix, p.fx, sh.y, lim_x);
+  pos[j] = p;
+}
+
+void launch_pos_update(PosInfo* pos, const int* jlist, const float2* shift, int count, int lim_y, int lim_x,
+                       hipStream_t s) {
+  if (count <= 0) return;
+  k_pos_update<<<(count + 127) / 128, 128, 0, s>>>(pos, jlist, shift, count, lim_y, lim_x);
+  PTY_LAUNCH_CHECK("pos_update");
 }
 
 bool epie_fused_supported(int n, int k) {

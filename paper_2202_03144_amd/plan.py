@@ -160,6 +160,12 @@ class Plan:
         self._check(self._lib.pty_get_errors(self._live(), buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
         return buf[: n.value].copy()
 
+    def positions(self) -> np.ndarray:
+        """Current scan positions (J, 2) float64: as loaded, or as refined."""
+        out = np.empty((self.n_pos, 2), dtype=np.float64)
+        self._check(self._lib.pty_get_positions(self._live(), out.ctypes.data_as(C.c_void_p)))
+        return out
+
     def set_mask(self, mask) -> None:
         """Detector mask (N x N, centred like the counts, nonzero = measured);
         None measures every pixel again."""

@@ -42,6 +42,7 @@ def test_default_params():
     assert L.lib().pty_default_params(C.byref(p)) == L.OK
     assert (p.alpha, p.beta, p.lsqml_batch, p.beta_obj, p.beta_probe) == (1.0, 1.0, 512, 1.0, 1.0)
     assert p.gamma_obj < 0 and p.gamma_probe < 0 and p.order_seed == 0 and p.chunk == 0
+    assert p.position_start == -1 and p.position_max_shift == 0.5
     assert L.lib().pty_default_params(None) == L.E_INVALID
 
 
@@ -72,6 +73,8 @@ def test_null_arguments_are_invalid():
     sz = C.c_size_t()
     assert lib.pty_get_state(None, None, 0, C.byref(sz)) == L.E_INVALID
     assert lib.pty_set_state(None, None, 0) == L.E_INVALID
+    assert lib.pty_get_positions(None, None) == L.E_INVALID
+    assert lib.pty_set_mask(None, None) == L.E_INVALID
     lib.pty_destroy(None)  # NULL-safe
 
 
