@@ -53,6 +53,8 @@ __all__ = [
     "forward_intensity",
     "simulate",
     "model_error",
+    "mode_basis",
+    "orthogonalise_modes",
     "splitmix64_stream",
     "epie_order",
     "epie",
@@ -221,6 +223,38 @@ def _exit_diff(probe: np.ndarray, oj: np.ndarray, a: np.ndarray, z: np.ndarray |
 
 
 # ---------------------------------------------------------------------------
+# Probe-mode orthogonalisation (mixed states, Thibault & Menzel 2013)
+# ---------------------------------------------------------------------------
+def mode_basis(probe) -> np.ndarray:
+    """Unitary K x K matrix V of the eigenvectors of the modes' Gram matrix
+    G_kl = sum_r P_k(r) conj(P_l(r)), columns in order of decreasing
+    eigenvalue, each column's phase set so that its largest-magnitude entry
+    (the first of equal ones) is real and positive."""
+    p = np.asarray(probe, dtype=np.complex128).reshape(len(probe), -1)
+    g = p @ p.conj().T
+    lam, v = np.linalg.eigh(g)
+    order = np.argsort(-lam, kind="stable")
+    v = v[:, order]
+    for k in range(v.shape[1]):
+        i = int(np.argmax(np.abs(v[:, k])))
+        v[:, k] *= np.conj(v[i, k]) / abs(v[i, k])
+    return v
+
+
+def orthogonalise_modes(probe, psi=None):
+    """P'_k = sum_l conj(V_lk) P_l with V = mode_basis(P): orthogonal modes in
+    order of decreasing power, the same incoherent sum sum_k |P_k|^2 and the
+    same mutual coherence.  DM exit waves, if given (J, K, N, N), are mixed
+    with the same matrix so that they stay paired with their modes.  Returns
+    (P', psi') (psi' None without psi)."""
+    v = mode_basis(probe)
+    m = v.conj().T
+    p2 = np.einsum("kl,l...->k...", m, np.asarray(probe, dtype=np.complex128))
+    psi2 = None if psi is None else np.einsum("kl,jl...->jk...", m, np.asarray(psi, dtype=np.complex128))
+    return p2, psi2
+
+
+# ---------------------------------------------------------------------------
 # ePIE (Maiden & Rodenburg 2009): sequential over positions
 # ---------------------------------------------------------------------------
 _M64 = (1 << 64) - 1
@@ -250,7 +284,7 @@ def epie_order(j: int, seed: int, t: int) -> np.ndarray:
     return np.asarray(order)
 
 
-def epie(obj, probe, a, pos, n_iter, t0=0, alpha=1.0, beta=1.0, start=0, order_seed=0):
+def epie(obj, probe, a, pos, n_iter, t0=0, alpha=1.0, beta=1.0, start=0, order_seed=0, ortho=False):
     """``n_iter`` ePIE iterations; returns (object, probe, [E per iteration]).
 
     For each position j in the iteration's order, with chi = F^-1 Delta(F(P S_j O))
@@ -261,7 +295,8 @@ def epie(obj, probe, a, pos, n_iter, t0=0, alpha=1.0, beta=1.0, start=0, order_s
 
     both right-hand sides evaluated with the values before this position's
     update.  A zero maximum skips that update.  E accumulates over positions as
-    they are visited.  ``a``: (J, N, N) moduli in natural order.
+    they are visited.  ``a``: (J, N, N) moduli in natural order.  ``ortho``:
+    after every iteration that updated the probe, :func:`orthogonalise_modes`.
     """
     obj = np.array(obj, dtype=np.complex128)
     probe = np.array(probe, dtype=np.complex128)
@@ -283,6 +318,8 @@ def epie(obj, probe, a, pos, n_iter, t0=0, alpha=1.0, beta=1.0, start=0, order_s
                 scatter_add(obj, alpha * np.sum(np.conj(probe) * chi, axis=0) / pmax, pos[j])
             probe = new_probe
         errs.append(num / den)
+        if ortho and t >= start:
+            probe, _ = orthogonalise_modes(probe)
     return obj, probe, errs
 
 
@@ -295,7 +332,7 @@ def dm_init(obj, probe, pos) -> np.ndarray:
     return np.stack([probe * gather(obj, r, n)[None] for r in pos]).astype(np.complex128)
 
 
-def dm(obj, probe, psi, a, pos, n_iter, t0=0, start=0, gamma_obj=1e-6, gamma_probe=1e-6):
+def dm(obj, probe, psi, a, pos, n_iter, t0=0, start=0, gamma_obj=1e-6, gamma_probe=1e-6, ortho=False):
     """``n_iter`` DM iterations from exit-wave state ``psi``.
 
     Returns (object, probe, psi, [E per iteration]).  Each iteration:
@@ -307,7 +344,9 @@ def dm(obj, probe, psi, a, pos, n_iter, t0=0, start=0, gamma_obj=1e-6, gamma_pro
     3. phi = P S_j O;  Z = F(2 phi - psi);  psi <- phi + F^-1 Delta(Z)
        (= psi + F^-1 Pi(Z) - phi); E is measured on Z.
 
-    dO = gamma_obj max(den_O), dP = gamma_probe max(den_P).
+    dO = gamma_obj max(den_O), dP = gamma_probe max(den_P).  ``ortho``: after
+    every iteration that updated the probe, :func:`orthogonalise_modes` of the
+    probe with the exit waves.
     """
     obj = np.array(obj, dtype=np.complex128)
     probe = np.array(probe, dtype=np.complex128)
@@ -342,6 +381,8 @@ def dm(obj, probe, psi, a, pos, n_iter, t0=0, start=0, gamma_obj=1e-6, gamma_pro
             e_num += e1
             e_den += e2
         errs.append(e_num / e_den)
+        if ortho and t >= start:
+            probe, psi = orthogonalise_modes(probe, psi)
     return obj, probe, psi, errs
 
 
@@ -385,7 +426,7 @@ def position_shift(obj, probe, chi, r, max_shift):
 
 def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
           gamma_probe=1e-3, beta_obj=1.0, beta_probe=1.0, return_alpha=False,
-          pos_start=-1, max_shift=0.5, return_positions=False):
+          pos_start=-1, max_shift=0.5, return_positions=False, ortho=False):
     """``n_iter`` LSQML iterations; returns (object, probe, [E], alpha of last iteration).
 
     Positions are split into G = ceil(J / batch) interleaved groups
@@ -405,7 +446,9 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
       of its positions moves by :func:`position_shift` of its pass-A chi
       (object and probe at the start of the group), kept inside the object
       (0 <= R <= size - N).  ``return_positions`` adds the refined positions
-      to the returned tuple.
+      to the returned tuple;
+    * ``ortho``: after every iteration that updated the probe,
+      :func:`orthogonalise_modes`.
     """
     obj = np.array(obj, dtype=np.complex128)
     probe = np.array(probe, dtype=np.complex128)
@@ -466,6 +509,8 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
             for j, sh in shifts.items():
                 pos[j] = np.clip(pos[j] + sh, 0.0, lim)
         errs.append(e_num / e_den)
+        if ortho and probe_on:
+            probe, _ = orthogonalise_modes(probe)
     out = (obj, probe, errs) + ((alpha,) if return_alpha else ()) + ((pos,) if return_positions else ())
     return out
 
