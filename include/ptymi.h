@@ -90,6 +90,16 @@ typedef struct {
  *                        replayed (fewer launches; same kernels, same results
  *                        as eager iterations); ignored for ePIE.  Kernel
  *                        timing is suspended while graphs run.
+ *                        PTY_ITER_ORTHO_MODES: after every iteration that
+ *                        updated the probe (K > 1), the modes are replaced by
+ *                        the orthogonal modes of their Gram matrix's
+ *                        eigenbasis, in order of decreasing power, each
+ *                        eigenvector phased so that its largest entry is real
+ *                        positive (mixed states, Thibault & Menzel 2013); DM
+ *                        exit waves are mixed alike.  The incoherent sum
+ *                        sum_k |P_k|^2 and the object trajectory do not
+ *                        change.  With equal mode powers the basis is not
+ *                        unique.
  *   position_start       LSQML position refinement from this global iteration
  *                        on; < 0 = never (default).  Each position moves by
  *                        the least-squares shift that explains its exit-wave
@@ -105,6 +115,7 @@ typedef struct {
  *   position_max_shift   clip of each shift component per iteration, pixels
  *                        (default 0.5). */
 #define PTY_ITER_GRAPH 1u
+#define PTY_ITER_ORTHO_MODES 2u
 typedef struct {
   float alpha, beta;
   int32_t probe_update_start;
@@ -113,7 +124,7 @@ typedef struct {
   float beta_obj, beta_probe;
   uint64_t order_seed;
   int32_t chunk;
-  uint32_t flags; /* 0 or PTY_ITER_GRAPH */
+  uint32_t flags; /* PTY_ITER_GRAPH | PTY_ITER_ORTHO_MODES */
   int32_t position_start;
   float position_max_shift;
 } pty_iter_params;

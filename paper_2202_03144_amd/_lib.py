@@ -112,6 +112,7 @@ SIGNATURES = {
 }
 
 ITER_GRAPH = 1
+ITER_ORTHO_MODES = 2
 
 TIMING_FAMILIES = ["rows_fwd", "cols", "rows_inv", "obj_gather", "probe_acc", "probe_finish_apply",
                    "lsq_steps", "epie_update", "other"]

@@ -106,6 +106,8 @@ struct pty_ctx {
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
   float2* shift = nullptr;         size_t shift_slots = 0;   // LSQML position shifts per slot
+  double2* mode_gram = nullptr;    // K x K Gram matrix of the probe modes
+  float2* mode_mix = nullptr;      // K x K mixing matrix of the orthogonalisation
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
 
   // device-side iteration counter (error / NRMSE history slot of the running
@@ -620,6 +622,24 @@ void require_loaded(pty_ctx* c) {
 
 bool probe_on(const pty_iter_params& p, int t) { return p.probe_update_start >= 0 && t >= p.probe_update_start; }
 
+// Orthogonal probe modes after an iteration that updated the probe (and the
+// DM exit waves alike), when the parameters ask for it.
+// Its two K x K scratch matrices are allocated with the other work buffers,
+// before any iteration (a captured iteration must not allocate).
+void ensure_mode_scratch(pty_ctx* c, const pty_iter_params& p) {
+  if (!(p.flags & PTY_ITER_ORTHO_MODES) || c->K <= 1) return;
+  c->ensure_once(c->mode_gram, size_t(c->K) * c->K);
+  c->ensure_once(c->mode_mix, size_t(c->K) * c->K);
+}
+
+void maybe_orthogonalise(pty_ctx* c, const pty_iter_params& p, bool pon, float2* psi) {
+  if (!(p.flags & PTY_ITER_ORTHO_MODES) || !pon || c->K <= 1) return;
+  timed(c, kOther, [&] {
+    launch_orthogonalise_modes(c->probe, psi, c->N, c->K, c->J, c->mode_gram, c->mode_mix, c->stream);
+  });
+  c->den_valid = false;
+}
+
 // ---------------------------------------------------------------------------
 // DM
 // ---------------------------------------------------------------------------
@@ -633,6 +653,7 @@ void run_dm(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   c->ensure_once(c->psi, size_t(c->J) * c->K * nn);
   ensure_probe_parts(c, c->J);
   ensure_err_slot(c, n_iter);
+  ensure_mode_scratch(c, p);
   const Group& g = c->all;
   if (!c->dm_valid) {
     DmInitArgs di{};
@@ -666,6 +687,7 @@ void run_dm(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       c->den_valid = false;
     }
     fourier_pass(c, g, 0, c->J, chunk, RowIn::DmReflect, ColOp::Project, RowOut::DmUpdate);
+    maybe_orthogonalise(c, p, probe_on(p, t), c->psi);
     end_iteration(c, t);
   }
 }
@@ -705,6 +727,7 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   if (refining) c->ensure(c->shift, c->shift_slots, size_t(bmax));
   ensure_probe_parts(c, bmax);
   ensure_err_slot(c, n_iter);
+  ensure_mode_scratch(c, p);
   c->dm_valid = false;
   for (int it = 0; it < n_iter; ++it) {
     const int t = c->iter;
@@ -758,6 +781,7 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
           launch_pos_update(c->pos, g.d_jl, c->shift, count, c->H - c->N, c->W - c->N, c->stream);
         });
     }
+    maybe_orthogonalise(c, p, pon, nullptr);
     end_iteration(c, t);
     if (refine) refresh_positions(c);
   }
@@ -781,6 +805,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   ensure_common(c, 1, 1);
   c->ensure(c->chi, c->chi_slots, size_t(c->K) * nn);
   ensure_err_slot(c, n_iter);
+  ensure_mode_scratch(c, p);
   c->dm_valid = false;
   FourierArgs a = fourier_args(c, c->all);
   a.nc = 1;
@@ -827,6 +852,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       r.stream = c->stream;
       timed(c, kEpie, [&] { launch_epie_fused(r); });
       if (c->J % 2 == 1) std::swap(c->probe, c->probe_alt);
+      maybe_orthogonalise(c, p, pon, nullptr);
       end_iteration(c, t);
       continue;
     }
@@ -854,6 +880,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       timed(c, kEpie, [&] { launch_epie_update(e); });
       std::swap(c->probe, c->probe_alt);
     }
+    maybe_orthogonalise(c, p, pon, nullptr);
     end_iteration(c, t);
   }
   c->den_valid = false;
@@ -1355,7 +1382,7 @@ pty_status pty_iterate(pty_ctx* c, pty_algo algo, int32_t n_iter, const pty_iter
     pty_iter_params p;
     pty_default_params(&p);
     if (prm) p = *prm;
-    require((p.flags & ~PTY_ITER_GRAPH) == 0, "pty_iterate: unknown flags");
+    require((p.flags & ~(PTY_ITER_GRAPH | PTY_ITER_ORTHO_MODES)) == 0, "pty_iterate: unknown flags");
     require(p.chunk >= 0, "pty_iterate: negative chunk");
     require(p.lsqml_batch >= 0, "pty_iterate: negative lsqml_batch");
     if (p.position_start >= 0) {

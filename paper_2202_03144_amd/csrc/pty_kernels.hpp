@@ -136,6 +136,11 @@ struct LsqStepArgs {
   hipStream_t stream;
 };
 void launch_lsq_steps(const LsqStepArgs& a);
+// Probe modes (and DM exit waves, if psi != nullptr: J sets of K modes)
+// replaced by the orthogonal modes of the probe's Gram eigenbasis; gram: K x K
+// double2 scratch, mix: K x K float2 scratch.  No-op for k == 1.
+void launch_orthogonalise_modes(float2* probe, float2* psi, int n, int k, int j, double2* gram, float2* mix,
+                                hipStream_t s);
 // pos[jlist[b]] += shift[b] for b < count, kept in [0, lim]
 void launch_pos_update(PosInfo* pos, const int* jlist, const float2* shift, int count, int lim_y, int lim_x,
                        hipStream_t s);

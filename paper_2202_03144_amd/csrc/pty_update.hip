@@ -925,6 +925,213 @@ void launch_lsq_steps(const LsqStepArgs& a) {
   PTY_LAUNCH_CHECK("lsq_solve");
 }
 
+// ---------------------------------------------------------------------------
+// Probe-mode orthogonalisation (mixed states, Thibault & Menzel 2013)
+// ---------------------------------------------------------------------------
+// Gram matrix of the modes, G_kl = sum_r P_k(r) conj(P_l(r)), in FP64 by one
+// 1024-thread block (fixed summation order).
+template <int K>
+__global__ __launch_bounds__(1024) void k_mode_gram(const float2* __restrict__ probe, int nn,
+                                                    double2* __restrict__ gram) {
+  constexpr int NP = K * (K + 1) / 2;
+  __shared__ double sh[16][2 * NP];
+  double re[NP], im[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) re[i] = im[i] = 0.0;
+  for (int q = threadIdx.x; q < nn; q += 1024) {
+    float2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = probe[(size_t)k * nn + q];
+    int i = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int l = k; l < K; ++l, ++i) {
+        // P_k conj(P_l)
+        re[i] += (double)v[k].x * v[l].x + (double)v[k].y * v[l].y;
+        im[i] += (double)v[k].y * v[l].x - (double)v[k].x * v[l].y;
+      }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      re[i] += __shfl_down(re[i], off, 64);
+      im[i] += __shfl_down(im[i], off, 64);
+    }
+    if (lane == 0) {
+      sh[wid][2 * i] = re[i];
+      sh[wid][2 * i + 1] = im[i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int i = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int l = k; l < K; ++l, ++i) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < 16; ++w) {
+          a += sh[w][2 * i];
+          b += sh[w][2 * i + 1];
+        }
+        gram[k * K + l] = make_double2(a, b);
+        gram[l * K + k] = make_double2(a, -b);
+      }
+  }
+}
+
+// Eigenvectors V of the Hermitian Gram matrix by cyclic complex Jacobi
+// rotations in FP64 (one thread; K <= 4), columns ordered by decreasing
+// eigenvalue and each phased so that its largest-magnitude entry (the first
+// of equal ones) is real and positive.  Writes the mixing matrix
+// mix[k][l] = conj(V[l][k]) of the new modes P'_k = sum_l mix[k][l] P_l.
+template <int K>
+__global__ void k_mode_eigen(const double2* __restrict__ gram, float2* __restrict__ mix) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double gr[K][K], gi[K][K], vr[K][K], vi[K][K];
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      gr[r][q] = gram[r * K + q].x;
+      gi[r][q] = gram[r * K + q].y;
+      vr[r][q] = r == q ? 1.0 : 0.0;
+      vi[r][q] = 0.0;
+    }
+#pragma unroll 1
+  for (int sweep = 0; sweep < 12; ++sweep) {
+#pragma unroll
+    for (int p = 0; p < K - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < K; ++q) {
+        const double br = gr[p][q], bi = gi[p][q];
+        const double ab = sqrt(br * br + bi * bi);
+        const double a = gr[p][p], d = gr[q][q];
+        if (!(ab > 1e-18 * (fabs(a) + fabs(d)))) continue;
+        const double er = br / ab, ei = -bi / ab;   // conj(b) / |b|
+        const double tau = (d - a) / (2.0 * ab);
+        const double t = fabs(tau) > 1e150 ? 0.5 / tau
+                                            : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        // U on (p, q): U_pp = c, U_pq = s, U_qp = -s e, U_qq = c e with e = conj(b)/|b|
+        const double u10r = -s * er, u10i = -s * ei, u11r = c * er, u11i = c * ei;
+        // columns: G <- G U, V <- V U
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const double xr = gr[r][p], xi = gi[r][p], yr = gr[r][q], yi = gi[r][q];
+          gr[r][p] = c * xr + (yr * u10r - yi * u10i);
+          gi[r][p] = c * xi + (yr * u10i + yi * u10r);
+          gr[r][q] = s * xr + (yr * u11r - yi * u11i);
+          gi[r][q] = s * xi + (yr * u11i + yi * u11r);
+          const double vxr = vr[r][p], vxi = vi[r][p], vyr = vr[r][q], vyi = vi[r][q];
+          vr[r][p] = c * vxr + (vyr * u10r - vyi * u10i);
+          vi[r][p] = c * vxi + (vyr * u10i + vyi * u10r);
+          vr[r][q] = s * vxr + (vyr * u11r - vyi * u11i);
+          vi[r][q] = s * vxi + (vyr * u11i + vyi * u11r);
+        }
+        // rows: G <- U^H G
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const double xr = gr[p][r], xi = gi[p][r], yr = gr[q][r], yi = gi[q][r];
+          // conj(u10) y = (u10r - i u10i)(yr + i yi)
+          gr[p][r] = c * xr + (u10r * yr + u10i * yi);
+          gi[p][r] = c * xi + (u10r * yi - u10i * yr);
+          gr[q][r] = s * xr + (u11r * yr + u11i * yi);
+          gi[q][r] = s * xi + (u11r * yi - u11i * yr);
+        }
+        gr[p][q] = gi[p][q] = gr[q][p] = gi[q][p] = 0.0;
+        gi[p][p] = gi[q][q] = 0.0;
+      }
+  }
+  // order by decreasing eigenvalue (stable selection)
+  int ord[K];
+  bool used[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) used[k] = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int best = -1;
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+      if (!used[m] && (best < 0 || gr[m][m] > gr[best][best])) best = m;
+    used[best] = true;
+    ord[k] = best;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int col = ord[k];
+    double cr[K], ci[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      cr[r] = vr[r][col];
+      ci[r] = vi[r][col];
+    }
+    int im = 0;
+    double mm = cr[0] * cr[0] + ci[0] * ci[0];
+#pragma unroll
+    for (int r = 1; r < K; ++r) {
+      const double m2 = cr[r] * cr[r] + ci[r] * ci[r];
+      if (m2 > mm) {
+        mm = m2;
+        im = r;
+      }
+    }
+    const double am = sqrt(mm);
+    const double fr = cr[im] / am, fi = -ci[im] / am;   // conj(v_im) / |v_im|
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      const double xr = cr[l] * fr - ci[l] * fi, xi = cr[l] * fi + ci[l] * fr;
+      mix[k * K + l] = make_float2((float)xr, (float)-xi);   // conj(V[l][k])
+    }
+  }
+}
+
+// x[set][k][q] <- sum_l mix[k][l] x[set][l][q] for every set (the probe: one
+// set; DM exit waves: one per pattern).
+template <int K>
+__global__ __launch_bounds__(256) void k_mode_mix(float2* __restrict__ x, const float2* __restrict__ mix, size_t nn,
+                                                  size_t sets) {
+  const size_t i = blockIdx.x * (size_t)256 + threadIdx.x;
+  if (i >= sets * nn) return;
+  const size_t set = i / nn, q = i % nn;
+  float2* base = x + set * K * nn + q;
+  float2 v[K], m[K * K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = base[(size_t)k * nn];
+#pragma unroll
+  for (int e = 0; e < K * K; ++e) m[e] = mix[e];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int l = 0; l < K; ++l) acc = acc + cmul(m[k * K + l], v[l]);
+    base[(size_t)k * nn] = acc;
+  }
+}
+
+void launch_orthogonalise_modes(float2* probe, float2* psi, int n, int k, int j, double2* gram, float2* mix,
+                                hipStream_t s) {
+  if (k <= 1) return;
+  const size_t nn = (size_t)n * n;
+  auto run = [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    k_mode_gram<K><<<1, 1024, 0, s>>>(probe, (int)nn, gram);
+    k_mode_eigen<K><<<1, 64, 0, s>>>(gram, mix);
+    k_mode_mix<K><<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(probe, mix, nn, 1);
+    if (psi) k_mode_mix<K><<<(unsigned)(((size_t)j * nn + 255) / 256), 256, 0, s>>>(psi, mix, nn, (size_t)j);
+  };
+  switch (k) {
+    case 2: run(ic<2>{}); break;
+    case 3: run(ic<3>{}); break;
+    case 4: run(ic<4>{}); break;
+    default: throw std::invalid_argument("unsupported mode count");
+  }
+  PTY_LAUNCH_CHECK("orthogonalise_modes");
+}
+
 // Moves the group's positions by their shifts, kept inside the object
 // (0 <= y <= lim_y, 0 <= x <= lim_x), and splits them again into floor and
 // fraction.

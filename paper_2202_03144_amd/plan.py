@@ -108,13 +108,17 @@ class Plan:
         del keep
 
     # -- iteration ---------------------------------------------------------
-    def iterate(self, algo, n_iter: int = 1, graph: bool = False, **params) -> None:
+    def iterate(self, algo, n_iter: int = 1, graph: bool = False, ortho_modes: bool = False, **params) -> None:
         """Enqueue ``n_iter`` iterations of 'epie', 'dm' or 'lsqml' (asynchronous).
 
-        graph=True replays captured iterations (PTY_ITER_GRAPH; DM and LSQML)."""
+        graph=True replays captured iterations (PTY_ITER_GRAPH; DM and LSQML);
+        ortho_modes=True orthogonalises the probe modes after every iteration
+        that updated the probe (PTY_ITER_ORTHO_MODES)."""
         a = ALGOS[algo] if isinstance(algo, str) else int(algo)
         if graph:
             params["flags"] = params.get("flags", 0) | L.ITER_GRAPH
+        if ortho_modes:
+            params["flags"] = params.get("flags", 0) | L.ITER_ORTHO_MODES
         p = self.default_params(**params)
         self._check(self._lib.pty_iterate(self._live(), a, int(n_iter), C.byref(p)))
 
@@ -350,10 +354,12 @@ class Batch:
         if st != L.OK:
             raise PtyError(st, self._lib.pty_batch_last_error(self._b).decode())
 
-    def iterate(self, algo, n_iter: int = 1, graph: bool = False, **params) -> None:
+    def iterate(self, algo, n_iter: int = 1, graph: bool = False, ortho_modes: bool = False, **params) -> None:
         a = ALGOS[algo] if isinstance(algo, str) else int(algo)
         if graph:
             params["flags"] = params.get("flags", 0) | L.ITER_GRAPH
+        if ortho_modes:
+            params["flags"] = params.get("flags", 0) | L.ITER_ORTHO_MODES
         p = Plan.default_params(**params)
         self._check(self._lib.pty_batch_iterate(self._b, a, int(n_iter), C.byref(p)))
 

@@ -1,0 +1,88 @@
+"""Probe-mode orthogonalisation on the GPU vs the FP64 oracle (pinned in
+test_oracle_modes.py): after iterations with PTY_ITER_ORTHO_MODES from a
+non-orthogonal start, object, every probe mode (its phase fixed by the basis
+convention, so no alignment), DM exit waves and errors match at the parity
+tolerance; graph replays equal eager iterations bit for bit; one mode is a
+no-op."""
+import numpy as np
+import pytest
+
+import oracle
+from _cases import c64, rel, spiral_case, start_state
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _mode_rel(x, y):
+    x = np.asarray(x, np.complex128)
+    y = np.asarray(y, np.complex128)
+    return max(float(np.linalg.norm(x[k] - y[k]) / np.linalg.norm(y[k])) for k in range(len(y)))
+
+
+def _start(case):
+    o0, p0 = start_state(case, perturb=0.05)
+    p0 = p0.copy()
+    p0[1] = p0[1] + 0.5 * p0[0]          # far from orthogonal
+    return o0, c64(p0).astype(np.complex128)
+
+
+def _plan(case, o0, p0):
+    from paper_2202_03144_amd import Plan
+    pl = Plan(case.n, case.k, case.j, case.shape)
+    pl.load_patterns(case.counts)
+    pl.load_positions(case.pos)
+    pl.set_object(c64(o0))
+    pl.set_probe(c64(p0))
+    return pl
+
+
+@pytest.mark.parametrize("algo", ["epie", "dm", "lsqml"])
+@pytest.mark.parametrize("n,k,j", [(64, 2, 20), (128, 3, 9)])
+def test_orthogonalised_iterations_match_oracle(algo, n, k, j):
+    case = spiral_case(n, k, j, cfg=63)
+    o0, p0 = _start(case)
+    pl = _plan(case, o0, p0)
+    pl.iterate(algo, 2, ortho_modes=True, probe_update_start=0, lsqml_batch=6)
+    if algo == "epie":
+        o1, p1, err = oracle.epie(o0, p0, case.amp, case.pos, 2, start=0, ortho=True)
+    elif algo == "dm":
+        o1, p1, psi1, err = oracle.dm(o0, p0, oracle.dm_init(o0, p0, case.pos), case.amp, case.pos, 2, start=0,
+                                      ortho=True)
+        assert rel(pl.exit_waves(), psi1) <= TOL
+    else:
+        o1, p1, err = oracle.lsqml(o0, p0, case.amp, case.pos, 2, start=0, batch=6, ortho=True)
+    assert rel(pl.object(), o1) <= TOL
+    assert _mode_rel(pl.probe(), p1) <= TOL
+    e = pl.errors()
+    assert np.all(np.abs(e - np.asarray(err)) <= TOL * np.asarray(err))
+    g = np.einsum("kxy,lxy->kl", pl.probe().astype(np.complex128), pl.probe().conj().astype(np.complex128))
+    assert np.max(np.abs(g - np.diag(np.diag(g)))) <= 1e-5 * abs(g[0, 0])
+    pl.close()
+
+
+def test_graph_replay_with_orthogonalisation_is_exact():
+    import torch
+    case = spiral_case(64, 2, 20, cfg=63)
+    o0, p0 = _start(case)
+    a, b = _plan(case, o0, p0), _plan(case, o0, p0)
+    for _ in range(3):
+        a.iterate("dm", 1, ortho_modes=True, probe_update_start=0)
+        b.iterate("dm", 1, graph=True, ortho_modes=True, probe_update_start=0)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.probe(), b.probe())
+        assert np.array_equal(a.object(), b.object())
+    a.close()
+    b.close()
+
+
+def test_one_mode_is_unchanged():
+    case = spiral_case(64, 1, 20, cfg=63)
+    o0, p0 = start_state(case, perturb=0.05)
+    a, b = _plan(case, o0, p0), _plan(case, o0, p0)
+    a.iterate("lsqml", 2, ortho_modes=True, probe_update_start=0)
+    b.iterate("lsqml", 2, probe_update_start=0)
+    assert np.array_equal(a.probe(), b.probe()) and np.array_equal(a.object(), b.object())
+    a.close()
+    b.close()
