@@ -53,6 +53,8 @@ __all__ = [
     "forward_intensity",
     "simulate",
     "model_error",
+    "photons_from_counts",
+    "probe_guess",
     "mode_basis",
     "orthogonalise_modes",
     "splitmix64_stream",
@@ -220,6 +222,40 @@ def _exit_diff(probe: np.ndarray, oj: np.ndarray, a: np.ndarray, z: np.ndarray |
         z = probe * oj[None]
     delta, e1, e2 = project_delta(fft2u(z), a)
     return ifft2u(delta), e1, e2
+
+
+# ---------------------------------------------------------------------------
+# Blind probe start
+# ---------------------------------------------------------------------------
+def photons_from_counts(d) -> float:
+    """Mean over patterns of the total counts, negative counts taken as 0."""
+    d = np.maximum(np.asarray(d, dtype=np.float64), 0.0)
+    return float(np.mean(np.sum(d, axis=(-2, -1))))
+
+
+def probe_guess(n: int, k: int, diameter: float, photons: float) -> np.ndarray:
+    """Starting probe when none is known (Sec. 2.2: the guess of the probe size
+    and the number of modes): an unaberrated aperture, a uniform real disk of
+    the given diameter (pixels) centred on the window (pixel centres at
+    distance <= diameter / 2 from ((n-1)/2, (n-1)/2)), and for k > 1 the disk
+    times x, y and x*y (centred pixel coordinates) made orthogonal to the
+    lower modes by Gram-Schmidt in that order; every mode has power
+    photons / k, so that with the unitary transform the mean pattern total
+    of a flat object equals ``photons`` (Sec. 3.2's normalisation)."""
+    c = (n - 1) / 2.0
+    u, v = np.meshgrid(np.arange(n) - c, np.arange(n) - c, indexing="ij")
+    disk = (u * u + v * v <= (diameter / 2.0) ** 2).astype(np.float64)
+    shapes = [disk, disk * v, disk * u, disk * u * v]
+    modes = []
+    for f in shapes[:k]:
+        g = f.astype(np.complex128)
+        for m in modes:
+            g = g - np.vdot(m, g) / np.vdot(m, m) * m
+        modes.append(g)
+    out = np.stack(modes)
+    for i in range(k):
+        out[i] *= math.sqrt(photons / k / float(np.sum(np.abs(out[i]) ** 2)))
+    return out
 
 
 # ---------------------------------------------------------------------------
