@@ -144,6 +144,20 @@ pty_status pty_create(const pty_plan_desc* plan, pty_ctx** out);
  * counts are treated as 0. */
 pty_status pty_load_patterns(pty_ctx* ctx, const float* counts, int on_device);
 
+/* Blind start: sets the probe to a guess built from its size alone (Sec. 2.2:
+ * the guess of the probe size and the number of modes).  Mode 0 is an
+ * unaberrated aperture, a uniform real disk of `diameter` pixels centred on
+ * the window (pixel centres within diameter / 2 of ((N-1)/2, (N-1)/2)); for
+ * K > 1 the disk times x, y and x*y (centred pixel coordinates), made
+ * orthogonal to the lower modes by Gram-Schmidt in that order.  Every mode
+ * gets the power P / K, where P is the mean over the loaded patterns of their
+ * total counts (negative counts as 0), so that with the unitary transform a
+ * flat object predicts patterns of that total (Sec. 3.2's normalisation).
+ * PTY_E_STATE before pty_load_patterns; PTY_E_INVALID for a diameter that is
+ * not positive and finite, above 2 N, or too small to hold K independent
+ * modes.  Synchronises. */
+pty_status pty_guess_probe(pty_ctx* ctx, double diameter);
+
 /* Detector mask shared by all patterns: N x N bytes in host memory, in the
  * counts' centred layout, nonzero where the pixel measured something and 0
  * where it did not (saturated or dead pixels, a beam stop: what Sec. 2.2's

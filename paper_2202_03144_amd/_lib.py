@@ -70,6 +70,7 @@ SIGNATURES = {
     "pty_get_exit_waves": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pty_mem_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "pty_set_mask": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pty_guess_probe": (C.c_int, [C.c_void_p, C.c_double]),
     "pty_get_positions": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pty_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "pty_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),

@@ -1306,6 +1306,65 @@ pty_status pty_load_patterns(pty_ctx* c, const float* counts, int on_device) {
   });
 }
 
+pty_status pty_guess_probe(pty_ctx* c, double diameter) {
+  return guarded(c, [&] {
+    require(c != nullptr, "pty_guess_probe: null context");
+    require(std::isfinite(diameter) && diameter > 0.0 && diameter <= 2.0 * c->N,
+            "pty_guess_probe: diameter must be in (0, 2 N]");
+    if (!c->have_patterns) throw StateError("pty_guess_probe: patterns not loaded");
+    c->set_device();
+    // mean total counts of the loaded patterns
+    std::vector<double> tot(c->J);
+    double* d_tot = c->alloc<double>(c->J);
+    try {
+      launch_amp_totals(c->amp, d_tot, c->N, c->J, c->stream);
+      copy_out(c, tot.data(), d_tot, sizeof(double) * c->J, 0);
+    } catch (...) {
+      c->dfree(d_tot);
+      throw;
+    }
+    c->dfree(d_tot);
+    double photons = 0.0;
+    for (double t : tot) photons += t;
+    photons /= c->J;
+    // disk and shape functions, modified Gram-Schmidt in FP64
+    const int n = c->N, K = c->K;
+    const size_t nn = size_t(n) * n;
+    const double cc = 0.5 * (n - 1), r2 = 0.25 * diameter * diameter;
+    std::vector<std::vector<double>> m(K, std::vector<double>(nn, 0.0));
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const double u = y - cc, w = x - cc;
+        if (u * u + w * w > r2) continue;
+        const double f[4] = {1.0, w, u, u * w};
+        for (int k = 0; k < K; ++k) m[k][size_t(y) * n + x] = f[k];
+      }
+    for (int k = 0; k < K; ++k) {
+      for (int l = 0; l < k; ++l) {
+        double num = 0.0, den = 0.0;
+        for (size_t q = 0; q < nn; ++q) {
+          num += m[l][q] * m[k][q];
+          den += m[l][q] * m[l][q];
+        }
+        const double a = num / den;
+        for (size_t q = 0; q < nn; ++q) m[k][q] -= a * m[l][q];
+      }
+      double pw = 0.0;
+      for (size_t q = 0; q < nn; ++q) pw += m[k][q] * m[k][q];
+      require(pw > 1e-12 * nn, "pty_guess_probe: diameter too small for the number of modes");
+      const double s = std::sqrt(photons / K / pw);
+      for (size_t q = 0; q < nn; ++q) m[k][q] *= s;
+    }
+    std::vector<float2> out(size_t(K) * nn);
+    for (int k = 0; k < K; ++k)
+      for (size_t q = 0; q < nn; ++q) out[size_t(k) * nn + q] = make_float2((float)m[k][q], 0.f);
+    copy_in(c, c->probe, out.data(), out.size() * sizeof(float2), 0);
+    c->have_probe = true;
+    c->dm_valid = false;
+    c->den_valid = false;
+  });
+}
+
 pty_status pty_set_mask(pty_ctx* c, const uint8_t* mask) {
   return guarded(c, [&] {
     require(c != nullptr, "pty_set_mask: null context");

@@ -203,6 +203,8 @@ void launch_amplitude(const float* counts, float* amp, double* totals, int n, in
 // Marks pixels without a measurement (mask[q] == 0, natural order, shared by
 // all patterns) by the sign bit of their stored modulus; nullptr clears it.
 void launch_apply_mask(float* amp, const unsigned char* mask, int n, int j, hipStream_t s);
+// totals[j] = sum_q amp[j][q]^2 (FP64, one block per pattern)
+void launch_amp_totals(const float* amp, double* totals, int n, int j, hipStream_t s);
 void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s);
 // out[*slot] = E of the partials (slot NULL: out[0]); advance: then ++*slot (the
 // device-side iteration counter, so that a captured iteration can be replayed).

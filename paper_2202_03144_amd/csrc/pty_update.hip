@@ -554,6 +554,18 @@ __global__ __launch_bounds__(256) void k_pattern_totals(const float* __restrict_
   if (threadIdx.x == 0) totals[blockIdx.x] = s;
 }
 
+// Per-pattern sum of the squared stored moduli (the counts, negative ones as
+// 0, whatever the mask).
+__global__ __launch_bounds__(256) void k_amp_totals(const float* __restrict__ amp, double* totals, int n) {
+  __shared__ double red[4];
+  const size_t nn = (size_t)n * n;
+  const float* ap = amp + blockIdx.x * nn;
+  double s = 0.0;
+  for (size_t i = threadIdx.x; i < nn; i += 256) s += (double)ap[i] * ap[i];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) totals[blockIdx.x] = s;
+}
+
 __global__ __launch_bounds__(256) void k_probe_intensity(const float2* probe, float* pint, int n, int k) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   const int nn = n * n;
@@ -1226,6 +1238,11 @@ void launch_apply_mask(float* amp, const unsigned char* mask, int n, int j, hipS
 void launch_pattern_totals(const float* x, double* totals, int n, int j, hipStream_t s) {
   k_pattern_totals<<<j, 256, 0, s>>>(x, totals, n);
   PTY_LAUNCH_CHECK("pattern_totals");
+}
+
+void launch_amp_totals(const float* amp, double* totals, int n, int j, hipStream_t s) {
+  k_amp_totals<<<j, 256, 0, s>>>(amp, totals, n);
+  PTY_LAUNCH_CHECK("amp_totals");
 }
 
 void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s) {

@@ -164,6 +164,11 @@ class Plan:
         self._check(self._lib.pty_get_errors(self._live(), buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
         return buf[: n.value].copy()
 
+    def guess_probe(self, diameter: float) -> None:
+        """Blind start: the probe becomes an aperture guess of the given
+        diameter (pixels), scaled to the loaded patterns (pty_guess_probe)."""
+        self._check(self._lib.pty_guess_probe(self._live(), float(diameter)))
+
     def positions(self) -> np.ndarray:
         """Current scan positions (J, 2) float64: as loaded, or as refined."""
         out = np.empty((self.n_pos, 2), dtype=np.float64)

@@ -75,6 +75,7 @@ def test_null_arguments_are_invalid():
     assert lib.pty_set_state(None, None, 0) == L.E_INVALID
     assert lib.pty_get_positions(None, None) == L.E_INVALID
     assert lib.pty_set_mask(None, None) == L.E_INVALID
+    assert lib.pty_guess_probe(None, 10.0) == L.E_INVALID
     lib.pty_destroy(None)  # NULL-safe
 
 
