@@ -519,6 +519,50 @@ def adjoint_leg(args, torch) -> dict:
     }
 
 
+def blind_leg(args, torch) -> dict:
+    """ePIE, LSQML and DM on the 64 x 64, one-mode, 10 x 10 raster workload
+    started from an aperture guess (pty_guess_probe) instead of the probe,
+    probe updates from the first iteration; NRMSE and E along the way."""
+    import ptysynth
+    import oracle
+    from paper_2202_03144_amd import Plan
+
+    wl = ptysynth.workload(1)
+    obj_true = wl.obj()
+    pos = wl.positions()
+    expected, probe = oracle.simulate(obj_true, wl.probe(), pos, wl.photons)
+    counts = ptysynth.poisson_counts(expected, wl.noise_rng())
+    iters = args.blind_iters
+    marks = [i for i in (10, 100, 300) if i <= iters]
+    out = {}
+    for start in ("disk26", "disk34", "true_probe"):
+        for algo in ("epie", "lsqml", "dm"):
+            pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w))
+            pl.load_patterns(counts)
+            pl.load_positions(pos)
+            pl.set_object(np.ones((wl.h, wl.w), np.complex64))
+            if start == "true_probe":
+                pl.set_probe(probe.astype(np.complex64))
+            else:
+                pl.guess_probe(float(start[4:]))
+            pl.set_truth(obj_true.astype(np.complex64), 0.3)
+            nr0 = pl.nrmse()
+            pl.iterate(algo, iters, probe_update_start=0)
+            h, e = pl.nrmse_history(), pl.errors()
+            pl.close()
+            out[f"{start}.{algo}"] = {"nrmse_start": round(nr0, 4),
+                                      "nrmse_at": {str(i): round(float(h[i - 1]), 4) for i in marks},
+                                      "e_at": {str(i): float(e[i - 1]) for i in marks}}
+            log(f"{start} {algo}: {out[f'{start}.{algo}']}")
+    return {"metric": "blind-start reconstructions (NRMSE)", "value": out["disk34.lsqml"]["nrmse_at"][str(marks[-1])],
+            "unit": "NRMSE", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "64x64 probe, 1 mode, 10x10 raster (8 px step), 160x160 object, Poisson 1e6; "
+                                   f"probe updates from 0, {iters} iterations; starts: disks of 26 and 34 px, "
+                                   "and the true probe"},
+            "runs": out}
+
+
 def positions_leg(args, torch) -> dict:
     """LSQML given the nominal (unjittered) spiral positions of the 256 x 256,
     3-mode, 2,500-position workload whose data were recorded at the jittered
@@ -614,6 +658,9 @@ def main() -> int:
     ap.add_argument("--tiny", action="store_true",
                     help="instead: the 64x64 one-mode raster workload, ePIE / DM / LSQML eager and graphed")
     ap.add_argument("--batch-iters", type=int, default=5)
+    ap.add_argument("--blind", action="store_true",
+                    help="instead: reconstructions of the 64x64 raster workload from an aperture guess")
+    ap.add_argument("--blind-iters", type=int, default=300)
     ap.add_argument("--positions", action="store_true",
                     help="instead: LSQML from nominal positions with and without position refinement")
     ap.add_argument("--position-iters", type=int, default=30)
@@ -644,6 +691,9 @@ def main() -> int:
         return 0
     if args.positions:
         print(json.dumps(positions_leg(args, torch)), flush=True)
+        return 0
+    if args.blind:
+        print(json.dumps(blind_leg(args, torch)), flush=True)
         return 0
     log("building config-2 inputs")
     wl, obj_true, probe, pos, counts = make_inputs(torch)
