@@ -32,7 +32,7 @@ def log(msg: str) -> None:
 
 
 def make_inputs(torch):
-    """Config-2 inputs on the GPU: counts via the library's forward model + a seeded Poisson draw."""
+    """Inputs of the 256 x 256, 3-mode, 2,500-position workload on the GPU: counts via the library's forward model + a seeded Poisson draw."""
     import ptysynth
     from paper_2202_03144_amd import Plan
 
@@ -695,7 +695,7 @@ def main() -> int:
     if args.blind:
         print(json.dumps(blind_leg(args, torch)), flush=True)
         return 0
-    log("building config-2 inputs")
+    log("building the 256x256x3, 2,500-position inputs")
     wl, obj_true, probe, pos, counts = make_inputs(torch)
     # a plain device copy of known size (J x N x N float32 read + written); its
     # HBM counters calibrate the kernel counters in profiles/

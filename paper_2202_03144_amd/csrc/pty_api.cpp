@@ -305,7 +305,7 @@ void timed(pty_ctx* c, int fam, F&& f) {
   if (c->pending.size() > 50000) c->drain_timing();
 }
 
-bool supported_n(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+bool supported_n(int n) { return n == 32 || n == 64 || n == 128 || n == 256 || n == 512; }
 
 void copy_in(pty_ctx* c, void* dst, const void* src, size_t bytes, int on_device) {
   PTY_HIP(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
@@ -1235,8 +1235,9 @@ pty_status pty_default_params(pty_iter_params* p) {
 pty_status pty_create(const pty_plan_desc* plan, pty_ctx** out) {
   return guarded(nullptr, [&] {
     require(plan != nullptr && out != nullptr, "pty_create: null argument");
-    require(supported_n(plan->n), "pty_create: n must be 32, 64, 128 or 256");
+    require(supported_n(plan->n), "pty_create: n must be 32, 64, 128, 256 or 512");
     require(plan->modes >= 1 && plan->modes <= 4, "pty_create: modes must be in 1..4");
+    require(plan->n < 512 || plan->modes <= 2, "pty_create: 512 x 512 windows take at most 2 modes");
     require(plan->n_pos >= 1, "pty_create: n_pos must be >= 1");
     require(plan->obj_h >= plan->n + 1 && plan->obj_w >= plan->n + 1, "pty_create: object must be at least (n+1) x (n+1)");
     require(plan->flags == 0, "pty_create: flags must be 0");

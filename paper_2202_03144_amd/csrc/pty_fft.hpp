@@ -127,6 +127,8 @@ template <>
 struct FftShape<128> { static constexpr int R = 16, T = 8; };
 template <>
 struct FftShape<256> { static constexpr int R = 16, T = 16; };
+template <>
+struct FftShape<512> { static constexpr int R = 32, T = 16; };
 
 // LDS float2 words per line for the exchange (row stride T + 1 avoids bank conflicts)
 template <int N>

@@ -109,6 +109,14 @@ inline void dispatch_nk(int n, int k, F&& f) {
     case 64: dispatch_k<64>(k, f); break;
     case 128: dispatch_k<128>(k, f); break;
     case 256: dispatch_k<256>(k, f); break;
+    case 512:   // 512 x 512 windows: at most 2 modes (register budget of the column pass)
+      if (k == 1)
+        f(ic<512>{}, ic<1>{});
+      else if (k == 2)
+        f(ic<512>{}, ic<2>{});
+      else
+        throw std::invalid_argument("512 x 512 windows take at most 2 probe modes");
+      break;
     default: throw std::invalid_argument("unsupported window size");
   }
 }
@@ -119,6 +127,7 @@ inline void dispatch_n(int n, F&& f) {
     case 64: f(ic<64>{}); break;
     case 128: f(ic<128>{}); break;
     case 256: f(ic<256>{}); break;
+    case 512: f(ic<512>{}); break;
     default: throw std::invalid_argument("unsupported window size");
   }
 }

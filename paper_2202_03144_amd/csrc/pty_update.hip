@@ -138,15 +138,20 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
 // Probe reductions over positions: sum_j w_j conj(S_j O) src_jk and sum_j |S_j O|^2
 // ---------------------------------------------------------------------------
 // Pixel mapping shared by the probe sums and the LSQML step sums: a block of
-// 256 threads covers G = 256 / N column groups; thread (column v, group)
-// walks RB consecutive rows u0 .. u0 + RB - 1, so the object rows under a
-// patch are read once and used for two bilinear rows.
+// 256 threads covers G = 256 / TPR groups of TPR = min(N, 256) consecutive
+// columns; thread (column v, group) walks RB consecutive rows u0 .. u0 + RB - 1,
+// so the object rows under a patch are read once and used for two bilinear
+// rows.  Windows wider than 256 take CB = N / 256 blocks per row band.
 template <int N, int RB>
 struct ColWalk {
-  static constexpr int G = 256 / N;               // row groups per block
+  static constexpr int TPR = N < 256 ? N : 256;   // threads per row segment
+  static constexpr int CB = N / TPR;              // column blocks per row band
+  static constexpr int G = 256 / TPR;             // row groups per block
   static constexpr int ROWS = G * RB;             // rows per block
-  static constexpr int BLOCKS = N / ROWS;         // blocks per window
-  static_assert(N % ROWS == 0 && BLOCKS >= 1, "window must tile");
+  static constexpr int BLOCKS = N / ROWS * CB;    // blocks per window
+  static_assert(N % ROWS == 0 && N % TPR == 0 && BLOCKS >= 1, "window must tile");
+  __device__ static int col(int rblk) { return (rblk % CB) * TPR + (int)threadIdx.x % TPR; }
+  __device__ static int row0(int rblk) { return ((rblk / CB) * G + (int)threadIdx.x / TPR) * RB; }
 };
 
 // Horizontal bilinear combination of object row r at columns c0, c0 + 1
@@ -172,8 +177,8 @@ __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
   const int slice = blockIdx.y, rblk = blockIdx.x;
   const int s_beg = a.s0 + slice * a.per_slice;
   const int s_end = min(s_beg + a.per_slice, a.s0 + a.count);
-  const int v = threadIdx.x % N;
-  const int u0 = (rblk * W::G + threadIdx.x / N) * RB;
+  const int v = W::col(rblk);
+  const int u0 = W::row0(rblk);
   float2 num[K][RB];
   float den[RB];
 #pragma unroll
@@ -336,8 +341,8 @@ __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
   __shared__ double red[NV * 4];
   const int j = a.jlist[b];
   const PosInfo p = a.pos[j];
-  const int v = threadIdx.x % N;
-  const int u0 = (rblk * W::G + threadIdx.x / N) * RB;
+  const int v = W::col(rblk);
+  const int u0 = W::row0(rblk);
   const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
   float m00 = 0.f, m11 = 0.f, m01 = 0.f, v0 = 0.f, v1 = 0.f;
   float ny = 0.f, nx = 0.f, gyy = 0.f, gxx = 0.f;

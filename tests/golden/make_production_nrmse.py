@@ -1,4 +1,4 @@
-"""Writes config2_nrmse.json: the FP64 oracle's NRMSE (and amplitude error E)
+"""Writes production_nrmse.json: the FP64 oracle's NRMSE (and amplitude error E)
 after each of 100 DM and 100 LSQML iterations on the production workload:
 256 x 256 probe with 3 modes, 2,500-point Fermat spiral with +-0.5 px jitter,
 1700 x 1700 object, Poisson counts at 1e8 photons per pattern; start from
@@ -8,7 +8,7 @@ invariant metric on the region where the true probe's illumination is at
 least 0.3 of its maximum.
 
 Only oracle/ and ptysynth/ are called.  Run from the repository root:
-    python tests/golden/make_config2_nrmse.py
+    python tests/golden/make_production_nrmse.py
 (about 1.5 h on 8 cores; writes the JSON next to this file).
 """
 import json
@@ -42,7 +42,7 @@ def main():
     p0 = probe.astype(np.complex64).astype(np.complex128)
     truth = obj_true.astype(np.complex64).astype(np.complex128)
     mask = oracle.roi_mask(p0, pos, *obj_true.shape)
-    out = {"workload": "config 2: 256x256x3, 2,500 spiral positions, 1700x1700, Poisson 1e8; "
+    out = {"workload": "256x256 probe, 3 modes, 2,500 spiral positions, 1700x1700 object, Poisson 1e8; "
                        f"O = 1, true probe, probe updates from {START}, LSQML groups of {BATCH}",
            "nrmse_start": oracle.nrmse(o0, truth, mask)}
     for algo in ("dm", "lsqml"):
@@ -61,7 +61,7 @@ def main():
                   flush=True)
         out[algo] = {"nrmse": nr, "E": es}
         del psi
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "config2_nrmse.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "production_nrmse.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

@@ -46,7 +46,7 @@ def test_default_params():
     assert L.lib().pty_default_params(None) == L.E_INVALID
 
 
-@pytest.mark.parametrize("field,value", [("n", 48), ("n", 512), ("modes", 0), ("modes", 5), ("n_pos", 0),
+@pytest.mark.parametrize("field,value", [("n", 48), ("n", 1024), ("modes", 0), ("modes", 5), ("n_pos", 0),
                                          ("obj_h", 64), ("flags", 1), ("device", -1)])
 def test_create_rejects_bad_plan_before_device(field, value):
     d = L.PlanDesc(64, 1, 10, 160, 160, 0, None, 0)
@@ -55,6 +55,13 @@ def test_create_rejects_bad_plan_before_device(field, value):
     assert L.lib().pty_create(C.byref(d), C.byref(out)) == L.E_INVALID
     assert out.value is None
     assert L.lib().pty_last_error(None)
+
+
+def test_512_windows_take_at_most_two_modes():
+    d = L.PlanDesc(512, 3, 10, 600, 600, 0, None, 0)
+    out = C.c_void_p()
+    assert L.lib().pty_create(C.byref(d), C.byref(out)) == L.E_INVALID
+    assert b"512" in L.lib().pty_last_error(None)
 
 
 def test_null_arguments_are_invalid():

@@ -7,8 +7,8 @@ times (default Fourier chunk, LSQML groups of 500, probe updates on):
   oracle's iteration over all 2,500 positions (object, probe, E, LSQML step
   lengths, sampled DM exit waves), phase-aligned relative L2 <= 1e-4;
 * the final NRMSE after 100 iterations (probe updates from iteration 10)
-  within 2% of the oracle's, read from tests/golden/config2_nrmse.json, which
-  tests/golden/make_config2_nrmse.py writes by calling only the oracle."""
+  within 2% of the oracle's, read from tests/golden/production_nrmse.json, which
+  tests/golden/make_production_nrmse.py writes by calling only the oracle."""
 import json
 import os
 
@@ -22,7 +22,7 @@ from _cases import c64, rel
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_nrmse.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "production_nrmse.json")
 
 
 @pytest.fixture(scope="module")

@@ -22,6 +22,7 @@ SHAPES = [
     (128, 4, 9, 4, 4),
     (256, 3, 10, 3, 4),
     (256, 4, 6, 4, 4),     # modes split over two lane groups in the column pass
+    (512, 2, 5, 3, 3),     # 512-wide windows: two column blocks per row band
 ]
 
 
@@ -121,7 +122,7 @@ def _oracle_run(algo, case, o0, p0, n_iter, start):
 
 @pytest.mark.parametrize("noise", [False, True])
 @pytest.mark.parametrize("algo", ["epie", "dm", "lsqml"])
-def test_config1_final_nrmse_within_2pct(algo, noise):
+def test_raster64_final_nrmse_within_2pct(algo, noise):
     """The full 64^2, 1-mode, 10x10 raster workload: 50 iterations, probe updates from 10.
 
     DM on Poisson data does not converge on this workload: its final NRMSE moves
