@@ -58,7 +58,8 @@ typedef enum {
 
 typedef enum { PTY_EPIE = 0, PTY_DM = 1, PTY_LSQML = 2 } pty_algo;
 
-/* Plan: sizes and device.  n in {32, 64, 128, 256}; 1 <= modes <= 4;
+/* Plan: sizes and device.  n in {32, 64, 128, 256, 512}; 1 <= modes <= 4
+ * (<= 2 at n = 512);
  * n_pos >= 1; obj_h, obj_w >= n + 1.  stream: a hipStream_t to enqueue on
  * (NULL = the library creates its own stream). */
 typedef struct {
