@@ -519,6 +519,60 @@ def adjoint_leg(args, torch) -> dict:
     }
 
 
+LISTING1 = ("./ptycho -jobID=sim512 -beamSize=110e-9 -scanDims=30,30 -step=50e-9,50e-9 -i=100 -size=512 "
+            "-lambda=2.4796837508399954e-10 -dx_d=172e-6 -z=1 -simulate=1 -blind=0")
+
+
+def listing1_leg(args, torch) -> dict:
+    """The paper's script example: the sim512 command string (512 x 512 window,
+    30 x 30 raster of 50 nm steps, 110 nm beam, known probe), simulated data,
+    ePIE driven one step call at a time as in the script; DM and LSQML on the
+    same data for comparison.  The oracle times one ePIE pass over a sample."""
+    import oracle
+    from paper_2202_03144_amd import command
+
+    res = {}
+    for algo in ("epie", "dm", "lsqml"):
+        pl, g, obj, probe = command.simulated_plan(LISTING1)
+        pl.set_truth(obj, 0.3)
+        prm = command.iteration_params(g)
+        pl.iterate(algo, 0, **prm)
+        pl.sync()
+        t = time.perf_counter()
+        for _ in range(g.iterations):
+            pl.iterate(algo, 1, **prm)     # one step call per iteration, as in the script
+        pl.sync()
+        s = time.perf_counter() - t
+        e, h = pl.errors(), pl.nrmse_history()
+        pl.close()
+        res[algo] = {"ms_per_iter": round(s * 1e3 / g.iterations, 3),
+                     "pattern_it_per_s": round(len(g.positions) * g.iterations / s, 1),
+                     "E_first": float(e[0]), "E_last": float(e[-1]),
+                     "nrmse_first": round(float(h[0]), 5), "nrmse_last": round(float(h[-1]), 5)}
+        log(f"{algo}: {res[algo]}")
+    # the oracle: one ePIE pass over the first positions of the same data
+    g = command.geometry(command.parse(LISTING1))
+    obj = command.synthetic_object(g.obj_shape, 0)
+    ns = args.listing1_cpu_sample
+    pos = g.positions[:ns]
+    cnt, pr = oracle.simulate(obj.astype(np.complex128), command.synthetic_probe(g.n, g.modes, g.beam_px), pos, 1e6)
+    amp = oracle.amplitude(cnt)
+    t = time.perf_counter()
+    oracle.epie(np.ones(g.obj_shape, complex), pr, amp, pos, 1, start=1 << 30)
+    cpu_s = time.perf_counter() - t
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"metric": "pattern-iterations/s (the paper's sim512 script, ePIE)",
+            "value": res["epie"]["pattern_it_per_s"], "unit": "pattern-iterations/s", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "512x512 window, 1 mode, 30x30 raster (50 nm = 17.76 px steps), 110 nm "
+                                   "(39.1 px) beam, 1029x1029 object, noise-free simulation at 1e6 photons; "
+                                   "known probe; 100 iterations, one step call each (host-timed)",
+                       "command": LISTING1},
+            "runs": res,
+            "cpu_baseline": {"value": round(ns / cpu_s, 2), "unit": "pattern-iterations/s", "cores": cores,
+                             "kind": "oracle", "sample": f"one ePIE pass over the first {ns} of the 900 positions"}}
+
+
 def blind_leg(args, torch) -> dict:
     """ePIE, LSQML and DM on the 64 x 64, one-mode, 10 x 10 raster workload
     started from an aperture guess (pty_guess_probe) instead of the probe,
@@ -658,6 +712,9 @@ def main() -> int:
     ap.add_argument("--tiny", action="store_true",
                     help="instead: the 64x64 one-mode raster workload, ePIE / DM / LSQML eager and graphed")
     ap.add_argument("--batch-iters", type=int, default=5)
+    ap.add_argument("--listing1", action="store_true",
+                    help="instead: the paper's sim512 script example (ePIE, with DM and LSQML beside it)")
+    ap.add_argument("--listing1-cpu-sample", type=int, default=30)
     ap.add_argument("--blind", action="store_true",
                     help="instead: reconstructions of the 64x64 raster workload from an aperture guess")
     ap.add_argument("--blind-iters", type=int, default=300)
@@ -694,6 +751,9 @@ def main() -> int:
         return 0
     if args.blind:
         print(json.dumps(blind_leg(args, torch)), flush=True)
+        return 0
+    if args.listing1:
+        print(json.dumps(listing1_leg(args, torch)), flush=True)
         return 0
     log("building the 256x256x3, 2,500-position inputs")
     wl, obj_true, probe, pos, counts = make_inputs(torch)

@@ -1,0 +1,163 @@
+"""Command-string front end in the style of the paper's script example
+(Sec. 3.2, Listing 1): ``-key=value`` tokens that describe the experiment in
+physical units, turned into the pixel geometry the library works in, and the
+simulation mode that builds a data set from them.
+
+Keys (a leading program name and unknown ``-`` tokens are rejected, except
+``jobID`` which only names the run):
+
+=============  ==========================================================
+``size``       detector window N (pixels)
+``lambda``     wavelength (m)
+``z``          sample-detector distance (m)
+``dx_d``       detector pixel (m)
+``beamSize``   probe diameter (m)
+``scanDims``   raster rows,cols
+``step``       raster step y,x (m)
+``i``          iterations
+``simulate``   1: build the data from a synthetic object and probe
+``blind``      0: the probe is known (not updated); 1: start from an
+               aperture guess of the beam size, probe updated throughout
+``probeModes`` number of probe modes (default 1)
+``jobID``      run name (kept, not used)
+=============  ==========================================================
+
+Far-field sampling gives the object-plane pixel dx = lambda z / (N dx_d).
+Positions are the raster's top-left corners in object pixels, row-major,
+from a 1-pixel margin; the object is just large enough to hold every patch.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+_FLOAT = {"lambda", "z", "dx_d", "beamSize"}
+_INT = {"size", "i", "simulate", "blind", "probeModes"}
+_PAIR = {"scanDims": int, "step": float}
+_TEXT = {"jobID"}
+
+
+def parse(cmd: str) -> dict:
+    """``-key=value`` tokens to typed values (a first token without ``-`` is
+    taken as the program name and skipped)."""
+    toks = cmd.split()
+    if toks and not toks[0].startswith("-"):
+        toks = toks[1:]
+    out = {}
+    for t in toks:
+        if not t.startswith("-") or "=" not in t:
+            raise ValueError(f"not a -key=value token: {t!r}")
+        k, v = t[1:].split("=", 1)
+        if k in _FLOAT:
+            out[k] = float(v)
+        elif k in _INT:
+            out[k] = int(v)
+        elif k in _PAIR:
+            parts = [_PAIR[k](x) for x in v.split(",")]
+            if len(parts) != 2:
+                raise ValueError(f"-{k} takes two comma-separated values")
+            out[k] = tuple(parts)
+        elif k in _TEXT:
+            out[k] = v
+        else:
+            raise ValueError(f"unknown key -{k}")
+    return out
+
+
+@dataclasses.dataclass
+class Geometry:
+    n: int
+    modes: int
+    pixel: float                 # object-plane pixel (m)
+    beam_px: float               # probe diameter (pixels)
+    step_px: tuple               # raster step y, x (pixels)
+    positions: np.ndarray        # (J, 2) top-left corners (pixels)
+    obj_shape: tuple             # (H, W)
+    iterations: int
+    blind: bool
+
+
+def geometry(opts: dict) -> Geometry:
+    for k in ("size", "lambda", "z", "dx_d", "beamSize", "scanDims", "step"):
+        if k not in opts:
+            raise ValueError(f"missing -{k}")
+    n = opts["size"]
+    dx = opts["lambda"] * opts["z"] / (n * opts["dx_d"])
+    sy, sx = (s / dx for s in opts["step"])
+    rows, cols = opts["scanDims"]
+    margin = 1.0
+    yy, xx = np.meshgrid(margin + sy * np.arange(rows), margin + sx * np.arange(cols), indexing="ij")
+    pos = np.stack([yy.ravel(), xx.ravel()], axis=1)
+    h = int(math.floor(pos[:, 0].max())) + n + 2
+    w = int(math.floor(pos[:, 1].max())) + n + 2
+    return Geometry(n=n, modes=opts.get("probeModes", 1), pixel=dx, beam_px=opts["beamSize"] / dx,
+                    step_px=(sy, sx), positions=pos, obj_shape=(h, w), iterations=opts.get("i", 100),
+                    blind=bool(opts.get("blind", 0)))
+
+
+def synthetic_object(shape, seed: int = 0, corr: float = 4.0) -> np.ndarray:
+    """A seeded phase-and-amplitude test object standing in for the paper's
+    simulation image: Gaussian-correlated noise (correlation length ``corr``
+    pixels), amplitude in [0.8, 1], phase in [-0.5, 0.5] rad."""
+    rng = np.random.default_rng([2202, 3144, seed])
+    ky = np.fft.fftfreq(shape[0])[:, None]
+    kx = np.fft.fftfreq(shape[1])[None, :]
+    g = np.exp(-2.0 * (math.pi * corr) ** 2 * (ky * ky + kx * kx))
+
+    def field():
+        f = np.real(np.fft.ifft2(np.fft.fft2(rng.standard_normal(shape)) * g))
+        return (f - f.min()) / (f.max() - f.min())
+    return ((0.8 + 0.2 * field()) * np.exp(1j * (field() - 0.5))).astype(np.complex64)
+
+
+def synthetic_probe(n: int, modes: int, beam_px: float) -> np.ndarray:
+    """The known probe of the simulation: a disk of the beam diameter with a
+    defocus-like quadratic phase (0.8 rad at the rim), later modes weaker
+    copies times x, y ramps, total power 1 (the forward model rescales it)."""
+    c = (n - 1) / 2.0
+    u, v = np.meshgrid(np.arange(n) - c, np.arange(n) - c, indexing="ij")
+    rr = (u * u + v * v) / (beam_px / 2.0) ** 2
+    disk = (rr <= 1.0) * np.exp(1j * 0.8 * rr)
+    shapes = [disk, disk * v / (beam_px / 2), disk * u / (beam_px / 2), disk * u * v / (beam_px / 2) ** 2]
+    p = np.stack([shapes[k] * (0.5 ** k) for k in range(modes)])
+    return (p / math.sqrt(float(np.sum(np.abs(p) ** 2)))).astype(np.complex64)
+
+
+def simulated_plan(cmd: str, photons: float = 1e6, seed: int = 0, device: int = 0, stream=None):
+    """Simulation mode: the plan of the command with noise-free expected
+    counts of a synthetic object and probe loaded (``photons`` per pattern on
+    average), the object set to 1, and the probe set to the true one
+    (``-blind=0``) or to the aperture guess of the beam size (``-blind=1``).
+    Returns (plan, geometry, true object, true probe)."""
+    import torch
+
+    from .plan import Plan
+
+    opts = parse(cmd)
+    if opts.get("simulate", 0) != 1:
+        raise ValueError("only the simulation mode (-simulate=1) builds its own data")
+    g = geometry(opts)
+    obj = synthetic_object(g.obj_shape, seed)
+    probe0 = synthetic_probe(g.n, g.modes, g.beam_px)
+    pl = Plan(g.n, g.modes, len(g.positions), g.obj_shape, device=device, stream=stream)
+    pl.load_positions(g.positions)
+    pl.set_object(obj)
+    pl.set_probe(probe0)
+    counts = torch.empty((len(g.positions), g.n, g.n), dtype=torch.float32, device=f"cuda:{device}")
+    pl.simulate(photons, out=counts)
+    probe = pl.probe()                 # scaled to the photon budget
+    pl.load_patterns(counts)
+    del counts
+    pl.set_object(np.ones(g.obj_shape, np.complex64))
+    if g.blind:
+        pl.guess_probe(g.beam_px)
+    else:
+        pl.set_probe(probe)
+    return pl, g, obj, probe
+
+
+def iteration_params(g: Geometry) -> dict:
+    """Known probe: never updated; blind start: updated from the first iteration."""
+    return {"probe_update_start": 0 if g.blind else -1}

@@ -6,7 +6,9 @@ the current object / probe back as NumPy arrays at any time, and
 ``<algo>post()`` releases everything.  Whole mode: ``<algo>(...)`` runs all
 iterations and returns (object, probe).  Inputs are arrays rather than the
 paper's command string: counts (J, N, N), positions (J, 2), object guess,
-probe guess, plus iteration parameters as keywords.
+probe guess, plus iteration parameters as keywords.  ``<algo>init(cmd)``
+with a command string instead (see :mod:`.command`) runs the paper's
+simulation mode, as in Listing 1.
 """
 from __future__ import annotations
 
@@ -15,8 +17,13 @@ from .plan import Plan, reconstruct
 _current: dict = {}
 
 
-def _init(algo, counts, positions, obj, probe, device=0, **params):
+def _init(algo, counts, positions=None, obj=None, probe=None, device=0, **params):
     _post(algo)
+    if isinstance(counts, str):
+        from .command import iteration_params, simulated_plan
+        pl, g, _, _ = simulated_plan(counts, device=device)
+        _current[algo] = (pl, {**iteration_params(g), **params})
+        return
     pl = Plan(counts.shape[-1], probe.shape[0], counts.shape[0], obj.shape, device=device)
     pl.load_patterns(counts)
     pl.load_positions(positions)
@@ -46,7 +53,7 @@ def _whole(algo, counts, positions, obj, probe, n_iter, **params):
     return o, p
 
 
-def epieinit(counts, positions, obj, probe, **params): _init("epie", counts, positions, obj, probe, **params)
+def epieinit(counts, positions=None, obj=None, probe=None, **params): _init("epie", counts, positions, obj, probe, **params)
 def epiestep(n=1): _step("epie", n)
 def epieresobj(): return _plan("epie")[0].object()
 def epieresprobe(): return _plan("epie")[0].probe()
@@ -54,7 +61,7 @@ def epiepost(): _post("epie")
 def epie(counts, positions, obj, probe, n_iter, **params): return _whole("epie", counts, positions, obj, probe, n_iter, **params)
 
 
-def dminit(counts, positions, obj, probe, **params): _init("dm", counts, positions, obj, probe, **params)
+def dminit(counts, positions=None, obj=None, probe=None, **params): _init("dm", counts, positions, obj, probe, **params)
 def dmstep(n=1): _step("dm", n)
 def dmresobj(): return _plan("dm")[0].object()
 def dmresprobe(): return _plan("dm")[0].probe()
@@ -62,7 +69,7 @@ def dmpost(): _post("dm")
 def dm(counts, positions, obj, probe, n_iter, **params): return _whole("dm", counts, positions, obj, probe, n_iter, **params)
 
 
-def lsqmlinit(counts, positions, obj, probe, **params): _init("lsqml", counts, positions, obj, probe, **params)
+def lsqmlinit(counts, positions=None, obj=None, probe=None, **params): _init("lsqml", counts, positions, obj, probe, **params)
 def lsqmlstep(n=1): _step("lsqml", n)
 def lsqmlresobj(): return _plan("lsqml")[0].object()
 def lsqmlresprobe(): return _plan("lsqml")[0].probe()

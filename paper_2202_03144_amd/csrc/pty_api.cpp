@@ -109,6 +109,7 @@ struct pty_ctx {
   double2* mode_gram = nullptr;    // K x K Gram matrix of the probe modes
   float2* mode_mix = nullptr;      // K x K mixing matrix of the orthogonalisation
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
+  unsigned* epie_max = nullptr;    // per position of an iteration: the two ePIE step normalisers
 
   // device-side iteration counter (error / NRMSE history slot of the running
   // iteration), so that one captured iteration can be replayed
@@ -856,6 +857,9 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       end_iteration(c, t);
       continue;
     }
+    c->ensure_once(c->epie_max, size_t(2) * c->J);
+    timed(c, kOther, [&] { launch_fill_u32(c->epie_max, size_t(2) * c->J, 0u, c->stream); });
+    int slot = 0;
     for (int j : order) {
       a.jl_off = j;
       a.obj = c->obj;
@@ -876,6 +880,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       e.alpha = p.alpha;
       e.beta = p.beta;
       e.probe_on = pon ? 1 : 0;
+      e.maxes = c->epie_max + 2 * slot++;
       e.stream = c->stream;
       timed(c, kEpie, [&] { launch_epie_update(e); });
       std::swap(c->probe, c->probe_alt);

@@ -155,6 +155,7 @@ struct EpieArgs {
   PosInfo pos;
   float alpha, beta;
   int probe_on;
+  unsigned* maxes;         // 2 zeroed slots of this position: max sum_k |P_k|^2, max |S_j O|^2 (float bits)
   hipStream_t stream;
 };
 void launch_epie_update(const EpieArgs& a);

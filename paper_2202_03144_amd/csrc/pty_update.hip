@@ -443,60 +443,77 @@ __global__ void k_lsq_solve(LsqStepArgs a, int nrb) {
 }
 
 // ---------------------------------------------------------------------------
-// ePIE update of one position (one block; positions are sequential)
+// ePIE update of one position (positions are sequential): the two step
+// normalisers max_r sum_k |P_k|^2 and max_r |S_j O|^2, then the probe update
+// with the pre-update patch, then the object update with the pre-update
+// probe — three grid-wide launches
 // ---------------------------------------------------------------------------
 template <int N, int K>
-__global__ __launch_bounds__(1024) void k_epie_update(EpieArgs a) {
-  __shared__ float redf[16];
-  const PosInfo p = a.pos;
+__global__ __launch_bounds__(256) void k_epie_max(EpieArgs a) {
+  __shared__ float redf[4];
   constexpr int NN = N * N;
-  float pm = 0.f, om = 0.f;
-  for (int q = threadIdx.x; q < NN; q += 1024) {
-    float s = 0.f;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  float s = 0.f, o = 0.f;
+  if (q < NN) {
 #pragma unroll
     for (int k = 0; k < K; ++k) s += cabs2(a.probe[(size_t)k * NN + q]);
-    pm = fmaxf(pm, s);
-    om = fmaxf(om, cabs2(obj_bilinear(a.obj, a.h, a.w, p, q / N, q % N)));
+    o = cabs2(obj_bilinear(a.obj, a.h, a.w, a.pos, q / N, q % N));
   }
-  const float pmax = block_max_all<1024>(pm, redf);
-  const float omax = block_max_all<1024>(om, redf);
-  // probe update with the pre-update object patch
+  const float ps = block_max_all<256>(s, redf);
+  const float os = block_max_all<256>(o, redf);
+  // non-negative floats order like their bit patterns
+  if (threadIdx.x == 0) {
+    atomicMax(a.maxes, __float_as_uint(ps));
+    atomicMax(a.maxes + 1, __float_as_uint(os));
+  }
+}
+
+template <int N, int K>
+__global__ __launch_bounds__(256) void k_epie_probe(EpieArgs a) {
+  constexpr int NN = N * N;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= NN) return;
+  const float omax = __uint_as_float(a.maxes[1]);
   const bool pu = a.probe_on && omax > 0.f;
   const float bs = pu ? a.beta / omax : 0.f;
-  for (int q = threadIdx.x; q < NN; q += 1024) {
-    const float2 o = obj_bilinear(a.obj, a.h, a.w, p, q / N, q % N);
+  const float2 o = obj_bilinear(a.obj, a.h, a.w, a.pos, q / N, q % N);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const size_t i = (size_t)k * NN + q;
-      a.probe_out[i] = a.probe[i] + bs * cconjmul(o, a.chi[i]);
-    }
+  for (int k = 0; k < K; ++k) {
+    const size_t i = (size_t)k * NN + q;
+    a.probe_out[i] = a.probe[i] + bs * cconjmul(o, a.chi[i]);
   }
-  __syncthreads();
+}
+
+template <int N, int K>
+__global__ __launch_bounds__(256) void k_epie_object(EpieArgs a) {
+  constexpr int NN = N * N;
+  const float pmax = __uint_as_float(a.maxes[0]);
   if (!(pmax > 0.f)) return;
-  // object update over the (N+1)^2 footprint with the pre-update probe
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (N + 1) * (N + 1)) return;
+  const PosInfo p = a.pos;
+  const int u = e / (N + 1), v = e % (N + 1);
+  const int Y = p.iy + u, X = p.ix + v;
+  if (Y >= a.h || X >= a.w) return;
+  // S_j^T over the (N+1)^2 footprint: the up to four patch pixels whose taps reach (Y, X)
   const float as = a.alpha / pmax;
   const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
-  for (int e = threadIdx.x; e < (N + 1) * (N + 1); e += 1024) {
-    const int u = e / (N + 1), v = e % (N + 1);
-    const int Y = p.iy + u, X = p.ix + v;
-    if (Y >= a.h || X >= a.w) continue;
-    float2 s = make_float2(0.f, 0.f);
+  float2 s = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int tap = 0; tap < 4; ++tap) {
-      const int uu = u - (tap >> 1), vv = v - (tap & 1);
-      if ((unsigned)uu >= (unsigned)N || (unsigned)vv >= (unsigned)N) continue;
-      const float wt = ((tap >> 1) ? wy1 : wy0) * ((tap & 1) ? wx1 : wx0);
-      float2 tv = make_float2(0.f, 0.f);
+  for (int tap = 0; tap < 4; ++tap) {
+    const int uu = u - (tap >> 1), vv = v - (tap & 1);
+    if ((unsigned)uu >= (unsigned)N || (unsigned)vv >= (unsigned)N) continue;
+    const float wt = ((tap >> 1) ? wy1 : wy0) * ((tap & 1) ? wx1 : wx0);
+    float2 tv = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const size_t i = (size_t)k * NN + uu * N + vv;
-        tv = tv + cconjmul(a.probe[i], a.chi[i]);
-      }
-      s = s + wt * tv;
+    for (int k = 0; k < K; ++k) {
+      const size_t i = (size_t)k * NN + uu * N + vv;
+      tv = tv + cconjmul(a.probe[i], a.chi[i]);
     }
-    const size_t o = (size_t)Y * a.w + X;
-    a.obj[o] = a.obj[o] + as * s;
+    s = s + wt * tv;
   }
+  const size_t o = (size_t)Y * a.w + X;
+  a.obj[o] = a.obj[o] + as * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -1207,7 +1224,10 @@ void launch_epie_fused(const EpieRunArgs& a) {
 void launch_epie_update(const EpieArgs& a) {
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
-    k_epie_update<N, K><<<1, 1024, 0, a.stream>>>(a);
+    const unsigned g = (N * N + 255) / 256, gf = ((N + 1) * (N + 1) + 255) / 256;
+    k_epie_max<N, K><<<g, 256, 0, a.stream>>>(a);
+    k_epie_probe<N, K><<<g, 256, 0, a.stream>>>(a);
+    k_epie_object<N, K><<<gf, 256, 0, a.stream>>>(a);
   });
   PTY_LAUNCH_CHECK("epie_update");
 }
