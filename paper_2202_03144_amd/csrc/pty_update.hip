@@ -448,16 +448,21 @@ __global__ void k_lsq_solve(LsqStepArgs a, int nrb) {
 // with the pre-update patch, then the object update with the pre-update
 // probe — three grid-wide launches
 // ---------------------------------------------------------------------------
+// Few blocks, each striding over the window, so that only a few hundred
+// atomics meet on the two slots (one per block and slot).
+constexpr int kEpieMaxBlocks = 64;
+
 template <int N, int K>
 __global__ __launch_bounds__(256) void k_epie_max(EpieArgs a) {
   __shared__ float redf[4];
   constexpr int NN = N * N;
-  const int q = blockIdx.x * 256 + threadIdx.x;
   float s = 0.f, o = 0.f;
-  if (q < NN) {
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < NN; q += kEpieMaxBlocks * 256) {
+    float t = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) s += cabs2(a.probe[(size_t)k * NN + q]);
-    o = cabs2(obj_bilinear(a.obj, a.h, a.w, a.pos, q / N, q % N));
+    for (int k = 0; k < K; ++k) t += cabs2(a.probe[(size_t)k * NN + q]);
+    s = fmaxf(s, t);
+    o = fmaxf(o, cabs2(obj_bilinear(a.obj, a.h, a.w, a.pos, q / N, q % N)));
   }
   const float ps = block_max_all<256>(s, redf);
   const float os = block_max_all<256>(o, redf);
@@ -1225,7 +1230,7 @@ void launch_epie_update(const EpieArgs& a) {
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
     const unsigned g = (N * N + 255) / 256, gf = ((N + 1) * (N + 1) + 255) / 256;
-    k_epie_max<N, K><<<g, 256, 0, a.stream>>>(a);
+    k_epie_max<N, K><<<std::min<unsigned>(g, kEpieMaxBlocks), 256, 0, a.stream>>>(a);
     k_epie_probe<N, K><<<g, 256, 0, a.stream>>>(a);
     k_epie_object<N, K><<<gf, 256, 0, a.stream>>>(a);
   });
