@@ -83,15 +83,15 @@ def iteration_bytes(plan, n, k, j, h, w, groups):
 # launches (profiles/dm_fourier_256x3_hbm_counters.md): read = 2.0 x FETCH_SIZE,
 # written = 1.0 x WRITE_SIZE (factors from a plain copy of known size).  Valid
 # only while the kernel sources hash to COUNTER_SRC_HASH.
-COUNTER_SRC_HASH = "c9b28c490fb3679f"
+COUNTER_SRC_HASH = "af74c615a51e9f08"
 COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp"]
 MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns per launch)
-    ("dm", "rows_fwd"): (68064.9, 98304.0, 64),
-    ("dm", "cols"): (65735.8, 98336.0, 64),
-    ("dm", "rows_inv"): (66733.7, 131072.0, 64),
-    ("lsqml", "rows_fwd"): (16621.9, 98304.0, 64),
-    ("lsqml", "cols"): (65735.8, 98336.0, 64),
-    ("lsqml", "rows_inv"): (51281.8, 131072.0, 64),
+    ("dm", "rows_fwd"): (67620.1, 98304.0, 64),
+    ("dm", "cols"): (65735.9, 98336.0, 64),
+    ("dm", "rows_inv"): (66728.4, 131072.0, 64),
+    ("lsqml", "rows_fwd"): (16584.9, 98304.0, 64),
+    ("lsqml", "cols"): (65735.9, 98336.0, 64),
+    ("lsqml", "rows_inv"): (51323.7, 131072.0, 64),
 }
 
 

@@ -503,6 +503,7 @@ FourierArgs fourier_args(pty_ctx* c, const Group& g) {
   a.posgrad = c->posgrad;
   a.tw = reinterpret_cast<const float*>(c->tw);
   a.nll_eps = 1e-6f;
+  a.masked = c->have_mask ? 1 : 0;
   a.stream = c->stream;
   return a;
 }
@@ -1385,6 +1386,7 @@ pty_status pty_set_mask(pty_ctx* c, const uint8_t* mask) {
       copy_in(c, c->mask, nat.data(), nat.size(), 0);
     }
     c->have_mask = mask != nullptr;
+    c->drop_graphs();   // captured iterations carry the mask flag in their arguments
     if (c->have_patterns) launch_apply_mask(c->amp, c->have_mask ? c->mask : nullptr, c->N, c->J, c->stream);
     PTY_HIP(hipStreamSynchronize(c->stream));
   });

@@ -93,7 +93,7 @@ struct ColSplit {
   static constexpr int BPP = N / CW;              // blocks per pattern
 };
 
-template <int N, int K, ColOp OP>
+template <int N, int K, ColOp OP, bool MASK>
 __global__ __launch_bounds__(Geo<N>::BS)
 void k_cols(FourierArgs a) {
   using G = Geo<N>;
@@ -140,26 +140,47 @@ void k_cols(FourierArgs a) {
       if (lead) {
         const float ar = a.amp[((size_t)j * N + pr) * N + x];
         const float d = ar * ar;
-        if (!signbit(ar)) e_num += inten - d * logf(inten + a.nll_eps);
+        const float l = inten - d * logf(inten + a.nll_eps);
+        if constexpr (MASK)
+          e_num += signbit(ar) ? 0.f : l;
+        else
+          e_num += l;
       }
     } else {
-      // a set sign bit marks a pixel without a measurement: the projection
-      // keeps the model there and the pixel adds to no sum
+      // With a detector mask, a set sign bit marks a pixel without a
+      // measurement: the projection keeps the model there and the pixel adds
+      // to no sum.  (A separate instantiation, so that the unmasked kernels
+      // keep their register budget.)
       const float ar = a.amp[((size_t)j * N + pr) * N + x];
-      const bool meas = !signbit(ar);
-      const float am = fabsf(ar);
+      float mf = 1.f, am = ar;
+      if constexpr (MASK) {
+        mf = signbit(ar) ? 0.f : 1.f;
+        am = fabsf(ar);
+      }
       float f;
       if constexpr (OP == ColOp::Project) {
         const float mod = sqrtf(iraw) * sc;
-        f = meas ? am / fmaxf(mod, 1e-6f) - 1.f : 0.f;
-        if (lead && meas) {
-          e_num += (mod - am) * (mod - am);
-          e_den += am * am;
+        f = am / fmaxf(mod, 1e-6f) - 1.f;
+        if constexpr (MASK) f *= mf;
+        if (lead) {
+          if constexpr (MASK) {
+            e_num += mf * ((mod - am) * (mod - am));
+            e_den += mf * (am * am);
+          } else {
+            e_num += (mod - am) * (mod - am);
+            e_den += am * am;
+          }
         }
       } else {
         const float d = am * am;
-        f = meas ? a.grad_scale * (1.f - d / (inten + a.nll_eps)) : 0.f;
-        if (lead && meas) e_num += inten - d * logf(inten + a.nll_eps);
+        f = a.grad_scale * (1.f - d / (inten + a.nll_eps));
+        const float l = inten - d * logf(inten + a.nll_eps);
+        if constexpr (MASK) {
+          f *= mf;
+          if (lead) e_num += mf * l;
+        } else {
+          if (lead) e_num += l;
+        }
       }
       f *= sc2;
 #pragma unroll
@@ -308,11 +329,20 @@ void launch_cols(const FourierArgs& a, ColOp op) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
     const dim3 grid(ColSplit<N, K>::BPP, a.nc);
     constexpr int BS = Geo<N>::BS;
-    switch (op) {
-      case ColOp::Project: k_cols<N, K, ColOp::Project><<<grid, BS, 0, a.stream>>>(a); break;
-      case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad><<<grid, BS, 0, a.stream>>>(a); break;
-      case ColOp::Intensity: k_cols<N, K, ColOp::Intensity><<<grid, BS, 0, a.stream>>>(a); break;
-      case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss><<<grid, BS, 0, a.stream>>>(a); break;
+    if (a.masked) {
+      switch (op) {
+        case ColOp::Project: k_cols<N, K, ColOp::Project, true><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad, true><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::Intensity: k_cols<N, K, ColOp::Intensity, false><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss, true><<<grid, BS, 0, a.stream>>>(a); break;
+      }
+    } else {
+      switch (op) {
+        case ColOp::Project: k_cols<N, K, ColOp::Project, false><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad, false><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::Intensity: k_cols<N, K, ColOp::Intensity, false><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss, false><<<grid, BS, 0, a.stream>>>(a); break;
+      }
     }
   });
   PTY_LAUNCH_CHECK("cols");

@@ -40,6 +40,7 @@ struct FourierArgs {
   int nc;                 // patterns in the chunk
   float nll_eps;
   float grad_scale;       // NllGrad: multiplies every gradient
+  int masked;             // 1: the moduli carry a detector mask (sign bits)
   hipStream_t stream;
 };
 
