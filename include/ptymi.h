@@ -225,7 +225,9 @@ pty_status pty_mem_bytes(const pty_ctx* ctx, size_t* out);
  * probe_update_start and the ePIE visiting order), the error history, the
  * NRMSE history while a truth is set, and the DM exit waves while they are
  * current.  With them a new context of the same shape continues a run
- * exactly: n iterations, save, restore, n iterations reproduce 2n.
+ * exactly: n iterations, save, restore, n iterations reproduce 2n.  Positions
+ * refined by LSQML travel separately (pty_get_positions, then
+ * pty_load_positions before the object, probe and state are restored).
  *
  * Host buffer, native byte order:
  *   64-byte header: the 8 characters "PTYSTAT1"; int32 n, modes, n_pos,
