@@ -72,3 +72,30 @@ def test_refinement_refusals_and_positions_round_trip():
     assert len(pl.errors()) == 0
     assert np.max(np.abs(pl.positions() - pos0)) <= 1e-6
     pl.close()
+
+
+def test_resume_with_refined_positions_is_exact():
+    from paper_2202_03144_amd import Plan
+    case = spiral_case(64, 2, 40, cfg=62)
+    pos0 = _nominal(case)
+    o0, p0 = start_state(case, perturb=0.05)
+    params = dict(probe_update_start=0, lsqml_batch=12, position_start=1)
+    ref = _plan(case, pos0, o0, p0)
+    ref.iterate("lsqml", 4, **params)
+    want = (ref.object(), ref.probe(), ref.errors(), ref.positions())
+    ref.close()
+    first = _plan(case, pos0, o0, p0)
+    first.iterate("lsqml", 2, **params)
+    blob, obj, probe, pos = first.state(), first.object(), first.probe(), first.positions()
+    first.close()
+    resumed = Plan(case.n, case.k, case.j, case.shape)
+    resumed.load_patterns(case.counts)
+    resumed.load_positions(pos)
+    resumed.set_object(obj)
+    resumed.set_probe(probe)
+    resumed.set_state(blob)
+    resumed.iterate("lsqml", 2, **params)
+    got = (resumed.object(), resumed.probe(), resumed.errors(), resumed.positions())
+    resumed.close()
+    for name, a, b in zip(("object", "probe", "E", "positions"), got, want):
+        assert np.array_equal(a, b), name
