@@ -110,6 +110,7 @@ struct pty_ctx {
   float2* mode_mix = nullptr;      // K x K mixing matrix of the orthogonalisation
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
   unsigned* epie_max = nullptr;    // per position of an iteration: the two ePIE step normalisers
+  float2* epie_patch = nullptr;    // N x N: the pre-update patch of the current ePIE position
 
   // device-side iteration counter (error / NRMSE history slot of the running
   // iteration), so that one captured iteration can be replayed
@@ -859,6 +860,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       continue;
     }
     c->ensure_once(c->epie_max, size_t(2) * c->J);
+    c->ensure_once(c->epie_patch, nn);
     timed(c, kOther, [&] { launch_fill_u32(c->epie_max, size_t(2) * c->J, 0u, c->stream); });
     int slot = 0;
     for (int j : order) {
@@ -882,6 +884,7 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       e.beta = p.beta;
       e.probe_on = pon ? 1 : 0;
       e.maxes = c->epie_max + 2 * slot++;
+      e.patch = c->epie_patch;
       e.stream = c->stream;
       timed(c, kEpie, [&] { launch_epie_update(e); });
       std::swap(c->probe, c->probe_alt);

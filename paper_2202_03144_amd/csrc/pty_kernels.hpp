@@ -157,6 +157,7 @@ struct EpieArgs {
   float alpha, beta;
   int probe_on;
   unsigned* maxes;         // 2 zeroed slots of this position: max sum_k |P_k|^2, max |S_j O|^2 (float bits)
+  float2* patch;           // N x N scratch: the pre-update patch S_j O
   hipStream_t stream;
 };
 void launch_epie_update(const EpieArgs& a);

@@ -444,9 +444,9 @@ __global__ void k_lsq_solve(LsqStepArgs a, int nrb) {
 
 // ---------------------------------------------------------------------------
 // ePIE update of one position (positions are sequential): the two step
-// normalisers max_r sum_k |P_k|^2 and max_r |S_j O|^2, then the probe update
-// with the pre-update patch, then the object update with the pre-update
-// probe — three grid-wide launches
+// normalisers max_r sum_k |P_k|^2 and max_r |S_j O|^2 (storing the
+// pre-update patch S_j O), then the probe update with that patch and the
+// object update with the pre-update probe — two grid-wide launches
 // ---------------------------------------------------------------------------
 // Few blocks, each striding over the window, so that only a few hundred
 // atomics meet on the two slots (one per block and slot).
@@ -462,7 +462,9 @@ __global__ __launch_bounds__(256) void k_epie_max(EpieArgs a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) t += cabs2(a.probe[(size_t)k * NN + q]);
     s = fmaxf(s, t);
-    o = fmaxf(o, cabs2(obj_bilinear(a.obj, a.h, a.w, a.pos, q / N, q % N)));
+    const float2 ov = obj_bilinear(a.obj, a.h, a.w, a.pos, q / N, q % N);
+    a.patch[q] = ov;      // the pre-update patch, for the probe update
+    o = fmaxf(o, cabs2(ov));
   }
   const float ps = block_max_all<256>(s, redf);
   const float os = block_max_all<256>(o, redf);
@@ -473,28 +475,30 @@ __global__ __launch_bounds__(256) void k_epie_max(EpieArgs a) {
   }
 }
 
+// Probe and object updates in one launch: the first blocks update the probe
+// pixels from the stored pre-update patch (into probe_out), the rest the
+// object footprint with the pre-update probe, so the two never touch the
+// same memory.
 template <int N, int K>
-__global__ __launch_bounds__(256) void k_epie_probe(EpieArgs a) {
+__global__ __launch_bounds__(256) void k_epie_apply(EpieArgs a, int probe_blocks) {
   constexpr int NN = N * N;
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= NN) return;
-  const float omax = __uint_as_float(a.maxes[1]);
-  const bool pu = a.probe_on && omax > 0.f;
-  const float bs = pu ? a.beta / omax : 0.f;
-  const float2 o = obj_bilinear(a.obj, a.h, a.w, a.pos, q / N, q % N);
+  if ((int)blockIdx.x < probe_blocks) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= NN) return;
+    const float omax = __uint_as_float(a.maxes[1]);
+    const bool pu = a.probe_on && omax > 0.f;
+    const float bs = pu ? a.beta / omax : 0.f;
+    const float2 o = a.patch[q];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const size_t i = (size_t)k * NN + q;
-    a.probe_out[i] = a.probe[i] + bs * cconjmul(o, a.chi[i]);
+    for (int k = 0; k < K; ++k) {
+      const size_t i = (size_t)k * NN + q;
+      a.probe_out[i] = a.probe[i] + bs * cconjmul(o, a.chi[i]);
+    }
+    return;
   }
-}
-
-template <int N, int K>
-__global__ __launch_bounds__(256) void k_epie_object(EpieArgs a) {
-  constexpr int NN = N * N;
   const float pmax = __uint_as_float(a.maxes[0]);
   if (!(pmax > 0.f)) return;
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = (blockIdx.x - probe_blocks) * 256 + threadIdx.x;
   if (e >= (N + 1) * (N + 1)) return;
   const PosInfo p = a.pos;
   const int u = e / (N + 1), v = e % (N + 1);
@@ -503,7 +507,7 @@ __global__ __launch_bounds__(256) void k_epie_object(EpieArgs a) {
   // S_j^T over the (N+1)^2 footprint: the up to four patch pixels whose taps reach (Y, X)
   const float as = a.alpha / pmax;
   const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
-  float2 s = make_float2(0.f, 0.f);
+  float2 sum = make_float2(0.f, 0.f);
 #pragma unroll
   for (int tap = 0; tap < 4; ++tap) {
     const int uu = u - (tap >> 1), vv = v - (tap & 1);
@@ -515,10 +519,10 @@ __global__ __launch_bounds__(256) void k_epie_object(EpieArgs a) {
       const size_t i = (size_t)k * NN + uu * N + vv;
       tv = tv + cconjmul(a.probe[i], a.chi[i]);
     }
-    s = s + wt * tv;
+    sum = sum + wt * tv;
   }
   const size_t o = (size_t)Y * a.w + X;
-  a.obj[o] = a.obj[o] + as * s;
+  a.obj[o] = a.obj[o] + as * sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -1231,8 +1235,7 @@ void launch_epie_update(const EpieArgs& a) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
     const unsigned g = (N * N + 255) / 256, gf = ((N + 1) * (N + 1) + 255) / 256;
     k_epie_max<N, K><<<std::min<unsigned>(g, kEpieMaxBlocks), 256, 0, a.stream>>>(a);
-    k_epie_probe<N, K><<<g, 256, 0, a.stream>>>(a);
-    k_epie_object<N, K><<<gf, 256, 0, a.stream>>>(a);
+    k_epie_apply<N, K><<<g + gf, 256, 0, a.stream>>>(a, (int)g);
   });
   PTY_LAUNCH_CHECK("epie_update");
 }
