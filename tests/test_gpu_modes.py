@@ -39,7 +39,7 @@ def _plan(case, o0, p0):
 
 
 @pytest.mark.parametrize("algo", ["epie", "dm", "lsqml"])
-@pytest.mark.parametrize("n,k,j", [(64, 2, 20), (128, 3, 9)])
+@pytest.mark.parametrize("n,k,j", [(64, 2, 20), (128, 3, 9), (256, 3, 6), (512, 2, 4)])
 def test_orthogonalised_iterations_match_oracle(algo, n, k, j):
     case = spiral_case(n, k, j, cfg=63)
     o0, p0 = _start(case)

@@ -31,7 +31,8 @@ def _plan(case, pos, o0, p0):
 
 
 # (N, K, J, chunk, lsqml batch, probe update start)
-@pytest.mark.parametrize("n,k,j,chunk,batch,start", [(64, 2, 40, 7, 12, 1), (128, 1, 20, 6, 8, 0)])
+@pytest.mark.parametrize("n,k,j,chunk,batch,start", [(64, 2, 40, 7, 12, 1), (128, 1, 20, 6, 8, 0),
+                                                     (256, 3, 10, 4, 6, 1)])
 def test_refined_lsqml_matches_oracle(n, k, j, chunk, batch, start):
     case = spiral_case(n, k, j, cfg=62)
     pos0 = _nominal(case)
