@@ -80,7 +80,7 @@ struct View {
 template <int BM, int BN, bool RELU, bool BIAS>
 __global__ __launch_bounds__(256) void k_conv_gemm(View in, const bf16* __restrict__ w,
                                                    const float* __restrict__ bias, View out, int nb, int S,
-                                                   int cin, int cout) {
+                                                   int cin, int cout, View lo, int clo) {
   constexpr int WN = BN / 32, WM = 4 / WN;
   static_assert(WM * 64 == BM, "wavefront tiles must cover the block tile");
   constexpr int MT = 4, NT = 2;
@@ -111,14 +111,23 @@ __global__ __launch_bounds__(256) void k_conv_gemm(View in, const bf16* __restri
   const bool b_on = tid < BN * 4;
   const int cb = cin / 32, steps = 9 * cb;
   bf16x8_t ra[AP], rb;
+  // Input channels below clo (inference only) come from the half-resolution
+  // tensor `lo`, read at (y / 2, x / 2): the nearest 2x upsampling of the
+  // decoder, folded into the load instead of being written out first.
+  const int Sl = S >> 1;
   auto fetch = [&](int st) {
     const int tap = st / cb, c0 = (st % cb) * 32;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const bool from_lo = c0 < clo;
 #pragma unroll
     for (int r = 0; r < AP; ++r) {
       const int yy = ay[r] + dy, xx = ax[r] + dx;
       if (aok[r] && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
-        ra[r] = *reinterpret_cast<const bf16x8_t*>(in.p + ((size_t)(ab[r] * S + yy) * S + xx) * in.cs + in.co + c0 + ac);
+        if (from_lo)
+          ra[r] = *reinterpret_cast<const bf16x8_t*>(lo.p + ((size_t)(ab[r] * Sl + (yy >> 1)) * Sl + (xx >> 1)) * lo.cs +
+                                                     lo.co + c0 + ac);
+        else
+          ra[r] = *reinterpret_cast<const bf16x8_t*>(in.p + ((size_t)(ab[r] * S + yy) * S + xx) * in.cs + in.co + c0 + ac);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) ra[r][e] = static_cast<bf16>(0.0f);
@@ -749,21 +758,25 @@ pty_status cnn_guard(pty_cnn* c, F&& f) {
 
 View V(bf16* p, int cs, int co = 0) { return View{p, cs, co}; }
 
+// lo / clo: the first clo input channels read from the half-resolution
+// tensor lo (a fused nearest 2x upsampling); clo = 0: all from `in`.
 void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out, int nb, int S, int cin, int cout,
-                 bool relu) {
+                 bool relu, View lo = View{nullptr, 0, 0}, int clo = 0) {
   const int mtot = nb * S * S;
   if (cin % 32 != 0 || cout % 32 != 0) throw std::invalid_argument("conv channels must be multiples of 32");
+  if (clo % 32 != 0 || clo > cin || (clo > 0 && (lo.p == nullptr || S % 2 != 0)))
+    throw std::invalid_argument("conv: bad upsampled-input split");
   hipStream_t s = c->stream;
   if (cout % 64 == 0) {
     dim3 grid(blocks(mtot, 128), cout / 64);
-    if (relu) k_conv_gemm<128, 64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else if (bias) k_conv_gemm<128, 64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else k_conv_gemm<128, 64, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    if (relu) k_conv_gemm<128, 64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
+    else if (bias) k_conv_gemm<128, 64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
+    else k_conv_gemm<128, 64, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
   } else {
     dim3 grid(blocks(mtot, 256), cout / 32);
-    if (relu) k_conv_gemm<256, 32, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else if (bias) k_conv_gemm<256, 32, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
-    else k_conv_gemm<256, 32, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout);
+    if (relu) k_conv_gemm<256, 32, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
+    else if (bias) k_conv_gemm<256, 32, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
+    else k_conv_gemm<256, 32, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
   }
   PTY_LAUNCH_CHECK("conv_gemm");
 }
@@ -815,12 +828,24 @@ void forward(pty_cnn* c, const float* x, int nb, bool train) {
   k_pool<<<blocks((size_t)nb * 8 * 8 * 16), 256, 0, s>>>(V(c->cat6, 384, 256), V(c->p3, 128), nb, 16, 128);
   launch_conv(c, V(c->p3, 128), w + L[4].woff, c->p + L[4].boff, V(c->a4, 256), nb, 8, 128, 256, true);
   launch_conv(c, V(c->a4, 256), w + L[5].woff, c->p + L[5].boff, V(c->a5, 256), nb, 8, 256, 256, true);
-  k_up<<<blocks((size_t)nb * 16 * 16 * 32), 256, 0, s>>>(V(c->a5, 256), V(c->cat6, 384, 0), nb, 8, 256);
-  launch_conv(c, V(c->cat6, 384), w + L[6].woff, c->p + L[6].boff, V(c->a6, 128), nb, 16, 384, 128, true);
-  k_up<<<blocks((size_t)nb * 32 * 32 * 16), 256, 0, s>>>(V(c->a6, 128), V(c->cat7, 192, 0), nb, 16, 128);
-  launch_conv(c, V(c->cat7, 192), w + L[7].woff, c->p + L[7].boff, V(c->a7, 64), nb, 32, 192, 64, true);
-  k_up<<<blocks((size_t)nb * 64 * 64 * 8), 256, 0, s>>>(V(c->a7, 64), V(c->cat8, 96, 0), nb, 32, 64);
-  launch_conv(c, V(c->cat8, 96), w + L[8].woff, c->p + L[8].boff, V(c->a8, 32), nb, 64, 96, 32, true);
+  if (train) {
+    // the weight gradients read the concatenated inputs, so write them out
+    k_up<<<blocks((size_t)nb * 16 * 16 * 32), 256, 0, s>>>(V(c->a5, 256), V(c->cat6, 384, 0), nb, 8, 256);
+    launch_conv(c, V(c->cat6, 384), w + L[6].woff, c->p + L[6].boff, V(c->a6, 128), nb, 16, 384, 128, true);
+    k_up<<<blocks((size_t)nb * 32 * 32 * 16), 256, 0, s>>>(V(c->a6, 128), V(c->cat7, 192, 0), nb, 16, 128);
+    launch_conv(c, V(c->cat7, 192), w + L[7].woff, c->p + L[7].boff, V(c->a7, 64), nb, 32, 192, 64, true);
+    k_up<<<blocks((size_t)nb * 64 * 64 * 8), 256, 0, s>>>(V(c->a7, 64), V(c->cat8, 96, 0), nb, 32, 64);
+    launch_conv(c, V(c->cat8, 96), w + L[8].woff, c->p + L[8].boff, V(c->a8, 32), nb, 64, 96, 32, true);
+  } else {
+    // inference: the upsampled channels are read straight from the decoder's
+    // half-resolution output inside the convolutions
+    launch_conv(c, V(c->cat6, 384), w + L[6].woff, c->p + L[6].boff, V(c->a6, 128), nb, 16, 384, 128, true,
+                V(c->a5, 256), 256);
+    launch_conv(c, V(c->cat7, 192), w + L[7].woff, c->p + L[7].boff, V(c->a7, 64), nb, 32, 192, 64, true,
+                V(c->a6, 128), 128);
+    launch_conv(c, V(c->cat8, 96), w + L[8].woff, c->p + L[8].boff, V(c->a8, 32), nb, 64, 96, 32, true,
+                V(c->a7, 64), 64);
+  }
   k_conv_out<<<blocks((size_t)nb * 64 * 64), 256, 0, s>>>(V(c->a8, 32), w + L[9].woff, c->p + L[9].boff, c->y, nb);
   PTY_LAUNCH_CHECK("cnn_forward");
 }
