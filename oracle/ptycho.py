@@ -50,6 +50,8 @@ __all__ = [
     "scatter_add",
     "amplitude",
     "project_delta",
+    "poisson_step",
+    "poisson_delta",
     "forward_intensity",
     "simulate",
     "model_error",
@@ -184,6 +186,47 @@ def project_delta(psi_f: np.ndarray, a: np.ndarray):
     return delta, float(np.sum(np.where(valid, (mod - am) ** 2, 0.0))), float(np.sum(am * am))
 
 
+def poisson_step(inten: np.ndarray, d: np.ndarray, eps: float = EPS_L) -> float:
+    """Step length alpha_R of the Poisson exit-wave update of one pattern.
+
+    ``inten``: (N, N) model intensity I; ``d``: (N, N) measured counts, NaN
+    where nothing was measured (those pixels add nothing).  Along the negative
+    gradient of the Poisson likelihood in the detector plane the far field
+    becomes Psi (1 - alpha g), g = 1 - d / (I + eps), so every intensity
+    becomes I (1 - alpha g)^2.  alpha_R is one Newton step from alpha = 0 on
+    L(alpha) = sum [I (1 - alpha g)^2 - d log(I (1 - alpha g)^2)]:
+    L'(0) = -2 sum I g^2, L''(0) = 2 sum (I + d) g^2, with d I / (I + eps) in
+    place of d so that eps enters as in g; hence
+    alpha_R = sum I g^2 / sum (I + d I / (I + eps)) g^2, in (0, 1]; 0 when the
+    numerator is 0.
+    """
+    valid = np.isfinite(d)
+    dm = np.where(valid, d, 0.0)
+    g = np.where(valid, 1.0 - dm / (inten + eps), 0.0)
+    num = float(np.sum(inten * g * g))
+    den = float(np.sum((inten + dm * inten / (inten + eps)) * g * g))
+    return num / den if num > 0.0 else 0.0
+
+
+def poisson_delta(psi_f: np.ndarray, a: np.ndarray, eps: float = EPS_L):
+    """Difference Delta = -alpha_R g Psi of the Poisson exit-wave update.
+
+    ``psi_f``: (K, N, N) far field; ``a``: (N, N) measured moduli (d = a^2),
+    NaN where nothing was measured (g = 0 there).  alpha_R from
+    :func:`poisson_step`.  Returns (Delta, alpha_R, and the amplitude-error
+    partials of :func:`project_delta`: sum (sqrt(I) - A)^2, sum A^2).
+    """
+    inten = np.sum(np.abs(psi_f) ** 2, axis=0)
+    valid = np.isfinite(a)
+    am = np.where(valid, a, 0.0)
+    d = np.where(valid, am * am, np.nan)
+    alpha = poisson_step(inten, d, eps)
+    g = np.where(valid, 1.0 - am * am / (inten + eps), 0.0)
+    delta = (-alpha * g)[None] * psi_f
+    mod = np.sqrt(inten)
+    return delta, alpha, float(np.sum(np.where(valid, (mod - am) ** 2, 0.0))), float(np.sum(am * am))
+
+
 def forward_intensity(obj: np.ndarray, probe: np.ndarray, r) -> np.ndarray:
     """I_j = sum_k |F(P_k S_j O)|^2 in natural order (mixed-state forward model)."""
     n = probe.shape[-1]
@@ -216,11 +259,19 @@ def model_error(obj: np.ndarray, probe: np.ndarray, a: np.ndarray, pos: np.ndarr
     return num / den
 
 
-def _exit_diff(probe: np.ndarray, oj: np.ndarray, a: np.ndarray, z: np.ndarray | None = None):
-    """chi = F^-1 Delta(F z) with z = P (S_j O) unless given; plus the error partials."""
+def _exit_diff(probe: np.ndarray, oj: np.ndarray, a: np.ndarray, z: np.ndarray | None = None,
+               likelihood: str = "amplitude"):
+    """chi = F^-1 Delta(F z) with z = P (S_j O) unless given; plus the error
+    partials.  Delta: the modulus projection's (``likelihood="amplitude"``) or
+    the Poisson update's (``"poisson"``, :func:`poisson_delta`)."""
     if z is None:
         z = probe * oj[None]
-    delta, e1, e2 = project_delta(fft2u(z), a)
+    if likelihood == "poisson":
+        delta, _, e1, e2 = poisson_delta(fft2u(z), a)
+    elif likelihood == "amplitude":
+        delta, e1, e2 = project_delta(fft2u(z), a)
+    else:
+        raise ValueError(f"unknown likelihood {likelihood!r}")
     return ifft2u(delta), e1, e2
 
 
@@ -462,7 +513,7 @@ def position_shift(obj, probe, chi, r, max_shift):
 
 def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
           gamma_probe=1e-3, beta_obj=1.0, beta_probe=1.0, return_alpha=False,
-          pos_start=-1, max_shift=0.5, return_positions=False, ortho=False):
+          pos_start=-1, max_shift=0.5, return_positions=False, ortho=False, likelihood="amplitude"):
     """``n_iter`` LSQML iterations; returns (object, probe, [E], alpha of last iteration).
 
     Positions are split into G = ceil(J / batch) interleaved groups
@@ -484,7 +535,11 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
       (0 <= R <= size - N).  ``return_positions`` adds the refined positions
       to the returned tuple;
     * ``ortho``: after every iteration that updated the probe,
-      :func:`orthogonalise_modes`.
+      :func:`orthogonalise_modes`;
+    * ``likelihood="poisson"``: chi_j = F^-1 of :func:`poisson_delta` (the
+      Poisson exit-wave update) in place of the modulus projection's; every
+      other step is the same least-squares solver (E stays the amplitude
+      error).
     """
     obj = np.array(obj, dtype=np.complex128)
     probe = np.array(probe, dtype=np.complex128)
@@ -509,7 +564,7 @@ def lsqml(obj, probe, a, pos, n_iter, t0=0, start=0, batch=512, gamma_obj=1e-3,
             chis, ojs = {}, {}
             for j in idx:
                 oj = gather(obj, pos[j], n)
-                chi, e1, e2 = _exit_diff(probe, oj, a[j])
+                chi, e1, e2 = _exit_diff(probe, oj, a[j], likelihood=likelihood)
                 e_num += e1
                 e_den += e2
                 chis[j], ojs[j] = chi, oj
