@@ -31,12 +31,16 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_inputs(torch):
-    """Inputs of the 256 x 256, 3-mode, 2,500-position workload on the GPU: counts via the library's forward model + a seeded Poisson draw."""
+def make_inputs(torch, photons=None):
+    """Inputs of the 256 x 256, 3-mode, 2,500-position workload on the GPU: counts via the library's forward model + a seeded Poisson draw
+    (``photons`` per pattern on average: the workload's own dose unless given)."""
+    import dataclasses
     import ptysynth
     from paper_2202_03144_amd import Plan
 
     wl = ptysynth.workload(2)
+    if photons is not None:
+        wl = dataclasses.replace(wl, photons=float(photons))
     obj_true = wl.obj().astype(np.complex64)
     probe = wl.probe().astype(np.complex64)
     pos = wl.positions()
@@ -83,15 +87,15 @@ def iteration_bytes(plan, n, k, j, h, w, groups):
 # launches (profiles/dm_fourier_256x3_hbm_counters.md): read = 2.0 x FETCH_SIZE,
 # written = 1.0 x WRITE_SIZE (factors from a plain copy of known size).  Valid
 # only while the kernel sources hash to COUNTER_SRC_HASH.
-COUNTER_SRC_HASH = "af74c615a51e9f08"
+COUNTER_SRC_HASH = "97c3d9de734fde33"
 COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp"]
 MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns per launch)
-    ("dm", "rows_fwd"): (67620.1, 98304.0, 64),
-    ("dm", "cols"): (65735.9, 98336.0, 64),
-    ("dm", "rows_inv"): (66728.4, 131072.0, 64),
-    ("lsqml", "rows_fwd"): (16584.9, 98304.0, 64),
-    ("lsqml", "cols"): (65735.9, 98336.0, 64),
-    ("lsqml", "rows_inv"): (51323.7, 131072.0, 64),
+    ("dm", "rows_fwd"): (67568.0, 98304.0, 64),
+    ("dm", "cols"): (65735.7, 98336.0, 64),
+    ("dm", "rows_inv"): (66733.9, 131072.0, 64),
+    ("lsqml", "rows_fwd"): (16534.9, 98304.0, 64),
+    ("lsqml", "cols"): (65735.7, 98336.0, 64),
+    ("lsqml", "rows_inv"): (50594.1, 131072.0, 64),
 }
 
 
@@ -684,6 +688,71 @@ def positions_leg(args, torch) -> dict:
     }
 
 
+def poisson_leg(args, torch) -> dict:
+    """LSQML on the 256 x 256, 3-mode, 2,500-position workload with the
+    modulus-projection (amplitude) and the Poisson exit-wave updates, from a
+    flat object with the true probe: per-iteration time, NRMSE, E and the
+    Poisson likelihood of the result, and the per-family kernel times."""
+    from paper_2202_03144_amd import Plan
+
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    iters = args.poisson_iters
+
+    def run(likelihood: str):
+        pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
+        pl.load_patterns(counts)
+        pl.load_positions(pos)
+        pl.set_object(np.ones((wl.h, wl.w), np.complex64))
+        pl.set_probe(probe)
+        pl.set_truth(obj_true, 0.3)
+        prm = dict(base, likelihood=likelihood)
+        pl.iterate("lsqml", 0, **prm)
+        pl.sync()
+        t = time.perf_counter()
+        pl.iterate("lsqml", iters, **prm)
+        pl.sync()
+        ms = (time.perf_counter() - t) * 1e3 / iters
+        h, e = pl.nrmse_history(), pl.errors()
+        o = torch.from_numpy(pl.object()).to("cuda")
+        p = torch.from_numpy(pl.probe()).to("cuda")
+        nll = pl.nll_forward(o, p)
+        pl.set_timing(True)
+        pl.iterate("lsqml", 1, **prm)
+        fam = {k: round(v[0], 3) for k, v in pl.timing().items() if v[1]}
+        pl.set_timing(False)
+        pl.close()
+        at = {str(i): round(float(h[i - 1]), 5) for i in (1, 2, 5, 10, 20, 30, 50) if i <= len(h)}
+        return {"ms_per_iter": round(ms, 3), "pattern_it_per_s": round(wl.j / (ms * 1e-3), 1), "nrmse_at": at,
+                "e_at": {k: float(e[int(k) - 1]) for k in at}, "poisson_nll_last": nll,
+                "kernel_ms_one_iteration": fam}
+
+    doses = {}
+    for photons in (None, args.poisson_low_dose):
+        wl, obj_true, probe, pos, counts = make_inputs(torch, photons)
+        base = dict(probe_update_start=wl.probe_start, lsqml_batch=500)
+        out = {}
+        for lk in ("amplitude", "poisson"):
+            log(f"{wl.photons:g} photons, {lk}")
+            out[lk] = run(lk)
+            log(f"{lk}: {out[lk]}")
+        out["poisson_cost"] = round(out["poisson"]["ms_per_iter"] / out["amplitude"]["ms_per_iter"], 3)
+        doses[f"{wl.photons:g}"] = out
+        del counts
+    high = doses[next(iter(doses))]
+    return {
+        "metric": "LSQML with the Poisson exit-wave update: pattern-iterations/s and NRMSE",
+        "value": high["poisson"]["pattern_it_per_s"], "unit": "pattern-iterations/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256x256 probe, 3 modes, 2,500-point jittered Fermat spiral, 1700x1700 object, "
+                               f"Poisson noise at the workload's 1e8 photons per pattern and at "
+                               f"{args.poisson_low_dose:g}; flat start, true probe, probe updates from "
+                               f"{wl.probe_start}, LSQML groups of 500, {iters} iterations (host-timed)",
+                   "n": wl.n, "modes": wl.k, "positions": wl.j},
+        "by_photons": doses,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -722,6 +791,10 @@ def main() -> int:
                     help="instead: LSQML from nominal positions with and without position refinement")
     ap.add_argument("--position-iters", type=int, default=30)
     ap.add_argument("--position-start", type=int, default=3)
+    ap.add_argument("--poisson", action="store_true",
+                    help="LSQML with the amplitude and the Poisson exit-wave updates on the production workload")
+    ap.add_argument("--poisson-iters", type=int, default=30)
+    ap.add_argument("--poisson-low-dose", type=float, default=1e5, help="photons per pattern of the low-dose arm")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing was run.",
@@ -751,6 +824,9 @@ def main() -> int:
         return 0
     if args.blind:
         print(json.dumps(blind_leg(args, torch)), flush=True)
+        return 0
+    if args.poisson:
+        print(json.dumps(poisson_leg(args, torch)), flush=True)
         return 0
     if args.listing1:
         print(json.dumps(listing1_leg(args, torch)), flush=True)

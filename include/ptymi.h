@@ -101,6 +101,17 @@ typedef struct {
  *                        sum_k |P_k|^2 and the object trajectory do not
  *                        change.  With equal mode powers the basis is not
  *                        unique.
+ *                        PTY_ITER_POISSON (LSQML only, else
+ *                        PTY_E_UNSUPPORTED): the exit-wave update follows
+ *                        the Poisson likelihood (the other noise model of
+ *                        LSQML, Odstrcil et al. 2018) instead of the modulus
+ *                        projection: chi_j = F^-1[-alpha_R,j g Psi_j],
+ *                        g = 1 - d / (I + 1e-6) on measured pixels (0 on
+ *                        unmeasured ones), with alpha_R,j one Newton step of
+ *                        pattern j's likelihood along that direction:
+ *                        sum I g^2 / sum (I + d I / (I + 1e-6)) g^2, in
+ *                        [0, 1].  The least-squares object and probe steps
+ *                        are unchanged; E stays the amplitude error.
  *   position_start       LSQML position refinement from this global iteration
  *                        on; < 0 = never (default).  Each position moves by
  *                        the least-squares shift that explains its exit-wave
@@ -117,6 +128,7 @@ typedef struct {
  *                        (default 0.5). */
 #define PTY_ITER_GRAPH 1u
 #define PTY_ITER_ORTHO_MODES 2u
+#define PTY_ITER_POISSON 4u
 typedef struct {
   float alpha, beta;
   int32_t probe_update_start;
@@ -125,7 +137,7 @@ typedef struct {
   float beta_obj, beta_probe;
   uint64_t order_seed;
   int32_t chunk;
-  uint32_t flags; /* PTY_ITER_GRAPH | PTY_ITER_ORTHO_MODES */
+  uint32_t flags; /* PTY_ITER_GRAPH | PTY_ITER_ORTHO_MODES | PTY_ITER_POISSON */
   int32_t position_start;
   float position_max_shift;
 } pty_iter_params;

@@ -114,6 +114,7 @@ SIGNATURES = {
 
 ITER_GRAPH = 1
 ITER_ORTHO_MODES = 2
+ITER_POISSON = 4
 
 TIMING_FAMILIES = ["rows_fwd", "cols", "rows_inv", "obj_gather", "probe_acc", "probe_finish_apply",
                    "lsq_steps", "epie_update", "other"]

@@ -106,6 +106,7 @@ struct pty_ctx {
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
   float2* shift = nullptr;         size_t shift_slots = 0;   // LSQML position shifts per slot
+  double* poisp = nullptr;         size_t poisp_n = 0;       // Poisson step sums per (slot, column block)
   double2* mode_gram = nullptr;    // K x K Gram matrix of the probe modes
   float2* mode_mix = nullptr;      // K x K mixing matrix of the orthogonalisation
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
@@ -519,6 +520,7 @@ void fourier_pass(pty_ctx* c, const Group& g, int s0, int count, int chunk, RowI
     a.slot_off = s0 + off;
     a.nc = std::min(chunk, count - off);
     timed(c, kRowsFwd, [&] { launch_rows_fwd(a, in); });
+    a.poisp = op == ColOp::Poisson ? c->poisp : nullptr;
     timed(c, kCols, [&] { launch_cols(a, op); });
     if (inverse && op != ColOp::Intensity) timed(c, kRowsInv, [&] { launch_rows_inv(a, out); });
   }
@@ -728,6 +730,8 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   const bool refining = p.position_start >= 0 && p.position_start < c->iter + n_iter;
   c->ensure(c->lsq_part, c->lsq_part_n, size_t(bmax) * nrb * (refining ? 9 : 5));
   if (refining) c->ensure(c->shift, c->shift_slots, size_t(bmax));
+  const bool poisson = (p.flags & PTY_ITER_POISSON) != 0;
+  if (poisson) c->ensure(c->poisp, c->poisp_n, size_t(bmax) * col_blocks(c->N, c->K) * 2);
   ensure_probe_parts(c, bmax);
   ensure_err_slot(c, n_iter);
   ensure_mode_scratch(c, p);
@@ -739,7 +743,8 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
     for (auto& g : c->groups) {
       const int count = (int)g.jl.size();
       density(c, g);
-      fourier_pass(c, g, 0, count, chunk, RowIn::Plain, ColOp::Project, RowOut::StoreChi);
+      fourier_pass(c, g, 0, count, chunk, RowIn::Plain, poisson ? ColOp::Poisson : ColOp::Project,
+                   RowOut::StoreChi);
       ObjGatherArgs o = obj_args(c, g);
       o.gamma = g_obj;
       o.out = c->dobj;
@@ -1452,7 +1457,10 @@ pty_status pty_iterate(pty_ctx* c, pty_algo algo, int32_t n_iter, const pty_iter
     pty_iter_params p;
     pty_default_params(&p);
     if (prm) p = *prm;
-    require((p.flags & ~(PTY_ITER_GRAPH | PTY_ITER_ORTHO_MODES)) == 0, "pty_iterate: unknown flags");
+    require((p.flags & ~(PTY_ITER_GRAPH | PTY_ITER_ORTHO_MODES | PTY_ITER_POISSON)) == 0,
+            "pty_iterate: unknown flags");
+    if ((p.flags & PTY_ITER_POISSON) && algo != PTY_LSQML)
+      throw Unsupported("pty_iterate: the Poisson exit-wave update runs in LSQML only");
     require(p.chunk >= 0, "pty_iterate: negative chunk");
     require(p.lsqml_batch >= 0, "pty_iterate: negative lsqml_batch");
     if (p.position_start >= 0) {

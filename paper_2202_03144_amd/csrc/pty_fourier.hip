@@ -94,8 +94,7 @@ struct ColSplit {
 };
 
 template <int N, int K, ColOp OP, bool MASK>
-__global__ __launch_bounds__(Geo<N>::BS)
-void k_cols(FourierArgs a) {
+__device__ __forceinline__ void cols_body(const FourierArgs& a) {
   using G = Geo<N>;
   using S = ColSplit<N, K>;
   constexpr int R = G::R, T = G::T, CW = S::CW, BPP = S::BPP, MS = S::MS, KM = K / MS;
@@ -124,7 +123,7 @@ void k_cols(FourierArgs a) {
   // unitary inverse of the whole pipeline contributes another 1 / N^2, both
   // folded into the per-pixel factor applied before the inverse transforms.
   constexpr float sc = 1.0f / N, sc2 = 1.0f / (float(N) * float(N));
-  float e_num = 0.f, e_den = 0.f;
+  float e_num = 0.f, e_den = 0.f, q_num = 0.f, q_den = 0.f;
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int pr = t + T * m;
@@ -158,9 +157,23 @@ void k_cols(FourierArgs a) {
         am = fabsf(ar);
       }
       float f;
-      if constexpr (OP == ColOp::Project) {
+      if constexpr (OP == ColOp::Project || OP == ColOp::Poisson) {
         const float mod = sqrtf(iraw) * sc;
-        f = am / fmaxf(mod, 1e-6f) - 1.f;
+        if constexpr (OP == ColOp::Project) {
+          f = am / fmaxf(mod, 1e-6f) - 1.f;
+        } else {
+          // the Poisson update moves Psi by -alpha_R g Psi; alpha_R is one
+          // Newton step of the pattern's likelihood along that ray, from the
+          // pattern-wide sums of I g^2 and (I + d I / (I + eps)) g^2
+          // (I + d I / (I + eps)) g^2 = I g^2 (1 + r), r = d / (I + eps);
+          // the hardware reciprocal (1 ulp) in place of the full division
+          // keeps the kernel within two wavefronts per SIMD
+          const float r = (am * am) * __builtin_amdgcn_rcpf(inten + a.nll_eps);
+          f = 1.f - r;
+          const float ig2 = (lead ? mf : 0.f) * (inten * f * f);
+          q_num += ig2;
+          q_den = fmaf(ig2, 2.f - f, q_den);   // 1 + r = 2 - g
+        }
         if constexpr (MASK) f *= mf;
         if (lead) {
           if constexpr (MASK) {
@@ -187,7 +200,22 @@ void k_cols(FourierArgs a) {
       for (int k = 0; k < KM; ++k) z[k][m] = f * z[k][m];
     }
   }
-  if constexpr (OP == ColOp::Project || OP == ColOp::NllGrad) {
+  if constexpr (OP == ColOp::Poisson) {
+    // reduced before the inverse transforms, which then carry no sums
+    const double s0 = block_sum<G::BS>((double)e_num, red);
+    const double s1 = block_sum<G::BS>((double)e_den, red);
+    const double s2 = block_sum<G::BS>((double)q_num, red);
+    const double s3 = block_sum<G::BS>((double)q_den, red);
+    if (threadIdx.x == 0) {
+      double* e = a.errp + ((size_t)j * BPP + cb) * 2;
+      e[0] = s0;
+      e[1] = s1;
+      double* q = a.poisp + ((size_t)(a.slot_off + c) * BPP + cb) * 2;
+      q[0] = s2;
+      q[1] = s3;
+    }
+  }
+  if constexpr (OP == ColOp::Project || OP == ColOp::NllGrad || OP == ColOp::Poisson) {
 #pragma unroll
     for (int k = 0; k < KM; ++k) line_fft<N, true>(z[k], buf, tw_s, t);
 #pragma unroll
@@ -196,7 +224,7 @@ void k_cols(FourierArgs a) {
       for (int m = 0; m < R; ++m) base[(size_t)k * N * N + zoff<N>(t + T * m, x)] = z[k][m];
     }
   }
-  if constexpr (OP != ColOp::Intensity) {
+  if constexpr (OP != ColOp::Intensity && OP != ColOp::Poisson) {
     const double s0 = block_sum<G::BS>((double)e_num, red);
     const double s1 = block_sum<G::BS>((double)e_den, red);
     if (threadIdx.x == 0) {
@@ -205,6 +233,21 @@ void k_cols(FourierArgs a) {
       e[1] = s1;
     }
   }
+}
+
+template <int N, int K, ColOp OP, bool MASK>
+__global__ __launch_bounds__(Geo<N>::BS)
+void k_cols(FourierArgs a) {
+  cols_body<N, K, OP, MASK>(a);
+}
+
+// The Poisson step carries two more sums and a division per pixel; left to
+// itself the compiler gives the 256^2 x 3-mode instance one wavefront per
+// SIMD, which doubles its time.  Held to two, it spills a few registers.
+template <int N, int K, bool MASK>
+__global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
+void k_cols_poisson(FourierArgs a) {
+  cols_body<N, K, ColOp::Poisson, MASK>(a);
 }
 
 template <int N, int K, RowOut MODE>
@@ -233,6 +276,21 @@ void k_rows_inv(FourierArgs a) {
 #pragma unroll
     for (int m = 0; m < R; ++m) obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, gdy[m], gdx[m]);
   }
+  // Poisson update: chi = -alpha_R F^-1[g Psi]; every block of the pattern
+  // sums the column blocks' partials in the same order
+  float chi_s = 1.f;
+  if constexpr (MODE == RowOut::StoreChi) {
+    if (a.poisp) {
+      constexpr int CB = ColSplit<N, K>::BPP;
+      const double* q = a.poisp + (size_t)slot * CB * 2;
+      double q0 = 0.0, q1 = 0.0;
+      for (int i = 0; i < CB; ++i) {
+        q0 += q[2 * i];
+        q1 += q[2 * i + 1];
+      }
+      chi_s = q0 > 0.0 ? (float)(-(q0 / q1)) : 0.f;
+    }
+  }
   float2 cacc[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) cacc[m] = make_float2(0.f, 0.f);
@@ -255,6 +313,12 @@ void k_rows_inv(FourierArgs a) {
       for (int m = 0; m < R; ++m) pkr[m] = pr[t + T * m];
     }
     line_fft<N, true>(z, xb + line * G::W, tw_s, t);
+    if constexpr (MODE == RowOut::StoreChi) {
+      if (a.poisp) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) z[m] = chi_s * z[m];
+      }
+    }
     if constexpr (MODE == RowOut::DmUpdate) {
       float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
 #pragma unroll
@@ -335,6 +399,7 @@ void launch_cols(const FourierArgs& a, ColOp op) {
         case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad, true><<<grid, BS, 0, a.stream>>>(a); break;
         case ColOp::Intensity: k_cols<N, K, ColOp::Intensity, false><<<grid, BS, 0, a.stream>>>(a); break;
         case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss, true><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::Poisson: k_cols_poisson<N, K, true><<<grid, BS, 0, a.stream>>>(a); break;
       }
     } else {
       switch (op) {
@@ -342,6 +407,7 @@ void launch_cols(const FourierArgs& a, ColOp op) {
         case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad, false><<<grid, BS, 0, a.stream>>>(a); break;
         case ColOp::Intensity: k_cols<N, K, ColOp::Intensity, false><<<grid, BS, 0, a.stream>>>(a); break;
         case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss, false><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::Poisson: k_cols_poisson<N, K, false><<<grid, BS, 0, a.stream>>>(a); break;
       }
     }
   });

@@ -8,8 +8,10 @@ namespace pty {
 
 // Prologue of the forward row pass: z = P S_j O, or z = 2 P S_j O - psi_j (DM).
 enum class RowIn { Plain = 0, DmReflect = 1 };
-// Per-pixel step of the column pass.
-enum class ColOp { Project = 0, NllGrad = 1, Intensity = 2, NllLoss = 3 };
+// Per-pixel step of the column pass.  Poisson: the direction g Psi of the
+// Poisson exit-wave update, g = 1 - d / (I + eps), with the two sums of its
+// step length per (slot, column block) in poisp and the amplitude error.
+enum class ColOp { Project = 0, NllGrad = 1, Intensity = 2, NllLoss = 3, Poisson = 4 };
 // Epilogue of the inverse row pass.
 enum class RowOut { DmUpdate = 0, StoreChi = 1, NllGrad = 2 };
 // Object-tile gather: what is accumulated and how it is applied.
@@ -41,6 +43,10 @@ struct FourierArgs {
   float nll_eps;
   float grad_scale;       // NllGrad: multiplies every gradient
   int masked;             // 1: the moduli carry a detector mask (sign bits)
+  double* poisp;          // Poisson: per (slot, column block) sum I g^2 and
+                          // sum (I + d I / (I + eps)) g^2; the StoreChi rows
+                          // then scale by -alpha_R = -(first / second); null:
+                          // the modulus projection's chi, unscaled
   hipStream_t stream;
 };
 

@@ -18,6 +18,13 @@ from ._lib import PtyError
 ALGOS = {"epie": L.EPIE, "dm": L.DM, "lsqml": L.LSQML}
 
 
+def _flags(flags: int, graph: bool, ortho_modes: bool, likelihood: str) -> int:
+    if likelihood not in ("amplitude", "poisson"):
+        raise ValueError(f"likelihood must be 'amplitude' or 'poisson', not {likelihood!r}")
+    return (int(flags) | (L.ITER_GRAPH if graph else 0) | (L.ITER_ORTHO_MODES if ortho_modes else 0)
+            | (L.ITER_POISSON if likelihood == "poisson" else 0))
+
+
 def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
 
@@ -108,17 +115,17 @@ class Plan:
         del keep
 
     # -- iteration ---------------------------------------------------------
-    def iterate(self, algo, n_iter: int = 1, graph: bool = False, ortho_modes: bool = False, **params) -> None:
+    def iterate(self, algo, n_iter: int = 1, graph: bool = False, ortho_modes: bool = False,
+                likelihood: str = "amplitude", **params) -> None:
         """Enqueue ``n_iter`` iterations of 'epie', 'dm' or 'lsqml' (asynchronous).
 
         graph=True replays captured iterations (PTY_ITER_GRAPH; DM and LSQML);
         ortho_modes=True orthogonalises the probe modes after every iteration
-        that updated the probe (PTY_ITER_ORTHO_MODES)."""
+        that updated the probe (PTY_ITER_ORTHO_MODES); likelihood='poisson'
+        takes LSQML's exit-wave update from the Poisson likelihood
+        (PTY_ITER_POISSON) instead of the modulus projection ('amplitude')."""
         a = ALGOS[algo] if isinstance(algo, str) else int(algo)
-        if graph:
-            params["flags"] = params.get("flags", 0) | L.ITER_GRAPH
-        if ortho_modes:
-            params["flags"] = params.get("flags", 0) | L.ITER_ORTHO_MODES
+        params["flags"] = _flags(params.get("flags", 0), graph, ortho_modes, likelihood)
         p = self.default_params(**params)
         self._check(self._lib.pty_iterate(self._live(), a, int(n_iter), C.byref(p)))
 
@@ -359,12 +366,10 @@ class Batch:
         if st != L.OK:
             raise PtyError(st, self._lib.pty_batch_last_error(self._b).decode())
 
-    def iterate(self, algo, n_iter: int = 1, graph: bool = False, ortho_modes: bool = False, **params) -> None:
+    def iterate(self, algo, n_iter: int = 1, graph: bool = False, ortho_modes: bool = False,
+                likelihood: str = "amplitude", **params) -> None:
         a = ALGOS[algo] if isinstance(algo, str) else int(algo)
-        if graph:
-            params["flags"] = params.get("flags", 0) | L.ITER_GRAPH
-        if ortho_modes:
-            params["flags"] = params.get("flags", 0) | L.ITER_ORTHO_MODES
+        params["flags"] = _flags(params.get("flags", 0), graph, ortho_modes, likelihood)
         p = Plan.default_params(**params)
         self._check(self._lib.pty_batch_iterate(self._b, a, int(n_iter), C.byref(p)))
 

@@ -37,6 +37,13 @@ def test_library_exports_every_declared_symbol():
     assert set(syms) == set(L.SIGNATURES), "binding and header disagree"
 
 
+def test_iteration_flags_match_the_header():
+    text = open(HEADER).read()
+    flags = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define PTY_ITER_(\w+) (\d+)u", text)}
+    assert flags == {"GRAPH": L.ITER_GRAPH, "ORTHO_MODES": L.ITER_ORTHO_MODES, "POISSON": L.ITER_POISSON}
+    assert len(set(flags.values())) == len(flags) and all(v & (v - 1) == 0 for v in flags.values())
+
+
 def test_default_params():
     p = L.IterParams()
     assert L.lib().pty_default_params(C.byref(p)) == L.OK
