@@ -14,8 +14,10 @@
 //
 // Convolutions with cin, cout multiples of 32 are implicit GEMMs on
 // v_mfma_f32_16x16x32_bf16 (pixels x output channels, reduction over
-// taps x input channels, float32 accumulation); the input gradient is the same
-// GEMM with transposed, spatially flipped weights; the weight gradient is an
+// taps x input channels, float32 accumulation); on 16-multiple images they
+// run from LDS-staged 18 x 18 halo tiles, on the 8 x 8 layers from per-tap
+// fetches; the input gradient is the same kernel with transposed, spatially
+// flipped weights; the weight gradient is an
 // MFMA GEMM over pixels with split-K partials summed in a fixed order.  The
 // 1-channel input layer and the 2-channel output layer use direct kernels.
 #include <hip/hip_runtime.h>
@@ -189,6 +191,137 @@ __global__ __launch_bounds__(256) void k_conv_gemm(View in, const bf16* __restri
     const int pl = e / (BN / 8), g = (e % (BN / 8)) * 8;
     const int m = m0 + pl;
     if (m >= mtot) continue;
+    *reinterpret_cast<bf16x8_t*>(out.at(m) + n0 + g) = *reinterpret_cast<const bf16x8_t*>(&so[pl * LDO + g]);
+  }
+}
+
+// Halo-tiled variant for S x S images, S a multiple of 16, BN = 32 or 64
+// output channels per block.  A block owns a 16 x 16 pixel tile of one image;
+// per 32-channel input block it stages the 18 x 18 halo tile and the 9 taps'
+// weights in LDS once (the next block's are fetched into registers
+// meanwhile) and runs the 9 taps from there, so every input value is fetched
+// once per channel block instead of once per tap (the GEMM above refetches
+// it for each tap from cache).  Wavefront w owns tile rows 4w .. 4w + 3:
+// 4 x BN/16 MFMA tiles, one tile row = 16 pixels.  Same lo / clo
+// upsampled-input split as the GEMM.
+template <int BN, bool RELU, bool BIAS>
+__global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restrict__ w,
+                                                   const float* __restrict__ bias, View out, int S, int cin,
+                                                   View lo, int clo) {
+  static_assert(BN == 32 || BN == 64, "32 or 64 output channels per block");
+  constexpr int TS = 16, HS = TS + 2, HP = HS * HS;   // 324 halo pixels
+  constexpr int LD = 40;                              // padded rows (80 bytes)
+  constexpr int AQ = (HP * 4 + 255) / 256;            // 16-byte halo pieces per thread
+  constexpr int BP = 9 * BN;                          // weight rows: tap * BN + output channel
+  constexpr int BQ = (BP * 4 + 255) / 256;            // 16-byte weight pieces per thread
+  constexpr int MT = 4, NT = BN / 16;
+  __shared__ __align__(16) bf16 smem[(HP + BP) * LD];
+  bf16* const sa = smem;                              // halo tile [pixel][channel]
+  bf16* const sb = smem + HP * LD;                    // weights [tap * BN + n][channel]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int row = lane & 15, grp = lane >> 4;
+  const int tiles = S / TS;
+  const int bt = blockIdx.x;
+  const int b = bt / (tiles * tiles), tyb = (bt / tiles) % tiles, txb = bt % tiles;
+  const int y0 = tyb * TS - 1, x0 = txb * TS - 1;     // halo origin in the image
+  const int n0 = blockIdx.y * BN;
+  const int cb = cin / 32;
+  const int ac = (tid & 3) * 8;                       // channel offset of this thread's pieces
+  const int Sl = S >> 1;
+  bf16x8_t ra[AQ], rb[BQ];
+  auto fetch = [&](int c0) {
+    const bool from_lo = c0 < clo;
+#pragma unroll
+    for (int q = 0; q < AQ; ++q) {
+      const int hp = (tid + 256 * q) >> 2;
+      const int yy = y0 + hp / HS, xx = x0 + hp % HS;
+      if (hp < HP && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
+        if (from_lo)
+          ra[q] = *reinterpret_cast<const bf16x8_t*>(lo.p + ((size_t)(b * Sl + (yy >> 1)) * Sl + (xx >> 1)) * lo.cs +
+                                                     lo.co + c0 + ac);
+        else
+          ra[q] = *reinterpret_cast<const bf16x8_t*>(in.p + ((size_t)(b * S + yy) * S + xx) * in.cs + in.co + c0 + ac);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ra[q][e] = static_cast<bf16>(0.0f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int e = (tid + 256 * q) >> 2;             // tap * BN + output channel
+      const int tap = e / BN, n = e % BN;
+      if (e < BP) rb[q] = *reinterpret_cast<const bf16x8_t*>(w + ((size_t)(n0 + n) * 9 + tap) * cin + c0 + ac);
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < AQ; ++q) {
+      const int hp = (tid + 256 * q) >> 2;
+      if (hp < HP) *reinterpret_cast<bf16x8_t*>(&sa[hp * LD + ac]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int e = (tid + 256 * q) >> 2;
+      if (e < BP) *reinterpret_cast<bf16x8_t*>(&sb[e * LD + ac]) = rb[q];
+    }
+  };
+  f32x4_t acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[i][t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int s = 0; s < cb; ++s) {
+    if (s + 1 < cb) fetch((s + 1) * 32);
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;
+      bf16x8_t a[MT], bw[NT];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+        a[i] = *reinterpret_cast<const bf16x8_t*>(&sa[((wv * 4 + i + dy) * HS + row + dx) * LD + grp * 8]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        bw[t] = *reinterpret_cast<const bf16x8_t*>(&sb[(tap * BN + t * 16 + row) * LD + grp * 8]);
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[t], acc[i][t], 0, 0, 0);
+    }
+    __syncthreads();
+    if (s + 1 < cb) {
+      stash();
+      __syncthreads();
+    }
+  }
+  // epilogue through LDS: D[i][j], i = 4 * (lane / 16) + r (pixel of tile row
+  // 4 wv + tile), j = lane % 16 (channel); every pixel's BN channels leave as
+  // 16-byte vectors
+  bf16* so = smem;
+  constexpr int LDO = BN + 8;
+  static_assert(TS * TS * LDO <= (HP + BP) * LD, "epilogue tile must fit");
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int nl = t * 16 + row;
+    const float bv = BIAS ? bias[n0 + nl] : 0.f;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[i][t][r] + bv;
+        if (RELU) v = fmaxf(v, 0.f);
+        so[((wv * 4 + i) * TS + grp * 4 + r) * LDO + nl] = tob(v);
+      }
+  }
+  __syncthreads();
+  constexpr int PV = BN / 8;                          // 16-byte vectors per pixel
+#pragma unroll
+  for (int q = 0; q < PV; ++q) {
+    const int e = tid + 256 * q;
+    const int pl = e / PV, g = (e % PV) * 8;
+    const size_t m = ((size_t)b * S + tyb * TS + pl / TS) * S + txb * TS + pl % TS;
     *reinterpret_cast<bf16x8_t*>(out.at(m) + n0 + g) = *reinterpret_cast<const bf16x8_t*>(&so[pl * LDO + g]);
   }
 }
@@ -767,7 +900,19 @@ void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out
   if (clo % 32 != 0 || clo > cin || (clo > 0 && (lo.p == nullptr || S % 2 != 0)))
     throw std::invalid_argument("conv: bad upsampled-input split");
   hipStream_t s = c->stream;
-  if (cout % 64 == 0) {
+  // 16 x 16 pixel halo tiles wherever the image holds whole tiles (the 8 x 8
+  // layers keep the GEMM)
+  if (S % 16 == 0 && cout % 64 == 0) {
+    dim3 grid(nb * (S / 16) * (S / 16), cout / 64);
+    if (relu) k_conv_halo<64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
+    else if (bias) k_conv_halo<64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
+    else k_conv_halo<64, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
+  } else if (S % 16 == 0 && cout == 32) {
+    dim3 grid(nb * (S / 16) * (S / 16), 1);
+    if (relu) k_conv_halo<32, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
+    else if (bias) k_conv_halo<32, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
+    else k_conv_halo<32, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
+  } else if (cout % 64 == 0) {
     dim3 grid(blocks(mtot, 128), cout / 64);
     if (relu) k_conv_gemm<128, 64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
     else if (bias) k_conv_gemm<128, 64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
