@@ -203,11 +203,13 @@ __global__ __launch_bounds__(256) void k_conv_gemm(View in, const bf16* __restri
 // once per channel block instead of once per tap (the GEMM above refetches
 // it for each tap from cache).  Wavefront w owns tile rows 4w .. 4w + 3:
 // 4 x BN/16 MFMA tiles, one tile row = 16 pixels.  Same lo / clo
-// upsampled-input split as the GEMM.
+// upsampled-input split as the GEMM.  With pool.p set, the block also writes
+// the 2 x 2 average pool of its (bf16) output tile (the four values summed
+// row by row, then scaled by 1/4), so the encoder needs no pooling pass.
 template <int BN, bool RELU, bool BIAS>
 __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restrict__ w,
                                                    const float* __restrict__ bias, View out, int S, int cin,
-                                                   View lo, int clo) {
+                                                   View lo, int clo, View pool) {
   static_assert(BN == 32 || BN == 64, "32 or 64 output channels per block");
   constexpr int TS = 16, HS = TS + 2, HP = HS * HS;   // 324 halo pixels
   constexpr int LD = 40;                              // padded rows (80 bytes)
@@ -323,6 +325,29 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
     const int pl = e / PV, g = (e % PV) * 8;
     const size_t m = ((size_t)b * S + tyb * TS + pl / TS) * S + txb * TS + pl % TS;
     *reinterpret_cast<bf16x8_t*>(out.at(m) + n0 + g) = *reinterpret_cast<const bf16x8_t*>(&so[pl * LDO + g]);
+  }
+  if (pool.p) {
+    constexpr int PT = TS / 2;                        // pooled tile side
+    const int Sp = S / 2;
+#pragma unroll
+    for (int q = 0; q < PT * PT * PV / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int pl = e / PV, g = (e % PV) * 8;
+      const int py = pl / PT, px = pl % PT;
+      float acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0}, v[8];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bf16x8_t x8 = *reinterpret_cast<const bf16x8_t*>(&so[((2 * py + k / 2) * TS + 2 * px + k % 2) * LDO + g]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = static_cast<float>(x8[i]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc8[i] += v[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc8[i] *= 0.25f;
+      const size_t mp = ((size_t)b * Sp + tyb * PT + py) * Sp + txb * PT + px;
+      st8(pool.at(mp) + n0 + g, acc8);
+    }
   }
 }
 
@@ -656,28 +681,9 @@ __global__ __launch_bounds__(256) void k_wgrad_out(View in, const float* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Pooling, upsampling, ReLU masks (8 channels per thread), loss, Adam
+// Pooling gradients, upsampling, ReLU masks (8 channels per thread), loss, Adam
+// (the forward pooling is fused into the convolutions that produce e1 - e3)
 // ---------------------------------------------------------------------------
-// out (S/2) = mean of 2x2 of in (S)
-__global__ void k_pool(View in, View out, int nb, int S, int c) {
-  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int so = S / 2, c8 = c / 8;
-  if (i >= (size_t)nb * so * so * c8) return;
-  const int g = (int)(i % c8) * 8;
-  const size_t m = i / c8;
-  const int b = (int)(m / (so * so)), y = (int)(m / so) % so, x = (int)(m % so);
-  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0}, v[8];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    ld8(in.at(((size_t)b * S + 2 * y + k / 2) * S + 2 * x + k % 2) + g, v);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) s[e] += v[e];
-  }
-#pragma unroll
-  for (int e = 0; e < 8; ++e) s[e] *= 0.25f;
-  st8(out.at(m) + g, s);
-}
-
 // dx (S) += dy (S/2) / 4 broadcast, then dx *= (act > 0): the skip gradient
 // of an encoder layer plus its pooled path, through its ReLU
 __global__ void k_pool_back_relu(View dy, View dx, View act, int nb, int S, int c) {
@@ -894,24 +900,26 @@ View V(bf16* p, int cs, int co = 0) { return View{p, cs, co}; }
 // lo / clo: the first clo input channels read from the half-resolution
 // tensor lo (a fused nearest 2x upsampling); clo = 0: all from `in`.
 void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out, int nb, int S, int cin, int cout,
-                 bool relu, View lo = View{nullptr, 0, 0}, int clo = 0) {
+                 bool relu, View lo = View{nullptr, 0, 0}, int clo = 0, View pool = View{nullptr, 0, 0}) {
   const int mtot = nb * S * S;
   if (cin % 32 != 0 || cout % 32 != 0) throw std::invalid_argument("conv channels must be multiples of 32");
   if (clo % 32 != 0 || clo > cin || (clo > 0 && (lo.p == nullptr || S % 2 != 0)))
     throw std::invalid_argument("conv: bad upsampled-input split");
+  const bool halo = S % 16 == 0 && (cout == 32 || cout % 64 == 0);
+  if (pool.p && !halo) throw std::invalid_argument("conv: a fused pool needs the halo-tiled kernel");
   hipStream_t s = c->stream;
   // 16 x 16 pixel halo tiles wherever the image holds whole tiles (the 8 x 8
   // layers keep the GEMM)
-  if (S % 16 == 0 && cout % 64 == 0) {
+  if (halo && cout % 64 == 0) {
     dim3 grid(nb * (S / 16) * (S / 16), cout / 64);
-    if (relu) k_conv_halo<64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
-    else if (bias) k_conv_halo<64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
-    else k_conv_halo<64, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
-  } else if (S % 16 == 0 && cout == 32) {
+    if (relu) k_conv_halo<64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
+    else if (bias) k_conv_halo<64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
+    else k_conv_halo<64, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
+  } else if (halo) {
     dim3 grid(nb * (S / 16) * (S / 16), 1);
-    if (relu) k_conv_halo<32, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
-    else if (bias) k_conv_halo<32, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
-    else k_conv_halo<32, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo);
+    if (relu) k_conv_halo<32, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
+    else if (bias) k_conv_halo<32, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
+    else k_conv_halo<32, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
   } else if (cout % 64 == 0) {
     dim3 grid(blocks(mtot, 128), cout / 64);
     if (relu) k_conv_gemm<128, 64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, nb, S, cin, cout, lo, clo);
@@ -965,12 +973,13 @@ void forward(pty_cnn* c, const float* x, int nb, bool train) {
   else
     k_conv_in_pool<false><<<gb, 256, 0, s>>>(x, w + L[0].woff, c->p + L[0].boff, V(c->a0, 32), V(c->p0, 32), nb);
   PTY_LAUNCH_CHECK("conv_in_pool");
-  launch_conv(c, V(c->p0, 32), w + L[1].woff, c->p + L[1].boff, V(c->cat8, 96, 64), nb, 64, 32, 32, true);  // e1
-  k_pool<<<blocks((size_t)nb * 32 * 32 * 4), 256, 0, s>>>(V(c->cat8, 96, 64), V(c->p1, 32), nb, 64, 32);
-  launch_conv(c, V(c->p1, 32), w + L[2].woff, c->p + L[2].boff, V(c->cat7, 192, 128), nb, 32, 32, 64, true);  // e2
-  k_pool<<<blocks((size_t)nb * 16 * 16 * 8), 256, 0, s>>>(V(c->cat7, 192, 128), V(c->p2, 64), nb, 32, 64);
-  launch_conv(c, V(c->p2, 64), w + L[3].woff, c->p + L[3].boff, V(c->cat6, 384, 256), nb, 16, 64, 128, true);  // e3
-  k_pool<<<blocks((size_t)nb * 8 * 8 * 16), 256, 0, s>>>(V(c->cat6, 384, 256), V(c->p3, 128), nb, 16, 128);
+  // e1, e2, e3 with their 2 x 2 pools written by the same kernels
+  launch_conv(c, V(c->p0, 32), w + L[1].woff, c->p + L[1].boff, V(c->cat8, 96, 64), nb, 64, 32, 32, true, View{}, 0,
+              V(c->p1, 32));
+  launch_conv(c, V(c->p1, 32), w + L[2].woff, c->p + L[2].boff, V(c->cat7, 192, 128), nb, 32, 32, 64, true, View{}, 0,
+              V(c->p2, 64));
+  launch_conv(c, V(c->p2, 64), w + L[3].woff, c->p + L[3].boff, V(c->cat6, 384, 256), nb, 16, 64, 128, true, View{},
+              0, V(c->p3, 128));
   launch_conv(c, V(c->p3, 128), w + L[4].woff, c->p + L[4].boff, V(c->a4, 256), nb, 8, 128, 256, true);
   launch_conv(c, V(c->a4, 256), w + L[5].woff, c->p + L[5].boff, V(c->a5, 256), nb, 8, 256, 256, true);
   if (train) {
