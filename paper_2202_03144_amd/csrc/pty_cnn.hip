@@ -19,7 +19,8 @@
 // fetches; the input gradient is the same kernel with transposed, spatially
 // flipped weights; the weight gradient is an
 // MFMA GEMM over pixels with split-K partials summed in a fixed order.  The
-// 1-channel input layer and the 2-channel output layer use direct kernels.
+// 2-channel output layer runs on the halo kernel over weights zero-padded to
+// 16 channels; the 1-channel input layer is a direct kernel.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -206,11 +207,15 @@ __global__ __launch_bounds__(256) void k_conv_gemm(View in, const bf16* __restri
 // upsampled-input split as the GEMM.  With pool.p set, the block also writes
 // the 2 x 2 average pool of its (bf16) output tile (the four values summed
 // row by row, then scaled by 1/4), so the encoder needs no pooling pass.
-template <int BN, bool RELU, bool BIAS>
+// OUT2 (the 2-channel output layer, BN = 16 over weights zero-padded to 16
+// output channels): channels 0 and 1 plus bias are written as float32 pairs
+// to y instead.
+template <int BN, bool RELU, bool BIAS, bool OUT2 = false>
 __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restrict__ w,
                                                    const float* __restrict__ bias, View out, int S, int cin,
-                                                   View lo, int clo, View pool) {
-  static_assert(BN == 32 || BN == 64, "32 or 64 output channels per block");
+                                                   View lo, int clo, View pool, float* __restrict__ y = nullptr) {
+  static_assert(BN == 16 || BN == 32 || BN == 64, "16, 32 or 64 output channels per block");
+  static_assert(!OUT2 || (BN == 16 && BIAS && !RELU), "the output layer: 16 padded channels, bias, linear");
   constexpr int TS = 16, HS = TS + 2, HP = HS * HS;   // 324 halo pixels
   constexpr int LD = 40;                              // padded rows (80 bytes)
   constexpr int AQ = (HP * 4 + 255) / 256;            // 16-byte halo pieces per thread
@@ -297,6 +302,21 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
       stash();
       __syncthreads();
     }
+  }
+  if constexpr (OUT2) {
+    // D[i][j] as below; lanes j < 2 hold the two real channels
+    float* sf = reinterpret_cast<float*>(smem);       // [pixel][2]
+    if (row < 2) {
+      const float bv = bias[row];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sf[((wv * 4 + i) * TS + grp * 4 + r) * 2 + row] = acc[i][0][r] + bv;
+    }
+    __syncthreads();
+    const size_t m = ((size_t)b * S + tyb * TS + tid / TS) * S + txb * TS + tid % TS;
+    reinterpret_cast<float2*>(y)[m] = make_float2(sf[tid * 2], sf[tid * 2 + 1]);
+    return;
   }
   // epilogue through LDS: D[i][j], i = 4 * (lane / 16) + r (pixel of tile row
   // 4 wv + tile), j = lane % 16 (channel); every pixel's BN channels leave as
@@ -497,34 +517,10 @@ __global__ __launch_bounds__(256) void k_conv_in_pool(const float* __restrict__ 
   }
 }
 
-// L9: y[m][n] = bias[n] + sum_{tap, c} in[m + tap][c] w[n][tap][c], float32, n < 2
-__global__ __launch_bounds__(256) void k_conv_out(View in, const bf16* __restrict__ w, const float* __restrict__ bias,
-                                                  float* __restrict__ y, int nb) {
-  constexpr int S = 64, C = 32;
-  __shared__ float ws[2 * 9 * C];
-  for (int i = threadIdx.x; i < 2 * 9 * C; i += 256) ws[i] = tof(w[i]);
-  __syncthreads();
-  const size_t m = blockIdx.x * (size_t)256 + threadIdx.x;
-  if (m >= (size_t)nb * S * S) return;
-  const int b = (int)(m / (S * S)), y0 = (int)(m / S) % S, x0 = (int)(m % S);
-  float s0 = bias[0], s1 = bias[1];
-  for (int tap = 0; tap < 9; ++tap) {
-    const int yy = y0 + tap / 3 - 1, xx = x0 + tap % 3 - 1;
-    if ((unsigned)yy >= (unsigned)S || (unsigned)xx >= (unsigned)S) continue;
-    const bf16* ip = in.at(((size_t)b * S + yy) * S + xx);
-#pragma unroll
-    for (int g = 0; g < C; g += 8) {
-      float a[8];
-      ld8(ip + g, a);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        s0 += a[k] * ws[tap * C + g + k];
-        s1 += a[k] * ws[(9 + tap) * C + g + k];
-      }
-    }
-  }
-  y[m * 2] = s0;
-  y[m * 2 + 1] = s1;
+// L9's weights zero-padded to 16 output channels for the MFMA output layer
+__global__ void k_pad_out_w(const bf16* __restrict__ w, bf16* __restrict__ wp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 16 * 9 * 32) wp[i] = i < 2 * 9 * 32 ? w[i] : static_cast<bf16>(0.0f);
 }
 
 // L9 input gradient with L8's ReLU: dz8[m][c] = (a8[m][c] > 0) *
@@ -844,6 +840,7 @@ struct pty_cnn {
   float* m2 = nullptr;
   bf16* wb = nullptr;    // bf16 copy of the whole vector (weights used from it)
   bf16* wt = nullptr;    // transposed-flipped weights scratch
+  bf16* w9p = nullptr;   // L9 weights zero-padded to 16 output channels
   float* part = nullptr; size_t part_n = 0;
   double* lpart = nullptr; double* lsum = nullptr;
   int64_t step = 0;
@@ -1000,7 +997,10 @@ void forward(pty_cnn* c, const float* x, int nb, bool train) {
     launch_conv(c, V(c->cat8, 96), w + L[8].woff, c->p + L[8].boff, V(c->a8, 32), nb, 64, 96, 32, true,
                 V(c->a7, 64), 64);
   }
-  k_conv_out<<<blocks((size_t)nb * 64 * 64), 256, 0, s>>>(V(c->a8, 32), w + L[9].woff, c->p + L[9].boff, c->y, nb);
+  // L9 on MFMA over the zero-padded weights
+  k_pad_out_w<<<blocks(16 * 9 * 32), 256, 0, s>>>(w + L[9].woff, c->w9p);
+  k_conv_halo<16, false, true, true><<<nb * 16, 256, 0, s>>>(V(c->a8, 32), c->w9p, c->p + L[9].boff, View{}, 64, 32,
+                                                             View{}, 0, View{}, c->y);
   PTY_LAUNCH_CHECK("cnn_forward");
 }
 
@@ -1151,6 +1151,7 @@ pty_status pty_cnn_create(int32_t device, void* stream, int32_t max_batch, uint6
     c->m2 = c->alloc<float>(off);
     c->wb = c->alloc<bf16>(off);
     c->wt = c->alloc<bf16>((size_t)384 * 9 * 256);
+    c->w9p = c->alloc<bf16>((size_t)16 * 9 * 32);
     // He-normal initialisation (std sqrt(2 / (9 cin))), zero biases
     std::vector<float> hp(off, 0.f);
     std::mt19937_64 rng(seed);
