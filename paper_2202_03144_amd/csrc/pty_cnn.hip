@@ -14,10 +14,10 @@
 //
 // Convolutions with cin, cout multiples of 32 are implicit GEMMs on
 // v_mfma_f32_16x16x32_bf16 (pixels x output channels, reduction over
-// taps x input channels, float32 accumulation); on 16-multiple images they
-// run from LDS-staged 18 x 18 halo tiles, on the 8 x 8 layers from per-tap
-// fetches; the input gradient is the same kernel with transposed, spatially
-// flipped weights; the weight gradient is an
+// taps x input channels, float32 accumulation) that run from LDS-staged halo
+// tiles (18 x 18 on 16-multiple images, four 10 x 10 ones for 8 x 8 images);
+// the input gradient is the same kernel with transposed, spatially flipped
+// weights; the weight gradient is an
 // MFMA GEMM over pixels with split-K partials summed in a fixed order.  The
 // 2-channel output layer runs on the halo kernel over weights zero-padded to
 // 16 channels; the 1-channel input layer is a direct kernel.
@@ -209,14 +209,19 @@ __global__ __launch_bounds__(256) void k_conv_gemm(View in, const bf16* __restri
 // row by row, then scaled by 1/4), so the encoder needs no pooling pass.
 // OUT2 (the 2-channel output layer, BN = 16 over weights zero-padded to 16
 // output channels): channels 0 and 1 plus bias are written as float32 pairs
-// to y instead.
-template <int BN, bool RELU, bool BIAS, bool OUT2 = false>
+// to y instead.  Q8 (8 x 8 images): the block's 16 x 16 tile holds four
+// images as quadrants, image 4 blockIdx.x + q in quadrant q (row-major), each
+// with its own zero-padded 10 x 10 halo in a 20 x 20 staging tile; images
+// past nb are zero and not written.
+template <int BN, bool RELU, bool BIAS, bool OUT2 = false, bool Q8 = false>
 __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restrict__ w,
                                                    const float* __restrict__ bias, View out, int S, int cin,
-                                                   View lo, int clo, View pool, float* __restrict__ y = nullptr) {
+                                                   View lo, int clo, View pool, float* __restrict__ y = nullptr,
+                                                   int nb = 0) {
   static_assert(BN == 16 || BN == 32 || BN == 64, "16, 32 or 64 output channels per block");
   static_assert(!OUT2 || (BN == 16 && BIAS && !RELU), "the output layer: 16 padded channels, bias, linear");
-  constexpr int TS = 16, HS = TS + 2, HP = HS * HS;   // 324 halo pixels
+  static_assert(!(Q8 && OUT2), "8 x 8 quadrants are for the hidden layers");
+  constexpr int TS = 16, HS = Q8 ? 20 : TS + 2, HP = HS * HS;   // 400 or 324 staged pixels
   constexpr int LD = 40;                              // padded rows (80 bytes)
   constexpr int AQ = (HP * 4 + 255) / 256;            // 16-byte halo pieces per thread
   constexpr int BP = 9 * BN;                          // weight rows: tap * BN + output channel
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
   bf16* const sb = smem + HP * LD;                    // weights [tap * BN + n][channel]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row = lane & 15, grp = lane >> 4;
-  const int tiles = S / TS;
+  const int tiles = Q8 ? 1 : S / TS;                  // Q8: one tile of four images
   const int bt = blockIdx.x;
   const int b = bt / (tiles * tiles), tyb = (bt / tiles) % tiles, txb = bt % tiles;
   const int y0 = tyb * TS - 1, x0 = txb * TS - 1;     // halo origin in the image
@@ -241,6 +246,18 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
 #pragma unroll
     for (int q = 0; q < AQ; ++q) {
       const int hp = (tid + 256 * q) >> 2;
+      if constexpr (Q8) {
+        // staged pixel (hy, hx) -> quadrant image, pixel (hy % 10 - 1, hx % 10 - 1)
+        const int hy = hp / HS, hx = hp % HS;
+        const int bq = 4 * bt + (hy / 10) * 2 + hx / 10, ly = hy % 10 - 1, lx = hx % 10 - 1;
+        if (hp < HP && bq < nb && (unsigned)ly < 8u && (unsigned)lx < 8u) {
+          ra[q] = *reinterpret_cast<const bf16x8_t*>(in.p + ((size_t)(bq * 8 + ly) * 8 + lx) * in.cs + in.co + c0 + ac);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) ra[q][e] = static_cast<bf16>(0.0f);
+        }
+        continue;
+      }
       const int yy = y0 + hp / HS, xx = x0 + hp % HS;
       if (hp < HP && (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
         if (from_lo)
@@ -287,8 +304,13 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
       const int dy = tap / 3, dx = tap % 3;
       bf16x8_t a[MT], bw[NT];
 #pragma unroll
-      for (int i = 0; i < MT; ++i)
-        a[i] = *reinterpret_cast<const bf16x8_t*>(&sa[((wv * 4 + i + dy) * HS + row + dx) * LD + grp * 8]);
+      for (int i = 0; i < MT; ++i) {
+        // tile pixel (Y, X) = (4 wv + i, row); Q8: quadrant halo coordinates
+        const int Y = wv * 4 + i, X = row;
+        const int hy = Q8 ? 10 * (Y >> 3) + (Y & 7) + dy : Y + dy;
+        const int hx = Q8 ? 10 * (X >> 3) + (X & 7) + dx : X + dx;
+        a[i] = *reinterpret_cast<const bf16x8_t*>(&sa[(hy * HS + hx) * LD + grp * 8]);
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         bw[t] = *reinterpret_cast<const bf16x8_t*>(&sb[(tap * BN + t * 16 + row) * LD + grp * 8]);
@@ -343,10 +365,17 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
   for (int q = 0; q < PV; ++q) {
     const int e = tid + 256 * q;
     const int pl = e / PV, g = (e % PV) * 8;
-    const size_t m = ((size_t)b * S + tyb * TS + pl / TS) * S + txb * TS + pl % TS;
+    size_t m;
+    if constexpr (Q8) {
+      const int Y = pl / TS, X = pl % TS, bq = 4 * bt + (Y >> 3) * 2 + (X >> 3);
+      if (bq >= nb) continue;
+      m = ((size_t)bq * 8 + (Y & 7)) * 8 + (X & 7);
+    } else {
+      m = ((size_t)b * S + tyb * TS + pl / TS) * S + txb * TS + pl % TS;
+    }
     *reinterpret_cast<bf16x8_t*>(out.at(m) + n0 + g) = *reinterpret_cast<const bf16x8_t*>(&so[pl * LDO + g]);
   }
-  if (pool.p) {
+  if (!Q8 && pool.p) {
     constexpr int PT = TS / 2;                        // pooled tile side
     const int Sp = S / 2;
 #pragma unroll
@@ -905,9 +934,18 @@ void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out
   const bool halo = S % 16 == 0 && (cout == 32 || cout % 64 == 0);
   if (pool.p && !halo) throw std::invalid_argument("conv: a fused pool needs the halo-tiled kernel");
   hipStream_t s = c->stream;
-  // 16 x 16 pixel halo tiles wherever the image holds whole tiles (the 8 x 8
-  // layers keep the GEMM)
-  if (halo && cout % 64 == 0) {
+  // 16 x 16 pixel halo tiles wherever the image holds whole tiles; 8 x 8
+  // images four to a tile
+  if (S == 8 && cout % 64 == 0 && clo == 0 && !pool.p) {
+    dim3 grid((nb + 3) / 4, cout / 64);
+    if (relu)
+      k_conv_halo<64, true, true, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, 0, View{}, nullptr, nb);
+    else if (bias)
+      k_conv_halo<64, false, true, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, 0, View{}, nullptr, nb);
+    else
+      k_conv_halo<64, false, false, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, 0, View{}, nullptr,
+                                                                      nb);
+  } else if (halo && cout % 64 == 0) {
     dim3 grid(nb * (S / 16) * (S / 16), cout / 64);
     if (relu) k_conv_halo<64, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
     else if (bias) k_conv_halo<64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
