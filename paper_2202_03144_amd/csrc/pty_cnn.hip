@@ -467,12 +467,24 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __r
   if (do_bias && threadIdx.x < 32) bpart[(size_t)split * cout + n0 + threadIdx.x] = bacc;
 }
 
-// dst[i] = sum over s of part[s * n + i], in order
+// dst[i] = sum over s of part[s * n + i], in order.  Sixteen partials are
+// loaded before they are added (same order), so a thread has sixteen loads in
+// flight instead of one: the big layers have few outputs (36 blocks at L1)
+// and up to 256 splits.
 __global__ void k_sum_splits(const float* __restrict__ part, int splits, size_t n, float* __restrict__ dst) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  constexpr int U = 16;
   float s = 0.f;
-  for (int k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
+  int k = 0;
+  for (; k + U <= splits; k += U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = part[(size_t)(k + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  for (; k < splits; ++k) s += part[(size_t)k * n + i];
   dst[i] = s;
 }
 
