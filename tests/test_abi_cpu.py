@@ -44,6 +44,15 @@ def test_iteration_flags_match_the_header():
     assert len(set(flags.values())) == len(flags) and all(v & (v - 1) == 0 for v in flags.values())
 
 
+def test_iterate_options_map_to_flags():
+    from paper_2202_03144_amd.plan import _flags
+    assert _flags(0, False, False, "amplitude") == 0
+    assert _flags(0, True, True, "poisson") == L.ITER_GRAPH | L.ITER_ORTHO_MODES | L.ITER_POISSON
+    assert _flags(L.ITER_GRAPH, False, False, "poisson") == L.ITER_GRAPH | L.ITER_POISSON
+    with pytest.raises(ValueError):
+        _flags(0, False, False, "gaussian")
+
+
 def test_default_params():
     p = L.IterParams()
     assert L.lib().pty_default_params(C.byref(p)) == L.OK
