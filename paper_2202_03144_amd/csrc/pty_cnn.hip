@@ -943,7 +943,7 @@ void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out
   if (cin % 32 != 0 || cout % 32 != 0) throw std::invalid_argument("conv channels must be multiples of 32");
   if (clo % 32 != 0 || clo > cin || (clo > 0 && (lo.p == nullptr || S % 2 != 0)))
     throw std::invalid_argument("conv: bad upsampled-input split");
-  const bool halo = S % 16 == 0 && (cout == 32 || cout % 64 == 0);
+  const bool halo = S % 16 == 0 && cout % 32 == 0;
   if (pool.p && !halo) throw std::invalid_argument("conv: a fused pool needs the halo-tiled kernel");
   hipStream_t s = c->stream;
   // 16 x 16 pixel halo tiles wherever the image holds whole tiles; 8 x 8
@@ -963,7 +963,7 @@ void launch_conv(pty_cnn* c, View in, const bf16* w, const float* bias, View out
     else if (bias) k_conv_halo<64, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
     else k_conv_halo<64, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
   } else if (halo) {
-    dim3 grid(nb * (S / 16) * (S / 16), 1);
+    dim3 grid(nb * (S / 16) * (S / 16), cout / 32);
     if (relu) k_conv_halo<32, true, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
     else if (bias) k_conv_halo<32, false, true><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
     else k_conv_halo<32, false, false><<<grid, 256, 0, s>>>(in, w, bias, out, S, cin, lo, clo, pool);
