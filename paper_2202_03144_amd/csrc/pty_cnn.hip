@@ -404,13 +404,17 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
 // m of dz[m][n] * in[m + tap][c]; the centre-tap blocks of the first channel
 // block also sum dz over the split into bpart[split][n] (the bias gradient).
 // Block = 4 wavefronts on a 32 x 32 (n, c) tile of one tap; each wavefront
-// owns a 16 x 16 quarter.  Pixel chunks of 32 are staged through LDS
-// transposed so that every fragment is 16 contiguous bytes.
+// owns a 16 x 16 quarter.  Pixel steps of 128 are staged through LDS
+// transposed so that every fragment is 16 contiguous bytes; each wavefront
+// then runs four MFMAs, one per 32-pixel chunk in pixel order.
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4_t;
+
 __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __restrict__ part,
                                                     float* __restrict__ bpart, int nb, int S, int cin, int cout,
                                                     int px_per_split) {
-  __shared__ __align__(16) bf16 sd[32][40];  // [n][pixel], 80-byte rows
-  __shared__ __align__(16) bf16 sx[32][40];  // [c][pixel]
+  constexpr int PS = 128, LDP = PS + 8;      // pixels per step, padded row
+  __shared__ __align__(16) bf16 sd[32][LDP];  // [n][pixel]
+  __shared__ __align__(16) bf16 sx[32][LDP];  // [c][pixel]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int cblk = blockIdx.y % (cin / 32), tap = blockIdx.y / (cin / 32);
   const int n0 = blockIdx.x * 32, c0 = cblk * 32;
@@ -423,40 +427,44 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __r
   const bool do_bias = tap == 4 && cblk == 0;
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
   float bacc = 0.f;
+  // loader role: pixels lp + 32 q of the step, channels lc .. lc + 3
   const int lp = threadIdx.x >> 3, lc = (threadIdx.x & 7) * 4;
-  for (int m = mb; m < me; m += 32) {
-    const int pm = m + lp;
-    bf16 vd[4], vx[4];
+  bf16x4_t zero4;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      vd[i] = tob(0.f);
-      vx[i] = tob(0.f);
-    }
-    if (pm < me) {
-      const int b = pm / (S * S), y = (pm / S) % S, x = pm % S;
-      const bf16* dp = dz.at(pm) + n0 + lc;
+  for (int i = 0; i < 4; ++i) zero4[i] = tob(0.f);
+  for (int m = mb; m < me; m += PS) {
+    bf16x4_t vd[PS / 32], vx[PS / 32];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) vd[i] = dp[i];
-      const int yy = y + dy, xx = x + dx;
-      if ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) {
-        const bf16* xp = in.at((size_t)(b * S + yy) * S + xx) + c0 + lc;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) vx[i] = xp[i];
+    for (int q = 0; q < PS / 32; ++q) {
+      vd[q] = zero4;
+      vx[q] = zero4;
+      const int pm = m + lp + 32 * q;
+      if (pm < me) {
+        const int b = pm / (S * S), y = (pm / S) % S, x = pm % S;
+        vd[q] = *reinterpret_cast<const bf16x4_t*>(dz.at(pm) + n0 + lc);
+        const int yy = y + dy, xx = x + dx;
+        if ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S)
+          vx[q] = *reinterpret_cast<const bf16x4_t*>(in.at((size_t)(b * S + yy) * S + xx) + c0 + lc);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      sd[lc + i][lp] = vd[i];
-      sx[lc + i][lp] = vx[i];
-    }
+    for (int q = 0; q < PS / 32; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        sd[lc + i][lp + 32 * q] = vd[q][i];
+        sx[lc + i][lp + 32 * q] = vx[q][i];
+      }
     __syncthreads();
-    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sd[wi + row][grp * 8]);
-    const bf16x8_t bb = *reinterpret_cast<const bf16x8_t*>(&sx[wj + row][grp * 8]);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+#pragma unroll
+    for (int kc = 0; kc < PS / 32; ++kc) {
+      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sd[wi + row][kc * 32 + grp * 8]);
+      const bf16x8_t bb = *reinterpret_cast<const bf16x8_t*>(&sx[wj + row][kc * 32 + grp * 8]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+    }
     if (do_bias && threadIdx.x < 32) {
 #pragma unroll 8
-      for (int q = 0; q < 32; ++q) bacc += tof(sd[threadIdx.x][q]);
+      for (int q = 0; q < PS; ++q) bacc += tof(sd[threadIdx.x][q]);
     }
   }
 #pragma unroll
