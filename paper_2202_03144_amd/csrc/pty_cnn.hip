@@ -425,6 +425,7 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __r
   const int wi = (wv >> 1) * 16, wj = (wv & 1) * 16;
   const int row = lane & 15, grp = lane >> 4;
   const bool do_bias = tap == 4 && cblk == 0;
+  const int lgS = 31 - __builtin_clz(S);
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
   float bacc = 0.f;
   // loader role: pixels lp + 32 q of the step, channels lc .. lc + 3
@@ -440,7 +441,8 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __r
       vx[q] = zero4;
       const int pm = m + lp + 32 * q;
       if (pm < me) {
-        const int b = pm / (S * S), y = (pm / S) % S, x = pm % S;
+        // S is a power of two (64, 32, 16, 8): shifts and masks, no divisions
+        const int b = pm >> (2 * lgS), y = (pm >> lgS) & (S - 1), x = pm & (S - 1);
         vd[q] = *reinterpret_cast<const bf16x4_t*>(dz.at(pm) + n0 + lc);
         const int yy = y + dy, xx = x + dx;
         if ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S)
@@ -1009,6 +1011,7 @@ void launch_wgrad(pty_cnn* c, int li, View dz, View in, int nb) {
   const size_t nw = (size_t)l.cout * 9 * l.cin;
   if ((size_t)splits * (nw + l.cout) > c->part_n) throw std::invalid_argument("wgrad scratch too small");
   float* bpart = c->part + (size_t)splits * nw;
+  if ((l.S & (l.S - 1)) != 0) throw std::invalid_argument("wgrad: image side must be a power of two");
   dim3 grid(l.cout / 32, 9 * (l.cin / 32), splits);
   k_wgrad_mfma<<<grid, 256, 0, c->stream>>>(dz, in, c->part, bpart, nb, l.S, l.cin, l.cout, kWgradPx);
   PTY_LAUNCH_CHECK("wgrad_mfma");
