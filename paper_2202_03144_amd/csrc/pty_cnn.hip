@@ -408,6 +408,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(View in, const bf16* __restri
 // transposed so that every fragment is 16 contiguous bytes; each wavefront
 // then runs four MFMAs, one per 32-pixel chunk in pixel order.
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4_t;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 
 __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __restrict__ part,
                                                     float* __restrict__ bpart, int nb, int S, int cin, int cout,
@@ -428,34 +429,40 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(View dz, View in, float* __r
   const int lgS = 31 - __builtin_clz(S);
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
   float bacc = 0.f;
-  // loader role: pixels lp + 32 q of the step, channels lc .. lc + 3
-  const int lp = threadIdx.x >> 3, lc = (threadIdx.x & 7) * 4;
+  // loader role: the pixel pairs lp, lp + 1 (+ 64 q) of the step, channels
+  // lc .. lc + 3; a pair's values of one channel leave as one 4-byte store
+  const int lp = (threadIdx.x >> 3) * 2, lc = (threadIdx.x & 7) * 4;
   bf16x4_t zero4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) zero4[i] = tob(0.f);
   for (int m = mb; m < me; m += PS) {
-    bf16x4_t vd[PS / 32], vx[PS / 32];
+    bf16x4_t vd[PS / 32], vx[PS / 32];   // [2 q + e]: pixel lp + e + 64 q
 #pragma unroll
-    for (int q = 0; q < PS / 32; ++q) {
-      vd[q] = zero4;
-      vx[q] = zero4;
-      const int pm = m + lp + 32 * q;
+    for (int h = 0; h < PS / 32; ++h) {
+      vd[h] = zero4;
+      vx[h] = zero4;
+      const int pm = m + lp + (h & 1) + 64 * (h >> 1);
       if (pm < me) {
         // S is a power of two (64, 32, 16, 8): shifts and masks, no divisions
         const int b = pm >> (2 * lgS), y = (pm >> lgS) & (S - 1), x = pm & (S - 1);
-        vd[q] = *reinterpret_cast<const bf16x4_t*>(dz.at(pm) + n0 + lc);
+        vd[h] = *reinterpret_cast<const bf16x4_t*>(dz.at(pm) + n0 + lc);
         const int yy = y + dy, xx = x + dx;
         if ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S)
-          vx[q] = *reinterpret_cast<const bf16x4_t*>(in.at((size_t)(b * S + yy) * S + xx) + c0 + lc);
+          vx[h] = *reinterpret_cast<const bf16x4_t*>(in.at((size_t)(b * S + yy) * S + xx) + c0 + lc);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PS / 32; ++q)
+    for (int q = 0; q < PS / 64; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        sd[lc + i][lp + 32 * q] = vd[q][i];
-        sx[lc + i][lp + 32 * q] = vx[q][i];
+        bf16x2_t pd, px;
+        pd[0] = vd[2 * q][i];
+        pd[1] = vd[2 * q + 1][i];
+        px[0] = vx[2 * q][i];
+        px[1] = vx[2 * q + 1][i];
+        *reinterpret_cast<bf16x2_t*>(&sd[lc + i][lp + 64 * q]) = pd;
+        *reinterpret_cast<bf16x2_t*>(&sx[lc + i][lp + 64 * q]) = px;
       }
     __syncthreads();
 #pragma unroll
