@@ -736,7 +736,8 @@ __global__ __launch_bounds__(256) void k_wgrad_out(View in, const float* __restr
 
 // ---------------------------------------------------------------------------
 // Pooling gradients, upsampling, ReLU masks (8 channels per thread), loss, Adam
-// (the forward pooling is fused into the convolutions that produce e1 - e3)
+// (the forward pooling is fused into the convolutions that produce e1 - e3).
+// Image sides and channel counts here are powers of two: indices by shifts.
 // ---------------------------------------------------------------------------
 // dx (S) += dy (S/2) / 4 broadcast, then dx *= (act > 0): the skip gradient
 // of an encoder layer plus its pooled path, through its ReLU
@@ -744,9 +745,10 @@ __global__ void k_pool_back_relu(View dy, View dx, View act, int nb, int S, int 
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int c8 = c / 8;
   if (i >= (size_t)nb * S * S * c8) return;
-  const int g = (int)(i % c8) * 8;
-  const size_t m = i / c8;
-  const int b = (int)(m / (S * S)), y = (int)(m / S) % S, x = (int)(m % S), so = S / 2;
+  const int lc = __builtin_ctz(c8), ls = __builtin_ctz(S);   // powers of two
+  const int g = (int)(i & (c8 - 1)) * 8;
+  const size_t m = i >> lc;
+  const int b = (int)(m >> (2 * ls)), y = (int)(m >> ls) & (S - 1), x = (int)m & (S - 1), so = S / 2;
   float d[8], v[8], a[8];
   ld8(dy.at(((size_t)b * so + y / 2) * so + x / 2) + g, d);
   ld8(dx.at(m) + g, v);
@@ -761,9 +763,10 @@ __global__ void k_up(View in, View out, int nb, int S, int c) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int so = 2 * S, c8 = c / 8;
   if (i >= (size_t)nb * so * so * c8) return;
-  const int g = (int)(i % c8) * 8;
-  const size_t m = i / c8;
-  const int b = (int)(m / (so * so)), y = (int)(m / so) % so, x = (int)(m % so);
+  const int lc = __builtin_ctz(c8), ls = __builtin_ctz(so);  // powers of two
+  const int g = (int)(i & (c8 - 1)) * 8;
+  const size_t m = i >> lc;
+  const int b = (int)(m >> (2 * ls)), y = (int)(m >> ls) & (so - 1), x = (int)m & (so - 1);
   *reinterpret_cast<bf16x8_t*>(out.at(m) + g) =
       *reinterpret_cast<const bf16x8_t*>(in.at(((size_t)b * S + y / 2) * S + x / 2) + g);
 }
@@ -773,9 +776,10 @@ __global__ void k_up_back_relu(View dy, View act, View dz, int nb, int S, int c)
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int c8 = c / 8;
   if (i >= (size_t)nb * S * S * c8) return;
-  const int g = (int)(i % c8) * 8;
-  const size_t m = i / c8;
-  const int b = (int)(m / (S * S)), y = (int)(m / S) % S, x = (int)(m % S), si = 2 * S;
+  const int lc = __builtin_ctz(c8), ls = __builtin_ctz(S);   // powers of two
+  const int g = (int)(i & (c8 - 1)) * 8;
+  const size_t m = i >> lc;
+  const int b = (int)(m >> (2 * ls)), y = (int)(m >> ls) & (S - 1), x = (int)m & (S - 1), si = 2 * S;
   float s[8] = {0, 0, 0, 0, 0, 0, 0, 0}, v[8], a[8];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
