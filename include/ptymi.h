@@ -85,7 +85,9 @@ typedef struct {
  *                        Fisher-Yates shuffle driven by SplitMix64 seeded with
  *                        order_seed + t in iteration t.
  *   chunk                patterns per Fourier-pass chunk (0 = automatic:
- *                        the value pty_autotune chose, else a 64 MB budget).
+ *                        the value pty_autotune chose, else as many
+ *                        patterns as a 96 MB scratch budget holds, rounded
+ *                        down to whole waves of blocks over 256 CUs).
  *   flags                PTY_ITER_GRAPH: DM and LSQML iterations are captured
  *                        once per distinct setting into a HIP graph and
  *                        replayed (fewer launches; same kernels, same results
@@ -300,19 +302,25 @@ pty_status pty_simulate(pty_ctx* ctx, double photons, float* out, int on_device)
 
 /* Adjoint of the Poisson likelihood (not in the paper; a differentiable forward
  * model for gradient-based refinement).  For the loaded counts d (natural
- * order) and the loaded positions,
+ * order) and the scan positions R_j,
  *   L = sum_j sum_q [I_jq - d_jq log(I_jq + 1e-6)],  I_j = sum_k |F(P_k S_j O)|^2
  * (the constant log(d!) dropped).  obj (H x W) and probe (K x N x N) are
- * complex64 device pointers.  pty_nll_forward writes L to *loss (host) and
- * synchronises; it stores no exit waves.  pty_nll_backward recomputes them
- * and writes grad_out times the gradients in PyTorch's convention for complex
- * tensors (dL/dRe z + i dL/dIm z): g_obj (H x W complex64), g_probe
- * (K x N x N complex64) and g_pos (J x 2 float32, derivatives with respect to
- * the top-left corners y_j, x_j; bilinear weights differentiated at fixed
- * floor), all device pointers; any of them may be NULL.  *loss (may be NULL)
+ * complex64 device pointers.  pos: J x 2 float32 (y, x) top-left corners in
+ * device memory, so that positions being optimised never leave the device;
+ * each coordinate is clamped into [0, H - N] (y) or [0, W - N] (x) (a NaN
+ * into 0), which keeps every patch inside the object.  pos == NULL uses the
+ * positions of pty_load_positions (PTY_E_STATE if none were loaded).
+ * pty_nll_forward writes L to *loss (host) and synchronises; it stores no
+ * exit waves.  pty_nll_backward recomputes them and writes grad_out times the
+ * gradients in PyTorch's convention for complex tensors
+ * (dL/dRe z + i dL/dIm z): g_obj (H x W complex64), g_probe (K x N x N
+ * complex64) and g_pos (J x 2 float32, derivatives with respect to the
+ * top-left corners y_j, x_j; bilinear weights differentiated at fixed floor),
+ * all device pointers; any of them may be NULL.  With device positions the
+ * object gradient's tile lists are built on the device.  *loss (may be NULL)
  * receives L.  Synchronises. */
-pty_status pty_nll_forward(pty_ctx* ctx, const void* obj, const void* probe, double* loss);
-pty_status pty_nll_backward(pty_ctx* ctx, const void* obj, const void* probe, float grad_out,
+pty_status pty_nll_forward(pty_ctx* ctx, const void* obj, const void* probe, const float* pos, double* loss);
+pty_status pty_nll_backward(pty_ctx* ctx, const void* obj, const void* probe, const float* pos, float grad_out,
                             void* g_obj, void* g_probe, float* g_pos, double* loss);
 
 /* ------------------------------------------------------------------------
@@ -320,7 +328,8 @@ pty_status pty_nll_backward(pty_ctx* ctx, const void* obj, const void* probe, fl
  * quality for synthetic data).
  * ---------------------------------------------------------------------- */
 
-/* Amplitude error E (Sec. 2.3's error metric) of the context's current object
+/* Amplitude error E (the per-iteration error of pty_get_errors; the paper
+ * reports reconstruction progress but defines no metric) of the context's current object
  * and probe over all positions, without changing the state.  Synchronises. */
 pty_status pty_model_error(pty_ctx* ctx, double* out);
 

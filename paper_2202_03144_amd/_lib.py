@@ -80,9 +80,9 @@ SIGNATURES = {
     "pty_simulate": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int]),
     "pty_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "pty_get_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
-    "pty_nll_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
-    "pty_nll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p,
-                                   C.c_void_p, C.POINTER(C.c_double)]),
+    "pty_nll_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "pty_nll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pty_model_error": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pty_set_truth": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_float]),
     "pty_nrmse": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),

@@ -9,7 +9,6 @@ forward call stores no exit waves; the backward call recomputes them
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 
@@ -17,21 +16,19 @@ class NLL(torch.autograd.Function):
     """loss = NLL.apply(obj, probe, positions, plan).
 
     obj: (H, W) complex64 CUDA tensor; probe: (K, N, N) complex64 CUDA tensor;
-    positions: (J, 2) float tensor of top-left corners (any device; they are
-    reloaded into the plan when they change); plan: a loaded Plan.
-    Returns a float64 scalar tensor on obj's device.
+    positions: (J, 2) float tensor of top-left corners, handed to the library
+    as a float32 device tensor (no host round trip when it already is one);
+    plan: a Plan with the counts loaded.  Returns a float64 scalar tensor on
+    obj's device.
     """
 
     @staticmethod
     def forward(ctx, obj, probe, positions, plan):
-        pos = positions.detach().to("cpu", torch.float64).numpy()
-        if getattr(plan, "_adj_pos", None) is None or not np.array_equal(plan._adj_pos, pos):
-            plan.load_positions(pos)
-            plan._adj_pos = pos.copy()
+        pos = positions.detach().to(device=obj.device, dtype=torch.float32).contiguous()
         obj_c = obj.detach().contiguous()
         probe_c = probe.detach().contiguous()
-        loss = plan.nll_forward(obj_c, probe_c)
-        ctx.save_for_backward(obj_c, probe_c)
+        loss = plan.nll_forward(obj_c, probe_c, pos)
+        ctx.save_for_backward(obj_c, probe_c, pos)
         ctx.plan = plan
         ctx.pos_dtype = positions.dtype
         ctx.pos_device = positions.device
@@ -39,13 +36,13 @@ class NLL(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out):
-        obj, probe = ctx.saved_tensors
+        obj, probe, pos = ctx.saved_tensors
         plan = ctx.plan
         need_o, need_p, need_r = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         g_obj = torch.empty_like(obj) if need_o else None
         g_probe = torch.empty_like(probe) if need_p else None
         g_pos = torch.empty((plan.n_pos, 2), dtype=torch.float32, device=obj.device) if need_r else None
-        plan.nll_backward(obj, probe, float(grad_out), g_obj, g_probe, g_pos)
+        plan.nll_backward(obj, probe, float(grad_out), g_obj, g_probe, g_pos, positions=pos)
         if g_pos is not None:
             g_pos = g_pos.to(device=ctx.pos_device, dtype=ctx.pos_dtype)
         return g_obj, g_probe, g_pos, None

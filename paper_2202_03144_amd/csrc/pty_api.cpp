@@ -112,6 +112,12 @@ struct pty_ctx {
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
   unsigned* epie_max = nullptr;    // per position of an iteration: the two ePIE step normalisers
   float2* epie_patch = nullptr;    // N x N: the pre-update patch of the current ePIE position
+  // adjoint with positions supplied on the device: their PosInfo form and
+  // device-built tile lists over all object tiles
+  PosInfo* adj_pos = nullptr;
+  int* adj_cnt = nullptr;
+  TileEntry* adj_tiles = nullptr;
+  PatchRef* adj_refs = nullptr;
 
   // device-side iteration counter (error / NRMSE history slot of the running
   // iteration), so that one captured iteration can be replayed
@@ -555,7 +561,7 @@ void density(pty_ctx* c, const Group& g) {
 
 // Probe sums over slots [0, count) of group g: part -> num_p / den_p
 void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern, PrbOp op,
-                  float2* num, bool with_den, const float2* obj = nullptr) {
+                  float2* num, bool with_den, const float2* obj = nullptr, const PosInfo* pos = nullptr) {
   const int count = (int)g.jl.size();
   const int per_slice = probe_per_slice(c->N, count);
   const int slices = probe_slices(count, per_slice);
@@ -566,7 +572,7 @@ void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern,
   pa.h = c->H;
   pa.w = c->W;
   pa.jlist = g.d_jl;
-  pa.pos = c->pos;
+  pa.pos = pos ? pos : c->pos;
   pa.src = src;
   pa.src_by_pattern = by_pattern;
   pa.alpha = c->alpha;
@@ -903,15 +909,24 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
 // ---------------------------------------------------------------------------
 // Poisson-likelihood adjoint
 // ---------------------------------------------------------------------------
-double run_nll(pty_ctx* c, const float2* obj, const float2* probe, bool grad, float grad_out, float2* g_obj,
-               float2* g_probe, float* g_pos) {
+// The identity slot list 0..J-1 (device), made once.
+const int* identity_slots(pty_ctx* c) {
+  if (!c->jl_identity) {
+    c->jl_identity = c->alloc<int>(size_t(c->J));
+    launch_iota_i32(c->jl_identity, c->J, c->stream);
+  }
+  return c->jl_identity;
+}
+
+double run_nll(pty_ctx* c, const float2* obj, const float2* probe, const float* pos_yx, bool grad, float grad_out,
+               float2* g_obj, float2* g_probe, float* g_pos) {
   if (!c->have_patterns) throw StateError("patterns not loaded");
-  if (!c->have_positions) throw StateError("positions not loaded");
+  if (!pos_yx && !c->have_positions) throw StateError("positions not loaded (and none supplied)");
   pty_iter_params p;
   pty_default_params(&p);
   const int chunk = chunk_patterns(c, p);
   const size_t nn = size_t(c->N) * c->N;
-  ensure_all_group(c);
+  if (!pos_yx) ensure_all_group(c);
   ensure_common(c, std::min(chunk, c->J), grad ? c->J : 1);
   c->ensure_once(c->loss_dev, 2);
   if (grad) {
@@ -919,8 +934,31 @@ double run_nll(pty_ctx* c, const float2* obj, const float2* probe, bool grad, fl
     c->ensure(c->posgrad, c->posgrad_slots, size_t(c->J) * row_blocks(c->N) * 2);
     ensure_probe_parts(c, c->J);
   }
-  const Group& g = c->all;
+  Group dev_group;   // positions on the device: identity slots, device-built tiles
+  const PosInfo* pos = c->pos;
+  if (pos_yx) {
+    const int nty = (c->H + kTileH - 1) / kTileH, ntx = (c->W + kTileW - 1) / kTileW;
+    c->ensure_once(c->adj_pos, size_t(c->J));
+    dev_group.d_jl = const_cast<int*>(identity_slots(c));
+    timed(c, kOther, [&] { launch_pos_from_yx(pos_yx, c->J, c->H - c->N, c->W - c->N, c->adj_pos, c->stream); });
+    pos = c->adj_pos;
+    if (grad && g_obj) {
+      c->ensure_once(c->adj_cnt, size_t(nty) * ntx);
+      c->ensure_once(c->adj_tiles, size_t(nty) * ntx);
+      c->ensure_once(c->adj_refs, device_tile_refs_max(c->N, c->J));
+      timed(c, kOther, [&] {
+        launch_build_tiles(pos, dev_group.d_jl, c->J, c->N, c->H, c->W, c->adj_cnt, c->adj_tiles, c->adj_refs,
+                           c->stream);
+      });
+      dev_group.tiles.tiles = c->adj_tiles;
+      dev_group.tiles.refs = c->adj_refs;
+      dev_group.tiles.ntiles = nty * ntx;
+    }
+    dev_group.jl.resize(c->J);
+  }
+  const Group& g = pos_yx ? dev_group : c->all;
   FourierArgs a = fourier_args(c, g);
+  a.pos = pos;
   a.obj = obj;
   a.probe = probe;
   a.chi = c->chi;
@@ -938,10 +976,11 @@ double run_nll(pty_ctx* c, const float2* obj, const float2* probe, bool grad, fl
   if (grad && g_obj) {
     timed(c, kOther, [&] { launch_fill_u32(reinterpret_cast<unsigned*>(g_obj), size_t(c->H) * c->W * 2, 0u, c->stream); });
     ObjGatherArgs o = obj_args(c, g);
+    o.pos = pos;
     o.out = g_obj;
     timed(c, kObjGather, [&] { launch_obj_gather(o, ObjOp::Gradient); });
   }
-  if (grad && g_probe) probe_reduce(c, g, c->chi, 0, PrbOp::Gradient, g_probe, false, obj);
+  if (grad && g_probe) probe_reduce(c, g, c->chi, 0, PrbOp::Gradient, g_probe, false, obj, pos);
   if (grad && g_pos)
     timed(c, kOther, [&] { launch_posgrad_reduce(c->posgrad, c->J, row_blocks(c->N), g_pos, g.d_jl, c->stream); });
   double loss = 0.0;
@@ -1699,23 +1738,23 @@ const char* pty_last_error(const pty_ctx* c) {
   return g_tls_error.c_str();
 }
 
-pty_status pty_nll_forward(pty_ctx* c, const void* obj, const void* probe, double* loss) {
+pty_status pty_nll_forward(pty_ctx* c, const void* obj, const void* probe, const float* pos, double* loss) {
   return guarded(c, [&] {
     require(c != nullptr && obj != nullptr && probe != nullptr && loss != nullptr, "pty_nll_forward: null argument");
     c->set_device();
-    *loss = run_nll(c, static_cast<const float2*>(obj), static_cast<const float2*>(probe), false, 1.f, nullptr,
+    *loss = run_nll(c, static_cast<const float2*>(obj), static_cast<const float2*>(probe), pos, false, 1.f, nullptr,
                     nullptr, nullptr);
   });
 }
 
-pty_status pty_nll_backward(pty_ctx* c, const void* obj, const void* probe, float grad_out, void* g_obj,
-                            void* g_probe, float* g_pos, double* loss) {
+pty_status pty_nll_backward(pty_ctx* c, const void* obj, const void* probe, const float* pos, float grad_out,
+                            void* g_obj, void* g_probe, float* g_pos, double* loss) {
   return guarded(c, [&] {
     require(c != nullptr && obj != nullptr && probe != nullptr, "pty_nll_backward: null argument");
     require(std::isfinite(grad_out), "pty_nll_backward: grad_out must be finite");
     c->set_device();
-    const double l = run_nll(c, static_cast<const float2*>(obj), static_cast<const float2*>(probe), true, grad_out,
-                             static_cast<float2*>(g_obj), static_cast<float2*>(g_probe), g_pos);
+    const double l = run_nll(c, static_cast<const float2*>(obj), static_cast<const float2*>(probe), pos, true,
+                             grad_out, static_cast<float2*>(g_obj), static_cast<float2*>(g_probe), g_pos);
     if (loss) *loss = l;
   });
 }

@@ -152,6 +152,18 @@ void launch_orthogonalise_modes(float2* probe, float2* psi, int n, int k, int j,
 void launch_pos_update(PosInfo* pos, const int* jlist, const float2* shift, int count, int lim_y, int lim_x,
                        hipStream_t s);
 
+// Device positions (J x 2 float32 y, x) -> PosInfo, clamped into [0, lim].
+void launch_pos_from_yx(const float* yx, int count, int lim_y, int lim_x, PosInfo* out, hipStream_t s);
+// Tile lists of the slots [0, count) of jlist built on the device: one
+// TileEntry per object tile (ceil(h / kTileH) x ceil(w / kTileW) of them, in
+// row-major tile order; cnt holds as many ints), refs at most
+// device_tile_refs_max(n, count) entries.
+size_t device_tile_refs_max(int n, int count);
+void launch_build_tiles(const PosInfo* pos, const int* jlist, int count, int n, int h, int w, int* cnt,
+                        TileEntry* tiles, PatchRef* refs, hipStream_t s);
+// p[i] = i for i < n
+void launch_iota_i32(int* p, int n, hipStream_t s);
+
 struct EpieArgs {
   int n, k;
   float2* obj;

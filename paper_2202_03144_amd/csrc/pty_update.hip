@@ -1206,6 +1206,137 @@ void launch_pos_update(PosInfo* pos, const int* jlist, const float2* shift, int 
   PTY_LAUNCH_CHECK("pos_update");
 }
 
+// Positions held on the device as J x 2 float32 (y, x) top-left corners:
+// integer floor and fraction of each, clamped into [0, lim] (a NaN becomes 0)
+// so that every patch stays inside the object.
+__global__ void k_pos_from_yx(const float* __restrict__ yx, int count, int lim_y, int lim_x,
+                              PosInfo* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  auto split = [](float v, int lim, int& i, float& f) {
+    const float r = fminf(fmaxf(v, 0.f), (float)lim);
+    i = (int)floorf(r);
+    f = r - (float)i;
+  };
+  PosInfo p;
+  split(yx[2 * (size_t)j], lim_y, p.iy, p.fy);
+  split(yx[2 * (size_t)j + 1], lim_x, p.ix, p.fx);
+  out[j] = p;
+}
+
+// Tile lists built on the device from device positions: every object tile
+// gets an entry (empty ones included) listing, in slot order, the patches
+// whose (N+1)^2 footprint overlaps it; the same lists the host builds from
+// loaded positions.  Count per tile, exclusive scan, then an ordered fill
+// (wave ballots), so the lists do not depend on scheduling.
+__device__ __forceinline__ bool tile_hit(const PosInfo& p, int n, int ty, int tx, int nty, int ntx) {
+  const int y0 = p.iy / kTileH, y1 = min(nty - 1, (p.iy + n) / kTileH);
+  const int x0 = p.ix / kTileW, x1 = min(ntx - 1, (p.ix + n) / kTileW);
+  return ty >= y0 && ty <= y1 && tx >= x0 && tx <= x1;
+}
+
+__global__ __launch_bounds__(256) void k_tiles_count(const PosInfo* __restrict__ pos, const int* __restrict__ jlist,
+                                                     int count, int n, int nty, int ntx, int* __restrict__ cnt) {
+  __shared__ int tot;
+  const int t = blockIdx.x, ty = t / ntx, tx = t % ntx;
+  if (threadIdx.x == 0) tot = 0;
+  __syncthreads();
+  int c = 0;
+  for (int s = threadIdx.x; s < count; s += 256) c += tile_hit(pos[jlist[s]], n, ty, tx, nty, ntx) ? 1 : 0;
+  atomicAdd(&tot, c);   // integers: the same total in any order
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[t] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_tiles_scan(const int* __restrict__ cnt, int ntiles, int ntx,
+                                                     TileEntry* __restrict__ tiles) {
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += 1024) {
+    const int t = base + threadIdx.x;
+    const int v = t < ntiles ? cnt[t] : 0;
+    int x = v;   // inclusive scan inside the wavefront
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int beg = carry + x - v;
+    for (int i = 0; i < w; ++i) beg += wsum[i];
+    if (t < ntiles) tiles[t] = TileEntry{(t / ntx) * kTileH, (t % ntx) * kTileW, beg, beg + v};
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = beg + v;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tiles_fill(const PosInfo* __restrict__ pos, const int* __restrict__ jlist,
+                                                    int count, int n, int nty, int ntx,
+                                                    const TileEntry* __restrict__ tiles,
+                                                    PatchRef* __restrict__ refs) {
+  __shared__ int wcnt[4];
+  const int t = blockIdx.x, ty = t / ntx, tx = t % ntx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int next = tiles[t].beg;
+  for (int base = 0; base < count; base += 256) {
+    const int s = base + threadIdx.x;
+    bool hit = false;
+    int j = 0;
+    PosInfo p{};
+    if (s < count) {
+      j = jlist[s];
+      p = pos[j];
+      hit = tile_hit(p, n, ty, tx, nty, ntx);
+    }
+    const unsigned long long bal = __ballot(hit);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int off = next;
+    for (int i = 0; i < w; ++i) off += wcnt[i];
+    if (hit) refs[off + before] = PatchRef{s, j, p.iy, p.ix, p.fy, p.fx, 0, 0};
+    next += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+}
+
+__global__ void k_iota_i32(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+void launch_pos_from_yx(const float* yx, int count, int lim_y, int lim_x, PosInfo* out, hipStream_t s) {
+  if (count <= 0) return;
+  k_pos_from_yx<<<(count + 127) / 128, 128, 0, s>>>(yx, count, lim_y, lim_x, out);
+  PTY_LAUNCH_CHECK("pos_from_yx");
+}
+
+size_t device_tile_refs_max(int n, int count) {
+  return (size_t)count * (size_t)(n / kTileH + 2) * (size_t)(n / kTileW + 2);
+}
+
+void launch_build_tiles(const PosInfo* pos, const int* jlist, int count, int n, int h, int w, int* cnt,
+                        TileEntry* tiles, PatchRef* refs, hipStream_t s) {
+  const int nty = (h + kTileH - 1) / kTileH, ntx = (w + kTileW - 1) / kTileW, nt = nty * ntx;
+  k_tiles_count<<<nt, 256, 0, s>>>(pos, jlist, count, n, nty, ntx, cnt);
+  PTY_LAUNCH_CHECK("tiles_count");
+  k_tiles_scan<<<1, 1024, 0, s>>>(cnt, nt, ntx, tiles);
+  PTY_LAUNCH_CHECK("tiles_scan");
+  k_tiles_fill<<<nt, 256, 0, s>>>(pos, jlist, count, n, nty, ntx, tiles, refs);
+  PTY_LAUNCH_CHECK("tiles_fill");
+}
+
+void launch_iota_i32(int* p, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_iota_i32<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+  PTY_LAUNCH_CHECK("iota");
+}
+
 bool epie_fused_supported(int n, int k) {
   if (n == 32) return k >= 1 && k <= 4;
   if (n == 64) return k >= 1 && k <= 2;

@@ -235,20 +235,25 @@ class Plan:
             raise ValueError(f"{name} must be contiguous")
         return ptr
 
-    def nll_forward(self, obj, probe) -> float:
-        """Poisson NLL of the loaded counts for (obj, probe) given as CUDA complex64 tensors."""
+    def nll_forward(self, obj, probe, positions=None) -> float:
+        """Poisson NLL of the loaded counts for (obj, probe) given as CUDA complex64 tensors;
+        ``positions``: (J, 2) float32 CUDA tensor of top-left corners, or None for the loaded ones."""
         loss = C.c_double()
         self._check(self._lib.pty_nll_forward(
             self._live(), self._dev(obj, np.complex64, self.obj_shape, "obj"),
-            self._dev(probe, np.complex64, (self.modes, self.n, self.n), "probe"), C.byref(loss)))
+            self._dev(probe, np.complex64, (self.modes, self.n, self.n), "probe"),
+            self._dev(positions, np.float32, (self.n_pos, 2), "positions"), C.byref(loss)))
         return loss.value
 
-    def nll_backward(self, obj, probe, grad_out: float = 1.0, g_obj=None, g_probe=None, g_pos=None) -> float:
-        """Writes grad_out times the NLL gradients into the given CUDA tensors (any may be None)."""
+    def nll_backward(self, obj, probe, grad_out: float = 1.0, g_obj=None, g_probe=None, g_pos=None,
+                     positions=None) -> float:
+        """Writes grad_out times the NLL gradients into the given CUDA tensors (any may be None);
+        ``positions`` as in :meth:`nll_forward`."""
         loss = C.c_double()
         self._check(self._lib.pty_nll_backward(
             self._live(), self._dev(obj, np.complex64, self.obj_shape, "obj"),
-            self._dev(probe, np.complex64, (self.modes, self.n, self.n), "probe"), float(grad_out),
+            self._dev(probe, np.complex64, (self.modes, self.n, self.n), "probe"),
+            self._dev(positions, np.float32, (self.n_pos, 2), "positions"), float(grad_out),
             self._dev(g_obj, np.complex64, self.obj_shape, "g_obj"),
             self._dev(g_probe, np.complex64, (self.modes, self.n, self.n), "g_probe"),
             self._dev(g_pos, np.float32, (self.n_pos, 2), "g_pos"), C.byref(loss)))

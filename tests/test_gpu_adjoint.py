@@ -105,12 +105,66 @@ def test_autograd_function():
     assert _rel(pt.grad.cpu().numpy(), 2 * ref_gp) <= TOL
     assert rt.grad.dtype == torch.float64
     assert np.linalg.norm(rt.grad.numpy() - 2 * ref_gr) <= TOL * np.linalg.norm(2 * ref_gr)
-    # moving the positions reloads them (bilinear weights change)
+    # moved positions change the bilinear weights
     rt2 = (rt.detach() + 0.25).requires_grad_(True)
     l2 = NLL.apply(ot.detach(), pt.detach(), rt2, pl)
     assert abs(l2.item() - oracle.nll(o.astype(np.complex128), p.astype(np.complex128), pos + 0.25,
                                       cnt.astype(np.float64))) <= 1e-5 * abs(l2.item())
     pl.close()
+
+
+def _f32(pos):
+    return np.asarray(pos, np.float32).astype(np.float64)
+
+
+def test_device_positions_moved_and_clamped():
+    """Positions handed over on the device: moved by several pixels from the loaded
+    ones (the object gradient's tile lists are rebuilt on the device), and some
+    outside the object (clamped into [0, H - N] x [0, W - N])."""
+    import torch
+    o, p, pos, cnt = _fd_case()
+    pl = _plan(32, 4, pos, o.shape, cnt)
+    lim = np.array([o.shape[0] - 32, o.shape[1] - 32], np.float64)
+    moved = np.clip(pos + np.array([3.3, -2.6]), 0.0, lim)
+    outside = pos.copy()
+    outside[0] = [-2.5, 1.25]
+    outside[5] = [3.75, lim[1] + 3.0]
+    outside[9] = [lim[0] + 0.5, 2.5]
+    ot = torch.from_numpy(o).cuda()
+    pt = torch.from_numpy(p).cuda()
+    for given in (moved, outside):
+        rt = torch.from_numpy(given.astype(np.float32)).cuda()
+        go = torch.empty_like(ot)
+        gp = torch.empty_like(pt)
+        gr = torch.empty((pl.n_pos, 2), dtype=torch.float32, device="cuda")
+        loss = pl.nll_backward(ot, pt, 1.0, go, gp, gr, positions=rt)
+        lf = pl.nll_forward(ot, pt, rt)
+        eff = np.clip(_f32(given), 0.0, lim)
+        ref_l, ref_go, ref_gp, ref_gr = oracle.nll_grad(o.astype(np.complex128), p.astype(np.complex128), eff,
+                                                        cnt.astype(np.float64))
+        assert abs(loss - ref_l) <= 1e-5 * abs(ref_l) and abs(lf - ref_l) <= 1e-5 * abs(ref_l)
+        assert _rel(go.cpu().numpy(), ref_go) <= TOL
+        assert _rel(gp.cpu().numpy(), ref_gp) <= TOL
+        g = gr.cpu().numpy()
+        assert np.linalg.norm(g - ref_gr) <= TOL * np.linalg.norm(ref_gr)
+    # the loaded positions are untouched by device ones
+    assert np.array_equal(pl.positions(), pos)
+    pl.close()
+
+
+def test_device_positions_without_loaded_ones():
+    import torch
+    from paper_2202_03144_amd import Plan
+    o, p, pos, cnt = _fd_case()
+    with Plan(32, 4, len(pos), o.shape) as pl:
+        pl.load_patterns(cnt)
+        ot = torch.from_numpy(o).cuda()
+        pt = torch.from_numpy(p).cuda()
+        with pytest.raises(RuntimeError, match="PTY_E_STATE"):
+            pl.nll_forward(ot, pt)
+        lf = pl.nll_forward(ot, pt, torch.from_numpy(pos.astype(np.float32)).cuda())
+    ref = oracle.nll(o.astype(np.complex128), p.astype(np.complex128), _f32(pos), cnt.astype(np.float64))
+    assert abs(lf - ref) <= 1e-5 * abs(ref)
 
 
 def test_gradient_descent_on_object_reduces_nll():
