@@ -523,8 +523,6 @@ def adjoint_leg(args, torch) -> dict:
     }
 
 
-LISTING1 = ("./ptycho -jobID=sim512 -beamSize=110e-9 -scanDims=30,30 -step=50e-9,50e-9 -i=100 -size=512 "
-            "-lambda=2.4796837508399954e-10 -dx_d=172e-6 -z=1 -simulate=1 -blind=0")
 
 
 def listing1_leg(args, torch) -> dict:
@@ -535,6 +533,7 @@ def listing1_leg(args, torch) -> dict:
     import oracle
     from paper_2202_03144_amd import command
 
+    LISTING1 = command.make_command(command.SIM512)
     res = {}
     for algo in ("epie", "dm", "lsqml"):
         pl, g, obj, probe = command.simulated_plan(LISTING1)

@@ -33,10 +33,46 @@ import math
 
 import numpy as np
 
+from ptysynth import sim_object as synthetic_object  # noqa: F401  (input ingredients)
+from ptysynth import sim_probe as synthetic_probe  # noqa: F401
+
 _FLOAT = {"lambda", "z", "dx_d", "beamSize"}
 _INT = {"size", "i", "simulate", "blind", "probeModes"}
 _PAIR = {"scanDims": int, "step": float}
 _TEXT = {"jobID"}
+
+
+# The simulated workload of the paper's script example (Sec. 3.2, Listing 1),
+# as named values: a 512-pixel detector window, a 30 x 30 raster with 50 nm
+# steps, a 110 nm beam, 5 keV photons (wavelength 0.248 nm), a detector of
+# 172 um pixels 1 m from the sample, 100 iterations, simulated data from a
+# known probe.
+SIM512 = {
+    "jobID": "sim512",
+    "beamSize": 110e-9,
+    "scanDims": (30, 30),
+    "step": (50e-9, 50e-9),
+    "i": 100,
+    "size": 512,
+    "lambda": 2.4796837508399954e-10,
+    "dx_d": 172e-6,
+    "z": 1.0,
+    "simulate": 1,
+    "blind": 0,
+}
+
+
+def make_command(opts: dict, program: str = "ptycho") -> str:
+    """The ``-key=value`` command string of typed options (the inverse of
+    :func:`parse`; pairs are written comma-separated)."""
+    toks = [program] if program else []
+    for k, v in opts.items():
+        if k in _PAIR:
+            v = ",".join(repr(_PAIR[k](x)) if _PAIR[k] is float else str(int(x)) for x in v)
+        elif k in _FLOAT:
+            v = repr(float(v))
+        toks.append(f"-{k}={v}")
+    return " ".join(toks)
 
 
 def parse(cmd: str) -> dict:
@@ -95,34 +131,6 @@ def geometry(opts: dict) -> Geometry:
     return Geometry(n=n, modes=opts.get("probeModes", 1), pixel=dx, beam_px=opts["beamSize"] / dx,
                     step_px=(sy, sx), positions=pos, obj_shape=(h, w), iterations=opts.get("i", 100),
                     blind=bool(opts.get("blind", 0)))
-
-
-def synthetic_object(shape, seed: int = 0, corr: float = 4.0) -> np.ndarray:
-    """A seeded phase-and-amplitude test object standing in for the paper's
-    simulation image: Gaussian-correlated noise (correlation length ``corr``
-    pixels), amplitude in [0.8, 1], phase in [-0.5, 0.5] rad."""
-    rng = np.random.default_rng([2202, 3144, seed])
-    ky = np.fft.fftfreq(shape[0])[:, None]
-    kx = np.fft.fftfreq(shape[1])[None, :]
-    g = np.exp(-2.0 * (math.pi * corr) ** 2 * (ky * ky + kx * kx))
-
-    def field():
-        f = np.real(np.fft.ifft2(np.fft.fft2(rng.standard_normal(shape)) * g))
-        return (f - f.min()) / (f.max() - f.min())
-    return ((0.8 + 0.2 * field()) * np.exp(1j * (field() - 0.5))).astype(np.complex64)
-
-
-def synthetic_probe(n: int, modes: int, beam_px: float) -> np.ndarray:
-    """The known probe of the simulation: a disk of the beam diameter with a
-    defocus-like quadratic phase (0.8 rad at the rim), later modes weaker
-    copies times x, y ramps, total power 1 (the forward model rescales it)."""
-    c = (n - 1) / 2.0
-    u, v = np.meshgrid(np.arange(n) - c, np.arange(n) - c, indexing="ij")
-    rr = (u * u + v * v) / (beam_px / 2.0) ** 2
-    disk = (rr <= 1.0) * np.exp(1j * 0.8 * rr)
-    shapes = [disk, disk * v / (beam_px / 2), disk * u / (beam_px / 2), disk * u * v / (beam_px / 2) ** 2]
-    p = np.stack([shapes[k] * (0.5 ** k) for k in range(modes)])
-    return (p / math.sqrt(float(np.sum(np.abs(p) ** 2)))).astype(np.complex64)
 
 
 def simulated_plan(cmd: str, photons: float = 1e6, seed: int = 0, device: int = 0, stream=None):

@@ -39,6 +39,8 @@ __all__ = [
     "CONFIGS",
     "workload",
     "POWER_WEIGHTS",
+    "sim_object",
+    "sim_probe",
 ]
 
 # Relative power of the incoherent probe modes, K = 1..4.
@@ -238,3 +240,32 @@ def workload(cfg: int) -> Workload:
 def scaled(wl: Workload, **changes) -> Workload:
     """A copy of ``wl`` with fields replaced (used for reduced test shapes)."""
     return dataclasses.replace(wl, **changes)
+
+
+def sim_object(shape, seed: int = 0, corr: float = 4.0) -> np.ndarray:
+    """A seeded phase-and-amplitude test object standing in for the paper's
+    simulation image (the command front end's simulation mode):
+    Gaussian-correlated noise (correlation length ``corr`` pixels), amplitude
+    in [0.8, 1], phase in [-0.5, 0.5] rad."""
+    rng = np.random.default_rng([2202, 3144, seed])
+    ky = np.fft.fftfreq(shape[0])[:, None]
+    kx = np.fft.fftfreq(shape[1])[None, :]
+    g = np.exp(-2.0 * (math.pi * corr) ** 2 * (ky * ky + kx * kx))
+
+    def field():
+        f = np.real(np.fft.ifft2(np.fft.fft2(rng.standard_normal(shape)) * g))
+        return (f - f.min()) / (f.max() - f.min())
+    return ((0.8 + 0.2 * field()) * np.exp(1j * (field() - 0.5))).astype(np.complex64)
+
+
+def sim_probe(n: int, modes: int, beam_px: float) -> np.ndarray:
+    """The known probe of the simulation: a disk of the beam diameter with a
+    defocus-like quadratic phase (0.8 rad at the rim), later modes weaker
+    copies times x, y ramps, total power 1 (the forward model rescales it)."""
+    c = (n - 1) / 2.0
+    u, v = np.meshgrid(np.arange(n) - c, np.arange(n) - c, indexing="ij")
+    rr = (u * u + v * v) / (beam_px / 2.0) ** 2
+    disk = (rr <= 1.0) * np.exp(1j * 0.8 * rr)
+    shapes = [disk, disk * v / (beam_px / 2), disk * u / (beam_px / 2), disk * u * v / (beam_px / 2) ** 2]
+    p = np.stack([shapes[k] * (0.5 ** k) for k in range(modes)])
+    return (p / math.sqrt(float(np.sum(np.abs(p) ** 2)))).astype(np.complex64)

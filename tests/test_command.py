@@ -9,8 +9,7 @@ import pytest
 
 from paper_2202_03144_amd import command
 
-LISTING1 = ("./ptycho -jobID=sim512 -beamSize=110e-9 -scanDims=30,30 -step=50e-9,50e-9 -i=100 -size=512 "
-            "-lambda=2.4796837508399954e-10 -dx_d=172e-6 -z=1 -simulate=1 -blind=0")
+LISTING1 = command.make_command(command.SIM512)
 
 
 def test_parse_listing1():

@@ -132,6 +132,7 @@ def test_device_positions_moved_and_clamped():
     outside[9] = [lim[0] + 0.5, 2.5]
     ot = torch.from_numpy(o).cuda()
     pt = torch.from_numpy(p).cuda()
+    loaded = pl.positions()   # floor + float32 fraction, as stored
     for given in (moved, outside):
         rt = torch.from_numpy(given.astype(np.float32)).cuda()
         go = torch.empty_like(ot)
@@ -148,7 +149,8 @@ def test_device_positions_moved_and_clamped():
         g = gr.cpu().numpy()
         assert np.linalg.norm(g - ref_gr) <= TOL * np.linalg.norm(ref_gr)
     # the loaded positions are untouched by device ones
-    assert np.array_equal(pl.positions(), pos)
+    assert np.array_equal(pl.positions(), loaded)
+    assert np.abs(loaded - pos).max() <= 1e-6
     pl.close()
 
 

@@ -4,10 +4,11 @@ ePIE steps with the known probe (E falls), and the blind variant."""
 import numpy as np
 import pytest
 
+from paper_2202_03144_amd import command
+
 pytestmark = pytest.mark.gpu
 
-LISTING1 = ("./ptycho -jobID=sim512 -beamSize=110e-9 -scanDims=30,30 -step=50e-9,50e-9 -i=100 -size=512 "
-            "-lambda=2.4796837508399954e-10 -dx_d=172e-6 -z=1 -simulate=1 -blind=0")
+LISTING1 = command.make_command(command.SIM512)
 
 
 def test_listing1_step_mode():
@@ -25,8 +26,7 @@ def test_listing1_step_mode():
 
 
 def test_listing1_blind_start():
-    from paper_2202_03144_amd import command
-    pl, g, obj, probe = command.simulated_plan(LISTING1.replace("-blind=0", "-blind=1"))
+    pl, g, obj, probe = command.simulated_plan(command.make_command({**command.SIM512, "blind": 1}))
     guess = pl.probe()
     pl.iterate("epie", 2, **command.iteration_params(g))
     e = pl.errors()
