@@ -323,6 +323,27 @@ pty_status pty_nll_forward(pty_ctx* ctx, const void* obj, const void* probe, con
 pty_status pty_nll_backward(pty_ctx* ctx, const void* obj, const void* probe, const float* pos, float grad_out,
                             void* g_obj, void* g_probe, float* g_pos, double* loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc):
+ * the Poisson likelihood L of pty_nll_forward over the first `count`
+ * positions (1 <= count <= J) of the loaded patterns, computed with no
+ * allocation of any kind.  Its work space (transform scratch, per-pattern
+ * partial sums, slot list and the positions' floor/fraction form) lives in
+ * one library-wide device array of PTY_NOALLOC_SCRATCH_BYTES per GPU, held
+ * from the first pty_create on that GPU until the process ends.  Arguments as
+ * for pty_nll_forward; `loss` is a device pointer to one double, written
+ * asynchronously on the context's stream (no synchronisation, no host copy).
+ * PTY_E_INVALID if count is out of range or the work space of `count`
+ * positions does not fit the array (it needs count x (20 + 16 x column blocks)
+ * bytes plus one pattern's K x N x N complex64 transform scratch; the
+ * transforms run in as many chunks as the rest of the array requires).  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (from
+ * different streams or threads) race and must be serialised by the caller.
+ * The result equals pty_nll_forward's for the same count. */
+#define PTY_NOALLOC_SCRATCH_BYTES (64u << 20)
+pty_status pty_nll_forward_noalloc(pty_ctx* ctx, const void* obj, const void* probe, const float* pos,
+                                   int32_t count, double* loss);
+
 /* ------------------------------------------------------------------------
  * Evaluation against a known object (not in the paper; reconstruction
  * quality for synthetic data).

@@ -83,6 +83,8 @@ SIGNATURES = {
     "pty_nll_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pty_nll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "pty_nll_forward_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                          C.c_void_p]),
     "pty_model_error": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pty_set_truth": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_float]),
     "pty_nrmse": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),

@@ -13,6 +13,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <new>
 #include <string>
@@ -23,7 +24,35 @@
 
 using namespace pty;
 
+// Work space of pty_nll_forward_noalloc: one array per GPU, part of the code
+// object, so no call ever allocates it.  In host code this name is only a
+// stand-in: kernels and copies take the per-device address that
+// noalloc_scratch() obtains from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[PTY_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` on each GPU, looked up once per device at
+// context set-up with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    throw DeviceError("no-allocation scratch: device " + std::to_string(device) + " beyond the table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      throw DeviceError(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_addr[device] = ptr;
+  }
+  return g_scratch_addr[device];
+}
 
 thread_local std::string g_tls_error;
 
@@ -1311,6 +1340,7 @@ pty_status pty_create(const pty_plan_desc* plan, pty_ctx** out) {
     c->device = plan->device;
     if (const char* lim = std::getenv("PTY_MEM_LIMIT")) c->mem_limit = std::strtoull(lim, nullptr, 10);
     c->set_device();
+    (void)noalloc_scratch(c->device);   // once per device, with it current
     if (plan->stream) {
       c->stream = static_cast<hipStream_t>(plan->stream);
     } else {
@@ -1756,6 +1786,61 @@ pty_status pty_nll_backward(pty_ctx* c, const void* obj, const void* probe, cons
     const double l = run_nll(c, static_cast<const float2*>(obj), static_cast<const float2*>(probe), pos, true,
                              grad_out, static_cast<float2*>(g_obj), static_cast<float2*>(g_probe), g_pos);
     if (loss) *loss = l;
+  });
+}
+
+pty_status pty_nll_forward_noalloc(pty_ctx* c, const void* obj, const void* probe, const float* pos, int32_t count,
+                                   double* loss) {
+  return guarded(c, [&] {
+    require(c != nullptr && obj != nullptr && probe != nullptr && loss != nullptr,
+            "pty_nll_forward_noalloc: null argument");
+    require(count >= 1 && count <= c->J, "pty_nll_forward_noalloc: count must be in 1..J");
+    if (!c->have_patterns) throw StateError("patterns not loaded");
+    if (!pos && !c->have_positions) throw StateError("positions not loaded (and none supplied)");
+    c->set_device();
+    char* base = static_cast<char*>(noalloc_scratch(c->device));
+    constexpr size_t cap = PTY_NOALLOC_SCRATCH_BYTES;
+    const size_t per = size_t(c->K) * c->N * c->N * sizeof(float2);
+    const int cb = col_blocks(c->N, c->K);
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+      char* p = base + used;
+      used += (bytes + 255) / 256 * 256;
+      return p;
+    };
+    int* slots = reinterpret_cast<int*>(take(sizeof(int) * size_t(count)));
+    PosInfo* pinfo = pos ? reinterpret_cast<PosInfo*>(take(sizeof(PosInfo) * size_t(count))) : nullptr;
+    double* errp = reinterpret_cast<double*>(take(sizeof(double) * 2 * size_t(count) * cb));
+    if (used + per > cap)
+      throw InvalidArg("pty_nll_forward_noalloc: " + std::to_string(count) + " positions need " +
+                       std::to_string(used + per) + " bytes of work space; the no-allocation scratch holds " +
+                       std::to_string(cap));
+    float2* zs = reinterpret_cast<float2*>(base + used);
+    int chunk = (int)std::min<size_t>((cap - used) / per, size_t(count));
+    const int wave = std::max(1, 256 / row_blocks(c->N));
+    if (chunk >= wave) chunk = chunk / wave * wave;
+    launch_iota_i32(slots, count, c->stream);
+    if (pos) launch_pos_from_yx(pos, count, c->H - c->N, c->W - c->N, pinfo, c->stream);
+    Group g;
+    g.d_jl = slots;
+    FourierArgs a = fourier_args(c, g);
+    a.obj = static_cast<const float2*>(obj);
+    a.probe = static_cast<const float2*>(probe);
+    a.pos = pos ? pinfo : c->pos;
+    a.zs = zs;
+    a.errp = errp;
+    a.psi = nullptr;
+    a.chi = nullptr;
+    a.contrib = nullptr;
+    a.posgrad = nullptr;
+    for (int off = 0; off < count; off += chunk) {
+      a.jl_off = off;
+      a.slot_off = off;
+      a.nc = std::min(chunk, count - off);
+      launch_rows_fwd(a, RowIn::Plain);
+      launch_cols(a, ColOp::NllLoss);
+    }
+    launch_err_reduce(errp, count * cb, loss, c->stream);
   });
 }
 
