@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -25,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pattern-iterations/s (256², 3 modes)"
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (256 CUs x 2.4 GHz x 256 flop/clk, packed FMA)
+PEAK_LDS_TBS = 78.6          # MI355X LDS (256 CUs x 2.4 GHz x 128 B/clk)
 
 
 def log(msg: str) -> None:
@@ -112,6 +115,29 @@ def kernel_src_hash():
         hdr = fh.read()
     h.update(hdr[:hdr.index("void launch_rows_fwd")].encode())
     return h.hexdigest()[:16]
+
+
+# Algorithmic flops per pattern of a Fourier-pass kernel: 5 L log2 L per
+# length-L line transform (N lines of length N per mode and direction, i.e.
+# 5 N^2 log2 N per mode and one-dimensional pass), plus the pointwise work per
+# pixel: bilinear gather 14 and exit wave 6 per mode (DM reflection +4 per
+# mode); projection 4 per mode for the intensity, 8 for modulus, ratio and
+# error, 2 per mode to scale; DM update 16 per mode (new exit wave and its
+# contribution), stored chi's contribution 8 per mode.
+def flops_per_pattern(plan, fam, n, k):
+    nn = n * n
+    line = 5.0 * nn * math.log2(n)
+    if fam == "rows_fwd":
+        return k * line + nn * (14 + 6 * k + (4 * k if plan == "dm" else 0))
+    if fam == "cols":
+        return 2 * k * line + nn * (6 * k + 8)
+    return k * line + nn * ((14 + 16 * k) if plan == "dm" else 8 * k)
+
+
+# Algorithmic LDS bytes per pattern: each line transform writes and reads its N
+# values once through LDS for the exchange (16 N bytes per line).
+def lds_bytes_per_pattern(fam, n, k):
+    return (2 if fam == "cols" else 1) * k * 16 * n * n
 
 
 KERNEL_NAMES = {
@@ -887,6 +913,7 @@ def main() -> int:
 
     roofline = None
     families = None
+    kernel_roofs = None
     if not args.no_timing_pass:
         log("event-timed kernel pass")
         for pl in plans.values():
@@ -899,24 +926,52 @@ def main() -> int:
                 if cnt:
                     families[f"{algo}.{fam}"] = {"ms_per_iter": ms / args.steps, "launches_per_iter": cnt / args.steps}
             pl.set_timing(False)
-        fourier = [f for f in families if f.split(".", 1)[1] in ("rows_fwd", "cols", "rows_inv")]
-        dom = max(fourier, key=lambda f: families[f]["ms_per_iter"])
-        plan_name, fam = dom.split(".", 1)
-        fdat = families[dom]
-        per_launch_ms = fdat["ms_per_iter"] / fdat["launches_per_iter"]
-        patterns_per_launch = wl.j / fdat["launches_per_iter"]
-        alg = algorithmic_bytes_per_pattern(plan_name, fam, wl.n, wl.k) * patterns_per_launch
-        achieved = alg / (per_launch_ms / 1e3) / 1e9
-        traffic = None
-        if kernel_src_hash() == COUNTER_SRC_HASH and (plan_name, fam) in MEASURED_KIB:
-            fk, wk, npl = MEASURED_KIB[(plan_name, fam)]
-            traffic = round((2.0 * fk + 1.0 * wk) * 1024 / npl * patterns_per_launch)
-        roofline = {"bound": "hbm", "kernel": f"{KERNEL_NAMES[(plan_name, fam)]} ({dom})",
-                    "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                    "algorithmic_bytes_per_launch": round(alg), "avg_launch_ms": round(per_launch_ms, 4),
-                    "patterns_per_launch": round(patterns_per_launch, 2)}
-        log(f"dominant kernel {dom}: {fdat}")
+        # one entry per compiled kernel: the column pass is the same kernel in
+        # DM and LSQML, so its launches are pooled
+        kern = {}
+        for (plan_name, fam), name in KERNEL_NAMES.items():
+            f = families.get(f"{plan_name}.{fam}")
+            if not f:
+                continue
+            e = kern.setdefault(name, {"fam": fam, "plan": plan_name, "ms_per_step": 0.0, "launches_per_step": 0.0,
+                                       "traffic_key": (plan_name, fam), "plans": 0})
+            e["plans"] += 1
+            e["ms_per_step"] += f["ms_per_iter"]
+            e["launches_per_step"] += f["launches_per_iter"]
+        src_ok = kernel_src_hash() == COUNTER_SRC_HASH
+        kernel_roofs = {}
+        for name, e in kern.items():
+            per_launch_ms = e["ms_per_step"] / e["launches_per_step"]
+            ppl = e["plans"] * wl.j / e["launches_per_step"]   # every plan passes all J patterns
+            b = algorithmic_bytes_per_pattern(e["plan"], e["fam"], wl.n, wl.k) * ppl
+            fl = flops_per_pattern(e["plan"], e["fam"], wl.n, wl.k) * ppl
+            lb = lds_bytes_per_pattern(e["fam"], wl.n, wl.k) * ppl
+            t = {"hbm": b / (PEAK_HBM_GBS * 1e9), "alu": fl / (PEAK_FP32_TFLOPS * 1e12),
+                 "lds": lb / (PEAK_LDS_TBS * 1e12)}
+            bound = max(t, key=t.get)
+            sec = per_launch_ms / 1e3
+            if bound == "hbm":
+                achieved, peak, unit = b / sec / 1e9, PEAK_HBM_GBS, "GB/s"
+            elif bound == "alu":
+                achieved, peak, unit = fl / sec / 1e12, PEAK_FP32_TFLOPS, "TFLOP/s"
+            else:
+                achieved, peak, unit = lb / sec / 1e12, PEAK_LDS_TBS, "TB/s"
+            traffic = None
+            if src_ok and e["traffic_key"] in MEASURED_KIB:
+                fk, wk, npl = MEASURED_KIB[e["traffic_key"]]
+                traffic = round((2.0 * fk + 1.0 * wk) * 1024 / npl * ppl)
+            kernel_roofs[name] = {
+                "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(t[bound] / sec, 4), "traffic": traffic,
+                "hbm_frac": round(t["hbm"] / sec, 4), "alu_frac": round(t["alu"] / sec, 4),
+                "lds_frac": round(t["lds"] / sec, 4),
+                "algorithmic_bytes_per_launch": round(b), "flops_per_launch": round(fl),
+                "lds_bytes_per_launch": round(lb), "avg_launch_ms": round(per_launch_ms, 4),
+                "patterns_per_launch": round(ppl, 2), "ms_per_step": round(e["ms_per_step"], 3),
+                "launches_per_step": e["launches_per_step"]}
+        dom = max(kernel_roofs, key=lambda n: kernel_roofs[n]["ms_per_step"])
+        roofline = dict(kernel_roofs[dom], kernel=dom)
+        log(f"dominant kernel {dom}: {roofline}")
     groups = -(-wl.j // params["lsqml"]["lsqml_batch"])
     iteration = {}
     for plan_name, ms in (("dm", dm_ms), ("lsqml", lsq_ms)):
@@ -951,6 +1006,7 @@ def main() -> int:
         "dm_ms_per_iter": round(dm_ms, 3),
         "lsqml_ms_per_iter": round(lsq_ms, 3),
         "roofline": roofline,
+        "kernel_rooflines": kernel_roofs,
         "iteration_roofline": iteration,
         "kernel_families": families,
         "cpu_baseline": cpu,

@@ -759,7 +759,7 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   c->ensure_once(c->dobj, size_t(c->H) * c->W);
   c->ensure(c->alpha, c->alpha_slots, size_t(bmax));
   c->ensure_once(c->alpha_by_j, size_t(c->J));
-  const int nrb = c->N * c->N >= 2048 ? c->N * c->N / 2048 : 1;  // row blocks of the step sums
+  const int nrb = lsq_row_blocks(c->N);  // row blocks of the step sums
   c->ensure_once(c->lsq_pq, nn);
   c->ensure_once(c->lsq_dint, nn);
   const bool refining = p.position_start >= 0 && p.position_start < c->iter + n_iter;

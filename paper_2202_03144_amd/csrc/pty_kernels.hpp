@@ -92,6 +92,7 @@ struct ProbeAccArgs {
   hipStream_t stream;
 };
 int probe_slices(int count, int per_slice);
+int lsq_row_blocks(int n);   // row blocks per window of the LSQML step sums
 int probe_per_slice(int n, int count);
 int probe_slices_max(int n, int count);
 void launch_probe_acc(const ProbeAccArgs& a, PrbOp op);

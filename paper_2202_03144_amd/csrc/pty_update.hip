@@ -166,17 +166,36 @@ __device__ __forceinline__ float2 obj_hrow(const float2* __restrict__ o, int h, 
 
 template <int N>
 struct ProbePix {
-  static constexpr int RB = (N >= 64) ? 8 : 4;
+  static constexpr int RB = 4;
   using W = ColWalk<N, RB>;
 };
+constexpr int kProbeSliceMax = 32;   // patterns per slice (probe_per_slice)
 
+// A block sums the patterns of one slice for its pixels.  The slice's
+// positions (and weights) are staged in LDS first, so that no pattern's
+// object reads wait behind a chain of list and position loads, and the next
+// pattern's source rows are loaded while the current one is summed.
 template <int N, int K, PrbOp OP>
 __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
   using W = typename ProbePix<N>::W;
   constexpr int RB = ProbePix<N>::RB;
+  __shared__ PosInfo sp[kProbeSliceMax];
+  __shared__ float sw[kProbeSliceMax];
+  __shared__ int ss[kProbeSliceMax];
   const int slice = blockIdx.y, rblk = blockIdx.x;
   const int s_beg = a.s0 + slice * a.per_slice;
-  const int s_end = min(s_beg + a.per_slice, a.s0 + a.count);
+  const int ns = min(a.per_slice, a.s0 + a.count - s_beg);
+  if ((int)threadIdx.x < ns) {
+    const int s = s_beg + threadIdx.x;
+    const int j = a.jlist[s];
+    sp[threadIdx.x] = a.pos[j];
+    float w = 1.f;
+    if constexpr (OP == PrbOp::AlphaWeighted) w = a.alpha[s].y;
+    if constexpr (OP == PrbOp::Gradient) w = 2.f;
+    sw[threadIdx.x] = w;
+    ss[threadIdx.x] = a.src_by_pattern ? j : s;
+  }
+  __syncthreads();
   const int v = W::col(rblk);
   const int u0 = W::row0(rblk);
   float2 num[K][RB];
@@ -187,13 +206,19 @@ __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) num[k][i] = make_float2(0.f, 0.f);
   }
-  for (int s = s_beg; s < s_end; ++s) {
-    const int j = a.jlist[s];
-    const PosInfo p = a.pos[j];
-    float w = 1.f;
-    if constexpr (OP == PrbOp::AlphaWeighted) w = a.alpha[s].y;
-    if constexpr (OP == PrbOp::Gradient) w = 2.f;
-    const float2* src = a.src + (size_t)(a.src_by_pattern ? j : s) * K * N * N + u0 * N + v;
+  float2 cur[K][RB], nxt[K][RB];
+  auto load_src = [&](int m, float2 (&x)[K][RB]) {
+    const float2* src = a.src + (size_t)ss[m] * K * N * N + u0 * N + v;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < RB; ++i) x[k][i] = src[(size_t)k * N * N + i * N];
+  };
+  if (ns > 0) load_src(0, cur);
+  for (int m = 0; m < ns; ++m) {
+    if (m + 1 < ns) load_src(m + 1, nxt);
+    const PosInfo p = sp[m];
+    const float w = sw[m];
     const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
     float2 top = obj_hrow(a.obj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
 #pragma unroll
@@ -204,8 +229,12 @@ __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
       if constexpr (OP == PrbOp::Plain) den[i] += cabs2(o);
       const float2 ow = w * o;
 #pragma unroll
-      for (int k = 0; k < K; ++k) num[k][i] = num[k][i] + cconjmul(ow, src[(size_t)k * N * N + i * N]);
+      for (int k = 0; k < K; ++k) num[k][i] = num[k][i] + cconjmul(ow, cur[k][i]);
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < RB; ++i) cur[k][i] = nxt[k][i];
   }
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
@@ -266,27 +295,11 @@ __global__ __launch_bounds__(256) void k_probe_apply(ProbeApplyArgs a) {
 // ---------------------------------------------------------------------------
 template <int N>
 struct LsqPix {
-  static constexpr int RB = (N * N >= 2048) ? 8 : 4;
+  static constexpr int RB = 4;          // rows per thread
+  static constexpr int M = 8;           // positions per block
   using W = ColWalk<N, RB>;
   static constexpr int NRB = W::BLOCKS;
 };
-
-// Deterministic block sum of NV doubles over 256 threads; valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum_n(double (&v)[NV], double* sh /* NV * 4 */) {
-#pragma unroll
-  for (int i = 0; i < NV; ++i)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) sh[i * 4 + wid] = v[i];
-  __syncthreads();
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = sh[i * 4] + sh[i * 4 + 1] + sh[i * 4 + 2] + sh[i * 4 + 3];
-}
 
 // Object taps O[r][c0], O[r][c0 + 1] for the position derivatives, zero past
 // the object's last row or column (only a patch at an integer position on the
@@ -332,81 +345,119 @@ __global__ __launch_bounds__(256) void k_lsq_planes(const float2* probe, const f
 // With POS, four more for the position refinement: with g = d(S O)/dy (and
 // likewise x) and d psi_k = P_k g, Re sum_k conj(d psi_k) chi_k =
 // Re conj(g) sum_k conj(P_k) chi_k and sum_k |d psi_k|^2 = |g|^2 sum_k |P_k|^2.
+// A block takes one row band of M positions: the probe planes of its pixels
+// (sum_k |P_k|^2, sum_k conj(P_k) dP_k, sum_k |dP_k|^2 and dP_k) are read
+// once into registers and serve all M; the positions come from LDS.  Each
+// wavefront reduces its sums with lane shuffles; the four wavefronts' sums are
+// added in a fixed order at the end.
 template <int N, int K, bool PROBE_ON, bool POS>
 __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
   using W = typename LsqPix<N>::W;
-  constexpr int RB = LsqPix<N>::RB;
+  constexpr int RB = LsqPix<N>::RB, M = LsqPix<N>::M;
   constexpr int NV = POS ? 9 : 5;
-  const int b = blockIdx.y, rblk = blockIdx.x;
-  __shared__ double red[NV * 4];
-  const int j = a.jlist[b];
-  const PosInfo p = a.pos[j];
+  constexpr int KP = PROBE_ON ? K : 1;
+  __shared__ PosInfo sp[M];
+  __shared__ double red[M][4][NV];
+  const int rblk = blockIdx.x, b0 = blockIdx.y * M;
+  const int nb = min(M, a.count - b0);
+  if ((int)threadIdx.x < nb) sp[threadIdx.x] = a.pos[a.jlist[b0 + threadIdx.x]];
   const int v = W::col(rblk);
   const int u0 = W::row0(rblk);
-  const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
-  float m00 = 0.f, m11 = 0.f, m01 = 0.f, v0 = 0.f, v1 = 0.f;
-  float ny = 0.f, nx = 0.f, gyy = 0.f, gxx = 0.f;
-  float2 dtop = obj_hrow(a.dobj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
-  float2 otop = make_float2(0.f, 0.f);
-  if constexpr (PROBE_ON) otop = obj_hrow(a.obj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
-  float2 ta = make_float2(0.f, 0.f), tb = make_float2(0.f, 0.f);
-  if constexpr (POS) obj_taps(a.obj, a.h, a.w, p.iy + u0, p.ix + v, ta, tb);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float pint[RB], dint[RB];
+  float2 pq[RB], dp[KP][RB];
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
     const int q = (u0 + i) * N + v;
-    const float2 dbot = obj_hrow(a.dobj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
-    const float2 dob = make_float2(wy0 * dtop.x + wy1 * dbot.x, wy0 * dtop.y + wy1 * dbot.y);
-    dtop = dbot;
-    const float2 cb = a.contrib[(size_t)b * N * N + q];
-    m00 += cabs2(dob) * a.pint[q];
-    v0 += dob.x * cb.x + dob.y * cb.y;
-    if constexpr (POS) {
-      float2 ba, bb;
-      obj_taps(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, ba, bb);
-      // d/dy: bottom minus top row, each interpolated along x;
-      // d/dx: right minus left tap, interpolated along y
-      const float2 gy = make_float2(wx0 * (ba.x - ta.x) + wx1 * (bb.x - tb.x), wx0 * (ba.y - ta.y) + wx1 * (bb.y - tb.y));
-      const float2 gx = make_float2(wy0 * (tb.x - ta.x) + wy1 * (bb.x - ba.x), wy0 * (tb.y - ta.y) + wy1 * (bb.y - ba.y));
-      ta = ba;
-      tb = bb;
-      const float pi = a.pint[q];
-      ny += gy.x * cb.x + gy.y * cb.y;
-      nx += gx.x * cb.x + gx.y * cb.y;
-      gyy += cabs2(gy) * pi;
-      gxx += cabs2(gx) * pi;
-    }
+    pint[i] = a.pint[q];
     if constexpr (PROBE_ON) {
-      const float2 obot = obj_hrow(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
-      const float2 ob = make_float2(wy0 * otop.x + wy1 * obot.x, wy0 * otop.y + wy1 * obot.y);
-      otop = obot;
-      m11 += cabs2(ob) * a.dint[q];
-      const float2 pq = a.pq[q];
-      const float2 dc = cconjmul(dob, ob);  // conj(S dO) S O
-      m01 += dc.x * pq.x - dc.y * pq.y;     // Re(dc * pq)
-      float2 t = make_float2(0.f, 0.f);
+      dint[i] = a.dint[q];
+      pq[i] = a.pq[q];
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        t = t + cconjmul(a.dprobe[(size_t)k * N * N + q], a.chi[((size_t)b * K + k) * N * N + q]);
-      v1 += ob.x * t.x + ob.y * t.y;        // Re(conj(S O) t)
+      for (int k = 0; k < K; ++k) dp[k][i] = a.dprobe[(size_t)k * N * N + q];
     }
   }
-  double s[NV];
-  s[0] = m00;
-  s[1] = m11;
-  s[2] = m01;
-  s[3] = v0;
-  s[4] = v1;
-  if constexpr (POS) {
-    s[5] = ny;
-    s[6] = nx;
-    s[7] = gyy;
-    s[8] = gxx;
-  }
-  block_sum_n<NV>(s, red);
-  if (threadIdx.x == 0) {
-    double* o = a.part + ((size_t)b * LsqPix<N>::NRB + rblk) * NV;
+  __syncthreads();
+  for (int mi = 0; mi < nb; ++mi) {
+    const int b = b0 + mi;
+    const PosInfo p = sp[mi];
+    const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
+    float m00 = 0.f, m11 = 0.f, m01 = 0.f, v0 = 0.f, v1 = 0.f;
+    float ny = 0.f, nx = 0.f, gyy = 0.f, gxx = 0.f;
+    float2 cb[RB], ch[KP][RB];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) o[i] = s[i];
+    for (int i = 0; i < RB; ++i) {
+      const int q = (u0 + i) * N + v;
+      cb[i] = a.contrib[(size_t)b * N * N + q];
+      if constexpr (PROBE_ON) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) ch[k][i] = a.chi[((size_t)b * K + k) * N * N + q];
+      }
+    }
+    float2 dtop = obj_hrow(a.dobj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
+    float2 otop = make_float2(0.f, 0.f);
+    if constexpr (PROBE_ON) otop = obj_hrow(a.obj, a.h, a.w, p.iy + u0, p.ix + v, wx0, wx1);
+    float2 ta = make_float2(0.f, 0.f), tb = make_float2(0.f, 0.f);
+    if constexpr (POS) obj_taps(a.obj, a.h, a.w, p.iy + u0, p.ix + v, ta, tb);
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const float2 dbot = obj_hrow(a.dobj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
+      const float2 dob = make_float2(wy0 * dtop.x + wy1 * dbot.x, wy0 * dtop.y + wy1 * dbot.y);
+      dtop = dbot;
+      m00 += cabs2(dob) * pint[i];
+      v0 += dob.x * cb[i].x + dob.y * cb[i].y;
+      if constexpr (POS) {
+        float2 ba, bb;
+        obj_taps(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, ba, bb);
+        // d/dy: bottom minus top row, each interpolated along x;
+        // d/dx: right minus left tap, interpolated along y
+        const float2 gy = make_float2(wx0 * (ba.x - ta.x) + wx1 * (bb.x - tb.x), wx0 * (ba.y - ta.y) + wx1 * (bb.y - tb.y));
+        const float2 gx = make_float2(wy0 * (tb.x - ta.x) + wy1 * (bb.x - ba.x), wy0 * (tb.y - ta.y) + wy1 * (bb.y - ba.y));
+        ta = ba;
+        tb = bb;
+        ny += gy.x * cb[i].x + gy.y * cb[i].y;
+        nx += gx.x * cb[i].x + gx.y * cb[i].y;
+        gyy += cabs2(gy) * pint[i];
+        gxx += cabs2(gx) * pint[i];
+      }
+      if constexpr (PROBE_ON) {
+        const float2 obot = obj_hrow(a.obj, a.h, a.w, p.iy + u0 + i + 1, p.ix + v, wx0, wx1);
+        const float2 ob = make_float2(wy0 * otop.x + wy1 * obot.x, wy0 * otop.y + wy1 * obot.y);
+        otop = obot;
+        m11 += cabs2(ob) * dint[i];
+        const float2 dc = cconjmul(dob, ob);  // conj(S dO) S O
+        m01 += dc.x * pq[i].x - dc.y * pq[i].y;   // Re(dc * pq)
+        float2 t = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < K; ++k) t = t + cconjmul(dp[k][i], ch[k][i]);
+        v1 += ob.x * t.x + ob.y * t.y;        // Re(conj(S O) t)
+      }
+    }
+    double sv[NV];
+    sv[0] = m00;
+    sv[1] = m11;
+    sv[2] = m01;
+    sv[3] = v0;
+    sv[4] = v1;
+    if constexpr (POS) {
+      sv[5] = ny;
+      sv[6] = nx;
+      sv[7] = gyy;
+      sv[8] = gxx;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sv[i] += __shfl_down(sv[i], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) red[mi][wid][i] = sv[i];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * NV; t += 256) {
+    const int mi = t / NV, i = t % NV;
+    a.part[((size_t)(b0 + mi) * LsqPix<N>::NRB + rblk) * NV + i] =
+        red[mi][0][i] + red[mi][1][i] + red[mi][2][i] + red[mi][3][i];
   }
 }
 
@@ -896,6 +947,12 @@ int probe_acc_blocks(int n) {
 // quarter of the source traffic. (Above 512 blocks the longer per-block
 // loops win: at 256 x 256 x 3 in groups of 500, 16 patterns per slice take
 // 10% longer than 32.)
+int lsq_row_blocks(int n) {
+  int b = 0;
+  dispatch_n(n, [&](auto nc) { b = LsqPix<decltype(nc)::value>::NRB; });
+  return b;
+}
+
 int probe_per_slice(int n, int count) {
   const int b = probe_acc_blocks(n);
   int per = 32;
@@ -912,6 +969,7 @@ int probe_slices_max(int n, int count) {
 
 void launch_probe_acc(const ProbeAccArgs& a, PrbOp op) {
   if (a.count <= 0) return;
+  if (a.per_slice < 1 || a.per_slice > kProbeSliceMax) throw std::runtime_error("probe_acc: slice size out of range");
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
     const dim3 grid(ProbePix<N>::W::BLOCKS, probe_slices(a.count, a.per_slice));
@@ -950,7 +1008,7 @@ void launch_lsq_steps(const LsqStepArgs& a) {
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
     nrb = LsqPix<N>::NRB;
-    const dim3 grid(LsqPix<N>::NRB, a.count);
+    const dim3 grid(LsqPix<N>::NRB, (a.count + LsqPix<N>::M - 1) / LsqPix<N>::M);
     if (a.shift) {
       if (a.probe_on)
         k_lsq_sums<N, K, true, true><<<grid, 256, 0, a.stream>>>(a);
