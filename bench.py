@@ -713,6 +713,86 @@ def positions_leg(args, torch) -> dict:
     }
 
 
+def strips_leg(args, torch) -> dict:
+    """The 256 x 256, 3-mode, 2,500-position workload split by row into strips
+    (one GPU's share each in a multi-GPU run), run one strip after another on
+    this GPU with the halo and probe messages exchanged, against one context:
+    time per iteration, each strip's share, and the bytes the exchange sends
+    (what RCCL would carry over xGMI)."""
+    from paper_2202_03144_amd import Plan
+    from paper_2202_03144_amd.plan import Domains
+
+    wl, obj_true, probe, pos, counts = make_inputs(torch)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    o0 = np.ones((wl.h, wl.w), np.complex64)
+    iters = args.strip_iters
+    out = {}
+    for algo, prm in (("dm", dict(probe_update_start=0)), ("lsqml", dict(probe_update_start=0, lsqml_batch=500))):
+        pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
+        pl.load_patterns(counts)
+        pl.load_positions(pos)
+        pl.set_object(o0)
+        pl.set_probe(probe)
+        dd = Domains(wl.n, wl.k, pos, (wl.h, wl.w), args.strips, stream=stream)
+        dd.load_patterns(counts)
+        dd.set_object(o0)
+        dd.set_probe(probe)
+        res = {}
+        for name, h in (("one_context", pl), ("strips", dd)):
+            h.iterate(algo, 1, **prm)
+            h.sync()
+            t0 = time.perf_counter()
+            h.iterate(algo, iters, **prm)
+            h.sync()
+            res[name] = (time.perf_counter() - t0) * 1e3 / iters
+        h0, p0 = dd.traffic()
+        dd.iterate(algo, 1, **prm)
+        dd.sync()
+        h1, p1 = dd.traffic()
+        pl.iterate(algo, 1, **prm)
+        info = [dd.strip(s) for s in range(args.strips)]
+        ref = pl.object()
+        rel = float(np.linalg.norm(dd.object() - ref) / np.linalg.norm(ref))
+        # the same iterations of one context from a start perturbed by 1e-7
+        # (relative, seeded): how far rounding-level differences grow
+        rng = np.random.default_rng(11)
+        o1 = (o0 * (1 + 1e-7 * rng.standard_normal(o0.shape))).astype(np.complex64)
+        pl.set_object(o1)
+        pl.set_probe(probe)
+        pl.iterate(algo, iters + 2, **prm)
+        pl.sync()
+        sens = float(np.linalg.norm(pl.object() - ref) / np.linalg.norm(ref))
+        pl.close()
+        dd.close()
+        halo_iter, probe_iter = h1 - h0, p1 - p0
+        borders = max(1, args.strips - 1)
+        out[algo] = {
+            "ms_per_iter_one_context": round(res["one_context"], 3),
+            "ms_per_iter_all_strips": round(res["strips"], 3),
+            "ms_per_strip_share": round(res["strips"] / args.strips, 3),
+            "halo_bytes_per_iter": halo_iter, "probe_message_bytes_per_iter": probe_iter,
+            "halo_bytes_per_border_per_iter": halo_iter // borders,
+            "strip_rows_held": [s["hi"] - s["lo"] for s in info],
+            "strip_rows_owned": [s["own_hi"] - s["own_lo"] for s in info],
+            "strip_positions": [s["positions"] for s in info],
+            "iterations": iters + 2,
+            "object_rel_strips_vs_one_context": rel,
+            "object_rel_one_context_vs_1e-7_perturbed_start": sens,
+        }
+        log(f"{algo}: {out[algo]}")
+    return {
+        "metric": "strip decomposition on one GPU: ms per iteration and exchanged bytes",
+        "value": out["dm"]["ms_per_strip_share"], "unit": "ms per strip share (DM)", "n_gpus": 1,
+        "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"256x256 probe, 3 modes, 2,500-point Fermat spiral, 1700x1700 object, Poisson 1e8; "
+                               f"{args.strips} row strips of equal position count, run one after another; "
+                               f"{iters} iterations each of DM and LSQML (groups of 500), host-timed",
+                   "n": wl.n, "modes": wl.k, "positions": wl.j, "strips": args.strips},
+        **out,
+    }
+
+
 def poisson_leg(args, torch) -> dict:
     """LSQML on the 256 x 256, 3-mode, 2,500-position workload with the
     modulus-projection (amplitude) and the Poisson exit-wave updates, from a
@@ -816,6 +896,10 @@ def main() -> int:
                     help="instead: LSQML from nominal positions with and without position refinement")
     ap.add_argument("--position-iters", type=int, default=30)
     ap.add_argument("--position-start", type=int, default=3)
+    ap.add_argument("--strips", type=int, default=0,
+                    help="instead: the production workload split into this many row strips (one GPU's share "
+                         "each), against one context")
+    ap.add_argument("--strip-iters", type=int, default=5)
     ap.add_argument("--poisson", action="store_true",
                     help="LSQML with the amplitude and the Poisson exit-wave updates on the production workload")
     ap.add_argument("--poisson-iters", type=int, default=30)
@@ -852,6 +936,9 @@ def main() -> int:
         return 0
     if args.poisson:
         print(json.dumps(poisson_leg(args, torch)), flush=True)
+        return 0
+    if args.strips:
+        print(json.dumps(strips_leg(args, torch)), flush=True)
         return 0
     if args.listing1:
         print(json.dumps(listing1_leg(args, torch)), flush=True)

@@ -469,6 +469,56 @@ const char* pty_batch_last_error(const pty_batch* b); /* never NULL */
 pty_status pty_autotune(pty_ctx* ctx, pty_algo algo, const pty_iter_params* prm, const char* cache_path,
                         int32_t* chunk);
 
+/* ------------------------------------------------------------------------
+ * Strip decomposition (the paper's multi-GPU mode splits the scan into
+ * sub-regions that overlap by a given size, Sec. 1 and Sec. 2.2).  DM and
+ * LSQML, whose updates sum over positions, are decomposed exactly: the
+ * positions are divided by row into `strips` groups of equal count, each held
+ * by a context of its own (one GPU's share in a multi-GPU run) with the object
+ * rows its patches touch.  Every object row has one owning strip.  Wherever
+ * an iteration sums over positions, each strip sums its own and the partial
+ * sums are exchanged: object numerator and denominator rows held by several
+ * strips go to their owner as packed halo messages (added in strip order) and
+ * come back as totals; the probe numerator and denominator of every strip
+ * are packed into one message and summed over the strips (an all-reduce);
+ * the maxima behind the regularisers and the amplitude error likewise.  The
+ * result equals one context's iteration up to the order of the sums.  On one
+ * GPU the strips run one after another on one stream.
+ * ---------------------------------------------------------------------- */
+typedef struct pty_domains pty_domains;
+
+/* plan: the whole scan (n, modes, n_pos, obj_h, obj_w, device, stream;
+ * flags 0); yx: its n_pos x 2 float64 top-left corners (host), as for
+ * pty_load_positions; strips: 1..16, at most n_pos.  *out is set only on
+ * success. */
+pty_status pty_domains_create(const pty_plan_desc* plan, const double* yx, int32_t strips, pty_domains** out);
+/* Counts of the whole scan (n_pos x N x N float32, centred), host or device;
+ * each strip keeps its patterns'.  Synchronises. */
+pty_status pty_domains_load_patterns(pty_domains* d, const float* counts, int on_device);
+/* Whole object (obj_h x obj_w complex64) and probe (modes x N x N), host or
+ * device; each strip keeps its rows of the object and a copy of the probe. */
+pty_status pty_domains_set_object(pty_domains* d, const void* obj, int on_device);
+pty_status pty_domains_set_probe(pty_domains* d, const void* probe, int on_device);
+/* n_iter iterations of PTY_DM or PTY_LSQML with the parameters of
+ * pty_iterate (flags 0, no position refinement; else PTY_E_UNSUPPORTED;
+ * ePIE is sequential and is not decomposed).  Asynchronous. */
+pty_status pty_domains_iterate(pty_domains* d, pty_algo algo, int32_t n_iter, const pty_iter_params* prm);
+/* The whole object assembled from the owned rows of every strip, the probe
+ * (identical in every strip), and the amplitude error of every iteration
+ * over all positions, as pty_get_object / pty_get_probe / pty_get_errors. */
+pty_status pty_domains_get_object(pty_domains* d, void* out, int on_device);
+pty_status pty_domains_get_probe(pty_domains* d, void* out, int on_device);
+pty_status pty_domains_get_errors(pty_domains* d, double* out, int32_t cap, int32_t* n_written);
+/* Strip s: info[0..4] = first and one-past-last object row it holds, first
+ * and one-past-last row it owns, number of positions. */
+pty_status pty_domains_strip(const pty_domains* d, int32_t s, int32_t* info);
+/* Bytes sent so far in halo messages (both directions) and in probe messages
+ * (one per strip and all-reduce). */
+pty_status pty_domains_traffic(const pty_domains* d, uint64_t* halo_bytes, uint64_t* probe_bytes);
+pty_status pty_domains_sync(pty_domains* d);
+void pty_domains_destroy(pty_domains* d);                  /* NULL-safe */
+const char* pty_domains_last_error(const pty_domains* d); /* never NULL */
+
 #ifdef __cplusplus
 }
 #endif

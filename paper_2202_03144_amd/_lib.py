@@ -85,6 +85,19 @@ SIGNATURES = {
                                    C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pty_nll_forward_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_void_p]),
+    "pty_domains_create": (C.c_int, [C.POINTER(PlanDesc), C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "pty_domains_load_patterns": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_domains_set_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_domains_set_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_domains_iterate": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(IterParams)]),
+    "pty_domains_get_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_domains_get_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pty_domains_get_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "pty_domains_strip": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "pty_domains_traffic": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "pty_domains_sync": (C.c_int, [C.c_void_p]),
+    "pty_domains_destroy": (None, [C.c_void_p]),
+    "pty_domains_last_error": (C.c_char_p, [C.c_void_p]),
     "pty_model_error": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pty_set_truth": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_float]),
     "pty_nrmse": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),

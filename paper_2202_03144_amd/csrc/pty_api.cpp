@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -2141,5 +2142,602 @@ pty_status pty_batch_sync(pty_batch* b) {
 void pty_batch_destroy(pty_batch* b) { delete b; }
 
 const char* pty_batch_last_error(const pty_batch* b) { return b ? b->err.c_str() : g_tls_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Strip decomposition of DM and LSQML (the multi-GPU layout of Sec. 1 and
+// Sec. 2.2's overlap between sub-regions, shown on one GPU)
+// ---------------------------------------------------------------------------
+// The positions are split by their row into strips of equal counts; each strip
+// is a context of its own holding the object rows its patches touch.  Every
+// global object row has one owning strip (the owned ranges partition the
+// object).  Wherever the method sums over positions, each strip sums its own;
+// the object-plane sums are completed by halo messages (strip -> owner, added
+// in strip order, then owner -> strip, copied), the probe sums by an
+// all-reduce of one packed message per strip, the maxima behind the
+// regularisers and the error by the same exchange.  On several GPUs each
+// message would be one RCCL send/receive or all-reduce; here the strips run
+// one after another on one stream.
+struct pty_domains {
+  int S = 0, N = 0, K = 0, J = 0, H = 0, W = 0, device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<pty_ctx*> sub;
+  std::vector<int> lo, hi, own_lo, own_hi;   // local and owned global rows [lo, hi)
+  std::vector<std::vector<int>> jmap;        // strip -> global pattern indices, ascending
+  std::vector<int*> d_jmap;
+  struct Seg {
+    int src, dst, a, b;   // global rows [a, b) of src's local rows owned by dst
+  };
+  std::vector<Seg> segs;
+  std::vector<void*> allocs;
+  float* msg = nullptr;                      // halo message staging
+  std::vector<float*> pmsg;                  // one probe message per strip
+  float* ptot = nullptr;                     // summed probe message
+  size_t pwords = 0;
+  double* errp_all = nullptr;                // J x column blocks x 2, by global pattern
+  double* err_dev = nullptr;
+  int err_cap = 0;
+  int* iter_dev = nullptr;
+  unsigned* dmax = nullptr;
+  std::vector<float2*> num2;                 // per strip: LSQML update numerator
+  std::vector<std::vector<Group>> groups;    // per strip: LSQML groups (global j mod G)
+  int groups_batch = -1;
+  int iter = 0;
+  size_t halo_bytes = 0, probe_bytes = 0;    // sent so far
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw NoMemError(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    }
+    allocs.push_back(p);
+    return p;
+  }
+  ~pty_domains() {
+    for (size_t s = 0; s < sub.size(); ++s) {
+      if (s < groups.size())
+        for (auto& g : groups[s]) free_group(sub[s], g);
+      pty_destroy(sub[s]);
+    }
+    for (void* p : allocs) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+template <typename F>
+pty_status guarded_d(pty_domains* d, F&& f) {
+  const pty_status st = guarded(nullptr, std::forward<F>(f));
+  if (st != PTY_OK && d) d->err = g_tls_error;
+  return st;
+}
+
+void dd_check_sub(pty_domains* d, int s, pty_status st) {
+  if (st == PTY_OK) return;
+  const std::string m = "strip " + std::to_string(s) + ": " + pty_last_error(d->sub[s]);
+  switch (st) {
+    case PTY_E_INVALID: throw InvalidArg(m);
+    case PTY_E_STATE: throw StateError(m);
+    case PTY_E_NOMEM: throw NoMemError(m);
+    case PTY_E_UNSUPPORTED: throw Unsupported(m);
+    default: throw DeviceError(m);
+  }
+}
+
+// Object-plane halos: partial sums of rows held by several strips go to the
+// rows' owner, which adds them in strip order; the totals go back.  Planes:
+// p0 (w0 words per row) and optionally p1 (w1 words per row), one message.
+void dd_halo(pty_domains* d, const std::vector<float*>& p0, int w0, const std::vector<float*>& p1, int w1) {
+  for (int pass = 0; pass < 2; ++pass) {
+    for (const auto& g : d->segs) {
+      const int from = pass == 0 ? g.src : g.dst, to = pass == 0 ? g.dst : g.src;
+      const int rows = g.b - g.a;
+      HaloPlanes a{{p0[from], w1 ? p1[from] : nullptr}, {w0, w1}, g.a - d->lo[from]};
+      HaloPlanes b{{p0[to], w1 ? p1[to] : nullptr}, {w0, w1}, g.a - d->lo[to]};
+      launch_halo_pack(a, rows, d->msg, d->stream);
+      launch_halo_unpack(b, rows, d->msg, pass == 0, d->stream);
+      d->halo_bytes += size_t(rows) * (w0 + w1) * sizeof(float);
+    }
+  }
+}
+
+// All-reduce of the probe sums: every strip's numerator (K x N x N complex)
+// and, with den, its denominator (N x N) are packed into one message; the
+// messages are summed in strip order and copied back into every strip.  With
+// den, the maximum of the summed denominator goes to every strip's slot 1.
+void dd_probe_allreduce(pty_domains* d, bool num2, bool with_den) {
+  const size_t nn = size_t(d->N) * d->N;
+  const int wn = int(2 * d->K * nn), wd = with_den ? int(nn) : 0;
+  std::vector<const float*> m(d->S);
+  for (int s = 0; s < d->S; ++s) {
+    pty_ctx* c = d->sub[s];
+    HaloPlanes a{{reinterpret_cast<float*>(num2 ? c->num_p2 : c->num_p), c->den_p}, {wn, wd}, 0};
+    launch_halo_pack(a, 1, d->pmsg[s], d->stream);
+    m[s] = d->pmsg[s];
+    d->probe_bytes += size_t(wn + wd) * sizeof(float);
+  }
+  launch_sum_messages(m.data(), d->S, size_t(wn + wd), d->ptot, d->stream);
+  for (int s = 0; s < d->S; ++s) {
+    pty_ctx* c = d->sub[s];
+    HaloPlanes b{{reinterpret_cast<float*>(num2 ? c->num_p2 : c->num_p), c->den_p}, {wn, wd}, 0};
+    launch_halo_unpack(b, 1, d->ptot, false, d->stream);
+  }
+  if (with_den) {
+    launch_fill_u32(d->dmax, 1, 0u, d->stream);
+    launch_plane_max(d->ptot + wn, nn, d->dmax, d->stream);
+    for (pty_ctx* c : d->sub)
+      PTY_HIP(hipMemcpyAsync(c->scal + 1, d->dmax, sizeof(unsigned), hipMemcpyDeviceToDevice, d->stream));
+  }
+}
+
+// After the halo exchange every strip holds complete object denominators on
+// its rows: their overall maximum goes to every strip's slot 0.
+void dd_den_max(pty_domains* d) {
+  launch_fill_u32(d->dmax, 1, 0u, d->stream);
+  for (pty_ctx* c : d->sub) launch_plane_max(c->den, size_t(c->H) * c->W, d->dmax, d->stream);
+  for (pty_ctx* c : d->sub)
+    PTY_HIP(hipMemcpyAsync(c->scal, d->dmax, sizeof(unsigned), hipMemcpyDeviceToDevice, d->stream));
+}
+
+// Object numerator (raw gather of the contribution planes: plain, or weighted
+// by the step lengths) and, with den, the denominator, over group g of strip c.
+void dd_object_sums(pty_ctx* c, const Group& g, float2* num, ObjOp op, bool with_den) {
+  const size_t hw = size_t(c->H) * c->W;
+  if (with_den) {
+    launch_probe_intensity(c->probe, c->pint, c->N, c->K, c->stream);
+    launch_fill_u32(reinterpret_cast<unsigned*>(c->den), hw, 0u, c->stream);
+    launch_fill_u32(c->scal, 1, 0u, c->stream);
+    ObjGatherArgs o = obj_args(c, g);
+    launch_obj_gather(o, ObjOp::Density);
+  }
+  launch_fill_u32(reinterpret_cast<unsigned*>(num), hw * 2, 0u, c->stream);
+  ObjGatherArgs o = obj_args(c, g);
+  o.out = num;
+  launch_obj_gather(o, op);
+}
+
+std::vector<float*> dd_planes(pty_domains* d, const std::function<void*(int)>& f) {
+  std::vector<float*> v(d->S);
+  for (int s = 0; s < d->S; ++s) v[s] = static_cast<float*>(f(s));
+  return v;
+}
+
+void dd_ensure_err(pty_domains* d, int n_iter) {
+  if (!d->iter_dev) {
+    d->iter_dev = static_cast<int*>(d->dalloc(sizeof(int)));
+    launch_set_i32(d->iter_dev, d->iter, d->stream);
+  }
+  if (d->err_dev && d->iter + n_iter <= d->err_cap) return;
+  int cap = std::max(256, d->err_cap);
+  while (cap < d->iter + n_iter) cap *= 2;
+  double* nb = static_cast<double*>(d->dalloc(sizeof(double) * cap));
+  if (d->err_dev && d->iter > 0)
+    PTY_HIP(hipMemcpyAsync(nb, d->err_dev, sizeof(double) * d->iter, hipMemcpyDeviceToDevice, d->stream));
+  d->err_dev = nb;   // the old buffer stays in allocs until destroy
+  d->err_cap = cap;
+}
+
+void dd_end_iteration(pty_domains* d) {
+  const int cb = col_blocks(d->N, d->K);
+  for (int s = 0; s < d->S; ++s)
+    launch_err_scatter(d->sub[s]->errp, d->d_jmap[s], d->sub[s]->J, 2 * cb, d->errp_all, d->stream);
+  launch_err_reduce(d->errp_all, d->J * cb, d->err_dev, d->stream, d->iter_dev, true);
+  d->iter++;
+  for (pty_ctx* c : d->sub) c->iter = d->iter;
+}
+
+void dd_dm(pty_domains* d, int n_iter, const pty_iter_params& p) {
+  const float g_obj = p.gamma_obj < 0 ? 1e-6f : p.gamma_obj;
+  const float g_prb = p.gamma_probe < 0 ? 1e-6f : p.gamma_probe;
+  for (pty_ctx* c : d->sub) {
+    const int chunk = chunk_patterns(c, p);
+    ensure_all_group(c);
+    ensure_common(c, std::min(chunk, c->J), c->J);
+    c->ensure_once(c->psi, size_t(c->J) * c->K * c->N * c->N);
+    c->ensure_once(c->dobj, size_t(c->H) * c->W);
+    ensure_probe_parts(c, c->J);
+    if (!c->dm_valid) {
+      DmInitArgs di{};
+      di.n = c->N;
+      di.k = c->K;
+      di.obj = c->obj;
+      di.h = c->H;
+      di.w = c->W;
+      di.probe = c->probe;
+      di.pos = c->pos;
+      di.j = c->J;
+      di.psi = c->psi;
+      di.contrib = c->contrib;
+      di.stream = c->stream;
+      launch_dm_init(di);
+      c->dm_valid = true;
+    }
+  }
+  dd_ensure_err(d, n_iter);
+  const auto num = dd_planes(d, [&](int s) { return (void*)d->sub[s]->dobj; });
+  const auto den = dd_planes(d, [&](int s) { return (void*)d->sub[s]->den; });
+  for (int it = 0; it < n_iter; ++it) {
+    const bool pon = probe_on(p, d->iter);
+    for (pty_ctx* c : d->sub) dd_object_sums(c, c->all, c->dobj, ObjOp::Gradient, true);
+    dd_halo(d, num, 2 * d->W, den, d->W);
+    dd_den_max(d);
+    for (pty_ctx* c : d->sub)
+      launch_obj_apply(c->dobj, c->den, c->scal, g_obj, 1.f, c->obj, nullptr, size_t(c->H) * c->W, ObjApply::Dm,
+                       c->stream);
+    if (pon) {
+      for (pty_ctx* c : d->sub) probe_reduce(c, c->all, c->psi, 1, PrbOp::Plain, c->num_p, true);
+      dd_probe_allreduce(d, false, true);
+      for (pty_ctx* c : d->sub) probe_apply(c, PrbApply::Dm, c->num_p, g_prb, 1.f);
+    }
+    for (pty_ctx* c : d->sub)
+      fourier_pass(c, c->all, 0, c->J, chunk_patterns(c, p), RowIn::DmReflect, ColOp::Project, RowOut::DmUpdate);
+    dd_end_iteration(d);
+  }
+}
+
+void dd_ensure_lsq_groups(pty_domains* d, int batch) {
+  if (d->groups_batch == batch) return;
+  const int G = std::max(1, (d->J + batch - 1) / batch);
+  for (int s = 0; s < d->S; ++s) {
+    for (auto& g : d->groups[s]) free_group(d->sub[s], g);
+    d->groups[s].assign(G, Group{});
+    for (int g = 0; g < G; ++g) {
+      std::vector<int> jl;
+      for (int l = 0; l < (int)d->jmap[s].size(); ++l)
+        if (d->jmap[s][l] % G == g) jl.push_back(l);
+      make_group(d->sub[s], d->groups[s][g], std::move(jl));
+    }
+  }
+  d->groups_batch = batch;
+}
+
+void dd_lsqml(pty_domains* d, int n_iter, const pty_iter_params& p) {
+  const float g_obj = p.gamma_obj < 0 ? 1e-3f : p.gamma_obj;
+  const float g_prb = p.gamma_probe < 0 ? 1e-3f : p.gamma_probe;
+  const int batch = p.lsqml_batch > 0 ? p.lsqml_batch : 512;
+  dd_ensure_lsq_groups(d, batch);
+  const size_t nn = size_t(d->N) * d->N;
+  for (int s = 0; s < d->S; ++s) {
+    pty_ctx* c = d->sub[s];
+    int bmax = 1;
+    for (auto& g : d->groups[s]) bmax = std::max(bmax, (int)g.jl.size());
+    const int chunk = chunk_patterns(c, p);
+    ensure_common(c, std::min(chunk, bmax), bmax);
+    c->ensure(c->chi, c->chi_slots, size_t(bmax) * c->K * nn);
+    c->ensure_once(c->dobj, size_t(c->H) * c->W);
+    c->ensure(c->alpha, c->alpha_slots, size_t(bmax));
+    c->ensure_once(c->alpha_by_j, size_t(c->J));
+    c->ensure_once(c->lsq_pq, nn);
+    c->ensure_once(c->lsq_dint, nn);
+    c->ensure(c->lsq_part, c->lsq_part_n, size_t(bmax) * lsq_row_blocks(c->N) * 5);
+    ensure_probe_parts(c, bmax);
+    if (!d->num2[s]) d->num2[s] = c->alloc<float2>(size_t(c->H) * c->W);
+    c->dm_valid = false;
+  }
+  dd_ensure_err(d, n_iter);
+  const auto dirp = dd_planes(d, [&](int s) { return (void*)d->sub[s]->dobj; });
+  const auto den = dd_planes(d, [&](int s) { return (void*)d->sub[s]->den; });
+  const auto upd = dd_planes(d, [&](int s) { return (void*)d->num2[s]; });
+  const int G = (int)d->groups[0].size();
+  for (int it = 0; it < n_iter; ++it) {
+    const bool pon = probe_on(p, d->iter);
+    for (int g = 0; g < G; ++g) {
+      // pass A: chi, the object direction and the probe direction
+      for (int s = 0; s < d->S; ++s) {
+        pty_ctx* c = d->sub[s];
+        const Group& grp = d->groups[s][g];
+        const int count = (int)grp.jl.size();
+        if (count > 0)
+          fourier_pass(c, grp, 0, count, chunk_patterns(c, p), RowIn::Plain, ColOp::Project, RowOut::StoreChi);
+        dd_object_sums(c, grp, c->dobj, ObjOp::Gradient, true);
+      }
+      dd_halo(d, dirp, 2 * d->W, den, d->W);
+      dd_den_max(d);
+      for (pty_ctx* c : d->sub)
+        launch_obj_apply(c->dobj, c->den, c->scal, g_obj, 1.f, nullptr, c->dobj, size_t(c->H) * c->W,
+                         ObjApply::LsqDirection, c->stream);
+      if (pon) {
+        for (int s = 0; s < d->S; ++s)
+          probe_reduce(d->sub[s], d->groups[s][g], d->sub[s]->chi, 0, PrbOp::Plain, d->sub[s]->num_p, true);
+        dd_probe_allreduce(d, false, true);
+        for (pty_ctx* c : d->sub) probe_apply(c, PrbApply::LsqDirection, c->num_p, g_prb, 1.f);
+      }
+      // pass B: per-position step lengths
+      for (int s = 0; s < d->S; ++s) {
+        pty_ctx* c = d->sub[s];
+        const Group& grp = d->groups[s][g];
+        LsqStepArgs ls{};
+        ls.n = c->N;
+        ls.k = c->K;
+        ls.obj = c->obj;
+        ls.dobj = c->dobj;
+        ls.h = c->H;
+        ls.w = c->W;
+        ls.probe = c->probe;
+        ls.dprobe = c->dprobe;
+        ls.chi = c->chi;
+        ls.contrib = c->contrib;
+        ls.pint = c->pint;
+        ls.pq = c->lsq_pq;
+        ls.dint = c->lsq_dint;
+        ls.jlist = grp.d_jl;
+        ls.pos = c->pos;
+        ls.count = (int)grp.jl.size();
+        ls.probe_on = pon ? 1 : 0;
+        ls.part = c->lsq_part;
+        ls.alpha = c->alpha;
+        ls.alpha_by_j = c->alpha_by_j;
+        ls.shift = nullptr;
+        ls.stream = c->stream;
+        launch_lsq_steps(ls);
+      }
+      // the step-weighted updates
+      if (pon) {
+        for (int s = 0; s < d->S; ++s)
+          probe_reduce(d->sub[s], d->groups[s][g], d->sub[s]->chi, 0, PrbOp::AlphaWeighted, d->sub[s]->num_p2,
+                       false);
+        dd_probe_allreduce(d, true, false);
+      }
+      for (int s = 0; s < d->S; ++s) dd_object_sums(d->sub[s], d->groups[s][g], d->num2[s], ObjOp::WeightedSum, false);
+      dd_halo(d, upd, 2 * d->W, {}, 0);
+      for (int s = 0; s < d->S; ++s) {
+        pty_ctx* c = d->sub[s];
+        launch_obj_apply(d->num2[s], c->den, c->scal, g_obj, p.beta_obj, c->obj, nullptr, size_t(c->H) * c->W,
+                         ObjApply::LsqUpdate, c->stream);
+      }
+      if (pon)
+        for (pty_ctx* c : d->sub) probe_apply(c, PrbApply::LsqUpdate, c->num_p2, g_prb, p.beta_probe);
+    }
+    dd_end_iteration(d);
+  }
+  for (pty_ctx* c : d->sub) c->den_valid = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+pty_status pty_domains_create(const pty_plan_desc* plan, const double* yx, int32_t strips, pty_domains** out) {
+  pty_domains* created = nullptr;
+  const pty_status st = guarded(nullptr, [&] {
+    require(plan != nullptr && yx != nullptr && out != nullptr, "pty_domains_create: null argument");
+    require(strips >= 1 && strips <= 16, "pty_domains_create: strips must be in 1..16");
+    require(plan->n_pos >= strips, "pty_domains_create: fewer positions than strips");
+    require(plan->flags == 0, "pty_domains_create: flags must be 0");
+    const int J = plan->n_pos, N = plan->n, H = plan->obj_h, W = plan->obj_w;
+    std::vector<int> iy(J), ey(J);
+    for (int j = 0; j < J; ++j) {
+      const double y = yx[2 * j], x = yx[2 * j + 1];
+      if (!(std::isfinite(y) && std::isfinite(x)) || y < 0 || x < 0)
+        throw InvalidArg("pty_domains_create: position " + std::to_string(j) + " is negative or not finite");
+      const double fy = std::floor(y);
+      iy[j] = (int)fy;
+      ey[j] = (int)fy + N + (y != fy ? 1 : 0);
+      if (ey[j] > H) throw InvalidArg("pty_domains_create: patch " + std::to_string(j) + " extends past the object");
+    }
+    std::unique_ptr<pty_domains> d(new pty_domains());
+    d->S = strips;
+    d->N = N;
+    d->K = plan->modes;
+    d->J = J;
+    d->H = H;
+    d->W = W;
+    d->device = plan->device;
+    PTY_HIP(hipSetDevice(plan->device));
+    if (plan->stream) {
+      d->stream = static_cast<hipStream_t>(plan->stream);
+    } else {
+      PTY_HIP(hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking));
+      d->own_stream = true;
+    }
+    // equal counts by row (stable in the pattern index), then ascending index per strip
+    std::vector<int> order(J);
+    for (int j = 0; j < J; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return yx[2 * a] < yx[2 * b]; });
+    d->jmap.resize(strips);
+    int at = 0;
+    for (int s = 0; s < strips; ++s) {
+      const int cnt = J / strips + (s < J % strips ? 1 : 0);
+      d->jmap[s].assign(order.begin() + at, order.begin() + at + cnt);
+      std::sort(d->jmap[s].begin(), d->jmap[s].end());
+      at += cnt;
+    }
+    std::vector<int> plo(strips), phi(strips);
+    for (int s = 0; s < strips; ++s) {
+      plo[s] = H;
+      phi[s] = 0;
+      for (int j : d->jmap[s]) {
+        plo[s] = std::min(plo[s], iy[j]);
+        phi[s] = std::max(phi[s], ey[j]);
+      }
+    }
+    d->own_lo.resize(strips);
+    d->own_hi.resize(strips);
+    d->lo.resize(strips);
+    d->hi.resize(strips);
+    for (int s = 0; s < strips; ++s) d->own_lo[s] = s == 0 ? 0 : std::max(d->own_lo[s - 1], plo[s]);
+    for (int s = 0; s < strips; ++s) d->own_hi[s] = s + 1 < strips ? d->own_lo[s + 1] : H;
+    for (int s = 0; s < strips; ++s) {
+      d->lo[s] = std::min(plo[s], d->own_lo[s]);
+      d->hi[s] = std::max({phi[s], d->own_hi[s], std::min(H, d->lo[s] + N + 1)});
+    }
+    for (int s = 0; s < strips; ++s)
+      for (int o = 0; o < strips; ++o) {
+        if (o == s) continue;
+        const int a = std::max(d->lo[s], d->own_lo[o]), b = std::min(d->hi[s], d->own_hi[o]);
+        if (a < b) d->segs.push_back({s, o, a, b});
+      }
+    std::stable_sort(d->segs.begin(), d->segs.end(),
+                     [](const pty_domains::Seg& x, const pty_domains::Seg& y) { return x.dst < y.dst; });
+    // one context per strip, all on the decomposition's stream
+    d->sub.assign(strips, nullptr);
+    d->d_jmap.assign(strips, nullptr);
+    d->num2.assign(strips, nullptr);
+    d->groups.resize(strips);
+    for (int s = 0; s < strips; ++s) {
+      pty_plan_desc sp = *plan;
+      sp.n_pos = (int)d->jmap[s].size();
+      sp.obj_h = d->hi[s] - d->lo[s];
+      sp.stream = d->stream;
+      dd_check_sub(d.get(), s, pty_create(&sp, &d->sub[s]));
+      std::vector<double> loc(2 * d->jmap[s].size());
+      for (size_t l = 0; l < d->jmap[s].size(); ++l) {
+        loc[2 * l] = yx[2 * d->jmap[s][l]] - d->lo[s];
+        loc[2 * l + 1] = yx[2 * d->jmap[s][l] + 1];
+      }
+      dd_check_sub(d.get(), s, pty_load_positions(d->sub[s], loc.data()));
+      d->d_jmap[s] = d->sub[s]->alloc<int>(d->jmap[s].size());
+      PTY_HIP(hipMemcpy(d->d_jmap[s], d->jmap[s].data(), sizeof(int) * d->jmap[s].size(), hipMemcpyHostToDevice));
+    }
+    size_t mrows = 1;
+    for (const auto& g : d->segs) mrows = std::max<size_t>(mrows, size_t(g.b - g.a));
+    d->msg = static_cast<float*>(d->dalloc(mrows * 3 * W * sizeof(float)));
+    d->pwords = size_t(2 * d->K + 1) * N * N;
+    for (int s = 0; s < strips; ++s) d->pmsg.push_back(static_cast<float*>(d->dalloc(d->pwords * sizeof(float))));
+    d->ptot = static_cast<float*>(d->dalloc(d->pwords * sizeof(float)));
+    d->errp_all = static_cast<double*>(d->dalloc(sizeof(double) * 2 * size_t(J) * col_blocks(N, d->K)));
+    d->dmax = static_cast<unsigned*>(d->dalloc(sizeof(unsigned)));
+    created = d.release();
+  });
+  if (st == PTY_OK) *out = created;
+  return st;
+}
+
+pty_status pty_domains_load_patterns(pty_domains* d, const float* counts, int on_device) {
+  return guarded_d(d, [&] {
+    require(d != nullptr && counts != nullptr, "pty_domains_load_patterns: null argument");
+    PTY_HIP(hipSetDevice(d->device));
+    const size_t nn = size_t(d->N) * d->N;
+    for (int s = 0; s < d->S; ++s) {
+      const auto& jm = d->jmap[s];
+      if (!on_device) {
+        std::vector<float> buf(jm.size() * nn);
+        for (size_t l = 0; l < jm.size(); ++l) std::memcpy(&buf[l * nn], counts + size_t(jm[l]) * nn, nn * sizeof(float));
+        dd_check_sub(d, s, pty_load_patterns(d->sub[s], buf.data(), 0));
+      } else {
+        float* tmp = d->sub[s]->alloc<float>(jm.size() * nn);
+        for (size_t l = 0; l < jm.size(); ++l)
+          PTY_HIP(hipMemcpyAsync(tmp + l * nn, counts + size_t(jm[l]) * nn, nn * sizeof(float),
+                                 hipMemcpyDeviceToDevice, d->stream));
+        const pty_status st = pty_load_patterns(d->sub[s], tmp, 1);
+        d->sub[s]->dfree(tmp);
+        dd_check_sub(d, s, st);
+      }
+    }
+  });
+}
+
+pty_status pty_domains_set_object(pty_domains* d, const void* obj, int on_device) {
+  return guarded_d(d, [&] {
+    require(d != nullptr && obj != nullptr, "pty_domains_set_object: null argument");
+    const float2* src = static_cast<const float2*>(obj);
+    for (int s = 0; s < d->S; ++s)
+      dd_check_sub(d, s, pty_set_object(d->sub[s], src + size_t(d->lo[s]) * d->W, on_device));
+  });
+}
+
+pty_status pty_domains_set_probe(pty_domains* d, const void* probe, int on_device) {
+  return guarded_d(d, [&] {
+    require(d != nullptr && probe != nullptr, "pty_domains_set_probe: null argument");
+    for (int s = 0; s < d->S; ++s) dd_check_sub(d, s, pty_set_probe(d->sub[s], probe, on_device));
+  });
+}
+
+pty_status pty_domains_iterate(pty_domains* d, pty_algo algo, int32_t n_iter, const pty_iter_params* prm) {
+  return guarded_d(d, [&] {
+    require(d != nullptr, "pty_domains_iterate: null argument");
+    require(n_iter >= 0, "pty_domains_iterate: negative iteration count");
+    pty_iter_params p;
+    if (prm)
+      p = *prm;
+    else
+      pty_default_params(&p);
+    if (algo != PTY_DM && algo != PTY_LSQML)
+      throw Unsupported("pty_domains_iterate: only DM and LSQML are decomposed (ePIE is sequential)");
+    if (p.flags != 0 || p.position_start >= 0)
+      throw Unsupported("pty_domains_iterate: no flags and no position refinement in the strip decomposition");
+    for (pty_ctx* c : d->sub) require_loaded(c);
+    PTY_HIP(hipSetDevice(d->device));
+    if (algo == PTY_DM)
+      dd_dm(d, n_iter, p);
+    else
+      dd_lsqml(d, n_iter, p);
+  });
+}
+
+pty_status pty_domains_get_object(pty_domains* d, void* out, int on_device) {
+  return guarded_d(d, [&] {
+    require(d != nullptr && out != nullptr, "pty_domains_get_object: null argument");
+    PTY_HIP(hipSetDevice(d->device));
+    float2* dst = static_cast<float2*>(out);
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int s = 0; s < d->S; ++s) {
+      const size_t rows = size_t(d->own_hi[s] - d->own_lo[s]);
+      if (!rows) continue;
+      PTY_HIP(hipMemcpyAsync(dst + size_t(d->own_lo[s]) * d->W,
+                             d->sub[s]->obj + size_t(d->own_lo[s] - d->lo[s]) * d->W, rows * d->W * sizeof(float2),
+                             kind, d->stream));
+    }
+    PTY_HIP(hipStreamSynchronize(d->stream));
+  });
+}
+
+pty_status pty_domains_get_probe(pty_domains* d, void* out, int on_device) {
+  return guarded_d(d, [&] {
+    require(d != nullptr && out != nullptr, "pty_domains_get_probe: null argument");
+    dd_check_sub(d, 0, pty_get_probe(d->sub[0], out, on_device));
+  });
+}
+
+pty_status pty_domains_get_errors(pty_domains* d, double* out, int32_t cap, int32_t* n_written) {
+  return guarded_d(d, [&] {
+    require(d != nullptr && n_written != nullptr && (out != nullptr || cap == 0),
+            "pty_domains_get_errors: null argument");
+    const int n = std::min<int>(cap, d->iter);
+    if (n > 0) {
+      PTY_HIP(hipMemcpyAsync(out, d->err_dev, sizeof(double) * n, hipMemcpyDeviceToHost, d->stream));
+      PTY_HIP(hipStreamSynchronize(d->stream));
+    }
+    *n_written = d->iter;
+  });
+}
+
+pty_status pty_domains_strip(const pty_domains* d, int32_t s, int32_t* info) {
+  return guarded(nullptr, [&] {
+    require(d != nullptr && info != nullptr, "pty_domains_strip: null argument");
+    require(s >= 0 && s < d->S, "pty_domains_strip: strip out of range");
+    info[0] = d->lo[s];
+    info[1] = d->hi[s];
+    info[2] = d->own_lo[s];
+    info[3] = d->own_hi[s];
+    info[4] = (int32_t)d->jmap[s].size();
+  });
+}
+
+pty_status pty_domains_traffic(const pty_domains* d, uint64_t* halo_bytes, uint64_t* probe_bytes) {
+  return guarded(nullptr, [&] {
+    require(d != nullptr && halo_bytes != nullptr && probe_bytes != nullptr, "pty_domains_traffic: null argument");
+    *halo_bytes = d->halo_bytes;
+    *probe_bytes = d->probe_bytes;
+  });
+}
+
+pty_status pty_domains_sync(pty_domains* d) {
+  return guarded_d(d, [&] {
+    require(d != nullptr, "pty_domains_sync: null argument");
+    PTY_HIP(hipStreamSynchronize(d->stream));
+    PTY_HIP(hipGetLastError());
+  });
+}
+
+void pty_domains_destroy(pty_domains* d) { delete d; }
+
+const char* pty_domains_last_error(const pty_domains* d) { return d ? d->err.c_str() : g_tls_error.c_str(); }
 
 }  // extern "C"

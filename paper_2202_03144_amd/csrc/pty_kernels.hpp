@@ -15,7 +15,9 @@ enum class ColOp { Project = 0, NllGrad = 1, Intensity = 2, NllLoss = 3, Poisson
 // Epilogue of the inverse row pass.
 enum class RowOut { DmUpdate = 0, StoreChi = 1, NllGrad = 2 };
 // Object-tile gather: what is accumulated and how it is applied.
-enum class ObjOp { Density = 0, DmObject = 1, LsqDirection = 2, LsqUpdate = 3, Gradient = 4 };
+// Gradient writes the plain sum to `out`; WeightedSum writes the sum weighted
+// by alpha[slot].x (LsqUpdate's numerator) to `out` without applying it.
+enum class ObjOp { Density = 0, DmObject = 1, LsqDirection = 2, LsqUpdate = 3, Gradient = 4, WeightedSum = 5 };
 // Probe reduction over positions.
 enum class PrbOp { Plain = 0, AlphaWeighted = 1, Gradient = 2 };
 // Probe apply step.
@@ -236,6 +238,31 @@ void launch_posgrad_reduce(const double* part, int count, int nrb, float* out, c
 void launch_scale_f32(float* p, size_t n, float s, hipStream_t st);
 void launch_scale_c64(float2* p, size_t n, float s, hipStream_t st);
 void launch_pattern_totals(const float* x, double* totals, int n, int j, hipStream_t s);
+
+// Spatial decomposition of the object into strips (one per GPU in a
+// multi-GPU run): halo messages of object-plane rows, probe-sum messages,
+// the update applied from exchanged sums, and the error partials.
+struct HaloPlanes {
+  float* plane[2];        // plane base (row 0 of the local array), as 32-bit words
+  int words_per_row[2];   // 0: plane unused
+  int row0;               // first local row of the message
+};
+// Copies `rows` rows of each used plane (plane 0 first) into msg.
+void launch_halo_pack(const HaloPlanes& p, int rows, float* msg, hipStream_t s);
+// Adds msg into (add) or overwrites (copy) the same rows of the planes.
+void launch_halo_unpack(const HaloPlanes& p, int rows, const float* msg, bool add, hipStream_t s);
+// out = sum of `count` messages of `words` floats each, in message order.
+void launch_sum_messages(const float* const* msgs, int count, size_t words, float* out, hipStream_t s);
+// atomic max (float bits) of a non-negative plane into *out
+void launch_plane_max(const float* x, size_t n, unsigned* out, hipStream_t s);
+enum class ObjApply { Dm = 0, LsqDirection = 1, LsqUpdate = 2 };
+// Per pixel, with d = den + gamma * max(den): Dm: obj = (num + delta obj) / d;
+// LsqDirection: dir = num / d (0 where d = 0); LsqUpdate: obj += beta num / d.
+void launch_obj_apply(const float2* num, const float* den, const unsigned* den_max, float gamma, float beta,
+                      float2* obj, float2* dir, size_t n, ObjApply op, hipStream_t s);
+// Copies the error partials of local patterns to their global pattern rows.
+void launch_err_scatter(const double* local, const int* jmap, int count, int per_pattern, double* global,
+                        hipStream_t s);
 
 // Learned initialiser data path and evaluation helpers.
 void launch_fill_c64(float2* p, size_t n, float2 v, hipStream_t s);

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
     const PatchRef r = rn;
     if (e + NW < te.end) rn = a.refs[e + NW];   // the next patch's entry, while this one is summed
     float wgt = 1.f;
-    if constexpr (OP == ObjOp::LsqUpdate) wgt = a.alpha[r.slot].x;
+    if constexpr (OP == ObjOp::LsqUpdate || OP == ObjOp::WeightedSum) wgt = a.alpha[r.slot].x;
     const V* src;
     if constexpr (OP == ObjOp::Density)
       src = a.pint;
@@ -92,7 +92,8 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
   // each wave applies TH / NW rows of the tile
   float mx = 0.f;
   float delta = 0.f;
-  if constexpr (OP != ObjOp::Density && OP != ObjOp::Gradient) delta = a.gamma * __uint_as_float(*a.den_max);
+  constexpr bool RAW = OP == ObjOp::Gradient || OP == ObjOp::WeightedSum;
+  if constexpr (OP != ObjOp::Density && !RAW) delta = a.gamma * __uint_as_float(*a.den_max);
   if (wv == 0) {
 #pragma unroll
     for (int i = 0; i < TH; ++i) {
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
     if constexpr (OP == ObjOp::Density) {
       a.den[o] = val;
       mx = fmaxf(mx, val);
-    } else if constexpr (OP == ObjOp::Gradient) {
+    } else if constexpr (RAW) {
       a.out[o] = val;
     } else {
       const float d = a.den[o] + delta;
@@ -918,6 +919,81 @@ __global__ __launch_bounds__(kEpieThreads) void k_epie_fused(EpieRunArgs a) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Strip decomposition: halo messages, probe-sum messages, applied updates
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_halo_pack(HaloPlanes p, int rows, float* __restrict__ msg) {
+  const size_t n0 = (size_t)rows * p.words_per_row[0], n1 = (size_t)rows * p.words_per_row[1];
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n0 + n1; i += (size_t)gridDim.x * 256) {
+    if (i < n0)
+      msg[i] = p.plane[0][(size_t)p.row0 * p.words_per_row[0] + i];
+    else
+      msg[i] = p.plane[1][(size_t)p.row0 * p.words_per_row[1] + (i - n0)];
+  }
+}
+
+template <bool ADD>
+__global__ __launch_bounds__(256) void k_halo_unpack(HaloPlanes p, int rows, const float* __restrict__ msg) {
+  const size_t n0 = (size_t)rows * p.words_per_row[0], n1 = (size_t)rows * p.words_per_row[1];
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n0 + n1; i += (size_t)gridDim.x * 256) {
+    float* dst = i < n0 ? p.plane[0] + (size_t)p.row0 * p.words_per_row[0] + i
+                        : p.plane[1] + (size_t)p.row0 * p.words_per_row[1] + (i - n0);
+    if constexpr (ADD)
+      *dst += msg[i];
+    else
+      *dst = msg[i];
+  }
+}
+
+struct MsgList {
+  const float* m[16];
+};
+
+__global__ __launch_bounds__(256) void k_sum_messages(MsgList l, int count, size_t words, float* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) {
+    float acc = l.m[0][i];
+    for (int c = 1; c < count; ++c) acc += l.m[c][i];
+    out[i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_plane_max(const float* __restrict__ x, size_t n, unsigned* out) {
+  __shared__ float redf[4];
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) mx = fmaxf(mx, x[i]);
+  mx = block_max_all<256>(mx, redf);
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(mx));
+}
+
+template <ObjApply OP>
+__global__ __launch_bounds__(256) void k_obj_apply(const float2* __restrict__ num, const float* __restrict__ den,
+                                                   const unsigned* den_max, float gamma, float beta, float2* obj,
+                                                   float2* dir, size_t n) {
+  const float delta = gamma * __uint_as_float(*den_max);
+  for (size_t o = blockIdx.x * (size_t)256 + threadIdx.x; o < n; o += (size_t)gridDim.x * 256) {
+    const float d = den[o] + delta;
+    const float2 val = num[o];
+    if constexpr (OP == ObjApply::Dm) {
+      if (d > 0.f) obj[o] = (1.f / d) * (val + delta * obj[o]);
+    } else if constexpr (OP == ObjApply::LsqDirection) {
+      dir[o] = d > 0.f ? (1.f / d) * val : make_float2(0.f, 0.f);
+    } else {
+      if (d > 0.f) obj[o] = obj[o] + (beta / d) * val;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_err_scatter(const double* __restrict__ local, const int* __restrict__ jmap,
+                                                     int count, int per_pattern, double* __restrict__ global) {
+  const size_t total = (size_t)count * per_pattern;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+    const size_t l = i / per_pattern, e = i % per_pattern;
+    global[(size_t)jmap[l] * per_pattern + e] = local[i];
+  }
+}
+
+static unsigned stream_grid(size_t n) { return (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 4096)); }
+
 void launch_obj_gather(const ObjGatherArgs& a, ObjOp op) {
   if (a.ntiles <= 0) return;
   dispatch_n(a.n, [&](auto nc) {
@@ -928,6 +1004,7 @@ void launch_obj_gather(const ObjGatherArgs& a, ObjOp op) {
       case ObjOp::LsqDirection: k_obj_gather<N, ObjOp::LsqDirection><<<a.ntiles, 256, 0, a.stream>>>(a); break;
       case ObjOp::LsqUpdate: k_obj_gather<N, ObjOp::LsqUpdate><<<a.ntiles, 256, 0, a.stream>>>(a); break;
       case ObjOp::Gradient: k_obj_gather<N, ObjOp::Gradient><<<a.ntiles, 256, 0, a.stream>>>(a); break;
+      case ObjOp::WeightedSum: k_obj_gather<N, ObjOp::WeightedSum><<<a.ntiles, 256, 0, a.stream>>>(a); break;
     }
   });
   PTY_LAUNCH_CHECK("obj_gather");
@@ -1493,6 +1570,61 @@ void launch_scale_c64(float2* p, size_t n, float s, hipStream_t st) {
   if (n == 0) return;
   k_scale_c64<<<grid_for(n, 256, 4096), 256, 0, st>>>(p, n, s);
   PTY_LAUNCH_CHECK("scale_c64");
+}
+
+
+void launch_halo_pack(const HaloPlanes& p, int rows, float* msg, hipStream_t s) {
+  const size_t n = (size_t)rows * (p.words_per_row[0] + p.words_per_row[1]);
+  if (n == 0) return;
+  k_halo_pack<<<stream_grid(n), 256, 0, s>>>(p, rows, msg);
+  PTY_LAUNCH_CHECK("halo_pack");
+}
+
+void launch_halo_unpack(const HaloPlanes& p, int rows, const float* msg, bool add, hipStream_t s) {
+  const size_t n = (size_t)rows * (p.words_per_row[0] + p.words_per_row[1]);
+  if (n == 0) return;
+  if (add)
+    k_halo_unpack<true><<<stream_grid(n), 256, 0, s>>>(p, rows, msg);
+  else
+    k_halo_unpack<false><<<stream_grid(n), 256, 0, s>>>(p, rows, msg);
+  PTY_LAUNCH_CHECK("halo_unpack");
+}
+
+void launch_sum_messages(const float* const* msgs, int count, size_t words, float* out, hipStream_t s) {
+  if (count < 1 || count > 16) throw std::runtime_error("sum_messages: 1 to 16 messages");
+  MsgList l{};
+  for (int i = 0; i < count; ++i) l.m[i] = msgs[i];
+  k_sum_messages<<<stream_grid(words), 256, 0, s>>>(l, count, words, out);
+  PTY_LAUNCH_CHECK("sum_messages");
+}
+
+void launch_plane_max(const float* x, size_t n, unsigned* out, hipStream_t s) {
+  if (n == 0) return;
+  k_plane_max<<<stream_grid(n), 256, 0, s>>>(x, n, out);
+  PTY_LAUNCH_CHECK("plane_max");
+}
+
+void launch_obj_apply(const float2* num, const float* den, const unsigned* den_max, float gamma, float beta,
+                      float2* obj, float2* dir, size_t n, ObjApply op, hipStream_t s) {
+  if (n == 0) return;
+  const unsigned g = stream_grid(n);
+  switch (op) {
+    case ObjApply::Dm: k_obj_apply<ObjApply::Dm><<<g, 256, 0, s>>>(num, den, den_max, gamma, beta, obj, dir, n); break;
+    case ObjApply::LsqDirection:
+      k_obj_apply<ObjApply::LsqDirection><<<g, 256, 0, s>>>(num, den, den_max, gamma, beta, obj, dir, n);
+      break;
+    case ObjApply::LsqUpdate:
+      k_obj_apply<ObjApply::LsqUpdate><<<g, 256, 0, s>>>(num, den, den_max, gamma, beta, obj, dir, n);
+      break;
+  }
+  PTY_LAUNCH_CHECK("obj_apply");
+}
+
+void launch_err_scatter(const double* local, const int* jmap, int count, int per_pattern, double* global,
+                        hipStream_t s) {
+  if (count <= 0) return;
+  k_err_scatter<<<stream_grid((size_t)count * per_pattern), 256, 0, s>>>(local, jmap, count, per_pattern, global);
+  PTY_LAUNCH_CHECK("err_scatter");
 }
 
 }  // namespace pty

@@ -410,3 +410,102 @@ def reconstruct(algo: str, counts, positions, obj, probe, n_iter: int, device: i
         pl.set_probe(probe)
         pl.iterate(algo, n_iter, **params)
         return pl.object(), pl.probe(), pl.errors()
+
+
+class Domains:
+    """One scan split by row into strips, each a context of its own, with the
+    object-row halos and the probe sums exchanged between them
+    (pty_domains_*; DM and LSQML)."""
+
+    def __init__(self, n: int, modes: int, positions, obj_shape, strips: int, device: int = 0, stream=None):
+        self._lib = L.lib()
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        yx = np.ascontiguousarray(positions, dtype=np.float64)
+        if yx.ndim != 2 or yx.shape[1] != 2:
+            raise ValueError("positions must be (J, 2)")
+        desc = L.PlanDesc(int(n), int(modes), int(yx.shape[0]), int(obj_shape[0]), int(obj_shape[1]),
+                          int(device), C.c_void_p(stream) if stream else None, 0)
+        out = C.c_void_p()
+        st = self._lib.pty_domains_create(C.byref(desc), yx.ctypes.data_as(C.c_void_p), int(strips), C.byref(out))
+        if st != L.OK:
+            raise PtyError(st, self._lib.pty_domains_last_error(None).decode())
+        self._d = out
+        self.n, self.modes, self.n_pos, self.strips = int(n), int(modes), int(yx.shape[0]), int(strips)
+        self.obj_shape = (int(obj_shape[0]), int(obj_shape[1]))
+
+    def _check(self, st: int) -> None:
+        if st != L.OK:
+            raise PtyError(st, self._lib.pty_domains_last_error(self._d).decode())
+
+    def _live(self):
+        if self._d is None:
+            raise PtyError(L.E_STATE, "domains are closed")
+        return self._d
+
+    def load_patterns(self, counts) -> None:
+        ptr, dev, keep = _ptr(counts, np.float32, (self.n_pos, self.n, self.n))
+        self._check(self._lib.pty_domains_load_patterns(self._live(), ptr, dev))
+        del keep
+
+    def set_object(self, obj) -> None:
+        ptr, dev, keep = _ptr(obj, np.complex64, self.obj_shape)
+        self._check(self._lib.pty_domains_set_object(self._live(), ptr, dev))
+        del keep
+
+    def set_probe(self, probe) -> None:
+        ptr, dev, keep = _ptr(probe, np.complex64, (self.modes, self.n, self.n))
+        self._check(self._lib.pty_domains_set_probe(self._live(), ptr, dev))
+        del keep
+
+    def iterate(self, algo, n_iter: int = 1, **params) -> None:
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        p = Plan.default_params(**params)
+        self._check(self._lib.pty_domains_iterate(self._live(), a, int(n_iter), C.byref(p)))
+
+    def object(self) -> np.ndarray:
+        a = np.empty(self.obj_shape, dtype=np.complex64)
+        self._check(self._lib.pty_domains_get_object(self._live(), a.ctypes.data_as(C.c_void_p), 0))
+        return a
+
+    def probe(self) -> np.ndarray:
+        a = np.empty((self.modes, self.n, self.n), dtype=np.complex64)
+        self._check(self._lib.pty_domains_get_probe(self._live(), a.ctypes.data_as(C.c_void_p), 0))
+        return a
+
+    def errors(self) -> np.ndarray:
+        cap = 1 << 16
+        buf = np.empty(cap, dtype=np.float64)
+        n = C.c_int32()
+        self._check(self._lib.pty_domains_get_errors(self._live(), buf.ctypes.data_as(C.c_void_p), cap,
+                                                     C.byref(n)))
+        return buf[: n.value].copy()
+
+    def strip(self, s: int) -> dict:
+        """Rows held [lo, hi), rows owned [own_lo, own_hi) and positions of strip s."""
+        info = (C.c_int32 * 5)()
+        self._check(self._lib.pty_domains_strip(self._live(), int(s), info))
+        return {"lo": info[0], "hi": info[1], "own_lo": info[2], "own_hi": info[3], "positions": info[4]}
+
+    def traffic(self) -> tuple:
+        """(halo bytes, probe-message bytes) sent so far."""
+        h, p = C.c_uint64(), C.c_uint64()
+        self._check(self._lib.pty_domains_traffic(self._live(), C.byref(h), C.byref(p)))
+        return int(h.value), int(p.value)
+
+    def sync(self) -> None:
+        self._check(self._lib.pty_domains_sync(self._live()))
+
+    def close(self) -> None:
+        if getattr(self, "_d", None) is not None:
+            self._lib.pty_domains_destroy(self._d)
+            self._d = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()

@@ -127,3 +127,22 @@ def test_product_path_does_not_import_oracle():
                     assert "ptysynth" not in text, f
     text = open(os.path.join(ROOT, "ptysynth", "__init__.py")).read()
     assert "oracle" not in text.replace("the oracle", "") and "paper_2202_03144_amd" not in text
+
+
+def test_domains_reject_bad_arguments_before_device():
+    lib = L.lib()
+    d = L.PlanDesc(64, 1, 4, 160, 160, 0, None, 0)
+    yx = np.array([[0.0, 0.0], [10.0, 0.0], [20.0, 5.0], [30.0, 5.0]])
+    ptr = yx.ctypes.data_as(C.c_void_p)
+    out = C.c_void_p()
+    assert lib.pty_domains_create(None, ptr, 2, C.byref(out)) == L.E_INVALID
+    for strips in (0, 5, 17):   # none, more strips than positions, beyond the limit
+        assert lib.pty_domains_create(C.byref(d), ptr, strips, C.byref(out)) == L.E_INVALID
+        assert out.value is None
+    bad = yx.copy()
+    bad[1, 0] = 120.0           # patch past the object's last row
+    assert lib.pty_domains_create(C.byref(d), bad.ctypes.data_as(C.c_void_p), 2, C.byref(out)) == L.E_INVALID
+    assert b"past the object" in lib.pty_domains_last_error(None)
+    assert lib.pty_domains_iterate(None, 1, 1, None) == L.E_INVALID
+    assert lib.pty_domains_get_object(None, None, 0) == L.E_INVALID
+    lib.pty_domains_destroy(None)
