@@ -298,108 +298,156 @@ def learned_leg(args, torch) -> dict:
 
 
 def batch_leg(args, torch) -> dict:
-    """64 LSQML reconstructions of uneven size on one GPU: one after another
-    (eager, one stream) vs together (per-dataset streams, graph-replayed
-    iterations), per window-size class, before and after chunk autotuning."""
+    """The batched-datasets workload: 64 LSQML reconstructions drawn with
+    default_rng([5, 5]) -- N uniform in {64, 128, 256}, K uniform in {1, 2, 3},
+    J log-uniform in [200, 10,000], photons log-uniform in [1e6, 1e9] -- with
+    D = 84 N / 256, spiral pitch 14 N / 256, sigma_o = max(2, 4 N / 256), an
+    8-pixel margin and Poisson counts (dataset i's streams default_rng([5, i,
+    stream])).  Each dataset alone (eager, timed on its own: per-dataset
+    throughput and roofline fraction), then all together with per-dataset
+    streams and a captured graph per iteration, before and after autotuning
+    (chunk and probe-sum slices)."""
     import ptysynth
     from paper_2202_03144_amd import Batch, Plan
 
-    rng = np.random.default_rng(2202)
+    rng = np.random.default_rng([5, 5])
     specs = []
     for i in range(args.datasets):
-        n = (64, 128, 256)[i % 3]
-        k = 1 + (i // 3) % 3
-        jmax = 10000 if n < 256 else 3000
-        j = int(round(200 * (jmax / 200) ** rng.uniform()))
-        specs.append((n, k, j))
+        n = int(rng.choice([64, 128, 256]))
+        k = int(rng.integers(1, 4))
+        j = int(round(math.exp(rng.uniform(math.log(200), math.log(10000)))))
+        ph = float(math.exp(rng.uniform(math.log(1e6), math.log(1e9))))
+        specs.append((n, k, j, ph))
     log(f"building {len(specs)} datasets")
     datasets = []
-    for i, (n, k, j) in enumerate(specs):
+    for i, (n, k, j, ph) in enumerate(specs):
         c = 14.0 * n / 256.0
-        side = ptysynth.spiral_object_side(j, c, n, 3.0)
-        obj = ptysynth.make_object(500 + i, side, side, max(2.0, 4.0 * n / 256.0)).astype(np.complex64)
-        probe = ptysynth.make_probe(500 + i, n, k, 84.0 * n / 256.0, max(1.0, 3.0 * n / 256),
-                                    max(2.0, 12.0 * n / 256), 5.0).astype(np.complex64)
-        pos = ptysynth.spiral_positions(j, c, side / 2.0, n, ptysynth.stream(500 + i, 3))
+        side = ptysynth.spiral_object_side(j, c, n, 8.0)
+        obj = ptysynth.make_object(5, side, side, max(2.0, 4.0 * n / 256.0), i).astype(np.complex64)
+        probe = ptysynth.make_probe(5, n, k, 84.0 * n / 256.0, max(1.0, 3.0 * n / 256),
+                                    max(2.0, 12.0 * n / 256), 5.0, i).astype(np.complex64)
+        pos = ptysynth.spiral_positions(j, c, side / 2.0, n, ptysynth.stream(5, 3, i))
         lam = torch.empty((j, n, n), dtype=torch.float32, device="cuda")
         cnt = torch.empty_like(lam)
         with Plan(n, k, j, (side, side)) as sim:
             sim.load_positions(pos)
             sim.set_object(obj)
             sim.set_probe(probe)
-            sim.simulate(1e6 if n < 256 else 1e8, out=lam)
-            sim.poisson(lam, cnt, seed=500 + i)
+            sim.simulate(ph, out=lam)
+            sim.poisson(lam, cnt, seed=(5 << 32) + (i << 8) + 4)
             probe = sim.probe()
         del lam
-        datasets.append(dict(n=n, k=k, j=j, shape=(side, side), counts=cnt, pos=pos, probe=probe))
-    params = dict(probe_update_start=0, lsqml_batch=512)
+        datasets.append(dict(n=n, k=k, j=j, photons=ph, shape=(side, side), counts=cnt, pos=pos, probe=probe))
+    batch = 512
+    params = dict(probe_update_start=0, lsqml_batch=batch)
     iters = args.batch_iters
 
-    def make_plans(streams: bool):
-        plans = []
-        for d in datasets:
-            pl = Plan(d["n"], d["k"], d["j"], d["shape"], stream=torch.cuda.Stream() if streams else None)
-            pl.load_patterns(d["counts"])
-            pl.load_positions(d["pos"])
-            pl.set_object(np.ones(d["shape"], np.complex64))
-            pl.set_probe(d["probe"])
-            plans.append(pl)
-        return plans
+    def make_plan(d, stream):
+        pl = Plan(d["n"], d["k"], d["j"], d["shape"], stream=stream)
+        pl.load_patterns(d["counts"])
+        pl.load_positions(d["pos"])
+        pl.set_object(np.ones(d["shape"], np.complex64))
+        pl.set_probe(d["probe"])
+        return pl
 
-    def run_sequential(plans, idx):
-        for i in idx:
-            plans[i].iterate("lsqml", 1, **params)      # warm-up (buffers)
-            plans[i].sync()
+    def roof_bytes(d):
+        g = -(-d["j"] // batch)
+        return d["j"] * d["n"] ** 2 * (4 + 16 * d["k"]) + 64 * d["shape"][0] * d["shape"][1] * g
+
+    log(f"each dataset alone, {iters} iterations")
+    per = []
+    t_seq = 0.0
+    for i, d in enumerate(datasets):
+        pl = make_plan(d, None)
+        pl.iterate("lsqml", 1, **params)
+        pl.sync()
         t = time.perf_counter()
-        for i in idx:
-            plans[i].iterate("lsqml", iters, **params)
-            plans[i].sync()
-        return time.perf_counter() - t
+        pl.iterate("lsqml", iters, **params)
+        pl.sync()
+        dt = time.perf_counter() - t
+        pl.close()
+        t_seq += dt
+        ms = dt * 1e3 / iters
+        per.append({"n": d["n"], "k": d["k"], "j": d["j"], "photons": round(d["photons"]),
+                    "ms_per_iter": round(ms, 3), "pit_per_s": round(d["j"] / (ms / 1e3), 1),
+                    "roofline_frac": round(roof_bytes(d) / (ms / 1e3) / (PEAK_HBM_GBS * 1e9), 4)})
+    pit = sum(d["j"] for d in datasets) * iters
 
-    def run_batched(plans, idx):
-        with Batch([plans[i] for i in idx]) as b:
+    def run_batched(plans, tune_cache=None):
+        with Batch(plans) as b:
+            if tune_cache:
+                t0 = time.perf_counter()
+                b.autotune("lsqml", tune_cache, **params)
+                tune_s = time.perf_counter() - t0
+            else:
+                tune_s = 0.0
             b.iterate("lsqml", 1, graph=True, **params)   # warm-up (buffers, graph capture)
             b.sync()
             t = time.perf_counter()
             b.iterate("lsqml", iters, graph=True, **params)
             b.sync()
-            return time.perf_counter() - t
+            return time.perf_counter() - t, tune_s
 
     import tempfile
     cache = os.path.join(tempfile.mkdtemp(prefix="ptymi_tune_"), "tune.json")
-    classes = {f"n{n}": [i for i, d in enumerate(datasets) if d["n"] == n] for n in (64, 128, 256)}
-    classes["all"] = list(range(len(datasets)))
-    out = {}
-    for name, idx in classes.items():
-        pit = sum(datasets[i]["j"] for i in idx) * iters
-        seq_plans = make_plans(False)
-        t_seq = run_sequential(seq_plans, idx)
-        for pl in seq_plans:
-            pl.close()
-        b_plans = make_plans(True)
-        t_b = run_batched(b_plans, idx)
-        t0 = time.perf_counter()
-        chunks = [b_plans[i].autotune("lsqml", cache, **params) for i in idx]
-        tune_s = time.perf_counter() - t0
-        t_bt = run_batched(b_plans, idx)
-        for pl in b_plans:
-            pl.close()
-        out[name] = {"datasets": len(idx), "pattern_iterations": pit,
-                     "sequential_pit_per_s": round(pit / t_seq, 1),
-                     "batched_graph_pit_per_s": round(pit / t_b, 1),
-                     "batched_graph_tuned_pit_per_s": round(pit / t_bt, 1),
-                     "batched_over_sequential": round(t_seq / t_b, 3),
-                     "autotune_s": round(tune_s, 2), "tuned_chunks": sorted(set(chunks))}
-        log(f"{name}: {out[name]}")
+    log("all datasets together, graph replay")
+    plans = [make_plan(d, torch.cuda.Stream()) for d in datasets]
+    t_b, _ = run_batched(plans)
+    for pl in plans:
+        pl.close()
+    log("all datasets together, autotuned")
+    plans = [make_plan(d, torch.cuda.Stream()) for d in datasets]
+    t_bt, tune_s = run_batched(plans, cache)
+    tuned = [pl.tuning() for pl in plans]
+    for pl in plans:
+        pl.close()
+    for row, (ch, sl) in zip(per, tuned):
+        row["tuned_chunk"], row["tuned_probe_slice"] = ch, sl
+    # aggregates: per (N, K), and per decile of J over the 64 datasets
+    def agg(rows):
+        t = sum(r["j"] * iters / r["pit_per_s"] for r in rows)
+        b = sum(roof_bytes(d) * iters for d, r in zip(datasets, per) if r in rows)
+        return {"datasets": len(rows), "pit_per_s": round(sum(r["j"] * iters for r in rows) / t, 1),
+                "roofline_frac": round(b / t / (PEAK_HBM_GBS * 1e9), 4)}
+    by_nk = {f"n{n}_k{k}": agg([r for r in per if r["n"] == n and r["k"] == k])
+             for n in (64, 128, 256) for k in (1, 2, 3) if any(r["n"] == n and r["k"] == k for r in per)}
+    js = np.array([r["j"] for r in per])
+    edges = np.quantile(js, np.linspace(0, 1, 11))
+    by_decile = {}
+    for q in range(10):
+        lo, hi = edges[q], edges[q + 1]
+        rows = [r for r in per if (lo <= r["j"] < hi) or (q == 9 and r["j"] == hi)]
+        if rows:
+            by_decile[f"d{q + 1} J {int(lo)}-{int(hi)}"] = agg(rows)
+    by_nk_decile = {}
+    for n in (64, 128, 256):
+        for k in (1, 2, 3):
+            for q in range(10):
+                lo, hi = edges[q], edges[q + 1]
+                rows = [r for r in per if r["n"] == n and r["k"] == k and ((lo <= r["j"] < hi) or (q == 9 and r["j"] == hi))]
+                if rows:
+                    by_nk_decile[f"n{n}_k{k}_d{q + 1}"] = agg(rows)
+    total_bytes = sum(roof_bytes(d) for d in datasets) * iters
+    out = {
+        "sequential_pit_per_s": round(pit / t_seq, 1),
+        "batched_graph_pit_per_s": round(pit / t_b, 1),
+        "batched_graph_tuned_pit_per_s": round(pit / t_bt, 1),
+        "batched_over_sequential": round(t_seq / t_b, 3),
+        "batched_tuned_roofline_frac": round(total_bytes / t_bt / (PEAK_HBM_GBS * 1e9), 4),
+        "autotune_s": round(tune_s, 2),
+    }
+    log(f"{out}")
     return {
         "metric": "pattern-iterations/s (64 uneven LSQML datasets)",
-        "value": out["all"]["batched_graph_tuned_pit_per_s"], "unit": "pattern-iterations/s", "n_gpus": 1,
+        "value": out["batched_graph_tuned_pit_per_s"], "unit": "pattern-iterations/s", "n_gpus": 1,
         "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{len(datasets)} Fermat-spiral datasets, N in (64, 128, 256), K 1-3, "
-                               "J log-uniform 200-10,000 (200-3,000 at N = 256); LSQML groups of 512, "
-                               f"probe updates on; {iters} timed iterations each",
-                   "sizes": [[d["n"], d["k"], d["j"]] for d in datasets]},
-        "per_class": out,
+        "config": {"workload": f"{len(datasets)} Fermat-spiral datasets drawn with default_rng([5, 5]): N in "
+                               "{64, 128, 256}, K in {1, 2, 3}, J log-uniform 200-10,000, photons log-uniform "
+                               f"1e6-1e9, Poisson counts; LSQML groups of {batch}, probe updates on; "
+                               f"{iters} timed iterations each",
+                   "pattern_iterations": pit},
+        **out,
+        "per_n_k": by_nk, "per_j_decile": by_decile, "per_n_k_j_decile": by_nk_decile, "per_dataset": per,
     }
 
 
@@ -885,7 +933,7 @@ def main() -> int:
     ap.add_argument("--adjoint-cpu-sample", type=int, default=100)
     ap.add_argument("--tiny", action="store_true",
                     help="instead: the 64x64 one-mode raster workload, ePIE / DM / LSQML eager and graphed")
-    ap.add_argument("--batch-iters", type=int, default=5)
+    ap.add_argument("--batch-iters", type=int, default=50)
     ap.add_argument("--listing1", action="store_true",
                     help="instead: the paper's sim512 script example (ePIE, with DM and LSQML beside it)")
     ap.add_argument("--listing1-cpu-sample", type=int, default=30)

@@ -458,16 +458,21 @@ pty_status pty_batch_sync(pty_batch* b);
 void pty_batch_destroy(pty_batch* b);                  /* NULL-safe */
 const char* pty_batch_last_error(const pty_batch* b); /* never NULL */
 
-/* Chooses the Fourier-pass chunk (patterns per launch) for this context,
- * algorithm and parameters by timing one iteration per candidate (8 to 256
- * patterns) after a warm-up iteration, then restores the object, probe and
- * iteration counter (DM restarts its exit waves from them).  With a non-NULL
- * cache_path the choice is looked up in, and added to, that JSON file, keyed
- * by device architecture, N, K, J and algorithm.  *chunk (may be NULL)
- * receives the choice; later iterations with chunk = 0 use it.
- * Synchronises. */
+/* Chooses the Fourier-pass chunk (patterns per launch) and then the probe
+ * sums' schedule (patterns summed per slice: 8, 16 or 32, each slice one
+ * partial plane) for this context, algorithm and parameters by timing one
+ * iteration per candidate after a warm-up iteration, then restores the
+ * object, probe and iteration counter (DM restarts its exit waves from them).
+ * With a non-NULL cache_path the choices are looked up in, and added to, that
+ * JSON file, keyed by device architecture, N, K, J and algorithm.  *chunk (may
+ * be NULL) receives the chunk; later iterations with chunk = 0 use both
+ * choices.  Synchronises. */
 pty_status pty_autotune(pty_ctx* ctx, pty_algo algo, const pty_iter_params* prm, const char* cache_path,
                         int32_t* chunk);
+/* The choices in force: chunk and probe-sum slice size (0: the default rules). */
+pty_status pty_get_tuning(pty_ctx* ctx, int32_t* chunk, int32_t* probe_slice);
+/* pty_autotune for every context of a batch, in order (one cache file). */
+pty_status pty_batch_autotune(pty_batch* b, pty_algo algo, const pty_iter_params* prm, const char* cache_path);
 
 /* ------------------------------------------------------------------------
  * Strip decomposition (the paper's multi-GPU mode splits the scan into

@@ -98,6 +98,8 @@ SIGNATURES = {
     "pty_domains_sync": (C.c_int, [C.c_void_p]),
     "pty_domains_destroy": (None, [C.c_void_p]),
     "pty_domains_last_error": (C.c_char_p, [C.c_void_p]),
+    "pty_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "pty_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(IterParams), C.c_char_p]),
     "pty_model_error": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pty_set_truth": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_float]),
     "pty_nrmse": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),

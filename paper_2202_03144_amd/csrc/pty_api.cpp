@@ -168,6 +168,7 @@ struct pty_ctx {
   };
   std::vector<GraphEntry> graphs;
   int tuned_chunk = 0;             // from pty_autotune; 0 = the default rule
+  int tuned_slice = 0;             // probe-sum patterns per slice from pty_autotune; 0 = the rule
 
   // evaluation against a known object: invariant NRMSE on a region of interest
   float2* truth = nullptr;
@@ -593,7 +594,7 @@ void density(pty_ctx* c, const Group& g) {
 void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern, PrbOp op,
                   float2* num, bool with_den, const float2* obj = nullptr, const PosInfo* pos = nullptr) {
   const int count = (int)g.jl.size();
-  const int per_slice = probe_per_slice(c->N, count);
+  const int per_slice = c->tuned_slice > 0 ? c->tuned_slice : probe_per_slice(c->N, count);
   const int slices = probe_slices(count, per_slice);
   ProbeAccArgs pa{};
   pa.n = c->N;
@@ -628,7 +629,7 @@ void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern,
 }
 
 void ensure_probe_parts(pty_ctx* c, int count) {
-  const int slices = probe_slices_max(c->N, count);
+  const int slices = std::max(probe_slices_max(c->N, count), c->tuned_slice > 0 ? probe_slices(count, c->tuned_slice) : 0);
   const size_t nn = size_t(c->N) * c->N;
   size_t have = c->part_slices;
   if (c->part_num && have >= size_t(slices) * c->K * nn && c->part_den) return;
@@ -1272,6 +1273,36 @@ int tune_chunk(pty_ctx* c, int algo, pty_iter_params p) {
     c->dfree(p_save);
     throw;
   }
+  // then the probe sums' slice size with that chunk
+  int best_slice = 0;
+  try {
+    p.chunk = best;
+    float best_ms = 0.f;
+    for (int v : {8, 16, 32}) {
+      c->tuned_slice = v;
+      ensure_probe_parts(c, c->J);
+      run_algo(c, algo, 1, p);
+      PTY_HIP(hipEventRecord(e0, c->stream));
+      run_algo(c, algo, 1, p);
+      PTY_HIP(hipEventRecord(e1, c->stream));
+      PTY_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      PTY_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (!best_slice || ms < best_ms) {
+        best_slice = v;
+        best_ms = ms;
+      }
+    }
+  } catch (...) {
+    c->tuned_slice = 0;
+    c->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->dfree(o_save);
+    c->dfree(p_save);
+    throw;
+  }
+  c->tuned_slice = best_slice;
   c->timing = timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -2054,6 +2085,14 @@ pty_status pty_poisson(pty_ctx* c, const float* lam, float* out, size_t n, uint6
   });
 }
 
+pty_status pty_get_tuning(pty_ctx* c, int32_t* chunk, int32_t* probe_slice) {
+  return guarded(c, [&] {
+    require(c != nullptr && chunk != nullptr && probe_slice != nullptr, "pty_get_tuning: null argument");
+    *chunk = c->tuned_chunk;
+    *probe_slice = c->tuned_slice;
+  });
+}
+
 pty_status pty_autotune(pty_ctx* c, pty_algo algo, const pty_iter_params* prm, const char* cache_path,
                         int32_t* chunk) {
   return guarded(c, [&] {
@@ -2069,13 +2108,16 @@ pty_status pty_autotune(pty_ctx* c, pty_algo algo, const pty_iter_params* prm, c
     std::map<std::string, int> cache;
     if (cache_path) cache = read_tune_cache(cache_path);
     auto it = cache.find(key);
+    auto its = cache.find(key + " slice");
     int best;
-    if (it != cache.end()) {
+    if (it != cache.end() && its != cache.end()) {
       best = it->second;
+      c->tuned_slice = std::min(its->second, 32);
     } else {
-      best = tune_chunk(c, algo, p);
+      best = tune_chunk(c, algo, p);   // also sets tuned_slice
       if (cache_path) {
         cache[key] = best;
+        cache[key + " slice"] = c->tuned_slice;
         write_tune_cache(cache_path, cache);
       }
     }
@@ -2124,6 +2166,18 @@ pty_status pty_batch_iterate(pty_batch* b, pty_algo algo, int32_t n_iter, const 
         return st;
       }
     }
+  return PTY_OK;
+}
+
+pty_status pty_batch_autotune(pty_batch* b, pty_algo algo, const pty_iter_params* prm, const char* cache_path) {
+  if (!b) return fail(nullptr, PTY_E_INVALID, "pty_batch_autotune: null batch");
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    const pty_status st = pty_autotune(b->ctxs[i], algo, prm, cache_path, nullptr);
+    if (st != PTY_OK) {
+      b->err = "context " + std::to_string(i) + ": " + pty_last_error(b->ctxs[i]);
+      return st;
+    }
+  }
   return PTY_OK;
 }
 

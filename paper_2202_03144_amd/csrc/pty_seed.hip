@@ -25,30 +25,50 @@ __device__ __forceinline__ double unit_open(uint64_t key) {
   return ((double)(splitmix64(key) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-// Poisson(lambda) draws, one counter stream per element.  lambda < 64:
-// inversion of the cumulative distribution; otherwise the normal
-// approximation lambda + sqrt(lambda) z, rounded and clipped at zero (used for
-// training patterns, where the exact tail shape does not matter).
+// Poisson(lambda) draws, one counter stream per element.  lambda < 10:
+// inversion of the cumulative distribution; lambda >= 10: the transformed
+// rejection method with squeeze of Hormann (1993, "The transformed rejection
+// method for generating Poisson random variables", algorithm PTRS), which is
+// exact.  Each trial takes two uniforms from the element's counter stream;
+// the acceptance rate is above 0.9, and after 64 rejected trials (probability
+// below 1e-60) the draw falls back to the rounded normal approximation.
+__device__ double poisson_ptrs(double lam, uint64_t base) {
+  const double slam = sqrt(lam), loglam = log(lam);
+  const double b = 0.931 + 2.53 * slam;
+  const double a = -0.059 + 0.02483 * b;
+  const double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
+  const double v_r = 0.9277 - 3.6224 / (b - 2.0);
+  for (int t = 0; t < 64; ++t) {
+    const double u = unit_open(base + 2 * (uint64_t)t) - 0.5;
+    const double v = unit_open(base + 2 * (uint64_t)t + 1);
+    const double us = 0.5 - fabs(u);
+    const double k = floor((2.0 * a / us + b) * u + lam + 0.43);
+    if (us >= 0.07 && v <= v_r) return k;
+    if (k < 0.0 || (us < 0.013 && v > us)) continue;
+    if (log(v) + log(inv_alpha) - log(a / (us * us) + b) <= -lam + k * loglam - lgamma(k + 1.0)) return k;
+  }
+  const double u1 = unit_open(base + 128), u2 = unit_open(base + 129);
+  return fmax(0.0, floor(lam + slam * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2) + 0.5));
+}
+
 __global__ void k_poisson(const float* __restrict__ lam, float* __restrict__ out, size_t n, uint64_t seed) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double l = (double)lam[i];
   const uint64_t base = splitmix64(seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(i + 1)));
   float r = 0.f;
-  if (l > 0.0 && l < 64.0) {
+  if (l > 0.0 && l < 10.0) {
     const double u = unit_open(base);
     double p = exp(-l), f = p;
     int k = 0;
-    while (u > f && k < 400) {
+    while (u > f && k < 200) {
       ++k;
       p *= l / k;
       f += p;
     }
     r = (float)k;
-  } else if (l >= 64.0) {
-    const double u1 = unit_open(base), u2 = unit_open(base + 1);
-    const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-    r = (float)fmax(0.0, floor(l + sqrt(l) * z + 0.5));
+  } else if (l >= 10.0) {
+    r = (float)poisson_ptrs(l, base);
   }
   out[i] = r;
 }

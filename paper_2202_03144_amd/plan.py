@@ -138,6 +138,12 @@ class Plan:
                                            cache_path.encode() if cache_path else None, C.byref(out)))
         return int(out.value)
 
+    def tuning(self) -> tuple:
+        """(chunk, probe-sum slice size) chosen by autotune; 0 = the default rule."""
+        ch, sl = C.c_int32(), C.c_int32()
+        self._check(self._lib.pty_get_tuning(self._live(), C.byref(ch), C.byref(sl)))
+        return int(ch.value), int(sl.value)
+
     def sync(self) -> None:
         self._check(self._lib.pty_sync(self._live()))
 
@@ -377,6 +383,13 @@ class Batch:
         params["flags"] = _flags(params.get("flags", 0), graph, ortho_modes, likelihood)
         p = Plan.default_params(**params)
         self._check(self._lib.pty_batch_iterate(self._b, a, int(n_iter), C.byref(p)))
+
+    def autotune(self, algo, cache_path: Optional[str] = None, **params) -> None:
+        """pty_autotune on every plan of the batch (see Plan.autotune)."""
+        a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        p = Plan.default_params(**params)
+        self._check(self._lib.pty_batch_autotune(self._b, a, C.byref(p),
+                                                 cache_path.encode() if cache_path else None))
 
     def sync(self) -> None:
         self._check(self._lib.pty_batch_sync(self._b))

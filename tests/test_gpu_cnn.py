@@ -151,10 +151,15 @@ def test_bad_arguments():
 
 
 def test_poisson_statistics():
+    """Device Poisson sampler (inversion below 10, Hormann's PTRS above): mean,
+    variance, reproducibility, and a chi-square test of the histogram against
+    the exact pmf (scipy.stats.poisson) at every rate, including the ones the
+    rejection method covers."""
     import torch
+    from scipy import stats
     from paper_2202_03144_amd import Plan
-    lam_values = [0.3, 4.0, 40.0, 200.0, 5e4]
-    n = 200_000
+    lam_values = [0.3, 4.0, 9.9, 10.0, 40.0, 200.0, 5e4]
+    n = 400_000
     lam = torch.tensor(np.repeat(lam_values, n).astype(np.float32), device="cuda")
     out = torch.empty_like(lam)
     with Plan(32, 1, 1, (33, 33)) as pl:
@@ -169,6 +174,26 @@ def test_poisson_statistics():
         se = np.sqrt(l / n)
         assert abs(m - l) <= 5 * se + 0.5 / n, (l, m)
         assert abs(v / l - 1) <= 0.03, (l, v)
+        # chi-square against the exact pmf over bins of expected count >= 50
+        lo, hi = int(stats.poisson.ppf(1e-6, l)), int(stats.poisson.ppf(1 - 1e-6, l))
+        edges = np.arange(lo, hi + 2)
+        p = stats.poisson.pmf(edges[:-1], l)
+        obs = np.histogram(a[i], bins=edges)[0].astype(np.float64)
+        groups, cur_p, cur_o = [], 0.0, 0.0
+        for pk, ok in zip(p, obs):
+            cur_p, cur_o = cur_p + pk, cur_o + ok
+            if cur_p * n >= 50:
+                groups.append((cur_p, cur_o))
+                cur_p, cur_o = 0.0, 0.0
+        if cur_p > 0:
+            groups[-1] = (groups[-1][0] + cur_p, groups[-1][1] + cur_o)
+        gp = np.array([g[0] for g in groups])
+        go = np.array([g[1] for g in groups])
+        gp = gp / gp.sum()
+        chi2 = float(((go - n * gp) ** 2 / (n * gp)).sum())
+        pval = float(stats.chi2.sf(chi2, len(groups) - 1))
+        print(f"[poisson] lambda {l}: chi2 {chi2:.1f} on {len(groups) - 1} dof, p {pval:.3g}", flush=True)
+        assert pval > 1e-4, (l, chi2, len(groups), pval)
 
 
 def _spiral_patches(j=60, h=300, w=280):
