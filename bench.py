@@ -219,7 +219,7 @@ def learned_leg(args, torch) -> dict:
     train_s = time.perf_counter() - t0
     del objs
     # one full-batch inference, timed alone: the network's MFMA roofline
-    xin = torch.rand((args.infer_batch, 128, 128), device="cuda") * 0.6
+    xin = torch.rand((args.infer_batch, 128, 128, 2), device="cuda") * 0.6
     yout = torch.empty((args.infer_batch, 64, 64, 2), dtype=torch.float32, device="cuda")
     net.forward(xin, yout)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -232,7 +232,7 @@ def learned_leg(args, torch) -> dict:
     infer_flop = 0.9576e9 * args.infer_batch       # 2 x MACs of the ten convolutions per pattern
     del xin, yout
 
-    def arm(learned: bool, max_iter: int):
+    def arm(learned: bool, max_iter: int, stride: int = 1):
         pl = Plan(wl.n, wl.k, wl.j, (wl.h, wl.w), stream=stream)
         pl.load_patterns(counts)
         pl.load_positions(pos)
@@ -241,10 +241,10 @@ def learned_leg(args, torch) -> dict:
         pl.set_truth(obj_true, 0.3)
         seed_ms, info, nrmse0 = 0.0, {}, pl.nrmse()
         if learned:
-            pl.seed_object(net, wl.photons, batch=args.infer_batch)   # warm: allocations
+            pl.seed_object(net, batch=args.infer_batch, stride=stride)   # warm: allocations
             torch.cuda.synchronize()
             t = time.perf_counter()
-            info = pl.seed_object(net, wl.photons, batch=args.infer_batch)
+            info = pl.seed_object(net, batch=args.infer_batch, stride=stride)
             torch.cuda.synchronize()
             seed_ms = (time.perf_counter() - t) * 1e3
             nrmse0 = pl.nrmse()
@@ -268,13 +268,18 @@ def learned_leg(args, torch) -> dict:
                         "e_flat": round(info["e_flat"], 5)})
         return res
 
-    log("learned arm")
-    learned = arm(True, args.learned_iters)
-    log(f"learned: {learned}")
     log("plain arm")
     plain = arm(False, args.plain_iters)
     log(f"plain: {plain}")
+    arms = {}
+    for stride in sorted({1, args.seed_stride}):
+        log(f"learned arm, every {stride}. pattern seeded")
+        arms[stride] = arm(True, args.learned_iters, stride)
+        arms[stride]["seed_stride"] = stride
+        log(f"learned (stride {stride}): {arms[stride]}")
     net.close()
+    best = min(arms, key=lambda k: arms[k]["ms_to_target"] or float("inf"))
+    learned = arms[best]
     speed = None
     if learned["ms_to_target"] and plain["ms_to_target"]:
         speed = round(plain["ms_to_target"] / learned["ms_to_target"], 3)
@@ -285,7 +290,8 @@ def learned_leg(args, torch) -> dict:
         "config": {"workload": "128x128 probe (D 48), 1 mode fixed, 4,096-point Fermat spiral (c 8), "
                                f"1200x1200 object, Poisson 1e8 photons; LSQML groups of {args.learned_lsqml_batch}",
                    "n": wl.n, "positions": wl.j, "object": [wl.h, wl.w]},
-        "learned": learned, "plain": plain, "plain_over_learned": speed,
+        "learned": learned, "learned_arms": {str(k): v for k, v in arms.items()}, "plain": plain,
+        "plain_over_learned": speed,
         "roofline": {"bound": "mfma", "kernel": f"network forward, batch {args.infer_batch}",
                      "achieved": round(infer_flop / (infer_ms * 1e-3) / 1e12, 1), "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": round(infer_flop / (infer_ms * 1e-3) / 1e12 / 2500.0, 4),
@@ -922,6 +928,8 @@ def main() -> int:
     ap.add_argument("--learned-iters", type=int, default=20)
     ap.add_argument("--plain-iters", type=int, default=200)
     ap.add_argument("--nrmse-target", type=float, default=1e-2)
+    ap.add_argument("--seed-stride", type=int, default=4,
+                    help="learned arm also run seeding only every this-many-th pattern (coverage, not redundancy)")
     ap.add_argument("--learned-lsqml-batch", type=int, default=4096,
                     help="LSQML group size of both arms (512-position groups leave a noise floor of "
                          "NRMSE 1.05e-2 on this workload, above the target)")

@@ -378,9 +378,14 @@ pty_status pty_get_nrmse(pty_ctx* ctx, double* out, int32_t cap, int32_t* n_writ
  * pooling, 2x nearest upsampling, skips concatenated after the upsampled
  * channels; channel widths 32-32-64-128-256-256-128-64-32-2 at resolutions
  * 128-64-32-16-8-8-16-32-64-64.  Parameters (float32 masters, bf16 copies used
- * by the kernels): per layer W[cout][3][3][cin] then b[cout].  Input
- * log1p(max(d, 0)) / log1p(photons) of the centred counts d; output channel 0
- * amplitude, channel 1 phase relative to the patch's mean phasor.  Loss: mean
+ * by the kernels): per layer W[cout][3][3][cin] then b[cout].  Input: a
+ * real-space estimate of the window's object patch from its counts d and the
+ * known probe P (mode 0): est = g F^-1(A u) with A = sqrt(max(d, 0)) in
+ * natural order, u = F(P) / |F(P)| (1 where F(P) = 0) and
+ * g = conj(P) / (|P|^2 + 0.01 max |P|^2); its central 64 x 64 upsampled 2x
+ * (nearest) to 128 x 128, channels Re, Im (so that the 64 x 64 output grid
+ * lies on the target patch).  Output channel 0 amplitude, channel 1 phase
+ * relative to the patch's mean phasor.  Loss: mean
  * squared error; optimiser: Adam (beta 0.9, 0.999, eps 1e-8).
  * ---------------------------------------------------------------------- */
 typedef struct pty_cnn pty_cnn;
@@ -395,8 +400,8 @@ pty_status pty_cnn_num_params(const pty_cnn* net, int64_t* n);
 /* Host copies of the float32 parameters (pty_cnn_num_params floats). */
 pty_status pty_cnn_get_params(pty_cnn* net, float* out);
 pty_status pty_cnn_set_params(pty_cnn* net, const float* in);
-/* Forward pass: x (batch x 128 x 128 float32, device) -> y (batch x 64 x 64 x 2
- * float32, device).  Synchronises. */
+/* Forward pass: x (batch x 128 x 128 x 2 float32, device) -> y (batch x 64 x
+ * 64 x 2 float32, device).  Synchronises. */
 pty_status pty_cnn_forward(pty_cnn* net, const float* x, int32_t batch, float* y);
 /* Loss and gradient with respect to the parameters for targets t (batch x 64
  * x 64 x 2, device); grad is a host array of pty_cnn_num_params floats.  The
@@ -407,13 +412,15 @@ pty_status pty_cnn_grad(pty_cnn* net, const float* x, const float* target, int32
  * the loss before the step.  Synchronises. */
 pty_status pty_cnn_train_step(pty_cnn* net, const float* x, const float* target, int32_t batch, float lr,
                               double* loss);
-/* Network input from n centred counts (device): x = log1p(max(d, 0)) / log1p(photons). */
-pty_status pty_cnn_input(pty_cnn* net, const float* counts, size_t n, double photons, float* x);
+/* Network input (batch x 128 x 128 x 2, device) from `batch` windows of centred
+ * counts (batch x 128 x 128, device) and the probe (1 x 128 x 128 complex64,
+ * device; mode 0 is used), as described above.  Synchronises. */
+pty_status pty_cnn_input(pty_cnn* net, const float* counts, int32_t batch, const void* probe, float* x);
 
 /* Training data on the context's device and stream.
- * pty_poisson: out[i] ~ Poisson(lam[i]) (device arrays; lam < 64 by
- * inversion, larger by the rounded normal approximation), a counter-based
- * stream per element keyed by seed.  pty_training_targets: for integer
+ * pty_poisson: out[i] ~ Poisson(lam[i]) (device arrays; lam < 10 by
+ * inversion, larger by Hormann's transformed rejection (PTRS), both exact), a
+ * counter-based stream per element keyed by seed.  pty_training_targets: for integer
  * positions and N = 128, the network targets of every window (J x 64 x 64 x 2,
  * device) from the context's object.  Both synchronise. */
 pty_status pty_poisson(pty_ctx* ctx, const float* lam, float* out, size_t n, uint64_t seed);
@@ -429,13 +436,15 @@ pty_status pty_training_targets(pty_ctx* ctx, float* out);
  * object.  N must be 128.  Synchronises. */
 pty_status pty_stitch(pty_ctx* ctx, const float* patches, void* out);
 
-/* Learned seed of the context's object: the network's forward pass over all
- * loaded patterns in batches of `batch` (on the context's stream), then
- * pty_stitch.  With fallback != 0 the seed is kept only if its model error is
+/* Learned seed of the context's object: the network input of every
+ * stride-th loaded pattern (j = 0, stride, 2 stride, ...; 1 = all) from its
+ * moduli and the context's probe, the forward pass in batches of `batch`
+ * (on the context's stream), then the stitching of pty_stitch over those
+ * windows.  With fallback != 0 the seed is kept only if its model error is
  * not above that of the flat object O = 1 (else the flat object is used and
  * *used_fallback = 1); *e_seed and *e_flat (each may be NULL) receive the two
  * errors.  The network must live on the context's device.  Synchronises. */
-pty_status pty_seed_object(pty_ctx* ctx, pty_cnn* net, double photons, int32_t batch, int32_t fallback,
+pty_status pty_seed_object(pty_ctx* ctx, pty_cnn* net, int32_t batch, int32_t stride, int32_t fallback,
                            int32_t* used_fallback, double* e_seed, double* e_flat);
 
 /* ------------------------------------------------------------------------

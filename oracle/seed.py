@@ -1,7 +1,8 @@
 """FP64 reference of the learned seed's data path (test infrastructure).
 
-Network input and training targets, and the stitching of predicted
-64 x 64 patches into an object seed:
+Network input (a real-space estimate of the patch from the pattern and the
+known probe) and training targets, and the stitching of predicted 64 x 64
+patches into an object seed:
 
 * placement: the central 64 x 64 of window j, at the window's nearest
   integer position (floor(p + 1/2)) plus (32, 32);
@@ -22,9 +23,40 @@ PATCH = 64
 GRID = 16
 
 
-def network_input(counts, photons):
-    """log1p(max(d, 0)) / log1p(photons) of centred counts."""
-    return np.log1p(np.maximum(np.asarray(counts, np.float64), 0.0)) / np.log1p(photons)
+EST_EPS = 0.01   # regulariser of the probe division, relative to max |P|^2
+
+
+def probe_planes(probe):
+    """For a single-mode probe P (N x N, or 1 x N x N): the phase of its far
+    field, u = F(P) / |F(P)| (1 where F(P) = 0), and the regularised inverse
+    of the probe, g = conj(P) / (|P|^2 + EST_EPS max |P|^2)."""
+    p = np.asarray(probe, np.complex128).reshape(np.shape(probe)[-2:])
+    n = p.shape[-1]
+    fp = np.fft.fft2(p) / n
+    a = np.abs(fp)
+    u = np.where(a > 0, fp / np.where(a > 0, a, 1.0), 1.0)
+    p2 = np.abs(p) ** 2
+    return u, np.conj(p) / (p2 + EST_EPS * p2.max())
+
+
+def network_input(counts, probe):
+    """Real-space estimate of each window's object patch from its centred
+    counts (..., N, N): the measured moduli in natural order, A = sqrt(max(d,
+    0)), given the known probe's far-field phase, taken back to the sample
+    plane by the unitary inverse transform and multiplied by g,
+        est = g * F^-1(A u)  (= O for a flat, noise-free O times a real
+        constant, up to the regulariser);
+    its central (N/2) x (N/2) is upsampled 2x (nearest) to N x N, so that the
+    network's (N/2) x (N/2) output grid lies on the target patch's pixels.
+    Returns (..., N, N, 2): channels Re, Im."""
+    d = np.asarray(counts, np.float64)
+    n = d.shape[-1]
+    u, g = probe_planes(probe)
+    a = np.sqrt(np.maximum(np.fft.ifftshift(d, axes=(-2, -1)), 0.0))
+    x = np.fft.ifft2(a * u, axes=(-2, -1)) * n
+    est = (g * x)[..., n // 4:3 * n // 4, n // 4:3 * n // 4]
+    est = np.repeat(np.repeat(est, 2, axis=-2), 2, axis=-1)
+    return np.stack([est.real, est.imag], axis=-1)
 
 
 def targets(obj, pos, n=128):

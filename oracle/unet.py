@@ -1,12 +1,12 @@
 """FP64 reference of the learned initialiser's network (test infrastructure).
 
-A small U-Net maps one diffraction pattern (128 x 128, input log1p(counts) /
-log1p(photons)) to the amplitude and phase of the central 64 x 64 object patch
-under the probe.  The layer list (NHWC activations, 3 x 3 convolutions with
+A small U-Net maps the real-space estimate of one window's object patch
+(128 x 128, two channels: real and imaginary part; see seed.network_input) to
+the amplitude and phase of the central 64 x 64 object patch under the probe.  The layer list (NHWC activations, 3 x 3 convolutions with
 zero padding 1 and stride 1, 2 x 2 average pooling, 2x nearest upsampling,
 skip connections concatenated after the upsampled channels):
 
-    L0 conv  1 ->  32 @128 relu;  pool -> 64
+    L0 conv  2 ->  32 @128 relu;  pool -> 64
     L1 conv 32 ->  32 @64  relu  (e1);  pool -> 32
     L2 conv 32 ->  64 @32  relu  (e2);  pool -> 16
     L3 conv 64 -> 128 @16  relu  (e3);  pool -> 8
@@ -30,7 +30,7 @@ import numpy as np
 
 # (cin, cout, size, relu) of L0..L9
 LAYERS = [
-    (1, 32, 128, True),
+    (2, 32, 128, True),
     (32, 32, 64, True),
     (32, 64, 32, True),
     (64, 128, 16, True),
@@ -135,7 +135,7 @@ def up_backward(dy):
 
 
 def forward(flat, x):
-    """Network output (B, 64, 64, 2) for input x (B, 128, 128, 1), plus the cache."""
+    """Network output (B, 64, 64, 2) for input x (B, 128, 128, 2), plus the cache."""
     ps = unflatten(flat)
     W = ps[0::2]
     Bs = ps[1::2]

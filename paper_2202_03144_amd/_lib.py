@@ -115,12 +115,11 @@ SIGNATURES = {
                                C.POINTER(C.c_double)]),
     "pty_cnn_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                      C.POINTER(C.c_double)]),
-    "pty_cnn_input": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_double, C.c_void_p]),
+    "pty_cnn_input": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "pty_poisson": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_uint64]),
     "pty_training_targets": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pty_stitch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
-    "pty_seed_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
-                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pty_seed_object": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pty_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "pty_batch_iterate": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(IterParams)]),
     "pty_batch_sync": (C.c_int, [C.c_void_p]),

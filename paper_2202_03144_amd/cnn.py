@@ -12,6 +12,7 @@ from ._lib import PtyError
 from .plan import _is_torch, _ptr
 
 IN_SIZE = 128
+IN_CH = 2
 OUT_SIZE = 64
 
 
@@ -64,7 +65,7 @@ class Net:
 
     def forward(self, x, out):
         b = x.shape[0]
-        self._check(self._lib.pty_cnn_forward(self._live(), self._dev(x, (b, IN_SIZE, IN_SIZE), "x"), b,
+        self._check(self._lib.pty_cnn_forward(self._live(), self._dev(x, (b, IN_SIZE, IN_SIZE, IN_CH), "x"), b,
                                               self._dev(out, (b, OUT_SIZE, OUT_SIZE, 2), "out")))
         return out
 
@@ -73,7 +74,7 @@ class Net:
         b = x.shape[0]
         g = np.empty(self.num_params, dtype=np.float32)
         loss = C.c_double()
-        self._check(self._lib.pty_cnn_grad(self._live(), self._dev(x, (b, IN_SIZE, IN_SIZE), "x"),
+        self._check(self._lib.pty_cnn_grad(self._live(), self._dev(x, (b, IN_SIZE, IN_SIZE, IN_CH), "x"),
                                            self._dev(target, (b, OUT_SIZE, OUT_SIZE, 2), "target"), b,
                                            g.ctypes.data_as(C.c_void_p), C.byref(loss)))
         return loss.value, g
@@ -81,16 +82,20 @@ class Net:
     def train_step(self, x, target, lr: float) -> float:
         b = x.shape[0]
         loss = C.c_double()
-        self._check(self._lib.pty_cnn_train_step(self._live(), self._dev(x, (b, IN_SIZE, IN_SIZE), "x"),
+        self._check(self._lib.pty_cnn_train_step(self._live(), self._dev(x, (b, IN_SIZE, IN_SIZE, IN_CH), "x"),
                                                  self._dev(target, (b, OUT_SIZE, OUT_SIZE, 2), "target"), b,
                                                  float(lr), C.byref(loss)))
         return loss.value
 
-    def input(self, counts, photons: float, out):
-        """Network input log1p(max(d, 0)) / log1p(photons) of centred counts (CUDA tensors)."""
-        n = int(np.prod(counts.shape))
-        self._check(self._lib.pty_cnn_input(self._live(), self._dev(counts, counts.shape, "counts"), n,
-                                            float(photons), self._dev(out, out.shape, "out")))
+    def input(self, counts, probe, out):
+        """Network input (B, 128, 128, 2) from centred counts (B, 128, 128) and the
+        probe (1, 128, 128) complex64, all CUDA tensors (see pty_cnn_input)."""
+        b = counts.shape[0]
+        if not (_is_torch(probe) and probe.is_cuda):
+            raise TypeError("probe must be a CUDA tensor")
+        pp, _, _ = _ptr(probe, np.complex64, (1, IN_SIZE, IN_SIZE))
+        self._check(self._lib.pty_cnn_input(self._live(), self._dev(counts, (b, IN_SIZE, IN_SIZE), "counts"), b,
+                                            pp, self._dev(out, (b, IN_SIZE, IN_SIZE, IN_CH), "out")))
         return out
 
     def close(self) -> None:

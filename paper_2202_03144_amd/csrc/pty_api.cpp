@@ -1042,28 +1042,32 @@ double model_error(pty_ctx* c) {
 
 // Placement of each predicted patch: the central N/2 x N/2 of the window at
 // the nearest integer position.
-std::vector<int2> seed_placements(const pty_ctx* c) {
-  std::vector<int2> t(c->J);
-  for (int j = 0; j < c->J; ++j) {
-    const PosInfo& p = c->hpos[j];
-    t[j] = make_int2(p.iy + (p.fy >= 0.5f ? 1 : 0) + c->N / 4, p.ix + (p.fx >= 0.5f ? 1 : 0) + c->N / 4);
+// placements of the windows `sel` (all when empty)
+std::vector<int2> seed_placements(const pty_ctx* c, const std::vector<int>& sel) {
+  const int m = sel.empty() ? c->J : (int)sel.size();
+  std::vector<int2> t(m);
+  for (int i = 0; i < m; ++i) {
+    const PosInfo& p = c->hpos[sel.empty() ? i : sel[i]];
+    t[i] = make_int2(p.iy + (p.fy >= 0.5f ? 1 : 0) + c->N / 4, p.ix + (p.fx >= 0.5f ? 1 : 0) + c->N / 4);
   }
   return t;
 }
 
-// Stitches J patches (J x 64 x 64 x (amplitude, phase), device) into dst.
-void stitch(pty_ctx* c, const float* patches, float2* dst) {
+// Stitches the patches of windows `sel` (all when empty; |sel| x 64 x 64 x
+// (amplitude, phase), device, in that order) into dst.
+void stitch(pty_ctx* c, const float* patches, float2* dst, const std::vector<int>& sel = {}) {
   if (c->N != 128) throw Unsupported("stitching needs 128 x 128 windows (64 x 64 patches)");
-  const std::vector<int2> t = seed_placements(c);
+  const std::vector<int2> t = seed_placements(c, sel);
+  const int m = (int)t.size();
   const int bh = (c->H + 63) / 64, bw = (c->W + 63) / 64;
-  std::vector<int> beg(size_t(bh) * bw + 1, 0), idx(c->J);
-  for (int j = 0; j < c->J; ++j) beg[size_t(t[j].x / 64) * bw + t[j].y / 64 + 1]++;
+  std::vector<int> beg(size_t(bh) * bw + 1, 0), idx(m);
+  for (int j = 0; j < m; ++j) beg[size_t(t[j].x / 64) * bw + t[j].y / 64 + 1]++;
   for (size_t b = 0; b < size_t(bh) * bw; ++b) beg[b + 1] += beg[b];
   std::vector<int> fill(beg.begin(), beg.end() - 1);
-  for (int j = 0; j < c->J; ++j) idx[fill[size_t(t[j].x / 64) * bw + t[j].y / 64]++] = j;
+  for (int j = 0; j < m; ++j) idx[fill[size_t(t[j].x / 64) * bw + t[j].y / 64]++] = j;
   const int gs = seed_chain_grid();
   const int hc = (c->H + gs - 1) / gs, wc = (c->W + gs - 1) / gs;
-  int2* d_t = c->alloc<int2>(c->J);
+  int2* d_t = c->alloc<int2>(m);
   int* d_beg = nullptr;
   int* d_idx = nullptr;
   float2* d_S = nullptr;
@@ -1072,12 +1076,12 @@ void stitch(pty_ctx* c, const float* patches, float2* dst) {
     d_beg = c->alloc<int>(beg.size());
     d_idx = c->alloc<int>(idx.size());
     d_S = c->alloc<float2>(size_t(hc) * wc);
-    d_ph = c->alloc<float2>(c->J);
-    PTY_HIP(hipMemcpyAsync(d_t, t.data(), sizeof(int2) * c->J, hipMemcpyHostToDevice, c->stream));
+    d_ph = c->alloc<float2>(m);
+    PTY_HIP(hipMemcpyAsync(d_t, t.data(), sizeof(int2) * m, hipMemcpyHostToDevice, c->stream));
     PTY_HIP(hipMemcpyAsync(d_beg, beg.data(), sizeof(int) * beg.size(), hipMemcpyHostToDevice, c->stream));
     PTY_HIP(hipMemcpyAsync(d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
     launch_fill_u32(reinterpret_cast<unsigned*>(d_S), size_t(hc) * wc * 2, 0u, c->stream);
-    launch_seed_chain(patches, d_t, c->J, d_S, hc, wc, d_ph, c->stream);
+    launch_seed_chain(patches, d_t, m, d_S, hc, wc, d_ph, c->stream);
     launch_seed_stitch(patches, d_t, d_ph, d_beg, d_idx, bw, bh, dst, c->H, c->W, c->stream);
     PTY_HIP(hipStreamSynchronize(c->stream));
   } catch (...) {
@@ -2014,39 +2018,46 @@ pty_status pty_stitch(pty_ctx* c, const float* patches, void* out) {
   });
 }
 
-pty_status pty_seed_object(pty_ctx* c, pty_cnn* net, double photons, int32_t batch, int32_t fallback,
+pty_status pty_seed_object(pty_ctx* c, pty_cnn* net, int32_t batch, int32_t stride, int32_t fallback,
                            int32_t* used_fallback, double* e_seed, double* e_flat) {
   return guarded(c, [&] {
     require(c != nullptr && net != nullptr, "pty_seed_object: null argument");
-    require(std::isfinite(photons) && photons > 1.0, "pty_seed_object: photons must be > 1");
     require(batch >= 1 && batch <= cnn_max_batch(net), "pty_seed_object: batch must be in 1..max_batch");
+    require(stride >= 1, "pty_seed_object: stride must be >= 1");
     if (c->N != 128) throw Unsupported("the learned seed needs 128 x 128 windows");
     if (cnn_device(net) != c->device) throw InvalidArg("pty_seed_object: network on another device");
     if (!c->have_patterns) throw StateError("patterns not loaded");
     if (!c->have_positions) throw StateError("positions not loaded");
-    if (fallback && !c->have_probe) throw StateError("probe not set");
+    if (!c->have_probe) throw StateError("probe not set");
     c->set_device();
+    std::vector<int> sel;
+    for (int j = 0; j < c->J; j += stride) sel.push_back(j);
+    const int m = (int)sel.size();
+    const size_t nn = size_t(c->N) * c->N;
     const size_t per = size_t(64) * 64 * 2;
-    c->ensure(c->seed_patches, c->seed_patches_n, size_t(c->J) * per);
-    const float inv = (float)(1.0 / std::log1p(photons));
+    c->ensure(c->seed_patches, c->seed_patches_n, size_t(m) * per + 4 * nn + size_t(m));
+    float2* planes = reinterpret_cast<float2*>(c->seed_patches + size_t(m) * per);
+    int* d_sel = reinterpret_cast<int*>(planes + 2 * nn);
+    PTY_HIP(hipMemcpyAsync(d_sel, sel.data(), sizeof(int) * m, hipMemcpyHostToDevice, c->stream));
+    launch_seed_planes(c->probe, planes, planes + nn, c->stream);
     float* x = cnn_input_buffer(net);
-    for (int j0 = 0; j0 < c->J; j0 += batch) {
-      const int nb = std::min(batch, c->J - j0);
-      launch_input_from_amp(c->amp, c->N, j0, nb, x, inv, c->stream);
+    for (int i0 = 0; i0 < m; i0 += batch) {
+      const int nb = std::min(batch, m - i0);
+      launch_seed_input_amp(c->amp, d_sel + i0, nb, planes, planes + nn, x, c->stream);
       const float* y = cnn_forward_batch(net, x, nb, c->stream);
-      PTY_HIP(hipMemcpyAsync(c->seed_patches + size_t(j0) * per, y, sizeof(float) * per * nb,
+      PTY_HIP(hipMemcpyAsync(c->seed_patches + size_t(i0) * per, y, sizeof(float) * per * nb,
                              hipMemcpyDeviceToDevice, c->stream));
     }
     const size_t hw = size_t(c->H) * c->W;
     if (!fallback) {
-      stitch(c, c->seed_patches, c->obj);
+      stitch(c, c->seed_patches, c->obj, sel);
       c->have_object = true;
       c->dm_valid = false;
       if (used_fallback) *used_fallback = 0;
       return;
     }
     c->ensure_once(c->seed_obj, hw);
-    stitch(c, c->seed_patches, c->seed_obj);
+    stitch(c, c->seed_patches, c->seed_obj, sel);
     PTY_HIP(hipMemcpyAsync(c->obj, c->seed_obj, hw * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
     const double es = model_error(c);
     launch_fill_c64(c->obj, hw, make_float2(1.f, 0.f), c->stream);

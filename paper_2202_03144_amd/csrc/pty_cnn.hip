@@ -3,13 +3,15 @@
 // Architecture (NHWC activations, 3 x 3 convolutions with zero padding 1,
 // 2 x 2 average pooling, 2x nearest upsampling, skips concatenated after the
 // upsampled channels):
-//   L0 conv 1->32 @128 relu, pool; L1 32->32 @64 relu (e1), pool;
+//   L0 conv 2->32 @128 relu, pool; L1 32->32 @64 relu (e1), pool;
 //   L2 32->64 @32 relu (e2), pool; L3 64->128 @16 relu (e3), pool;
 //   L4 128->256 @8 relu; L5 256->256 @8 relu, up, concat e3;
 //   L6 384->128 @16 relu, up, concat e2; L7 192->64 @32 relu, up, concat e1;
 //   L8 96->32 @64 relu; L9 32->2 @64 linear (amplitude, phase).
-// Input: one 128 x 128 pattern as log1p(counts) / log1p(photons); output: the
-// central 64 x 64 object patch.  Weights W[cout][ky][kx][cin] (bf16 copies of
+// Input: a real-space estimate of one window's object patch, 128 x 128 x 2
+// (real and imaginary part; the pattern's moduli with the known probe's
+// far-field phase, transformed back and divided by the probe, central half
+// upsampled 2x); output: the central 64 x 64 object patch.  Weights W[cout][ky][kx][cin] (bf16 copies of
 // float32 masters), biases float32; loss = mean squared error; Adam.
 //
 // Convolutions with cin, cout multiples of 32 are implicit GEMMs on
@@ -20,7 +22,7 @@
 // weights; the weight gradient is an
 // MFMA GEMM over pixels with split-K partials summed in a fixed order.  The
 // 2-channel output layer runs on the halo kernel over weights zero-padded to
-// 16 channels; the 1-channel input layer is a direct kernel.
+// 16 channels; the 2-channel input layer is a direct kernel.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -525,29 +527,32 @@ __global__ void k_wflip(const bf16* __restrict__ w, bf16* __restrict__ wt, int c
 }
 
 // ---------------------------------------------------------------------------
-// The 1-channel input layer and the 2-channel output layer
+// The 2-channel input and output layers
 // ---------------------------------------------------------------------------
 // L0 + ReLU + 2 x 2 pooling: one thread per pooled pixel computes the four
 // 32-channel pre-activations below it; writes the pooled p0 and, for
 // training, the activations a0.
+constexpr int kIn = 2;   // input channels (Re, Im of the estimate)
 template <bool STORE_A0>
 __global__ __launch_bounds__(256) void k_conv_in_pool(const float* __restrict__ x, const bf16* __restrict__ w,
                                                       const float* __restrict__ bias, View a0, View p0, int nb) {
-  constexpr int S = 128, P = 64, C = 32;
-  __shared__ float ws[C * 9], bs[C];
-  for (int i = threadIdx.x; i < C * 9; i += 256) ws[i] = tof(w[i]);
+  constexpr int S = 128, P = 64, C = 32, CI = kIn;
+  __shared__ float ws[C * 9 * CI], bs[C];
+  for (int i = threadIdx.x; i < C * 9 * CI; i += 256) ws[i] = tof(w[i]);
   if (threadIdx.x < C) bs[threadIdx.x] = bias[threadIdx.x];
   __syncthreads();
   const size_t q = blockIdx.x * (size_t)256 + threadIdx.x;
   if (q >= (size_t)nb * P * P) return;
   const int b = (int)(q / (P * P)), py = (int)(q / P) % P, px = (int)(q % P);
-  float v[4][4];  // input rows 2py-1 .. 2py+2, cols 2px-1 .. 2px+2
+  float v[4][4][CI];  // input rows 2py-1 .. 2py+2, cols 2px-1 .. 2px+2
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int yy = 2 * py - 1 + r, xx = 2 * px - 1 + c;
-      v[r][c] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) ? x[((size_t)b * S + yy) * S + xx] : 0.f;
+      const bool ok = (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
+#pragma unroll
+      for (int ci = 0; ci < CI; ++ci) v[r][c][ci] = ok ? x[(((size_t)b * S + yy) * S + xx) * CI + ci] : 0.f;
     }
 #pragma unroll 1
   for (int g = 0; g < C; g += 8) {
@@ -563,7 +568,9 @@ __global__ __launch_bounds__(256) void k_conv_in_pool(const float* __restrict__ 
         for (int k = 0; k < 8; ++k) {
           float s = bs[g + k];
 #pragma unroll
-          for (int tap = 0; tap < 9; ++tap) s += v[sy + tap / 3][sx + tap % 3] * ws[(g + k) * 9 + tap];
+          for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int ci = 0; ci < CI; ++ci) s += v[sy + tap / 3][sx + tap % 3][ci] * ws[((g + k) * 9 + tap) * CI + ci];
           o[k] = fmaxf(s, 0.f);
           pool[k] += o[k];
         }
@@ -622,24 +629,27 @@ __global__ __launch_bounds__(256) void k_conv_out_dgrad(const float* __restrict_
 // gradient and the ReLU of a0: dz[p][n] = (a0[p][n] > 0) gp0[parent(p)][n] / 4.
 // part[block][n * 10 + k]: k < 9 tap, k = 9 bias.
 constexpr int kInRows = 4;
+constexpr int kInK = 9 * kIn + 1;   // weight-gradient entries per output channel (taps x channels, bias)
 __global__ __launch_bounds__(256) void k_wgrad_in(const float* __restrict__ x, View a0, View gp0,
                                                   float* __restrict__ part, int nb) {
-  constexpr int S = 128, C = 32, R = kInRows;
-  __shared__ float xs[R + 2][S + 2];
+  constexpr int S = 128, C = 32, R = kInRows, CI = kIn, K = kInK;
+  __shared__ float xs[R + 2][S + 2][CI];
   __shared__ float ds[R * S][C + 1];
-  __shared__ float red[8][C * 10];
+  __shared__ float red[8][C * K];
   const int n = threadIdx.x & 31, q = threadIdx.x >> 5;
-  float acc[10];
+  float acc[K];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) acc[k] = 0.f;
+  for (int k = 0; k < K; ++k) acc[k] = 0.f;
   const int bands = nb * (S / R);
   for (int band = blockIdx.x; band < bands; band += gridDim.x) {
     const int b = band / (S / R), y0 = (band % (S / R)) * R;
     __syncthreads();
-    for (int i = threadIdx.x; i < (R + 2) * (S + 2); i += 256) {
-      const int r = i / (S + 2), cc = i % (S + 2);
+    for (int i = threadIdx.x; i < (R + 2) * (S + 2) * CI; i += 256) {
+      const int ci = i % CI, rc = i / CI;
+      const int r = rc / (S + 2), cc = rc % (S + 2);
       const int yy = y0 - 1 + r, xx = cc - 1;
-      xs[r][cc] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S) ? x[((size_t)b * S + yy) * S + xx] : 0.f;
+      xs[r][cc][ci] = ((unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S)
+                          ? x[(((size_t)b * S + yy) * S + xx) * CI + ci] : 0.f;
     }
     for (int i = threadIdx.x; i < R * S * (C / 8); i += 256) {
       const int pix = i / (C / 8), g = (i % (C / 8)) * 8;
@@ -655,19 +665,21 @@ __global__ __launch_bounds__(256) void k_wgrad_in(const float* __restrict__ x, V
       const int r = pix / S, cc = pix % S;
       const float d = ds[pix][n];
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap) acc[tap] += d * xs[r + tap / 3][cc + tap % 3];
-      acc[9] += d;
+      for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) acc[tap * CI + ci] += d * xs[r + tap / 3][cc + tap % 3][ci];
+      acc[K - 1] += d;
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 10; ++k) red[q][n * 10 + k] = acc[k];
+  for (int k = 0; k < K; ++k) red[q][n * K + k] = acc[k];
   __syncthreads();
-  for (int i = threadIdx.x; i < C * 10; i += 256) {
+  for (int i = threadIdx.x; i < C * K; i += 256) {
     float s = 0.f;
 #pragma unroll
     for (int qq = 0; qq < 8; ++qq) s += red[qq][i];
-    part[(size_t)blockIdx.x * C * 10 + i] = s;
+    part[(size_t)blockIdx.x * C * K + i] = s;
   }
 }
 
@@ -861,10 +873,6 @@ __global__ void k_to_bf16(const float* __restrict__ src, bf16* __restrict__ dst,
 }
 
 // network input from centred counts: log1p(max(d, 0)) / log1p(photons)
-__global__ void k_cnn_input(const float* __restrict__ d, float* __restrict__ x, size_t n, float inv) {
-  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i < n) x[i] = log1pf(fmaxf(d[i], 0.f)) * inv;
-}
 
 inline unsigned blocks(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -878,7 +886,7 @@ struct Conv {
 };
 
 constexpr int kLayers = 10;
-const int kSpec[kLayers][4] = {{1, 32, 128, 1},   {32, 32, 64, 1},   {32, 64, 32, 1},  {64, 128, 16, 1},
+const int kSpec[kLayers][4] = {{kIn, 32, 128, 1},   {32, 32, 64, 1},   {32, 64, 32, 1},  {64, 128, 16, 1},
                                {128, 256, 8, 1},  {256, 256, 8, 1},  {384, 128, 16, 1}, {192, 64, 32, 1},
                                {96, 32, 64, 1},   {32, 2, 64, 0}};
 
@@ -911,6 +919,7 @@ struct pty_cnn {
   // gradients
   bf16 *gp0, *gcat8, *gp1, *gcat7, *gp2, *gcat6, *gp3, *g4, *g5, *g6, *g7, *g8;
   float *y, *gy, *xin;
+  float2* planes = nullptr;   // the input's far-field phase and inverse-probe planes
 
   void* dalloc(size_t bytes) {
     void* q = nullptr;
@@ -1126,11 +1135,12 @@ void backward(pty_cnn* c, const float* x, int nb) {
   launch_dgrad(c, 1, V(c->gcat8, 96, 64), V(c->gp0, 32), nb);
   // L0: dz formed inside the tiled weight-gradient kernel from gp0 and a0
   {
-    const int grid = std::min(nb * (128 / kInRows), kSmallGrid), np = 32 * 10;
+    const int grid = std::min(nb * (128 / kInRows), kSmallGrid), np = 32 * kInK;
     k_wgrad_in<<<grid, 256, 0, s>>>(x, V(c->a0, 32), V(c->gp0, 32), c->part, nb);
     k_sum_splits<<<blocks(np), 256, 0, s>>>(c->part, grid, np, c->part + (size_t)grid * np);
     PTY_LAUNCH_CHECK("wgrad_in");
-    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)grid * np, 9, 32, c->g + L[0].woff, c->g + L[0].boff);
+    k_unpack_wb<<<blocks(np), 256, 0, s>>>(c->part + (size_t)grid * np, kInK - 1, 32, c->g + L[0].woff,
+                                           c->g + L[0].boff);
   }
   PTY_LAUNCH_CHECK("cnn_backward");
 }
@@ -1264,7 +1274,8 @@ pty_status pty_cnn_create(int32_t device, void* stream, int32_t max_batch, uint6
     c->g8 = act(4096, 32);
     c->y = c->alloc<float>(B * 4096 * 2);
     c->gy = c->alloc<float>(B * 4096 * 2);
-    c->xin = c->alloc<float>(B * 16384);
+    c->xin = c->alloc<float>(B * 16384 * kIn);
+    c->planes = c->alloc<float2>(2 * 16384);
     // split-K scratch: the largest (splits x weights) of any layer, plus unpack room
     size_t need = 0;
     for (int i = 0; i < kLayers; ++i) {
@@ -1274,6 +1285,7 @@ pty_status pty_cnn_create(int32_t device, void* stream, int32_t max_batch, uint6
     }
     // the tiled L0 / L9 weight gradients: up to kSmallGrid block partials plus their sums
     need = std::max(need, (size_t)(kSmallGrid + 1) * 2 * (9 * 32 + 1));
+    need = std::max(need, (size_t)(kSmallGrid + 1) * 32 * kInK);
     c->part = c->alloc<float>(need);
     c->part_n = need;
     c->lpart = c->alloc<double>(blocks(B * 4096 * 2) + 16);
@@ -1357,13 +1369,13 @@ pty_status pty_cnn_train_step(pty_cnn* c, const float* x, const float* target, i
   });
 }
 
-pty_status pty_cnn_input(pty_cnn* c, const float* counts, size_t n, double photons, float* x) {
+pty_status pty_cnn_input(pty_cnn* c, const float* counts, int32_t batch, const void* probe, float* x) {
   return cnn_guard(c, [&] {
-    if (!c || !counts || !x) throw std::invalid_argument("pty_cnn_input: null argument");
-    if (!(photons > 1.0)) throw std::invalid_argument("pty_cnn_input: photons must be > 1");
+    if (!c || !counts || !probe || !x) throw std::invalid_argument("pty_cnn_input: null argument");
+    if (batch < 1) throw std::invalid_argument("pty_cnn_input: batch must be >= 1");
     PTY_HIP(hipSetDevice(c->device));
-    k_cnn_input<<<blocks(n), 256, 0, c->stream>>>(counts, x, n, (float)(1.0 / std::log1p(photons)));
-    PTY_LAUNCH_CHECK("cnn_input");
+    launch_seed_planes(static_cast<const float2*>(probe), c->planes, c->planes + 16384, c->stream);
+    launch_seed_input_counts(counts, batch, c->planes, c->planes + 16384, x, c->stream);
     PTY_HIP(hipStreamSynchronize(c->stream));
   });
 }

@@ -267,7 +267,13 @@ void launch_err_scatter(const double* local, const int* jmap, int count, int per
 // Learned initialiser data path and evaluation helpers.
 void launch_fill_c64(float2* p, size_t n, float2 v, hipStream_t s);
 void launch_poisson(const float* lam, float* out, size_t n, uint64_t seed, hipStream_t s);
-void launch_input_from_amp(const float* amp, int n, int j0, int nb, float* x, float inv, hipStream_t s);
+// Network input (128 x 128 windows): u = F(P0) / |F(P0)| and
+// g = conj(P0) / (|P0|^2 + 0.01 max |P0|^2) from probe mode 0, then per window
+// the central 64 x 64 of g F^-1(A u), upsampled 2x, as 128 x 128 x (Re, Im).
+void launch_seed_planes(const float2* probe, float2* u, float2* g, hipStream_t s);
+void launch_seed_input_counts(const float* counts, int nb, const float2* u, const float2* g, float* x, hipStream_t s);
+void launch_seed_input_amp(const float* amp, const int* jsel, int nb, const float2* u, const float2* g, float* x,
+                           hipStream_t s);
 void launch_targets(const float2* obj, int w, const PosInfo* pos, int j, int n, float* out, hipStream_t s);
 int seed_chain_grid();   // spacing of the chain's coarse sample grid (object pixels)
 void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int hc, int wc, float2* phasor,

@@ -8,6 +8,8 @@
 #include <cstdint>
 
 #include "pty_common.hpp"
+#include "pty_fft.hpp"
+#include "pty_geom.hpp"
 #include "pty_kernels.hpp"
 
 namespace pty {
@@ -73,17 +75,140 @@ __global__ void k_poisson(const float* __restrict__ lam, float* __restrict__ out
   out[i] = r;
 }
 
-// Network input of pattern j0 + b from the measured moduli (natural order):
-// x[b][y][x] = log1p(A^2 at the centred pixel (y, x)) * inv.
-__global__ void k_input_from_amp(const float* __restrict__ amp, int n, int j0, int nb, float* __restrict__ x,
-                                 float inv) {
-  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const size_t nn = (size_t)n * n;
-  if (i >= (size_t)nb * nn) return;
-  const int b = (int)(i / nn), q = (int)(i % nn), y = q / n, xx = q % n;
-  const int h = n / 2;
-  const float a = amp[(size_t)(j0 + b) * nn + (size_t)((y + h) % n) * n + (xx + h) % n];
-  x[i] = log1pf(a * a) * inv;
+// ---------------------------------------------------------------------------
+// Network input: a real-space estimate of each window's object patch,
+//   est = g * F^-1(A u),   u = F(P) / |F(P)|,   g = conj(P) / (|P|^2 + 0.01 max |P|^2),
+// A the measured moduli in natural order; the central 64 x 64 of est is
+// written upsampled 2x (nearest) as a 128 x 128 x 2 (Re, Im) input.  One
+// 128 x 128 window per block of 128 threads (16 lines of 8), transformed in
+// LDS (rows padded to 129 entries against bank conflicts).
+// ---------------------------------------------------------------------------
+constexpr int kSeedN = 128;
+constexpr int kSeedPitch = kSeedN + 1;
+constexpr int kSeedThreads = 128;
+constexpr int kSeedT = FftShape<kSeedN>::T, kSeedR = FftShape<kSeedN>::R;
+constexpr int kSeedLines = kSeedThreads / kSeedT;
+static_assert(kSeedT * kSeedR == kSeedN && kSeedLines * kSeedT == kSeedThreads, "seed input tiling");
+
+struct SeedLds {
+  float2 data[kSeedN * kSeedPitch];
+  float2 xb[kSeedLines * LineLds<kSeedN>::words];
+  float2 tw[kSeedN];
+};
+
+// W_128^i = exp(-2 pi i i / 128) from the double-precision sine and cosine
+__device__ void seed_twiddles(float2* tw) {
+  for (int i = threadIdx.x; i < kSeedN; i += kSeedThreads) {
+    double sn, cs;
+    sincospi(-2.0 * i / kSeedN, &sn, &cs);
+    tw[i] = make_float2((float)cs, (float)sn);
+  }
+}
+
+// line transforms of every row of the LDS window (unscaled)
+template <bool INV>
+__device__ void seed_rows(SeedLds& L) {
+  const int line = threadIdx.x / kSeedT, t = threadIdx.x % kSeedT;
+  for (int r0 = 0; r0 < kSeedN; r0 += kSeedLines) {
+    float2* row = L.data + (r0 + line) * kSeedPitch;
+    float2 v[kSeedR];
+#pragma unroll
+    for (int m = 0; m < kSeedR; ++m) v[m] = row[t + kSeedT * m];
+    line_fft<kSeedN, INV>(v, L.xb + line * LineLds<kSeedN>::words, L.tw, t);
+#pragma unroll
+    for (int m = 0; m < kSeedR; ++m) row[t + kSeedT * m] = v[m];
+  }
+}
+
+// F(P) / |F(P)| and g of mode 0 of the probe (one block)
+__global__ __launch_bounds__(kSeedThreads) void k_seed_planes(const float2* __restrict__ probe, float2* __restrict__ u,
+                                                              float2* __restrict__ g) {
+  __shared__ SeedLds L;
+  __shared__ float redf[kSeedThreads / 64];
+  seed_twiddles(L.tw);
+  float mx = 0.f;
+  for (int q = threadIdx.x; q < kSeedN * kSeedN; q += kSeedThreads) {
+    const float2 p = probe[q];
+    L.data[(q / kSeedN) * kSeedPitch + q % kSeedN] = p;
+    mx = fmaxf(mx, cabs2(p));
+  }
+  mx = block_max_all<kSeedThreads>(mx, redf);
+  const float eps = 0.01f * mx;
+  for (int q = threadIdx.x; q < kSeedN * kSeedN; q += kSeedThreads) {
+    const float2 p = probe[q];
+    const float d = cabs2(p) + eps;
+    g[q] = d > 0.f ? make_float2(p.x / d, -p.y / d) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  seed_rows<false>(L);
+  __syncthreads();
+  // columns: every column, transposed through registers
+  const int line = threadIdx.x / kSeedT, t = threadIdx.x % kSeedT;
+  for (int c0 = 0; c0 < kSeedN; c0 += kSeedLines) {
+    const int c = c0 + line;
+    float2 v[kSeedR];
+#pragma unroll
+    for (int m = 0; m < kSeedR; ++m) v[m] = L.data[(t + kSeedT * m) * kSeedPitch + c];
+    line_fft<kSeedN, false>(v, L.xb + line * LineLds<kSeedN>::words, L.tw, t);
+#pragma unroll
+    for (int m = 0; m < kSeedR; ++m) {
+      const float a = sqrtf(cabs2(v[m]));
+      u[(t + kSeedT * m) * kSeedN + c] = a > 0.f ? make_float2(v[m].x / a, v[m].y / a) : make_float2(1.f, 0.f);
+    }
+  }
+}
+
+// One window per block.  FROM_COUNTS: centred counts of window b (training);
+// else the context's natural-order moduli of pattern jsel[b] (a set sign bit,
+// a masked pixel, reads as 0).
+template <bool FROM_COUNTS>
+__global__ __launch_bounds__(kSeedThreads) void k_seed_input(const float* __restrict__ src, const int* __restrict__ jsel,
+                                                             const float2* __restrict__ u, const float2* __restrict__ g,
+                                                             float* __restrict__ x) {
+  __shared__ SeedLds L;
+  seed_twiddles(L.tw);
+  const int b = blockIdx.x;
+  const size_t base = (size_t)(FROM_COUNTS ? b : jsel[b]) * kSeedN * kSeedN;
+  for (int q = threadIdx.x; q < kSeedN * kSeedN; q += kSeedThreads) {
+    const int r = q / kSeedN, c = q % kSeedN;
+    float a;
+    if constexpr (FROM_COUNTS) {
+      const float d = src[base + (size_t)((r + kSeedN / 2) % kSeedN) * kSeedN + (c + kSeedN / 2) % kSeedN];
+      a = sqrtf(fmaxf(d, 0.f));
+    } else {
+      const float m = src[base + q];
+      a = signbit(m) ? 0.f : m;
+    }
+    const float2 w = u[q];
+    L.data[r * kSeedPitch + c] = make_float2(a * w.x, a * w.y);
+  }
+  __syncthreads();
+  seed_rows<true>(L);
+  __syncthreads();
+  // columns of the central half only; keep its central rows
+  const int line = threadIdx.x / kSeedT, t = threadIdx.x % kSeedT;
+  constexpr int Q = kSeedN / 4;
+  constexpr float inv_n = 1.0f / kSeedN;
+  float* xo = x + (size_t)b * kSeedN * kSeedN * 2;
+  for (int c0 = Q; c0 < 3 * Q; c0 += kSeedLines) {
+    const int c = c0 + line;
+    float2 v[kSeedR];
+#pragma unroll
+    for (int m = 0; m < kSeedR; ++m) v[m] = L.data[(t + kSeedT * m) * kSeedPitch + c];
+    line_fft<kSeedN, true>(v, L.xb + line * LineLds<kSeedN>::words, L.tw, t);
+#pragma unroll
+    for (int m = 0; m < kSeedR; ++m) {
+      const int r = t + kSeedT * m;
+      if (r < Q || r >= 3 * Q) continue;
+      const float2 e = cmul(g[r * kSeedN + c], inv_n * v[m]);
+      const int y = 2 * (r - Q), xx = 2 * (c - Q);
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx)
+          reinterpret_cast<float2*>(xo)[(size_t)(y + dy) * kSeedN + xx + dx] = e;
+    }
+  }
 }
 
 // Training targets: amplitude and phase (relative to the mean phasor) of the
@@ -299,8 +424,21 @@ void launch_poisson(const float* lam, float* out, size_t n, uint64_t seed, hipSt
   PTY_LAUNCH_CHECK("poisson");
 }
 
-void launch_input_from_amp(const float* amp, int n, int j0, int nb, float* x, float inv, hipStream_t s) {
-  k_input_from_amp<<<nblk((size_t)nb * n * n), 256, 0, s>>>(amp, n, j0, nb, x, inv);
+void launch_seed_planes(const float2* probe, float2* u, float2* g, hipStream_t s) {
+  k_seed_planes<<<1, kSeedThreads, 0, s>>>(probe, u, g);
+  PTY_LAUNCH_CHECK("seed_planes");
+}
+
+void launch_seed_input_counts(const float* counts, int nb, const float2* u, const float2* g, float* x, hipStream_t s) {
+  if (nb <= 0) return;
+  k_seed_input<true><<<nb, kSeedThreads, 0, s>>>(counts, nullptr, u, g, x);
+  PTY_LAUNCH_CHECK("seed_input");
+}
+
+void launch_seed_input_amp(const float* amp, const int* jsel, int nb, const float2* u, const float2* g, float* x,
+                           hipStream_t s) {
+  if (nb <= 0) return;
+  k_seed_input<false><<<nb, kSeedThreads, 0, s>>>(amp, jsel, u, g, x);
   PTY_LAUNCH_CHECK("input_from_amp");
 }
 

@@ -4,7 +4,8 @@ marshalling and scheduling only; every step runs in the library's kernels).
 Training data are made on the device: for a batch of random integer window
 positions on a training object, the forward model gives the expected counts
 (``Plan.simulate``), ``Plan.poisson`` draws the counts, ``Net.input`` forms the
-network input and ``Plan.training_targets`` the targets (amplitude and phase
+network input (the real-space estimate from the counts and the probe) and
+``Plan.training_targets`` the targets (amplitude and phase
 relative to the mean phasor of the central 64 x 64 patch).
 """
 from __future__ import annotations
@@ -37,7 +38,8 @@ def train(net: Net, objects, probe, photons: float, steps: int, batch: int, lr: 
     dev = objects[0].device
     lam = torch.empty((batch, 128, 128), dtype=torch.float32, device=dev)
     cnt = torch.empty_like(lam)
-    x = torch.empty_like(lam)
+    x = torch.empty((batch, 128, 128, 2), dtype=torch.float32, device=dev)
+    probe_dev = None
     tg = torch.empty((batch, 64, 64, 2), dtype=torch.float32, device=dev)
     t0 = time.perf_counter()
     with Plan(128, 1, batch, (h, w)) as pl:
@@ -49,9 +51,11 @@ def train(net: Net, objects, probe, photons: float, steps: int, batch: int, lr: 
             pos = np.stack([rng.integers(0, h - 128, batch), rng.integers(0, w - 128, batch)], axis=1)
             pl.load_positions(pos.astype(np.float64))
             pl.simulate(0.0 if scaled else photons, out=lam)
+            if not scaled:
+                probe_dev = torch.from_numpy(pl.probe()).to(dev)   # scaled to the photon budget
             scaled = True
             pl.poisson(lam, cnt, seed=(seed << 32) + s)
-            net.input(cnt, photons, x)
+            net.input(cnt, probe_dev, x)
             pl.training_targets(tg)
             rate = lr if lr_final is None else lr * (lr_final / lr) ** (s / max(1, steps - 1))
             losses.append(net.train_step(x, tg, rate))

@@ -300,12 +300,12 @@ class Plan:
         self._check(self._lib.pty_stitch(self._live(), pp, po))
         return out
 
-    def seed_object(self, net, photons: float, batch: int = 4096, fallback: bool = True) -> dict:
-        """Learned seed of the object from the loaded patterns (see pty_seed_object)."""
+    def seed_object(self, net, batch: int = 4096, stride: int = 1, fallback: bool = True) -> dict:
+        """Learned seed of the object from every stride-th loaded pattern (see pty_seed_object)."""
         used = C.c_int32()
         es = C.c_double(float("nan"))
         ef = C.c_double(float("nan"))
-        self._check(self._lib.pty_seed_object(self._live(), net._live(), float(photons), int(batch),
+        self._check(self._lib.pty_seed_object(self._live(), net._live(), int(batch), int(stride),
                                               1 if fallback else 0, C.byref(used), C.byref(es), C.byref(ef)))
         return {"used_fallback": bool(used.value), "e_seed": es.value, "e_flat": ef.value}
 

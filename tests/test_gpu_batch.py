@@ -154,7 +154,7 @@ def test_error_paths_of_the_newer_entry_points():
             pl.stitch(torch.zeros((20, 64, 64, 2), dtype=torch.float32, device="cuda"))
         with Net(4, seed=0) as net:
             with pytest.raises(PtyError, match="UNSUPPORTED"):
-                pl.seed_object(net, 1e6, batch=4)     # the network takes 128 x 128 windows
+                pl.seed_object(net, batch=4)     # the network takes 128 x 128 windows
         with pytest.raises(PtyError, match="INVALID"):
             pl.set_truth(c64(case.obj_true), 1.5)     # roi_frac outside [0, 1]
         with pytest.raises(PtyError, match="INVALID"):

@@ -4,8 +4,8 @@ oracle.seed, oracle.ptycho), which are pinned on the CPU.
 The network computes with bf16 weights and activations and float32
 accumulation; the reference is evaluated in FP64 with the same bf16-rounded
 weights, so the tolerance covers only the rounding of activations and
-gradients to bf16 (8 significant bits): relative L2 error 3e-2 for outputs
-and 6e-2 per layer for gradients."""
+gradients to bf16 (8 significant bits): relative L2 error 1e-2 for outputs
+and 3e-2 per layer for gradients."""
 import numpy as np
 import pytest
 
@@ -17,8 +17,8 @@ from _cases import c64
 
 pytestmark = pytest.mark.gpu
 
-TOL_Y = 3e-2
-TOL_G = 6e-2
+TOL_Y = 1e-2
+TOL_G = 3e-2
 
 
 def _bf16(a):
@@ -59,8 +59,8 @@ def _inputs(b, seed=12):
     obj = ptysynth.make_object(40 + seed, 128 + 16 * b, 144, wl.sigma_o)
     probe = wl.probe()
     pos = np.array([[16.0 * i, 8.0] for i in range(b)])
-    cnt, _ = oracle.simulate(obj, probe, pos, wl.photons)
-    return oseed.network_input(cnt, wl.photons), obj, pos
+    cnt, pr = oracle.simulate(obj, probe, pos, wl.photons)
+    return oseed.network_input(cnt, pr), obj, pos
 
 
 def _net(b, flat):
@@ -79,7 +79,7 @@ def test_forward_matches_oracle():
     xt = torch.from_numpy(x.astype(np.float32)).cuda()
     y = torch.empty((b, 64, 64, 2), dtype=torch.float32, device="cuda")
     net.forward(xt, y)
-    ref, _ = unet.forward(_as_kernel_sees(flat), x.astype(np.float32).astype(np.float64)[..., None])
+    ref, _ = unet.forward(_as_kernel_sees(flat), x.astype(np.float32).astype(np.float64))
     err = _rel(y.cpu().numpy(), ref)
     print("forward rel err", err)
     assert err <= TOL_Y
@@ -97,7 +97,7 @@ def test_gradient_matches_oracle():
     t = (0.3 * rng.standard_normal((b, 64, 64, 2))).astype(np.float32)
     net = _net(b, flat)
     loss, g = net.grad(torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(t).cuda())
-    rl, rg = unet.loss_and_grad(_as_kernel_sees(flat), x.astype(np.float32).astype(np.float64)[..., None],
+    rl, rg = unet.loss_and_grad(_as_kernel_sees(flat), x.astype(np.float32).astype(np.float64),
                                 t.astype(np.float64))
     print("loss", loss, rl)
     assert abs(loss - rl) <= TOL_Y * rl
@@ -139,7 +139,7 @@ def test_bad_arguments():
     from paper_2202_03144_amd import PtyError
     from paper_2202_03144_amd.cnn import Net
     net = Net(2, seed=0)
-    x = torch.zeros((3, 128, 128), dtype=torch.float32, device="cuda")
+    x = torch.zeros((3, 128, 128, 2), dtype=torch.float32, device="cuda")
     y = torch.zeros((3, 64, 64, 2), dtype=torch.float32, device="cuda")
     with pytest.raises(PtyError, match="INVALID"):
         net.forward(x, y)            # batch above max_batch
@@ -238,7 +238,24 @@ def _seed_case(j=10):
     return obj, probe, pos, cnt, wl.photons
 
 
-def test_seed_object_matches_oracle():
+def test_network_input_matches_oracle():
+    """The real-space input from counts and the probe (pty_cnn_input) against
+    oracle.seed.network_input (float32 transforms: relative L2 1e-4)."""
+    import torch
+    from paper_2202_03144_amd.cnn import Net
+    obj, probe, pos, cnt, photons = _seed_case(6)
+    ref = oseed.network_input(cnt, c64(probe).astype(np.complex128))
+    with Net(6, seed=0) as net:
+        x = torch.empty((6, 128, 128, 2), dtype=torch.float32, device="cuda")
+        net.input(torch.from_numpy(cnt).cuda(), torch.from_numpy(c64(probe)).cuda(), x)
+        got = x.cpu().numpy()
+    err = _rel(got, ref)
+    print("input rel err", err)
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("stride", [1, 3])
+def test_seed_object_matches_oracle(stride):
     from paper_2202_03144_amd import Plan
     from paper_2202_03144_amd.cnn import Net
     obj, probe, pos, cnt, photons = _seed_case()
@@ -248,14 +265,16 @@ def test_seed_object_matches_oracle():
         net.set_params(flat)
         pl.load_patterns(cnt)
         pl.load_positions(pos)
-        r = pl.seed_object(net, photons, batch=4, fallback=False)   # ragged last batch (10 = 4 + 4 + 2)
+        pl.set_probe(c64(probe))
+        r = pl.seed_object(net, batch=4, stride=stride, fallback=False)   # ragged last batch at stride 1
         assert r["used_fallback"] is False
         got = pl.object()
+    sel = np.arange(0, j, stride)
     # the kernels read the counts through A = sqrt(max(d, 0)) in float32
-    a32 = np.sqrt(np.maximum(cnt, 0).astype(np.float32))
-    x = np.log1p(a32.astype(np.float64) ** 2) / np.log1p(photons)
-    y, _ = unet.forward(_as_kernel_sees(flat), x[..., None])
-    ref, _ = oseed.stitch(y, pos, *obj.shape)
+    a32 = np.sqrt(np.maximum(cnt, 0).astype(np.float32)).astype(np.float64)
+    x = oseed.network_input(a32[sel] ** 2, c64(probe).astype(np.complex128))
+    y, _ = unet.forward(_as_kernel_sees(flat), x)
+    ref, _ = oseed.stitch(y, pos[sel], *obj.shape)
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     print("seed rel err", err)
     assert err <= TOL_Y
@@ -270,10 +289,10 @@ def test_seed_fallback_and_model_error():
         pl.load_patterns(cnt)
         pl.load_positions(pos)
         pl.set_probe(c64(probe))
-        pl.seed_object(net, photons, batch=8, fallback=False)
+        pl.seed_object(net, batch=8, fallback=False)
         seed_obj = pl.object()
         e_seed_direct = pl.model_error()
-        r = pl.seed_object(net, photons, batch=8, fallback=True)
+        r = pl.seed_object(net, batch=8, fallback=True)
         got = pl.object()
     amp = oracle.amplitude(cnt.astype(np.float64))
     pr = c64(probe).astype(np.complex128)
@@ -327,7 +346,7 @@ def test_full_size_inference_and_stitch():
     b = wl.j
     flat = _params(31)
     rng = np.random.default_rng(32)
-    x = rng.uniform(0.0, 0.6, (b, 128, 128)).astype(np.float32)
+    x = rng.uniform(0.0, 0.6, (b, 128, 128, 2)).astype(np.float32)
     with Net(b, seed=0) as net:
         net.set_params(flat)
         xt = torch.from_numpy(x).cuda()
@@ -335,7 +354,7 @@ def test_full_size_inference_and_stitch():
         net.forward(xt, y)
         yh = y.cpu().numpy()
     samples = [0, 1777, b - 1]
-    ref, _ = unet.forward(_as_kernel_sees(flat), x[samples].astype(np.float64)[..., None])
+    ref, _ = unet.forward(_as_kernel_sees(flat), x[samples].astype(np.float64))
     err = _rel(yh[samples], ref)
     print("full-batch forward rel err", err)
     assert err <= TOL_Y
@@ -386,3 +405,42 @@ def test_stitch_large_object_global_chain():
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     print("global-chain stitch rel err", err)
     assert err <= 1e-5
+
+
+def test_trained_network_seeds_better_than_the_flat_start():
+    """What the trained network gains: trained on the GPU (forward model,
+    Poisson draws, real-space inputs and targets all made by the library's
+    kernels) for 300 Adam steps of 128 patterns from eight training objects,
+    its stitched seed of a held-out object (the learned-initialiser workload's
+    probe and dose, a 1,000-point spiral on a 600 x 600 object) is at most
+    0.75 of the flat start's NRMSE (measured: see the printed line)."""
+    import torch
+    from paper_2202_03144_amd import Plan
+    from paper_2202_03144_amd.cnn import Net
+    from paper_2202_03144_amd.learned import train
+    wl = ptysynth.workload(4)
+    objs = [torch.from_numpy(ptysynth.make_object(1000 + i, 512, 512, wl.sigma_o).astype(np.complex64)).cuda()
+            for i in range(8)]
+    side = ptysynth.spiral_object_side(1000, wl.pitch, 128, 3.0)
+    obj = ptysynth.make_object(9, side, side, wl.sigma_o).astype(np.complex64)
+    pos = ptysynth.spiral_positions(1000, wl.pitch, side / 2.0, 128, ptysynth.stream(9, 3))
+    with Net(256, seed=7) as net:
+        losses = train(net, objs, wl.probe().astype(np.complex64), wl.photons, 300, 128, lr=1e-3,
+                       lr_final=1e-4, seed=3)
+        with Plan(128, 1, len(pos), (side, side)) as pl:
+            lam = torch.empty((len(pos), 128, 128), dtype=torch.float32, device="cuda")
+            cnt = torch.empty_like(lam)
+            pl.load_positions(pos)
+            pl.set_object(obj)
+            pl.set_probe(wl.probe().astype(np.complex64))
+            pl.simulate(wl.photons, out=lam)
+            pl.poisson(lam, cnt, seed=9)
+            pl.load_patterns(cnt)
+            pl.set_object(np.ones((side, side), np.complex64))
+            pl.set_truth(obj, 0.3)
+            flat = pl.nrmse()
+            r = pl.seed_object(net, batch=256, stride=1, fallback=False)
+            seeded = pl.nrmse()
+    print(f"[learned] loss {np.mean(losses[:10]):.5f} -> {np.mean(losses[-10:]):.5f}; "
+          f"seed NRMSE {seeded:.4f} vs flat {flat:.4f} ({seeded / flat:.2f}x)", flush=True)
+    assert seeded <= 0.75 * flat

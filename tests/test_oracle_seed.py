@@ -75,6 +75,71 @@ def test_targets_closed_form():
         assert s.real > 0 and abs(s.imag) <= 1e-9 * abs(s)
 
 
-def test_network_input_closed_form():
-    d = np.array([np.e - 1.0, 0.0, -3.0, np.e ** 2 - 1.0])
-    np.testing.assert_allclose(seed.network_input(d, np.e - 1.0), [1.0, 0.0, 0.0, 2.0], atol=1e-15)
+def _probe(n, rng):
+    y, x = np.mgrid[:n, :n] - n / 2
+    amp = np.exp(-(x ** 2 + y ** 2) / (2 * (n / 6) ** 2))
+    return amp * np.exp(1j * (0.3 * rng.standard_normal((n, n)) + 0.02 * (x ** 2 + y ** 2)))
+
+
+def _input_brute_force(d, p):
+    """The network input written out for a tiny window: DFT sums, index
+    arithmetic for the centring, the crop and the 2x repetition."""
+    n = p.shape[0]
+    # far-field phase of the probe by the DFT definition (unitary)
+    fp = np.zeros((n, n), complex)
+    for a in range(n):
+        for b in range(n):
+            fp[a, b] = sum(p[u, v] * np.exp(-2j * np.pi * (a * u + b * v) / n)
+                           for u in range(n) for v in range(n)) / n
+    uphase = fp / np.abs(fp)
+    p2 = np.abs(p) ** 2
+    g = np.conj(p) / (p2 + 0.01 * p2.max())
+    # natural-order moduli: natural frequency a sits at centred index (a + n/2) mod n
+    amp = np.array([[np.sqrt(max(d[(a + n // 2) % n, (b + n // 2) % n], 0.0)) for b in range(n)]
+                    for a in range(n)])
+    out = np.zeros((n, n, 2))
+    for y in range(n):
+        for xx in range(n):
+            r, c = n // 4 + y // 2, n // 4 + xx // 2
+            v = sum(amp[a, b] * uphase[a, b] * np.exp(2j * np.pi * (a * r + b * c) / n)
+                    for a in range(n) for b in range(n)) / n
+            v *= g[r, c]
+            out[y, xx] = v.real, v.imag
+    return out
+
+
+def test_network_input_brute_force():
+    """Against the definition on an 8 x 8 window (any slip in the centring,
+    the transform direction or scale, the crop or the repetition changes it)."""
+    rng = np.random.default_rng(12)
+    p = _probe(8, rng)
+    d = rng.uniform(0.0, 40.0, (8, 8))
+    d[0, 3] = -2.0   # negative counts read as 0
+    np.testing.assert_allclose(seed.network_input(d, p), _input_brute_force(d, p), atol=1e-12)
+    # two planted mistakes the check catches: the forward transform, and the
+    # centred pattern used without moving zero frequency to the corner
+    wrong_dir = np.fft.fft2(np.sqrt(np.maximum(np.fft.ifftshift(d), 0)) * seed.probe_planes(p)[0]) / 8
+    assert not np.allclose((seed.probe_planes(p)[1] * wrong_dir)[2:6, 2:6].real,
+                           _input_brute_force(d, p)[::2, ::2, 0], atol=1e-3)
+    shifted = seed.network_input(np.fft.ifftshift(d), p)
+    assert not np.allclose(shifted, _input_brute_force(d, p), atol=1e-3)
+
+
+def test_network_input_of_a_flat_object():
+    """O = c (constant, complex) and noise-free counts: the estimate is
+    |c| |P|^2 / (|P|^2 + 0.01 max |P|^2), real, on the window's centre (the
+    pattern fixes O only up to a global phase)."""
+    rng = np.random.default_rng(13)
+    n = 32
+    p = _probe(n, rng)
+    c = 0.9 * np.exp(0.7j)
+    d = np.fft.fftshift(np.abs(np.fft.fft2(c * p) / n) ** 2)
+    x = seed.network_input(d, p)
+    p2 = np.abs(p) ** 2
+    want = abs(c) * p2 / (p2 + 0.01 * p2.max())
+    want = np.repeat(np.repeat(want[n // 4:3 * n // 4, n // 4:3 * n // 4], 2, axis=0), 2, axis=1)
+    np.testing.assert_allclose(x[..., 0], want, atol=1e-12)
+    np.testing.assert_allclose(x[..., 1], 0.0, atol=1e-12)
+    # batched counts give the same per pattern
+    xb = seed.network_input(np.stack([d, 4 * d]), p)
+    np.testing.assert_allclose(xb[1], 2 * x, atol=1e-12)

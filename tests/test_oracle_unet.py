@@ -81,7 +81,7 @@ def _rep(x, f):
 
 def test_network_wiring_closed_forms():
     rng = np.random.default_rng(4)
-    x = rng.uniform(0.0, 1.0, (2, 128, 128, 1))
+    x = rng.uniform(0.0, 1.0, (2, 128, 128, 2))
     x0 = x[..., 0]
     # through the bottleneck: 16 x 16 block means, repeated 8x
     y, _ = unet.forward(_routing_params([0, 0, 0, 0, 0, 0, 0, 0, 0, 0]), x)
@@ -116,7 +116,7 @@ def fd_setup():
     rng = np.random.default_rng(5)
     flat = unet.init_params(3)
     flat[unet.num_params() - 2:] = [0.3, -0.2]
-    x = rng.uniform(0.0, 1.0, (1, 128, 128, 1))
+    x = rng.uniform(0.0, 1.0, (1, 128, 128, 2))
     t = rng.standard_normal((1, 64, 64, 2)) * 0.1
     loss, g = unet.loss_and_grad(flat, x, t)
     return flat, x, t, loss, g
