@@ -272,7 +272,7 @@ def learned_leg(args, torch) -> dict:
     plain = arm(False, args.plain_iters)
     log(f"plain: {plain}")
     arms = {}
-    for stride in sorted({1, args.seed_stride}):
+    for stride in sorted({int(v) for v in args.seed_strides.split(",")}):
         log(f"learned arm, every {stride}. pattern seeded")
         arms[stride] = arm(True, args.learned_iters, stride)
         arms[stride]["seed_stride"] = stride
@@ -928,8 +928,8 @@ def main() -> int:
     ap.add_argument("--learned-iters", type=int, default=20)
     ap.add_argument("--plain-iters", type=int, default=200)
     ap.add_argument("--nrmse-target", type=float, default=1e-2)
-    ap.add_argument("--seed-stride", type=int, default=4,
-                    help="learned arm also run seeding only every this-many-th pattern (coverage, not redundancy)")
+    ap.add_argument("--seed-strides", default="2,4",
+                    help="learned arms seeding every k-th pattern, for each k listed (coverage, not redundancy)")
     ap.add_argument("--learned-lsqml-batch", type=int, default=4096,
                     help="LSQML group size of both arms (512-position groups leave a noise floor of "
                          "NRMSE 1.05e-2 on this workload, above the target)")

@@ -384,8 +384,8 @@ pty_status pty_get_nrmse(pty_ctx* ctx, double* out, int32_t cap, int32_t* n_writ
  * natural order, u = F(P) / |F(P)| (1 where F(P) = 0) and
  * g = conj(P) / (|P|^2 + 0.01 max |P|^2); its central 64 x 64 upsampled 2x
  * (nearest) to 128 x 128, channels Re, Im (so that the 64 x 64 output grid
- * lies on the target patch).  Output channel 0 amplitude, channel 1 phase
- * relative to the patch's mean phasor.  Loss: mean
+ * lies on the target patch).  Output channel 0 amplitude, channel 1 phase of
+ * the patch (the input fixes each patch's phase relative to the known probe).  Loss: mean
  * squared error; optimiser: Adam (beta 0.9, 0.999, eps 1e-8).
  * ---------------------------------------------------------------------- */
 typedef struct pty_cnn pty_cnn;
@@ -430,7 +430,7 @@ pty_status pty_training_targets(pty_ctx* ctx, float* out);
  * an object: patch j sits at the nearest integer position of window j plus
  * (32, 32); a sequential chain in position order gives each patch a phase
  * factor e_j = z / |z|, z = sum over already stitched samples (the pixels
- * whose coordinates are multiples of 16) of S conj(c_j); the result is the
+ * whose coordinates are multiples of 8) of S conj(c_j); the result is the
  * mean of c_j e_j over the patches covering a pixel, 1 where none does.
  * out: H x W complex64 device buffer, or NULL to replace the context's
  * object.  N must be 128.  Synchronises. */
@@ -439,9 +439,11 @@ pty_status pty_stitch(pty_ctx* ctx, const float* patches, void* out);
 /* Learned seed of the context's object: the network input of every
  * stride-th loaded pattern (j = 0, stride, 2 stride, ...; 1 = all) from its
  * moduli and the context's probe, the forward pass in batches of `batch`
- * (on the context's stream), then the stitching of pty_stitch over those
- * windows.  With fallback != 0 the seed is kept only if its model error is
- * not above that of the flat object O = 1 (else the flat object is used and
+ * (on the context's stream), then the mean of the predicted patches over the
+ * windows covering each pixel (placed as in pty_stitch, without its phase
+ * chain: the patches already share the probe's phase reference), 1 where
+ * none does.  With fallback != 0 the seed is kept only if its model error
+ * (over the seeded windows) is not above that of the flat object O = 1 (else the flat object is used and
  * *used_fallback = 1); *e_seed and *e_flat (each may be NULL) receive the two
  * errors.  The network must live on the context's device.  Synchronises. */
 pty_status pty_seed_object(pty_ctx* ctx, pty_cnn* net, int32_t batch, int32_t stride, int32_t fallback,

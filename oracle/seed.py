@@ -6,12 +6,15 @@ patches into an object seed:
 
 * placement: the central 64 x 64 of window j, at the window's nearest
   integer position (floor(p + 1/2)) plus (32, 32);
-* phase offsets: a sequential chain over the patches in position order on
-  the coarse grid of object pixels whose coordinates are multiples of 16:
+* phase offsets (for patches of unknown relative phase): a sequential chain
+  over the patches in position order on the coarse grid of object pixels
+  whose coordinates are multiples of 8:
   z_j = sum over patch j's coarse samples of S conj(c_j), e_j = z_j / |z_j|
   (1 if z_j = 0), then S += c_j e_j on those samples;
-* the seed: the mean of c_j e_j over the patches covering a pixel, 1 where no
-  patch covers it.
+* the stitched object: the mean of c_j e_j over the patches covering a pixel,
+  1 where no patch covers it;
+* the learned seed: the same mean of the predicted c_j without phase factors
+  (the network's input fixes each patch's phase relative to the known probe).
 
 c_j = a_j exp(i phi_j) from the predicted amplitude a_j and phase phi_j.
 """
@@ -20,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 PATCH = 64
-GRID = 16
+GRID = 8
 
 
 EST_EPS = 0.01   # regulariser of the probe division, relative to max |P|^2
@@ -60,17 +63,15 @@ def network_input(counts, probe):
 
 
 def targets(obj, pos, n=128):
-    """Amplitude and phase relative to the mean phasor of the central n/2 x n/2
-    patch of each window at integer positions pos (J, 2): (J, n/2, n/2, 2)."""
+    """Amplitude and phase of the central n/2 x n/2 patch of each window at
+    integer positions pos (J, 2): (J, n/2, n/2, 2)."""
     m, q = n // 2, n // 4
     out = np.empty((len(pos), m, m, 2))
     for j, (y, x) in enumerate(np.asarray(pos)):
         y, x = int(y), int(x)
         o = np.asarray(obj, np.complex128)[y + q:y + q + m, x + q:x + q + m]
-        s = o.sum()
-        ph = s / abs(s) if abs(s) > 0 else 1.0
         out[j, ..., 0] = np.abs(o)
-        out[j, ..., 1] = np.angle(o * np.conj(ph))
+        out[j, ..., 1] = np.angle(o)
     return out
 
 
@@ -102,3 +103,20 @@ def stitch(patches, pos, h, w, n=128):
     cov = cnt > 0
     out[cov] = acc[cov] / cnt[cov]
     return out, e
+
+
+def average(patches, pos, h, w, n=128):
+    """Learned seed (h, w): the mean of the patches (J, 64, 64, 2) of amplitude
+    and phase over the windows covering each pixel, placed as in stitch, with
+    no phase factors; 1 where no patch covers a pixel."""
+    p = np.asarray(patches, np.float64)
+    c = p[..., 0] * np.exp(1j * p[..., 1])
+    acc = np.zeros((h, w), np.complex128)
+    cnt = np.zeros((h, w))
+    for j, (ty, tx) in enumerate(placements(pos, n)):
+        acc[ty:ty + PATCH, tx:tx + PATCH] += c[j]
+        cnt[ty:ty + PATCH, tx:tx + PATCH] += 1
+    out = np.ones((h, w), np.complex128)
+    cov = cnt > 0
+    out[cov] = acc[cov] / cnt[cov]
+    return out

@@ -180,6 +180,12 @@ struct pty_ctx {
   // learned seed
   float* seed_patches = nullptr;   size_t seed_patches_n = 0;
   float2* seed_obj = nullptr;
+  // stitching work buffers (kept between calls)
+  int2* st_t = nullptr;            size_t st_t_n = 0;
+  int* st_beg = nullptr;           size_t st_beg_n = 0;
+  int* st_idx = nullptr;           size_t st_idx_n = 0;
+  float2* st_S = nullptr;          size_t st_S_n = 0;
+  float2* st_ph = nullptr;         size_t st_ph_n = 0;
 
   bool dm_valid = false;           // psi / contrib consistent with object and probe
   bool den_valid = false;          // den holds sum_j S_j^T sum_k |P_k|^2 for all positions
@@ -1025,14 +1031,19 @@ double run_nll(pty_ctx* c, const float2* obj, const float2* probe, const float* 
 // ---------------------------------------------------------------------------
 // Amplitude error E of the current object and probe over all positions
 // (forward rows, columns with the projection's error partials, no inverse).
-double model_error(pty_ctx* c) {
+// sub: only the patterns of that group (the others' partials are zeroed).
+double model_error(pty_ctx* c, const Group* sub = nullptr) {
   pty_iter_params p;
   pty_default_params(&p);
   const int chunk = chunk_patterns(c, p);
-  ensure_all_group(c);
+  if (!sub) ensure_all_group(c);
   ensure_common(c, std::min(chunk, c->J), 1);
   c->ensure_once(c->eval_dev, 8);
-  fourier_pass(c, c->all, 0, c->J, chunk, RowIn::Plain, ColOp::Project, RowOut::StoreChi, false);
+  if (sub)
+    launch_fill_u32(reinterpret_cast<unsigned*>(c->errp), size_t(c->J) * col_blocks(c->N, c->K) * 4, 0u,
+                    c->stream);
+  const Group& g = sub ? *sub : c->all;
+  fourier_pass(c, g, 0, (int)g.jl.size(), chunk, RowIn::Plain, ColOp::Project, RowOut::StoreChi, false);
   launch_err_reduce(c->errp, c->J * col_blocks(c->N, c->K), c->eval_dev, c->stream);
   double e = 0.0;
   PTY_HIP(hipMemcpyAsync(&e, c->eval_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -1054,8 +1065,10 @@ std::vector<int2> seed_placements(const pty_ctx* c, const std::vector<int>& sel)
 }
 
 // Stitches the patches of windows `sel` (all when empty; |sel| x 64 x 64 x
-// (amplitude, phase), device, in that order) into dst.
-void stitch(pty_ctx* c, const float* patches, float2* dst, const std::vector<int>& sel = {}) {
+// (amplitude, phase), device, in that order) into dst: with `chain`, each
+// patch first gets the phase factor of the sequential chain; without, the
+// patches are averaged as they are.
+void stitch(pty_ctx* c, const float* patches, float2* dst, const std::vector<int>& sel = {}, bool chain = true) {
   if (c->N != 128) throw Unsupported("stitching needs 128 x 128 windows (64 x 64 patches)");
   const std::vector<int2> t = seed_placements(c, sel);
   const int m = (int)t.size();
@@ -1067,36 +1080,21 @@ void stitch(pty_ctx* c, const float* patches, float2* dst, const std::vector<int
   for (int j = 0; j < m; ++j) idx[fill[size_t(t[j].x / 64) * bw + t[j].y / 64]++] = j;
   const int gs = seed_chain_grid();
   const int hc = (c->H + gs - 1) / gs, wc = (c->W + gs - 1) / gs;
-  int2* d_t = c->alloc<int2>(m);
-  int* d_beg = nullptr;
-  int* d_idx = nullptr;
-  float2* d_S = nullptr;
-  float2* d_ph = nullptr;
-  try {
-    d_beg = c->alloc<int>(beg.size());
-    d_idx = c->alloc<int>(idx.size());
-    d_S = c->alloc<float2>(size_t(hc) * wc);
-    d_ph = c->alloc<float2>(m);
-    PTY_HIP(hipMemcpyAsync(d_t, t.data(), sizeof(int2) * m, hipMemcpyHostToDevice, c->stream));
-    PTY_HIP(hipMemcpyAsync(d_beg, beg.data(), sizeof(int) * beg.size(), hipMemcpyHostToDevice, c->stream));
-    PTY_HIP(hipMemcpyAsync(d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
-    launch_fill_u32(reinterpret_cast<unsigned*>(d_S), size_t(hc) * wc * 2, 0u, c->stream);
-    launch_seed_chain(patches, d_t, m, d_S, hc, wc, d_ph, c->stream);
-    launch_seed_stitch(patches, d_t, d_ph, d_beg, d_idx, bw, bh, dst, c->H, c->W, c->stream);
-    PTY_HIP(hipStreamSynchronize(c->stream));
-  } catch (...) {
-    c->dfree(d_t);
-    c->dfree(d_beg);
-    c->dfree(d_idx);
-    c->dfree(d_S);
-    c->dfree(d_ph);
-    throw;
+  c->ensure(c->st_t, c->st_t_n, size_t(std::max(m, 1)));
+  c->ensure(c->st_beg, c->st_beg_n, beg.size());
+  c->ensure(c->st_idx, c->st_idx_n, size_t(std::max(m, 1)));
+  c->ensure(c->st_ph, c->st_ph_n, size_t(std::max(m, 1)));
+  if (chain) c->ensure(c->st_S, c->st_S_n, size_t(hc) * wc);
+  PTY_HIP(hipMemcpyAsync(c->st_t, t.data(), sizeof(int2) * m, hipMemcpyHostToDevice, c->stream));
+  PTY_HIP(hipMemcpyAsync(c->st_beg, beg.data(), sizeof(int) * beg.size(), hipMemcpyHostToDevice, c->stream));
+  PTY_HIP(hipMemcpyAsync(c->st_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
+  if (chain) {
+    launch_fill_u32(reinterpret_cast<unsigned*>(c->st_S), size_t(hc) * wc * 2, 0u, c->stream);
+    launch_seed_chain(patches, c->st_t, m, c->st_S, hc, wc, c->st_ph, c->stream);
   }
-  c->dfree(d_t);
-  c->dfree(d_beg);
-  c->dfree(d_idx);
-  c->dfree(d_S);
-  c->dfree(d_ph);
+  launch_seed_stitch(patches, c->st_t, chain ? c->st_ph : nullptr, c->st_beg, c->st_idx, bw, bh, dst, c->H, c->W,
+                     c->stream);
+  PTY_HIP(hipStreamSynchronize(c->stream));   // the host lists above must outlive their copies
 }
 
 void run_algo(pty_ctx* c, int algo, int n_iter, const pty_iter_params& p) {
@@ -2050,18 +2048,22 @@ pty_status pty_seed_object(pty_ctx* c, pty_cnn* net, int32_t batch, int32_t stri
     }
     const size_t hw = size_t(c->H) * c->W;
     if (!fallback) {
-      stitch(c, c->seed_patches, c->obj, sel);
+      stitch(c, c->seed_patches, c->obj, sel, false);
       c->have_object = true;
       c->dm_valid = false;
       if (used_fallback) *used_fallback = 0;
       return;
     }
     c->ensure_once(c->seed_obj, hw);
-    stitch(c, c->seed_patches, c->seed_obj, sel);
+    stitch(c, c->seed_patches, c->seed_obj, sel, false);
     PTY_HIP(hipMemcpyAsync(c->obj, c->seed_obj, hw * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));
-    const double es = model_error(c);
+    // the two model errors over the seeded windows
+    Group sub;
+    sub.jl = sel;
+    sub.d_jl = d_sel;
+    const double es = model_error(c, stride > 1 ? &sub : nullptr);
     launch_fill_c64(c->obj, hw, make_float2(1.f, 0.f), c->stream);
-    const double ef = model_error(c);
+    const double ef = model_error(c, stride > 1 ? &sub : nullptr);
     const bool use_seed = std::isfinite(es) && es <= ef;
     if (use_seed)
       PTY_HIP(hipMemcpyAsync(c->obj, c->seed_obj, hw * sizeof(float2), hipMemcpyDeviceToDevice, c->stream));

@@ -211,40 +211,16 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_input(const float* __rest
   }
 }
 
-// Training targets: amplitude and phase (relative to the mean phasor) of the
-// central n/2 x n/2 object patch of each window at an integer position.
-// One block (256 threads) per pattern.
+// Training targets: amplitude and phase of the central n/2 x n/2 object patch
+// of each window at an integer position.  One block (256 threads) per pattern.
 __global__ __launch_bounds__(256) void k_targets(const float2* __restrict__ obj, int w, const PosInfo* __restrict__ pos,
                                                  int n, float* __restrict__ out) {
-  __shared__ double sh[2][4];
   const int j = blockIdx.x, m = n / 2, q = n / 4;
   const PosInfo p = pos[j];
-  double sr = 0.0, si = 0.0;
   for (int e = threadIdx.x; e < m * m; e += 256) {
     const float2 o = obj[(size_t)(p.iy + q + e / m) * w + p.ix + q + e % m];
-    sr += o.x;
-    si += o.y;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    sr += __shfl_down(sr, off, 64);
-    si += __shfl_down(si, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = sr;
-    sh[1][threadIdx.x >> 6] = si;
-  }
-  __syncthreads();
-  const double mr = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-  const double mi = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
-  const double mn = sqrt(mr * mr + mi * mi);
-  const float cr = mn > 0 ? (float)(mr / mn) : 1.f, ci = mn > 0 ? (float)(mi / mn) : 0.f;
-  for (int e = threadIdx.x; e < m * m; e += 256) {
-    const float2 o = obj[(size_t)(p.iy + q + e / m) * w + p.ix + q + e % m];
-    // o * conj(mean phasor)
-    const float re = o.x * cr + o.y * ci, im = o.y * cr - o.x * ci;
     out[((size_t)j * m * m + e) * 2] = sqrtf(o.x * o.x + o.y * o.y);
-    out[((size_t)j * m * m + e) * 2 + 1] = atan2f(im, re);
+    out[((size_t)j * m * m + e) * 2 + 1] = atan2f(o.y, o.x);
   }
 }
 
@@ -256,21 +232,20 @@ __device__ __forceinline__ float2 patch_value(const float* __restrict__ pt, size
 }
 
 // Sequential phase-offset chain over the patches in index order, on the
-// coarse grid G of object pixels whose coordinates are multiples of 16 (4 x 4
-// samples per 64 x 64 patch; lane l of the single wavefront takes sample
-// l mod 16).  For patch j: z = sum over its samples of S * conj(c_j),
+// coarse grid G of object pixels whose coordinates are multiples of 8 (8 x 8
+// samples per 64 x 64 patch; lane l of the single wavefront takes sample l).  For patch j: z = sum over its samples of S * conj(c_j),
 // e_j = z / |z| (1 if z = 0), then S += c_j e_j on those samples.  Writes
 // e_j to phasor[j].  S lives in LDS when it fits (IN_LDS), else in the
 // zero-filled global array S_g.  The next patch's samples are loaded while
 // the current one is processed (they do not depend on S).
-constexpr int kChainGrid = 16;
+constexpr int kChainGrid = 8;
 template <bool IN_LDS>
 __global__ __launch_bounds__(64) void k_seed_chain(const float* __restrict__ patches, const int2* __restrict__ place,
                                                    int j_count, float2* S_g, int hc, int wc,
                                                    float2* __restrict__ phasor) {
   extern __shared__ float2 S_l[];
   const int lane = threadIdx.x;
-  const int sy = (lane >> 2) & 3, sx = lane & 3;
+  const int sy = lane >> 3, sx = lane & 7;
   float2* S = IN_LDS ? S_l : S_g;
   if (IN_LDS) {
     for (int i = lane; i < hc * wc; i += 64) S_l[i] = make_float2(0.f, 0.f);
@@ -292,13 +267,13 @@ __global__ __launch_bounds__(64) void k_seed_chain(const float* __restrict__ pat
     const float2 s = S[cell];
     float zr = s.x * c.x + s.y * c.y, zi = s.y * c.x - s.x * c.y;
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-      zr += __shfl_xor(zr, off, 16);
-      zi += __shfl_xor(zi, off, 16);
+    for (int off = 32; off > 0; off >>= 1) {
+      zr += __shfl_xor(zr, off, 64);
+      zi += __shfl_xor(zi, off, 64);
     }
     const float zn = sqrtf(zr * zr + zi * zi);
     const float er = zn > 0.f ? zr / zn : 1.f, ei = zn > 0.f ? zi / zn : 0.f;
-    if (lane < 16) S[cell] = make_float2(s.x + c.x * er - c.y * ei, s.y + c.x * ei + c.y * er);
+    S[cell] = make_float2(s.x + c.x * er - c.y * ei, s.y + c.x * ei + c.y * er);
     if (lane == 0) phasor[j] = make_float2(er, ei);
     // the next patch may read what this one wrote
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -336,7 +311,7 @@ __global__ void k_seed_stitch(const float* __restrict__ patches, const int2* __r
         const int u = y - t.x, v = x - t.y;
         if ((unsigned)u >= 64u || (unsigned)v >= 64u) continue;
         const float2 c = patch_value(patches, (size_t)j * 4096 + u * 64 + v);
-        const float2 ph = phasor[j];
+        const float2 ph = phasor ? phasor[j] : make_float2(1.f, 0.f);
         ar += c.x * ph.x - c.y * ph.y;
         ai += c.x * ph.y + c.y * ph.x;
         ++cnt;
@@ -453,7 +428,7 @@ int seed_chain_grid() { return kChainGrid; }
 void launch_seed_chain(const float* patches, const int2* place, int j, float2* S, int hc, int wc, float2* phasor,
                        hipStream_t s) {
   const size_t lds = (size_t)hc * wc * sizeof(float2);
-  if (lds <= 128 * 1024) {
+  if (lds <= 160 * 1024) {
     PTY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seed_chain<true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     k_seed_chain<true><<<1, 64, lds, s>>>(patches, place, j, S, hc, wc, phasor);

@@ -68,11 +68,34 @@ def test_targets_closed_form():
     for j, (y, x) in enumerate(pos):
         o = obj[y + 32:y + 96, x + 32:x + 96]
         v = tg[j, ..., 0] * np.exp(1j * tg[j, ..., 1])
-        # v is o times one unit phasor, and that phasor makes sum(v) real and positive
-        r = v / o
-        assert np.allclose(np.abs(r), 1.0, atol=1e-12) and np.allclose(r, r[0, 0], atol=1e-12)
-        s = v.sum()
-        assert s.real > 0 and abs(s.imag) <= 1e-9 * abs(s)
+        # amplitude and phase of the patch itself: they recombine to it
+        np.testing.assert_allclose(v, o, atol=1e-12)
+        assert np.all(tg[j, ..., 0] >= 0) and np.all(np.abs(tg[j, ..., 1]) <= np.pi)
+
+
+def test_average_of_patches():
+    """Patches cut from an object (consistent phases) average back to it on
+    every covered pixel, exactly; a pixel covered by two patches gets their
+    mean; uncovered pixels are 1."""
+    rng = np.random.default_rng(7)
+    obj = _object(300, 280, 8)
+    pos = rng.uniform(0, 150, size=(30, 2))
+    t = seed.placements(pos)
+    p = np.empty((len(pos), 64, 64, 2))
+    for j, (ty, tx) in enumerate(t):
+        o = obj[ty:ty + 64, tx:tx + 64]
+        p[j, ..., 0], p[j, ..., 1] = np.abs(o), np.angle(o)
+    out = seed.average(p, pos, 300, 280)
+    cov = np.zeros((300, 280), bool)
+    for ty, tx in t:
+        cov[ty:ty + 64, tx:tx + 64] = True
+    np.testing.assert_allclose(out[cov], obj[cov], atol=1e-12)
+    assert np.all(out[~cov] == 1.0)
+    # two overlapping patches of different values: their mean where they overlap
+    q = np.zeros((2, 64, 64, 2))
+    q[0, ..., 0], q[1, ..., 0], q[1, ..., 1] = 1.0, 2.0, np.pi / 2
+    two = seed.average(q, np.array([[0.0, 0.0], [0.0, 32.0]]), 128, 160)
+    assert two[40, 40] == 1.0 and abs(two[40, 70] - (1 + 2j) / 2) < 1e-12 and abs(two[40, 100] - 2j) < 1e-12
 
 
 def _probe(n, rng):
