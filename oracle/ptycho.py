@@ -51,6 +51,7 @@ __all__ = [
     "amplitude",
     "project_delta",
     "poisson_step",
+    "POISSON_NEWTON_STEPS",
     "poisson_delta",
     "forward_intensity",
     "simulate",
@@ -186,6 +187,10 @@ def project_delta(psi_f: np.ndarray, a: np.ndarray):
     return delta, float(np.sum(np.where(valid, (mod - am) ** 2, 0.0))), float(np.sum(am * am))
 
 
+POISSON_NEWTON_STEPS = 12
+POISSON_STEP_TOL = 1e-7
+
+
 def poisson_step(inten: np.ndarray, d: np.ndarray, eps: float = EPS_L) -> float:
     """Step length alpha_R of the Poisson exit-wave update of one pattern.
 
@@ -193,19 +198,47 @@ def poisson_step(inten: np.ndarray, d: np.ndarray, eps: float = EPS_L) -> float:
     where nothing was measured (those pixels add nothing).  Along the negative
     gradient of the Poisson likelihood in the detector plane the far field
     becomes Psi (1 - alpha g), g = 1 - d / (I + eps), so every intensity
-    becomes I (1 - alpha g)^2.  alpha_R is one Newton step from alpha = 0 on
-    L(alpha) = sum [I (1 - alpha g)^2 - d log(I (1 - alpha g)^2)]:
-    L'(0) = -2 sum I g^2, L''(0) = 2 sum (I + d) g^2, with d I / (I + eps) in
-    place of d so that eps enters as in g; hence
-    alpha_R = sum I g^2 / sum (I + d I / (I + eps)) g^2, in (0, 1]; 0 when the
-    numerator is 0.
+    becomes I s^2 with s = 1 - alpha g.  alpha_R minimises the pattern's
+    likelihood along that ray,
+
+        L(alpha) = sum [I s^2 - d log(I s^2 + eps)],
+        L'(alpha) = -2 sum I g s (1 - r),
+        L''(alpha) = 2 sum I g^2 (1 - r + 2 r I s^2 / (I s^2 + eps)),
+        r = d / (I s^2 + eps),
+
+    on [0, 1]: L'(0) = -2 sum I g^2 < 0 unless the pattern is already met,
+    and every pixel's own minimiser 1 / (1 + sqrt(d / I)) (eps -> 0) lies in
+    (0, 1].  It is found by POISSON_NEWTON_STEPS Newton steps from 1/2 inside
+    the bracket [lo, hi] that the sign of L' keeps (a step that would leave
+    the closed bracket, or a non-positive L'', bisects it instead), stopping
+    early once a Newton step moves alpha by at most POISSON_STEP_TOL; 0 when
+    sum I g^2 = 0.  For a uniform ratio d = c I (eps = 0) it is
+    1 / (1 + sqrt(c)), where the moved intensity equals d.
     """
     valid = np.isfinite(d)
     dm = np.where(valid, d, 0.0)
     g = np.where(valid, 1.0 - dm / (inten + eps), 0.0)
-    num = float(np.sum(inten * g * g))
-    den = float(np.sum((inten + dm * inten / (inten + eps)) * g * g))
-    return num / den if num > 0.0 else 0.0
+    if float(np.sum(inten * g * g)) <= 0.0:
+        return 0.0
+    lo, hi, a = 0.0, 1.0, 0.5
+    for _ in range(POISSON_NEWTON_STEPS):
+        s = 1.0 - a * g
+        u = inten * s * s
+        t = u + eps
+        r = dm / t
+        d1 = float(np.sum(np.where(valid, -2.0 * inten * g * s * (1.0 - r), 0.0)))
+        d2 = float(np.sum(np.where(valid, 2.0 * inten * g * g * (1.0 - r + 2.0 * r * u / t), 0.0)))
+        if d1 < 0.0:
+            lo = a
+        else:
+            hi = a
+        nxt = a - d1 / d2 if d2 > 0.0 else -1.0
+        if not (lo <= nxt <= hi):
+            nxt = 0.5 * (lo + hi)
+        elif abs(nxt - a) <= POISSON_STEP_TOL:
+            return nxt                      # converged
+        a = nxt
+    return a
 
 
 def poisson_delta(psi_f: np.ndarray, a: np.ndarray, eps: float = EPS_L):

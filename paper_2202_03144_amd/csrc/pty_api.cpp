@@ -136,7 +136,8 @@ struct pty_ctx {
   float2* alpha = nullptr;         size_t alpha_slots = 0;
   float2* alpha_by_j = nullptr;
   float2* shift = nullptr;         size_t shift_slots = 0;   // LSQML position shifts per slot
-  double* poisp = nullptr;         size_t poisp_n = 0;       // Poisson step sums per (slot, column block)
+  double* poisp = nullptr;         size_t poisp_n = 0;       // Poisson step length per slot
+  float* pinten_c = nullptr;       size_t pinten_c_n = 0;    // Poisson: chunk x N x N model intensity
   double2* mode_gram = nullptr;    // K x K Gram matrix of the probe modes
   float2* mode_mix = nullptr;      // K x K mixing matrix of the orthogonalisation
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
@@ -564,7 +565,9 @@ void fourier_pass(pty_ctx* c, const Group& g, int s0, int count, int chunk, RowI
     a.nc = std::min(chunk, count - off);
     timed(c, kRowsFwd, [&] { launch_rows_fwd(a, in); });
     a.poisp = op == ColOp::Poisson ? c->poisp : nullptr;
+    a.pinten = op == ColOp::Poisson ? c->pinten_c : nullptr;
     timed(c, kCols, [&] { launch_cols(a, op); });
+    if (op == ColOp::Poisson) timed(c, kCols, [&] { launch_poisson_alpha(a); });
     if (inverse && op != ColOp::Intensity) timed(c, kRowsInv, [&] { launch_rows_inv(a, out); });
   }
 }
@@ -774,7 +777,10 @@ void run_lsqml(pty_ctx* c, int n_iter, const pty_iter_params& p) {
   c->ensure(c->lsq_part, c->lsq_part_n, size_t(bmax) * nrb * (refining ? 9 : 5));
   if (refining) c->ensure(c->shift, c->shift_slots, size_t(bmax));
   const bool poisson = (p.flags & PTY_ITER_POISSON) != 0;
-  if (poisson) c->ensure(c->poisp, c->poisp_n, size_t(bmax) * col_blocks(c->N, c->K) * 2);
+  if (poisson) {
+    c->ensure(c->poisp, c->poisp_n, size_t(bmax));
+    c->ensure(c->pinten_c, c->pinten_c_n, size_t(std::min(chunk, bmax)) * nn);
+  }
   ensure_probe_parts(c, bmax);
   ensure_err_slot(c, n_iter);
   ensure_mode_scratch(c, p);

@@ -123,7 +123,7 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
   // unitary inverse of the whole pipeline contributes another 1 / N^2, both
   // folded into the per-pixel factor applied before the inverse transforms.
   constexpr float sc = 1.0f / N, sc2 = 1.0f / (float(N) * float(N));
-  float e_num = 0.f, e_den = 0.f, q_num = 0.f, q_den = 0.f;
+  float e_num = 0.f, e_den = 0.f;
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int pr = t + T * m;
@@ -162,17 +162,14 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
         if constexpr (OP == ColOp::Project) {
           f = am / fmaxf(mod, 1e-6f) - 1.f;
         } else {
-          // the Poisson update moves Psi by -alpha_R g Psi; alpha_R is one
-          // Newton step of the pattern's likelihood along that ray, from the
-          // pattern-wide sums of I g^2 and (I + d I / (I + eps)) g^2
-          // (I + d I / (I + eps)) g^2 = I g^2 (1 + r), r = d / (I + eps);
-          // the hardware reciprocal (1 ulp) in place of the full division
-          // keeps the kernel within two wavefronts per SIMD
+          // the Poisson update moves Psi by -alpha_R g Psi, g = 1 - d / (I + eps);
+          // alpha_R (k_poisson_alpha) minimises the pattern's likelihood along
+          // that ray and needs every pixel's I, stored here.  The hardware
+          // reciprocal (1 ulp) in place of the full division keeps the kernel
+          // within two wavefronts per SIMD
           const float r = (am * am) * __builtin_amdgcn_rcpf(inten + a.nll_eps);
           f = 1.f - r;
-          const float ig2 = (lead ? mf : 0.f) * (inten * f * f);
-          q_num += ig2;
-          q_den = fmaf(ig2, 2.f - f, q_den);   // 1 + r = 2 - g
+          if (lead) a.pinten[((size_t)c * N + pr) * N + x] = inten;
         }
         if constexpr (MASK) f *= mf;
         if (lead) {
@@ -204,15 +201,10 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
     // reduced before the inverse transforms, which then carry no sums
     const double s0 = block_sum<G::BS>((double)e_num, red);
     const double s1 = block_sum<G::BS>((double)e_den, red);
-    const double s2 = block_sum<G::BS>((double)q_num, red);
-    const double s3 = block_sum<G::BS>((double)q_den, red);
     if (threadIdx.x == 0) {
       double* e = a.errp + ((size_t)j * BPP + cb) * 2;
       e[0] = s0;
       e[1] = s1;
-      double* q = a.poisp + ((size_t)(a.slot_off + c) * BPP + cb) * 2;
-      q[0] = s2;
-      q[1] = s3;
     }
   }
   if constexpr (OP == ColOp::Project || OP == ColOp::NllGrad || OP == ColOp::Poisson) {
@@ -276,20 +268,10 @@ void k_rows_inv(FourierArgs a) {
 #pragma unroll
     for (int m = 0; m < R; ++m) obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, gdy[m], gdx[m]);
   }
-  // Poisson update: chi = -alpha_R F^-1[g Psi]; every block of the pattern
-  // sums the column blocks' partials in the same order
+  // Poisson update: chi = -alpha_R F^-1[g Psi]
   float chi_s = 1.f;
   if constexpr (MODE == RowOut::StoreChi) {
-    if (a.poisp) {
-      constexpr int CB = ColSplit<N, K>::BPP;
-      const double* q = a.poisp + (size_t)slot * CB * 2;
-      double q0 = 0.0, q1 = 0.0;
-      for (int i = 0; i < CB; ++i) {
-        q0 += q[2 * i];
-        q1 += q[2 * i + 1];
-      }
-      chi_s = q0 > 0.0 ? (float)(-(q0 / q1)) : 0.f;
-    }
+    if (a.poisp) chi_s = (float)(-a.poisp[slot]);
   }
   float2 cacc[R];
 #pragma unroll
@@ -361,7 +343,94 @@ void k_rows_inv(FourierArgs a) {
   for (int m = 0; m < R; ++m) cb[t + T * m] = cacc[m];
 }
 
+// Step length of the Poisson exit-wave update of each pattern of the chunk:
+// the minimiser on [0, 1] of the pattern's likelihood along the ray
+// I s^2, s = 1 - alpha g, g = 1 - d / (I + eps): safeguarded Newton steps from
+// 1/2 on L'(alpha) = -2 sum I g s (1 - r) and
+// L''(alpha) = 2 sum I g^2 (1 - r + 2 r I s^2 / (I s^2 + eps)),
+// r = d / (I s^2 + eps) (float32 terms with the hardware reciprocal,
+// per-thread float32 and block-wide float64 sums), kept inside the bracket
+// the sign of L' maintains (else bisection), stopping once a step moves alpha
+// by at most 1e-7; 0 when sum I g^2 = 0.  One block per pattern; masked pixels
+// (sign bit of the modulus) take no part.
+constexpr int kPoissonSteps = 12;
+constexpr int kPoissonThreads = 1024;
+template <int N>
+__global__ __launch_bounds__(kPoissonThreads) void k_poisson_alpha(FourierArgs a) {
+  static_assert((N * N) % (4 * kPoissonThreads) == 0 || N * N < 4 * kPoissonThreads, "pixel quads");
+  __shared__ double red[kPoissonThreads / 64];
+  __shared__ double sh_a;
+  const int c = blockIdx.x;
+  const int j = a.jlist[a.jl_off + c];
+  const float4* it4 = reinterpret_cast<const float4*>(a.pinten + (size_t)c * N * N);
+  const float4* am4 = reinterpret_cast<const float4*>(a.amp + (size_t)j * N * N);
+  const float eps = a.nll_eps;
+  double lo = 0.0, hi = 1.0, al = 0.5;
+  bool done = false;
+  for (int step = 0; step < kPoissonSteps && !done; ++step) {
+    const float af = (float)al;
+    float d1 = 0.f, d2 = 0.f, s0 = 0.f;
+    for (int q4 = threadIdx.x; q4 < N * N / 4; q4 += kPoissonThreads) {
+      const float4 iv = it4[q4], av = am4[q4];
+      const float Is[4] = {iv.x, iv.y, iv.z, iv.w}, As[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (signbit(As[e])) continue;
+        const float I = Is[e], d = As[e] * As[e];
+        const float g = 1.f - d * __builtin_amdgcn_rcpf(I + eps);
+        const float sv = 1.f - af * g;
+        const float u = I * sv * sv, rt = __builtin_amdgcn_rcpf(u + eps);
+        const float r = d * rt;
+        d1 += -2.f * I * g * sv * (1.f - r);
+        d2 += 2.f * I * g * g * (1.f - r + 2.f * r * u * rt);
+        s0 += I * g * g;
+      }
+    }
+    const double t1 = block_sum<kPoissonThreads>((double)d1, red);
+    const double t2 = block_sum<kPoissonThreads>((double)d2, red);
+    const double t0 = step == 0 ? block_sum<kPoissonThreads>((double)s0, red) : 1.0;
+    if (threadIdx.x == 0) {
+      if (step == 0 && !(t0 > 0.0)) {
+        al = 0.0;
+        done = true;
+      } else {
+        if (t1 < 0.0)
+          lo = al;
+        else
+          hi = al;
+        double nxt = t2 > 0.0 ? al - t1 / t2 : -1.0;
+        if (!(lo <= nxt && nxt <= hi)) {
+          nxt = 0.5 * (lo + hi);
+        } else if (fabs(nxt - al) <= 1e-7) {
+          done = true;
+        }
+        al = nxt;
+      }
+      sh_a = done ? -1.0 - al : al;   // a negative value carries "done"
+    }
+    __syncthreads();
+    const double v = sh_a;
+    __syncthreads();
+    if (v < 0.0) {
+      al = -1.0 - v;
+      done = true;
+    } else {
+      al = v;
+    }
+  }
+  if (threadIdx.x == 0) a.poisp[a.slot_off + c] = al;
+}
+
 }  // namespace
+
+void launch_poisson_alpha(const FourierArgs& a) {
+  if (a.nc <= 0) return;
+  dispatch_n(a.n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    k_poisson_alpha<N><<<a.nc, kPoissonThreads, 0, a.stream>>>(a);
+  });
+  PTY_LAUNCH_CHECK("poisson_alpha");
+}
 
 int col_blocks(int n, int k) {
   int r = 0;

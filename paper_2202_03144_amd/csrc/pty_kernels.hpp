@@ -45,16 +45,19 @@ struct FourierArgs {
   float nll_eps;
   float grad_scale;       // NllGrad: multiplies every gradient
   int masked;             // 1: the moduli carry a detector mask (sign bits)
-  double* poisp;          // Poisson: per (slot, column block) sum I g^2 and
-                          // sum (I + d I / (I + eps)) g^2; the StoreChi rows
-                          // then scale by -alpha_R = -(first / second); null:
-                          // the modulus projection's chi, unscaled
+  double* poisp;          // Poisson: per slot the step length alpha_R of the
+                          // pattern (k_poisson_alpha); the StoreChi rows then
+                          // scale by -alpha_R; null: the modulus projection's
+                          // chi, unscaled
+  float* pinten;          // Poisson: chunk x N x N model intensity (natural order)
   hipStream_t stream;
 };
 
 void launch_rows_fwd(const FourierArgs& a, RowIn mode);
 void launch_cols(const FourierArgs& a, ColOp op);
 void launch_rows_inv(const FourierArgs& a, RowOut mode);
+// Poisson: the step length of every pattern of the chunk (one block each)
+void launch_poisson_alpha(const FourierArgs& a);
 int col_blocks(int n, int k);   // column blocks per pattern in the column pass
 int row_blocks(int n);   // row blocks per pattern in the row passes
 

@@ -1,10 +1,11 @@
 """Pins of the oracle's Poisson exit-wave update (LSQML with the Poisson
 likelihood, Odstrcil et al. 2018 as cited for LSQML in Sec. 2.3):
 
-* its step is the Newton step from 0 of the likelihood evaluated from its
-  definition along the ray (finite differences of a direct sum over modes);
+* its step is the minimiser along the ray of the likelihood evaluated from
+  its definition (a direct sum over modes), found by a brute-force 1-D
+  minimisation (a dense grid, then scipy's bounded scalar minimiser);
 * with a uniform measured/model ratio c the step has the closed form
-  1 / (1 + c);
+  1 / (1 + sqrt(c)) and moves every intensity onto the data;
 * its direction is the likelihood gradient that ``nll_grad`` gives (itself
   pinned by finite differences);
 * unmeasured pixels take no part in it;
@@ -34,23 +35,44 @@ def _likelihood_on_ray(psi, d, g, alpha):
     (eps = 0, log(d!) dropped)."""
     moved = psi * (1.0 - alpha * g)[None]
     inten = np.sum(np.abs(moved) ** 2, axis=0)
-    return float(np.sum(inten - d * np.log(inten)))
+    with np.errstate(divide="ignore"):
+        logs = np.where(d > 0, d * np.log(np.where(d > 0, inten, 1.0)), 0.0)   # 0 log 0 = 0
+    return float(np.sum(inten - logs))
 
 
-def test_step_is_the_newton_step_of_the_likelihood_on_the_ray():
-    psi, inten, d = _field()
+def _brute_minimiser(psi, d, g):
+    """argmin over [0, 1] of the likelihood on the ray: the best of 20,001 grid
+    points, then scipy's bounded minimiser around it."""
+    from scipy.optimize import minimize_scalar
+    grid = np.linspace(0.0, 1.0, 20001)
+    vals = [_likelihood_on_ray(psi, d, g, a) for a in grid]
+    k = int(np.argmin(vals))
+    lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, len(grid) - 1)]
+    r = minimize_scalar(lambda a: _likelihood_on_ray(psi, d, g, a), bounds=(lo, hi), method="bounded",
+                        options={"xatol": 1e-12})
+    return float(r.x)
+
+
+@pytest.mark.parametrize("seed,dose", [(0, 4.0), (3, 0.3), (4, 30.0)])
+def test_step_minimises_the_likelihood_on_the_ray(seed, dose):
+    rng = np.random.default_rng([78, seed])
+    psi = _crandn(rng, 3, 16, 16) * dose
+    inten = np.sum(np.abs(psi) ** 2, axis=0)
+    d = rng.poisson(inten).astype(np.float64)
+    d[0, :3] = 5.0 * inten[0, :3] + 3.0           # a few pixels far above the model
     g = 1.0 - d / inten
-    h = 1e-4
-    l0, lp, lm = (_likelihood_on_ray(psi, d, g, a) for a in (0.0, h, -h))
-    d1 = (lp - lm) / (2 * h)
-    d2 = (lp - 2 * l0 + lm) / (h * h)
-    assert d1 < 0
-    want = -d1 / d2
+    want = _brute_minimiser(psi, d, g)
     got = oracle.poisson_step(inten, d, eps=0.0)
-    assert abs(got - want) <= 1e-5 * want
     assert 0.0 < got <= 1.0
-    # and the step lowers the likelihood
-    assert _likelihood_on_ray(psi, d, g, got) < l0
+    assert abs(got - want) <= 1e-6 * want, (got, want)
+    # no point of the ray has a lower likelihood
+    l_got = _likelihood_on_ray(psi, d, g, got)
+    for a in np.linspace(0.0, 1.0, 101):
+        assert l_got <= _likelihood_on_ray(psi, d, g, a) + 1e-9 * abs(l_got)
+    # a planted mistake the pin catches: one Newton step from 0 instead
+    num = float(np.sum(inten * g * g))
+    den = float(np.sum((inten + d) * g * g))
+    assert abs(num / den - want) > 1e-3 * want
 
 
 @pytest.mark.parametrize("c", [0.25, 0.9, 1.0, 1.7, 4.0])
@@ -61,10 +83,10 @@ def test_uniform_ratio_closed_form(c):
     if c == 1.0:
         assert a == 0.0                      # nothing to correct
         return
-    assert abs(a - 1.0 / (1.0 + c)) <= 1e-12
+    assert abs(a - 1.0 / (1.0 + np.sqrt(c))) <= 1e-12
     delta, alpha, _, _ = oracle.poisson_delta(psi, np.sqrt(d), eps=0.0)
-    # every mode scaled by 1 - (1 - c) / (1 + c) = 2c / (1 + c)
-    assert np.max(np.abs(psi + delta - (2 * c / (1 + c)) * psi)) <= 1e-12 * np.max(np.abs(psi))
+    # every mode scaled by s = 1 - alpha (1 - c) = sqrt(c): the moved intensity is the data
+    assert np.max(np.abs(psi + delta - np.sqrt(c) * psi)) <= 1e-12 * np.max(np.abs(psi))
 
 
 def test_direction_is_the_likelihood_gradient():
