@@ -708,80 +708,232 @@ inline unsigned grid_for(size_t n, unsigned bs, unsigned cap = 65535u * 4) {
 // ---------------------------------------------------------------------------
 // Fused ePIE iteration for small windows (one workgroup, positions in order)
 // ---------------------------------------------------------------------------
-constexpr int kEpieThreads = 512;
-
-template <int N>
-struct EpieFusedGeo {
+// One thread group of T lanes per line and one line per group: N groups, so
+// a row pass covers every row of a mode at once and a column pass every
+// column.  Per position the workgroup makes four passes with one barrier
+// after each:
+//   A  rows, forward: the pre-update patch S_j O (bilinear, kept in
+//      registers until C), the exit waves P_k S_j O and their x-transforms;
+//      the two step normalisers' partial maxima;
+//   B  columns: y-transform of every mode, the multi-mode modulus
+//      projection with the amplitude-error partials, inverse y-transform;
+//   C  rows, inverse: chi_k, the object-update contribution
+//      sum_k conj(P_k) chi_k (into plane 0) and the probe update from the
+//      pre-update patch, each pixel by the thread that owns it;
+//   D  the object update over the patch's (N+1)^2 footprint.
+// LDS planes (field, probe) are N x N with the columns of each row
+// XOR-swizzled (epie_swz): a wavefront reading 8 (N = 32: 16) rows' segments
+// or 8 (16) columns' segments then touches distinct bank pairs (gfx950 LDS:
+// 64 banks of 4 bytes).  The line exchange of a transform goes through a
+// padded per-line area when it fits in LDS with the field and the probe,
+// else in place through the line's own row or column of the field.
+template <int N, int K>
+struct EpieGeo {
   static constexpr int R = FftShape<N>::R, T = FftShape<N>::T;
-  static constexpr int P = N + 1;                      // padded row (LDS banks)
-  static constexpr int LINES = kEpieThreads / T;       // lines transformed at once
-  static constexpr int W = LineLds<N>::words;
-  static constexpr int F = N + 1;                      // object footprint side
-  template <int K>
-  static constexpr size_t base_bytes() {
-    return sizeof(float2) * ((size_t)K * N * P + LINES * W + N + F * F);
-  }
-  // the probe stays in LDS too when it fits
-  template <int K>
-  static constexpr bool probe_lds() { return base_bytes<K>() + sizeof(float2) * K * N * N <= 150 * 1024; }
-  template <int K>
-  static constexpr size_t lds_bytes() { return base_bytes<K>() + (probe_lds<K>() ? sizeof(float2) * K * N * N : 0); }
+  static constexpr int NT = N * T;                     // threads: one line per T-lane group
+  static constexpr int W = LineLds<N>::words;          // padded exchange area per line
+  static constexpr size_t budget = 150 * 1024;
+  static constexpr size_t plane_bytes = sizeof(float2) * (size_t)N * N;
+  static constexpr size_t z_bytes = plane_bytes * K;
+  static constexpr size_t tw_bytes = sizeof(float2) * N;
+  static constexpr size_t xb_bytes = sizeof(float2) * (size_t)N * W;
+  static constexpr bool PL = z_bytes + tw_bytes + plane_bytes * K <= budget;          // probe in LDS
+  static constexpr bool XB = z_bytes + tw_bytes + (PL ? plane_bytes * K : 0) + xb_bytes <= budget;
+  static constexpr size_t lds = z_bytes + tw_bytes + (PL ? plane_bytes * K : 0) + (XB ? xb_bytes : 0);
+  static constexpr bool TWREG = R <= 8;                // twiddles in registers (else from LDS)
+  static constexpr bool PREFETCH = R <= 8;             // next position's moduli fetched a pass early
 };
 
-// All K x N rows (ROWS) or columns of the LDS field Z transformed in place.
-template <int N, int K, bool INV, bool ROWS>
-__device__ __forceinline__ void epie_fft_pass(float2* Z, float2* xb, const float2* tw) {
-  using G = EpieFusedGeo<N>;
-  constexpr int R = G::R, T = G::T, P = G::P;
-  const int li = threadIdx.x / T, t = threadIdx.x % T;
-  float2* buf = xb + li * G::W;
-  for (int l0 = 0; l0 < K * N; l0 += G::LINES) {
-    const int l = l0 + li;
-    if (l < K * N) {
-      const int k = l / N, r = l % N;
-      float2 v[R];
+// Column swizzle of row y, 8 (y & 3) + 4 ((y >> 2) & 1): distinct for the 8
+// rows of an aligned group of 8, and distinct in its bits 3-4 for the 4 rows
+// of an aligned group of 4 (linear under XOR in y mod 8).
+__device__ __forceinline__ int epie_swz(int y) { return ((y & 3) << 3) | ((y & 4) ? 4 : 0); }
+
+// Exchange areas of one line transform: wr(q) is where register q of this
+// lane goes, rd(i, s) where the i-th T-point input s of this lane comes from.
+template <int N>
+struct XbArea {   // padded per-line area (row stride T + 1)
+  float2* b;
+  int t;
+  __device__ float2& wr(int q) const { return b[q * (FftShape<N>::T + 1) + t]; }
+  __device__ float2& rd(int i, int s) const {
+    return b[(t + i * FftShape<N>::T) * (FftShape<N>::T + 1) + s];
+  }
+};
+template <int N>
+struct RowArea {  // the line's own (swizzled) row: element e at e ^ sw
+  float2* row;
+  int sw, t;
+  __device__ float2& wr(int q) const {
+    constexpr int T = FftShape<N>::T;
+    return row[(q * T + (t ^ (q & (T - 1)))) ^ sw];
+  }
+  __device__ float2& rd(int i, int s) const {
+    constexpr int T = FftShape<N>::T;
+    return row[((t + i * T) * T + (s ^ t)) ^ sw];
+  }
+};
+template <int N>
+struct ColArea {  // the line's own column x of a (swizzled) plane
+  float2* plane;
+  int x, t;
+  __device__ float2& at(int e) const { return plane[e * N + (x ^ epie_swz(e))]; }
+  __device__ float2& wr(int q) const {
+    constexpr int T = FftShape<N>::T;
+    return at(q * T + (t ^ (q & (T - 1))));
+  }
+  __device__ float2& rd(int i, int s) const {
+    constexpr int T = FftShape<N>::T;
+    return at((t + i * T) * T + (s ^ t));
+  }
+};
+
+// Length-N line transform (the four-step scheme of line_fft) with the
+// exchange through `ar`.  In the in-place areas element (q, lane) is kept at
+// q T + (lane ^ (q mod T)), so the write and the transposed read touch
+// distinct banks.  `twr`: W_N^(t q), q = 1 .. R-1 (forward), when TWREG.
+template <int N, bool INV, bool TWREG, class Area>
+__device__ __forceinline__ void epie_line(float2* v, const Area& ar, const float2* twr, const float2* tw_s, int t) {
+  constexpr int R = FftShape<N>::R, T = FftShape<N>::T;
+  Dft<R, INV>::run(v);
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[m] = ROWS ? Z[(k * N + r) * P + t + T * m] : Z[(k * N + t + T * m) * P + r];
-      line_fft<N, INV>(v, buf, tw, t);
+  for (int q = 1; q < R; ++q) {
+    float2 w = TWREG ? twr[q - 1] : tw_s[(t * q) & (N - 1)];
+    if (INV) w.y = -w.y;
+    v[q] = cmul(v[q], w);
+  }
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        if (ROWS) Z[(k * N + r) * P + t + T * m] = v[m];
-        else Z[(k * N + t + T * m) * P + r] = v[m];
-      }
+  for (int q = 0; q < R; ++q) ar.wr(q) = v[q];
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < R / T; ++i) {
+    float2 u[T];
+#pragma unroll
+    for (int s = 0; s < T; ++s) u[s] = ar.rd(i, s);
+    Dft<T, INV>::run(u);
+#pragma unroll
+    for (int s = 0; s < T; ++s) v[i + (R / T) * s] = u[s];
+  }
+  wave_sync();
+}
+
+// Wavefront reductions through DPP lane moves (VALU only, no LDS round
+// trips): quad swaps, half-row and row mirrors, then row broadcasts 15 and
+// 31, after which lane 63 holds the result over all 64 lanes; fixed order.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_or_zero(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xf, false);
+}
+// maximum of non-negative floats (their bit patterns order like integers)
+__device__ __forceinline__ float wave_max_nonneg(float x) {
+  unsigned v = __float_as_uint(x);
+  v = max(v, (unsigned)dpp_or_zero<0xB1, 0xf>((int)v));    // quad_perm [1, 0, 3, 2]
+  v = max(v, (unsigned)dpp_or_zero<0x4E, 0xf>((int)v));    // quad_perm [2, 3, 0, 1]
+  v = max(v, (unsigned)dpp_or_zero<0x141, 0xf>((int)v));   // row_half_mirror
+  v = max(v, (unsigned)dpp_or_zero<0x140, 0xf>((int)v));   // row_mirror
+  v = max(v, (unsigned)dpp_or_zero<0x142, 0xa>((int)v));   // row_bcast:15
+  v = max(v, (unsigned)dpp_or_zero<0x143, 0xc>((int)v));   // row_bcast:31
+  return __uint_as_float((unsigned)__builtin_amdgcn_readlane((int)v, 63));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_or_zero_d(double x) {
+  const int lo = dpp_or_zero<CTRL, ROWMASK>(__double2loint(x));
+  const int hi = dpp_or_zero<CTRL, ROWMASK>(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_or_zero_d<0xB1, 0xf>(v);
+  v += dpp_or_zero_d<0x4E, 0xf>(v);
+  v += dpp_or_zero_d<0x141, 0xf>(v);
+  v += dpp_or_zero_d<0x140, 0xf>(v);
+  v += dpp_or_zero_d<0x142, 0xa>(v);
+  v += dpp_or_zero_d<0x143, 0xc>(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
+// Workgroup barrier that orders LDS only: global loads still in flight (the
+// next pattern's moduli) stay in flight across it.  Global memory written in
+// one pass and read by other threads in the next needs __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Hides a value's origin from loop-invariant code motion: the per-thread
+// LDS addresses of a pass are then formed in that pass instead of being held
+// (or spilled) across the whole position loop.
+__device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
+
+// Patch row u of S_j O at columns t + T m (the bilinear gather of
+// obj_bilinear, with the two object rows addressed once per thread so that
+// the R loads of a row differ only by constant offsets).
+template <int N>
+__device__ __forceinline__ void epie_patch_row(const float2* __restrict__ obj, int h, int w, const PosInfo& p,
+                                               int u, int t, float2* o) {
+  constexpr int R = FftShape<N>::R, T = FftShape<N>::T;
+  const int r0 = p.iy + u, r1 = min(r0 + 1, h - 1);
+  const float wx1 = p.fx, wx0 = 1.f - p.fx, wy1 = p.fy, wy0 = 1.f - p.fy;
+  auto mix = [&](float2 va, float2 vb, float2 vc, float2 vd) {
+    return make_float2(wy0 * (wx0 * va.x + wx1 * vb.x) + wy1 * (wx0 * vc.x + wx1 * vd.x),
+                       wy0 * (wx0 * va.y + wx1 * vb.y) + wy1 * (wx0 * vc.y + wx1 * vd.y));
+  };
+  if (p.ix + N < w) {
+    // no column reaches the object's last one: all taps at constant offsets
+    const float2* b0 = obj + (size_t)r0 * w + p.ix + t;
+    const float2* b1 = obj + (size_t)r1 * w + p.ix + t;
+#pragma unroll
+    for (int m = 0; m < R; ++m) o[m] = mix(b0[T * m], b0[T * m + 1], b1[T * m], b1[T * m + 1]);
+  } else {
+    const float2* a0 = obj + (size_t)r0 * w;
+    const float2* a1 = obj + (size_t)r1 * w;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int c0 = p.ix + t + T * m, c1 = min(c0 + 1, w - 1);
+      o[m] = mix(a0[c0], a0[c1], a1[c0], a1[c1]);
     }
   }
 }
 
 template <int N, int K>
-__global__ __launch_bounds__(kEpieThreads) void k_epie_fused(EpieRunArgs a) {
-  using G = EpieFusedGeo<N>;
-  constexpr int NN = N * N, P = G::P, F = G::F;
-  constexpr bool PL = G::template probe_lds<K>();
-  constexpr int QP = (NN + kEpieThreads - 1) / kEpieThreads;   // pixels per thread
+__global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused(EpieRunArgs a) {
+  using G = EpieGeo<N, K>;
+  constexpr int R = G::R, T = G::T, NT = G::NT, NN = N * N, NW = NT / 64;
+  constexpr bool PL = G::PL, XB = G::XB;
   extern __shared__ float2 lds[];
-  float2* Z = lds;                                   // K x N x P: exit waves / far field / chi
-  float2* xb = Z + (size_t)K * N * P;                // line-transform exchange
-  float2* tw_s = xb + G::LINES * G::W;               // W_N table
-  float2* foot = tw_s + N;                           // F x F pre-update object footprint
-  float2* pl = foot + F * F;                         // K x N x N probe (when PL)
-  __shared__ double redd[kEpieThreads / 64];
-  __shared__ float redf[kEpieThreads / 64];
-  for (int i = threadIdx.x; i < N; i += kEpieThreads) tw_s[i] = reinterpret_cast<const float2*>(a.tw)[i];
-  float2* probe = a.probe0;
-  float2* probe_nxt = a.probe1;
-  if constexpr (PL) {
-    for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) pl[i] = a.probe0[i];
-  }
-  // the next position's moduli, fetched while the current one is processed
-  float amp_n[QP];
-  if (a.count > 0) {
-    const int j0 = a.order[0];
+  float2* Z = lds;                                   // K swizzled planes: exit waves / far field / chi
+  float2* tw_s = Z + (size_t)K * NN;                 // W_N table
+  float2* pl = tw_s + N;                             // K swizzled probe planes (when PL)
+  float2* xb = pl + (PL ? (size_t)K * NN : 0);       // per-line exchange areas (when XB)
+  __shared__ float redf[NW][2];
+  __shared__ double redd[NW][2];
+  int li = threadIdx.x / T, t = threadIdx.x % T;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < N; i += NT) tw_s[i] = reinterpret_cast<const float2*>(a.tw)[i];
+  float2 twr[G::TWREG ? R - 1 : 1];
+  if constexpr (G::TWREG) {
+    const float2* tw = reinterpret_cast<const float2*>(a.tw);
 #pragma unroll
-    for (int r = 0; r < QP; ++r) {
-      const int q = threadIdx.x + r * kEpieThreads;
-      amp_n[r] = q < NN ? a.amp[(size_t)j0 * NN + q] : 0.f;
+    for (int q = 1; q < R; ++q) twr[q - 1] = tw[(t * q) & (N - 1)];
+  }
+  if constexpr (PL) {
+    for (int i = threadIdx.x; i < K * NN; i += NT) {
+      const int y = (i / N) % N, x = i % N;
+      pl[(i / N) * N + (x ^ epie_swz(y))] = a.probe0[i];
     }
   }
+  // probe row y of mode k: LDS (swizzled) or global (plain)
+  auto probe_row = [&](int k, int y) -> float2* { return PL ? pl + ((size_t)k * N + y) * N : a.probe0 + ((size_t)k * N + y) * N; };
+  const int psw = PL ? 1 : 0;   // probe rows are swizzled in LDS only
+  // moduli of the pixels this thread owns in the column pass: (t + T m, li)
+  float amp_n[R];
+#define PTY_EPIE_LOAD_AMP(nidx)                                                \
+  do {                                                                        \
+    const float* ap_ = a.amp + (size_t)a.order[(nidx)] * NN;                  \
+    _Pragma("unroll") for (int m_ = 0; m_ < R; ++m_) amp_n[m_] = ap_[(unsigned)((t + T * m_) * N + li)]; \
+  } while (0)
+  if (G::PREFETCH && a.count > 0) PTY_EPIE_LOAD_AMP(0);
   __syncthreads();
   // the transforms are unscaled: the unitary far field is Z / N, and the
   // unitary inverse contributes another 1 / N^2, folded into the projection
@@ -789,133 +941,576 @@ __global__ __launch_bounds__(kEpieThreads) void k_epie_fused(EpieRunArgs a) {
   for (int n = 0; n < a.count; ++n) {
     const int j = a.order[n];
     const PosInfo p = a.pos[j];
-    float amp_c[QP];
+    float amp_c[R];
+    if constexpr (G::PREFETCH) {
 #pragma unroll
-    for (int r = 0; r < QP; ++r) amp_c[r] = amp_n[r];
-    if (n + 1 < a.count) {
-      const int jn = a.order[n + 1];
+      for (int m = 0; m < R; ++m) amp_c[m] = amp_n[m];
+    } else {
+      PTY_EPIE_LOAD_AMP(n);   // consumed in pass B, after pass A's work
 #pragma unroll
-      for (int r = 0; r < QP; ++r) {
-        const int q = threadIdx.x + r * kEpieThreads;
-        amp_n[r] = q < NN ? a.amp[(size_t)jn * NN + q] : 0.f;
+      for (int m = 0; m < R; ++m) amp_c[m] = amp_n[m];
+    }
+    // ---- A: row li of the patch and of every exit wave, forward x-transform
+    opaque(li);
+    opaque(t);
+    float2 o[R];
+    float om = 0.f, pm = 0.f, sp[K == 1 ? 1 : R];
+    epie_patch_row<N>(a.obj, a.h, a.w, p, li, t, o);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      om = fmaxf(om, cabs2(o[m]));
+      if constexpr (K > 1) sp[m] = 0.f;
+    }
+    const int rsw = epie_swz(li);
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+      const float2* pr = probe_row(k, li);
+      float2 z[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const float2 pk = pr[(t + T * m) ^ (psw * rsw)];
+        if constexpr (K == 1) pm = fmaxf(pm, cabs2(pk));
+        else sp[m] += cabs2(pk);
+        z[m] = cmul(pk, o[m]);
+      }
+      float2* row = Z + ((size_t)k * N + li) * N;
+      if constexpr (XB) epie_line<N, false, G::TWREG>(z, XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+      else epie_line<N, false, G::TWREG>(z, RowArea<N>{row, rsw, t}, twr, tw_s, t);
+#pragma unroll
+      for (int m = 0; m < R; ++m) row[(t + T * m) ^ rsw] = z[m];
+    }
+    if constexpr (K > 1) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) pm = fmaxf(pm, sp[m]);
+    }
+    pm = wave_max_nonneg(pm);
+    om = wave_max_nonneg(om);
+    if (lane == 0) {
+      redf[wid][0] = pm;
+      redf[wid][1] = om;
+    }
+    lds_barrier();
+    // ---- B: column li of every mode: y-transform, projection, inverse y-transform
+    opaque(li);
+    opaque(t);
+    {
+      float2 z[K][R];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const ColArea<N> col{Z + (size_t)k * NN, li, t};
+#pragma unroll
+        for (int m = 0; m < R; ++m) z[k][m] = col.at(t + T * m);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if constexpr (XB) epie_line<N, false, G::TWREG>(z[k], XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+        else epie_line<N, false, G::TWREG>(z[k], ColArea<N>{Z + (size_t)k * NN, li, t}, twr, tw_s, t);
+      }
+      if (G::PREFETCH && n + 1 < a.count) PTY_EPIE_LOAD_AMP(n + 1);
+      float en = 0.f, ed = 0.f;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        float iraw = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) iraw += cabs2(z[k][m]);
+        // hardware square root and reciprocal (within 1 ulp each)
+        const float mod = __builtin_amdgcn_sqrtf(iraw) * sc;
+        const bool meas = !signbit(amp_c[m]);      // sign bit: no measurement
+        const float am = fabsf(amp_c[m]);
+        const float f = meas ? (am * __builtin_amdgcn_rcpf(fmaxf(mod, 1e-6f)) - 1.f) * sc2 : 0.f;
+        if (meas) {
+          en += (mod - am) * (mod - am);
+          ed += am * am;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) z[k][m] = f * z[k][m];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const ColArea<N> col{Z + (size_t)k * NN, li, t};
+        if constexpr (XB) epie_line<N, true, G::TWREG>(z[k], XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+        else epie_line<N, true, G::TWREG>(z[k], col, twr, tw_s, t);
+#pragma unroll
+        for (int m = 0; m < R; ++m) col.at(t + T * m) = z[k][m];
+      }
+      const double s0 = wave_sum_d(en), s1 = wave_sum_d(ed);
+      if (lane == 0) {
+        redd[wid][0] = s0;
+        redd[wid][1] = s1;
       }
     }
-    // pre-update footprint (reads clamped to the object, as the bilinear gather does)
-    for (int e = threadIdx.x; e < F * F; e += kEpieThreads) {
-      const int u = e / F, v = e % F;
-      foot[e] = a.obj[(size_t)min(p.iy + u, a.h - 1) * a.w + min(p.ix + v, a.w - 1)];
-    }
-    __syncthreads();
-    const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
-    auto patch = [&](int u, int v) -> float2 {
-      const float2 a0 = foot[u * F + v], b0 = foot[u * F + v + 1];
-      const float2 c0 = foot[(u + 1) * F + v], d0 = foot[(u + 1) * F + v + 1];
-      return make_float2(wy0 * (wx0 * a0.x + wx1 * b0.x) + wy1 * (wx0 * c0.x + wx1 * d0.x),
-                         wy0 * (wx0 * a0.y + wx1 * b0.y) + wy1 * (wx0 * c0.y + wx1 * d0.y));
-    };
-    const float2* pr = PL ? pl : probe;
-    // exit waves P_k S_j O
-    for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) {
-      const int k = i / NN, q = i % NN, u = q / N, v = q % N;
-      Z[(k * N + u) * P + v] = cmul(pr[i], patch(u, v));
-    }
-    __syncthreads();
-    epie_fft_pass<N, K, false, true>(Z, xb, tw_s);
-    __syncthreads();
-    epie_fft_pass<N, K, false, false>(Z, xb, tw_s);
-    __syncthreads();
-    // modulus projection and the amplitude-error partials of this position
-    float en = 0.f, ed = 0.f;
+    lds_barrier();
+    // block maxima of pass A (written before the previous barrier)
+    float pmax = 0.f, omax = 0.f;
 #pragma unroll
-    for (int r = 0; r < QP; ++r) {
-      const int q = threadIdx.x + r * kEpieThreads;
-      if (q >= NN) continue;
-      const int u = q / N, v = q % N;
-      float iraw = 0.f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) iraw += cabs2(Z[(k * N + u) * P + v]);
-      const float mod = sqrtf(iraw) * sc;
-      const bool meas = !signbit(amp_c[r]);      // sign bit: no measurement
-      const float am = fabsf(amp_c[r]);
-      const float f = meas ? (am / fmaxf(mod, 1e-6f) - 1.f) * sc2 : 0.f;
-      if (meas) {
-        en += (mod - am) * (mod - am);
-        ed += am * am;
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) Z[(k * N + u) * P + v] = f * Z[(k * N + u) * P + v];
+    for (int w = 0; w < NW; ++w) {
+      pmax = fmaxf(pmax, redf[w][0]);
+      omax = fmaxf(omax, redf[w][1]);
     }
-    const double s0 = block_sum<kEpieThreads>((double)en, redd);
-    const double s1 = block_sum<kEpieThreads>((double)ed, redd);
     if (threadIdx.x == 0) {
+      double e0 = 0.0, e1 = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        e0 += redd[w][0];
+        e1 += redd[w][1];
+      }
       double* e = a.errp + (size_t)j * a.bpp * 2;
-      e[0] = s0;
-      e[1] = s1;
+      e[0] = e0;
+      e[1] = e1;
       for (int cb = 1; cb < a.bpp; ++cb) e[2 * cb] = e[2 * cb + 1] = 0.0;
     }
-    __syncthreads();
-    epie_fft_pass<N, K, true, true>(Z, xb, tw_s);
-    __syncthreads();
-    epie_fft_pass<N, K, true, false>(Z, xb, tw_s);
-    __syncthreads();
-    // Z now holds chi_k.  Step normalisers from the pre-update probe and patch.
-    float pm = 0.f, om = 0.f;
-    for (int q = threadIdx.x; q < NN; q += kEpieThreads) {
-      float sp = 0.f;
+    // ---- C: row li, inverse x-transform of every mode; contribution and probe update
+    opaque(li);
+    opaque(t);
+    {
+      const float bs = (a.probe_on && omax > 0.f) ? a.beta / omax : 0.f;
+      const int csw = epie_swz(li);
+      float2 cn[R];
 #pragma unroll
-      for (int k = 0; k < K; ++k) sp += cabs2(pr[(size_t)k * NN + q]);
-      pm = fmaxf(pm, sp);
-      om = fmaxf(om, cabs2(patch(q / N, q % N)));
-    }
-    const float pmax = block_max_all<kEpieThreads>(pm, redf);
-    const float omax = block_max_all<kEpieThreads>(om, redf);
-    // object update over the (N+1)^2 footprint with the pre-update probe
-    if (pmax > 0.f) {
-      const float as = a.alpha / pmax;
-      for (int e = threadIdx.x; e < F * F; e += kEpieThreads) {
-        const int u = e / F, v = e % F;
-        const int Y = p.iy + u, X = p.ix + v;
-        if (Y >= a.h || X >= a.w) continue;
-        float2 s = make_float2(0.f, 0.f);
+      for (int m = 0; m < R; ++m) cn[m] = make_float2(0.f, 0.f);
+#pragma unroll 1
+      for (int k = 0; k < K; ++k) {
+        float2* row = Z + ((size_t)k * N + li) * N;
+        float2 z[R];
 #pragma unroll
-        for (int tap = 0; tap < 4; ++tap) {
-          const int uu = u - (tap >> 1), vv = v - (tap & 1);
-          if ((unsigned)uu >= (unsigned)N || (unsigned)vv >= (unsigned)N) continue;
-          const float wt = ((tap >> 1) ? wy1 : wy0) * ((tap & 1) ? wx1 : wx0);
-          float2 tv = make_float2(0.f, 0.f);
+        for (int m = 0; m < R; ++m) z[m] = row[(t + T * m) ^ csw];
+        if constexpr (XB) epie_line<N, true, G::TWREG>(z, XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+        else epie_line<N, true, G::TWREG>(z, RowArea<N>{row, csw, t}, twr, tw_s, t);
+        float2* pr = probe_row(k, li);
 #pragma unroll
-          for (int k = 0; k < K; ++k) tv = tv + cconjmul(pr[(size_t)k * NN + uu * N + vv], Z[(k * N + uu) * P + vv]);
-          s = s + wt * tv;
+        for (int m = 0; m < R; ++m) {
+          const int x = (t + T * m) ^ (psw * csw);
+          const float2 pk = pr[x];
+          cn[m] = cn[m] + cconjmul(pk, z[m]);
+          if (bs != 0.f) pr[x] = pk + bs * cconjmul(o[m], z[m]);
         }
-        a.obj[(size_t)Y * a.w + X] = foot[e] + as * s;
       }
+      // plane 0, row li: read by this line group only, so it can hold the contribution
+      float2* row0 = Z + (size_t)li * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) row0[(t + T * m) ^ csw] = cn[m];
     }
-    // probe update with the pre-update patch (after every read of the old probe)
-    const float bs = (a.probe_on && omax > 0.f) ? a.beta / omax : 0.f;
-    if constexpr (PL) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) {
-        const int k = i / NN, q = i % NN, u = q / N, v = q % N;
-        pl[i] = pl[i] + bs * cconjmul(patch(u, v), Z[(k * N + u) * P + v]);
+    lds_barrier();
+    // ---- D: object update over the (N+1)^2 footprint with the pre-update probe
+    opaque(li);
+    opaque(t);
+    if (pmax > 0.f) {
+      // Thread (column v, row block rb) walks rows rb R .. rb R + R - 1 of
+      // footprint column v; the last row block also takes row N and the
+      // threads of column N - 1 also column N.  The horizontal tap pair of row
+      // u - 1 is kept from the previous row, so each row reads two values of
+      // the contribution plane.
+      const float as = a.alpha / pmax;
+      const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
+      int tid = threadIdx.x;
+      opaque(tid);
+      const int v = tid % N, rb = tid / N, u0 = rb * R;
+      const bool row_n = rb == T - 1 && p.iy + N < a.h;     // footprint row N lies in the object
+      const bool col_n = v == N - 1 && p.ix + N < a.w;      // footprint column N lies in the object
+      float2* op = a.obj + (size_t)(p.iy + u0) * a.w + p.ix + v;
+      float2 ov[R + 1], ox[R + 1];
+      // every old value of this thread is loaded before any is written
+#pragma unroll
+      for (int i = 0; i <= R; ++i) {
+        const bool ok = i < R || row_n;
+        ov[i] = ok ? op[(size_t)i * a.w] : make_float2(0.f, 0.f);
+        ox[i] = (ok && col_n) ? op[(size_t)i * a.w + 1] : make_float2(0.f, 0.f);
       }
-    } else {
-      for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) {
-        const int k = i / NN, q = i % NN, u = q / N, v = q % N;
-        probe_nxt[i] = probe[i] + bs * cconjmul(patch(u, v), Z[(k * N + u) * P + v]);
+      const float2 zero = make_float2(0.f, 0.f);
+      // contribution c(u, v) and c(u, v - 1) (zero left of the patch)
+      auto ctap = [&](int u, float2& c0, float2& c1) {
+        const int sw = epie_swz(u);
+        c0 = Z[u * N + (v ^ sw)];
+        c1 = v > 0 ? Z[u * N + ((v - 1) ^ sw)] : make_float2(0.f, 0.f);
+      };
+      float2 hp = zero, hxp = zero;
+      if (u0 > 0) {
+        float2 c0, c1;
+        ctap(u0 - 1, c0, c1);
+        hp = wx0 * c0 + wx1 * c1;
+        hxp = wx1 * c0;
       }
-      float2* tmp = probe;
-      probe = probe_nxt;
-      probe_nxt = tmp;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        float2 c0, c1;
+        ctap(u0 + i, c0, c1);
+        const float2 hc = wx0 * c0 + wx1 * c1, hxc = wx1 * c0;
+        op[(size_t)i * a.w] = ov[i] + as * (wy0 * hc + wy1 * hp);
+        if (col_n) op[(size_t)i * a.w + 1] = ox[i] + as * (wy0 * hxc + wy1 * hxp);
+        hp = hc;
+        hxp = hxc;
+      }
+      if (row_n) {   // footprint row N: only the taps of patch row N - 1
+        op[(size_t)R * a.w] = ov[R] + as * (wy1 * hp);
+        if (col_n) op[(size_t)R * a.w + 1] = ox[R] + as * (wy1 * hxp);
+      }
     }
     // the next position reads the updated object and probe
     __syncthreads();
   }
-  if constexpr (PL) {
-    // leave the probe where the alternating scheme would: probe1 after an odd count
+  // leave the probe where an alternating scheme would: probe1 after an odd count
+  if (a.count % 2 == 1 || PL) {
     float2* dst = (a.count % 2 == 1) ? a.probe1 : a.probe0;
-    for (int i = threadIdx.x; i < K * NN; i += kEpieThreads) dst[i] = pl[i];
+    for (int i = threadIdx.x; i < K * NN; i += NT) {
+      const int y = (i / N) % N, x = i % N;
+      dst[i] = PL ? pl[(i / N) * N + (x ^ epie_swz(y))] : a.probe0[i];
+    }
   }
 }
+#undef PTY_EPIE_LOAD_AMP
+
+// The scan order and positions, which the fused kernels only read, through
+// the constant address space: their uniform loads become scalar loads.
+struct ScanTables {
+  const int* order;
+  const PosInfo* pos;
+  __device__ int operator[](int i) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) int*)order)[i];
+#else
+    return order[i];
+#endif
+  }
+  __device__ PosInfo at(int j) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __attribute__((address_space(4))) PosInfo& q = ((const __attribute__((address_space(4))) PosInfo*)pos)[j];
+    return PosInfo{q.iy, q.ix, q.fy, q.fx};
+#else
+    return pos[j];
+#endif
+  }
+};
+
+__device__ __forceinline__ int dx_of(const PosInfo& p, const PosInfo& pn) { return p.ix - pn.ix; }
+
+// Fused ePIE with the object footprint and the probe on chip (windows up to
+// 64 x 64): the pre-update (N+1)^2 footprint of the current position sits in
+// LDS (FS-strided rows), so the patch gather and the object update read no
+// global memory; the footprint of the next position is assembled during the
+// current one: its pixels outside the current footprint are fetched from
+// global memory in pass B (they are final already), the others are taken
+// from the update of pass D as it is written.  Each thread keeps the probe
+// pixels it transforms (mode k, row li, columns t + T m) in registers for the
+// whole iteration.  Passes and the field layout as in k_epie_fused.
+template <int N, int K>
+struct EpieFbGeo {
+  static constexpr int R = FftShape<N>::R, T = FftShape<N>::T;
+  static constexpr int NT = N * T, W = LineLds<N>::words, F = N + 1;
+  static constexpr int FS = N + T;                     // footprint row stride: 8 (4) rows x 8 (4) columns conflict-free
+  static constexpr size_t budget = 150 * 1024;
+  static constexpr size_t z_bytes = sizeof(float2) * (size_t)K * N * N;
+  static constexpr size_t tw_bytes = sizeof(float2) * N;
+  static constexpr size_t fb_bytes = sizeof(float2) * 2 * (size_t)F * FS;
+  static constexpr size_t xb_bytes = sizeof(float2) * (size_t)N * W;
+  static constexpr bool XB = z_bytes + tw_bytes + fb_bytes + xb_bytes <= budget;
+  static constexpr size_t lds = z_bytes + tw_bytes + fb_bytes + (XB ? xb_bytes : 0);
+  static constexpr bool TWREG = R <= 8;
+};
+
+template <int N, int K>
+__global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused_fb(EpieRunArgs a) {
+  using G = EpieFbGeo<N, K>;
+  constexpr int R = G::R, T = G::T, NT = G::NT, NN = N * N, NW = NT / 64, F = G::F, FS = G::FS;
+  constexpr bool XB = G::XB;
+  extern __shared__ float2 lds[];
+  float2* Z = lds;                                   // K swizzled planes: exit waves / far field / chi
+  float2* tw_s = Z + (size_t)K * NN;                 // W_N table
+  float2* fb = tw_s + N;                             // two footprints, F x FS each
+  float2* xb = fb + 2 * F * FS;                      // per-line exchange areas (when XB)
+  __shared__ float redf[NW][2];
+  __shared__ double redd[NW][2];
+  const ScanTables order{a.order, a.pos};
+  int li = threadIdx.x / T, t = threadIdx.x % T;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < N; i += NT) tw_s[i] = reinterpret_cast<const float2*>(a.tw)[i];
+  float2 twr[G::TWREG ? R - 1 : 1];
+  if constexpr (G::TWREG) {
+    const float2* tw = reinterpret_cast<const float2*>(a.tw);
+#pragma unroll
+    for (int q = 1; q < R; ++q) twr[q - 1] = tw[(t * q) & (N - 1)];
+  }
+  float2 pk[K][R];   // this thread's probe pixels (k, li, t + T m)
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) pk[k][m] = a.probe0[((size_t)k * N + li) * N + t + T * m];
+  }
+  float amp_n[R];
+#define PTY_EPIE_LOAD_AMP(nidx) PTY_EPIE_LOAD_AMP_J(order[(nidx)])
+#define PTY_EPIE_LOAD_AMP_J(jidx)                                              \
+  do {                                                                        \
+    const float* ap_ = a.amp + (size_t)(jidx) * NN;                           \
+    _Pragma("unroll") for (int m_ = 0; m_ < R; ++m_) amp_n[m_] = ap_[(unsigned)((t + T * m_) * N + li)]; \
+  } while (0)
+  // scan entries, fetched ahead: this position (jc, pc), the next (jn, pnx)
+  // and the index of the one after (jnn, read in pass A, its position in C)
+  int jc = 0, jn = 0;
+  PosInfo pc{}, pnx{};
+  if (a.count > 0) {
+    jc = order[0];
+    jn = a.count > 1 ? order[1] : jc;
+    pc = order.at(jc);
+    pnx = order.at(jn);
+    PTY_EPIE_LOAD_AMP(0);
+    const PosInfo p0 = pc;
+    for (int e = threadIdx.x; e < F * F; e += NT) {
+      const int u = e / F, v = e % F, Y = p0.iy + u, X = p0.ix + v;
+      fb[u * FS + v] = (Y < a.h && X < a.w) ? a.obj[(size_t)Y * a.w + X] : make_float2(0.f, 0.f);
+    }
+  }
+  __syncthreads();
+  constexpr float sc = 1.0f / N, sc2 = 1.0f / (float(N) * float(N));
+  for (int n = 0; n < a.count; ++n) {
+    const int j = jc;
+    const PosInfo p = pc;
+    const bool more = n + 1 < a.count;
+    const PosInfo pn = pnx;
+    const int jnn = n + 2 < a.count ? order[n + 2] : jn;
+    float2* cur = fb + (n & 1) * F * FS;
+    float2* nxt = fb + ((n + 1) & 1) * F * FS;
+    float amp_c[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) amp_c[m] = amp_n[m];
+    // ---- A: row li of the patch and of every exit wave, forward x-transform
+    opaque(li);
+    opaque(t);
+    float2 o[R];
+    float om = 0.f, pm = 0.f;
+    {
+      const float wx1 = p.fx, wx0 = 1.f - p.fx, wy1 = p.fy, wy0 = 1.f - p.fy;
+      const float2* f0 = cur + li * FS + t;
+      const float2* f1 = f0 + FS;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const float2 va = f0[T * m], vb = f0[T * m + 1], vc = f1[T * m], vd = f1[T * m + 1];
+        o[m] = make_float2(wy0 * (wx0 * va.x + wx1 * vb.x) + wy1 * (wx0 * vc.x + wx1 * vd.x),
+                           wy0 * (wx0 * va.y + wx1 * vb.y) + wy1 * (wx0 * vc.y + wx1 * vd.y));
+        om = fmaxf(om, cabs2(o[m]));
+        float sp = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sp += cabs2(pk[k][m]);
+        pm = fmaxf(pm, sp);
+      }
+    }
+    const int rsw = epie_swz(li);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      float2 z[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) z[m] = cmul(pk[k][m], o[m]);
+      float2* row = Z + ((size_t)k * N + li) * N;
+      if constexpr (XB) epie_line<N, false, G::TWREG>(z, XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+      else epie_line<N, false, G::TWREG>(z, RowArea<N>{row, rsw, t}, twr, tw_s, t);
+#pragma unroll
+      for (int m = 0; m < R; ++m) row[(t + T * m) ^ rsw] = z[m];
+    }
+    pm = wave_max_nonneg(pm);
+    om = wave_max_nonneg(om);
+    if (lane == 0) {
+      redf[wid][0] = pm;
+      redf[wid][1] = om;
+    }
+    // full barrier: the previous position's object stores are complete
+    // before pass B fetches the next footprint from global memory
+    __syncthreads();
+    // ---- B: column li of every mode: y-transform, projection, inverse y-transform
+    opaque(li);
+    opaque(t);
+    // next footprint, pixels (rb R + i, v) (+ row N, + column N), fetched now
+    int tid = threadIdx.x;
+    opaque(tid);
+    const int v = tid % N, rb = tid / N, u0 = rb * R;
+    float2 nv[R + 1], ncn;
+    {
+      // unconditional loads (a load under a branch would be waited for at
+      // once): rows below N are inside the object, row N is clamped to it;
+      // column N of the next footprint comes one pixel per thread (rows
+      // tid <= N), clamped likewise; pixels past the object are dropped in D
+      const float2* rp = a.obj + (size_t)(pn.iy + u0) * a.w + pn.ix + v;
+#pragma unroll
+      for (int i = 0; i < R; ++i) nv[i] = rp[(size_t)i * a.w];
+      nv[R] = a.obj[(size_t)min(pn.iy + u0 + R, a.h - 1) * a.w + pn.ix + v];
+      ncn = a.obj[(size_t)min(pn.iy + min(tid, N), a.h - 1) * a.w + min(pn.ix + N, a.w - 1)];
+    }
+    {
+      float2 z[K][R];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const ColArea<N> col{Z + (size_t)k * NN, li, t};
+#pragma unroll
+        for (int m = 0; m < R; ++m) z[k][m] = col.at(t + T * m);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if constexpr (XB) epie_line<N, false, G::TWREG>(z[k], XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+        else epie_line<N, false, G::TWREG>(z[k], ColArea<N>{Z + (size_t)k * NN, li, t}, twr, tw_s, t);
+      }
+      if (more) PTY_EPIE_LOAD_AMP_J(jn);
+      float en = 0.f, ed = 0.f;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        float iraw = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) iraw += cabs2(z[k][m]);
+        // hardware square root and reciprocal (within 1 ulp each)
+        const float mod = __builtin_amdgcn_sqrtf(iraw) * sc;
+        const bool meas = !signbit(amp_c[m]);      // sign bit: no measurement
+        const float am = fabsf(amp_c[m]);
+        const float f = meas ? (am * __builtin_amdgcn_rcpf(fmaxf(mod, 1e-6f)) - 1.f) * sc2 : 0.f;
+        if (meas) {
+          en += (mod - am) * (mod - am);
+          ed += am * am;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) z[k][m] = f * z[k][m];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const ColArea<N> col{Z + (size_t)k * NN, li, t};
+        if constexpr (XB) epie_line<N, true, G::TWREG>(z[k], XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+        else epie_line<N, true, G::TWREG>(z[k], col, twr, tw_s, t);
+#pragma unroll
+        for (int m = 0; m < R; ++m) col.at(t + T * m) = z[k][m];
+      }
+      const double s0 = wave_sum_d(en), s1 = wave_sum_d(ed);
+      if (lane == 0) {
+        redd[wid][0] = s0;
+        redd[wid][1] = s1;
+      }
+    }
+    lds_barrier();
+    float pmax = 0.f, omax = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      pmax = fmaxf(pmax, redf[w][0]);
+      omax = fmaxf(omax, redf[w][1]);
+    }
+    if (threadIdx.x == 0) {
+      double e0 = 0.0, e1 = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        e0 += redd[w][0];
+        e1 += redd[w][1];
+      }
+      double* e = a.errp + (size_t)j * a.bpp * 2;
+      e[0] = e0;
+      e[1] = e1;
+      for (int cb = 1; cb < a.bpp; ++cb) e[2 * cb] = e[2 * cb + 1] = 0.0;
+    }
+    // ---- C: row li, inverse x-transform of every mode; contribution and probe update
+    opaque(li);
+    opaque(t);
+    const PosInfo pnn = order.at(jnn);
+    {
+      const float bs = (a.probe_on && omax > 0.f) ? a.beta / omax : 0.f;
+      const int csw = epie_swz(li);
+      float2 cn[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) cn[m] = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float2* row = Z + ((size_t)k * N + li) * N;
+        float2 z[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) z[m] = row[(t + T * m) ^ csw];
+        if constexpr (XB) epie_line<N, true, G::TWREG>(z, XbArea<N>{xb + li * G::W, t}, twr, tw_s, t);
+        else epie_line<N, true, G::TWREG>(z, RowArea<N>{row, csw, t}, twr, tw_s, t);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          cn[m] = cn[m] + cconjmul(pk[k][m], z[m]);
+          pk[k][m] = pk[k][m] + bs * cconjmul(o[m], z[m]);
+        }
+      }
+      float2* row0 = Z + (size_t)li * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) row0[(t + T * m) ^ csw] = cn[m];
+    }
+    lds_barrier();
+    // ---- D: object update over the (N+1)^2 footprint; the next footprint
+    {
+      const float as = pmax > 0.f ? a.alpha / pmax : 0.f;
+      const float wx0 = 1.f - p.fx, wx1 = p.fx, wy0 = 1.f - p.fy, wy1 = p.fy;
+      const bool last_rb = rb == T - 1;
+      const bool row_n = last_rb && p.iy + N < a.h;         // footprint row N lies in the object
+      const bool col_n = p.ix + N < a.w;                    // footprint column N lies in the object
+      // every LDS value this pass reads, before any LDS write: contribution
+      // taps c(u, v), c(u, v - 1) of rows u0 - 1 .. u0 + R - 1 and the
+      // footprint's old values of column v; column N (row tid <= N): the taps
+      // c(u, N - 1) of rows tid - 1 and tid and its old value
+      float2 c0v[R + 1], c1v[R + 1], ocv[R + 1];
+#pragma unroll
+      for (int i = 0; i <= R; ++i) {
+        const int u = max(u0 + i - 1, 0);
+        const int sw = epie_swz(u);
+        c0v[i] = Z[u * N + (v ^ sw)];
+        c1v[i] = Z[u * N + (max(v - 1, 0) ^ sw)];   // v = 0: weight zero below
+      }
+      const float2* oc = cur + u0 * FS + v;
+#pragma unroll
+      for (int i = 0; i <= R; ++i) ocv[i] = oc[i * FS];
+      const int uc = min(tid, N);
+      const float2 cnc = Z[min(uc, N - 1) * N + ((N - 1) ^ epie_swz(min(uc, N - 1)))];
+      const float2 cnp = Z[max(uc - 1, 0) * N + ((N - 1) ^ epie_swz(max(uc - 1, 0)))];
+      const float2 ocn = cur[uc * FS + N];
+      if (more) {
+        // pixels of the next footprint outside this one: from pass B's fetch
+        const int du = pn.iy + u0 - p.iy;                    // row of this footprint, minus i
+        const int xr = pn.ix + v - p.ix;                     // column of this footprint
+        const bool xin = (unsigned)xr <= (unsigned)N;
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+          if (i == R && !last_rb) continue;
+          const bool in_obj = i < R || pn.iy + N < a.h;
+          const bool yin = (unsigned)(du + i) <= (unsigned)N && in_obj;
+          if (!(yin && xin)) nxt[(u0 + i) * FS + v] = in_obj ? nv[i] : make_float2(0.f, 0.f);
+        }
+        if (tid <= N) {   // column N, row tid
+          const bool in_obj = pn.iy + tid < a.h && pn.ix + N < a.w;
+          const bool in_cur = (unsigned)(pn.iy + tid - p.iy) <= (unsigned)N &&
+                              (unsigned)(pn.ix + N - p.ix) <= (unsigned)N && in_obj;
+          if (!in_cur) nxt[tid * FS + N] = in_obj ? ncn : make_float2(0.f, 0.f);
+        }
+      }
+      float2* op = a.obj + (size_t)(p.iy + u0) * a.w + p.ix + v;
+      // this footprint's pixel (u, vv) is the next one's (u + dy, vv + dx)
+      const int dy = p.iy - pn.iy, dx = p.ix - pn.ix, vn = v + dx;
+      const bool vin = more && (unsigned)vn <= (unsigned)N;
+      const float cm = v > 0 ? wx1 : 0.f;                    // weight of c(u, v - 1)
+      float2 hp = u0 > 0 ? wx0 * c0v[0] + cm * c1v[0] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i <= R; ++i) {
+        if (i == R && !row_n) continue;
+        const float2 hc = i < R ? wx0 * c0v[i + 1] + cm * c1v[i + 1] : make_float2(0.f, 0.f);
+        const float2 val = ocv[i] + as * (wy0 * hc + wy1 * hp);
+        const int un = u0 + i + dy;
+        if (as != 0.f) op[(size_t)i * a.w] = val;
+        if (vin && (unsigned)un <= (unsigned)N) nxt[un * FS + vn] = val;
+        hp = hc;
+      }
+      if (tid <= N && col_n && (tid < N || p.iy + N < a.h)) {
+        // column N, row tid: only the taps of patch column N - 1
+        const float2 hxc = tid < N ? wx1 * cnc : make_float2(0.f, 0.f);
+        const float2 hxp = tid > 0 ? wx1 * cnp : make_float2(0.f, 0.f);
+        const float2 vx = ocn + as * (wy0 * hxc + wy1 * hxp);
+        if (as != 0.f) a.obj[(size_t)(p.iy + tid) * a.w + p.ix + N] = vx;
+        const int un = tid + dy, vnn = N + dx;
+        if (more && (unsigned)un <= (unsigned)N && (unsigned)vnn <= (unsigned)N) nxt[un * FS + vnn] = vx;
+      }
+    }
+    lds_barrier();
+    jc = jn;
+    pc = pnx;
+    jn = jnn;
+    pnx = pnn;
+  }
+  // probe out: probe1 after an odd count (the buffer an alternating scheme ends in)
+  float2* dst = (a.count % 2 == 1) ? a.probe1 : a.probe0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) dst[((size_t)k * N + li) * N + t + T * m] = pk[k][m];
+  }
+}
+#undef PTY_EPIE_LOAD_AMP_J
+#undef PTY_EPIE_LOAD_AMP
 
 }  // namespace
 
@@ -1473,8 +2068,8 @@ void launch_iota_i32(int* p, int n, hipStream_t s) {
 }
 
 bool epie_fused_supported(int n, int k) {
-  if (n == 32) return k >= 1 && k <= 4;
-  if (n == 64) return k >= 1 && k <= 2;
+  if (n == 32 || n == 64) return k >= 1 && k <= 4;
+  if (n == 128) return k == 1;
   return false;
 }
 
@@ -1483,16 +2078,24 @@ void launch_epie_fused(const EpieRunArgs& a) {
   if (!epie_fused_supported(a.n, a.k)) throw std::invalid_argument("fused ePIE: unsupported window");
   auto go = [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
-    if constexpr ((N == 32 && K <= 4) || (N == 64 && K <= 2)) {
-      constexpr size_t lds = EpieFusedGeo<N>::template lds_bytes<K>();
-      static_assert(lds <= 150 * 1024, "fused ePIE field must fit in LDS");
+    if constexpr (N == 32 || (N == 64 && K <= 2)) {
+      // footprint and probe on chip
+      using G = EpieFbGeo<N, K>;
+      static_assert(G::lds <= G::budget, "fused ePIE field and footprints must fit in LDS");
+      PTY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_epie_fused_fb<N, K>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds));
+      k_epie_fused_fb<N, K><<<1, G::NT, G::lds, a.stream>>>(a);
+    } else if constexpr (N == 64 || K == 1) {
+      using G = EpieGeo<N, K>;
+      static_assert(G::lds <= G::budget, "fused ePIE field must fit in LDS");
       PTY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_epie_fused<N, K>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      k_epie_fused<N, K><<<1, kEpieThreads, lds, a.stream>>>(a);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds));
+      k_epie_fused<N, K><<<1, G::NT, G::lds, a.stream>>>(a);
     }
   };
   if (a.n == 32) dispatch_k<32>(a.k, go);
-  else dispatch_k<64>(a.k, go);
+  else if (a.n == 64) dispatch_k<64>(a.k, go);
+  else dispatch_k<128>(a.k, go);
   PTY_LAUNCH_CHECK("epie_fused");
 }
 

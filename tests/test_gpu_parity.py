@@ -110,6 +110,24 @@ def test_epie_one_iteration(n, k, j, chunk, batch, seed):
     pl.close()
 
 
+# windows of the one-workgroup ePIE kernel (32^2 and 64^2 up to four modes,
+# 128^2 with one), odd and even position counts (the probe's final buffer)
+FUSED = [(32, 4, 13), (64, 2, 12), (64, 3, 9), (64, 4, 7), (128, 1, 9), (128, 1, 8)]
+
+
+@pytest.mark.parametrize("n,k,j", FUSED)
+def test_epie_fused_window_two_iterations(n, k, j):
+    case = _case(n, k, j)
+    o0, p0 = start_state(case, perturb=0.05)
+    pl = _plan(case, o0, p0)
+    pl.iterate("epie", 2, probe_update_start=0, order_seed=5)
+    o1, p1, err = oracle.epie(o0, p0, case.amp, case.pos, 2, start=0, order_seed=5)
+    assert rel(pl.object(), o1) <= TOL
+    assert rel(pl.probe(), p1) <= TOL
+    assert np.allclose(pl.errors()[:2], err[:2], rtol=TOL, atol=0)
+    pl.close()
+
+
 def _oracle_run(algo, case, o0, p0, n_iter, start):
     if algo == "epie":
         o, _, err = oracle.epie(o0, p0, case.amp, case.pos, n_iter, start=start)
