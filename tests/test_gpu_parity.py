@@ -110,8 +110,9 @@ def test_epie_one_iteration(n, k, j, chunk, batch, seed):
     pl.close()
 
 
-# windows of the one-workgroup ePIE kernel (32^2 and 64^2 up to four modes,
-# 128^2 with one), odd and even position counts (the probe's final buffer)
+# windows of the one-workgroup ePIE kernels (32^2 and 64^2 up to four modes;
+# 128^2 runs the per-position launches), odd and even position counts (the
+# probe's final buffer)
 FUSED = [(32, 4, 13), (64, 2, 12), (64, 3, 9), (64, 4, 7), (128, 1, 9), (128, 1, 8)]
 
 
