@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libptymi.so")
 
-SOURCES = ["pty_fourier.hip", "pty_update.hip", "pty_seed.hip", "pty_cnn.hip", "pty_api.cpp"]
+SOURCES = ["pty_fourier.hip", "pty_update.hip", "pty_epie_wide.hip", "pty_seed.hip", "pty_cnn.hip", "pty_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -143,6 +143,8 @@ struct pty_ctx {
   int* epie_order = nullptr;       // device copy of a shuffled ePIE order
   unsigned* epie_max = nullptr;    // per position of an iteration: the two ePIE step normalisers
   float2* epie_patch = nullptr;    // N x N: the pre-update patch of the current ePIE position
+  float* epw_max = nullptr;        // 512 x 512 ePIE: per row block the two step maxima
+  double* epw_err = nullptr;       // 512 x 512 ePIE: per column block the two error sums
   // adjoint with positions supplied on the device: their PosInfo form and
   // device-built tile lists over all object tiles
   PosInfo* adj_pos = nullptr;
@@ -913,8 +915,45 @@ void run_epie(pty_ctx* c, int n_iter, const pty_iter_params& p) {
       end_iteration(c, t);
       continue;
     }
-    c->ensure_once(c->epie_max, size_t(2) * c->J);
     c->ensure_once(c->epie_patch, nn);
+    if (epie_wide_supported(c->N, c->K)) {
+      // 512 x 512: one wavefront per line, three launches per position; with
+      // probe updates the new probe goes to the other buffer
+      c->ensure_once(c->epw_max, epie_wide_max_words());
+      c->ensure_once(c->epw_err, epie_wide_err_words());
+      EpieWideArgs w{};
+      w.n = c->N;
+      w.k = c->K;
+      w.obj = c->obj;
+      w.h = c->H;
+      w.w = c->W;
+      w.amp = c->amp;
+      w.zs = c->zs;
+      w.patch = c->epie_patch;
+      w.contrib = c->contrib;
+      w.maxw = c->epw_max;
+      w.errw = c->epw_err;
+      w.errp = c->errp;
+      w.bpp = col_blocks(c->N, c->K);
+      w.tw = reinterpret_cast<const float*>(c->tw);
+      w.alpha = p.alpha;
+      w.beta = p.beta;
+      w.probe_on = pon ? 1 : 0;
+      w.masked = c->have_mask ? 1 : 0;
+      w.stream = c->stream;
+      for (int j : order) {
+        w.pos = c->hpos[j];
+        w.j = j;
+        w.probe = c->probe;
+        w.probe_out = pon ? c->probe_alt : c->probe;
+        timed(c, kEpie, [&] { launch_epie_wide(w); });
+        if (pon) std::swap(c->probe, c->probe_alt);
+      }
+      maybe_orthogonalise(c, p, pon, nullptr);
+      end_iteration(c, t);
+      continue;
+    }
+    c->ensure_once(c->epie_max, size_t(2) * c->J);
     timed(c, kOther, [&] { launch_fill_u32(c->epie_max, size_t(2) * c->J, 0u, c->stream); });
     int slot = 0;
     for (int j : order) {

@@ -186,6 +186,41 @@ struct EpieArgs {
 };
 void launch_epie_update(const EpieArgs& a);
 
+// ePIE positions of 512 x 512 windows (1 or 2 modes), one 64-lane wavefront
+// per line: per position three launches (rows with the step maxima, columns
+// with the projection, inverse rows with the probe update and the object
+// update).  probe_out receives the updated probe; it may be the probe itself
+// only when probe updates are off (then nothing is written).  zs: K x N x N scratch; patch,
+// contrib: N x N scratch; maxw: epie_wide_max_words() floats; errw:
+// epie_wide_err_words() doubles.  The position's error partials go to errp
+// (pattern j, bpp column slots: the sums in the first, zeros in the rest).
+struct EpieWideArgs {
+  int n, k;
+  float2* obj;
+  int h, w;
+  const float2* probe;    // K x N x N
+  float2* probe_out;      // K x N x N: the updated probe
+  const float* amp;       // J x N x N measured moduli (natural order)
+  PosInfo pos;
+  int j;                  // pattern index
+  float2* zs;
+  float2* patch;
+  float2* contrib;
+  float* maxw;
+  double* errw;
+  double* errp;
+  int bpp;
+  const float* tw;        // W_N table (N float2)
+  float alpha, beta;
+  int probe_on;
+  int masked;
+  hipStream_t stream;
+};
+bool epie_wide_supported(int n, int k);
+size_t epie_wide_max_words();
+size_t epie_wide_err_words();
+void launch_epie_wide(const EpieWideArgs& a);
+
 // A whole ePIE iteration in one workgroup (small windows): for each position
 // in `order`, the exit waves, both 2-D transforms, the projection with its
 // error partials and both updates stay in LDS; positions run in sequence

@@ -16,9 +16,10 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 # (N, K, J, chunk, lsqml batch): the fused ePIE path (64^2), the per-position
-# launches with the mode split of the column pass (128^2, 4 modes) and the
-# production window (256^2, 3 modes)
-SHAPES = [(64, 2, 20, 7, 6), (128, 4, 9, 4, 4), (256, 3, 8, 3, 4)]
+# launches with the mode split of the column pass (128^2, 4 modes), the
+# production window (256^2, 3 modes) and the wavefront-per-line ePIE
+# launches (512^2)
+SHAPES = [(64, 2, 20, 7, 6), (128, 4, 9, 4, 4), (256, 3, 8, 3, 4), (512, 1, 4, 2, 2)]
 
 
 def _mask(n):

@@ -110,14 +110,16 @@ def test_epie_one_iteration(n, k, j, chunk, batch, seed):
     pl.close()
 
 
-# windows of the one-workgroup ePIE kernels (32^2 and 64^2 up to four modes;
-# 128^2 runs the per-position launches), odd and even position counts (the
-# probe's final buffer)
-FUSED = [(32, 4, 13), (64, 2, 12), (64, 3, 9), (64, 4, 7), (128, 1, 9), (128, 1, 8)]
+# ePIE windows of each kernel family: the one-workgroup kernels (32^2 and
+# 64^2 up to four modes), the per-position launches (128^2) and the
+# wavefront-per-line launches (512^2, one and two modes); odd and even
+# position counts (the probe's final buffer)
+EPIE_WINDOWS = [(32, 4, 13), (64, 2, 12), (64, 3, 9), (64, 4, 7), (128, 1, 9), (128, 1, 8),
+                (512, 1, 5), (512, 2, 4)]
 
 
-@pytest.mark.parametrize("n,k,j", FUSED)
-def test_epie_fused_window_two_iterations(n, k, j):
+@pytest.mark.parametrize("n,k,j", EPIE_WINDOWS)
+def test_epie_window_two_iterations(n, k, j):
     case = _case(n, k, j)
     o0, p0 = start_state(case, perturb=0.05)
     pl = _plan(case, o0, p0)
