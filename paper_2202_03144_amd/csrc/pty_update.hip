@@ -463,14 +463,25 @@ __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
   }
 }
 
-__global__ void k_lsq_solve(LsqStepArgs a, int nrb) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.count) return;
-  const int nv = a.shift ? 9 : 5;
-  double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int r = 0; r < nrb; ++r)
-    for (int i = 0; i < nv; ++i) s[i] += a.part[((size_t)b * nrb + r) * nv + i];
-  if (a.shift) {
+// One wavefront per position: lane r sums row-block partials r, r + 64, ...
+// (coalesced across the lanes), the wavefront adds the lanes' sums in a fixed
+// DPP order, lane 0 solves.
+constexpr int kLsqSolveWaves = 4;
+template <int NV>
+__device__ __forceinline__ void lsq_solve_one(const LsqStepArgs& a, int b, int nrb) {
+  const int lane = threadIdx.x & 63;
+  double s[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) s[i] = 0.0;
+  for (int r = lane; r < nrb; r += 64) {
+    const double* pp = a.part + ((size_t)b * nrb + r) * NV;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s[i] += pp[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) s[i] = wave_sum_d(s[i]);
+  if (lane != 0) return;
+  if constexpr (NV == 9) {
     // least-squares shift along each axis, clipped
     const double m = a.max_shift;
     const double sy = s[7] > 0.0 ? s[5] / s[7] : 0.0, sx = s[8] > 0.0 ? s[6] / s[8] : 0.0;
@@ -493,6 +504,15 @@ __global__ void k_lsq_solve(LsqStepArgs a, int nrb) {
   const float2 al = make_float2((float)ao, (float)ap);
   a.alpha[b] = al;
   a.alpha_by_j[a.jlist[b]] = al;
+}
+
+__global__ __launch_bounds__(64 * kLsqSolveWaves) void k_lsq_solve(LsqStepArgs a, int nrb) {
+  const int b = blockIdx.x * kLsqSolveWaves + (threadIdx.x >> 6);
+  if (b >= a.count) return;   // whole wavefronts
+  if (a.shift)
+    lsq_solve_one<9>(a, b, nrb);
+  else
+    lsq_solve_one<5>(a, b, nrb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1660,7 +1680,7 @@ void launch_lsq_steps(const LsqStepArgs& a) {
     }
   });
   PTY_LAUNCH_CHECK("lsq_sums");
-  k_lsq_solve<<<(a.count + 127) / 128, 128, 0, a.stream>>>(a, nrb);
+  k_lsq_solve<<<(a.count + kLsqSolveWaves - 1) / kLsqSolveWaves, 64 * kLsqSolveWaves, 0, a.stream>>>(a, nrb);
   PTY_LAUNCH_CHECK("lsq_solve");
 }
 
