@@ -44,6 +44,38 @@ __device__ __forceinline__ V hrow(const V* __restrict__ src, int u, int v0c, int
   return axpy(w1 * uok, r[v1c], axpy(w0 * uok, r[v0c], Zero<V>::v()));
 }
 
+// The value of lane i - 1 (lane 0: `first`), by a wavefront-wide DPP shift.
+__device__ __forceinline__ float lane_shr1(float x, float first) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first), __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float2 lane_shr1(float2 x, float2 first) {
+  return make_float2(lane_shr1(x.x, first.x), lane_shr1(x.y, first.y));
+}
+// A load from a wavefront-uniform address, through the constant address space
+// (a scalar load; the planes read here are not written by the kernel).
+template <typename V>
+__device__ __forceinline__ V uniform_load(const V* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // the address is the same in every lane: make that explicit
+  const unsigned long long a = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a), hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  return *(const __attribute__((address_space(4))) V*)(((unsigned long long)hi << 32) | lo);
+#else
+  return *p;
+#endif
+}
+// hrow for a wavefront whose lanes are consecutive columns: one vector load
+// of column v per lane; column v - 1 is the neighbouring lane's value, and
+// lane 0's (column v1c0, uniform) comes from a scalar load.
+template <int N, typename V>
+__device__ __forceinline__ V hrow_wave(const V* __restrict__ src, int u, int v0c, int v1c0, float w0, float w1) {
+  const float uok = (unsigned)u < (unsigned)N ? 1.f : 0.f;
+  const V* r = src + min(max(u, 0), N - 1) * N;
+  const V c0 = r[v0c];
+  const V c1 = lane_shr1(c0, uniform_load(r + v1c0));
+  return axpy(w1 * uok, c1, axpy(w0 * uok, c0, Zero<V>::v()));
+}
+
 
 template <int N, ObjOp OP>
 __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
@@ -73,13 +105,15 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
     const int v = X - r.ix;
     const float w0 = (unsigned)v < (unsigned)N ? 1.f - r.fx : 0.f;
     const float w1 = (unsigned)(v - 1) < (unsigned)N ? r.fx : 0.f;
-    const int v0c = min(max(v, 0), N - 1), v1c = min(max(v - 1, 0), N - 1);
+    // lane i's column v - 1 is lane i - 1's column v (the lanes are
+    // consecutive columns), lane 0's is te.tx - 1 - r.ix
+    const int v0c = min(max(v, 0), N - 1), v1c0 = min(max(te.tx - 1 - r.ix, 0), N - 1);
     const float wy0 = wgt * (1.f - r.fy), wy1 = wgt * r.fy;
     const int u0 = te.ty - r.iy;
-    V prev = hrow<N, V>(src, u0 - 1, v0c, v1c, w0, w1);
+    V prev = hrow_wave<N, V>(src, u0 - 1, v0c, v1c0, w0, w1);
 #pragma unroll
     for (int i = 0; i < TH; ++i) {
-      const V cur = hrow<N, V>(src, u0 + i, v0c, v1c, w0, w1);
+      const V cur = hrow_wave<N, V>(src, u0 + i, v0c, v1c0, w0, w1);
       acc[i] = axpy(wy0, cur, axpy(wy1, prev, acc[i]));
       prev = cur;
     }
