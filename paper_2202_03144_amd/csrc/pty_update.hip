@@ -872,6 +872,32 @@ __device__ __forceinline__ void epie_line(float2* v, const Area& ar, const float
   wave_sync();
 }
 
+// The iteration's amplitude-error sums of a one-workgroup ePIE kernel: each
+// lane's sums over the positions, added over the wavefront (DPP, fixed
+// order) and the wavefronts in order, go to the first pair of the error
+// partials; every other pair of the iteration's patterns is zeroed (the
+// reduction sums them all).
+__device__ __forceinline__ void epie_error_out(const EpieRunArgs& a, double num, double den, double (*red)[2], int nt) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double s0 = wave_sum_d(num), s1 = wave_sum_d(den);
+  if (lane == 0) {
+    red[wid][0] = s0;
+    red[wid][1] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e0 = 0.0, e1 = 0.0;
+    for (int w = 0; w < nt / 64; ++w) {
+      e0 += red[w][0];
+      e1 += red[w][1];
+    }
+    a.errp[0] = e0;
+    a.errp[1] = e1;
+  }
+  const size_t pairs = (size_t)a.count * a.bpp;
+  for (size_t i = 1 + threadIdx.x; i < pairs; i += nt) a.errp[2 * i] = a.errp[2 * i + 1] = 0.0;
+}
+
 // Workgroup barrier that orders LDS only: global loads still in flight (the
 // next pattern's moduli) stay in flight across it.  Global memory written in
 // one pass and read by other threads in the next needs __syncthreads().
@@ -958,6 +984,7 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused(EpieRunArgs a
   // the transforms are unscaled: the unitary far field is Z / N, and the
   // unitary inverse contributes another 1 / N^2, folded into the projection
   constexpr float sc = 1.0f / N, sc2 = 1.0f / (float(N) * float(N));
+  double err_num = 0.0, err_den = 0.0;   // this lane's amplitude-error sums over the positions
   for (int n = 0; n < a.count; ++n) {
     const int j = a.order[n];
     const PosInfo p = a.pos[j];
@@ -1053,11 +1080,9 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused(EpieRunArgs a
 #pragma unroll
         for (int m = 0; m < R; ++m) col.at(t + T * m) = z[k][m];
       }
-      const double s0 = wave_sum_d(en), s1 = wave_sum_d(ed);
-      if (lane == 0) {
-        redd[wid][0] = s0;
-        redd[wid][1] = s1;
-      }
+      // the error needs only the sums over all positions: kept per lane
+      err_num += en;
+      err_den += ed;
     }
     lds_barrier();
     // block maxima of pass A (written before the previous barrier)
@@ -1066,17 +1091,6 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused(EpieRunArgs a
     for (int w = 0; w < NW; ++w) {
       pmax = fmaxf(pmax, redf[w][0]);
       omax = fmaxf(omax, redf[w][1]);
-    }
-    if (threadIdx.x == 0) {
-      double e0 = 0.0, e1 = 0.0;
-      for (int w = 0; w < NW; ++w) {
-        e0 += redd[w][0];
-        e1 += redd[w][1];
-      }
-      double* e = a.errp + (size_t)j * a.bpp * 2;
-      e[0] = e0;
-      e[1] = e1;
-      for (int cb = 1; cb < a.bpp; ++cb) e[2 * cb] = e[2 * cb + 1] = 0.0;
     }
     // ---- C: row li, inverse x-transform of every mode; contribution and probe update
     opaque(li);
@@ -1167,6 +1181,7 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused(EpieRunArgs a
     // the next position reads the updated object and probe
     __syncthreads();
   }
+  epie_error_out(a, err_num, err_den, redd, NT);
   // leave the probe where an alternating scheme would: probe1 after an odd count
   if (a.count % 2 == 1 || PL) {
     float2* dst = (a.count % 2 == 1) ? a.probe1 : a.probe0;
@@ -1279,6 +1294,7 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused_fb(EpieRunArg
   }
   __syncthreads();
   constexpr float sc = 1.0f / N, sc2 = 1.0f / (float(N) * float(N));
+  double err_num = 0.0, err_den = 0.0;   // this lane's amplitude-error sums over the positions
   for (int n = 0; n < a.count; ++n) {
     const int j = jc;
     const PosInfo p = pc;
@@ -1391,11 +1407,9 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused_fb(EpieRunArg
 #pragma unroll
         for (int m = 0; m < R; ++m) col.at(t + T * m) = z[k][m];
       }
-      const double s0 = wave_sum_d(en), s1 = wave_sum_d(ed);
-      if (lane == 0) {
-        redd[wid][0] = s0;
-        redd[wid][1] = s1;
-      }
+      // the error needs only the sums over all positions: kept per lane
+      err_num += en;
+      err_den += ed;
     }
     lds_barrier();
     float pmax = 0.f, omax = 0.f;
@@ -1403,17 +1417,6 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused_fb(EpieRunArg
     for (int w = 0; w < NW; ++w) {
       pmax = fmaxf(pmax, redf[w][0]);
       omax = fmaxf(omax, redf[w][1]);
-    }
-    if (threadIdx.x == 0) {
-      double e0 = 0.0, e1 = 0.0;
-      for (int w = 0; w < NW; ++w) {
-        e0 += redd[w][0];
-        e1 += redd[w][1];
-      }
-      double* e = a.errp + (size_t)j * a.bpp * 2;
-      e[0] = e0;
-      e[1] = e1;
-      for (int cb = 1; cb < a.bpp; ++cb) e[2 * cb] = e[2 * cb + 1] = 0.0;
     }
     // ---- C: row li, inverse x-transform of every mode; contribution and probe update
     opaque(li);
@@ -1521,6 +1524,7 @@ __global__ __launch_bounds__(N * FftShape<N>::T) void k_epie_fused_fb(EpieRunArg
     jn = jnn;
     pnx = pnn;
   }
+  epie_error_out(a, err_num, err_den, redd, NT);
   // probe out: probe1 after an odd count (the buffer an alternating scheme ends in)
   float2* dst = (a.count % 2 == 1) ? a.probe1 : a.probe0;
 #pragma unroll
