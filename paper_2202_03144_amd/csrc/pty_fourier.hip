@@ -30,6 +30,57 @@ __device__ __forceinline__ size_t zoff(int y, int x) {
   return ((size_t)(x >> 2) * N + y) * 4 + (x & 3);
 }
 
+// Row y of S_j O at the columns t + T m a line's lanes own, for lines of
+// T = 16 lanes (one DPP row): the taps of column c + 1 are the next lane's
+// taps of column c (for the last lane, lane 0's of the next m; past the last
+// m, one more load, clamped like obj_bilinear's), so an element costs two
+// loads instead of four.  Values and arithmetic are obj_bilinear's.
+__device__ __forceinline__ float2 row_rotl1(float2 v) {   // lane i <- lane i + 1 of its row of 16
+  return make_float2(__int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v.x), 0x12F, 0xf, 0xf, false)),
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v.y), 0x12F, 0xf, 0xf, false)));
+}
+template <int N>
+__device__ __forceinline__ void line_bilinear(const float2* __restrict__ o, int h, int w, const PosInfo& p, int y, int t,
+                                              float2* out) {
+  constexpr int R = FftShape<N>::R, T = FftShape<N>::T;
+  if constexpr (T != 16) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) out[m] = obj_bilinear(o, h, w, p, y, t + T * m);
+  } else {
+    const int r0 = p.iy + y, r1 = min(r0 + 1, h - 1);
+    const float2* a0 = o + (size_t)r0 * w + p.ix + t;
+    const float2* a1 = o + (size_t)r1 * w + p.ix + t;
+    float2 va[R], vc[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      va[m] = a0[T * m];
+      vc[m] = a1[T * m];
+    }
+    const int ce = min(p.ix + N, w - 1);
+    const float2 ea = o[(size_t)r0 * w + ce], ec = o[(size_t)r1 * w + ce];
+    const float wx1 = p.fx, wx0 = 1.f - p.fx, wy1 = p.fy, wy0 = 1.f - p.fy;
+    const bool last = t == T - 1;
+    float2 ra = row_rotl1(va[0]), rc = row_rotl1(vc[0]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      float2 b, d;
+      if (m + 1 < R) {
+        const float2 na = row_rotl1(va[m + 1]), nc = row_rotl1(vc[m + 1]);
+        b = last ? na : ra;
+        d = last ? nc : rc;
+        ra = na;
+        rc = nc;
+      } else {
+        b = last ? ea : ra;
+        d = last ? ec : rc;
+      }
+      const float2 a = va[m], c = vc[m];
+      out[m] = make_float2(wy0 * (wx0 * a.x + wx1 * b.x) + wy1 * (wx0 * c.x + wx1 * d.x),
+                           wy0 * (wx0 * a.y + wx1 * b.y) + wy1 * (wx0 * c.y + wx1 * d.y));
+    }
+  }
+}
+
 template <int N, int K, RowIn MODE>
 __global__ __launch_bounds__(Geo<N>::BS)
 void k_rows_fwd(FourierArgs a) {
@@ -45,8 +96,7 @@ void k_rows_fwd(FourierArgs a) {
   const int j = a.jlist[a.jl_off + c];
   const PosInfo p = a.pos[j];
   float2 o[R];
-#pragma unroll
-  for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
+  line_bilinear<N>(a.obj, a.h, a.w, p, y, t, o);
   // One mode at a time keeps the register footprint at one line per thread;
   // the next mode's probe (and DM exit-wave) row is loaded before this mode's
   // transform and stores, so the loads overlap them.
@@ -260,10 +310,7 @@ void k_rows_inv(FourierArgs a) {
   // the column pass already applied the unitary scales of both transforms
   float2 o[MODE == RowOut::DmUpdate ? R : 1];
   float2 gdy[MODE == RowOut::NllGrad ? R : 1], gdx[MODE == RowOut::NllGrad ? R : 1];
-  if constexpr (MODE == RowOut::DmUpdate) {
-#pragma unroll
-    for (int m = 0; m < R; ++m) o[m] = obj_bilinear(a.obj, a.h, a.w, p, y, t + T * m);
-  }
+  if constexpr (MODE == RowOut::DmUpdate) line_bilinear<N>(a.obj, a.h, a.w, p, y, t, o);
   if constexpr (MODE == RowOut::NllGrad) {
 #pragma unroll
     for (int m = 0; m < R; ++m) obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, gdy[m], gdx[m]);
