@@ -81,51 +81,101 @@ __device__ __forceinline__ void line_bilinear(const float2* __restrict__ o, int 
   }
 }
 
+// Patterns per block of the forward rows: with three or more modes each
+// probe row is loaded once for two patterns (with fewer modes the two
+// patterns' registers do not fit beside each other).
+template <int N, int K>
+constexpr int rows_fwd_patterns() { return (K >= 3 && N <= 256) ? 2 : 1; }
+
 template <int N, int K, RowIn MODE>
 __global__ __launch_bounds__(Geo<N>::BS)
 void k_rows_fwd(FourierArgs a) {
   using G = Geo<N>;
-  constexpr int R = G::R, T = G::T;
+  constexpr int R = G::R, T = G::T, PB = rows_fwd_patterns<N, K>();
   __shared__ float2 tw_s[N];
   __shared__ float2 xb[G::LINES * G::W];
   load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
   const int line = threadIdx.x / T, t = threadIdx.x % T;
-  const int c = blockIdx.y;
   const int y = blockIdx.x * G::LINES + line;
-  const int slot = a.slot_off + c;
-  const int j = a.jlist[a.jl_off + c];
-  const PosInfo p = a.pos[j];
-  float2 o[R];
-  line_bilinear<N>(a.obj, a.h, a.w, p, y, t, o);
-  // One mode at a time keeps the register footprint at one line per thread;
-  // the next mode's probe (and DM exit-wave) row is loaded before this mode's
-  // transform and stores, so the loads overlap them.
   constexpr bool DMR = MODE == RowIn::DmReflect;
-  float2 pa[R], pb[DMR ? R : 1];
-  auto load_mode = [&](int k) {
-    const float2* pr = a.probe + ((size_t)k * N + y) * N;
+  if constexpr (PB == 1) {
+    const int c = blockIdx.y;
+    const int j = a.jlist[a.jl_off + c];
+    float2 o[R];
+    line_bilinear<N>(a.obj, a.h, a.w, a.pos[j], y, t, o);
+    // One mode at a time keeps the register footprint at one line per thread;
+    // the next mode's probe (and DM exit-wave) row is loaded before this mode's
+    // transform and stores, so the loads overlap them.
+    float2 pa[R], pb[DMR ? R : 1];
+    auto load_mode = [&](int k) {
+      const float2* pr = a.probe + ((size_t)k * N + y) * N;
 #pragma unroll
-    for (int m = 0; m < R; ++m) pa[m] = pr[t + T * m];
-    if constexpr (DMR) {
-      const float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
+      for (int m = 0; m < R; ++m) pa[m] = pr[t + T * m];
+      if constexpr (DMR) {
+        const float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
 #pragma unroll
-      for (int m = 0; m < R; ++m) pb[m] = ps[t + T * m];
-    }
-  };
-  load_mode(0);
+        for (int m = 0; m < R; ++m) pb[m] = ps[t + T * m];
+      }
+    };
+    load_mode(0);
 #pragma unroll 1
-  for (int k = 0; k < K; ++k) {
-    float2 z[R];
+    for (int k = 0; k < K; ++k) {
+      float2 z[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-      z[m] = cmul(pa[m], o[m]);
-      if constexpr (DMR) z[m] = 2.f * z[m] - pb[m];
+      for (int m = 0; m < R; ++m) {
+        z[m] = cmul(pa[m], o[m]);
+        if constexpr (DMR) z[m] = 2.f * z[m] - pb[m];
+      }
+      if (k + 1 < K) load_mode(k + 1);
+      line_fft<N, false>(z, xb + line * G::W, tw_s, t);
+      float2* out = a.zs + ((size_t)c * K + k) * N * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) out[zoff<N>(y, t + T * m)] = z[m];
     }
-    if (k + 1 < K) load_mode(k + 1);
-    line_fft<N, false>(z, xb + line * G::W, tw_s, t);
-    float2* out = a.zs + ((size_t)c * K + k) * N * N;
+  } else {
+    const int c0 = blockIdx.y * PB;
+    const int np = min(PB, a.nc - c0);          // patterns of this block (uniform)
+    int j[PB];
+    float2 o[PB][R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) out[zoff<N>(y, t + T * m)] = z[m];
+    for (int q = 0; q < PB; ++q) {
+      j[q] = a.jlist[a.jl_off + c0 + min(q, np - 1)];
+      line_bilinear<N>(a.obj, a.h, a.w, a.pos[j[q]], y, t, o[q]);
+    }
+    // One mode at a time; the mode's probe row serves both patterns, and the
+    // DM exit-wave rows of both are loaded with it, before the transforms.
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+      float2 pa[R], pb[DMR ? PB : 1][R];
+      const float2* pr = a.probe + ((size_t)k * N + y) * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) pa[m] = pr[t + T * m];
+      if constexpr (DMR) {
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+          const float2* ps = a.psi + (((size_t)j[q] * K + k) * N + y) * N;
+#pragma unroll
+          for (int m = 0; m < R; ++m) pb[q][m] = ps[t + T * m];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        if (q >= np) break;
+        float2 z[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          z[m] = cmul(pa[m], o[q][m]);
+          if constexpr (DMR) z[m] = 2.f * z[m] - pb[q][m];
+        }
+        line_fft<N, false>(z, xb + line * G::W, tw_s, t);
+        float2* out = a.zs + ((size_t)(c0 + q) * K + k) * N * N;
+#pragma unroll
+        for (int m = 0; m < R; ++m) out[zoff<N>(y, t + T * m)] = z[m];
+        // the second pattern's transform after the first's (interleaving the
+        // two would double the live registers)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
   }
 }
 
@@ -494,7 +544,8 @@ void launch_rows_fwd(const FourierArgs& a, RowIn mode) {
   if (a.nc <= 0) return;
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
-    const dim3 grid(N / Geo<N>::LINES, a.nc);
+    constexpr int PB = rows_fwd_patterns<N, K>();
+    const dim3 grid(N / Geo<N>::LINES, (a.nc + PB - 1) / PB);
     if (mode == RowIn::Plain)
       k_rows_fwd<N, K, RowIn::Plain><<<grid, Geo<N>::BS, 0, a.stream>>>(a);
     else
