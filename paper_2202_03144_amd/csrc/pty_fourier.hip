@@ -342,102 +342,172 @@ void k_cols_poisson(FourierArgs a) {
   cols_body<N, K, ColOp::Poisson, MASK>(a);
 }
 
+// Patterns per block of the inverse rows: storing chi with three or more
+// modes, each probe row is loaded once for two patterns (the DM update's
+// second object patch would not fit beside the first).
+template <int N, int K, RowOut MODE>
+constexpr int rows_inv_patterns() { return (K >= 3 && N <= 256 && MODE == RowOut::StoreChi) ? 2 : 1; }
+
 template <int N, int K, RowOut MODE>
 __global__ __launch_bounds__(Geo<N>::BS)
 void k_rows_inv(FourierArgs a) {
   using G = Geo<N>;
-  constexpr int R = G::R, T = G::T, BPP = N / G::LINES;
+  constexpr int R = G::R, T = G::T, BPP = N / G::LINES, PB = rows_inv_patterns<N, K, MODE>();
   __shared__ float2 tw_s[N];
   __shared__ float2 xb[G::LINES * G::W];
   __shared__ double red[G::BS / 64];
   load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
-  const int line = threadIdx.x / T, t = threadIdx.x % T;
-  const int c = blockIdx.y, rb = blockIdx.x;
-  const int y = rb * G::LINES + line;
-  const int slot = a.slot_off + c;
-  const int j = a.jlist[a.jl_off + c];
-  const PosInfo p = a.pos[j];
-  // the column pass already applied the unitary scales of both transforms
-  float2 o[MODE == RowOut::DmUpdate ? R : 1];
-  float2 gdy[MODE == RowOut::NllGrad ? R : 1], gdx[MODE == RowOut::NllGrad ? R : 1];
-  if constexpr (MODE == RowOut::DmUpdate) line_bilinear<N>(a.obj, a.h, a.w, p, y, t, o);
-  if constexpr (MODE == RowOut::NllGrad) {
-#pragma unroll
-    for (int m = 0; m < R; ++m) obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, gdy[m], gdx[m]);
-  }
-  // Poisson update: chi = -alpha_R F^-1[g Psi]
-  float chi_s = 1.f;
-  if constexpr (MODE == RowOut::StoreChi) {
-    if (a.poisp) chi_s = (float)(-a.poisp[slot]);
-  }
-  float2 cacc[R];
-#pragma unroll
-  for (int m = 0; m < R; ++m) cacc[m] = make_float2(0.f, 0.f);
-  float gy = 0.f, gx = 0.f;
-  // one mode at a time keeps the register footprint at one line per thread
-#pragma unroll 1
-  for (int k = 0; k < K; ++k) {
-    float2 z[R];
-    const float2* src = a.zs + ((size_t)c * K + k) * N * N;
-#pragma unroll
-    for (int m = 0; m < R; ++m) z[m] = src[zoff<N>(y, t + T * m)];
-    // the probe row is read before the transform: the epilogue's stores could
-    // alias it, so loads issued among them would each wait for the memory
-    // (the position-gradient epilogue keeps the late loads: its registers are full)
-    const float2* pr = a.probe + ((size_t)k * N + y) * N;
-    constexpr bool PRE = MODE != RowOut::NllGrad;
-    float2 pkr[PRE ? R : 1];
-    if constexpr (PRE) {
-#pragma unroll
-      for (int m = 0; m < R; ++m) pkr[m] = pr[t + T * m];
+  if constexpr (PB == 1) {
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int c = blockIdx.y, rb = blockIdx.x;
+    const int y = rb * G::LINES + line;
+    const int slot = a.slot_off + c;
+    const int j = a.jlist[a.jl_off + c];
+    const PosInfo p = a.pos[j];
+    // the column pass already applied the unitary scales of both transforms
+    float2 o[MODE == RowOut::DmUpdate ? R : 1];
+    float2 gdy[MODE == RowOut::NllGrad ? R : 1], gdx[MODE == RowOut::NllGrad ? R : 1];
+    if constexpr (MODE == RowOut::DmUpdate) line_bilinear<N>(a.obj, a.h, a.w, p, y, t, o);
+    if constexpr (MODE == RowOut::NllGrad) {
+  #pragma unroll
+      for (int m = 0; m < R; ++m) obj_bilinear_grad(a.obj, a.h, a.w, p, y, t + T * m, gdy[m], gdx[m]);
     }
-    line_fft<N, true>(z, xb + line * G::W, tw_s, t);
+    // Poisson update: chi = -alpha_R F^-1[g Psi]
+    float chi_s = 1.f;
     if constexpr (MODE == RowOut::StoreChi) {
-      if (a.poisp) {
-#pragma unroll
-        for (int m = 0; m < R; ++m) z[m] = chi_s * z[m];
-      }
+      if (a.poisp) chi_s = (float)(-a.poisp[slot]);
     }
-    if constexpr (MODE == RowOut::DmUpdate) {
-      float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const float2 pk = pkr[m];
-        const float2 nw = cmul(pk, o[m]) + z[m];
-        ps[t + T * m] = nw;
-        cacc[m] = cacc[m] + cconjmul(pk, nw);
+    float2 cacc[R];
+  #pragma unroll
+    for (int m = 0; m < R; ++m) cacc[m] = make_float2(0.f, 0.f);
+    float gy = 0.f, gx = 0.f;
+    // one mode at a time keeps the register footprint at one line per thread
+  #pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+      float2 z[R];
+      const float2* src = a.zs + ((size_t)c * K + k) * N * N;
+  #pragma unroll
+      for (int m = 0; m < R; ++m) z[m] = src[zoff<N>(y, t + T * m)];
+      // the probe row is read before the transform: the epilogue's stores could
+      // alias it, so loads issued among them would each wait for the memory
+      // (the position-gradient epilogue keeps the late loads: its registers are full)
+      const float2* pr = a.probe + ((size_t)k * N + y) * N;
+      constexpr bool PRE = MODE != RowOut::NllGrad;
+      float2 pkr[PRE ? R : 1];
+      if constexpr (PRE) {
+  #pragma unroll
+        for (int m = 0; m < R; ++m) pkr[m] = pr[t + T * m];
       }
-    } else {
-      const float gscale = (MODE == RowOut::NllGrad) ? 2.f : 1.f;
-      float2* ch = a.chi + (((size_t)slot * K + k) * N + y) * N;
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        float2 pk;
-        if constexpr (PRE) pk = pkr[m];
-        else pk = pr[t + T * m];
-        ch[t + T * m] = z[m];
-        cacc[m] = cacc[m] + gscale * cconjmul(pk, z[m]);
-        if constexpr (MODE == RowOut::NllGrad) {
-          const float2 gpy = cmul(pk, gdy[m]), gpx = cmul(pk, gdx[m]);
-          // Re(conj(g_psi) * P_k * d(S_j O))
-          gy += z[m].x * gpy.x + z[m].y * gpy.y;
-          gx += z[m].x * gpx.x + z[m].y * gpx.y;
+      line_fft<N, true>(z, xb + line * G::W, tw_s, t);
+      if constexpr (MODE == RowOut::StoreChi) {
+        if (a.poisp) {
+  #pragma unroll
+          for (int m = 0; m < R; ++m) z[m] = chi_s * z[m];
+        }
+      }
+      if constexpr (MODE == RowOut::DmUpdate) {
+        float2* ps = a.psi + (((size_t)j * K + k) * N + y) * N;
+  #pragma unroll
+        for (int m = 0; m < R; ++m) {
+          const float2 pk = pkr[m];
+          const float2 nw = cmul(pk, o[m]) + z[m];
+          ps[t + T * m] = nw;
+          cacc[m] = cacc[m] + cconjmul(pk, nw);
+        }
+      } else {
+        const float gscale = (MODE == RowOut::NllGrad) ? 2.f : 1.f;
+        float2* ch = a.chi + (((size_t)slot * K + k) * N + y) * N;
+  #pragma unroll
+        for (int m = 0; m < R; ++m) {
+          float2 pk;
+          if constexpr (PRE) pk = pkr[m];
+          else pk = pr[t + T * m];
+          ch[t + T * m] = z[m];
+          cacc[m] = cacc[m] + gscale * cconjmul(pk, z[m]);
+          if constexpr (MODE == RowOut::NllGrad) {
+            const float2 gpy = cmul(pk, gdy[m]), gpx = cmul(pk, gdx[m]);
+            // Re(conj(g_psi) * P_k * d(S_j O))
+            gy += z[m].x * gpy.x + z[m].y * gpy.y;
+            gx += z[m].x * gpx.x + z[m].y * gpx.y;
+          }
         }
       }
     }
-  }
-  if constexpr (MODE == RowOut::NllGrad) {
-    const double sy = block_sum<G::BS>(2.0 * gy, red);
-    const double sx = block_sum<G::BS>(2.0 * gx, red);
-    if (threadIdx.x == 0) {
-      double* g = a.posgrad + ((size_t)slot * BPP + rb) * 2;
-      g[0] = sy;
-      g[1] = sx;
+    if constexpr (MODE == RowOut::NllGrad) {
+      const double sy = block_sum<G::BS>(2.0 * gy, red);
+      const double sx = block_sum<G::BS>(2.0 * gx, red);
+      if (threadIdx.x == 0) {
+        double* g = a.posgrad + ((size_t)slot * BPP + rb) * 2;
+        g[0] = sy;
+        g[1] = sx;
+      }
+    }
+    float2* cb = a.contrib + ((size_t)slot * N + y) * N;
+  #pragma unroll
+    for (int m = 0; m < R; ++m) cb[t + T * m] = cacc[m];
+  } else {
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int y = blockIdx.x * G::LINES + line;
+    const int c0 = blockIdx.y * PB;
+    const int np = min(PB, a.nc - c0);          // patterns of this block (uniform)
+    constexpr bool DMU = MODE == RowOut::DmUpdate;
+    int j[PB], slot[PB];
+    float chi_s[PB];
+    float2 o[DMU ? PB : 1][R], cacc[PB][R];
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      j[q] = a.jlist[a.jl_off + c0 + min(q, np - 1)];
+      slot[q] = a.slot_off + c0 + min(q, np - 1);
+      if constexpr (DMU) line_bilinear<N>(a.obj, a.h, a.w, a.pos[j[q]], y, t, o[q]);
+      // Poisson update: chi = -alpha_R F^-1[g Psi]
+      chi_s[q] = (MODE == RowOut::StoreChi && a.poisp) ? (float)(-a.poisp[slot[q]]) : 1.f;
+#pragma unroll
+      for (int m = 0; m < R; ++m) cacc[q][m] = make_float2(0.f, 0.f);
+    }
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+      // the mode's probe row, once for both patterns
+      const float2* pr = a.probe + ((size_t)k * N + y) * N;
+      float2 pkr[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) pkr[m] = pr[t + T * m];
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        if (q >= np) break;
+        float2 z[R];
+        const float2* src = a.zs + ((size_t)(c0 + q) * K + k) * N * N;
+#pragma unroll
+        for (int m = 0; m < R; ++m) z[m] = src[zoff<N>(y, t + T * m)];
+        line_fft<N, true>(z, xb + line * G::W, tw_s, t);
+        if constexpr (DMU) {
+          float2* ps = a.psi + (((size_t)j[q] * K + k) * N + y) * N;
+#pragma unroll
+          for (int m = 0; m < R; ++m) {
+            const float2 nw = cmul(pkr[m], o[q][m]) + z[m];
+            ps[t + T * m] = nw;
+            cacc[q][m] = cacc[q][m] + cconjmul(pkr[m], nw);
+          }
+        } else {
+          float2* ch = a.chi + (((size_t)slot[q] * K + k) * N + y) * N;
+#pragma unroll
+          for (int m = 0; m < R; ++m) {
+            if (a.poisp) z[m] = chi_s[q] * z[m];
+            ch[t + T * m] = z[m];
+            cacc[q][m] = cacc[q][m] + cconjmul(pkr[m], z[m]);
+          }
+        }
+        // the second pattern's transform after the first's
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      if (q >= np) break;
+      float2* cb = a.contrib + ((size_t)slot[q] * N + y) * N;
+#pragma unroll
+      for (int m = 0; m < R; ++m) cb[t + T * m] = cacc[q][m];
     }
   }
-  float2* cb = a.contrib + ((size_t)slot * N + y) * N;
-#pragma unroll
-  for (int m = 0; m < R; ++m) cb[t + T * m] = cacc[m];
 }
 
 // Step length of the Poisson exit-wave update of each pattern of the chunk:
@@ -585,11 +655,20 @@ void launch_rows_inv(const FourierArgs& a, RowOut mode) {
   if (a.nc <= 0) return;
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
-    const dim3 grid(N / Geo<N>::LINES, a.nc);
+    auto grid = [&](auto mc) {
+      constexpr int PB = rows_inv_patterns<N, K, decltype(mc)::value>();
+      return dim3(N / Geo<N>::LINES, (a.nc + PB - 1) / PB);
+    };
     switch (mode) {
-      case RowOut::DmUpdate: k_rows_inv<N, K, RowOut::DmUpdate><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
-      case RowOut::StoreChi: k_rows_inv<N, K, RowOut::StoreChi><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
-      case RowOut::NllGrad: k_rows_inv<N, K, RowOut::NllGrad><<<grid, Geo<N>::BS, 0, a.stream>>>(a); break;
+      case RowOut::DmUpdate:
+        k_rows_inv<N, K, RowOut::DmUpdate><<<grid(std::integral_constant<RowOut, RowOut::DmUpdate>{}), Geo<N>::BS, 0, a.stream>>>(a);
+        break;
+      case RowOut::StoreChi:
+        k_rows_inv<N, K, RowOut::StoreChi><<<grid(std::integral_constant<RowOut, RowOut::StoreChi>{}), Geo<N>::BS, 0, a.stream>>>(a);
+        break;
+      case RowOut::NllGrad:
+        k_rows_inv<N, K, RowOut::NllGrad><<<grid(std::integral_constant<RowOut, RowOut::NllGrad>{}), Geo<N>::BS, 0, a.stream>>>(a);
+        break;
     }
   });
   PTY_LAUNCH_CHECK("rows_inv");
