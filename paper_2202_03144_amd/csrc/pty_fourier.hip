@@ -333,6 +333,16 @@ void k_cols(FourierArgs a) {
   cols_body<N, K, OP, MASK>(a);
 }
 
+// The masked instantiations carry the mask test and its sums; left to itself
+// the compiler gives the 256^2 x 3-mode projection one wavefront per SIMD.
+// Held to two (a few spilled registers), it keeps the unmasked kernel's
+// occupancy.
+template <int N, int K, ColOp OP>
+__global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
+void k_cols_masked(FourierArgs a) {
+  cols_body<N, K, OP, true>(a);
+}
+
 // The Poisson step carries two more sums and a division per pixel; left to
 // itself the compiler gives the 256^2 x 3-mode instance one wavefront per
 // SIMD, which doubles its time.  Held to two, it spills a few registers.
@@ -632,10 +642,10 @@ void launch_cols(const FourierArgs& a, ColOp op) {
     constexpr int BS = Geo<N>::BS;
     if (a.masked) {
       switch (op) {
-        case ColOp::Project: k_cols<N, K, ColOp::Project, true><<<grid, BS, 0, a.stream>>>(a); break;
-        case ColOp::NllGrad: k_cols<N, K, ColOp::NllGrad, true><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::Project: k_cols_masked<N, K, ColOp::Project><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::NllGrad: k_cols_masked<N, K, ColOp::NllGrad><<<grid, BS, 0, a.stream>>>(a); break;
         case ColOp::Intensity: k_cols<N, K, ColOp::Intensity, false><<<grid, BS, 0, a.stream>>>(a); break;
-        case ColOp::NllLoss: k_cols<N, K, ColOp::NllLoss, true><<<grid, BS, 0, a.stream>>>(a); break;
+        case ColOp::NllLoss: k_cols_masked<N, K, ColOp::NllLoss><<<grid, BS, 0, a.stream>>>(a); break;
         case ColOp::Poisson: k_cols_poisson<N, K, true><<<grid, BS, 0, a.stream>>>(a); break;
       }
     } else {
