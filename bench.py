@@ -90,15 +90,15 @@ def iteration_bytes(plan, n, k, j, h, w, groups):
 # launches (profiles/dm_fourier_256x3_hbm_counters.md): read = 2.0 x FETCH_SIZE,
 # written = 1.0 x WRITE_SIZE (factors from a plain copy of known size).  Valid
 # only while the kernel sources hash to COUNTER_SRC_HASH.
-COUNTER_SRC_HASH = "5bb8933820dbe3e2"
+COUNTER_SRC_HASH = "d7d195c9f63297d9"
 COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp"]
 MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns per launch)
-    ("dm", "rows_fwd"): (64208.0, 98304.0, 64),
-    ("dm", "cols"): (65733.0, 98336.0, 64),
-    ("dm", "rows_inv"): (66776.5, 131072.0, 64),
-    ("lsqml", "rows_fwd"): (14428.3, 98304.0, 64),
-    ("lsqml", "cols"): (65733.0, 98336.0, 64),
-    ("lsqml", "rows_inv"): (50003.7, 131072.0, 64),
+    ("dm", "rows_fwd"): (64207.3, 98304.0, 64),
+    ("dm", "cols"): (65834.1, 98336.0, 64),
+    ("dm", "rows_inv"): (66791.9, 131072.0, 64),
+    ("lsqml", "rows_fwd"): (14426.5, 98304.0, 64),
+    ("lsqml", "cols"): (65834.1, 98336.0, 64),
+    ("lsqml", "rows_inv"): (50008.7, 131072.0, 64),
 }
 
 

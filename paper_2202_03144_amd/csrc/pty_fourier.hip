@@ -17,6 +17,7 @@
 // probes, Sec. 2.2).
 #include "pty_geom.hpp"
 #include "pty_kernels.hpp"
+#include "pty_wave.hpp"
 
 namespace pty {
 namespace {
@@ -198,10 +199,21 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
   using G = Geo<N>;
   using S = ColSplit<N, K>;
   constexpr int R = G::R, T = G::T, CW = S::CW, BPP = S::BPP, MS = S::MS, KM = K / MS;
+  // The block's measured amplitudes (N rows x CW columns) are staged in LDS,
+  // column-major with a 16-word skew per column: each thread writes and later
+  // reads the rows of its own line, so a wavefront's lines (adjacent columns)
+  // touch distinct banks both ways.  Only where the register budget already
+  // holds the kernel to two wavefronts per SIMD (256^2 with two or three
+  // modes, one thread group per column, the ops that invert), so that the
+  // 17 KB do not lower it.
+  constexpr bool AMP_LDS = N == 256 && K >= 2 && MS == 1 &&
+                           (OP == ColOp::Project || OP == ColOp::NllGrad || OP == ColOp::Poisson);
+  constexpr int AS = N + 16;   // words per staged column
   __shared__ float2 tw_s[N];
   __shared__ float2 xb[G::LINES * G::W];
   __shared__ double red[G::BS / 64];
-  load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
+  __shared__ double red2[G::BS / 64][2];
+  __shared__ float amp_s[AMP_LDS ? CW * AS : 1];
   // each line's T threads are consecutive lanes of one wavefront; the MS
   // groups of a column are adjacent, so their lanes differ by T
   const int grp = threadIdx.x / T, t = threadIdx.x % T;
@@ -211,12 +223,46 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
   const int j = a.jlist[a.jl_off + c];
   float2* base = a.zs + ((size_t)c * K + kg * KM) * N * N;
   float2* buf = xb + grp * G::W;
+  // twiddles and amplitudes first, then the column values; the LDS copies
+  // wait only for the first two (an LDS-only barrier leaves the column loads
+  // in flight).  At 512 the twiddles are copied before the column loads (two
+  // per thread held across them spill the masked projection).
+  constexpr bool TW_EARLY = N <= 256;
+  constexpr int TWQ = (N + G::BS - 1) / G::BS;
+  if constexpr (!TW_EARLY) load_twiddles<N>(tw_s, reinterpret_cast<const float2*>(a.tw));
+  float2 twv[TW_EARLY ? TWQ : 1];
+  if constexpr (TW_EARLY) {
+#pragma unroll
+    for (int i = 0; i < TWQ; ++i) {
+      const int q = threadIdx.x + G::BS * i;
+      if (q < N) twv[i] = reinterpret_cast<const float2*>(a.tw)[q];
+    }
+  }
+  float av[AMP_LDS ? R : 1];
+  if constexpr (AMP_LDS) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) av[m] = a.amp[((size_t)j * N + t + T * m) * N + x];
+  }
   float2 z[KM][R];
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
 #pragma unroll
     for (int m = 0; m < R; ++m) z[k][m] = base[(size_t)k * N * N + zoff<N>(t + T * m, x)];
   }
+  if constexpr (TW_EARLY) {
+#pragma unroll
+    for (int i = 0; i < TWQ; ++i) {
+      const int q = threadIdx.x + G::BS * i;
+      if (q < N) tw_s[q] = twv[i];
+    }
+  }
+  if constexpr (AMP_LDS) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) amp_s[col * AS + t + T * m] = av[m];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 #pragma unroll
   for (int k = 0; k < KM; ++k) line_fft<N, false>(z[k], buf, tw_s, t);
   // The transforms are unscaled: the unitary far field is z / N and the
@@ -237,7 +283,7 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
         a.intensity_out[((size_t)j * N + ((pr + N / 2) & (N - 1))) * N + ((x + N / 2) & (N - 1))] = inten;
     } else if constexpr (OP == ColOp::NllLoss) {
       if (lead) {
-        const float ar = a.amp[((size_t)j * N + pr) * N + x];
+        const float ar = AMP_LDS ? amp_s[col * AS + pr] : a.amp[((size_t)j * N + pr) * N + x];
         const float d = ar * ar;
         const float l = inten - d * logf(inten + a.nll_eps);
         if constexpr (MASK)
@@ -250,7 +296,7 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
       // measurement: the projection keeps the model there and the pixel adds
       // to no sum.  (A separate instantiation, so that the unmasked kernels
       // keep their register budget.)
-      const float ar = a.amp[((size_t)j * N + pr) * N + x];
+      const float ar = AMP_LDS ? amp_s[col * AS + pr] : a.amp[((size_t)j * N + pr) * N + x];
       float mf = 1.f, am = ar;
       if constexpr (MASK) {
         mf = signbit(ar) ? 0.f : 1.f;
@@ -258,9 +304,11 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
       }
       float f;
       if constexpr (OP == ColOp::Project || OP == ColOp::Poisson) {
-        const float mod = sqrtf(iraw) * sc;
+        // hardware square root and reciprocal (1 ulp each) in place of the
+        // correctly rounded forms and their refinement steps
+        const float mod = __builtin_amdgcn_sqrtf(iraw) * sc;
         if constexpr (OP == ColOp::Project) {
-          f = am / fmaxf(mod, 1e-6f) - 1.f;
+          f = am * __builtin_amdgcn_rcpf(fmaxf(mod, 1e-6f)) - 1.f;
         } else {
           // the Poisson update moves Psi by -alpha_R g Psi, g = 1 - d / (I + eps);
           // alpha_R (k_poisson_alpha) minimises the pattern's likelihood along
@@ -308,18 +356,31 @@ __device__ __forceinline__ void cols_body(const FourierArgs& a) {
     }
   }
   if constexpr (OP == ColOp::Project || OP == ColOp::NllGrad || OP == ColOp::Poisson) {
-#pragma unroll
-    for (int k = 0; k < KM; ++k) line_fft<N, true>(z[k], buf, tw_s, t);
+    // each mode is stored as soon as its inverse transform is done, so the
+    // stores drain under the next mode's transform
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
+      line_fft<N, true>(z[k], buf, tw_s, t);
 #pragma unroll
       for (int m = 0; m < R; ++m) base[(size_t)k * N * N + zoff<N>(t + T * m, x)] = z[k][m];
     }
   }
   if constexpr (OP != ColOp::Intensity && OP != ColOp::Poisson) {
-    const double s0 = block_sum<G::BS>((double)e_num, red);
-    const double s1 = block_sum<G::BS>((double)e_den, red);
+    // both sums per wavefront by DPP lane moves, then the wavefronts' in order
+    const double w0 = wave_sum_d((double)e_num), w1 = wave_sum_d((double)e_den);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+      red2[wid][0] = w0;
+      red2[wid][1] = w1;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int w = 0; w < G::BS / 64; ++w) {
+        s0 += red2[w][0];
+        s1 += red2[w][1];
+      }
       double* e = a.errp + ((size_t)j * BPP + cb) * 2;
       e[0] = s0;
       e[1] = s1;
@@ -334,9 +395,8 @@ void k_cols(FourierArgs a) {
 }
 
 // The masked instantiations carry the mask test and its sums; left to itself
-// the compiler gives the 256^2 x 3-mode projection one wavefront per SIMD.
-// Held to two (a few spilled registers), it keeps the unmasked kernel's
-// occupancy.
+// the compiler has given the 256^2 x 3-mode projection one wavefront per
+// SIMD.  Held to two, it keeps the unmasked kernel's occupancy.
 template <int N, int K, ColOp OP>
 __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
 void k_cols_masked(FourierArgs a) {
