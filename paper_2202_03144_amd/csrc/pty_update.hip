@@ -51,28 +51,22 @@ __device__ __forceinline__ float lane_shr1(float x, float first) {
 __device__ __forceinline__ float2 lane_shr1(float2 x, float2 first) {
   return make_float2(lane_shr1(x.x, first.x), lane_shr1(x.y, first.y));
 }
-// A load from a wavefront-uniform address, through the constant address space
-// (a scalar load; the planes read here are not written by the kernel).
-template <typename V>
-__device__ __forceinline__ V uniform_load(const V* p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  // the address is the same in every lane: make that explicit
-  const unsigned long long a = (unsigned long long)p;
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a), hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
-  return *(const __attribute__((address_space(4))) V*)(((unsigned long long)hi << 32) | lo);
-#else
-  return *p;
-#endif
+// Lane l's value of x (l wavefront-uniform), for every lane.
+__device__ __forceinline__ float lane_value(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ float2 lane_value(float2 x, int l) {
+  return make_float2(lane_value(x.x, l), lane_value(x.y, l));
 }
 // hrow for a wavefront whose lanes are consecutive columns: one vector load
 // of column v per lane; column v - 1 is the neighbouring lane's value, and
-// lane 0's (column v1c0, uniform) comes from a scalar load.
+// lane 0's (column v1c0) is `left`, loaded for all of a patch's rows at once.
 template <int N, typename V>
-__device__ __forceinline__ V hrow_wave(const V* __restrict__ src, int u, int v0c, int v1c0, float w0, float w1) {
+__device__ __forceinline__ V hrow_wave(const V* __restrict__ src, int u, int v0c, V left, float w0, float w1) {
   const float uok = (unsigned)u < (unsigned)N ? 1.f : 0.f;
   const V* r = src + min(max(u, 0), N - 1) * N;
   const V c0 = r[v0c];
-  const V c1 = lane_shr1(c0, uniform_load(r + v1c0));
+  const V c1 = lane_shr1(c0, left);
   return axpy(w1 * uok, c1, axpy(w0 * uok, c0, Zero<V>::v()));
 }
 
@@ -110,10 +104,15 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
     const int v0c = min(max(v, 0), N - 1), v1c0 = min(max(te.tx - 1 - r.ix, 0), N - 1);
     const float wy0 = wgt * (1.f - r.fy), wy1 = wgt * r.fy;
     const int u0 = te.ty - r.iy;
-    V prev = hrow_wave<N, V>(src, u0 - 1, v0c, v1c0, w0, w1);
+    // lane k <= TH loads column v1c0 of patch row u0 - 1 + k: every row's
+    // tap left of the tile in one vector load, handed to lane 0 per row
+    static_assert(TH + 1 <= 64, "one lane per patch row");
+    const V* rk = src + min(max(u0 - 1 + min(lane, TH), 0), N - 1) * N;
+    const V left = rk[v1c0];
+    V prev = hrow_wave<N, V>(src, u0 - 1, v0c, lane_value(left, 0), w0, w1);
 #pragma unroll
     for (int i = 0; i < TH; ++i) {
-      const V cur = hrow_wave<N, V>(src, u0 + i, v0c, v1c0, w0, w1);
+      const V cur = hrow_wave<N, V>(src, u0 + i, v0c, lane_value(left, i + 1), w0, w1);
       acc[i] = axpy(wy0, cur, axpy(wy1, prev, acc[i]));
       prev = cur;
     }
