@@ -71,13 +71,16 @@ __device__ __forceinline__ V hrow_wave(const V* __restrict__ src, int u, int v0c
 }
 
 
-template <int N, ObjOp OP>
-__global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
+// NW wavefronts per tile (wave w takes every NW-th patch): 4, or 8 or 16
+// where the grid has too few tiles to fill the chip and each tile's list is
+// walked by more waves.
+template <int N, ObjOp OP, int NW>
+__global__ __launch_bounds__(64 * NW) void k_obj_gather(ObjGatherArgs a) {
   using V = typename std::conditional<OP == ObjOp::Density, float, float2>::type;
   constexpr int TH = kTileH;
-  constexpr int NW = 4;  // wavefronts per tile; wave w takes every NW-th patch
+  static_assert(TH % NW == 0, "each wave applies whole rows");
   __shared__ V part[NW - 1][TH][kTileW];
-  __shared__ float redf[4];
+  __shared__ float redf[NW];
   const TileEntry te = a.tiles[blockIdx.x];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int X = te.tx + lane;
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
       prev = cur;
     }
   }
-  // combine the wavefronts' partial sums in a fixed order (wave 0 + 1 + 2 + 3)
+  // combine the wavefronts' partial sums in a fixed order (wave 0 + 1 + ...)
   if (wv > 0) {
 #pragma unroll
     for (int i = 0; i < TH; ++i) part[wv - 1][i][lane] = acc[i];
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(256) void k_obj_gather(ObjGatherArgs a) {
     }
   }
   if constexpr (OP == ObjOp::Density) {
-    mx = block_max_all<256>(mx, redf);
+    mx = block_max_all<64 * NW>(mx, redf);
     if (threadIdx.x == 0) atomicMax(a.den_max, __float_as_uint(mx));
   }
 }
@@ -1612,18 +1615,31 @@ __global__ __launch_bounds__(256) void k_err_scatter(const double* __restrict__ 
 
 static unsigned stream_grid(size_t n) { return (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 4096)); }
 
+// Tiles below which a tile's patch list is split over eight wavefronts
+// instead of four (two blocks per CU), and over sixteen (half a block per CU).
+constexpr int kGatherWideTiles = 512, kGatherWidestTiles = 128;
+
 void launch_obj_gather(const ObjGatherArgs& a, ObjOp op) {
   if (a.ntiles <= 0) return;
   dispatch_n(a.n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    switch (op) {
-      case ObjOp::Density: k_obj_gather<N, ObjOp::Density><<<a.ntiles, 256, 0, a.stream>>>(a); break;
-      case ObjOp::DmObject: k_obj_gather<N, ObjOp::DmObject><<<a.ntiles, 256, 0, a.stream>>>(a); break;
-      case ObjOp::LsqDirection: k_obj_gather<N, ObjOp::LsqDirection><<<a.ntiles, 256, 0, a.stream>>>(a); break;
-      case ObjOp::LsqUpdate: k_obj_gather<N, ObjOp::LsqUpdate><<<a.ntiles, 256, 0, a.stream>>>(a); break;
-      case ObjOp::Gradient: k_obj_gather<N, ObjOp::Gradient><<<a.ntiles, 256, 0, a.stream>>>(a); break;
-      case ObjOp::WeightedSum: k_obj_gather<N, ObjOp::WeightedSum><<<a.ntiles, 256, 0, a.stream>>>(a); break;
-    }
+    auto go = [&](auto wc) {
+      constexpr int NW = decltype(wc)::value;
+      switch (op) {
+        case ObjOp::Density: k_obj_gather<N, ObjOp::Density, NW><<<a.ntiles, 64 * NW, 0, a.stream>>>(a); break;
+        case ObjOp::DmObject: k_obj_gather<N, ObjOp::DmObject, NW><<<a.ntiles, 64 * NW, 0, a.stream>>>(a); break;
+        case ObjOp::LsqDirection: k_obj_gather<N, ObjOp::LsqDirection, NW><<<a.ntiles, 64 * NW, 0, a.stream>>>(a); break;
+        case ObjOp::LsqUpdate: k_obj_gather<N, ObjOp::LsqUpdate, NW><<<a.ntiles, 64 * NW, 0, a.stream>>>(a); break;
+        case ObjOp::Gradient: k_obj_gather<N, ObjOp::Gradient, NW><<<a.ntiles, 64 * NW, 0, a.stream>>>(a); break;
+        case ObjOp::WeightedSum: k_obj_gather<N, ObjOp::WeightedSum, NW><<<a.ntiles, 64 * NW, 0, a.stream>>>(a); break;
+      }
+    };
+    if (a.ntiles < kGatherWidestTiles)
+      go(ic<16>{});
+    else if (a.ntiles < kGatherWideTiles)
+      go(ic<8>{});
+    else
+      go(ic<4>{});
   });
   PTY_LAUNCH_CHECK("obj_gather");
 }
