@@ -595,8 +595,7 @@ ObjGatherArgs obj_args(pty_ctx* c, const Group& g) {
 
 // den_O = sum over the group of S_j^T sum_k |P_k|^2 and its maximum
 void density(pty_ctx* c, const Group& g) {
-  timed(c, kOther, [&] { launch_probe_intensity(c->probe, c->pint, c->N, c->K, c->stream); });
-  timed(c, kOther, [&] { launch_fill_u32(c->scal, 1, 0u, c->stream); });
+  timed(c, kOther, [&] { launch_probe_intensity(c->probe, c->pint, c->N, c->K, c->stream, c->scal); });
   ObjGatherArgs o = obj_args(c, g);
   timed(c, kObjGather, [&] { launch_obj_gather(o, ObjOp::Density); });
 }
@@ -623,6 +622,7 @@ void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern,
   pa.per_slice = per_slice;
   pa.part_num = c->part_num;
   pa.part_den = c->part_den;
+  pa.zero = with_den ? c->scal + 1 : nullptr;   // the finish's max of den_P
   pa.stream = c->stream;
   timed(c, kProbeAcc, [&] { launch_probe_acc(pa, op); });
   ProbeFinishArgs pf{};
@@ -635,7 +635,6 @@ void probe_reduce(pty_ctx* c, const Group& g, const float2* src, int by_pattern,
   pf.den = with_den ? c->den_p : nullptr;
   pf.den_max = with_den ? c->scal + 1 : nullptr;
   pf.stream = c->stream;
-  if (with_den) timed(c, kOther, [&] { launch_fill_u32(c->scal + 1, 1, 0u, c->stream); });
   timed(c, kProbeFin, [&] { launch_probe_finish(pf); });
 }
 

@@ -94,6 +94,7 @@ struct ProbeAccArgs {
   int per_slice;
   float2* part_num;       // slices x K x N x N
   float* part_den;        // slices x N x N
+  unsigned* zero;         // if set, zeroed by the first thread (the max that the finish takes next)
   hipStream_t stream;
 };
 int probe_slices(int count, int per_slice);
@@ -267,7 +268,8 @@ void launch_amplitude(const float* counts, float* amp, double* totals, int n, in
 void launch_apply_mask(float* amp, const unsigned char* mask, int n, int j, hipStream_t s);
 // totals[j] = sum_q amp[j][q]^2 (FP64, one block per pattern)
 void launch_amp_totals(const float* amp, double* totals, int n, int j, hipStream_t s);
-void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s);
+// pint = sum_k |P_k|^2; `zero`, if set, is zeroed too (the max the density gather takes next)
+void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s, unsigned* zero = nullptr);
 // out[*slot] = E of the partials (slot NULL: out[0]); advance: then ++*slot (the
 // device-side iteration counter, so that a captured iteration can be replayed).
 void launch_err_reduce(const double* errp, int count, double* out, hipStream_t s, int* slot = nullptr,

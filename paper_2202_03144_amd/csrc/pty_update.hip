@@ -221,6 +221,7 @@ __global__ __launch_bounds__(256) void k_probe_acc(ProbeAccArgs a) {
   __shared__ float sw[kProbeSliceMax];
   __shared__ int ss[kProbeSliceMax];
   const int slice = blockIdx.y, rblk = blockIdx.x;
+  if (a.zero && slice == 0 && rblk == 0 && threadIdx.x == 0) *a.zero = 0u;
   const int s_beg = a.s0 + slice * a.per_slice;
   const int ns = min(a.per_slice, a.s0 + a.count - s_beg);
   if ((int)threadIdx.x < ns) {
@@ -388,10 +389,13 @@ __global__ __launch_bounds__(256) void k_lsq_planes(const float2* probe, const f
 // once into registers and serve all M; the positions come from LDS.  Each
 // wavefront reduces its sums with lane shuffles; the four wavefronts' sums are
 // added in a fixed order at the end.
-template <int N, int K, bool PROBE_ON, bool POS>
+// M positions per block: LsqPix<N>::M, or 2 where a launch would have too
+// few blocks to fill the chip (the partials, one per position and row block,
+// are the same either way).
+template <int N, int K, bool PROBE_ON, bool POS, int M>
 __global__ __launch_bounds__(256) void k_lsq_sums(LsqStepArgs a) {
   using W = typename LsqPix<N>::W;
-  constexpr int RB = LsqPix<N>::RB, M = LsqPix<N>::M;
+  constexpr int RB = LsqPix<N>::RB;
   constexpr int NV = POS ? 9 : 5;
   constexpr int KP = PROBE_ON ? K : 1;
   __shared__ PosInfo sp[M];
@@ -706,9 +710,11 @@ __global__ __launch_bounds__(256) void k_amp_totals(const float* __restrict__ am
   if (threadIdx.x == 0) totals[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_probe_intensity(const float2* probe, float* pint, int n, int k) {
+__global__ __launch_bounds__(256) void k_probe_intensity(const float2* probe, float* pint, int n, int k,
+                                                         unsigned* zero) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   const int nn = n * n;
+  if (q == 0 && zero) *zero = 0u;
   if (q >= nn) return;
   float s = 0.f;
   for (int i = 0; i < k; ++i) s += cabs2(probe[(size_t)i * nn + q]);
@@ -1719,18 +1725,26 @@ void launch_lsq_steps(const LsqStepArgs& a) {
   dispatch_nk(a.n, a.k, [&](auto nc, auto kc) {
     constexpr int N = decltype(nc)::value, K = decltype(kc)::value;
     nrb = LsqPix<N>::NRB;
-    const dim3 grid(LsqPix<N>::NRB, (a.count + LsqPix<N>::M - 1) / LsqPix<N>::M);
-    if (a.shift) {
-      if (a.probe_on)
-        k_lsq_sums<N, K, true, true><<<grid, 256, 0, a.stream>>>(a);
-      else
-        k_lsq_sums<N, K, false, true><<<grid, 256, 0, a.stream>>>(a);
-    } else {
-      if (a.probe_on)
-        k_lsq_sums<N, K, true, false><<<grid, 256, 0, a.stream>>>(a);
-      else
-        k_lsq_sums<N, K, false, false><<<grid, 256, 0, a.stream>>>(a);
-    }
+    auto go = [&](auto mc) {
+      constexpr int M = decltype(mc)::value;
+      const dim3 grid(LsqPix<N>::NRB, (a.count + M - 1) / M);
+      if (a.shift) {
+        if (a.probe_on)
+          k_lsq_sums<N, K, true, true, M><<<grid, 256, 0, a.stream>>>(a);
+        else
+          k_lsq_sums<N, K, false, true, M><<<grid, 256, 0, a.stream>>>(a);
+      } else {
+        if (a.probe_on)
+          k_lsq_sums<N, K, true, false, M><<<grid, 256, 0, a.stream>>>(a);
+        else
+          k_lsq_sums<N, K, false, false, M><<<grid, 256, 0, a.stream>>>(a);
+      }
+    };
+    constexpr int MB = LsqPix<N>::M;
+    if ((long)LsqPix<N>::NRB * ((a.count + MB - 1) / MB) < 512)
+      go(ic<2>{});
+    else
+      go(ic<MB>{});
   });
   PTY_LAUNCH_CHECK("lsq_sums");
   k_lsq_solve<<<(a.count + kLsqSolveWaves - 1) / kLsqSolveWaves, 64 * kLsqSolveWaves, 0, a.stream>>>(a, nrb);
@@ -2189,8 +2203,8 @@ void launch_amp_totals(const float* amp, double* totals, int n, int j, hipStream
   PTY_LAUNCH_CHECK("amp_totals");
 }
 
-void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s) {
-  k_probe_intensity<<<(n * n + 255) / 256, 256, 0, s>>>(probe, pint, n, k);
+void launch_probe_intensity(const float2* probe, float* pint, int n, int k, hipStream_t s, unsigned* zero) {
+  k_probe_intensity<<<(n * n + 255) / 256, 256, 0, s>>>(probe, pint, n, k, zero);
   PTY_LAUNCH_CHECK("probe_intensity");
 }
 
