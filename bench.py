@@ -93,12 +93,12 @@ def iteration_bytes(plan, n, k, j, h, w, groups):
 COUNTER_SRC_HASH = "d7d195c9f63297d9"
 COUNTER_SRCS = ["pty_fourier.hip", "pty_fft.hpp", "pty_geom.hpp", "pty_common.hpp"]
 MEASURED_KIB = {  # (plan, family): (FETCH_SIZE KiB, WRITE_SIZE KiB, patterns per launch)
-    ("dm", "rows_fwd"): (64207.3, 98304.0, 64),
-    ("dm", "cols"): (65834.1, 98336.0, 64),
-    ("dm", "rows_inv"): (66791.9, 131072.0, 64),
-    ("lsqml", "rows_fwd"): (14426.5, 98304.0, 64),
-    ("lsqml", "cols"): (65834.1, 98336.0, 64),
-    ("lsqml", "rows_inv"): (50008.7, 131072.0, 64),
+    ("dm", "rows_fwd"): (64185.7, 98304.0, 64),
+    ("dm", "cols"): (65853.6, 98336.0, 64),
+    ("dm", "rows_inv"): (66791.8, 131072.0, 64),
+    ("lsqml", "rows_fwd"): (14428.8, 98304.0, 64),
+    ("lsqml", "cols"): (65853.6, 98336.0, 64),
+    ("lsqml", "rows_inv"): (50008.3, 131072.0, 64),
 }
 
 
