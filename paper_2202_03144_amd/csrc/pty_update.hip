@@ -18,8 +18,9 @@ namespace {
 // ---------------------------------------------------------------------------
 // Object tiles: sum_j S_j^T (.) in gather form, then the algorithm's update
 // ---------------------------------------------------------------------------
-// One block of four wavefronts per 16 x 64 tile; lane = column, and the
-// wavefronts split the tile's patch list.  For each patch the thread walks its
+// One block of four wavefronts per 16 x 64 tile (8 or 16 on grids too small
+// to fill the chip); lane = column, and the wavefronts split the tile's
+// patch list.  For each patch the thread walks its
 // column downwards: the horizontal combination of patch row u (taps v and
 // v - 1) is computed once and used for object rows u and u + 1, so each patch
 // row is read once per tile column.
@@ -33,16 +34,6 @@ struct Zero<float2> { __device__ static float2 v() { return make_float2(0.f, 0.f
 __device__ __forceinline__ float2 axpy(float a, float2 x, float2 y) { return make_float2(fmaf(a, x.x, y.x), fmaf(a, x.y, y.y)); }
 __device__ __forceinline__ float axpy(float a, float x, float y) { return fmaf(a, x, y); }
 
-// Horizontal combination of patch row u at columns v (weight w0) and v - 1
-// (weight w1).  Branch-free: indices are clamped into the plane and the
-// weights are zero where a tap falls outside it, so the loads of all rows can
-// be issued together.
-template <int N, typename V>
-__device__ __forceinline__ V hrow(const V* __restrict__ src, int u, int v0c, int v1c, float w0, float w1) {
-  const float uok = (unsigned)u < (unsigned)N ? 1.f : 0.f;
-  const V* r = src + min(max(u, 0), N - 1) * N;
-  return axpy(w1 * uok, r[v1c], axpy(w0 * uok, r[v0c], Zero<V>::v()));
-}
 
 // The value of lane i - 1 (lane 0: `first`), by a wavefront-wide DPP shift.
 __device__ __forceinline__ float lane_shr1(float x, float first) {
@@ -58,9 +49,13 @@ __device__ __forceinline__ float lane_value(float x, int l) {
 __device__ __forceinline__ float2 lane_value(float2 x, int l) {
   return make_float2(lane_value(x.x, l), lane_value(x.y, l));
 }
-// hrow for a wavefront whose lanes are consecutive columns: one vector load
-// of column v per lane; column v - 1 is the neighbouring lane's value, and
-// lane 0's (column v1c0) is `left`, loaded for all of a patch's rows at once.
+// Horizontal combination of patch row u at columns v (weight w0) and v - 1
+// (weight w1), for a wavefront whose lanes are consecutive columns: one
+// vector load of column v per lane; column v - 1 is the neighbouring lane's
+// value, and lane 0's (column v1c0) is `left`, loaded for all of a patch's
+// rows at once.  Branch-free: indices are clamped into the plane and the
+// weights are zero where a tap falls outside it, so the loads of all rows
+// can be issued together.
 template <int N, typename V>
 __device__ __forceinline__ V hrow_wave(const V* __restrict__ src, int u, int v0c, V left, float w0, float w1) {
   const float uok = (unsigned)u < (unsigned)N ? 1.f : 0.f;
